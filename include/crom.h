@@ -1,0 +1,211 @@
+/*
+ * crom.h - C interface of the MI355X (gfx950) library for the latent time
+ * step of Continuous Reduced-Order Modeling (CROM, Chen et al., ICLR 2023,
+ * arXiv 2206.02607).
+ *
+ * The method represents a PDE field f(x, t) by a neural field g(x, q(t)):
+ * an MLP over the concatenation of a spatial point x (m values) and a latent
+ * vector q (r values) with `depth` hidden ELU layers of equal `width` and a
+ * linear output layer of d values (Sec. "Manifold Construction", Sec.
+ * "Network Details").  One latent step q_n -> q_{n+1} has three stages
+ * (Sec. "Method: Latent Space Dynamics", Alg. "Latent-space dynamics"):
+ *   1. network inference at a small set of integration samples, with the
+ *      spatial derivatives and the latent Jacobian dg/dq taken through the
+ *      network by the forward chain rule (Alg. "Network gradient");
+ *   2. explicit time stepping of the exact PDE at the samples
+ *      (eqs. "discrete-time", "time-integration");
+ *   3. network inversion: q_{n+1} minimises sum_j |g(y_j, q) - f_{n+1}(y_j)|^2
+ *      (eq. "invert") by Gauss-Newton with backtracking line search
+ *      (Sec. "Network Inversion") or by one linearised normal-equation solve
+ *      (Sec. "Linearization").
+ *
+ * Conventions for every call below
+ *   - Array pointers are DEVICE pointers owned by the caller unless a
+ *     parameter says "host".  Nothing here allocates device memory; scratch
+ *     space comes from a caller-owned workspace sized by a *_workspace call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call only enqueues work on it and returns; none synchronises,
+ *     so the calls can be captured into a HIP graph.
+ *   - Argument errors (bad sizes, unsupported shapes, NULL pointers where
+ *     one is required, too small a workspace) are detected on the host and
+ *     returned before anything is enqueued; crom_last_error() then holds a
+ *     message.  A failed launch returns CROM_ERR_HIP.  Numerical outcomes of
+ *     the inversion (singular system, non-finite values, line-search
+ *     failure) are reported per instance in device memory (crom_step_info).
+ *   - Layouts are row-major and fully packed; the indices are listed with
+ *     each argument, slowest first.
+ *   - Supported decoder shapes (m, r, d, width): (1, 3, 1, 32),
+ *     (2, 8, 1, 128), (3, 16, 3, 256); depth >= 1.  Other shapes return
+ *     CROM_ERR_UNSUPPORTED.
+ */
+#ifndef CROM_H
+#define CROM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CROM_OK = 0,
+  CROM_ERR_INVALID_ARG = 1,
+  CROM_ERR_UNSUPPORTED = 2,
+  CROM_ERR_WORKSPACE = 3,
+  CROM_ERR_HIP = 4
+} crom_status;
+
+/* Arithmetic of the hidden-to-hidden layers.
+ *   FP32    FP32 operands and accumulation.
+ *   BF16    operands rounded to bfloat16 (round to nearest even), products
+ *           accumulated in FP32 on the matrix cores.
+ *   BF16X3  value columns carry each operand as a sum of two bfloat16
+ *           numbers (hi + lo) and take three products (hi*hi + hi*lo +
+ *           lo*hi), about 16 significant bits; derivative columns as BF16.
+ * The input layer, the ELU epilogues, the derivative recurrences and the
+ * output layer are FP32 in every mode; the latent fold q -> W1q q + b1 is
+ * accumulated in FP64. */
+enum { CROM_PREC_FP32 = 0, CROM_PREC_BF16 = 1, CROM_PREC_BF16X3 = 2 };
+
+/* Second spatial derivatives requested from crom_decode_jac. */
+enum {
+  CROM_D2_NONE = 0,      /* none                                           */
+  CROM_D2_LAPLACIAN = 1, /* sum_i d2g/dx_i^2 : [P][d]                      */
+  CROM_D2_HESSIAN = 2    /* upper triangle i <= j, row-major : [P][d][m(m+1)/2] */
+};
+
+/* Decoder description.
+ * params: FP32, natural layout, layer by layer for l = 1 .. depth+1:
+ *   W_l [n_l][n_{l-1}] row-major, then b_l [n_l], with n_0 = m + r
+ *   (input order [x; q]: x first), n_1..n_depth = width, n_{depth+1} = d.
+ *   Hidden layers use ELU with alpha = 1 (ELU(z) = z for z > 0, e^z - 1
+ *   otherwise; z = 0 takes the exponential branch); the output layer is
+ *   linear.
+ * packed: the fragment-ordered copy of the hidden-to-hidden weights that
+ *   crom_net_pack writes (crom_net_packed_bytes long).  It must be
+ *   refreshed after params change. */
+typedef struct {
+  int32_t m, r, d, width, depth, precision;
+  const float* params;
+  const void* packed;
+} crom_net;
+
+/* Number of FP32 values in `params` for the given shape. */
+size_t crom_net_param_count(int32_t m, int32_t r, int32_t d, int32_t width, int32_t depth);
+
+/* Bytes of the packed buffer for net->precision (0 on invalid shape). */
+size_t crom_net_packed_bytes(const crom_net* net);
+
+/* Write the packed hidden-layer weights of net->params into `packed`
+ * (device, crom_net_packed_bytes bytes) in net->precision. */
+crom_status crom_net_pack(const crom_net* net, void* packed, void* stream);
+
+/* Decoder values g(x_p, q) (Sec. "Step 1: Network Inference").
+ * x [P][m] FP32 points, q [r] FP64 latent, g [P][d] FP32 out.  P >= 0. */
+crom_status crom_decode(const crom_net* net, const float* x, int64_t P, const double* q,
+                        float* g, void* stream);
+
+/* Values with any subset of the derivative columns, all from one forward
+ * pass of value and tangents through the layers (Alg. "Network gradient",
+ * extended to second order in x and to the latent directions):
+ *   g    [P][d]                values (required)
+ *   dgdx [P][d][m]             dg/dx (NULL = not computed)
+ *   d2g  per d2_mode           see CROM_D2_* (NULL iff d2_mode == NONE)
+ *   dgdq [P][d][r]             latent Jacobian dg/dq (NULL = not computed)
+ * d2_mode != NONE needs dgdx's columns internally but dgdx may still be NULL. */
+crom_status crom_decode_jac(const crom_net* net, const float* x, int64_t P, const double* q,
+                            int32_t d2_mode, float* g, float* dgdx, float* d2g, float* dgdq,
+                            void* stream);
+
+/* Spatial derivatives only: crom_decode_jac with dgdq = NULL. */
+crom_status crom_decode_jac_x(const crom_net* net, const float* x, int64_t P, const double* q,
+                              int32_t d2_mode, float* g, float* dgdx, float* d2g, void* stream);
+
+/* Latent Jacobian only (the matrix J of Sec. "Linearization"):
+ * crom_decode_jac with d2_mode = NONE and dgdx = NULL. */
+crom_status crom_decode_jac_q(const crom_net* net, const float* x, int64_t P, const double* q,
+                              float* g, float* dgdq, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Latent step for a batch of independent instances.
+ * ------------------------------------------------------------------------- */
+
+enum { CROM_PDE_HEAT = 0 };
+
+/* PDE of the instances.  HEAT: u_t = nu * Laplacian(u) with forward Euler,
+ * f_{n+1}(y) = g(y, q_n) + dt * nu * Laplacian_x g(y, q_n); coef = nu
+ * [n_inst] FP64 (device).  Needs d == 1. */
+typedef struct {
+  int32_t kind, _pad;
+  double dt;
+  const double* coef;
+} crom_pde;
+
+/* Inversion options (host struct).
+ *   max_iter   >= 1 Gauss-Newton iterations (accepted steps) at most
+ *   linearized 1: one normal-equation solve with unit step (Sec.
+ *              "Linearization"); 0: Gauss-Newton with line search
+ *   ls_max     the line search tries alpha = 1, s, s^2, ..., s^ls_max
+ *   tol_step   stop when |alpha delta| or |delta| <= tol_step (1 + |q|)
+ *   armijo_c   accept alpha when phi(q + alpha delta) <= phi(q) - c alpha b.delta
+ *   ls_shrink  s in (0, 1)
+ *   launches   number of evaluate/solve rounds enqueued after the first
+ *              (0 = max_iter + 2).  Each round evaluates 4 line-search
+ *              trials, so a step that needs more rounds than this ends with
+ *              CROM_FLAG_MAXITER. */
+typedef struct {
+  int32_t max_iter, linearized, ls_max, launches;
+  double tol_step, armijo_c, ls_shrink;
+} crom_gn_opts;
+
+enum {
+  CROM_FLAG_MAXITER = 1,   /* iteration budget used up                      */
+  CROM_FLAG_SINGULAR = 2,  /* Cholesky pivot <= 1e-14 * max diag(J^T J)     */
+  CROM_FLAG_NONFINITE = 4, /* NaN/Inf in the residual or normal equations   */
+  CROM_FLAG_LS_FAIL = 8    /* no trial step satisfied the Armijo condition  */
+};
+
+/* Per-instance outcome (device memory, written by crom_step). */
+typedef struct {
+  int32_t flags, iters, ls_evals, _pad;
+  double obj_first, obj_last; /* 1/2 |f_{n+1} - g(Y, q)|^2 at q_n and at q_{n+1} */
+} crom_step_info;
+
+/* Workspace bytes for crom_step with n_inst instances and total_samples
+ * samples (host out-parameter `bytes`). */
+crom_status crom_step_workspace(const crom_net* net, int32_t n_inst, int64_t total_samples,
+                                size_t* bytes);
+
+/* One latent step q_n -> q_{n+1} for every instance.
+ *   offsets [n_inst+1] int64  CSR offsets of each instance's samples in y
+ *                             (device; non-decreasing, offsets[0] = 0,
+ *                             offsets[n_inst] = total_samples, and every
+ *                             instance needs r <= d * S_i samples)
+ *   y       [total_samples][m] FP32 sample points
+ *   clamp   NULL or [total_samples] uint8: 1 = Dirichlet sample, target 0
+ *   q_n     [n_inst][r] FP64;  q_next [n_inst][r] FP64 out (must not alias q_n)
+ *   info    [n_inst] crom_step_info out
+ *   ws      workspace of at least crom_step_workspace bytes, 256-byte aligned
+ * The target values f_{n+1} are kept in the workspace and are readable with
+ * crom_step_targets after the step. On SINGULAR / NONFINITE / LS_FAIL the
+ * instance's q_next holds the last accepted iterate. */
+crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
+                      const int64_t* offsets, int64_t total_samples, const float* y,
+                      const uint8_t* clamp, const double* q_n, double* q_next,
+                      const crom_gn_opts* opts, crom_step_info* info, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Device pointer to the FP64 targets f_{n+1} [total_samples][d] inside a
+ * workspace used by crom_step (NULL on invalid arguments). */
+const double* crom_step_targets(const crom_net* net, int32_t n_inst, int64_t total_samples,
+                                const void* ws);
+
+/* Message describing the last error returned on the calling thread. */
+const char* crom_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CROM_H */

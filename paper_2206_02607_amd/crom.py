@@ -1,0 +1,294 @@
+"""Python binding of libcrom.so (include/crom.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels; this module converts
+torch tensors into device pointers and sizes, passes the current HIP stream
+and raises on error codes.  It never falls back to another implementation:
+if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, Structure, c_double, c_int32, c_int64, c_size_t, c_void_p
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcrom.so")
+
+PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2
+D2_NONE, D2_LAPLACIAN, D2_HESSIAN = 0, 1, 2
+PDE_HEAT = 0
+FLAG_MAXITER, FLAG_SINGULAR, FLAG_NONFINITE, FLAG_LS_FAIL = 1, 2, 4, 8
+_PREC_NAMES = {"fp32": PREC_FP32, "bf16": PREC_BF16, "bf16x3": PREC_BF16X3}
+
+
+class CromNet(Structure):
+    _fields_ = [("m", c_int32), ("r", c_int32), ("d", c_int32), ("width", c_int32),
+                ("depth", c_int32), ("precision", c_int32), ("params", c_void_p),
+                ("packed", c_void_p)]
+
+
+class CromPDE(Structure):
+    _fields_ = [("kind", c_int32), ("_pad", c_int32), ("dt", c_double), ("coef", c_void_p)]
+
+
+class CromGNOpts(Structure):
+    _fields_ = [("max_iter", c_int32), ("linearized", c_int32), ("ls_max", c_int32),
+                ("launches", c_int32), ("tol_step", c_double), ("armijo_c", c_double),
+                ("ls_shrink", c_double)]
+
+
+INFO_DTYPE = np.dtype([("flags", "<i4"), ("iters", "<i4"), ("ls_evals", "<i4"), ("_pad", "<i4"),
+                       ("obj_first", "<f8"), ("obj_last", "<f8")])
+
+_lib = None
+
+
+class CromError(RuntimeError):
+    pass
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CromError(f"{LIB_PATH} is missing: build it with "
+                            "`python -m paper_2206_02607_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.crom_last_error.restype = ctypes.c_char_p
+        L.crom_net_param_count.restype = c_size_t
+        L.crom_net_param_count.argtypes = [c_int32] * 5
+        L.crom_net_packed_bytes.restype = c_size_t
+        L.crom_net_packed_bytes.argtypes = [POINTER(CromNet)]
+        L.crom_net_pack.argtypes = [POINTER(CromNet), c_void_p, c_void_p]
+        L.crom_decode.argtypes = [POINTER(CromNet), c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
+        L.crom_decode_jac.argtypes = [POINTER(CromNet), c_void_p, c_int64, c_void_p, c_int32,
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.crom_decode_jac_x.argtypes = [POINTER(CromNet), c_void_p, c_int64, c_void_p, c_int32,
+                                        c_void_p, c_void_p, c_void_p, c_void_p]
+        L.crom_decode_jac_q.argtypes = [POINTER(CromNet), c_void_p, c_int64, c_void_p,
+                                        c_void_p, c_void_p, c_void_p]
+        L.crom_step_workspace.argtypes = [POINTER(CromNet), c_int32, c_int64, POINTER(c_size_t)]
+        L.crom_step_targets.restype = c_void_p
+        L.crom_step_targets.argtypes = [POINTER(CromNet), c_int32, c_int64, c_void_p]
+        L.crom_step.argtypes = [POINTER(CromNet), POINTER(CromPDE), c_int32, c_void_p, c_int64,
+                                c_void_p, c_void_p, c_void_p, c_void_p, POINTER(CromGNOpts),
+                                c_void_p, c_void_p, c_size_t, c_void_p]
+        for name in ("crom_net_pack", "crom_decode", "crom_decode_jac", "crom_decode_jac_x",
+                     "crom_decode_jac_q", "crom_step_workspace", "crom_step"):
+            getattr(L, name).restype = c_int32
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str) -> None:
+    if status != 0:
+        raise CromError(f"{what} failed ({status}): {lib().crom_last_error().decode()}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream() -> c_void_p:
+    torch = _torch()
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise CromError("device tensor expected")
+    if not t.is_contiguous():
+        raise CromError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+def param_count(m: int, r: int, d: int, width: int, depth: int) -> int:
+    return int(lib().crom_net_param_count(m, r, d, width, depth))
+
+
+def flatten_layers(layers: Sequence[Tuple[np.ndarray, np.ndarray]]) -> np.ndarray:
+    """Natural parameter layout: W_1, b_1, W_2, b_2, ... as one FP32 vector."""
+    parts = []
+    for W, b in layers:
+        parts.append(np.asarray(W, dtype=np.float32).ravel())
+        parts.append(np.asarray(b, dtype=np.float32).ravel())
+    return np.concatenate(parts)
+
+
+class Decoder:
+    """A decoder g(x, q) resident on the GPU: FP32 parameters plus the packed
+    fragment copy for the chosen precision."""
+
+    def __init__(self, params, m: int, r: int, d: int, width: int, depth: int,
+                 precision="bf16", device="cuda"):
+        torch = _torch()
+        self.m, self.r, self.d, self.width, self.depth = m, r, d, width, depth
+        self.precision = _PREC_NAMES[precision] if isinstance(precision, str) else int(precision)
+        n = param_count(m, r, d, width, depth)
+        if isinstance(params, np.ndarray):
+            params = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32))
+        params = params.to(device=device, dtype=torch.float32).contiguous()
+        if params.numel() != n:
+            raise CromError(f"expected {n} parameters, got {params.numel()}")
+        self.params = params
+        nb = int(lib().crom_net_packed_bytes(ctypes.byref(self._net(packed=False))))
+        self.packed = torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
+        self.pack()
+
+    @classmethod
+    def from_layers(cls, layers, m: int, precision="bf16", device="cuda"):
+        r = layers[0][0].shape[1] - m
+        return cls(flatten_layers(layers), m, r, layers[-1][0].shape[0], layers[0][0].shape[0],
+                   len(layers) - 1, precision, device)
+
+    def _net(self, packed=True) -> CromNet:
+        return CromNet(self.m, self.r, self.d, self.width, self.depth, self.precision,
+                       self.params.data_ptr(), self.packed.data_ptr() if packed else None)
+
+    def pack(self) -> None:
+        net = self._net(packed=False)
+        _check(lib().crom_net_pack(ctypes.byref(net), self.packed.data_ptr(), _stream()), "crom_net_pack")
+
+    # -- decode ---------------------------------------------------------
+    def _prep(self, x, q):
+        torch = _torch()
+        x = x.to(dtype=torch.float32).contiguous()
+        q = q.to(device=x.device, dtype=torch.float64).contiguous()
+        if x.dim() != 2 or x.shape[1] != self.m or q.numel() != self.r:
+            raise CromError("x must be [P, m] and q [r]")
+        return x, q
+
+    def decode(self, x, q, out=None):
+        torch = _torch()
+        x, q = self._prep(x, q)
+        P = x.shape[0]
+        g = out if out is not None else torch.empty(P, self.d, dtype=torch.float32, device=x.device)
+        net = self._net()
+        _check(lib().crom_decode(ctypes.byref(net), _ptr(x), P, _ptr(q), _ptr(g), _stream()), "crom_decode")
+        return g
+
+    def decode_jac(self, x, q, dx=True, d2=D2_NONE, dq=True):
+        """Returns (g, dgdx | None, d2g | None, dgdq | None)."""
+        torch = _torch()
+        x, q = self._prep(x, q)
+        P, dev = x.shape[0], x.device
+        f32 = dict(dtype=torch.float32, device=dev)
+        g = torch.empty(P, self.d, **f32)
+        gx = torch.empty(P, self.d, self.m, **f32) if dx else None
+        if d2 == D2_LAPLACIAN:
+            h = torch.empty(P, self.d, **f32)
+        elif d2 == D2_HESSIAN:
+            h = torch.empty(P, self.d, self.m * (self.m + 1) // 2, **f32)
+        else:
+            h = None
+        gq = torch.empty(P, self.d, self.r, **f32) if dq else None
+        net = self._net()
+        _check(lib().crom_decode_jac(ctypes.byref(net), _ptr(x), P, _ptr(q), int(d2), _ptr(g),
+                                     _ptr(gx), _ptr(h), _ptr(gq), _stream()), "crom_decode_jac")
+        return g, gx, h, gq
+
+    def decode_jac_x(self, x, q, d2=D2_LAPLACIAN):
+        torch = _torch()
+        x, q = self._prep(x, q)
+        P, dev = x.shape[0], x.device
+        f32 = dict(dtype=torch.float32, device=dev)
+        g = torch.empty(P, self.d, **f32)
+        gx = torch.empty(P, self.d, self.m, **f32)
+        nh = {D2_NONE: 0, D2_LAPLACIAN: 1, D2_HESSIAN: self.m * (self.m + 1) // 2}[d2]
+        h = torch.empty(P, self.d, nh, **f32).squeeze(-1) if nh else None
+        net = self._net()
+        _check(lib().crom_decode_jac_x(ctypes.byref(net), _ptr(x), P, _ptr(q), int(d2), _ptr(g),
+                                       _ptr(gx), _ptr(h), _stream()), "crom_decode_jac_x")
+        return g, gx, h
+
+    def decode_jac_q(self, x, q):
+        torch = _torch()
+        x, q = self._prep(x, q)
+        P, dev = x.shape[0], x.device
+        g = torch.empty(P, self.d, dtype=torch.float32, device=dev)
+        gq = torch.empty(P, self.d, self.r, dtype=torch.float32, device=dev)
+        net = self._net()
+        _check(lib().crom_decode_jac_q(ctypes.byref(net), _ptr(x), P, _ptr(q), _ptr(g), _ptr(gq),
+                                       _stream()), "crom_decode_jac_q")
+        return g, gq
+
+
+@dataclass
+class GNOptions:
+    max_iter: int = 5
+    linearized: bool = False
+    ls_max: int = 10
+    tol_step: float = 1e-6
+    armijo_c: float = 1e-4
+    ls_shrink: float = 0.5
+    launches: int = 0
+
+    def c_struct(self) -> CromGNOpts:
+        return CromGNOpts(self.max_iter, int(self.linearized), self.ls_max, self.launches,
+                          self.tol_step, self.armijo_c, self.ls_shrink)
+
+
+class Stepper:
+    """Reusable latent-step launcher for a fixed batch layout (instances,
+    CSR sample offsets, sample points): owns the workspace."""
+
+    def __init__(self, dec: Decoder, offsets, y, clamp=None):
+        torch = _torch()
+        self.dec = dec
+        off = torch.as_tensor(offsets, dtype=torch.int64)
+        self.n_inst = int(off.numel() - 1)
+        self.total = int(off[-1].item())
+        self.offsets = off.to(dec.params.device).contiguous()
+        self.y = y.to(device=dec.params.device, dtype=torch.float32).contiguous()
+        if self.y.shape != (self.total, dec.m):
+            raise CromError("y must be [total_samples, m]")
+        self.clamp = None if clamp is None else clamp.to(device=dec.params.device, dtype=torch.uint8).contiguous()
+        nbytes = c_size_t(0)
+        net = dec._net()
+        _check(lib().crom_step_workspace(ctypes.byref(net), self.n_inst, self.total, ctypes.byref(nbytes)),
+               "crom_step_workspace")
+        self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dec.params.device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.ws_bytes = int(nbytes.value)
+        self.info_buf = torch.zeros(self.n_inst * INFO_DTYPE.itemsize, dtype=torch.uint8,
+                                    device=dec.params.device)
+
+    def step(self, q_n, nu, dt: float, opts: GNOptions = GNOptions(), q_next=None):
+        torch = _torch()
+        dev = self.dec.params.device
+        q_n = q_n.to(device=dev, dtype=torch.float64).contiguous()
+        nu = torch.as_tensor(nu, dtype=torch.float64, device=dev).reshape(-1).expand(self.n_inst).contiguous()
+        if q_next is None:
+            q_next = torch.empty_like(q_n)
+        net = self.dec._net()
+        pde = CromPDE(PDE_HEAT, 0, float(dt), nu.data_ptr())
+        o = opts.c_struct()
+        self._nu = nu  # keep alive until the stream has consumed it
+        _check(lib().crom_step(ctypes.byref(net), ctypes.byref(pde), self.n_inst, _ptr(self.offsets),
+                               self.total, _ptr(self.y), _ptr(self.clamp), _ptr(q_n), _ptr(q_next),
+                               ctypes.byref(o), self.info_buf.data_ptr(), self.ws_ptr, self.ws_bytes,
+                               _stream()), "crom_step")
+        return q_next
+
+    def info(self) -> np.ndarray:
+        """Per-instance outcome of the last step (synchronises)."""
+        return np.frombuffer(self.info_buf.cpu().numpy().tobytes(), dtype=INFO_DTYPE)
+
+    def targets(self):
+        """FP64 targets f_{n+1} [total, d] of the last step (a view into the workspace)."""
+        torch = _torch()
+        n = self.total * self.dec.d
+        off = self.ws_ptr - self.ws.data_ptr()
+        net = self.dec._net()
+        p = lib().crom_step_targets(ctypes.byref(net), self.n_inst, self.total, c_void_p(self.ws_ptr))
+        start = off + (p - self.ws_ptr)
+        return self.ws[start:start + 8 * n].view(torch.float64).reshape(self.total, self.dec.d)

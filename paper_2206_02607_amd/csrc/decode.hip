@@ -1,0 +1,327 @@
+// Decoder entry points: weight packing, value decode and decode with
+// derivative columns (Sec. "Step 1: Network Inference", Alg. "Network
+// gradient").
+#include <stdarg.h>
+
+#include "common.hpp"
+
+namespace crom {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+crom_status check_net(const crom_net* net, bool need_packed) {
+  if (!net) return fail(CROM_ERR_INVALID_ARG, "net is NULL");
+  if (net->depth < 1 || net->depth > 15) return fail(CROM_ERR_INVALID_ARG, "depth must be in [1, 15]");
+  if (shape_id(net->m, net->r, net->d, net->width) == SHAPE_NONE)
+    return fail(CROM_ERR_UNSUPPORTED,
+                "unsupported (m, r, d, width); compiled: (1,3,1,32), (2,8,1,128), (3,16,3,256)");
+  if (net->precision != CROM_PREC_FP32 && net->precision != CROM_PREC_BF16 &&
+      net->precision != CROM_PREC_BF16X3)
+    return fail(CROM_ERR_UNSUPPORTED, "unknown precision");
+  if (!net->params) return fail(CROM_ERR_INVALID_ARG, "net->params is NULL");
+  if (need_packed && net->depth > 1 && !net->packed)
+    return fail(CROM_ERR_INVALID_ARG, "net->packed is NULL (call crom_net_pack)");
+  return CROM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Packing of the hidden-to-hidden weights into MFMA A-operand fragments.
+// ---------------------------------------------------------------------------
+template <int W, int PREC>
+__global__ void pack_kernel(const float* __restrict__ params, ParamIndex pi, int depth,
+                            char* __restrict__ out) {
+  constexpr int MTILES = W / 16;
+  const int h = blockIdx.y;                       // hidden layer 0 .. depth-2
+  const float* Wl = params + pi.w[h + 1];         // [W][W]
+  if constexpr (PREC == PREC_FP32) {
+    constexpr int KQ = W / 16;
+    constexpr int N = MTILES * KQ * 64 * 4;
+    float* o = reinterpret_cast<float*>(out) + (size_t)h * N;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+      const int v = i & 3, lane = (i >> 2) & 63, kq = (i >> 8) % KQ, mt = (i >> 8) / KQ;
+      o[i] = Wl[(mt * 16 + (lane & 15)) * W + kq * 16 + (lane >> 4) * 4 + v];
+    }
+  } else {
+    constexpr int KB = W / 32;
+    constexpr int N = MTILES * KB * 64 * 8;
+    __bf16* o = reinterpret_cast<__bf16*>(out) + (size_t)h * 2 * N;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+      const int e = i & 7, lane = (i >> 3) & 63, kb = (i >> 9) % KB, mt = (i >> 9) / KB;
+      const float w = Wl[(mt * 16 + (lane & 15)) * W + (2 * kb + (e >> 2)) * 16 + (lane >> 4) * 4 + (e & 3)];
+      const __bf16 hi = (__bf16)w;
+      o[i] = hi;
+      o[N + i] = (__bf16)(w - (float)hi);
+    }
+  }
+}
+
+static size_t packed_bytes(int w, int depth, int prec) {
+  if (depth < 2) return 0;
+  const size_t mt = w / 16;
+  const size_t per = prec == CROM_PREC_FP32 ? mt * (w / 16) * 64 * 16 : mt * (w / 32) * 64 * 16 * 2;
+  return per * (depth - 1);
+}
+
+// ---------------------------------------------------------------------------
+// Decode kernel: one workgroup per NB*16 points.
+// ---------------------------------------------------------------------------
+struct DecodeArgs {
+  const float* x;
+  int64_t P;
+  const double* q;
+  const float* params;
+  const char* packed;
+  ParamIndex pi;
+  int depth;
+  int qb;            // first latent index of the q-tangent columns
+  float* g;
+  float* dgdx;
+  float* d2g;
+  float* dgdq;
+};
+
+template <class S, class C, int NB, int NW, int PREC>
+__global__ __launch_bounds__(NW * 64) void decode_kernel(DecodeArgs a) {
+  using E = Engine<S, C, NB, NW, PREC>;
+  extern __shared__ __align__(16) char lds[];
+  const int64_t first = (int64_t)blockIdx.x * E::NPTS;
+  const int64_t rem = a.P - first;
+  const int n_valid = rem < E::NPTS ? (int)rem : E::NPTS;
+  E::stage(lds, a.x, first, n_valid, a.q, S::R, a.params, a.pi);
+  __syncthreads();
+  E::run(lds, a.params, a.pi, a.packed, a.depth, a.qb);
+  const float* res = reinterpret_cast<const float*>(lds + E::RES_OFF);
+  constexpr int D = S::D, M = S::M, R = S::R;
+  for (int i = threadIdx.x; i < D * E::NT * PT; i += E::THREADS) {
+    const int oo = i / (E::NT * PT);
+    const int t = (i / PT) % E::NT;
+    const int jj = i % PT;
+    const int b = t / C::C, c = t % C::C;
+    const int lp = b * PT + jj;
+    if (lp >= n_valid) continue;
+    const int64_t p = first + lp;
+    const float v = res[i];
+    const int k = C::kind(c);
+    if (k == CK_VAL) {
+      a.g[p * D + oo] = v;
+    } else if (k == CK_XT) {
+      if (a.dgdx) a.dgdx[(p * D + oo) * M + (c - C::X0)] = v;
+    } else if (k == CK_LAP) {
+      a.d2g[p * D + oo] = v;
+    } else if (k == CK_HESS) {
+      a.d2g[(p * D + oo) * C::ND2 + (c - C::D0)] = v;
+    } else {
+      a.dgdq[(p * D + oo) * R + a.qb + (c - C::Q0)] = v;
+    }
+  }
+}
+
+template <class S, class C, int NB, int NW, int PREC>
+static crom_status launch_decode(const DecodeArgs& a, hipStream_t st) {
+  using E = Engine<S, C, NB, NW, PREC>;
+  if constexpr (E::LDS_BYTES > 160 * 1024) {
+    return fail(CROM_ERR_UNSUPPORTED, "column set does not fit in LDS at this width/precision");
+  }
+  auto k = decode_kernel<S, C, NB, NW, PREC>;
+  static bool attr = false;
+  if (!attr) {
+    crom_status s = set_lds(k, E::LDS_BYTES);
+    if (s != CROM_OK) return s;
+    attr = true;
+  }
+  if (a.P == 0) return CROM_OK;
+  const int64_t blocks = (a.P + E::NPTS - 1) / E::NPTS;
+  if (blocks > 0x7fffffff) return fail(CROM_ERR_INVALID_ARG, "P too large");
+  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(E::THREADS), E::LDS_BYTES, st, a);
+  return hip_check(hipGetLastError(), "decode launch");
+}
+
+// Column request of one pass.
+struct Pass {
+  bool xt;
+  int d2;
+  int nq, qb;
+};
+
+template <class S, int NW, int PREC, bool XT, int D2, int NQ>
+static crom_status run_pass(const DecodeArgs& a, hipStream_t st) {
+  if constexpr (!XT && D2 == D2_NONE && NQ == 0) {
+    using C = Cols<S::M, S::R, 1, false, D2_NONE, 0>;
+    return launch_decode<S, C, 4, NW, PREC>(a, st);
+  } else {
+    using C = Cols<S::M, S::R, 1, XT, D2, NQ>;
+    return launch_decode<S, C, 1, NW, PREC>(a, st);
+  }
+}
+
+// Dispatch of a pass to the compiled column sets.  NQ is either 0 or the
+// per-pass chunk QC of the shape.
+template <class S, int NW, int PREC, int QC>
+static crom_status dispatch_pass(const Pass& p, const DecodeArgs& a, hipStream_t st) {
+  const bool q = p.nq > 0;
+  if (q && p.nq != QC) return fail(CROM_ERR_UNSUPPORTED, "internal: q chunk");
+#define CROM_CASE(XT, D2)                                                        \
+  if (p.xt == XT && p.d2 == D2) {                                                \
+    return q ? run_pass<S, NW, PREC, XT, D2, QC>(a, st) : run_pass<S, NW, PREC, XT, D2, 0>(a, st); \
+  }
+  CROM_CASE(false, D2_NONE)
+  CROM_CASE(true, D2_NONE)
+  CROM_CASE(true, D2_LAP)
+  if constexpr (S::M > 1) {
+    CROM_CASE(true, D2_HESS)
+  }
+#undef CROM_CASE
+  return fail(CROM_ERR_UNSUPPORTED, "unsupported derivative column set");
+}
+
+// Plans the passes of a request so that each pass's activations fit in LDS:
+// the x tangents and second-derivative columns go together (the second
+// derivatives need the x tangents' pre-activations); the latent tangents
+// are split into chunks of QC.  Every pass also writes the values, with
+// identical results.
+template <class S, int NW, int PREC, int QC>
+static crom_status decode_shape(const DecodeArgs& a0, bool xt, int d2, bool qt, hipStream_t st) {
+  DecodeArgs a = a0;
+  const bool spatial = xt || d2 != D2_NONE;
+  if (S::R <= QC) return dispatch_pass<S, NW, PREC, QC>(Pass{spatial, d2, qt ? QC : 0, 0}, a, st);
+  if (spatial || !qt) {
+    crom_status s = dispatch_pass<S, NW, PREC, QC>(Pass{spatial, d2, 0, 0}, a, st);
+    if (s != CROM_OK) return s;
+  }
+  if (qt) {
+    for (int qb = 0; qb < S::R; qb += QC) {
+      a.qb = qb;
+      crom_status s = dispatch_pass<S, NW, PREC, QC>(Pass{false, D2_NONE, QC, qb}, a, st);
+      if (s != CROM_OK) return s;
+    }
+  }
+  return CROM_OK;
+}
+
+template <class S, int NW, int QC32, int QC16>
+static crom_status decode_prec(int prec, const DecodeArgs& a, bool xt, int d2, bool qt, hipStream_t st) {
+  if (prec == CROM_PREC_FP32) return decode_shape<S, NW, PREC_FP32, QC32>(a, xt, d2, qt, st);
+  if (prec == CROM_PREC_BF16) return decode_shape<S, NW, PREC_BF16, QC16>(a, xt, d2, qt, st);
+  return decode_shape<S, NW, PREC_BF16X3, QC16>(a, xt, d2, qt, st);
+}
+
+static crom_status decode_any(const crom_net* net, const float* x, int64_t P, const double* q,
+                              int d2_mode, float* g, float* dgdx, float* d2g, float* dgdq,
+                              void* stream) {
+  crom_status s = check_net(net, true);
+  if (s != CROM_OK) return s;
+  if (P < 0) return fail(CROM_ERR_INVALID_ARG, "P < 0");
+  if (P > 0 && (!x || !q || !g)) return fail(CROM_ERR_INVALID_ARG, "x, q and g are required");
+  if (d2_mode < CROM_D2_NONE || d2_mode > CROM_D2_HESSIAN)
+    return fail(CROM_ERR_INVALID_ARG, "d2_mode");
+  if ((d2_mode != CROM_D2_NONE) != (d2g != nullptr))
+    return fail(CROM_ERR_INVALID_ARG, "d2g must be given iff d2_mode != NONE");
+  if (d2_mode == CROM_D2_HESSIAN && net->m == 1)
+    return fail(CROM_ERR_INVALID_ARG, "m = 1: use CROM_D2_LAPLACIAN");
+  DecodeArgs a{};
+  a.x = x;
+  a.P = P;
+  a.q = q;
+  a.params = net->params;
+  a.packed = static_cast<const char*>(net->packed);
+  a.pi = param_index(net->m, net->r, net->d, net->width, net->depth);
+  a.depth = net->depth;
+  a.qb = 0;
+  a.g = g;
+  a.dgdx = dgdx;
+  a.d2g = d2g;
+  a.dgdq = dgdq;
+  const bool xt = dgdx != nullptr;
+  const int d2 = d2_mode == CROM_D2_LAPLACIAN ? D2_LAP : d2_mode == CROM_D2_HESSIAN ? D2_HESS : D2_NONE;
+  const bool qt = dgdq != nullptr;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (shape_id(net->m, net->r, net->d, net->width)) {
+    case SHAPE_1D: return decode_prec<Shape<32, 1, 3, 1>, 2, 3, 3>(net->precision, a, xt, d2, qt, st);
+    case SHAPE_2D: return decode_prec<Shape<128, 2, 8, 1>, 4, 8, 8>(net->precision, a, xt, d2, qt, st);
+    case SHAPE_3D: return decode_prec<Shape<256, 3, 16, 3>, 8, 4, 8>(net->precision, a, xt, d2, qt, st);
+    default: return fail(CROM_ERR_UNSUPPORTED, "shape");
+  }
+}
+
+}  // namespace crom
+
+using namespace crom;
+
+extern "C" {
+
+const char* crom_last_error(void) { return g_err.c_str(); }
+
+size_t crom_net_param_count(int32_t m, int32_t r, int32_t d, int32_t width, int32_t depth) {
+  if (m < 1 || r < 0 || d < 1 || width < 1 || depth < 1) return 0;
+  size_t n = (size_t)width * (m + r) + width;
+  n += (size_t)(depth - 1) * ((size_t)width * width + width);
+  n += (size_t)d * width + d;
+  return n;
+}
+
+size_t crom_net_packed_bytes(const crom_net* net) {
+  if (!net || shape_id(net->m, net->r, net->d, net->width) == SHAPE_NONE || net->depth < 1) return 0;
+  return packed_bytes(net->width, net->depth, net->precision);
+}
+
+crom_status crom_net_pack(const crom_net* net, void* packed, void* stream) {
+  crom_status s = check_net(net, false);
+  if (s != CROM_OK) return s;
+  if (net->depth < 2) return CROM_OK;
+  if (!packed) return fail(CROM_ERR_INVALID_ARG, "packed is NULL");
+  ParamIndex pi = param_index(net->m, net->r, net->d, net->width, net->depth);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  dim3 grid(64, net->depth - 1);
+  char* out = static_cast<char*>(packed);
+  const bool f32 = net->precision == CROM_PREC_FP32;
+  switch (net->width) {
+    case 32:
+      if (f32) hipLaunchKernelGGL((pack_kernel<32, PREC_FP32>), grid, dim3(256), 0, st, net->params, pi, net->depth, out);
+      else hipLaunchKernelGGL((pack_kernel<32, PREC_BF16>), grid, dim3(256), 0, st, net->params, pi, net->depth, out);
+      break;
+    case 128:
+      if (f32) hipLaunchKernelGGL((pack_kernel<128, PREC_FP32>), grid, dim3(256), 0, st, net->params, pi, net->depth, out);
+      else hipLaunchKernelGGL((pack_kernel<128, PREC_BF16>), grid, dim3(256), 0, st, net->params, pi, net->depth, out);
+      break;
+    case 256:
+      if (f32) hipLaunchKernelGGL((pack_kernel<256, PREC_FP32>), grid, dim3(256), 0, st, net->params, pi, net->depth, out);
+      else hipLaunchKernelGGL((pack_kernel<256, PREC_BF16>), grid, dim3(256), 0, st, net->params, pi, net->depth, out);
+      break;
+    default:
+      return fail(CROM_ERR_UNSUPPORTED, "width");
+  }
+  return hip_check(hipGetLastError(), "pack launch");
+}
+
+crom_status crom_decode(const crom_net* net, const float* x, int64_t P, const double* q, float* g,
+                        void* stream) {
+  return decode_any(net, x, P, q, CROM_D2_NONE, g, nullptr, nullptr, nullptr, stream);
+}
+
+crom_status crom_decode_jac(const crom_net* net, const float* x, int64_t P, const double* q,
+                            int32_t d2_mode, float* g, float* dgdx, float* d2g, float* dgdq,
+                            void* stream) {
+  return decode_any(net, x, P, q, d2_mode, g, dgdx, d2g, dgdq, stream);
+}
+
+crom_status crom_decode_jac_x(const crom_net* net, const float* x, int64_t P, const double* q,
+                              int32_t d2_mode, float* g, float* dgdx, float* d2g, void* stream) {
+  return decode_any(net, x, P, q, d2_mode, g, dgdx, d2g, nullptr, stream);
+}
+
+crom_status crom_decode_jac_q(const crom_net* net, const float* x, int64_t P, const double* q,
+                              float* g, float* dgdq, void* stream) {
+  if (P > 0 && !dgdq) return crom::fail(CROM_ERR_INVALID_ARG, "dgdq is required");
+  return decode_any(net, x, P, q, CROM_D2_NONE, g, nullptr, nullptr, dgdq, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,510 @@
+// Latent step q_n -> q_{n+1} for a ragged batch of instances (Sec. "Method:
+// Latent Space Dynamics"; Alg. "Latent-space dynamics", "Network inference",
+// "Network inversion"; Sec. "Network Inversion", "Linearization").
+//
+// Kernels, in launch order (all on the caller's stream, no host sync):
+//   setup        block map (16-sample batches of every instance), state init
+//   eval_jets    value, x tangents, Laplacian and latent Jacobian at q_n;
+//                heat update f_{n+1} = g + dt nu Lap g (FP64), residual
+//                rho = f_{n+1} - g, and per-batch partial sums of
+//                J^T J, J^T rho and 1/2 rho^T rho (FP64)
+//   solve        per instance: fixed-order sum of the partials, Armijo test
+//                of the evaluated trials, Cholesky of J^T J, next direction
+//   eval_trials  values at four line-search trials q + alpha_t delta and the
+//                Jacobian at the first one, with the same partial sums
+// (eval_trials, solve) rounds repeat a fixed number of times; an instance
+// that has finished makes the remaining launches return at once, so the
+// sequence can be captured in a graph.
+#include "common.hpp"
+
+namespace crom {
+
+constexpr int RMAX = 16;
+constexpr int TV = 4;  // line-search trials per round
+enum { PH_INIT = 0, PH_TRIALS = 1, PH_REJAC = 2, PH_DONE = 3 };
+
+struct GNState {
+  double q[RMAX];       // accepted iterate
+  double delta[RMAX];   // Gauss-Newton direction at q
+  double qt[TV][RMAX];  // latents evaluated by the next round (trial 0 also gets J)
+  double alpha[TV];
+  double phi, slope, dnorm, pad0;
+  double obj_first, obj_last;
+  int32_t phase, iters, ls_evals, flags, ls_tried, pad1;
+};
+
+struct WsLayout {
+  size_t blk_start, blk_inst, first_blk, nblk, targets, partials, state, total;
+  int64_t nblk_max;
+  int nred;
+};
+
+static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static WsLayout ws_layout(int r, int d, int n_inst, int64_t total) {
+  WsLayout L{};
+  L.nblk_max = total / PT + n_inst;
+  L.nred = r * (r + 1) / 2 + r + TV;
+  size_t o = 0;
+  L.blk_start = o; o = align256(o + 8 * (size_t)L.nblk_max);
+  L.blk_inst = o;  o = align256(o + 4 * (size_t)L.nblk_max);
+  L.first_blk = o; o = align256(o + 4 * (size_t)(n_inst + 1));
+  L.nblk = o;      o = align256(o + 8);
+  L.targets = o;   o = align256(o + 8 * (size_t)total * d);
+  L.partials = o;  o = align256(o + 8 * (size_t)L.nblk_max * L.nred);
+  L.state = o;     o = align256(o + sizeof(GNState) * (size_t)n_inst);
+  L.total = o;
+  return L;
+}
+
+struct StepArgs {
+  const float* params;
+  const char* packed;
+  ParamIndex pi;
+  int depth, r, n_inst;
+  int64_t total;
+  const int64_t* offsets;
+  const float* y;
+  const uint8_t* clamp;
+  const double* coef;
+  double dt;
+  const double* q_n;
+  double* q_next;
+  crom_step_info* info;
+  char* ws;
+  WsLayout L;
+  int max_iter, linearized, ls_max;
+  double tol, armijo_c, shrink;
+};
+
+template <class T>
+__device__ __forceinline__ T* wsp(const StepArgs& a, size_t off) {
+  return reinterpret_cast<T*>(a.ws + off);
+}
+
+// ---------------------------------------------------------------------------
+__global__ void setup_kernel(StepArgs a) {
+  int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
+  int64_t* blk_start = wsp<int64_t>(a, a.L.blk_start);
+  int32_t* blk_inst = wsp<int32_t>(a, a.L.blk_inst);
+  GNState* st = wsp<GNState>(a, a.L.state);
+  if (threadIdx.x == 0) {
+    // An instance whose offsets are out of order or outside [0, total]
+    // gets no batches (it then ends SINGULAR), and the batch count never
+    // exceeds the bound the workspace was sized for.
+    int64_t acc = 0;
+    for (int i = 0; i < a.n_inst; ++i) {
+      first_blk[i] = (int32_t)acc;
+      const int64_t lo = a.offsets[i], hi = a.offsets[i + 1];
+      int64_t nb = (lo >= 0 && hi >= lo && hi <= a.total) ? (hi - lo + PT - 1) / PT : 0;
+      if (acc + nb > a.L.nblk_max) nb = 0;
+      acc += nb;
+    }
+    first_blk[a.n_inst] = (int32_t)acc;
+    *wsp<int64_t>(a, a.L.nblk) = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.n_inst; i += blockDim.x) {
+    const int32_t b0 = first_blk[i], b1 = first_blk[i + 1];
+    for (int32_t b = b0; b < b1; ++b) {
+      blk_start[b] = a.offsets[i] + (int64_t)(b - b0) * PT;
+      blk_inst[b] = i;
+    }
+    GNState& s = st[i];
+    for (int k = 0; k < RMAX; ++k) {
+      const double v = k < a.r ? a.q_n[(int64_t)i * a.r + k] : 0.0;
+      s.q[k] = v;
+      s.delta[k] = 0.0;
+      for (int t = 0; t < TV; ++t) s.qt[t][k] = v;
+    }
+    for (int t = 0; t < TV; ++t) s.alpha[t] = 0.0;
+    s.phi = s.slope = s.dnorm = 0.0;
+    s.obj_first = s.obj_last = __builtin_nan("");
+    s.phase = PH_INIT;
+    s.iters = s.ls_evals = s.flags = s.ls_tried = 0;
+  }
+}
+
+// Partial sums of one batch from per-point J rows and residuals staged in LDS
+// (jd [PT][R], rho [PT][TV], both FP64; invalid points hold zeros).
+template <int R>
+__device__ __forceinline__ void batch_partials(const double* jd, const double* rho, double* out) {
+  constexpr int NA = R * (R + 1) / 2;
+  constexpr int NRED = NA + R + TV;
+  for (int e = threadIdx.x; e < NRED; e += blockDim.x) {
+    double s = 0.0;
+    if (e < NA) {
+      int a = 0, rem = e, n = R;
+      while (rem >= n) { rem -= n; ++a; --n; }
+      const int b = a + rem;
+      for (int i = 0; i < PT; ++i) s += jd[i * R + a] * jd[i * R + b];
+    } else if (e < NA + R) {
+      const int k = e - NA;
+      for (int i = 0; i < PT; ++i) s += jd[i * R + k] * rho[i * TV];
+    } else {
+      const int t = e - NA - R;
+      for (int i = 0; i < PT; ++i) s += 0.5 * rho[i * TV + t] * rho[i * TV + t];
+    }
+    out[e] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <class S, int NW, int PREC>
+__global__ __launch_bounds__(NW * 64) void eval_jets_kernel(StepArgs a) {
+  constexpr int R = S::R;
+  using C = Cols<S::M, R, 1, true, D2_LAP, R>;
+  using E = Engine<S, C, 1, NW, PREC>;
+  extern __shared__ __align__(16) char lds[];
+  const int64_t blk = blockIdx.x;
+  if (blk >= *wsp<int64_t>(a, a.L.nblk)) return;
+  const int inst = wsp<int32_t>(a, a.L.blk_inst)[blk];
+  const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
+  const int64_t rem = a.offsets[inst + 1] - first;
+  const int n_valid = rem < PT ? (int)rem : PT;
+  E::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * R, R, a.params, a.pi);
+  __syncthreads();
+  E::run(lds, a.params, a.pi, a.packed, a.depth, 0);
+  const float* res = reinterpret_cast<const float*>(lds + E::RES_OFF);
+  double* jd = reinterpret_cast<double*>(lds);  // the activation region is free now
+  double* rho = jd + PT * R;
+  double* targets = wsp<double>(a, a.L.targets);
+  if (threadIdx.x < PT) {
+    const int i = threadIdx.x;
+    const bool valid = i < n_valid;
+    const int64_t p = first + i;
+    const double gv = (double)res[0 * PT + i];
+    const double lap = (double)res[C::D0 * PT + i];
+    double f = gv + a.dt * a.coef[inst] * lap;
+    if (valid && a.clamp && a.clamp[p]) f = 0.0;
+    if (valid) targets[p] = f;
+    rho[i * TV] = valid ? f - gv : 0.0;
+    for (int t = 1; t < TV; ++t) rho[i * TV + t] = 0.0;
+    for (int k = 0; k < R; ++k) jd[i * R + k] = valid ? (double)res[(C::Q0 + k) * PT + i] : 0.0;
+  }
+  __syncthreads();
+  batch_partials<R>(jd, rho, wsp<double>(a, a.L.partials) + blk * a.L.nred);
+}
+
+template <class S, int NW, int PREC>
+__global__ __launch_bounds__(NW * 64) void eval_trials_kernel(StepArgs a) {
+  constexpr int R = S::R;
+  using C = Cols<S::M, R, TV, false, D2_NONE, R>;
+  using E = Engine<S, C, 1, NW, PREC>;
+  extern __shared__ __align__(16) char lds[];
+  const int64_t blk = blockIdx.x;
+  if (blk >= *wsp<int64_t>(a, a.L.nblk)) return;
+  const int inst = wsp<int32_t>(a, a.L.blk_inst)[blk];
+  const GNState* st = wsp<GNState>(a, a.L.state) + inst;
+  if (st->phase != PH_TRIALS && st->phase != PH_REJAC) return;
+  const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
+  const int64_t rem = a.offsets[inst + 1] - first;
+  const int n_valid = rem < PT ? (int)rem : PT;
+  E::stage(lds, a.y, first, n_valid, &st->qt[0][0], RMAX, a.params, a.pi);
+  __syncthreads();
+  E::run(lds, a.params, a.pi, a.packed, a.depth, 0);
+  const float* res = reinterpret_cast<const float*>(lds + E::RES_OFF);
+  double* jd = reinterpret_cast<double*>(lds);
+  double* rho = jd + PT * R;
+  const double* targets = wsp<double>(a, a.L.targets);
+  if (threadIdx.x < PT) {
+    const int i = threadIdx.x;
+    const bool valid = i < n_valid;
+    const double f = valid ? targets[first + i] : 0.0;
+    for (int t = 0; t < TV; ++t) rho[i * TV + t] = valid ? f - (double)res[t * PT + i] : 0.0;
+    for (int k = 0; k < R; ++k) jd[i * R + k] = valid ? (double)res[(C::Q0 + k) * PT + i] : 0.0;
+  }
+  __syncthreads();
+  batch_partials<R>(jd, rho, wsp<double>(a, a.L.partials) + blk * a.L.nred);
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Newton control for one instance (one wave per instance).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void solve_kernel(StepArgs a, int is_last) {
+  const int inst = blockIdx.x;
+  GNState* st = wsp<GNState>(a, a.L.state) + inst;
+  const int phase = st->phase;
+  if (phase == PH_DONE) return;
+  __shared__ double red[RMAX * (RMAX + 1) / 2 + RMAX + TV];
+  __shared__ double A[RMAX * RMAX];
+  __shared__ double L[RMAX * RMAX];
+  const int r = a.r;
+  const int nA = r * (r + 1) / 2;
+  const int nred = a.L.nred;
+  const int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
+  const int32_t b0 = first_blk[inst], b1 = first_blk[inst + 1];
+  const double* part = wsp<double>(a, a.L.partials);
+  for (int e = threadIdx.x; e < nred; e += blockDim.x) {
+    double s = 0.0;
+    for (int32_t b = b0; b < b1; ++b) s += part[(int64_t)b * nred + e];
+    red[e] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+
+  const double* bv = red + nA;
+  const double* phit = red + nA + r;
+  bool done = false, newdir = false;
+  if (phase == PH_INIT) {
+    st->obj_first = st->obj_last = st->phi = phit[0];
+    newdir = true;
+  } else if (phase == PH_TRIALS) {
+    int acc = -1;
+    for (int t = 0; t < TV; ++t) {
+      if (st->ls_tried + t > a.ls_max) break;
+      st->ls_evals += 1;
+      const double ph = phit[t];
+      if (isfinite(ph) && ph <= st->phi - a.armijo_c * st->alpha[t] * st->slope) {
+        acc = t;
+        break;
+      }
+    }
+    if (acc < 0) {
+      st->ls_tried += TV;
+      if (st->ls_tried > a.ls_max) {
+        st->flags |= CROM_FLAG_LS_FAIL;
+        done = true;
+      } else {
+        double al = st->alpha[TV - 1];
+        for (int t = 0; t < TV; ++t) {
+          al *= a.shrink;
+          st->alpha[t] = al;
+          for (int k = 0; k < r; ++k) st->qt[t][k] = st->q[k] + al * st->delta[k];
+        }
+      }
+    } else {
+      double qn = 0.0;
+      for (int k = 0; k < r; ++k) qn += st->q[k] * st->q[k];
+      qn = sqrt(qn);
+      const double step = st->alpha[acc] * st->dnorm;
+      for (int k = 0; k < r; ++k) st->q[k] = st->qt[acc][k];
+      st->iters += 1;
+      st->phi = phit[acc];
+      st->obj_last = st->phi;
+      if (step <= a.tol * (1.0 + qn)) {
+        done = true;
+      } else if (st->iters >= a.max_iter) {
+        st->flags |= CROM_FLAG_MAXITER;
+        done = true;
+      } else if (acc == 0) {
+        newdir = true;
+      } else {
+        st->phase = PH_REJAC;
+        for (int t = 0; t < TV; ++t)
+          for (int k = 0; k < r; ++k) st->qt[t][k] = st->q[k];
+      }
+    }
+  } else {  // PH_REJAC: J^T J and J^T rho at the accepted iterate
+    newdir = true;
+  }
+
+  if (newdir) {
+    bool finite = isfinite(st->phi);
+    for (int e = 0; e < nA + r; ++e) finite = finite && isfinite(red[e]);
+    if (!finite) {
+      st->flags |= CROM_FLAG_NONFINITE;
+      done = true;
+    } else {
+      // unpack the upper triangle
+      int e = 0;
+      for (int i = 0; i < r; ++i)
+        for (int j = i; j < r; ++j) {
+          A[i * r + j] = red[e];
+          A[j * r + i] = red[e];
+          ++e;
+        }
+      double dmax = 0.0;
+      for (int i = 0; i < r; ++i) dmax = i == 0 ? A[0] : fmax(dmax, A[i * r + i]);
+      const double thresh = 1e-14 * dmax;
+      bool ok = true;
+      for (int j = 0; j < r && ok; ++j) {
+        double s = A[j * r + j];
+        for (int k = 0; k < j; ++k) s -= L[j * r + k] * L[j * r + k];
+        if (!isfinite(s) || s <= thresh) {
+          ok = false;
+          break;
+        }
+        L[j * r + j] = sqrt(s);
+        for (int i = j + 1; i < r; ++i) {
+          double t = A[i * r + j];
+          for (int k = 0; k < j; ++k) t -= L[i * r + k] * L[j * r + k];
+          L[i * r + j] = t / L[j * r + j];
+        }
+      }
+      if (!ok) {
+        st->flags |= CROM_FLAG_SINGULAR;
+        done = true;
+      } else {
+        double y[RMAX], x[RMAX];
+        for (int i = 0; i < r; ++i) {
+          double t = bv[i];
+          for (int k = 0; k < i; ++k) t -= L[i * r + k] * y[k];
+          y[i] = t / L[i * r + i];
+        }
+        for (int i = r - 1; i >= 0; --i) {
+          double t = y[i];
+          for (int k = i + 1; k < r; ++k) t -= L[k * r + i] * x[k];
+          x[i] = t / L[i * r + i];
+        }
+        double dn = 0.0, qn = 0.0, sl = 0.0;
+        for (int k = 0; k < r; ++k) {
+          st->delta[k] = x[k];
+          dn += x[k] * x[k];
+          qn += st->q[k] * st->q[k];
+          sl += bv[k] * x[k];
+        }
+        st->dnorm = sqrt(dn);
+        if (a.linearized) {
+          for (int k = 0; k < r; ++k) st->q[k] += x[k];
+          st->iters = 1;
+          done = true;
+        } else if (st->dnorm <= a.tol * (1.0 + sqrt(qn))) {
+          done = true;
+        } else {
+          st->slope = sl;
+          st->ls_tried = 0;
+          double al = 1.0;
+          for (int t = 0; t < TV; ++t) {
+            st->alpha[t] = al;
+            for (int k = 0; k < r; ++k) st->qt[t][k] = st->q[k] + al * x[k];
+            al *= a.shrink;
+          }
+          st->phase = PH_TRIALS;
+        }
+      }
+    }
+  }
+  if (!done && is_last) {
+    st->flags |= CROM_FLAG_MAXITER;
+    done = true;
+  }
+  if (done) st->phase = PH_DONE;
+  for (int k = 0; k < r; ++k) a.q_next[(int64_t)inst * r + k] = st->q[k];
+  crom_step_info inf;
+  inf.flags = st->flags;
+  inf.iters = st->iters;
+  inf.ls_evals = st->ls_evals;
+  inf._pad = 0;
+  inf.obj_first = st->obj_first;
+  inf.obj_last = st->obj_last;
+  a.info[inst] = inf;
+}
+
+// ---------------------------------------------------------------------------
+template <class S, int NW, int PREC>
+static crom_status launch_step(const StepArgs& a, int rounds, hipStream_t st) {
+  using EJ = Engine<S, Cols<S::M, S::R, 1, true, D2_LAP, S::R>, 1, NW, PREC>;
+  using ET = Engine<S, Cols<S::M, S::R, TV, false, D2_NONE, S::R>, 1, NW, PREC>;
+  static_assert(EJ::LDS_BYTES <= 160 * 1024 && ET::LDS_BYTES <= 160 * 1024, "LDS");
+  static_assert(PT * S::R * 8 + PT * TV * 8 <= EJ::ACT_REGION, "staging fits");
+  static_assert(PT * S::R * 8 + PT * TV * 8 <= ET::ACT_REGION, "staging fits");
+  auto kj = eval_jets_kernel<S, NW, PREC>;
+  auto kt = eval_trials_kernel<S, NW, PREC>;
+  static bool attr = false;
+  if (!attr) {
+    crom_status s = set_lds(kj, EJ::LDS_BYTES);
+    if (s == CROM_OK) s = set_lds(kt, ET::LDS_BYTES);
+    if (s != CROM_OK) return s;
+    attr = true;
+  }
+  const unsigned nb = (unsigned)a.L.nblk_max;
+  hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(256), 0, st, a);
+  if (nb > 0) hipLaunchKernelGGL(kj, dim3(nb), dim3(NW * 64), EJ::LDS_BYTES, st, a);
+  hipLaunchKernelGGL(solve_kernel, dim3(a.n_inst), dim3(64), 0, st, a, rounds == 0 ? 1 : 0);
+  for (int i = 0; i < rounds; ++i) {
+    if (nb > 0) hipLaunchKernelGGL(kt, dim3(nb), dim3(NW * 64), ET::LDS_BYTES, st, a);
+    hipLaunchKernelGGL(solve_kernel, dim3(a.n_inst), dim3(64), 0, st, a, i == rounds - 1 ? 1 : 0);
+  }
+  return hip_check(hipGetLastError(), "step launch");
+}
+
+template <class S, int NW>
+static crom_status step_prec(int prec, const StepArgs& a, int rounds, hipStream_t st) {
+  if (prec == CROM_PREC_FP32) return launch_step<S, NW, PREC_FP32>(a, rounds, st);
+  if (prec == CROM_PREC_BF16) return launch_step<S, NW, PREC_BF16>(a, rounds, st);
+  return launch_step<S, NW, PREC_BF16X3>(a, rounds, st);
+}
+
+}  // namespace crom
+
+using namespace crom;
+
+extern "C" {
+
+crom_status crom_step_workspace(const crom_net* net, int32_t n_inst, int64_t total_samples,
+                                size_t* bytes) {
+  crom_status s = check_net(net, false);
+  if (s != CROM_OK) return s;
+  if (!bytes) return fail(CROM_ERR_INVALID_ARG, "bytes is NULL");
+  if (n_inst < 0 || total_samples < 0) return fail(CROM_ERR_INVALID_ARG, "negative size");
+  *bytes = ws_layout(net->r, net->d, n_inst, total_samples).total;
+  return CROM_OK;
+}
+
+const double* crom_step_targets(const crom_net* net, int32_t n_inst, int64_t total_samples,
+                                const void* ws) {
+  if (!net || !ws || n_inst < 0 || total_samples < 0) return nullptr;
+  WsLayout L = ws_layout(net->r, net->d, n_inst, total_samples);
+  return reinterpret_cast<const double*>(static_cast<const char*>(ws) + L.targets);
+}
+
+crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
+                      const int64_t* offsets, int64_t total_samples, const float* y,
+                      const uint8_t* clamp, const double* q_n, double* q_next,
+                      const crom_gn_opts* opts, crom_step_info* info, void* ws, size_t ws_bytes,
+                      void* stream) {
+  crom_status s = check_net(net, true);
+  if (s != CROM_OK) return s;
+  if (!pde || !opts) return fail(CROM_ERR_INVALID_ARG, "pde and opts are required");
+  if (pde->kind != CROM_PDE_HEAT) return fail(CROM_ERR_UNSUPPORTED, "pde kind");
+  if (net->d != 1) return fail(CROM_ERR_UNSUPPORTED, "the heat step needs d == 1");
+  if (net->r > RMAX) return fail(CROM_ERR_UNSUPPORTED, "r > 16");
+  if (n_inst < 0 || total_samples < 0) return fail(CROM_ERR_INVALID_ARG, "negative size");
+  if (n_inst == 0) return CROM_OK;
+  if (!offsets || !q_n || !q_next || !info || !pde->coef)
+    return fail(CROM_ERR_INVALID_ARG, "offsets, q_n, q_next, info and pde->coef are required");
+  if (total_samples > 0 && !y) return fail(CROM_ERR_INVALID_ARG, "y is NULL");
+  if (q_next == q_n) return fail(CROM_ERR_INVALID_ARG, "q_next must not alias q_n");
+  if (opts->max_iter < 1 || opts->ls_max < 0 || opts->launches < 0 || !(opts->tol_step >= 0.0) ||
+      !(opts->ls_shrink > 0.0 && opts->ls_shrink < 1.0) || !(opts->armijo_c >= 0.0))
+    return fail(CROM_ERR_INVALID_ARG, "gn opts out of range");
+  if (!(pde->dt > 0.0)) return fail(CROM_ERR_INVALID_ARG, "dt must be positive");
+  WsLayout L = ws_layout(net->r, net->d, n_inst, total_samples);
+  if (!ws || ws_bytes < L.total) return fail(CROM_ERR_WORKSPACE, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(CROM_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (L.nblk_max > 0x7fffffff) return fail(CROM_ERR_INVALID_ARG, "too many samples");
+  StepArgs a{};
+  a.params = net->params;
+  a.packed = static_cast<const char*>(net->packed);
+  a.pi = param_index(net->m, net->r, net->d, net->width, net->depth);
+  a.depth = net->depth;
+  a.r = net->r;
+  a.n_inst = n_inst;
+  a.total = total_samples;
+  a.offsets = offsets;
+  a.y = y;
+  a.clamp = clamp;
+  a.coef = pde->coef;
+  a.dt = pde->dt;
+  a.q_n = q_n;
+  a.q_next = q_next;
+  a.info = info;
+  a.ws = static_cast<char*>(ws);
+  a.L = L;
+  a.max_iter = opts->max_iter;
+  a.linearized = opts->linearized;
+  a.ls_max = opts->ls_max;
+  a.tol = opts->tol_step;
+  a.armijo_c = opts->armijo_c;
+  a.shrink = opts->ls_shrink;
+  const int rounds = opts->linearized ? 0 : (opts->launches > 0 ? opts->launches : opts->max_iter + 2);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (shape_id(net->m, net->r, net->d, net->width)) {
+    case SHAPE_1D: return step_prec<Shape<32, 1, 3, 1>, 2>(net->precision, a, rounds, st);
+    case SHAPE_2D: return step_prec<Shape<128, 2, 8, 1>, 4>(net->precision, a, rounds, st);
+    default: return fail(CROM_ERR_UNSUPPORTED, "shape");
+  }
+}
+
+}  // extern "C"

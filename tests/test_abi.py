@@ -1,0 +1,90 @@
+"""The C-ABI library loads, exports every entry point the header declares,
+and rejects bad arguments on the host before touching a GPU (no GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2206_02607_amd import crom
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "crom.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(crom_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    L = crom.lib()
+    names = _declared()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_param_count_formula():
+    # (m + r + 1) * w + (depth - 1) * (w + 1) * w + (w + 1) * d
+    for m, r, d, w, depth in ((1, 3, 1, 32, 5), (2, 8, 1, 128, 5), (3, 16, 3, 256, 6)):
+        expect = (m + r + 1) * w + (depth - 1) * (w + 1) * w + (w + 1) * d
+        assert crom.param_count(m, r, d, w, depth) == expect
+    assert crom.param_count(2, 8, 1, 128, 5) == 67585
+    assert crom.param_count(3, 16, 3, 256, 6) == 334851
+
+
+def _net(**kw):
+    base = dict(m=2, r=8, d=1, width=128, depth=5, precision=1, params=1 << 20, packed=1 << 21)
+    base.update(kw)
+    return crom.CromNet(*[base[k] for k, _ in crom.CromNet._fields_])
+
+
+def test_host_validation_before_launch():
+    L = crom.lib()
+    bad_shape = _net(width=96)
+    assert L.crom_decode(ctypes.byref(bad_shape), 1, 10, 1, 1, None) == 2
+    assert b"unsupported" in L.crom_last_error()
+    assert L.crom_decode(None, 1, 10, 1, 1, None) == 1
+    assert L.crom_decode(ctypes.byref(_net()), 1, -1, 1, 1, None) == 1
+    assert L.crom_decode(ctypes.byref(_net()), None, 10, 1, 1, None) == 1
+    assert L.crom_decode(ctypes.byref(_net(packed=None)), 1, 10, 1, 1, None) == 1
+    assert L.crom_decode(ctypes.byref(_net(precision=7)), 1, 10, 1, 1, None) == 2
+    # d2g given without a d2 mode, and the reverse
+    assert L.crom_decode_jac(ctypes.byref(_net()), 1, 10, 1, 0, 1, None, 1, None, None) == 1
+    assert L.crom_decode_jac(ctypes.byref(_net()), 1, 10, 1, 1, 1, None, None, None, None) == 1
+    assert L.crom_decode_jac_q(ctypes.byref(_net()), 1, 10, 1, 1, None, None) == 1
+
+
+def test_step_validation():
+    L = crom.lib()
+    n = ctypes.c_size_t(0)
+    assert L.crom_step_workspace(ctypes.byref(_net()), 4, 1000, ctypes.byref(n)) == 0
+    assert n.value > 1000 * 8
+    pde = crom.CromPDE(0, 0, 1e-4, 1 << 22)
+    opts = crom.GNOptions().c_struct()
+    args = dict(offsets=1 << 23, total=1000, y=1 << 24, clamp=None, qn=1 << 25, qnext=1 << 26,
+                info=1 << 27, ws=1 << 28, wsb=n.value)
+
+    def call(net=None, pde_=pde, opts_=opts, **kw):
+        a = dict(args)
+        a.update(kw)
+        return L.crom_step(ctypes.byref(net or _net()), ctypes.byref(pde_), 4, a["offsets"], a["total"],
+                           a["y"], a["clamp"], a["qn"], a["qnext"], ctypes.byref(opts_), a["info"],
+                           a["ws"], a["wsb"], None)
+
+    assert call(wsb=n.value - 1) == 3
+    assert call(ws=(1 << 28) + 8) == 3                     # misaligned workspace
+    assert call(qnext=1 << 25) == 1                        # aliasing q_n
+    assert call(net=_net(m=3, r=16, d=3, width=256, depth=6)) == 2   # heat needs d == 1
+    bad = crom.GNOptions(ls_shrink=1.5).c_struct()
+    assert call(opts_=bad) == 1
+    assert call(pde_=crom.CromPDE(0, 0, -1.0, 1 << 22)) == 1
+    assert call(pde_=crom.CromPDE(5, 0, 1e-4, 1 << 22)) == 2
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(crom, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(crom, "_lib", None)
+    with pytest.raises(crom.CromError):
+        crom.lib()

@@ -1,0 +1,148 @@
+"""Parity of the HIP decoder kernels with the CPU FP64 oracle (GPU).
+
+Every output column (value, dg/dx, Laplacian or Hessian, dg/dq) is compared
+element by element, normwise relative: 1e-5 in FP32, 2e-2 in BF16 (the
+tolerances the method's precision plan states), 1e-4 on BF16X3 values.
+Point counts span several 16-point batches and a ragged tail; the empty and
+one-point cases are covered too."""
+import numpy as np
+import pytest
+
+from conftest import normwise_rel
+from oracle import mlp
+from workloads import rng, uniform_points, xavier_mlp
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = {"1d": (1, 3, 1, 32, 5), "2d": (2, 8, 1, 128, 5), "3d": (3, 16, 3, 256, 6)}
+TOL = {"fp32": 1e-5, "bf16": 2e-2, "bf16x3": 2e-2}
+TOL_VALUE = {"fp32": 1e-5, "bf16": 2e-2, "bf16x3": 1e-4}
+
+
+def _case(shape, seed, P):
+    m, r, d, w, depth = SHAPES[shape]
+    g = rng(seed)
+    layers = xavier_mlp(g, m, r, d, w, depth, bias_scale=0.2)
+    x = uniform_points(g, P, m)
+    q = g.uniform(-1, 1, size=r)
+    return layers, x, q, m
+
+
+def _decoder(layers, m, prec):
+    from paper_2206_02607_amd import crom
+    return crom.Decoder.from_layers(layers, m, precision=prec, device="cuda:0")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("shape", ["1d", "2d", "3d"])
+def test_decode_values(cuda, shape, prec):
+    import torch
+    layers, x, q, m = _case(shape, 1, 16 * 7 + 5)
+    dec = _decoder(layers, m, prec)
+    g = dec.decode(torch.from_numpy(x).to(cuda), torch.from_numpy(q).to(cuda)).cpu().numpy()
+    ref = mlp.decode(layers, x, q)
+    err = normwise_rel(g, ref)
+    print(f"decode {shape} {prec}: {err:.2e}")
+    assert err <= TOL_VALUE[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("shape", ["1d", "2d", "3d"])
+def test_decode_jac_all_columns(cuda, shape, prec):
+    import torch
+    from paper_2206_02607_amd import crom
+    layers, x, q, m = _case(shape, 2, 16 * 5 + 9)
+    dec = _decoder(layers, m, prec)
+    d2 = crom.D2_LAPLACIAN if m == 1 else crom.D2_HESSIAN
+    if shape == "3d" and prec == "fp32":
+        d2 = crom.D2_LAPLACIAN          # FP32 activations of 10 columns at width 256 exceed LDS
+    xd, qd = torch.from_numpy(x).to(cuda), torch.from_numpy(q).to(cuda)
+    g, gx, h, gq = [t.cpu().numpy() for t in dec.decode_jac(xd, qd, dx=True, d2=d2, dq=True)]
+    og, ogx, oh, ogq = mlp.decode_jets(layers, x, q, m)
+    oh2 = mlp.laplacian(oh) if d2 == crom.D2_LAPLACIAN else mlp.hessian_packed(oh)
+    errs = dict(g=normwise_rel(g, og), gx=normwise_rel(gx, ogx),
+                d2=normwise_rel(h.reshape(oh2.shape), oh2), gq=normwise_rel(gq, ogq))
+    print(f"jac {shape} {prec}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    assert errs["g"] <= TOL_VALUE[prec]
+    for k in ("gx", "d2", "gq"):
+        assert errs[k] <= TOL[prec], k
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_decode_jac_x_and_q_entry_points(cuda, prec):
+    import torch
+    from paper_2206_02607_amd import crom
+    layers, x, q, m = _case("2d", 3, 100)
+    dec = _decoder(layers, m, prec)
+    xd, qd = torch.from_numpy(x).to(cuda), torch.from_numpy(q).to(cuda)
+    og, ogx, oh, ogq = mlp.decode_jets(layers, x, q, m)
+    g, gx, lap = dec.decode_jac_x(xd, qd, d2=crom.D2_LAPLACIAN)
+    assert normwise_rel(gx.cpu().numpy(), ogx) <= TOL[prec]
+    assert normwise_rel(lap.cpu().numpy().reshape(-1), mlp.laplacian(oh).reshape(-1)) <= TOL[prec]
+    g2, gq = dec.decode_jac_q(xd, qd)
+    assert normwise_rel(gq.cpu().numpy(), ogq) <= TOL[prec]
+    assert normwise_rel(g2.cpu().numpy(), og) <= TOL_VALUE[prec]
+    # the value written by every entry point is the same arithmetic
+    g3 = dec.decode(xd, qd)
+    assert torch.equal(g.cpu(), g3.cpu()) and torch.equal(g2.cpu(), g3.cpu())
+
+
+@pytest.mark.parametrize("P", [0, 1, 15, 16, 17])
+def test_decode_edge_sizes(cuda, P):
+    import torch
+    layers, x, q, m = _case("2d", 4, max(P, 1))
+    x = x[:P]
+    dec = _decoder(layers, m, "fp32")
+    g, gx, h, gq = dec.decode_jac(torch.from_numpy(x).to(cuda), torch.from_numpy(q).to(cuda),
+                                  dx=True, d2=1, dq=True)
+    assert g.shape == (P, 1)
+    if P:
+        og, ogx, oh, ogq = mlp.decode_jets(layers, x, q, m)
+        assert normwise_rel(g.cpu().numpy(), og) <= 1e-5
+        assert normwise_rel(gq.cpu().numpy(), ogq) <= 1e-5
+
+
+def test_full_field_decode_256x256(cuda):
+    """Full-field decode of the 65,536 nodes of a 256 x 256 grid (the size
+    the 2D heat benchmark times) against the oracle on every node."""
+    import torch
+    from workloads import Heat2D
+    wl = Heat2D(seed=0, bias_scale=0.1)
+    nodes = wl.nodes
+    ref = mlp.decode(wl.layers, nodes, wl.q0)
+    for prec in ("fp32", "bf16", "bf16x3"):
+        dec = _decoder(wl.layers, wl.m, prec)
+        g = dec.decode(torch.from_numpy(nodes).to(cuda), torch.from_numpy(wl.q0).to(cuda)).cpu().numpy()
+        err = normwise_rel(g, ref)
+        print(f"full field {prec}: {err:.2e}")
+        assert err <= TOL_VALUE[prec]
+
+
+def test_full_field_jac_sampled(cuda):
+    """All 12 columns at the 65,536 grid nodes; checked against the oracle
+    on a seeded sample of 2,048 nodes (the oracle's cost is per point)."""
+    import torch
+    from workloads import Heat2D
+    wl = Heat2D(seed=1, bias_scale=0.1)
+    nodes = wl.nodes
+    dec = _decoder(wl.layers, wl.m, "bf16")
+    g, gx, lap, gq = [t.cpu().numpy() for t in dec.decode_jac(
+        torch.from_numpy(nodes).to(cuda), torch.from_numpy(wl.q0).to(cuda), dx=True, d2=1, dq=True)]
+    idx = np.sort(rng(7).choice(len(nodes), 2048, replace=False))
+    og, ogx, oh, ogq = mlp.decode_jets(wl.layers, nodes[idx], wl.q0, wl.m)
+    assert normwise_rel(g[idx], og) <= 2e-2
+    assert normwise_rel(gx[idx], ogx) <= 2e-2
+    assert normwise_rel(lap[idx].reshape(-1), mlp.laplacian(oh).reshape(-1)) <= 2e-2
+    assert normwise_rel(gq[idx], ogq) <= 2e-2
+
+
+def test_deterministic_repeat(cuda):
+    import torch
+    layers, x, q, m = _case("2d", 5, 333)
+    dec = _decoder(layers, m, "bf16")
+    xd, qd = torch.from_numpy(x).to(cuda), torch.from_numpy(q).to(cuda)
+    a = [t.cpu() for t in dec.decode_jac(xd, qd, dx=True, d2=1, dq=True)]
+    for _ in range(3):
+        b = [t.cpu() for t in dec.decode_jac(xd, qd, dx=True, d2=1, dq=True)]
+        for u, v in zip(a, b):
+            assert torch.equal(u, v)
