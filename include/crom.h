@@ -57,16 +57,21 @@ typedef enum {
 } crom_status;
 
 /* Arithmetic of the hidden-to-hidden layers.
- *   FP32    FP32 operands and accumulation.
- *   BF16    operands rounded to bfloat16 (round to nearest even), products
- *           accumulated in FP32 on the matrix cores.
- *   BF16X3  value columns carry each operand as a sum of two bfloat16
- *           numbers (hi + lo) and take three products (hi*hi + hi*lo +
- *           lo*hi), about 16 significant bits; derivative columns as BF16.
+ *   FP32       FP32 operands and accumulation.
+ *   BF16       matrix-core products with FP32 accumulation.  Latent-tangent
+ *              columns (dg/dq) use bfloat16 operands (round to nearest
+ *              even).  Value, x-tangent and second-derivative columns carry
+ *              each operand as a sum of two bfloat16 numbers (hi + lo) and
+ *              take three products (hi*hi + hi*lo + lo*hi), about 16
+ *              significant bits: the inversion compares values at nearby
+ *              latents, and the Laplacian feeds the PDE update.
+ *   BF16_PURE  every column with plain bfloat16 operands (precision study;
+ *              values then carry errors of order 1e-2).
+ *   BF16X3     every column with split hi + lo operands.
  * The input layer, the ELU epilogues, the derivative recurrences and the
  * output layer are FP32 in every mode; the latent fold q -> W1q q + b1 is
  * accumulated in FP64. */
-enum { CROM_PREC_FP32 = 0, CROM_PREC_BF16 = 1, CROM_PREC_BF16X3 = 2 };
+enum { CROM_PREC_FP32 = 0, CROM_PREC_BF16 = 1, CROM_PREC_BF16_PURE = 2, CROM_PREC_BF16X3 = 3 };
 
 /* Second spatial derivatives requested from crom_decode_jac. */
 enum {
@@ -150,12 +155,15 @@ typedef struct {
  *   tol_step   stop when |alpha delta| or |delta| <= tol_step (1 + |q|)
  *   armijo_c   accept alpha when phi(q + alpha delta) <= phi(q) - c alpha b.delta
  *   ls_shrink  s in (0, 1)
- *   launches   number of evaluate/solve rounds enqueued after the first
- *              (0 = max_iter + 2).  Each round evaluates 4 line-search
- *              trials, so a step that needs more rounds than this ends with
- *              CROM_FLAG_MAXITER. */
+ *   max_rounds evaluation rounds after the first, 0 = enough for max_iter
+ *              iterations that each need the longest line search.  A round
+ *              evaluates 4 line-search trials (or re-linearises after a
+ *              shortened step); an instance still running after the last
+ *              round ends with CROM_FLAG_MAXITER.
+ * The step runs as one cooperative kernel whose workgroups are all resident
+ * on the GPU; it loops until every instance has finished. */
 typedef struct {
-  int32_t max_iter, linearized, ls_max, launches;
+  int32_t max_iter, linearized, ls_max, max_rounds;
   double tol_step, armijo_c, ls_shrink;
 } crom_gn_opts;
 
@@ -168,7 +176,10 @@ enum {
 
 /* Per-instance outcome (device memory, written by crom_step). */
 typedef struct {
-  int32_t flags, iters, ls_evals, _pad;
+  int32_t flags;    /* CROM_FLAG_* bits                                       */
+  int32_t iters;    /* accepted Gauss-Newton steps                            */
+  int32_t ls_evals; /* line-search trials examined, in order, up to acceptance */
+  int32_t rounds;   /* evaluation rounds after the first that this instance used */
   double obj_first, obj_last; /* 1/2 |f_{n+1} - g(Y, q)|^2 at q_n and at q_{n+1} */
 } crom_step_info;
 

@@ -18,11 +18,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcrom.so")
 
-PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2
+PREC_FP32, PREC_BF16, PREC_BF16_PURE, PREC_BF16X3 = 0, 1, 2, 3
 D2_NONE, D2_LAPLACIAN, D2_HESSIAN = 0, 1, 2
 PDE_HEAT = 0
 FLAG_MAXITER, FLAG_SINGULAR, FLAG_NONFINITE, FLAG_LS_FAIL = 1, 2, 4, 8
-_PREC_NAMES = {"fp32": PREC_FP32, "bf16": PREC_BF16, "bf16x3": PREC_BF16X3}
+_PREC_NAMES = {"fp32": PREC_FP32, "bf16": PREC_BF16, "bf16pure": PREC_BF16_PURE, "bf16x3": PREC_BF16X3}
 
 
 class CromNet(Structure):
@@ -37,11 +37,11 @@ class CromPDE(Structure):
 
 class CromGNOpts(Structure):
     _fields_ = [("max_iter", c_int32), ("linearized", c_int32), ("ls_max", c_int32),
-                ("launches", c_int32), ("tol_step", c_double), ("armijo_c", c_double),
+                ("max_rounds", c_int32), ("tol_step", c_double), ("armijo_c", c_double),
                 ("ls_shrink", c_double)]
 
 
-INFO_DTYPE = np.dtype([("flags", "<i4"), ("iters", "<i4"), ("ls_evals", "<i4"), ("_pad", "<i4"),
+INFO_DTYPE = np.dtype([("flags", "<i4"), ("iters", "<i4"), ("ls_evals", "<i4"), ("rounds", "<i4"),
                        ("obj_first", "<f8"), ("obj_last", "<f8")])
 
 _lib = None
@@ -229,10 +229,10 @@ class GNOptions:
     tol_step: float = 1e-6
     armijo_c: float = 1e-4
     ls_shrink: float = 0.5
-    launches: int = 0
+    max_rounds: int = 0
 
     def c_struct(self) -> CromGNOpts:
-        return CromGNOpts(self.max_iter, int(self.linearized), self.ls_max, self.launches,
+        return CromGNOpts(self.max_iter, int(self.linearized), self.ls_max, self.max_rounds,
                           self.tol_step, self.armijo_c, self.ls_shrink)
 
 

@@ -24,8 +24,7 @@ crom_status check_net(const crom_net* net, bool need_packed) {
   if (shape_id(net->m, net->r, net->d, net->width) == SHAPE_NONE)
     return fail(CROM_ERR_UNSUPPORTED,
                 "unsupported (m, r, d, width); compiled: (1,3,1,32), (2,8,1,128), (3,16,3,256)");
-  if (net->precision != CROM_PREC_FP32 && net->precision != CROM_PREC_BF16 &&
-      net->precision != CROM_PREC_BF16X3)
+  if (net->precision < CROM_PREC_FP32 || net->precision > CROM_PREC_BF16X3)
     return fail(CROM_ERR_UNSUPPORTED, "unknown precision");
   if (!net->params) return fail(CROM_ERR_INVALID_ARG, "net->params is NULL");
   if (need_packed && net->depth > 1 && !net->packed)
@@ -96,11 +95,12 @@ __global__ __launch_bounds__(NW * 64) void decode_kernel(DecodeArgs a) {
   const int64_t first = (int64_t)blockIdx.x * E::NPTS;
   const int64_t rem = a.P - first;
   const int n_valid = rem < E::NPTS ? (int)rem : E::NPTS;
-  E::stage(lds, a.x, first, n_valid, a.q, S::R, a.params, a.pi);
+  E::stage(lds, a.x, first, n_valid, a.q, S::R, nullptr, 0, a.params, a.pi);
   __syncthreads();
   E::run(lds, a.params, a.pi, a.packed, a.depth, a.qb);
   const float* res = reinterpret_cast<const float*>(lds + E::RES_OFF);
   constexpr int D = S::D, M = S::M, R = S::R;
+  constexpr int NHT = M * (M + 1) / 2;  // Hessian entries per output
   for (int i = threadIdx.x; i < D * E::NT * PT; i += E::THREADS) {
     const int oo = i / (E::NT * PT);
     const int t = (i / PT) % E::NT;
@@ -118,8 +118,8 @@ __global__ __launch_bounds__(NW * 64) void decode_kernel(DecodeArgs a) {
     } else if (k == CK_LAP) {
       a.d2g[p * D + oo] = v;
     } else if (k == CK_HESS) {
-      a.d2g[(p * D + oo) * C::ND2 + (c - C::D0)] = v;
-    } else {
+      a.d2g[(p * D + oo) * NHT + C::HB + (c - C::D0)] = v;
+    } else if (k == CK_QT) {
       a.dgdq[(p * D + oo) * R + a.qb + (c - C::Q0)] = v;
     }
   }
@@ -130,88 +130,94 @@ static crom_status launch_decode(const DecodeArgs& a, hipStream_t st) {
   using E = Engine<S, C, NB, NW, PREC>;
   if constexpr (E::LDS_BYTES > 160 * 1024) {
     return fail(CROM_ERR_UNSUPPORTED, "column set does not fit in LDS at this width/precision");
+  } else {
+    auto k = decode_kernel<S, C, NB, NW, PREC>;
+    static bool attr = false;
+    if (!attr) {
+      crom_status s = set_lds(k, E::LDS_BYTES);
+      if (s != CROM_OK) return s;
+      attr = true;
+    }
+    const int64_t blocks = (a.P + E::NPTS - 1) / E::NPTS;
+    if (blocks > 0x7fffffff) return fail(CROM_ERR_INVALID_ARG, "P too large");
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(E::THREADS), E::LDS_BYTES, st, a);
+    return hip_check(hipGetLastError(), "decode launch");
   }
-  auto k = decode_kernel<S, C, NB, NW, PREC>;
-  static bool attr = false;
-  if (!attr) {
-    crom_status s = set_lds(k, E::LDS_BYTES);
-    if (s != CROM_OK) return s;
-    attr = true;
-  }
-  if (a.P == 0) return CROM_OK;
-  const int64_t blocks = (a.P + E::NPTS - 1) / E::NPTS;
-  if (blocks > 0x7fffffff) return fail(CROM_ERR_INVALID_ARG, "P too large");
-  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(E::THREADS), E::LDS_BYTES, st, a);
-  return hip_check(hipGetLastError(), "decode launch");
 }
 
-// Column request of one pass.
-struct Pass {
-  bool xt;
-  int d2;
-  int nq, qb;
-};
-
-template <class S, int NW, int PREC, bool XT, int D2, int NQ>
+// One pass over the points with a fixed column set (value first).
+template <class S, int NW, int PREC, bool XT, int D2, int NQ, int HB = 0,
+          int NH = S::M * (S::M + 1) / 2>
 static crom_status run_pass(const DecodeArgs& a, hipStream_t st) {
   if constexpr (!XT && D2 == D2_NONE && NQ == 0) {
-    using C = Cols<S::M, S::R, 1, false, D2_NONE, 0>;
-    return launch_decode<S, C, 4, NW, PREC>(a, st);
+    using C = Cols<S::M, S::R, 1, 0, false, D2_NONE, 0>;
+    return launch_decode<S, C, 4, NW, PREC>(a, st);  // 64 points per workgroup
   } else {
-    using C = Cols<S::M, S::R, 1, XT, D2, NQ>;
+    using C = Cols<S::M, S::R, 1, 0, XT, D2, NQ, HB, NH>;
     return launch_decode<S, C, 1, NW, PREC>(a, st);
   }
 }
 
-// Dispatch of a pass to the compiled column sets.  NQ is either 0 or the
-// per-pass chunk QC of the shape.
-template <class S, int NW, int PREC, int QC>
-static crom_status dispatch_pass(const Pass& p, const DecodeArgs& a, hipStream_t st) {
-  const bool q = p.nq > 0;
-  if (q && p.nq != QC) return fail(CROM_ERR_UNSUPPORTED, "internal: q chunk");
-#define CROM_CASE(XT, D2)                                                        \
-  if (p.xt == XT && p.d2 == D2) {                                                \
-    return q ? run_pass<S, NW, PREC, XT, D2, QC>(a, st) : run_pass<S, NW, PREC, XT, D2, 0>(a, st); \
+// Hessian entries in chunks of HC (x tangents recomputed per chunk).
+template <class S, int NW, int PREC, int HC, int HB>
+static crom_status hess_chunks(const DecodeArgs& a, hipStream_t st) {
+  constexpr int NHT = S::M * (S::M + 1) / 2;
+  if constexpr (HB >= NHT) {
+    return CROM_OK;
+  } else {
+    constexpr int NH = (NHT - HB) < HC ? (NHT - HB) : HC;
+    crom_status s = run_pass<S, NW, PREC, true, D2_HESS, 0, HB, NH>(a, st);
+    if (s != CROM_OK) return s;
+    return hess_chunks<S, NW, PREC, HC, HB + HC>(a, st);
   }
-  CROM_CASE(false, D2_NONE)
-  CROM_CASE(true, D2_NONE)
-  CROM_CASE(true, D2_LAP)
-  if constexpr (S::M > 1) {
-    CROM_CASE(true, D2_HESS)
-  }
-#undef CROM_CASE
-  return fail(CROM_ERR_UNSUPPORTED, "unsupported derivative column set");
 }
 
-// Plans the passes of a request so that each pass's activations fit in LDS:
-// the x tangents and second-derivative columns go together (the second
-// derivatives need the x tangents' pre-activations); the latent tangents
-// are split into chunks of QC.  Every pass also writes the values, with
-// identical results.
-template <class S, int NW, int PREC, int QC>
+// Plans the passes of a request.  Narrow nets (width <= 128) take every
+// column in one pass.  At width 256 the activations of all columns would not
+// fit in LDS, so the x tangents with the second derivatives form one pass
+// (Hessian entries in chunks of HC: they need the x tangents'
+// pre-activations in the same pass), and the latent tangents follow in
+// chunks of QC.  Every pass rewrites the values, with identical results.
+template <class S, int NW, int PREC, int QC, int HC>
 static crom_status decode_shape(const DecodeArgs& a0, bool xt, int d2, bool qt, hipStream_t st) {
   DecodeArgs a = a0;
   const bool spatial = xt || d2 != D2_NONE;
-  if (S::R <= QC) return dispatch_pass<S, NW, PREC, QC>(Pass{spatial, d2, qt ? QC : 0, 0}, a, st);
-  if (spatial || !qt) {
-    crom_status s = dispatch_pass<S, NW, PREC, QC>(Pass{spatial, d2, 0, 0}, a, st);
-    if (s != CROM_OK) return s;
-  }
-  if (qt) {
+  if constexpr (S::W <= 128) {
+#define CROM_ONE(XT, D2)                                                                  \
+    if (spatial == XT && d2 == D2)                                                        \
+      return qt ? run_pass<S, NW, PREC, XT, D2, S::R>(a, st) : run_pass<S, NW, PREC, XT, D2, 0>(a, st);
+    CROM_ONE(false, D2_NONE)
+    CROM_ONE(true, D2_NONE)
+    CROM_ONE(true, D2_LAP)
+    if constexpr (S::M > 1) {
+      CROM_ONE(true, D2_HESS)
+    }
+#undef CROM_ONE
+    return fail(CROM_ERR_UNSUPPORTED, "unsupported derivative column set");
+  } else {
+    crom_status s = CROM_OK;
+    if (d2 == D2_HESS) s = hess_chunks<S, NW, PREC, HC, 0>(a, st);
+    else if (d2 == D2_LAP) s = run_pass<S, NW, PREC, true, D2_LAP, 0>(a, st);
+    else if (xt) s = run_pass<S, NW, PREC, true, D2_NONE, 0>(a, st);
+    else if (!qt) s = run_pass<S, NW, PREC, false, D2_NONE, 0>(a, st);
+    if (s != CROM_OK || !qt) return s;
     for (int qb = 0; qb < S::R; qb += QC) {
       a.qb = qb;
-      crom_status s = dispatch_pass<S, NW, PREC, QC>(Pass{false, D2_NONE, QC, qb}, a, st);
+      s = run_pass<S, NW, PREC, false, D2_NONE, QC>(a, st);
       if (s != CROM_OK) return s;
     }
+    return CROM_OK;
   }
-  return CROM_OK;
 }
 
-template <class S, int NW, int QC32, int QC16>
+template <class S, int NW>
 static crom_status decode_prec(int prec, const DecodeArgs& a, bool xt, int d2, bool qt, hipStream_t st) {
-  if (prec == CROM_PREC_FP32) return decode_shape<S, NW, PREC_FP32, QC32>(a, xt, d2, qt, st);
-  if (prec == CROM_PREC_BF16) return decode_shape<S, NW, PREC_BF16, QC16>(a, xt, d2, qt, st);
-  return decode_shape<S, NW, PREC_BF16X3, QC16>(a, xt, d2, qt, st);
+  switch (prec) {
+    case CROM_PREC_FP32: return decode_shape<S, NW, PREC_FP32, 4, 3>(a, xt, d2, qt, st);
+    case CROM_PREC_BF16: return decode_shape<S, NW, PREC_BF16, 8, 3>(a, xt, d2, qt, st);
+    case CROM_PREC_BF16_PURE: return decode_shape<S, NW, PREC_BF16_PURE, 8, 6>(a, xt, d2, qt, st);
+    default: return decode_shape<S, NW, PREC_BF16X3, 8, 3>(a, xt, d2, qt, st);
+  }
 }
 
 static crom_status decode_any(const crom_net* net, const float* x, int64_t P, const double* q,
@@ -220,13 +226,14 @@ static crom_status decode_any(const crom_net* net, const float* x, int64_t P, co
   crom_status s = check_net(net, true);
   if (s != CROM_OK) return s;
   if (P < 0) return fail(CROM_ERR_INVALID_ARG, "P < 0");
-  if (P > 0 && (!x || !q || !g)) return fail(CROM_ERR_INVALID_ARG, "x, q and g are required");
   if (d2_mode < CROM_D2_NONE || d2_mode > CROM_D2_HESSIAN)
     return fail(CROM_ERR_INVALID_ARG, "d2_mode");
-  if ((d2_mode != CROM_D2_NONE) != (d2g != nullptr))
-    return fail(CROM_ERR_INVALID_ARG, "d2g must be given iff d2_mode != NONE");
   if (d2_mode == CROM_D2_HESSIAN && net->m == 1)
     return fail(CROM_ERR_INVALID_ARG, "m = 1: use CROM_D2_LAPLACIAN");
+  if (P == 0) return CROM_OK;  // nothing to do; output pointers may be NULL
+  if (!x || !q || !g) return fail(CROM_ERR_INVALID_ARG, "x, q and g are required");
+  if ((d2_mode != CROM_D2_NONE) != (d2g != nullptr))
+    return fail(CROM_ERR_INVALID_ARG, "d2g must be given iff d2_mode != NONE");
   DecodeArgs a{};
   a.x = x;
   a.P = P;
@@ -245,9 +252,9 @@ static crom_status decode_any(const crom_net* net, const float* x, int64_t P, co
   const bool qt = dgdq != nullptr;
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (shape_id(net->m, net->r, net->d, net->width)) {
-    case SHAPE_1D: return decode_prec<Shape<32, 1, 3, 1>, 2, 3, 3>(net->precision, a, xt, d2, qt, st);
-    case SHAPE_2D: return decode_prec<Shape<128, 2, 8, 1>, 4, 8, 8>(net->precision, a, xt, d2, qt, st);
-    case SHAPE_3D: return decode_prec<Shape<256, 3, 16, 3>, 8, 4, 8>(net->precision, a, xt, d2, qt, st);
+    case SHAPE_1D: return decode_prec<Shape<32, 1, 3, 1>, 2>(net->precision, a, xt, d2, qt, st);
+    case SHAPE_2D: return decode_prec<Shape<128, 2, 8, 1>, 4>(net->precision, a, xt, d2, qt, st);
+    case SHAPE_3D: return decode_prec<Shape<256, 3, 16, 3>, 8>(net->precision, a, xt, d2, qt, st);
     default: return fail(CROM_ERR_UNSUPPORTED, "shape");
   }
 }

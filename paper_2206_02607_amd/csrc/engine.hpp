@@ -9,9 +9,17 @@
 //   D2z_l = W_l D2a_{l-1},    D2a_l = s2(z_l) dz_i dz_j + s1(z_l) D2z_l
 // with s1 = ELU', s2 = ELU''; the Laplacian column carries sum_i of the
 // diagonal second derivatives in one column (s2 * sum_i dz_i^2 + s1 * D2z).
+// Difference columns carry g(x, q_t) - g(x, q_b) for latents q_t near the
+// value column's latent q_b, layer by layer as
+//   Dz_l = W_l Da_{l-1},      Da_l = ELU(z_l + Dz_l) - ELU(z_l),
+// evaluated without cancellation (e^z expm1(Dz) on the exponential branch),
+// so their rounding error is relative to the difference itself.  The latent
+// tangents then belong to the first difference column's latent
+// (z_l + Dz_l); without difference columns, to the value column's.
 // The first layer is folded: W_1 [x; q] + b_1 = W_1x x + c with the per-
 // latent bias c = W_1q q + b_1 (FP64), so its tangents are columns of W_1
-// and its second derivatives are zero.  The output layer is linear.
+// and its second derivatives are zero; a difference column starts from
+// W_1q (q_t - q_b).  The output layer is linear.
 //
 // Layout.  Points are the MFMA N dimension, 16 points per N-tile; every
 // derivative column of a batch of 16 points is one more N-tile, so the
@@ -37,8 +45,14 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int PT = 16;  // points per N-tile
 
-enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2 };
-enum { CK_VAL = 0, CK_XT = 1, CK_LAP = 2, CK_HESS = 3, CK_QT = 4 };
+// Arithmetic of the hidden-to-hidden layers (see crom.h):
+//   FP32      FP32 MFMA
+//   BF16      split hi+lo operands on value and spatial-derivative columns,
+//             plain bfloat16 on difference and latent-tangent columns
+//   BF16_PURE plain bfloat16 everywhere
+//   BF16X3    split hi+lo operands on every column
+enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_BF16_PURE = 2, PREC_BF16X3 = 3 };
+enum { CK_VAL = 0, CK_DIFF = 1, CK_XT = 2, CK_LAP = 3, CK_HESS = 4, CK_QT = 5 };
 enum { D2_NONE = 0, D2_LAP = 1, D2_HESS = 2 };
 
 template <int W_, int M_, int R_, int D_>
@@ -48,33 +62,55 @@ struct Shape {
   static constexpr int N0 = M_ + R_;
 };
 
-// Columns of one batch of 16 points: NV value columns (value 0 is the point
-// the derivative columns belong to; values 1.. are extra latents, e.g. line-
-// search trials), then the x tangents, the second-derivative columns and
-// NQ latent tangents (latent indices qb .. qb+NQ-1, qb given at run time).
-template <int M_, int R_, int NV_, bool XT_, int D2_, int NQ_>
+// Columns of one batch of 16 points, in this order:
+//   NV value columns (value 0 is the base latent of the derivative columns),
+//   ND difference columns (latents q_t relative to value 0's latent),
+//   the M x tangents (when XT or any second derivative is requested),
+//   the second-derivative columns (Laplacian, or Hessian entries HB..HB+NH-1
+//   of the upper triangle, row-major),
+//   NQ latent tangents (latent indices qb .. qb+NQ-1, qb given at run time).
+template <int M_, int R_, int NV_, int ND_, bool XT_, int D2_, int NQ_, int HB_ = 0,
+          int NH_ = M_ * (M_ + 1) / 2>
 struct Cols {
-  static constexpr int M = M_, R = R_, NV = NV_, D2 = D2_;
+  static constexpr int M = M_, R = R_, NV = NV_, ND = ND_, D2 = D2_, HB = HB_;
   static constexpr int NX = (XT_ || D2_ != D2_NONE) ? M_ : 0;
-  static constexpr int ND2 = D2_ == D2_LAP ? 1 : (D2_ == D2_HESS ? M_ * (M_ + 1) / 2 : 0);
+  static constexpr int ND2 = D2_ == D2_LAP ? 1 : (D2_ == D2_HESS ? NH_ : 0);
   static constexpr int NQ = NQ_;
-  static constexpr int C = NV + NX + ND2 + NQ;
-  static constexpr int X0 = NV, D0 = NV + NX, Q0 = NV + NX + ND2;
+  static constexpr int C = NV + ND + NX + ND2 + NQ;
+  static constexpr int F0 = NV, X0 = NV + ND, D0 = NV + ND + NX, Q0 = NV + ND + NX + ND2;
   __host__ __device__ static constexpr int kind(int c) {
-    return c < X0 ? CK_VAL : c < D0 ? CK_XT : c < Q0 ? (D2_ == D2_LAP ? CK_LAP : CK_HESS) : CK_QT;
+    return c < F0 ? CK_VAL
+         : c < X0 ? CK_DIFF
+         : c < D0 ? CK_XT
+         : c < Q0 ? (D2_ == D2_LAP ? CK_LAP : CK_HESS)
+                  : CK_QT;
   }
-  // Hessian column k -> (i, j), upper triangle i <= j, row-major.
-  __host__ __device__ static constexpr int hess_i(int k) {
-    int i = 0, n = M_;
+  // Hessian column c -> (i, j) of the upper triangle i <= j (row-major).
+  __host__ __device__ static constexpr int hess_i(int c) {
+    int k = c - D0 + HB_, i = 0, n = M_;
     while (k >= n) { k -= n; ++i; --n; }
     return i;
   }
-  __host__ __device__ static constexpr int hess_j(int k) {
-    int i = 0, n = M_;
+  __host__ __device__ static constexpr int hess_j(int c) {
+    int k = c - D0 + HB_, i = 0, n = M_;
     while (k >= n) { k -= n; ++i; --n; }
     return i + k;
   }
 };
+
+template <class C, int PREC>
+__host__ __device__ constexpr bool is_split(int c) {
+  return PREC == PREC_BF16X3 ||
+         (PREC == PREC_BF16 && (C::kind(c) == CK_VAL || C::kind(c) == CK_XT ||
+                                C::kind(c) == CK_LAP || C::kind(c) == CK_HESS));
+}
+
+template <class C, int PREC>
+__host__ __device__ constexpr int n_split_before(int c) {
+  int n = 0;
+  for (int i = 0; i < c; ++i) n += is_split<C, PREC>(i) ? 1 : 0;
+  return n;
+}
 
 template <class S, int PREC>
 struct Packing {
@@ -92,12 +128,20 @@ struct ParamIndex {
   int64_t w[16], b[16];
 };
 
-__device__ __forceinline__ float elu_exp(float z) { return __expf(fminf(z, 0.0f)); }
+// e^min(z, 0), written so that a NaN z stays NaN (fminf would drop it).
+__device__ __forceinline__ float elu_exp(float z) { return __expf(z > 0.0f ? 0.0f : z); }
+
+// e^x - 1 without cancellation: Taylor series (6 terms, relative error
+// below 2e-12 for |x| < 1/32) near 0, e^x - 1 beyond.
+__device__ __forceinline__ float expm1_acc(float x) {
+  const float p = x * (1.0f + x * (0.5f + x * (1.0f / 6 + x * (1.0f / 24 + x * (1.0f / 120)))));
+  return fabsf(x) < 0.03125f ? p : __expf(x) - 1.0f;
+}
 
 // All per-batch tables live in one dynamic LDS block:
-//   act    activations (fragment order), NT (+ lo tiles) tiles
+//   act    activations (fragment order): NT tiles, then the lo tiles
 //   xs     [NB*16][M] points (FP32)
-//   fold   [NV][W] per-latent first-layer bias (FP32)
+//   fold   [NV + ND][W] per-latent first-layer terms (FP32)
 //   res    [D][NT][16] outputs (FP32)
 // The cross-wave output reduction reuses `act`.
 template <class S, class C, int NB, int NW, int PREC>
@@ -105,34 +149,37 @@ struct Engine {
   static constexpr int W = S::W, M = S::M, R = S::R, D = S::D;
   static constexpr int CC = C::C;
   static constexpr int NT = NB * CC;
-  static constexpr int NVT = NB * C::NV;  // value tiles (split in BF16X3)
   static constexpr int MTILES = S::MTILES;
   static constexpr int MT = MTILES / NW;
   static_assert(MTILES % NW == 0, "waves must split the M-tiles evenly");
   static constexpr int NPTS = NB * PT;
-  static constexpr bool SPLIT = PREC == PREC_BF16X3;
+  static constexpr bool BF = PREC != PREC_FP32;
+  static constexpr int SPB = n_split_before<C, PREC>(CC);  // split columns per batch
+  static constexpr int NSPL = BF ? NB * SPB : 0;
   static constexpr int KQ = Packing<S, PREC>::KQ;
-  // activation tiles: every column, plus a lo tile per value column in split mode
-  static constexpr int NACT = NT + (SPLIT ? NVT : 0);
+  static constexpr int NACT = NT + NSPL;
   static constexpr int ACT_BYTES = NACT * KQ * 64 * 16;
   static constexpr int RED_BYTES = NW * D * NT * PT * 4;
   static constexpr int ACT_REGION = ACT_BYTES > RED_BYTES ? ACT_BYTES : RED_BYTES;
   static constexpr int XS_OFF = ACT_REGION;
+  static constexpr int NF = C::NV + C::ND;
   static constexpr int FOLD_OFF = XS_OFF + ((NPTS * M * 4 + 15) / 16) * 16;
-  static constexpr int RES_OFF = FOLD_OFF + C::NV * W * 4;
+  static constexpr int RES_OFF = FOLD_OFF + NF * W * 4;
   static constexpr int LDS_BYTES = RES_OFF + D * NT * PT * 4;
   static constexpr int THREADS = NW * 64;
 
-  static __device__ __forceinline__ int tile_of(int b, int c) { return b * CC + c; }
-  // lo tile of value tile (b, v) in split mode
-  static __device__ __forceinline__ int lo_tile(int b, int v) { return NT + b * C::NV + v; }
+  static __host__ __device__ constexpr int lo_tile(int b, int c) {
+    return NT + b * SPB + n_split_before<C, PREC>(c);
+  }
 
-  // ---- stage points and per-latent fold -------------------------------
+  // ---- stage points and per-latent first-layer terms --------------------
   // Points first .. first+n_valid-1 of x (n_valid <= NPTS; the rest of the
-  // batch is padded with x = 0); lat: NV latent vectors, vector v at
-  // lat + v * lat_stride, FP64.
+  // batch is padded with x = 0).  lat: NV latent vectors (v at lat + v *
+  // lat_stride), folded with the bias; dlat: ND latent differences (t at
+  // dlat + t * dlat_stride), folded without it.  FP64.
   static __device__ void stage(char* lds, const float* __restrict__ x, int64_t first, int n_valid,
                                const double* __restrict__ lat, int lat_stride,
+                               const double* __restrict__ dlat, int dlat_stride,
                                const float* __restrict__ params, const ParamIndex& pi) {
     float* xs = reinterpret_cast<float*>(lds + XS_OFF);
     for (int i = threadIdx.x; i < NPTS * M; i += THREADS) {
@@ -142,11 +189,17 @@ struct Engine {
     float* fold = reinterpret_cast<float*>(lds + FOLD_OFF);
     const float* W1 = params + pi.w[0];
     const float* b1 = params + pi.b[0];
-    for (int i = threadIdx.x; i < C::NV * W; i += THREADS) {
-      int v = i / W, u = i - v * W;
-      double s = (double)b1[u];
-#pragma unroll
-      for (int k = 0; k < R; ++k) s += (double)W1[u * (M + R) + M + k] * lat[v * lat_stride + k];
+    for (int i = threadIdx.x; i < NF * W; i += THREADS) {
+      const int v = i / W, u = i - v * W;
+      double s;
+      if (v < C::NV) {
+        s = (double)b1[u];
+        for (int k = 0; k < R; ++k) s += (double)W1[u * (M + R) + M + k] * lat[v * lat_stride + k];
+      } else {
+        s = 0.0;
+        const double* dl = dlat + (v - C::NV) * dlat_stride;
+        for (int k = 0; k < R; ++k) s += (double)W1[u * (M + R) + M + k] * dl[k];
+      }
       fold[i] = (float)s;
     }
   }
@@ -156,35 +209,53 @@ struct Engine {
   static __device__ __forceinline__ void epilogue(const float (&z)[NT], float (&o)[NT]) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      float s1 = 1.0f, s2 = 0.0f;
+      const float* zb = &z[b * CC];
+      float* ob = &o[b * CC];
+      float s1 = 1.0f, s2 = 0.0f, e0 = 1.0f;
+      bool pos0 = true;
 #pragma unroll
       for (int c = 0; c < C::NV; ++c) {
-        const float zz = z[b * CC + c];
+        const float zz = zb[c];
         const float e = elu_exp(zz);
         const bool pos = zz > 0.0f;
-        o[b * CC + c] = pos ? zz : e - 1.0f;
+        ob[c] = pos ? zz : e - 1.0f;
         if (c == 0) {
           s1 = pos ? 1.0f : e;
           s2 = pos ? 0.0f : e;
+          e0 = e;
+          pos0 = pos;
         }
       }
+      float st = s1;  // tangent scale: at the base latent, or at difference column 0's
 #pragma unroll
-      for (int c = C::X0; c < C::D0; ++c) o[b * CC + c] = s1 * z[b * CC + c];
+      for (int c = C::F0; c < C::X0; ++c) {
+        const float dz = zb[c];
+        const float zt = zb[0] + dz;
+        const bool post = zt > 0.0f;
+        const float et = elu_exp(zt);
+        const float both_pos = dz;
+        const float both_neg = e0 * expm1_acc(dz);
+        const float cross = (post ? zt : et - 1.0f) - (pos0 ? zb[0] : e0 - 1.0f);
+        ob[c] = (pos0 && post) ? both_pos : ((!pos0 && !post) ? both_neg : cross);
+        if (c == C::F0) st = post ? 1.0f : et;
+      }
+#pragma unroll
+      for (int c = C::X0; c < C::D0; ++c) ob[c] = s1 * zb[c];
       if constexpr (C::D2 == D2_LAP) {
         float sq = 0.0f;
 #pragma unroll
-        for (int i = 0; i < C::NX; ++i) sq += z[b * CC + C::X0 + i] * z[b * CC + C::X0 + i];
-        o[b * CC + C::D0] = s1 * z[b * CC + C::D0] + s2 * sq;
+        for (int i = 0; i < C::NX; ++i) sq += zb[C::X0 + i] * zb[C::X0 + i];
+        ob[C::D0] = s1 * zb[C::D0] + s2 * sq;
       } else if constexpr (C::D2 == D2_HESS) {
 #pragma unroll
-        for (int k = 0; k < C::ND2; ++k) {
-          const float zi = z[b * CC + C::X0 + C::hess_i(k)];
-          const float zj = z[b * CC + C::X0 + C::hess_j(k)];
-          o[b * CC + C::D0 + k] = s1 * z[b * CC + C::D0 + k] + s2 * zi * zj;
+        for (int c = C::D0; c < C::Q0; ++c) {
+          const float zi = zb[C::X0 + C::hess_i(c)];
+          const float zj = zb[C::X0 + C::hess_j(c)];
+          ob[c] = s1 * zb[c] + s2 * zi * zj;
         }
       }
 #pragma unroll
-      for (int c = C::Q0; c < CC; ++c) o[b * CC + c] = s1 * z[b * CC + c];
+      for (int c = C::Q0; c < CC; ++c) ob[c] = st * zb[c];
     }
   }
 
@@ -210,16 +281,14 @@ struct Engine {
         h[2] = (__bf16)o[t][2];
         h[3] = (__bf16)o[t][3];
         act[((t * KQ + (mtg >> 1)) * 64 + lane) * 2 + half] = h;
-        if constexpr (SPLIT) {
-          const int b = t / CC, c = t - (t / CC) * CC;
-          if (c < C::NV) {
-            bf16x4 l;
-            l[0] = (__bf16)(o[t][0] - (float)h[0]);
-            l[1] = (__bf16)(o[t][1] - (float)h[1]);
-            l[2] = (__bf16)(o[t][2] - (float)h[2]);
-            l[3] = (__bf16)(o[t][3] - (float)h[3]);
-            act[((lo_tile(b, c) * KQ + (mtg >> 1)) * 64 + lane) * 2 + half] = l;
-          }
+        const int b = t / CC, c = t % CC;
+        if (BF && is_split<C, PREC>(c)) {
+          bf16x4 l;
+          l[0] = (__bf16)(o[t][0] - (float)h[0]);
+          l[1] = (__bf16)(o[t][1] - (float)h[1]);
+          l[2] = (__bf16)(o[t][2] - (float)h[2]);
+          l[3] = (__bf16)(o[t][3] - (float)h[3]);
+          act[((lo_tile(b, c) * KQ + (mtg >> 1)) * 64 + lane) * 2 + half] = l;
         }
       }
     }
@@ -284,6 +353,7 @@ struct Engine {
               const int k = C::kind(c);
               float val;
               if (k == CK_VAL) val = lin + fold[c * W + u];
+              else if (k == CK_DIFF) val = fold[c * W + u];
               else if (k == CK_XT) val = wx[c - C::X0];
               else if (k == CK_QT) val = W1[u * (M + R) + M + qb + (c - C::Q0)];
               else val = 0.0f;
@@ -312,7 +382,7 @@ struct Engine {
         const f32x4 bv = {bp[0], bp[1], bp[2], bp[3]};
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          const bool isval = (t % CC) < C::NV;
+          const bool isval = C::kind(t % CC) == CK_VAL;
           acc[mt][t] = isval ? bv : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         }
       }
@@ -352,17 +422,18 @@ struct Engine {
             for (int mt = 0; mt < MT; ++mt)
               acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bfr, acc[mt][t], 0, 0, 0);
           }
-          if constexpr (SPLIT) {
+          if constexpr (NSPL > 0) {
             bf16x8 al[MT];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) al[mt] = wf[LO + ((wave * MT + mt) * KQ + kb) * 64 + lane];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
 #pragma unroll
-              for (int v = 0; v < C::NV; ++v) {
-                const int t = b * CC + v;
+              for (int c = 0; c < CC; ++c) {
+                if (!is_split<C, PREC>(c)) continue;
+                const int t = b * CC + c;
                 const bf16x8 bh = act[(t * KQ + kb) * 64 + lane];
-                const bf16x8 bl = act[(lo_tile(b, v) * KQ + kb) * 64 + lane];
+                const bf16x8 bl = act[(lo_tile(b, c) * KQ + kb) * 64 + lane];
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                   acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bl, acc[mt][t], 0, 0, 0);
@@ -417,7 +488,7 @@ struct Engine {
     for (int i = threadIdx.x; i < D * NT * PT; i += THREADS) {
       const int oo = i / (NT * PT);
       const int t = (i / PT) % NT;
-      float s = ((t % CC) < C::NV) ? bout[oo] : 0.0f;
+      float s = C::kind(t % CC) == CK_VAL ? bout[oo] : 0.0f;
 #pragma unroll
       for (int w = 0; w < NW; ++w) s += red[w * D * NT * PT + i];
       res[i] = s;

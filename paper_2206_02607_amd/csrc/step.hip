@@ -2,20 +2,33 @@
 // Latent Space Dynamics"; Alg. "Latent-space dynamics", "Network inference",
 // "Network inversion"; Sec. "Network Inversion", "Linearization").
 //
-// Kernels, in launch order (all on the caller's stream, no host sync):
-//   setup        block map (16-sample batches of every instance), state init
-//   eval_jets    value, x tangents, Laplacian and latent Jacobian at q_n;
-//                heat update f_{n+1} = g + dt nu Lap g (FP64), residual
-//                rho = f_{n+1} - g, and per-batch partial sums of
-//                J^T J, J^T rho and 1/2 rho^T rho (FP64)
-//   solve        per instance: fixed-order sum of the partials, Armijo test
-//                of the evaluated trials, Cholesky of J^T J, next direction
-//   eval_trials  values at four line-search trials q + alpha_t delta and the
-//                Jacobian at the first one, with the same partial sums
-// (eval_trials, solve) rounds repeat a fixed number of times; an instance
-// that has finished makes the remaining launches return at once, so the
-// sequence can be captured in a graph.
+// Two launches per step, both on the caller's stream with no host sync:
+//   setup   block map (16-sample batches of every instance), state init
+//   step    one cooperative (co-resident, persistent) kernel that loops:
+//     eval_jets    value, x tangents, Laplacian and latent Jacobian at q_n;
+//                  heat update f_{n+1} = g + dt nu Lap g (FP64), residual
+//                  rho_0 = f_{n+1} - g(q_n) = dt nu Lap g (formed directly),
+//                  and per-batch partial sums of J^T J, J^T rho and
+//                  1/2 rho^T rho (FP64)
+//     solve        per instance: fixed-order sum of the partials, Armijo test
+//                  of the evaluated trials, Cholesky of J^T J, next direction
+//     eval_trials  the decoder differences g(q_t) - g(q_n) at four line-search
+//                  trials q_t = q + alpha_t delta and the Jacobian at the
+//                  first one; residual rho_t = rho_0 - (g(q_t) - g(q_n)),
+//                  with the same partial sums
+// The residual is the paper's f_{n+1} - g(q) written incrementally: over a
+// time step g moves by a small fraction of its size, and a difference
+// carried through the network keeps its rounding error relative to itself,
+// where a difference of two separately rounded values would not.
+//   with a grid barrier between phases, until every instance is done or a
+//   bound on the rounds (enough for max_iter iterations with ls_max shrinks)
+//   is reached.  Every workgroup takes the same branch at every barrier: the
+//   loop test reads a counter that only the solve phase writes.
+#include <hip/hip_cooperative_groups.h>
+
 #include "common.hpp"
+
+namespace cg = cooperative_groups;
 
 namespace crom {
 
@@ -27,14 +40,15 @@ struct GNState {
   double q[RMAX];       // accepted iterate
   double delta[RMAX];   // Gauss-Newton direction at q
   double qt[TV][RMAX];  // latents evaluated by the next round (trial 0 also gets J)
+  double qd[TV][RMAX];  // the same latents minus q_n
   double alpha[TV];
   double phi, slope, dnorm, pad0;
   double obj_first, obj_last;
-  int32_t phase, iters, ls_evals, flags, ls_tried, pad1;
+  int32_t phase, iters, ls_evals, flags, ls_tried, rounds;
 };
 
 struct WsLayout {
-  size_t blk_start, blk_inst, first_blk, nblk, targets, partials, state, total;
+  size_t blk_start, blk_inst, first_blk, nblk, active, targets, rho0, partials, state, total;
   int64_t nblk_max;
   int nred;
 };
@@ -50,7 +64,9 @@ static WsLayout ws_layout(int r, int d, int n_inst, int64_t total) {
   L.blk_inst = o;  o = align256(o + 4 * (size_t)L.nblk_max);
   L.first_blk = o; o = align256(o + 4 * (size_t)(n_inst + 1));
   L.nblk = o;      o = align256(o + 8);
+  L.active = o;    o = align256(o + 8);
   L.targets = o;   o = align256(o + 8 * (size_t)total * d);
+  L.rho0 = o;      o = align256(o + 8 * (size_t)total * d);
   L.partials = o;  o = align256(o + 8 * (size_t)L.nblk_max * L.nred);
   L.state = o;     o = align256(o + sizeof(GNState) * (size_t)n_inst);
   L.total = o;
@@ -102,6 +118,7 @@ __global__ void setup_kernel(StepArgs a) {
     }
     first_blk[a.n_inst] = (int32_t)acc;
     *wsp<int64_t>(a, a.L.nblk) = acc;
+    *wsp<int64_t>(a, a.L.active) = a.n_inst;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < a.n_inst; i += blockDim.x) {
@@ -115,13 +132,16 @@ __global__ void setup_kernel(StepArgs a) {
       const double v = k < a.r ? a.q_n[(int64_t)i * a.r + k] : 0.0;
       s.q[k] = v;
       s.delta[k] = 0.0;
-      for (int t = 0; t < TV; ++t) s.qt[t][k] = v;
+      for (int t = 0; t < TV; ++t) {
+        s.qt[t][k] = v;
+        s.qd[t][k] = 0.0;
+      }
     }
     for (int t = 0; t < TV; ++t) s.alpha[t] = 0.0;
     s.phi = s.slope = s.dnorm = 0.0;
     s.obj_first = s.obj_last = __builtin_nan("");
     s.phase = PH_INIT;
-    s.iters = s.ls_evals = s.flags = s.ls_tried = 0;
+    s.iters = s.ls_evals = s.flags = s.ls_tried = s.rounds = 0;
   }
 }
 
@@ -149,86 +169,87 @@ __device__ __forceinline__ void batch_partials(const double* jd, const double* r
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Evaluation of one 16-sample batch (all threads of the workgroup).
 // ---------------------------------------------------------------------------
 template <class S, int NW, int PREC>
-__global__ __launch_bounds__(NW * 64) void eval_jets_kernel(StepArgs a) {
+__device__ void eval_jets_batch(const StepArgs& a, char* lds, int64_t blk) {
   constexpr int R = S::R;
-  using C = Cols<S::M, R, 1, true, D2_LAP, R>;
+  using C = Cols<S::M, R, 1, 0, true, D2_LAP, R>;
   using E = Engine<S, C, 1, NW, PREC>;
-  extern __shared__ __align__(16) char lds[];
-  const int64_t blk = blockIdx.x;
-  if (blk >= *wsp<int64_t>(a, a.L.nblk)) return;
   const int inst = wsp<int32_t>(a, a.L.blk_inst)[blk];
   const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
   const int64_t rem = a.offsets[inst + 1] - first;
   const int n_valid = rem < PT ? (int)rem : PT;
-  E::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * R, R, a.params, a.pi);
+  E::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * R, R, nullptr, 0, a.params, a.pi);
   __syncthreads();
   E::run(lds, a.params, a.pi, a.packed, a.depth, 0);
   const float* res = reinterpret_cast<const float*>(lds + E::RES_OFF);
   double* jd = reinterpret_cast<double*>(lds);  // the activation region is free now
   double* rho = jd + PT * R;
   double* targets = wsp<double>(a, a.L.targets);
+  double* rho0 = wsp<double>(a, a.L.rho0);
   if (threadIdx.x < PT) {
     const int i = threadIdx.x;
     const bool valid = i < n_valid;
     const int64_t p = first + i;
     const double gv = (double)res[0 * PT + i];
     const double lap = (double)res[C::D0 * PT + i];
-    double f = gv + a.dt * a.coef[inst] * lap;
-    if (valid && a.clamp && a.clamp[p]) f = 0.0;
-    if (valid) targets[p] = f;
-    rho[i * TV] = valid ? f - gv : 0.0;
+    const bool clamped = valid && a.clamp && a.clamp[p];
+    const double r0 = clamped ? -gv : a.dt * a.coef[inst] * lap;
+    if (valid) {
+      targets[p] = clamped ? 0.0 : gv + r0;
+      rho0[p] = r0;
+    }
+    rho[i * TV] = valid ? r0 : 0.0;
     for (int t = 1; t < TV; ++t) rho[i * TV + t] = 0.0;
     for (int k = 0; k < R; ++k) jd[i * R + k] = valid ? (double)res[(C::Q0 + k) * PT + i] : 0.0;
   }
   __syncthreads();
   batch_partials<R>(jd, rho, wsp<double>(a, a.L.partials) + blk * a.L.nred);
+  __syncthreads();
 }
 
 template <class S, int NW, int PREC>
-__global__ __launch_bounds__(NW * 64) void eval_trials_kernel(StepArgs a) {
+__device__ void eval_trials_batch(const StepArgs& a, char* lds, int64_t blk, int inst) {
   constexpr int R = S::R;
-  using C = Cols<S::M, R, TV, false, D2_NONE, R>;
+  using C = Cols<S::M, R, 1, TV, false, D2_NONE, R>;
   using E = Engine<S, C, 1, NW, PREC>;
-  extern __shared__ __align__(16) char lds[];
-  const int64_t blk = blockIdx.x;
-  if (blk >= *wsp<int64_t>(a, a.L.nblk)) return;
-  const int inst = wsp<int32_t>(a, a.L.blk_inst)[blk];
   const GNState* st = wsp<GNState>(a, a.L.state) + inst;
-  if (st->phase != PH_TRIALS && st->phase != PH_REJAC) return;
   const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
   const int64_t rem = a.offsets[inst + 1] - first;
   const int n_valid = rem < PT ? (int)rem : PT;
-  E::stage(lds, a.y, first, n_valid, &st->qt[0][0], RMAX, a.params, a.pi);
+  E::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * R, R, &st->qd[0][0], RMAX, a.params,
+           a.pi);
   __syncthreads();
   E::run(lds, a.params, a.pi, a.packed, a.depth, 0);
   const float* res = reinterpret_cast<const float*>(lds + E::RES_OFF);
   double* jd = reinterpret_cast<double*>(lds);
   double* rho = jd + PT * R;
-  const double* targets = wsp<double>(a, a.L.targets);
+  const double* rho0 = wsp<double>(a, a.L.rho0);
   if (threadIdx.x < PT) {
     const int i = threadIdx.x;
     const bool valid = i < n_valid;
-    const double f = valid ? targets[first + i] : 0.0;
-    for (int t = 0; t < TV; ++t) rho[i * TV + t] = valid ? f - (double)res[t * PT + i] : 0.0;
+    const double r0 = valid ? rho0[first + i] : 0.0;
+    for (int t = 0; t < TV; ++t) rho[i * TV + t] = valid ? r0 - (double)res[(C::F0 + t) * PT + i] : 0.0;
     for (int k = 0; k < R; ++k) jd[i * R + k] = valid ? (double)res[(C::Q0 + k) * PT + i] : 0.0;
   }
   __syncthreads();
   batch_partials<R>(jd, rho, wsp<double>(a, a.L.partials) + blk * a.L.nred);
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// Gauss-Newton control for one instance (one wave per instance).
+// Gauss-Newton control of one instance (all threads reduce, thread 0 decides).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void solve_kernel(StepArgs a, int is_last) {
-  const int inst = blockIdx.x;
+__device__ void solve_instance(const StepArgs& a, char* lds, int inst, bool is_last) {
   GNState* st = wsp<GNState>(a, a.L.state) + inst;
   const int phase = st->phase;
   if (phase == PH_DONE) return;
-  __shared__ double red[RMAX * (RMAX + 1) / 2 + RMAX + TV];
-  __shared__ double A[RMAX * RMAX];
-  __shared__ double L[RMAX * RMAX];
+  double* red = reinterpret_cast<double*>(lds);
+  double* A = red + 160;
+  double* L = A + RMAX * RMAX;
   const int r = a.r;
   const int nA = r * (r + 1) / 2;
   const int nred = a.L.nred;
@@ -241,189 +262,245 @@ __global__ __launch_bounds__(64) void solve_kernel(StepArgs a, int is_last) {
     red[e] = s;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-
-  const double* bv = red + nA;
-  const double* phit = red + nA + r;
-  bool done = false, newdir = false;
-  if (phase == PH_INIT) {
-    st->obj_first = st->obj_last = st->phi = phit[0];
-    newdir = true;
-  } else if (phase == PH_TRIALS) {
-    int acc = -1;
-    for (int t = 0; t < TV; ++t) {
-      if (st->ls_tried + t > a.ls_max) break;
-      st->ls_evals += 1;
-      const double ph = phit[t];
-      if (isfinite(ph) && ph <= st->phi - a.armijo_c * st->alpha[t] * st->slope) {
-        acc = t;
-        break;
-      }
-    }
-    if (acc < 0) {
-      st->ls_tried += TV;
-      if (st->ls_tried > a.ls_max) {
-        st->flags |= CROM_FLAG_LS_FAIL;
-        done = true;
-      } else {
-        double al = st->alpha[TV - 1];
-        for (int t = 0; t < TV; ++t) {
-          al *= a.shrink;
-          st->alpha[t] = al;
-          for (int k = 0; k < r; ++k) st->qt[t][k] = st->q[k] + al * st->delta[k];
-        }
-      }
-    } else {
-      double qn = 0.0;
-      for (int k = 0; k < r; ++k) qn += st->q[k] * st->q[k];
-      qn = sqrt(qn);
-      const double step = st->alpha[acc] * st->dnorm;
-      for (int k = 0; k < r; ++k) st->q[k] = st->qt[acc][k];
-      st->iters += 1;
-      st->phi = phit[acc];
-      st->obj_last = st->phi;
-      if (step <= a.tol * (1.0 + qn)) {
-        done = true;
-      } else if (st->iters >= a.max_iter) {
-        st->flags |= CROM_FLAG_MAXITER;
-        done = true;
-      } else if (acc == 0) {
-        newdir = true;
-      } else {
-        st->phase = PH_REJAC;
-        for (int t = 0; t < TV; ++t)
-          for (int k = 0; k < r; ++k) st->qt[t][k] = st->q[k];
-      }
-    }
-  } else {  // PH_REJAC: J^T J and J^T rho at the accepted iterate
-    newdir = true;
-  }
-
-  if (newdir) {
-    bool finite = isfinite(st->phi);
-    for (int e = 0; e < nA + r; ++e) finite = finite && isfinite(red[e]);
-    if (!finite) {
-      st->flags |= CROM_FLAG_NONFINITE;
-      done = true;
-    } else {
-      // unpack the upper triangle
-      int e = 0;
-      for (int i = 0; i < r; ++i)
-        for (int j = i; j < r; ++j) {
-          A[i * r + j] = red[e];
-          A[j * r + i] = red[e];
-          ++e;
-        }
-      double dmax = 0.0;
-      for (int i = 0; i < r; ++i) dmax = i == 0 ? A[0] : fmax(dmax, A[i * r + i]);
-      const double thresh = 1e-14 * dmax;
-      bool ok = true;
-      for (int j = 0; j < r && ok; ++j) {
-        double s = A[j * r + j];
-        for (int k = 0; k < j; ++k) s -= L[j * r + k] * L[j * r + k];
-        if (!isfinite(s) || s <= thresh) {
-          ok = false;
+  if (threadIdx.x == 0) {
+    if (phase != PH_INIT) st->rounds += 1;
+    const double* qn0 = a.q_n + (int64_t)inst * r;
+    const double* bv = red + nA;
+    const double* phit = red + nA + r;
+    bool done = false, newdir = false;
+    if (phase == PH_INIT) {
+      st->obj_first = st->obj_last = st->phi = phit[0];
+      newdir = true;
+    } else if (phase == PH_TRIALS) {
+      int acc = -1;
+      for (int t = 0; t < TV; ++t) {
+        if (st->ls_tried + t > a.ls_max) break;
+        st->ls_evals += 1;
+        const double ph = phit[t];
+        if (isfinite(ph) && ph <= st->phi - a.armijo_c * st->alpha[t] * st->slope) {
+          acc = t;
           break;
         }
-        L[j * r + j] = sqrt(s);
-        for (int i = j + 1; i < r; ++i) {
-          double t = A[i * r + j];
-          for (int k = 0; k < j; ++k) t -= L[i * r + k] * L[j * r + k];
-          L[i * r + j] = t / L[j * r + j];
-        }
       }
-      if (!ok) {
-        st->flags |= CROM_FLAG_SINGULAR;
-        done = true;
-      } else {
-        double y[RMAX], x[RMAX];
-        for (int i = 0; i < r; ++i) {
-          double t = bv[i];
-          for (int k = 0; k < i; ++k) t -= L[i * r + k] * y[k];
-          y[i] = t / L[i * r + i];
-        }
-        for (int i = r - 1; i >= 0; --i) {
-          double t = y[i];
-          for (int k = i + 1; k < r; ++k) t -= L[k * r + i] * x[k];
-          x[i] = t / L[i * r + i];
-        }
-        double dn = 0.0, qn = 0.0, sl = 0.0;
-        for (int k = 0; k < r; ++k) {
-          st->delta[k] = x[k];
-          dn += x[k] * x[k];
-          qn += st->q[k] * st->q[k];
-          sl += bv[k] * x[k];
-        }
-        st->dnorm = sqrt(dn);
-        if (a.linearized) {
-          for (int k = 0; k < r; ++k) st->q[k] += x[k];
-          st->iters = 1;
-          done = true;
-        } else if (st->dnorm <= a.tol * (1.0 + sqrt(qn))) {
+      if (acc < 0) {
+        st->ls_tried += TV;
+        if (st->ls_tried > a.ls_max) {
+          st->flags |= CROM_FLAG_LS_FAIL;
           done = true;
         } else {
-          st->slope = sl;
-          st->ls_tried = 0;
-          double al = 1.0;
+          double al = st->alpha[TV - 1];
           for (int t = 0; t < TV; ++t) {
-            st->alpha[t] = al;
-            for (int k = 0; k < r; ++k) st->qt[t][k] = st->q[k] + al * x[k];
             al *= a.shrink;
+            st->alpha[t] = al;
+            for (int k = 0; k < r; ++k) {
+              st->qt[t][k] = st->q[k] + al * st->delta[k];
+              st->qd[t][k] = (st->q[k] - qn0[k]) + al * st->delta[k];
+            }
           }
-          st->phase = PH_TRIALS;
+        }
+      } else {
+        double qn = 0.0;
+        for (int k = 0; k < r; ++k) qn += st->q[k] * st->q[k];
+        qn = sqrt(qn);
+        const double step = st->alpha[acc] * st->dnorm;
+        for (int k = 0; k < r; ++k) st->q[k] = st->qt[acc][k];
+        st->iters += 1;
+        st->phi = phit[acc];
+        st->obj_last = st->phi;
+        if (step <= a.tol * (1.0 + qn)) {
+          done = true;
+        } else if (st->iters >= a.max_iter) {
+          st->flags |= CROM_FLAG_MAXITER;
+          done = true;
+        } else if (acc == 0) {
+          newdir = true;
+        } else {
+          st->phase = PH_REJAC;
+          for (int t = 0; t < TV; ++t)
+            for (int k = 0; k < r; ++k) {
+              st->qt[t][k] = st->q[k];
+              st->qd[t][k] = st->q[k] - qn0[k];
+            }
+        }
+      }
+    } else {  // PH_REJAC: J^T J and J^T rho at the accepted iterate
+      newdir = true;
+    }
+
+    if (newdir) {
+      bool finite = isfinite(st->phi);
+      for (int e = 0; e < nA + r; ++e) finite = finite && isfinite(red[e]);
+      if (!finite) {
+        st->flags |= CROM_FLAG_NONFINITE;
+        done = true;
+      } else {
+        int e = 0;
+        for (int i = 0; i < r; ++i)
+          for (int j = i; j < r; ++j) {
+            A[i * r + j] = red[e];
+            A[j * r + i] = red[e];
+            ++e;
+          }
+        double dmax = A[0];
+        for (int i = 1; i < r; ++i) dmax = fmax(dmax, A[i * r + i]);
+        const double thresh = 1e-14 * dmax;
+        bool ok = true;
+        for (int j = 0; j < r && ok; ++j) {
+          double sj = A[j * r + j];
+          for (int k = 0; k < j; ++k) sj -= L[j * r + k] * L[j * r + k];
+          if (!isfinite(sj) || sj <= thresh) {
+            ok = false;
+            break;
+          }
+          L[j * r + j] = sqrt(sj);
+          for (int i = j + 1; i < r; ++i) {
+            double t = A[i * r + j];
+            for (int k = 0; k < j; ++k) t -= L[i * r + k] * L[j * r + k];
+            L[i * r + j] = t / L[j * r + j];
+          }
+        }
+        if (!ok) {
+          st->flags |= CROM_FLAG_SINGULAR;
+          done = true;
+        } else {
+          double y[RMAX], x[RMAX];
+          for (int i = 0; i < r; ++i) {
+            double t = bv[i];
+            for (int k = 0; k < i; ++k) t -= L[i * r + k] * y[k];
+            y[i] = t / L[i * r + i];
+          }
+          for (int i = r - 1; i >= 0; --i) {
+            double t = y[i];
+            for (int k = i + 1; k < r; ++k) t -= L[k * r + i] * x[k];
+            x[i] = t / L[i * r + i];
+          }
+          double dn = 0.0, qn = 0.0, sl = 0.0;
+          for (int k = 0; k < r; ++k) {
+            st->delta[k] = x[k];
+            dn += x[k] * x[k];
+            qn += st->q[k] * st->q[k];
+            sl += bv[k] * x[k];
+          }
+          st->dnorm = sqrt(dn);
+          if (a.linearized) {
+            for (int k = 0; k < r; ++k) st->q[k] += x[k];
+            st->iters = 1;
+            done = true;
+          } else if (st->dnorm <= a.tol * (1.0 + sqrt(qn))) {
+            done = true;
+          } else {
+            st->slope = sl;
+            st->ls_tried = 0;
+            double al = 1.0;
+            for (int t = 0; t < TV; ++t) {
+              st->alpha[t] = al;
+              for (int k = 0; k < r; ++k) {
+                st->qt[t][k] = st->q[k] + al * x[k];
+                st->qd[t][k] = (st->q[k] - qn0[k]) + al * x[k];
+              }
+              al *= a.shrink;
+            }
+            st->phase = PH_TRIALS;
+          }
         }
       }
     }
+    if (!done && is_last) {
+      st->flags |= CROM_FLAG_MAXITER;
+      done = true;
+    }
+    if (done) {
+      st->phase = PH_DONE;
+      atomicAdd(reinterpret_cast<unsigned long long*>(wsp<int64_t>(a, a.L.active)),
+                (unsigned long long)-1ll);
+    }
+    for (int k = 0; k < r; ++k) a.q_next[(int64_t)inst * r + k] = st->q[k];
+    crom_step_info inf;
+    inf.flags = st->flags;
+    inf.iters = st->iters;
+    inf.ls_evals = st->ls_evals;
+    inf.rounds = st->rounds;
+    inf.obj_first = st->obj_first;
+    inf.obj_last = st->obj_last;
+    a.info[inst] = inf;
   }
-  if (!done && is_last) {
-    st->flags |= CROM_FLAG_MAXITER;
-    done = true;
-  }
-  if (done) st->phase = PH_DONE;
-  for (int k = 0; k < r; ++k) a.q_next[(int64_t)inst * r + k] = st->q[k];
-  crom_step_info inf;
-  inf.flags = st->flags;
-  inf.iters = st->iters;
-  inf.ls_evals = st->ls_evals;
-  inf._pad = 0;
-  inf.obj_first = st->obj_first;
-  inf.obj_last = st->obj_last;
-  a.info[inst] = inf;
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
+// The persistent step kernel (cooperative launch: every workgroup resident).
+// ---------------------------------------------------------------------------
 template <class S, int NW, int PREC>
-static crom_status launch_step(const StepArgs& a, int rounds, hipStream_t st) {
-  using EJ = Engine<S, Cols<S::M, S::R, 1, true, D2_LAP, S::R>, 1, NW, PREC>;
-  using ET = Engine<S, Cols<S::M, S::R, TV, false, D2_NONE, S::R>, 1, NW, PREC>;
-  static_assert(EJ::LDS_BYTES <= 160 * 1024 && ET::LDS_BYTES <= 160 * 1024, "LDS");
+__global__ __launch_bounds__(NW * 64) void step_kernel(StepArgs a, int max_rounds) {
+  extern __shared__ __align__(16) char lds[];
+  cg::grid_group grid = cg::this_grid();
+  const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
+  const int32_t* blk_inst = wsp<int32_t>(a, a.L.blk_inst);
+  const GNState* state = wsp<GNState>(a, a.L.state);
+  int64_t* active = wsp<int64_t>(a, a.L.active);
+
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) eval_jets_batch<S, NW, PREC>(a, lds, blk);
+  grid.sync();
+  for (int inst = blockIdx.x; inst < a.n_inst; inst += gridDim.x)
+    solve_instance(a, lds, inst, max_rounds == 0);
+  grid.sync();
+  for (int round = 0; round < max_rounds; ++round) {
+    if (__hip_atomic_load(active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+      const int inst = blk_inst[blk];
+      const int ph = __hip_atomic_load(&state[inst].phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (ph == PH_TRIALS || ph == PH_REJAC) eval_trials_batch<S, NW, PREC>(a, lds, blk, inst);
+    }
+    grid.sync();
+    for (int inst = blockIdx.x; inst < a.n_inst; inst += gridDim.x)
+      solve_instance(a, lds, inst, round == max_rounds - 1);
+    grid.sync();
+  }
+}
+
+template <class S, int NW, int PREC>
+static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
+  using EJ = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC>;
+  using ET = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, S::R>, 1, NW, PREC>;
+  constexpr int LDS = EJ::LDS_BYTES > ET::LDS_BYTES ? EJ::LDS_BYTES : ET::LDS_BYTES;
+  static_assert(LDS <= 160 * 1024, "LDS");
   static_assert(PT * S::R * 8 + PT * TV * 8 <= EJ::ACT_REGION, "staging fits");
   static_assert(PT * S::R * 8 + PT * TV * 8 <= ET::ACT_REGION, "staging fits");
-  auto kj = eval_jets_kernel<S, NW, PREC>;
-  auto kt = eval_trials_kernel<S, NW, PREC>;
-  static bool attr = false;
-  if (!attr) {
-    crom_status s = set_lds(kj, EJ::LDS_BYTES);
-    if (s == CROM_OK) s = set_lds(kt, ET::LDS_BYTES);
+  static_assert((160 + 2 * RMAX * RMAX) * 8 <= LDS, "solve scratch fits");
+  auto k = step_kernel<S, NW, PREC>;
+  static int resident = 0;
+  if (!resident) {
+    crom_status s = set_lds(k, LDS);
     if (s != CROM_OK) return s;
-    attr = true;
+    int dev = 0, per_cu = 0, ncu = 0;
+    s = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (s == CROM_OK) s = hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "attr");
+    if (s == CROM_OK)
+      s = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, NW * 64, LDS), "occupancy");
+    if (s != CROM_OK) return s;
+    if (per_cu < 1) return fail(CROM_ERR_UNSUPPORTED, "step kernel does not fit on a compute unit");
+    resident = per_cu * ncu;
   }
-  const unsigned nb = (unsigned)a.L.nblk_max;
   hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(256), 0, st, a);
-  if (nb > 0) hipLaunchKernelGGL(kj, dim3(nb), dim3(NW * 64), EJ::LDS_BYTES, st, a);
-  hipLaunchKernelGGL(solve_kernel, dim3(a.n_inst), dim3(64), 0, st, a, rounds == 0 ? 1 : 0);
-  for (int i = 0; i < rounds; ++i) {
-    if (nb > 0) hipLaunchKernelGGL(kt, dim3(nb), dim3(NW * 64), ET::LDS_BYTES, st, a);
-    hipLaunchKernelGGL(solve_kernel, dim3(a.n_inst), dim3(64), 0, st, a, i == rounds - 1 ? 1 : 0);
-  }
-  return hip_check(hipGetLastError(), "step launch");
+  crom_status s = hip_check(hipGetLastError(), "setup launch");
+  if (s != CROM_OK) return s;
+  int64_t g = a.L.nblk_max > a.n_inst ? a.L.nblk_max : a.n_inst;
+  if (g > resident) g = resident;
+  if (g < 1) g = 1;
+  void* args[] = {&a, &max_rounds};
+  return hip_check(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k), dim3((unsigned)g),
+                                              dim3(NW * 64), args, LDS, st),
+                   "step launch");
 }
 
 template <class S, int NW>
 static crom_status step_prec(int prec, const StepArgs& a, int rounds, hipStream_t st) {
-  if (prec == CROM_PREC_FP32) return launch_step<S, NW, PREC_FP32>(a, rounds, st);
-  if (prec == CROM_PREC_BF16) return launch_step<S, NW, PREC_BF16>(a, rounds, st);
-  return launch_step<S, NW, PREC_BF16X3>(a, rounds, st);
+  switch (prec) {
+    case CROM_PREC_FP32: return launch_step<S, NW, PREC_FP32>(a, rounds, st);
+    case CROM_PREC_BF16: return launch_step<S, NW, PREC_BF16>(a, rounds, st);
+    case CROM_PREC_BF16_PURE: return launch_step<S, NW, PREC_BF16_PURE>(a, rounds, st);
+    default: return launch_step<S, NW, PREC_BF16X3>(a, rounds, st);
+  }
 }
 
 }  // namespace crom
@@ -466,7 +543,7 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
     return fail(CROM_ERR_INVALID_ARG, "offsets, q_n, q_next, info and pde->coef are required");
   if (total_samples > 0 && !y) return fail(CROM_ERR_INVALID_ARG, "y is NULL");
   if (q_next == q_n) return fail(CROM_ERR_INVALID_ARG, "q_next must not alias q_n");
-  if (opts->max_iter < 1 || opts->ls_max < 0 || opts->launches < 0 || !(opts->tol_step >= 0.0) ||
+  if (opts->max_iter < 1 || opts->ls_max < 0 || opts->max_rounds < 0 || !(opts->tol_step >= 0.0) ||
       !(opts->ls_shrink > 0.0 && opts->ls_shrink < 1.0) || !(opts->armijo_c >= 0.0))
     return fail(CROM_ERR_INVALID_ARG, "gn opts out of range");
   if (!(pde->dt > 0.0)) return fail(CROM_ERR_INVALID_ARG, "dt must be positive");
@@ -498,7 +575,10 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
   a.tol = opts->tol_step;
   a.armijo_c = opts->armijo_c;
   a.shrink = opts->ls_shrink;
-  const int rounds = opts->linearized ? 0 : (opts->launches > 0 ? opts->launches : opts->max_iter + 2);
+  // Enough rounds for max_iter accepted steps, each after the longest line
+  // search (ceil((ls_max + 1) / TV) rounds) and one re-linearisation.
+  const int worst = opts->max_iter * (1 + (opts->ls_max + TV) / TV) + 1;
+  const int rounds = opts->linearized ? 0 : (opts->max_rounds > 0 ? opts->max_rounds : worst);
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (shape_id(net->m, net->r, net->d, net->width)) {
     case SHAPE_1D: return step_prec<Shape<32, 1, 3, 1>, 2>(net->precision, a, rounds, st);
