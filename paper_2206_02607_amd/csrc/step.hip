@@ -99,49 +99,76 @@ __device__ __forceinline__ T* wsp(const StepArgs& a, size_t off) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ void setup_kernel(StepArgs a) {
+// Block map and state initialisation (one workgroup of 256 threads).
+// Offsets that are not a valid CSR array (a negative size, a range outside
+// [0, total]) give every instance zero batches: nothing is evaluated and the
+// instances end SINGULAR.  Valid CSR ranges are disjoint, so the batch count
+// stays within the bound the workspace was sized for.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void setup_kernel(StepArgs a) {
   int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
   int64_t* blk_start = wsp<int64_t>(a, a.L.blk_start);
   int32_t* blk_inst = wsp<int32_t>(a, a.L.blk_inst);
   GNState* st = wsp<GNState>(a, a.L.state);
-  if (threadIdx.x == 0) {
-    // An instance whose offsets are out of order or outside [0, total]
-    // gets no batches (it then ends SINGULAR), and the batch count never
-    // exceeds the bound the workspace was sized for.
-    int64_t acc = 0;
-    for (int i = 0; i < a.n_inst; ++i) {
-      first_blk[i] = (int32_t)acc;
-      const int64_t lo = a.offsets[i], hi = a.offsets[i + 1];
-      int64_t nb = (lo >= 0 && hi >= lo && hi <= a.total) ? (hi - lo + PT - 1) / PT : 0;
-      if (acc + nb > a.L.nblk_max) nb = 0;
-      acc += nb;
+  __shared__ int32_t scan[256];
+  __shared__ int32_t carry;
+  int bad = 0;
+  for (int i = threadIdx.x; i < a.n_inst; i += 256) {
+    const int64_t lo = a.offsets[i], hi = a.offsets[i + 1];
+    bad |= !(lo >= 0 && hi >= lo && hi <= a.total);
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int c = 0; c < a.n_inst; c += 256) {
+    const int i = c + threadIdx.x;
+    int32_t nb = 0;
+    if (i < a.n_inst && !bad) nb = (int32_t)((a.offsets[i + 1] - a.offsets[i] + PT - 1) / PT);
+    scan[threadIdx.x] = nb;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {  // inclusive Hillis-Steele scan
+      const int32_t v = threadIdx.x >= d ? scan[threadIdx.x - d] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += v;
+      __syncthreads();
     }
-    first_blk[a.n_inst] = (int32_t)acc;
-    *wsp<int64_t>(a, a.L.nblk) = acc;
+    if (i < a.n_inst) first_blk[i] = carry + scan[threadIdx.x] - nb;
+    __syncthreads();
+    if (threadIdx.x == 255) carry += scan[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    first_blk[a.n_inst] = carry;
+    *wsp<int64_t>(a, a.L.nblk) = carry;
     *wsp<int64_t>(a, a.L.active) = a.n_inst;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < a.n_inst; i += blockDim.x) {
+  // batches: instance i owns first_blk[i] .. first_blk[i+1]-1
+  for (int i = threadIdx.x; i < a.n_inst; i += 256) {
     const int32_t b0 = first_blk[i], b1 = first_blk[i + 1];
     for (int32_t b = b0; b < b1; ++b) {
       blk_start[b] = a.offsets[i] + (int64_t)(b - b0) * PT;
       blk_inst[b] = i;
     }
-    GNState& s = st[i];
-    for (int k = 0; k < RMAX; ++k) {
-      const double v = k < a.r ? a.q_n[(int64_t)i * a.r + k] : 0.0;
-      s.q[k] = v;
-      s.delta[k] = 0.0;
-      for (int t = 0; t < TV; ++t) {
-        s.qt[t][k] = v;
-        s.qd[t][k] = 0.0;
-      }
+  }
+  // state: one 8-byte word per thread step
+  constexpr int NWORD = sizeof(GNState) / 8;
+  for (int64_t w = threadIdx.x; w < (int64_t)a.n_inst * NWORD; w += 256) {
+    const int i = (int)(w / NWORD), k = (int)(w % NWORD);
+    GNState* s = st + i;
+    uint64_t* word = reinterpret_cast<uint64_t*>(s) + k;
+    const int qk = k;  // q[] occupies the first RMAX words
+    if (qk < RMAX) {
+      const double v = qk < a.r ? a.q_n[(int64_t)i * a.r + qk] : 0.0;
+      *reinterpret_cast<double*>(word) = v;
+    } else {
+      *word = 0;
     }
-    for (int t = 0; t < TV; ++t) s.alpha[t] = 0.0;
-    s.phi = s.slope = s.dnorm = 0.0;
-    s.obj_first = s.obj_last = __builtin_nan("");
-    s.phase = PH_INIT;
-    s.iters = s.ls_evals = s.flags = s.ls_tried = s.rounds = 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.n_inst; i += 256) {
+    st[i].obj_first = st[i].obj_last = __builtin_nan("");
+    st[i].phase = PH_INIT;
   }
 }
 
@@ -241,86 +268,118 @@ __device__ void eval_trials_batch(const StepArgs& a, char* lds, int64_t blk, int
 }
 
 // ---------------------------------------------------------------------------
-// Gauss-Newton control of one instance (all threads reduce, thread 0 decides).
+// Gauss-Newton control of one instance.  The workgroup copies the state to
+// LDS and sums the partials in a fixed order (every thread a strided subset
+// of the batches for one entry, then the subsets in order); thread 0 then
+// takes the decisions on register copies; the workgroup writes the state
+// back.
 // ---------------------------------------------------------------------------
+template <int R>
 __device__ void solve_instance(const StepArgs& a, char* lds, int inst, bool is_last) {
-  GNState* st = wsp<GNState>(a, a.L.state) + inst;
+  constexpr int NA = R * (R + 1) / 2;
+  constexpr int NRED = NA + R + TV;
+  constexpr int NWORD = sizeof(GNState) / 8;
+  GNState* gst = wsp<GNState>(a, a.L.state) + inst;
+  GNState* st = reinterpret_cast<GNState*>(lds);
+  double* sub = reinterpret_cast<double*>(lds + ((sizeof(GNState) + 15) / 16) * 16);
+  const int nth = blockDim.x;
+  const int NS = nth / NRED;  // strided subsets per entry
+  double* red = sub + NS * NRED;
+  for (int w = threadIdx.x; w < NWORD; w += nth)
+    reinterpret_cast<uint64_t*>(st)[w] = reinterpret_cast<const uint64_t*>(gst)[w];
+  __syncthreads();
   const int phase = st->phase;
-  if (phase == PH_DONE) return;
-  double* red = reinterpret_cast<double*>(lds);
-  double* A = red + 160;
-  double* L = A + RMAX * RMAX;
-  const int r = a.r;
-  const int nA = r * (r + 1) / 2;
-  const int nred = a.L.nred;
+  if (phase == PH_DONE) {
+    __syncthreads();
+    return;
+  }
   const int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
   const int32_t b0 = first_blk[inst], b1 = first_blk[inst + 1];
   const double* part = wsp<double>(a, a.L.partials);
-  for (int e = threadIdx.x; e < nred; e += blockDim.x) {
-    double s = 0.0;
-    for (int32_t b = b0; b < b1; ++b) s += part[(int64_t)b * nred + e];
-    red[e] = s;
+  if (threadIdx.x < NS * NRED) {
+    const int e = threadIdx.x % NRED, sl = threadIdx.x / NRED;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int32_t b = b0 + sl;
+    for (; b + 3 * NS < b1; b += 4 * NS) {
+      s0 += part[(int64_t)b * NRED + e];
+      s1 += part[(int64_t)(b + NS) * NRED + e];
+      s2 += part[(int64_t)(b + 2 * NS) * NRED + e];
+      s3 += part[(int64_t)(b + 3 * NS) * NRED + e];
+    }
+    for (; b < b1; b += NS) s0 += part[(int64_t)b * NRED + e];
+    sub[sl * NRED + e] = (s0 + s1) + (s2 + s3);
   }
   __syncthreads();
+  if (threadIdx.x < NRED) {
+    double s = 0.0;
+    for (int sl = 0; sl < NS; ++sl) s += sub[sl * NRED + threadIdx.x];
+    red[threadIdx.x] = s;
+  }
+  __syncthreads();
+
   if (threadIdx.x == 0) {
-    if (phase != PH_INIT) st->rounds += 1;
-    const double* qn0 = a.q_n + (int64_t)inst * r;
-    const double* bv = red + nA;
-    const double* phit = red + nA + r;
+    const double* qn0 = a.q_n + (int64_t)inst * R;
+    double q[R], dl[R], qn0r[R], alpha[TV];
+    for (int k = 0; k < R; ++k) {
+      q[k] = st->q[k];
+      dl[k] = st->delta[k];
+      qn0r[k] = qn0[k];
+    }
+    for (int t = 0; t < TV; ++t) alpha[t] = st->alpha[t];
+    double phi = st->phi, slope = st->slope, dnorm = st->dnorm;
+    int iters = st->iters, ls_evals = st->ls_evals, flags = st->flags, ls_tried = st->ls_tried;
+    int ph = phase;
+    if (ph != PH_INIT) st->rounds += 1;
+    const double* bv = red + NA;
+    const double* phit = red + NA + R;
     bool done = false, newdir = false;
-    if (phase == PH_INIT) {
-      st->obj_first = st->obj_last = st->phi = phit[0];
+    int settrials = 0;  // 1: trials q + alpha_t delta; 2: every trial at q (re-linearise)
+    if (ph == PH_INIT) {
+      st->obj_first = st->obj_last = phi = phit[0];
       newdir = true;
-    } else if (phase == PH_TRIALS) {
+    } else if (ph == PH_TRIALS) {
       int acc = -1;
       for (int t = 0; t < TV; ++t) {
-        if (st->ls_tried + t > a.ls_max) break;
-        st->ls_evals += 1;
-        const double ph = phit[t];
-        if (isfinite(ph) && ph <= st->phi - a.armijo_c * st->alpha[t] * st->slope) {
+        if (ls_tried + t > a.ls_max) break;
+        ls_evals += 1;
+        const double pt = phit[t];
+        if (isfinite(pt) && pt <= phi - a.armijo_c * alpha[t] * slope) {
           acc = t;
           break;
         }
       }
       if (acc < 0) {
-        st->ls_tried += TV;
-        if (st->ls_tried > a.ls_max) {
-          st->flags |= CROM_FLAG_LS_FAIL;
+        ls_tried += TV;
+        if (ls_tried > a.ls_max) {
+          flags |= CROM_FLAG_LS_FAIL;
           done = true;
         } else {
-          double al = st->alpha[TV - 1];
+          double al = alpha[TV - 1];
           for (int t = 0; t < TV; ++t) {
             al *= a.shrink;
-            st->alpha[t] = al;
-            for (int k = 0; k < r; ++k) {
-              st->qt[t][k] = st->q[k] + al * st->delta[k];
-              st->qd[t][k] = (st->q[k] - qn0[k]) + al * st->delta[k];
-            }
+            alpha[t] = al;
           }
+          settrials = 1;
         }
       } else {
         double qn = 0.0;
-        for (int k = 0; k < r; ++k) qn += st->q[k] * st->q[k];
+        for (int k = 0; k < R; ++k) qn += q[k] * q[k];
         qn = sqrt(qn);
-        const double step = st->alpha[acc] * st->dnorm;
-        for (int k = 0; k < r; ++k) st->q[k] = st->qt[acc][k];
-        st->iters += 1;
-        st->phi = phit[acc];
-        st->obj_last = st->phi;
+        const double step = alpha[acc] * dnorm;
+        for (int k = 0; k < R; ++k) q[k] = st->qt[acc][k];
+        iters += 1;
+        phi = phit[acc];
+        st->obj_last = phi;
         if (step <= a.tol * (1.0 + qn)) {
           done = true;
-        } else if (st->iters >= a.max_iter) {
-          st->flags |= CROM_FLAG_MAXITER;
+        } else if (iters >= a.max_iter) {
+          flags |= CROM_FLAG_MAXITER;
           done = true;
         } else if (acc == 0) {
           newdir = true;
         } else {
-          st->phase = PH_REJAC;
-          for (int t = 0; t < TV; ++t)
-            for (int k = 0; k < r; ++k) {
-              st->qt[t][k] = st->q[k];
-              st->qd[t][k] = st->q[k] - qn0[k];
-            }
+          ph = PH_REJAC;
+          settrials = 2;
         }
       }
     } else {  // PH_REJAC: J^T J and J^T rho at the accepted iterate
@@ -328,102 +387,128 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, bool is_l
     }
 
     if (newdir) {
-      bool finite = isfinite(st->phi);
-      for (int e = 0; e < nA + r; ++e) finite = finite && isfinite(red[e]);
+      bool finite = isfinite(phi);
+      for (int e = 0; e < NA + R; ++e) finite = finite && isfinite(red[e]);
       if (!finite) {
-        st->flags |= CROM_FLAG_NONFINITE;
+        flags |= CROM_FLAG_NONFINITE;
         done = true;
       } else {
-        int e = 0;
-        for (int i = 0; i < r; ++i)
-          for (int j = i; j < r; ++j) {
-            A[i * r + j] = red[e];
-            A[j * r + i] = red[e];
-            ++e;
-          }
-        double dmax = A[0];
-        for (int i = 1; i < r; ++i) dmax = fmax(dmax, A[i * r + i]);
+        double L[R][R];
+        double A[R][R];
+        {
+          int e = 0;
+          for (int i = 0; i < R; ++i)
+            for (int j = i; j < R; ++j) {
+              A[i][j] = red[e];
+              A[j][i] = red[e];
+              ++e;
+            }
+        }
+        double dmax = A[0][0];
+        for (int i = 1; i < R; ++i) dmax = fmax(dmax, A[i][i]);
         const double thresh = 1e-14 * dmax;
         bool ok = true;
-        for (int j = 0; j < r && ok; ++j) {
-          double sj = A[j * r + j];
-          for (int k = 0; k < j; ++k) sj -= L[j * r + k] * L[j * r + k];
-          if (!isfinite(sj) || sj <= thresh) {
+        for (int j = 0; j < R; ++j) {
+          double sj = A[j][j];
+          for (int k = 0; k < j; ++k) sj -= L[j][k] * L[j][k];
+          if (!(isfinite(sj) && sj > thresh)) {
             ok = false;
             break;
           }
-          L[j * r + j] = sqrt(sj);
-          for (int i = j + 1; i < r; ++i) {
-            double t = A[i * r + j];
-            for (int k = 0; k < j; ++k) t -= L[i * r + k] * L[j * r + k];
-            L[i * r + j] = t / L[j * r + j];
+          L[j][j] = sqrt(sj);
+          for (int i = j + 1; i < R; ++i) {
+            double t = A[i][j];
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t / L[j][j];
           }
         }
         if (!ok) {
-          st->flags |= CROM_FLAG_SINGULAR;
+          flags |= CROM_FLAG_SINGULAR;
           done = true;
         } else {
-          double y[RMAX], x[RMAX];
-          for (int i = 0; i < r; ++i) {
+          double y[R], x[R];
+          for (int i = 0; i < R; ++i) {
             double t = bv[i];
-            for (int k = 0; k < i; ++k) t -= L[i * r + k] * y[k];
-            y[i] = t / L[i * r + i];
+            for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
+            y[i] = t / L[i][i];
           }
-          for (int i = r - 1; i >= 0; --i) {
+          for (int i = R - 1; i >= 0; --i) {
             double t = y[i];
-            for (int k = i + 1; k < r; ++k) t -= L[k * r + i] * x[k];
-            x[i] = t / L[i * r + i];
+            for (int k = i + 1; k < R; ++k) t -= L[k][i] * x[k];
+            x[i] = t / L[i][i];
           }
           double dn = 0.0, qn = 0.0, sl = 0.0;
-          for (int k = 0; k < r; ++k) {
-            st->delta[k] = x[k];
+          for (int k = 0; k < R; ++k) {
+            dl[k] = x[k];
             dn += x[k] * x[k];
-            qn += st->q[k] * st->q[k];
+            qn += q[k] * q[k];
             sl += bv[k] * x[k];
           }
-          st->dnorm = sqrt(dn);
+          dnorm = sqrt(dn);
           if (a.linearized) {
-            for (int k = 0; k < r; ++k) st->q[k] += x[k];
-            st->iters = 1;
+            for (int k = 0; k < R; ++k) q[k] += x[k];
+            iters = 1;
             done = true;
-          } else if (st->dnorm <= a.tol * (1.0 + sqrt(qn))) {
+          } else if (dnorm <= a.tol * (1.0 + sqrt(qn))) {
             done = true;
           } else {
-            st->slope = sl;
-            st->ls_tried = 0;
+            slope = sl;
+            ls_tried = 0;
             double al = 1.0;
             for (int t = 0; t < TV; ++t) {
-              st->alpha[t] = al;
-              for (int k = 0; k < r; ++k) {
-                st->qt[t][k] = st->q[k] + al * x[k];
-                st->qd[t][k] = (st->q[k] - qn0[k]) + al * x[k];
-              }
+              alpha[t] = al;
               al *= a.shrink;
             }
-            st->phase = PH_TRIALS;
+            ph = PH_TRIALS;
+            settrials = 1;
           }
         }
       }
     }
     if (!done && is_last) {
-      st->flags |= CROM_FLAG_MAXITER;
+      flags |= CROM_FLAG_MAXITER;
       done = true;
     }
+    if (!done && settrials) {
+      for (int t = 0; t < TV; ++t) {
+        const double al = settrials == 1 ? alpha[t] : 0.0;
+        for (int k = 0; k < R; ++k) {
+          st->qt[t][k] = q[k] + al * dl[k];
+          st->qd[t][k] = (q[k] - qn0r[k]) + al * dl[k];
+        }
+      }
+    }
     if (done) {
-      st->phase = PH_DONE;
+      ph = PH_DONE;
       atomicAdd(reinterpret_cast<unsigned long long*>(wsp<int64_t>(a, a.L.active)),
                 (unsigned long long)-1ll);
     }
-    for (int k = 0; k < r; ++k) a.q_next[(int64_t)inst * r + k] = st->q[k];
+    for (int k = 0; k < R; ++k) {
+      st->q[k] = q[k];
+      st->delta[k] = dl[k];
+      a.q_next[(int64_t)inst * R + k] = q[k];
+    }
+    for (int t = 0; t < TV; ++t) st->alpha[t] = alpha[t];
+    st->phi = phi;
+    st->slope = slope;
+    st->dnorm = dnorm;
+    st->iters = iters;
+    st->ls_evals = ls_evals;
+    st->flags = flags;
+    st->ls_tried = ls_tried;
+    st->phase = ph;
     crom_step_info inf;
-    inf.flags = st->flags;
-    inf.iters = st->iters;
-    inf.ls_evals = st->ls_evals;
+    inf.flags = flags;
+    inf.iters = iters;
+    inf.ls_evals = ls_evals;
     inf.rounds = st->rounds;
     inf.obj_first = st->obj_first;
     inf.obj_last = st->obj_last;
     a.info[inst] = inf;
   }
+  __syncthreads();
+  for (int w = threadIdx.x; w < NWORD; w += nth)
+    reinterpret_cast<uint64_t*>(gst)[w] = reinterpret_cast<const uint64_t*>(st)[w];
   __syncthreads();
 }
 
@@ -442,7 +527,7 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepArgs a, int max_round
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) eval_jets_batch<S, NW, PREC>(a, lds, blk);
   grid.sync();
   for (int inst = blockIdx.x; inst < a.n_inst; inst += gridDim.x)
-    solve_instance(a, lds, inst, max_rounds == 0);
+    solve_instance<S::R>(a, lds, inst, max_rounds == 0);
   grid.sync();
   for (int round = 0; round < max_rounds; ++round) {
     if (__hip_atomic_load(active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
@@ -453,7 +538,7 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepArgs a, int max_round
     }
     grid.sync();
     for (int inst = blockIdx.x; inst < a.n_inst; inst += gridDim.x)
-      solve_instance(a, lds, inst, round == max_rounds - 1);
+      solve_instance<S::R>(a, lds, inst, round == max_rounds - 1);
     grid.sync();
   }
 }
@@ -466,7 +551,9 @@ static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
   static_assert(LDS <= 160 * 1024, "LDS");
   static_assert(PT * S::R * 8 + PT * TV * 8 <= EJ::ACT_REGION, "staging fits");
   static_assert(PT * S::R * 8 + PT * TV * 8 <= ET::ACT_REGION, "staging fits");
-  static_assert((160 + 2 * RMAX * RMAX) * 8 <= LDS, "solve scratch fits");
+  static_assert(sizeof(GNState) + 16 + (NW * 64 + S::R * (S::R + 1) / 2 + S::R + TV) * 8 <= LDS,
+                "solve scratch fits");
+  static_assert(NW * 64 >= S::R * (S::R + 1) / 2 + S::R + TV, "one thread per reduced entry");
   auto k = step_kernel<S, NW, PREC>;
   static int resident = 0;
   if (!resident) {
