@@ -35,6 +35,7 @@ W, DEPTH, M, R = 128, 5, 2, 8
 FLOP_VALUE_COL = 2 * M * W + 2 * (DEPTH - 1) * W * W + 2 * W        # 131,840
 FLOP_TAN_COL = 2 * (DEPTH - 1) * W * W + 2 * W                      # 131,328
 FLOP_POINT_EVAL = FLOP_VALUE_COL + (M + 1 + R) * FLOP_TAN_COL      # 1,576,448
+TOL_STEP = 1e-6   # Gauss-Newton step tolerance, relative to 1 + |q| (both sides)
 PEAK = {"bf16": 2500.0, "bf16x3": 2500.0, "bf16pure": 2500.0, "fp32": 157.3}  # TFLOP/s, dense
 
 
@@ -61,7 +62,7 @@ def cpu_baseline(wl, nodes, n_steps: int):
     for _ in range(n_steps):
         mlp.decode(wl.layers, nodes, q)
         q, info, _ = ostep.heat_step(dec, wl.samples, q, wl.mu, wl.dt,
-                                     GNOptions(max_iter=5, tol_step=1e-10))
+                                     GNOptions(max_iter=5, tol_step=TOL_STEP))
         flop += len(nodes) * FLOP_VALUE_COL + step_flops(len(wl.samples), info.iters, info.ls_evals)
     dt = time.perf_counter() - t0
     return {"value": flop / FLOP_POINT_EVAL / dt, "unit": "point-evals/s", "cores": cores,
@@ -97,7 +98,7 @@ def main():
     q = [torch.from_numpy(wl.q0[None].copy()).to(dev), torch.empty(1, R, dtype=torch.float64, device=dev)]
     nu = torch.tensor([wl.mu], dtype=torch.float64, device=dev)
     g = torch.empty(len(nodes), 1, dtype=torch.float32, device=dev)
-    opts = crom.GNOptions(max_iter=5, tol_step=1e-10)
+    opts = crom.GNOptions(max_iter=5, tol_step=TOL_STEP)
 
     def one(i, ev=None):
         if ev is not None:
@@ -151,6 +152,18 @@ def main():
             "other": {k: {"avg_ms": v[0] * 1e3, "achieved_tflops": v[1] / v[0] / 1e12}
                       for k, v in cand.items() if k != name}}
 
+    # the linearised inversion (one normal-equation solve per step), same rollout
+    lls = crom.GNOptions(max_iter=1, linearized=True)
+    q[0].copy_(torch.from_numpy(wl.q0[None].copy()))
+    for i in range(args.warmup):
+        st.step(q[i % 2], nu, wl.dt, lls, q_next=q[(i + 1) % 2])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        st.step(q[i % 2], nu, wl.dt, lls, q_next=q[(i + 1) % 2])
+    torch.cuda.synchronize()
+    lls_steps_per_s = args.steps / (time.perf_counter() - t1)
+
     cpu = cpu_baseline(wl, nodes, args.cpu_steps) if args.cpu_steps > 0 else None
     its = np.array([int(i["iters"]) for i in infos])
     lse = np.array([int(i["ls_evals"]) for i in infos])
@@ -165,6 +178,8 @@ def main():
                               f"{args.seed}",
                    "mu": wl.mu, "dt": wl.dt, "gn_max_iter": 5, "precision": args.prec},
         "latent_steps_per_s": args.steps / wall,
+        "lls_latent_steps_per_s": lls_steps_per_s,
+        "gn_tol_step": TOL_STEP,
         "step_ms_avg": t_step.mean() * 1e3, "decode_ms_avg": t_dec.mean() * 1e3,
         "gn_iters_mean": float(its.mean()), "ls_evals_mean": float(lse.mean()),
         "roofline": roof,

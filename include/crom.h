@@ -60,11 +60,12 @@ typedef enum {
  *   FP32       FP32 operands and accumulation.
  *   BF16       matrix-core products with FP32 accumulation.  Latent-tangent
  *              columns (dg/dq) use bfloat16 operands (round to nearest
- *              even).  Value, x-tangent and second-derivative columns carry
- *              each operand as a sum of two bfloat16 numbers (hi + lo) and
- *              take three products (hi*hi + hi*lo + lo*hi), about 16
- *              significant bits: the inversion compares values at nearby
- *              latents, and the Laplacian feeds the PDE update.
+ *              even).  Value, x-tangent and second-derivative columns, and
+ *              the decoder differences the inversion's line search
+ *              evaluates, carry each operand as a sum of two bfloat16
+ *              numbers (hi + lo) and take three products (hi*hi + hi*lo +
+ *              lo*hi), about 16 significant bits: the Laplacian feeds the
+ *              PDE update and the line search compares nearby values.
  *   BF16_PURE  every column with plain bfloat16 operands (precision study;
  *              values then carry errors of order 1e-2).
  *   BF16X3     every column with split hi + lo operands.
@@ -156,10 +157,10 @@ typedef struct {
  *   armijo_c   accept alpha when phi(q + alpha delta) <= phi(q) - c alpha b.delta
  *   ls_shrink  s in (0, 1)
  *   max_rounds evaluation rounds after the first, 0 = enough for max_iter
- *              iterations that each need the longest line search.  A round
- *              evaluates 4 line-search trials (or re-linearises after a
- *              shortened step); an instance still running after the last
- *              round ends with CROM_FLAG_MAXITER.
+ *              iterations that each need the longest line search (at most
+ *              256).  A round evaluates 4 line-search trials (or
+ *              re-linearises after a shortened step); an instance still
+ *              running after the last round ends with CROM_FLAG_MAXITER.
  * The step runs as one cooperative kernel whose workgroups are all resident
  * on the GPU; it loops until every instance has finished. */
 typedef struct {
@@ -171,7 +172,9 @@ enum {
   CROM_FLAG_MAXITER = 1,   /* iteration budget used up                      */
   CROM_FLAG_SINGULAR = 2,  /* Cholesky pivot <= 1e-14 * max diag(J^T J)     */
   CROM_FLAG_NONFINITE = 4, /* NaN/Inf in the residual or normal equations   */
-  CROM_FLAG_LS_FAIL = 8    /* no trial step satisfied the Armijo condition  */
+  CROM_FLAG_LS_FAIL = 8,   /* no trial step satisfied the Armijo condition  */
+  CROM_FLAG_ABORTED = 16   /* the step kernel gave up waiting on a phase (an
+                              internal error; q_next holds the last iterate) */
 };
 
 /* Per-instance outcome (device memory, written by crom_step). */
@@ -211,6 +214,15 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
  * workspace used by crom_step (NULL on invalid arguments). */
 const double* crom_step_targets(const crom_net* net, int32_t n_inst, int64_t total_samples,
                                 const void* ws);
+
+/* Debugging aid: when buf (device memory, 128 uint64) is not NULL, every
+ * later crom_step writes the GPU wall-clock tick (100 MHz) at each phase
+ * boundary of its step kernel's first and last workgroup into it: slots
+ * 0..63 and 64..127, in the order start, end of the first evaluation, after
+ * its barrier, after the first solve, then four marks per round (start,
+ * end of evaluation, after its barrier, after the solve).  NULL turns it
+ * off. */
+void crom_debug_step_trace(uint64_t* buf);
 
 /* Message describing the last error returned on the calling thread. */
 const char* crom_last_error(void);

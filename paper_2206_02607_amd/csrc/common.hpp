@@ -28,6 +28,8 @@ inline crom_status hip_check(hipError_t e, const char* what) {
   return CROM_OK;
 }
 
+constexpr int LDS_MAX = 160 * 1024;  // LDS per workgroup on gfx950
+
 // Shapes with compiled kernels.
 enum ShapeId { SHAPE_NONE = -1, SHAPE_1D = 0, SHAPE_2D = 1, SHAPE_3D = 2 };
 

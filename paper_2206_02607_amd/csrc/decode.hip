@@ -95,9 +95,12 @@ __global__ __launch_bounds__(NW * 64) void decode_kernel(DecodeArgs a) {
   const int64_t first = (int64_t)blockIdx.x * E::NPTS;
   const int64_t rem = a.P - first;
   const int n_valid = rem < E::NPTS ? (int)rem : E::NPTS;
-  E::stage(lds, a.x, first, n_valid, a.q, S::R, nullptr, 0, a.params, a.pi);
+  float* par = reinterpret_cast<float*>(lds + E::LDS_BYTES);
+  E::PC::load(par, a.params, a.pi, a.depth, E::THREADS);
   __syncthreads();
-  E::run(lds, a.params, a.pi, a.packed, a.depth, a.qb);
+  E::stage(lds, a.x, first, n_valid, a.q, S::R, nullptr, 0, par);
+  __syncthreads();
+  E::run(lds, par, a.packed, a.depth, a.qb);
   const float* res = reinterpret_cast<const float*>(lds + E::RES_OFF);
   constexpr int D = S::D, M = S::M, R = S::R;
   constexpr int NHT = M * (M + 1) / 2;  // Hessian entries per output
@@ -128,19 +131,20 @@ __global__ __launch_bounds__(NW * 64) void decode_kernel(DecodeArgs a) {
 template <class S, class C, int NB, int NW, int PREC>
 static crom_status launch_decode(const DecodeArgs& a, hipStream_t st) {
   using E = Engine<S, C, NB, NW, PREC>;
-  if constexpr (E::LDS_BYTES > 160 * 1024) {
-    return fail(CROM_ERR_UNSUPPORTED, "column set does not fit in LDS at this width/precision");
+  const int lds_bytes = E::LDS_BYTES + E::PC::bytes(a.depth);
+  if (lds_bytes > LDS_MAX) {
+    return fail(CROM_ERR_UNSUPPORTED, "column set does not fit in LDS at this width/precision/depth");
   } else {
     auto k = decode_kernel<S, C, NB, NW, PREC>;
     static bool attr = false;
     if (!attr) {
-      crom_status s = set_lds(k, E::LDS_BYTES);
+      crom_status s = set_lds(k, LDS_MAX);
       if (s != CROM_OK) return s;
       attr = true;
     }
     const int64_t blocks = (a.P + E::NPTS - 1) / E::NPTS;
     if (blocks > 0x7fffffff) return fail(CROM_ERR_INVALID_ARG, "P too large");
-    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(E::THREADS), E::LDS_BYTES, st, a);
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(E::THREADS), lds_bytes, st, a);
     return hip_check(hipGetLastError(), "decode launch");
   }
 }

@@ -37,6 +37,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace crom {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -47,8 +49,8 @@ constexpr int PT = 16;  // points per N-tile
 
 // Arithmetic of the hidden-to-hidden layers (see crom.h):
 //   FP32      FP32 MFMA
-//   BF16      split hi+lo operands on value and spatial-derivative columns,
-//             plain bfloat16 on difference and latent-tangent columns
+//   BF16      split hi+lo operands on value, difference and spatial-
+//             derivative columns, plain bfloat16 on latent-tangent columns
 //   BF16_PURE plain bfloat16 everywhere
 //   BF16X3    split hi+lo operands on every column
 enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_BF16_PURE = 2, PREC_BF16X3 = 3 };
@@ -100,9 +102,7 @@ struct Cols {
 
 template <class C, int PREC>
 __host__ __device__ constexpr bool is_split(int c) {
-  return PREC == PREC_BF16X3 ||
-         (PREC == PREC_BF16 && (C::kind(c) == CK_VAL || C::kind(c) == CK_XT ||
-                                C::kind(c) == CK_LAP || C::kind(c) == CK_HESS));
+  return PREC == PREC_BF16X3 || (PREC == PREC_BF16 && C::kind(c) != CK_QT);
 }
 
 template <class C, int PREC>
@@ -138,13 +138,41 @@ __device__ __forceinline__ float expm1_acc(float x) {
   return fabsf(x) < 0.03125f ? p : __expf(x) - 1.0f;
 }
 
+// Small parameters, staged once into LDS by every workgroup (FP32):
+//   W1 [W][M+R] | b1 [W] | hidden biases [depth-1][W] | Wout [D][W] | bout [D]
+template <class S>
+struct ParamCache {
+  static constexpr int W = S::W, M = S::M, R = S::R, D = S::D;
+  static __host__ __device__ constexpr int W1(int) { return 0; }
+  static __host__ __device__ constexpr int B1() { return W * (M + R); }
+  static __host__ __device__ constexpr int BH(int h) { return W * (M + R) + W + h * W; }
+  static __host__ __device__ constexpr int WOUT(int depth) { return BH(depth - 1); }
+  static __host__ __device__ constexpr int BOUT(int depth) { return WOUT(depth) + D * W; }
+  static __host__ __device__ constexpr int floats(int depth) { return BOUT(depth) + D; }
+  static __host__ __device__ constexpr int bytes(int depth) { return ((floats(depth) * 4 + 15) / 16) * 16; }
+  // All threads of the workgroup; `par` is 16-byte aligned LDS.
+  static __device__ void load(float* par, const float* __restrict__ params, const ParamIndex& pi,
+                              int depth, int nthreads) {
+    const int n1 = W * (M + R) + W;  // W1 and b1 are adjacent in the parameter array
+    for (int i = threadIdx.x; i < n1; i += nthreads) par[i] = params[pi.w[0] + i];
+    for (int h = 0; h < depth - 1; ++h)
+      for (int i = threadIdx.x; i < W; i += nthreads) par[BH(h) + i] = params[pi.b[h + 1] + i];
+    for (int i = threadIdx.x; i < D * W + D; i += nthreads) par[WOUT(depth) + i] = params[pi.w[depth] + i];
+  }
+};
+
 // All per-batch tables live in one dynamic LDS block:
 //   act    activations (fragment order): NT tiles, then the lo tiles
 //   xs     [NB*16][M] points (FP32)
 //   fold   [NV + ND][W] per-latent first-layer terms (FP32)
 //   res    [D][NT][16] outputs (FP32)
-// The cross-wave output reduction reuses `act`.
-template <class S, class C, int NB, int NW, int PREC>
+// The cross-wave output reduction reuses `act`.  The parameter cache lives
+// after these tables (its offset is passed in, so that kernels running
+// several engines share one cache).
+// PF: 1 prefetches the next layer's weight fragments into a second register
+// set during this layer's products, 0 loads each layer's fragments when the
+// layer starts, -1 chooses by a register estimate.
+template <class S, class C, int NB, int NW, int PREC, int PF = -1>
 struct Engine {
   static constexpr int W = S::W, M = S::M, R = S::R, D = S::D;
   static constexpr int CC = C::C;
@@ -165,110 +193,124 @@ struct Engine {
   static constexpr int NF = C::NV + C::ND;
   static constexpr int FOLD_OFF = XS_OFF + ((NPTS * M * 4 + 15) / 16) * 16;
   static constexpr int RES_OFF = FOLD_OFF + NF * W * 4;
-  static constexpr int LDS_BYTES = RES_OFF + D * NT * PT * 4;
+  static constexpr int LDS_BYTES = RES_OFF + D * NT * PT * 4;  // without the parameter cache
   static constexpr int THREADS = NW * 64;
+  using PC = ParamCache<S>;
+  using AFrag = typename std::conditional<PREC == PREC_FP32, f32x4, bf16x8>::type;
+  static constexpr int NLO = NSPL > 0 ? KQ : 1;  // lo fragments only in split mode
+  // Prefetch the next layer's weight fragments while computing this one,
+  // unless the two register sets would crowd out the accumulators.
+  static constexpr int FRAG_REGS = MT * KQ * 4 * (NSPL > 0 ? 2 : 1);
+  static constexpr bool PREFETCH = PF >= 0 ? PF == 1 : 2 * FRAG_REGS + MT * NT * 4 <= 320;
+  static constexpr int TG = 4;  // operand loads allowed to run ahead of their products
+
+  struct Frags {
+    AFrag hi[MT][KQ];
+    AFrag lo[MT][NLO];
+  };
 
   static __host__ __device__ constexpr int lo_tile(int b, int c) {
     return NT + b * SPB + n_split_before<C, PREC>(c);
+  }
+
+  static __device__ __forceinline__ void load_frags(Frags& f, const char* __restrict__ packed, int h,
+                                                    int wave, int lane) {
+    const AFrag* wf = reinterpret_cast<const AFrag*>(packed + (size_t)h * Packing<S, PREC>::LAYER_BYTES);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int kb = 0; kb < KQ; ++kb) f.hi[mt][kb] = wf[((wave * MT + mt) * KQ + kb) * 64 + lane];
+    if constexpr (NSPL > 0) {
+      constexpr int LO = MTILES * KQ * 64;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int kb = 0; kb < KQ; ++kb) f.lo[mt][kb] = wf[LO + ((wave * MT + mt) * KQ + kb) * 64 + lane];
+    }
   }
 
   // ---- stage points and per-latent first-layer terms --------------------
   // Points first .. first+n_valid-1 of x (n_valid <= NPTS; the rest of the
   // batch is padded with x = 0).  lat: NV latent vectors (v at lat + v *
   // lat_stride), folded with the bias; dlat: ND latent differences (t at
-  // dlat + t * dlat_stride), folded without it.  FP64.
+  // dlat + t * dlat_stride), folded without it.  FP64.  par: the staged
+  // parameter cache.
   static __device__ void stage(char* lds, const float* __restrict__ x, int64_t first, int n_valid,
                                const double* __restrict__ lat, int lat_stride,
-                               const double* __restrict__ dlat, int dlat_stride,
-                               const float* __restrict__ params, const ParamIndex& pi) {
+                               const double* __restrict__ dlat, int dlat_stride, const float* par) {
     float* xs = reinterpret_cast<float*>(lds + XS_OFF);
     for (int i = threadIdx.x; i < NPTS * M; i += THREADS) {
       int p = i / M;
       xs[i] = p < n_valid ? x[(first + p) * M + (i - p * M)] : 0.0f;
     }
     float* fold = reinterpret_cast<float*>(lds + FOLD_OFF);
-    const float* W1 = params + pi.w[0];
-    const float* b1 = params + pi.b[0];
+    const float* W1 = par + PC::W1(0);
+    const float* b1 = par + PC::B1();
     for (int i = threadIdx.x; i < NF * W; i += THREADS) {
       const int v = i / W, u = i - v * W;
-      double s;
-      if (v < C::NV) {
-        s = (double)b1[u];
-        for (int k = 0; k < R; ++k) s += (double)W1[u * (M + R) + M + k] * lat[v * lat_stride + k];
-      } else {
-        s = 0.0;
-        const double* dl = dlat + (v - C::NV) * dlat_stride;
-        for (int k = 0; k < R; ++k) s += (double)W1[u * (M + R) + M + k] * dl[k];
-      }
+      const double* l = v < C::NV ? lat + v * lat_stride : dlat + (v - C::NV) * dlat_stride;
+      double s = v < C::NV ? (double)b1[u] : 0.0;
+#pragma unroll
+      for (int k = 0; k < R; ++k) s += (double)W1[u * (M + R) + M + k] * l[k];
       fold[i] = (float)s;
     }
   }
 
   // ---- epilogue ---------------------------------------------------------
-  // z[t] -> o[t] for one (unit, lane) across all tiles.
-  static __device__ __forceinline__ void epilogue(const float (&z)[NT], float (&o)[NT]) {
+  // In place on z[t] for one (unit, lane) across all tiles.
+  static __device__ __forceinline__ void epilogue(float (&z)[NT]) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const float* zb = &z[b * CC];
-      float* ob = &o[b * CC];
-      float s1 = 1.0f, s2 = 0.0f, e0 = 1.0f;
-      bool pos0 = true;
-#pragma unroll
-      for (int c = 0; c < C::NV; ++c) {
-        const float zz = zb[c];
-        const float e = elu_exp(zz);
-        const bool pos = zz > 0.0f;
-        ob[c] = pos ? zz : e - 1.0f;
-        if (c == 0) {
-          s1 = pos ? 1.0f : e;
-          s2 = pos ? 0.0f : e;
-          e0 = e;
-          pos0 = pos;
-        }
-      }
+      float* zb = &z[b * CC];
+      const float z0 = zb[0];
+      const float e0 = elu_exp(z0);
+      const bool pos0 = z0 > 0.0f;
+      const float s1 = pos0 ? 1.0f : e0;
+      const float s2 = pos0 ? 0.0f : e0;
       float st = s1;  // tangent scale: at the base latent, or at difference column 0's
 #pragma unroll
       for (int c = C::F0; c < C::X0; ++c) {
         const float dz = zb[c];
-        const float zt = zb[0] + dz;
+        const float zt = z0 + dz;
         const bool post = zt > 0.0f;
         const float et = elu_exp(zt);
-        const float both_pos = dz;
         const float both_neg = e0 * expm1_acc(dz);
-        const float cross = (post ? zt : et - 1.0f) - (pos0 ? zb[0] : e0 - 1.0f);
-        ob[c] = (pos0 && post) ? both_pos : ((!pos0 && !post) ? both_neg : cross);
+        const float cross = (post ? zt : et - 1.0f) - (pos0 ? z0 : e0 - 1.0f);
+        zb[c] = (pos0 && post) ? dz : ((!pos0 && !post) ? both_neg : cross);
         if (c == C::F0) st = post ? 1.0f : et;
       }
-#pragma unroll
-      for (int c = C::X0; c < C::D0; ++c) ob[c] = s1 * zb[c];
       if constexpr (C::D2 == D2_LAP) {
         float sq = 0.0f;
 #pragma unroll
         for (int i = 0; i < C::NX; ++i) sq += zb[C::X0 + i] * zb[C::X0 + i];
-        ob[C::D0] = s1 * zb[C::D0] + s2 * sq;
+        zb[C::D0] = s1 * zb[C::D0] + s2 * sq;
       } else if constexpr (C::D2 == D2_HESS) {
 #pragma unroll
         for (int c = C::D0; c < C::Q0; ++c) {
           const float zi = zb[C::X0 + C::hess_i(c)];
           const float zj = zb[C::X0 + C::hess_j(c)];
-          ob[c] = s1 * zb[c] + s2 * zi * zj;
+          zb[c] = s1 * zb[c] + s2 * zi * zj;
         }
       }
 #pragma unroll
-      for (int c = C::Q0; c < CC; ++c) ob[c] = st * zb[c];
+      for (int c = C::X0; c < C::D0; ++c) zb[c] = s1 * zb[c];
+#pragma unroll
+      for (int c = C::Q0; c < CC; ++c) zb[c] = st * zb[c];
+#pragma unroll
+      for (int c = 1; c < C::NV; ++c) {
+        const float zz = zb[c];
+        zb[c] = zz > 0.0f ? zz : elu_exp(zz) - 1.0f;
+      }
+      zb[0] = pos0 ? z0 : e0 - 1.0f;
     }
   }
 
   // ---- write one M-tile of activations (all tiles, 4 units per lane) ----
-  static __device__ __forceinline__ void write_act(char* lds, int mtg, int lane,
-                                                   const float (&o)[NT][4]) {
+  static __device__ __forceinline__ void write_act(char* lds, int mtg, int lane, const f32x4 (&o)[NT]) {
     if constexpr (PREC == PREC_FP32) {
       f32x4* act = reinterpret_cast<f32x4*>(lds);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        f32x4 v = {o[t][0], o[t][1], o[t][2], o[t][3]};
-        act[(t * KQ + mtg) * 64 + lane] = v;
-      }
+      for (int t = 0; t < NT; ++t) act[(t * KQ + mtg) * 64 + lane] = o[t];
     } else {
       // fragment (t, kb = mtg/2), element offset (mtg%2)*4
       bf16x4* act = reinterpret_cast<bf16x4*>(lds);
@@ -282,7 +324,7 @@ struct Engine {
         h[3] = (__bf16)o[t][3];
         act[((t * KQ + (mtg >> 1)) * 64 + lane) * 2 + half] = h;
         const int b = t / CC, c = t % CC;
-        if (BF && is_split<C, PREC>(c)) {
+        if (is_split<C, PREC>(c)) {
           bf16x4 l;
           l[0] = (__bf16)(o[t][0] - (float)h[0]);
           l[1] = (__bf16)(o[t][1] - (float)h[1]);
@@ -295,8 +337,8 @@ struct Engine {
   }
 
   // ---- output layer partial sums for one M-tile --------------------------
-  static __device__ __forceinline__ void out_accum(float (&part)[D][NT], const float (&o)[NT][4],
-                                                   const float* __restrict__ Wout, int ubase) {
+  static __device__ __forceinline__ void out_accum(float (&part)[D][NT], const f32x4 (&o)[NT],
+                                                   const float* Wout, int ubase) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
 #pragma unroll
@@ -308,25 +350,135 @@ struct Engine {
     }
   }
 
+  // epilogue over the 4 accumulator rows of one M-tile, in place
+  static __device__ __forceinline__ void epilogue_tile(f32x4 (&acc)[NT]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float z[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) z[t] = acc[t][v];
+      epilogue(z);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t][v] = z[t];
+    }
+  }
+
+  // One hidden layer h (weights of layer h + 2 of the network): MFMA over
+  // the staged activations, epilogue, and either the next activations or the
+  // output layer's partial sums.  `cur` holds this layer's fragments; `nxt`
+  // receives the next layer's when prefetching.
+  static __device__ __forceinline__ void hidden_layer(char* lds, const float* par,
+                                                      const char* __restrict__ packed, int depth,
+                                                      int h, Frags& cur, Frags& nxt,
+                                                      float (&part)[D][NT], int wave, int lane) {
+    const int g = lane >> 4;
+    const float* Wout = par + PC::WOUT(depth);
+    if constexpr (PREFETCH) {
+      if (h + 1 < depth - 1) load_frags(nxt, packed, h + 1, wave, lane);
+    } else {
+      if (h > 0) load_frags(cur, packed, h, wave, lane);
+    }
+    const float* bias = par + PC::BH(h);
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int mtg = wave * MT + mt;
+      const float* bp = bias + mtg * 16 + g * 4;
+      const f32x4 bv = {bp[0], bp[1], bp[2], bp[3]};
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const bool isval = C::kind(t % CC) == CK_VAL;
+        acc[mt][t] = isval ? bv : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      }
+    }
+    if constexpr (PREC == PREC_FP32) {
+      const f32x4* act = reinterpret_cast<const f32x4*>(lds);
+#pragma unroll
+      for (int kq = 0; kq < KQ; ++kq) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const f32x4 bfr = act[(t * KQ + kq) * 64 + lane];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const f32x4 a = cur.hi[mt][kq];
+            acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], bfr[0], acc[mt][t], 0, 0, 0);
+            acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], bfr[1], acc[mt][t], 0, 0, 0);
+            acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], bfr[2], acc[mt][t], 0, 0, 0);
+            acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], bfr[3], acc[mt][t], 0, 0, 0);
+          }
+          if ((t + 1) % TG == 0) __builtin_amdgcn_sched_barrier(0);  // bound the run-ahead
+        }
+        // keep the next k-block's operand loads from being hoisted above this
+        // one's products: hoisting all of them would exhaust the registers
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      const bf16x8* act = reinterpret_cast<const bf16x8*>(lds);
+#pragma unroll
+      for (int kb = 0; kb < KQ; ++kb) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const bf16x8 bfr = act[(t * KQ + kb) * 64 + lane];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.hi[mt][kb], bfr, acc[mt][t], 0, 0, 0);
+          if ((t + 1) % TG == 0) __builtin_amdgcn_sched_barrier(0);  // bound the run-ahead
+        }
+        if constexpr (NSPL > 0) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+#pragma unroll
+            for (int c = 0; c < CC; ++c) {
+              if (!is_split<C, PREC>(c)) continue;
+              const int t = b * CC + c;
+              const bf16x8 bh = act[(t * KQ + kb) * 64 + lane];
+              const bf16x8 bl = act[(lo_tile(b, c) * KQ + kb) * 64 + lane];
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) {
+                acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.hi[mt][kb], bl, acc[mt][t], 0, 0, 0);
+                acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.lo[mt][kb], bh, acc[mt][t], 0, 0, 0);
+              }
+            }
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);  // as above
+      }
+    }
+    __syncthreads();  // every wave has read this layer's activations
+    const bool last = (h == depth - 2);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int mtg = wave * MT + mt;
+      epilogue_tile(acc[mt]);
+      if (!last) write_act(lds, mtg, lane, acc[mt]);
+      else out_accum(part, acc[mt], Wout, mtg * 16 + g * 4);
+    }
+    __syncthreads();
+  }
+
   // ---- the whole network for one batch -----------------------------------
-  // Leaves the outputs in res[D][NT][16]; all threads must call it.
-  static __device__ void run(char* lds, const float* __restrict__ params, const ParamIndex& pi,
-                             const char* __restrict__ packed, int depth, int qb) {
+  // Leaves the outputs in res[D][NT][16]; all threads must call it.  par:
+  // the staged parameter cache; packed: the fragment-ordered hidden weights.
+  static __device__ void run(char* lds, const float* par, const char* __restrict__ packed, int depth,
+                             int qb) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4, j = lane & 15;
     const float* xs = reinterpret_cast<const float*>(lds + XS_OFF);
     const float* fold = reinterpret_cast<const float*>(lds + FOLD_OFF);
+    const float* W1 = par + PC::W1(0);
+    const float* Wout = par + PC::WOUT(depth);
     float part[D][NT];
 #pragma unroll
     for (int oo = 0; oo < D; ++oo)
 #pragma unroll
       for (int t = 0; t < NT; ++t) part[oo][t] = 0.0f;
-    const float* Wout = params + pi.w[depth];
+
+    Frags fa, fb;  // current and next layer's weight fragments
+    if (depth > 1) load_frags(fa, packed, 0, wave, lane);
 
     // ---------------- layer 1 (VALU, folded) ----------------
     {
-      const float* W1 = params + pi.w[0];
       float xr[NB][M];
 #pragma unroll
       for (int b = 0; b < NB; ++b)
@@ -335,14 +487,14 @@ struct Engine {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const int mtg = wave * MT + mt;
-        float o4[NT][4];
+        f32x4 o4[NT];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int u = mtg * 16 + g * 4 + v;
           float wx[M];
 #pragma unroll
           for (int i = 0; i < M; ++i) wx[i] = W1[u * (M + R) + i];
-          float z[NT], o[NT];
+          float z[NT];
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
             float lin = 0.0f;
@@ -360,9 +512,9 @@ struct Engine {
               z[b * CC + c] = val;
             }
           }
-          epilogue(z, o);
+          epilogue(z);
 #pragma unroll
-          for (int t = 0; t < NT; ++t) o4[t][v] = o[t];
+          for (int t = 0; t < NT; ++t) o4[t][v] = z[t];
         }
         if (depth > 1) write_act(lds, mtg, lane, o4);
         else out_accum(part, o4, Wout, mtg * 16 + g * 4);
@@ -371,98 +523,11 @@ struct Engine {
     __syncthreads();
 
     // ---------------- hidden layers 2..depth (MFMA) ----------------
-    for (int h = 0; h < depth - 1; ++h) {
-      const char* wl = packed + (size_t)h * Packing<S, PREC>::LAYER_BYTES;
-      const float* bias = params + pi.b[h + 1];
-      f32x4 acc[MT][NT];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int mtg = wave * MT + mt;
-        const float* bp = bias + mtg * 16 + g * 4;  // not 16-byte aligned in general
-        const f32x4 bv = {bp[0], bp[1], bp[2], bp[3]};
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const bool isval = C::kind(t % CC) == CK_VAL;
-          acc[mt][t] = isval ? bv : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        }
-      }
-      if constexpr (PREC == PREC_FP32) {
-        const f32x4* act = reinterpret_cast<const f32x4*>(lds);
-        const f32x4* wf = reinterpret_cast<const f32x4*>(wl);
-#pragma unroll 2
-        for (int kq = 0; kq < KQ; ++kq) {
-          f32x4 a[MT];
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) a[mt] = wf[((wave * MT + mt) * KQ + kq) * 64 + lane];
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            const f32x4 bfr = act[(t * KQ + kq) * 64 + lane];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-              acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt][0], bfr[0], acc[mt][t], 0, 0, 0);
-              acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt][1], bfr[1], acc[mt][t], 0, 0, 0);
-              acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt][2], bfr[2], acc[mt][t], 0, 0, 0);
-              acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt][3], bfr[3], acc[mt][t], 0, 0, 0);
-            }
-          }
-        }
-      } else {
-        const bf16x8* act = reinterpret_cast<const bf16x8*>(lds);
-        const bf16x8* wf = reinterpret_cast<const bf16x8*>(wl);
-        constexpr int LO = MTILES * KQ * 64;  // offset of the lo fragments
-#pragma unroll 2
-        for (int kb = 0; kb < KQ; ++kb) {
-          bf16x8 a[MT];
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) a[mt] = wf[((wave * MT + mt) * KQ + kb) * 64 + lane];
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            const bf16x8 bfr = act[(t * KQ + kb) * 64 + lane];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-              acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bfr, acc[mt][t], 0, 0, 0);
-          }
-          if constexpr (NSPL > 0) {
-            bf16x8 al[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) al[mt] = wf[LO + ((wave * MT + mt) * KQ + kb) * 64 + lane];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-#pragma unroll
-              for (int c = 0; c < CC; ++c) {
-                if (!is_split<C, PREC>(c)) continue;
-                const int t = b * CC + c;
-                const bf16x8 bh = act[(t * KQ + kb) * 64 + lane];
-                const bf16x8 bl = act[(lo_tile(b, c) * KQ + kb) * 64 + lane];
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                  acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bl, acc[mt][t], 0, 0, 0);
-                  acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bh, acc[mt][t], 0, 0, 0);
-                }
-              }
-            }
-          }
-        }
-      }
-      __syncthreads();  // every wave has read this layer's activations
-      const bool last = (h == depth - 2);
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int mtg = wave * MT + mt;
-        float o4[NT][4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          float z[NT], o[NT];
-#pragma unroll
-          for (int t = 0; t < NT; ++t) z[t] = acc[mt][t][v];
-          epilogue(z, o);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) o4[t][v] = o[t];
-        }
-        if (!last) write_act(lds, mtg, lane, o4);
-        else out_accum(part, o4, Wout, mtg * 16 + g * 4);
-      }
-      __syncthreads();
+    // Two layers per trip so that each weight-fragment buffer keeps a fixed
+    // register home.
+    for (int h = 0; h < depth - 1; h += 2) {
+      hidden_layer(lds, par, packed, depth, h, fa, fb, part, wave, lane);
+      if (h + 1 < depth - 1) hidden_layer(lds, par, packed, depth, h + 1, fb, fa, part, wave, lane);
     }
 
     // ---------------- output layer: reduce partial dot products ----------
@@ -484,7 +549,7 @@ struct Engine {
     }
     __syncthreads();
     float* res = reinterpret_cast<float*>(lds + RES_OFF);
-    const float* bout = params + pi.b[depth];
+    const float* bout = par + PC::BOUT(depth);
     for (int i = threadIdx.x; i < D * NT * PT; i += THREADS) {
       const int oo = i / (NT * PT);
       const int t = (i / PT) % NT;

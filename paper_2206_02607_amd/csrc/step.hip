@@ -4,36 +4,44 @@
 //
 // Two launches per step, both on the caller's stream with no host sync:
 //   setup   block map (16-sample batches of every instance), state init
-//   step    one cooperative (co-resident, persistent) kernel that loops:
-//     eval_jets    value, x tangents, Laplacian and latent Jacobian at q_n;
-//                  heat update f_{n+1} = g + dt nu Lap g (FP64), residual
-//                  rho_0 = f_{n+1} - g(q_n) = dt nu Lap g (formed directly),
-//                  and per-batch partial sums of J^T J, J^T rho and
-//                  1/2 rho^T rho (FP64)
-//     solve        per instance: fixed-order sum of the partials, Armijo test
-//                  of the evaluated trials, Cholesky of J^T J, next direction
-//     eval_trials  the decoder differences g(q_t) - g(q_n) at four line-search
-//                  trials q_t = q + alpha_t delta and the Jacobian at the
-//                  first one; residual rho_t = rho_0 - (g(q_t) - g(q_n)),
+//   step    one persistent kernel (cooperative launch, so that every
+//           workgroup is resident) running phases:
+//     phase 0      eval_jets: value, x tangents, Laplacian and latent
+//                  Jacobian at q_n; heat update f_{n+1} = g + dt nu Lap g
+//                  (FP64); residual rho_0 = f_{n+1} - g(q_n) = dt nu Lap g,
+//                  formed directly; per-batch partial sums of J^T J, J^T rho
+//                  and 1/2 rho^T rho (FP64)
+//     phase p > 0  eval_trials: the decoder differences g(q_t) - g(q_n) at
+//                  four line-search trials q_t = q + alpha_t delta and the
+//                  Jacobian at the first; rho_t = rho_0 - (g(q_t) - g(q_n)),
 //                  with the same partial sums
+//   The workgroup that completes the last batch of an instance in a phase
+//   solves that instance at once: fixed-order sum of its partials, Armijo
+//   test of the trials, Cholesky of J^T J, next direction.  A phase ends
+//   when every instance that was active in it has been solved.
 // The residual is the paper's f_{n+1} - g(q) written incrementally: over a
 // time step g moves by a small fraction of its size, and a difference
 // carried through the network keeps its rounding error relative to itself,
 // where a difference of two separately rounded values would not.
-//   with a grid barrier between phases, until every instance is done or a
-//   bound on the rounds (enough for max_iter iterations with ls_max shrinks)
-//   is reached.  Every workgroup takes the same branch at every barrier: the
-//   loop test reads a counter that only the solve phase writes.
-#include <hip/hip_cooperative_groups.h>
+//
+// Synchronisation.  Workgroups exchange only the batch partials, the
+// per-instance state and a few counters, always through device-coherent
+// loads and stores (relaxed atomics at agent scope: they bypass the
+// per-XCD L2 caches, which are not coherent with each other), and every
+// thread waits for its stores to complete before its workgroup signals.
+// No device-wide fence is taken, so the decoder weights stay cached across
+// phases.  Waits are bounded: a wait that exceeds its bound (about two
+// seconds) sets an abort word, every workgroup leaves, and the unfinished
+// instances report CROM_FLAG_ABORTED.
+#include <stddef.h>
 
 #include "common.hpp"
-
-namespace cg = cooperative_groups;
 
 namespace crom {
 
 constexpr int RMAX = 16;
-constexpr int TV = 4;  // line-search trials per round
+constexpr int TV = 4;        // line-search trials per round
+constexpr int MAXP = 256;    // bound on the phases of one step
 enum { PH_INIT = 0, PH_TRIALS = 1, PH_REJAC = 2, PH_DONE = 3 };
 
 struct GNState {
@@ -48,10 +56,14 @@ struct GNState {
 };
 
 struct WsLayout {
-  size_t blk_start, blk_inst, first_blk, nblk, active, targets, rho0, partials, state, total;
+  size_t blk_start, blk_inst, first_blk, nblk, sync, act_phase, inst_cnt, targets, rho0, partials,
+      state, total;
   int64_t nblk_max;
   int nred;
 };
+
+// sync words (one 256-byte line each): solved count, abort flag
+enum { SYNC_SOLVED = 0, SYNC_ABORT = 32 };
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -64,7 +76,9 @@ static WsLayout ws_layout(int r, int d, int n_inst, int64_t total) {
   L.blk_inst = o;  o = align256(o + 4 * (size_t)L.nblk_max);
   L.first_blk = o; o = align256(o + 4 * (size_t)(n_inst + 1));
   L.nblk = o;      o = align256(o + 8);
-  L.active = o;    o = align256(o + 8);
+  L.sync = o;      o = align256(o + 512);
+  L.act_phase = o; o = align256(o + 8 * (size_t)(MAXP + 2));
+  L.inst_cnt = o;  o = align256(o + 4 * (size_t)n_inst);
   L.targets = o;   o = align256(o + 8 * (size_t)total * d);
   L.rho0 = o;      o = align256(o + 8 * (size_t)total * d);
   L.partials = o;  o = align256(o + 8 * (size_t)L.nblk_max * L.nred);
@@ -91,6 +105,7 @@ struct StepArgs {
   WsLayout L;
   int max_iter, linearized, ls_max;
   double tol, armijo_c, shrink;
+  uint64_t* trace;  // optional phase timestamps (see crom_debug_step_trace)
 };
 
 template <class T>
@@ -98,82 +113,149 @@ __device__ __forceinline__ T* wsp(const StepArgs& a, size_t off) {
   return reinterpret_cast<T*>(a.ws + off);
 }
 
+// Device-coherent accesses (see the synchronisation note above).
+template <class T>
+__device__ __forceinline__ T ld_c(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void st_c(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// every thread: wait until this thread's memory operations have completed
+__device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Phase timestamps of workgroups 0 and G-1 (wall clock, 100 MHz ticks),
+// written only when a trace buffer was registered.
+__device__ __forceinline__ void trace_mark(const StepArgs& a, int slot) {
+  if (a.trace && threadIdx.x == 0 && slot < 64) {
+    if (blockIdx.x == 0) a.trace[slot] = wall_clock64();
+    if (blockIdx.x == gridDim.x - 1) a.trace[64 + slot] = wall_clock64();
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Block map and state initialisation (one workgroup of 256 threads).
+// Block map and state initialisation (one workgroup of 1024 threads).
 // Offsets that are not a valid CSR array (a negative size, a range outside
-// [0, total]) give every instance zero batches: nothing is evaluated and the
-// instances end SINGULAR.  Valid CSR ranges are disjoint, so the batch count
-// stays within the bound the workspace was sized for.
+// [0, total]) give every instance zero batches; an instance without batches
+// ends at once as SINGULAR with q_{n+1} = q_n.  Valid CSR ranges are
+// disjoint, so the batch count stays within the bound the workspace was
+// sized for.  Up to SETUP_LDS instances the prefix and the offsets are kept
+// in LDS for the block fill; beyond that they are read back from memory.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void setup_kernel(StepArgs a) {
+constexpr int SETUP_THREADS = 1024;
+constexpr int SETUP_LDS = 2048;
+
+__global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(StepArgs a) {
   int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
   int64_t* blk_start = wsp<int64_t>(a, a.L.blk_start);
   int32_t* blk_inst = wsp<int32_t>(a, a.L.blk_inst);
+  int64_t* act_phase = wsp<int64_t>(a, a.L.act_phase);
+  uint32_t* inst_cnt = wsp<uint32_t>(a, a.L.inst_cnt);
+  uint64_t* sync = wsp<uint64_t>(a, a.L.sync);
   GNState* st = wsp<GNState>(a, a.L.state);
-  __shared__ int32_t scan[256];
+  __shared__ int32_t scan[SETUP_THREADS];
+  __shared__ int32_t fb[SETUP_LDS + 1];
+  __shared__ int64_t lo_off[SETUP_LDS];
   __shared__ int32_t carry;
+  __shared__ int32_t n_active;
+  const int tid = threadIdx.x;
+  const bool in_lds = a.n_inst <= SETUP_LDS;
   int bad = 0;
-  for (int i = threadIdx.x; i < a.n_inst; i += 256) {
+  for (int i = tid; i < a.n_inst; i += SETUP_THREADS) {
     const int64_t lo = a.offsets[i], hi = a.offsets[i + 1];
     bad |= !(lo >= 0 && hi >= lo && hi <= a.total);
+    if (in_lds) lo_off[i] = lo;
   }
   bad = __syncthreads_or(bad);
-  if (threadIdx.x == 0) carry = 0;
+  if (tid == 0) {
+    carry = 0;
+    n_active = 0;
+  }
   __syncthreads();
-  for (int c = 0; c < a.n_inst; c += 256) {
-    const int i = c + threadIdx.x;
+  for (int c = 0; c < a.n_inst; c += SETUP_THREADS) {
+    const int i = c + tid;
     int32_t nb = 0;
     if (i < a.n_inst && !bad) nb = (int32_t)((a.offsets[i + 1] - a.offsets[i] + PT - 1) / PT);
-    scan[threadIdx.x] = nb;
+    scan[tid] = nb;
     __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {  // inclusive Hillis-Steele scan
-      const int32_t v = threadIdx.x >= d ? scan[threadIdx.x - d] : 0;
+    for (int d = 1; d < SETUP_THREADS; d <<= 1) {  // inclusive Hillis-Steele scan
+      const int32_t v = tid >= d ? scan[tid - d] : 0;
       __syncthreads();
-      scan[threadIdx.x] += v;
+      scan[tid] += v;
       __syncthreads();
     }
-    if (i < a.n_inst) first_blk[i] = carry + scan[threadIdx.x] - nb;
+    if (i < a.n_inst) {
+      const int32_t f = carry + scan[tid] - nb;
+      first_blk[i] = f;
+      if (in_lds) fb[i] = f;
+      if (nb > 0) atomicAdd(&n_active, 1);
+    }
     __syncthreads();
-    if (threadIdx.x == 255) carry += scan[255];
+    if (tid == SETUP_THREADS - 1) carry += scan[SETUP_THREADS - 1];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    first_blk[a.n_inst] = carry;
-    *wsp<int64_t>(a, a.L.nblk) = carry;
-    *wsp<int64_t>(a, a.L.active) = a.n_inst;
+  const int32_t nblk = carry;
+  if (tid == 0) {
+    first_blk[a.n_inst] = nblk;
+    if (in_lds) fb[a.n_inst] = nblk;
+    *wsp<int64_t>(a, a.L.nblk) = nblk;
+    sync[SYNC_SOLVED] = 0;
+    sync[SYNC_ABORT] = 0;
+    act_phase[0] = n_active;
   }
+  for (int p = tid + 1; p < MAXP + 2; p += SETUP_THREADS) act_phase[p] = 0;
+  for (int i = tid; i < a.n_inst; i += SETUP_THREADS) inst_cnt[i] = 0;
   __syncthreads();
-  // batches: instance i owns first_blk[i] .. first_blk[i+1]-1
-  for (int i = threadIdx.x; i < a.n_inst; i += 256) {
-    const int32_t b0 = first_blk[i], b1 = first_blk[i + 1];
-    for (int32_t b = b0; b < b1; ++b) {
-      blk_start[b] = a.offsets[i] + (int64_t)(b - b0) * PT;
-      blk_inst[b] = i;
+  // batch b belongs to the instance i with fb[i] <= b < fb[i+1] (binary search)
+  const int32_t* fbp = in_lds ? fb : first_blk;
+  for (int32_t b = tid; b < nblk; b += SETUP_THREADS) {
+    int lo = 0, hi = a.n_inst - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (fbp[mid] <= b) lo = mid;
+      else hi = mid - 1;
     }
+    const int64_t base = in_lds ? lo_off[lo] : a.offsets[lo];
+    blk_start[b] = base + (int64_t)(b - fbp[lo]) * PT;
+    blk_inst[b] = lo;
   }
   // state: one 8-byte word per thread step
   constexpr int NWORD = sizeof(GNState) / 8;
-  for (int64_t w = threadIdx.x; w < (int64_t)a.n_inst * NWORD; w += 256) {
+  constexpr int W_OBJ = (int)(offsetof(GNState, obj_first) / 8);
+  constexpr int W_PHASE = (int)(offsetof(GNState, phase) / 8);  // phase and iters share this word
+  constexpr int W_FLAGS = (int)(offsetof(GNState, ls_evals) / 8);  // ls_evals and flags
+  for (int64_t w = tid; w < (int64_t)a.n_inst * NWORD; w += SETUP_THREADS) {
     const int i = (int)(w / NWORD), k = (int)(w % NWORD);
-    GNState* s = st + i;
-    uint64_t* word = reinterpret_cast<uint64_t*>(s) + k;
-    const int qk = k;  // q[] occupies the first RMAX words
-    if (qk < RMAX) {
-      const double v = qk < a.r ? a.q_n[(int64_t)i * a.r + qk] : 0.0;
-      *reinterpret_cast<double*>(word) = v;
-    } else {
-      *word = 0;
+    uint64_t* word = reinterpret_cast<uint64_t*>(st + i) + k;
+    const bool empty = fbp[i + 1] == fbp[i];
+    uint64_t v = 0;
+    if (k < RMAX) {  // q[] occupies the first RMAX words
+      const double d = k < a.r ? a.q_n[(int64_t)i * a.r + k] : 0.0;
+      v = __double_as_longlong(d);
+    } else if (k == W_OBJ || k == W_OBJ + 1) {
+      v = __double_as_longlong(__builtin_nan(""));
+    } else if (k == W_PHASE) {
+      v = (uint64_t)(uint32_t)(empty ? PH_DONE : PH_INIT);  // iters = 0 in the high half
+    } else if (k == W_FLAGS) {
+      v = empty ? ((uint64_t)(uint32_t)CROM_FLAG_SINGULAR << 32) : 0;  // ls_evals = 0, flags
     }
+    *word = v;
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < a.n_inst; i += 256) {
-    st[i].obj_first = st[i].obj_last = __builtin_nan("");
-    st[i].phase = PH_INIT;
+  for (int i = tid; i < a.n_inst; i += SETUP_THREADS) {
+    if (fbp[i + 1] != fbp[i]) continue;
+    for (int k = 0; k < a.r; ++k) a.q_next[(int64_t)i * a.r + k] = a.q_n[(int64_t)i * a.r + k];
+    crom_step_info inf;
+    inf.flags = CROM_FLAG_SINGULAR;
+    inf.iters = inf.ls_evals = inf.rounds = 0;
+    inf.obj_first = inf.obj_last = __builtin_nan("");
+    a.info[i] = inf;
   }
 }
 
 // Partial sums of one batch from per-point J rows and residuals staged in LDS
-// (jd [PT][R], rho [PT][TV], both FP64; invalid points hold zeros).
+// (jd [PT][R], rho [PT][TV], both FP64; invalid points hold zeros), stored
+// device-coherently for the solving workgroup.
 template <int R>
 __device__ __forceinline__ void batch_partials(const double* jd, const double* rho, double* out) {
   constexpr int NA = R * (R + 1) / 2;
@@ -192,26 +274,26 @@ __device__ __forceinline__ void batch_partials(const double* jd, const double* r
       const int t = e - NA - R;
       for (int i = 0; i < PT; ++i) s += 0.5 * rho[i * TV + t] * rho[i * TV + t];
     }
-    out[e] = s;
+    st_c(out + e, s);
   }
 }
 
-
 // ---------------------------------------------------------------------------
-// Evaluation of one 16-sample batch (all threads of the workgroup).
+// Evaluation of one 16-sample batch (all threads of the workgroup).  `qdl`:
+// LDS scratch for the trial latents.
 // ---------------------------------------------------------------------------
-template <class S, int NW, int PREC>
-__device__ void eval_jets_batch(const StepArgs& a, char* lds, int64_t blk) {
+template <class S, int NW, int PREC, int PF>
+__device__ void eval_jets_batch(const StepArgs& a, char* lds, const float* par, int64_t blk) {
   constexpr int R = S::R;
   using C = Cols<S::M, R, 1, 0, true, D2_LAP, R>;
-  using E = Engine<S, C, 1, NW, PREC>;
+  using E = Engine<S, C, 1, NW, PREC, PF>;
   const int inst = wsp<int32_t>(a, a.L.blk_inst)[blk];
   const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
   const int64_t rem = a.offsets[inst + 1] - first;
   const int n_valid = rem < PT ? (int)rem : PT;
-  E::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * R, R, nullptr, 0, a.params, a.pi);
+  E::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * R, R, nullptr, 0, par);
   __syncthreads();
-  E::run(lds, a.params, a.pi, a.packed, a.depth, 0);
+  E::run(lds, par, a.packed, a.depth, 0);
   const float* res = reinterpret_cast<const float*>(lds + E::RES_OFF);
   double* jd = reinterpret_cast<double*>(lds);  // the activation region is free now
   double* rho = jd + PT * R;
@@ -227,7 +309,7 @@ __device__ void eval_jets_batch(const StepArgs& a, char* lds, int64_t blk) {
     const double r0 = clamped ? -gv : a.dt * a.coef[inst] * lap;
     if (valid) {
       targets[p] = clamped ? 0.0 : gv + r0;
-      rho0[p] = r0;
+      rho0[p] = r0;  // read back by this same workgroup in later phases
     }
     rho[i * TV] = valid ? r0 : 0.0;
     for (int t = 1; t < TV; ++t) rho[i * TV + t] = 0.0;
@@ -238,19 +320,25 @@ __device__ void eval_jets_batch(const StepArgs& a, char* lds, int64_t blk) {
   __syncthreads();
 }
 
-template <class S, int NW, int PREC>
-__device__ void eval_trials_batch(const StepArgs& a, char* lds, int64_t blk, int inst) {
+template <class S, int NW, int PREC, int PF>
+__device__ void eval_trials_batch(const StepArgs& a, char* lds, const float* par, double* qdl,
+                                  int64_t blk, int inst, int mb) {
   constexpr int R = S::R;
   using C = Cols<S::M, R, 1, TV, false, D2_NONE, R>;
-  using E = Engine<S, C, 1, NW, PREC>;
+  using E = Engine<S, C, 1, NW, PREC, PF>;
   const GNState* st = wsp<GNState>(a, a.L.state) + inst;
+  if (mb >= 0) trace_mark(a, mb);
+  for (int i = threadIdx.x; i < TV * R; i += blockDim.x) qdl[i] = ld_c(&st->qd[i / R][i % R]);
+  __syncthreads();
+  if (mb >= 0) trace_mark(a, mb + 1);
   const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
   const int64_t rem = a.offsets[inst + 1] - first;
   const int n_valid = rem < PT ? (int)rem : PT;
-  E::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * R, R, &st->qd[0][0], RMAX, a.params,
-           a.pi);
+  E::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * R, R, qdl, R, par);
   __syncthreads();
-  E::run(lds, a.params, a.pi, a.packed, a.depth, 0);
+  if (mb >= 0) trace_mark(a, mb + 2);
+  E::run(lds, par, a.packed, a.depth, 0);
+  if (mb >= 0) trace_mark(a, mb + 3);
   const float* res = reinterpret_cast<const float*>(lds + E::RES_OFF);
   double* jd = reinterpret_cast<double*>(lds);
   double* rho = jd + PT * R;
@@ -268,46 +356,140 @@ __device__ void eval_trials_batch(const StepArgs& a, char* lds, int64_t blk, int
 }
 
 // ---------------------------------------------------------------------------
-// Gauss-Newton control of one instance.  The workgroup copies the state to
-// LDS and sums the partials in a fixed order (every thread a strided subset
-// of the batches for one entry, then the subsets in order); thread 0 then
-// takes the decisions on register copies; the workgroup writes the state
-// back.
+// Small dense algebra on one wave (64 lanes), FP64.
+// A symmetric R x R matrix is held one element per lane and slot: element
+// e = lane + 64 * slot is (i, k) = (e / R, e % R).  fetch(x, i, k) returns
+// element (i, k) of x to every lane that asks for it.
 // ---------------------------------------------------------------------------
 template <int R>
-__device__ void solve_instance(const StepArgs& a, char* lds, int inst, bool is_last) {
+struct WaveMat {
+  static constexpr int NE = (R * R + 63) / 64;
+  double v[NE];
+  __device__ __forceinline__ double fetch(int i, int k) const {
+    const int e = i * R + k;
+    const int src = e & 63, slot = e >> 6;
+    double out = 0.0;
+#pragma unroll
+    for (int s = 0; s < NE; ++s) {
+      const double t = __shfl(v[s], src);
+      out = (slot == s) ? t : out;
+    }
+    return out;
+  }
+};
+
+// Cholesky factorisation A = L L^T of the packed upper triangle `up` (LDS,
+// row-major over i <= k), right-looking, one column per step; then the
+// solves L y = b and L^T x = y.  A pivot (the value under the square root)
+// that is not finite or not above thresh = 1e-14 * max diag(A) fails the
+// factorisation (returns false).  On success lane k < R returns x_k.
+template <int R>
+__device__ bool wave_chol_solve(const double* up, const double* b, double& xk) {
+  const int lane = threadIdx.x & 63;
+  WaveMat<R> A;
+  double dmax = -1.0;
+#pragma unroll
+  for (int s = 0; s < WaveMat<R>::NE; ++s) {
+    const int e = lane + 64 * s;
+    double val = 0.0;
+    if (e < R * R) {
+      int i = e / R, k = e % R;
+      if (i > k) { const int t = i; i = k; k = t; }
+      val = up[i * R - i * (i - 1) / 2 + (k - i)];
+      if (i == k) dmax = fmax(dmax, val);
+    }
+    A.v[s] = val;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o));
+  const double thresh = 1e-14 * dmax;
+  for (int j = 0; j < R; ++j) {
+    const double d = A.fetch(j, j);
+    if (!(isfinite(d) && d > thresh)) return false;  // uniform across the wave
+    const double ljj = sqrt(d);
+    const double inv = 1.0 / ljj;
+#pragma unroll
+    for (int s = 0; s < WaveMat<R>::NE; ++s) {
+      const int e = lane + 64 * s;
+      const int i = e / R, k = e % R;
+      const double lij = A.fetch(i < R ? i : 0, j) * inv;
+      const double lkj = A.fetch(k, j) * inv;
+      double val = A.v[s];
+      if (e < R * R) {
+        if (i > j && k > j) val -= lij * lkj;
+        else if (k == j && i > j) val = lij;
+        else if (i == j && k == j) val = ljj;
+      }
+      A.v[s] = val;
+    }
+  }
+  // lane i holds row i of the substitutions
+  const int i = lane;
+  double acc = i < R ? b[i] : 0.0;
+  double y = 0.0;
+  for (int j = 0; j < R; ++j) {  // L y = b
+    const double yj = __shfl(acc, j) / A.fetch(j, j);
+    const double lij = A.fetch(i < R ? i : 0, j);  // every lane takes part in the shuffles
+    if (i == j) y = yj;
+    if (i > j && i < R) acc -= lij * yj;
+  }
+  acc = y;
+  double x = 0.0;
+  for (int j = R - 1; j >= 0; --j) {  // L^T x = y
+    const double xj = __shfl(acc, j) / A.fetch(j, j);
+    const double lji = A.fetch(j, i < R ? i : 0);
+    if (i == j) x = xj;
+    if (i < j) acc -= lji * xj;
+  }
+  xk = x;
+  return true;
+}
+
+
+// ---------------------------------------------------------------------------
+// Gauss-Newton control of one instance in phase p, by the workgroup that
+// completed the instance's last batch of the phase.  The workgroup copies
+// the state to LDS and sums the partials in a fixed order (every thread a
+// strided subset of the batches for one entry, all its loads issued
+// together, then the subsets in order).  Wave 0 then takes the decisions:
+// every lane evaluates the same scalar rules from LDS, the vectors are
+// spread over the lanes.  Finally the state goes back, the instance's
+// arrival counter is reset, and the phase's counters are advanced.
+// ---------------------------------------------------------------------------
+template <int R>
+__device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bool is_last) {
   constexpr int NA = R * (R + 1) / 2;
   constexpr int NRED = NA + R + TV;
   constexpr int NWORD = sizeof(GNState) / 8;
+  constexpr int UNR = 16;  // loads in flight per thread
   GNState* gst = wsp<GNState>(a, a.L.state) + inst;
   GNState* st = reinterpret_cast<GNState*>(lds);
   double* sub = reinterpret_cast<double*>(lds + ((sizeof(GNState) + 15) / 16) * 16);
   const int nth = blockDim.x;
   const int NS = nth / NRED;  // strided subsets per entry
   double* red = sub + NS * NRED;
+  __shared__ int s_done;
   for (int w = threadIdx.x; w < NWORD; w += nth)
-    reinterpret_cast<uint64_t*>(st)[w] = reinterpret_cast<const uint64_t*>(gst)[w];
+    reinterpret_cast<uint64_t*>(st)[w] = ld_c(reinterpret_cast<const uint64_t*>(gst) + w);
   __syncthreads();
   const int phase = st->phase;
-  if (phase == PH_DONE) {
-    __syncthreads();
-    return;
-  }
   const int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
   const int32_t b0 = first_blk[inst], b1 = first_blk[inst + 1];
   const double* part = wsp<double>(a, a.L.partials);
   if (threadIdx.x < NS * NRED) {
     const int e = threadIdx.x % NRED, sl = threadIdx.x / NRED;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int32_t b = b0 + sl;
-    for (; b + 3 * NS < b1; b += 4 * NS) {
-      s0 += part[(int64_t)b * NRED + e];
-      s1 += part[(int64_t)(b + NS) * NRED + e];
-      s2 += part[(int64_t)(b + 2 * NS) * NRED + e];
-      s3 += part[(int64_t)(b + 3 * NS) * NRED + e];
+    double acc = 0.0;
+    for (int32_t base = b0 + sl; base < b1; base += UNR * NS) {
+      double v[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {  // clamped, branch-free: all loads issue at once
+        const int32_t b = base + u * NS;
+        v[u] = ld_c(part + (int64_t)(b < b1 ? b : b0) * NRED + e);
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) acc += (base + u * NS < b1) ? v[u] : 0.0;
     }
-    for (; b < b1; b += NS) s0 += part[(int64_t)b * NRED + e];
-    sub[sl * NRED + e] = (s0 + s1) + (s2 + s3);
+    sub[sl * NRED + e] = acc;
   }
   __syncthreads();
   if (threadIdx.x < NRED) {
@@ -317,25 +499,25 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, bool is_l
   }
   __syncthreads();
 
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
     const double* qn0 = a.q_n + (int64_t)inst * R;
-    double q[R], dl[R], qn0r[R], alpha[TV];
-    for (int k = 0; k < R; ++k) {
-      q[k] = st->q[k];
-      dl[k] = st->delta[k];
-      qn0r[k] = qn0[k];
-    }
-    for (int t = 0; t < TV; ++t) alpha[t] = st->alpha[t];
-    double phi = st->phi, slope = st->slope, dnorm = st->dnorm;
-    int iters = st->iters, ls_evals = st->ls_evals, flags = st->flags, ls_tried = st->ls_tried;
-    int ph = phase;
-    if (ph != PH_INIT) st->rounds += 1;
     const double* bv = red + NA;
     const double* phit = red + NA + R;
+    // scalar state (identical in every lane)
+    double phi = st->phi, slope = st->slope, dnorm = st->dnorm;
+    double alpha[TV];
+    for (int t = 0; t < TV; ++t) alpha[t] = st->alpha[t];
+    int iters = st->iters, ls_evals = st->ls_evals, flags = st->flags, ls_tried = st->ls_tried;
+    int ph = phase;
+    double obj_first = st->obj_first, obj_last = st->obj_last;
+    // vectors: lane k < R holds entry k
+    double qk = lane < R ? st->q[lane] : 0.0;
+    double dk = lane < R ? st->delta[lane] : 0.0;
     bool done = false, newdir = false;
     int settrials = 0;  // 1: trials q + alpha_t delta; 2: every trial at q (re-linearise)
     if (ph == PH_INIT) {
-      st->obj_first = st->obj_last = phi = phit[0];
+      obj_first = obj_last = phi = phit[0];
       newdir = true;
     } else if (ph == PH_TRIALS) {
       int acc = -1;
@@ -362,15 +544,15 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, bool is_l
           settrials = 1;
         }
       } else {
-        double qn = 0.0;
-        for (int k = 0; k < R; ++k) qn += q[k] * q[k];
-        qn = sqrt(qn);
+        double qq = qk * qk;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) qq += __shfl_xor(qq, o);
         const double step = alpha[acc] * dnorm;
-        for (int k = 0; k < R; ++k) q[k] = st->qt[acc][k];
+        qk = lane < R ? st->qt[acc][lane] : 0.0;
         iters += 1;
         phi = phit[acc];
-        st->obj_last = phi;
-        if (step <= a.tol * (1.0 + qn)) {
+        obj_last = phi;
+        if (step <= a.tol * (1.0 + sqrt(qq))) {
           done = true;
         } else if (iters >= a.max_iter) {
           flags |= CROM_FLAG_MAXITER;
@@ -388,68 +570,31 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, bool is_l
 
     if (newdir) {
       bool finite = isfinite(phi);
-      for (int e = 0; e < NA + R; ++e) finite = finite && isfinite(red[e]);
+      for (int e = 0; e < NA + R; ++e) finite &= (bool)isfinite(red[e]);
       if (!finite) {
         flags |= CROM_FLAG_NONFINITE;
         done = true;
       } else {
-        double L[R][R];
-        double A[R][R];
-        {
-          int e = 0;
-          for (int i = 0; i < R; ++i)
-            for (int j = i; j < R; ++j) {
-              A[i][j] = red[e];
-              A[j][i] = red[e];
-              ++e;
-            }
-        }
-        double dmax = A[0][0];
-        for (int i = 1; i < R; ++i) dmax = fmax(dmax, A[i][i]);
-        const double thresh = 1e-14 * dmax;
-        bool ok = true;
-        for (int j = 0; j < R; ++j) {
-          double sj = A[j][j];
-          for (int k = 0; k < j; ++k) sj -= L[j][k] * L[j][k];
-          if (!(isfinite(sj) && sj > thresh)) {
-            ok = false;
-            break;
-          }
-          L[j][j] = sqrt(sj);
-          for (int i = j + 1; i < R; ++i) {
-            double t = A[i][j];
-            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
-            L[i][j] = t / L[j][j];
-          }
-        }
-        if (!ok) {
+        double xk = 0.0;
+        if (!wave_chol_solve<R>(red, bv, xk)) {
           flags |= CROM_FLAG_SINGULAR;
           done = true;
         } else {
-          double y[R], x[R];
-          for (int i = 0; i < R; ++i) {
-            double t = bv[i];
-            for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
-            y[i] = t / L[i][i];
+          if (lane >= R) xk = 0.0;
+          double dn = xk * xk, qq = qk * qk, sl = lane < R ? bv[lane] * xk : 0.0;
+#pragma unroll
+          for (int o = 32; o >= 1; o >>= 1) {
+            dn += __shfl_xor(dn, o);
+            qq += __shfl_xor(qq, o);
+            sl += __shfl_xor(sl, o);
           }
-          for (int i = R - 1; i >= 0; --i) {
-            double t = y[i];
-            for (int k = i + 1; k < R; ++k) t -= L[k][i] * x[k];
-            x[i] = t / L[i][i];
-          }
-          double dn = 0.0, qn = 0.0, sl = 0.0;
-          for (int k = 0; k < R; ++k) {
-            dl[k] = x[k];
-            dn += x[k] * x[k];
-            qn += q[k] * q[k];
-            sl += bv[k] * x[k];
-          }
+          dk = xk;
           dnorm = sqrt(dn);
           if (a.linearized) {
-            for (int k = 0; k < R; ++k) q[k] += x[k];
+            qk += xk;
             iters = 1;
             done = true;
-          } else if (dnorm <= a.tol * (1.0 + sqrt(qn))) {
+          } else if (dnorm <= a.tol * (1.0 + sqrt(qq))) {
             done = true;
           } else {
             slope = sl;
@@ -469,124 +614,197 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, bool is_l
       flags |= CROM_FLAG_MAXITER;
       done = true;
     }
-    if (!done && settrials) {
-      for (int t = 0; t < TV; ++t) {
-        const double al = settrials == 1 ? alpha[t] : 0.0;
-        for (int k = 0; k < R; ++k) {
-          st->qt[t][k] = q[k] + al * dl[k];
-          st->qd[t][k] = (q[k] - qn0r[k]) + al * dl[k];
-        }
-      }
+    if (done) ph = PH_DONE;
+    // vector entries: lane k < R
+    if (lane < R) {
+      st->q[lane] = qk;
+      st->delta[lane] = dk;
+      st_c(a.q_next + (int64_t)inst * R + lane, qk);  // coherent: solvers of later phases may sit on other XCDs
     }
-    if (done) {
-      ph = PH_DONE;
-      atomicAdd(reinterpret_cast<unsigned long long*>(wsp<int64_t>(a, a.L.active)),
-                (unsigned long long)-1ll);
+    // trial latents: lane t * R + k (TV * R <= 64)
+    const double q_k = __shfl(qk, lane % R), d_k = __shfl(dk, lane % R);  // all lanes shuffle
+    if (!done && settrials && lane < TV * R) {
+      const int t = lane / R, k = lane % R;
+      const double al = settrials == 1 ? alpha[t] : 0.0;
+      st->qt[t][k] = q_k + al * d_k;
+      st->qd[t][k] = (q_k - qn0[k]) + al * d_k;
     }
-    for (int k = 0; k < R; ++k) {
-      st->q[k] = q[k];
-      st->delta[k] = dl[k];
-      a.q_next[(int64_t)inst * R + k] = q[k];
+    if (lane == 0) {
+      for (int t = 0; t < TV; ++t) st->alpha[t] = alpha[t];
+      st->phi = phi;
+      st->slope = slope;
+      st->dnorm = dnorm;
+      st->iters = iters;
+      st->ls_evals = ls_evals;
+      st->flags = flags;
+      st->ls_tried = ls_tried;
+      st->obj_first = obj_first;
+      st->obj_last = obj_last;
+      if (phase != PH_INIT) st->rounds += 1;
+      st->phase = ph;
+      s_done = done ? 1 : 0;
+      crom_step_info* inf = a.info + inst;
+      st_c(&inf->flags, flags);
+      st_c(&inf->iters, iters);
+      st_c(&inf->ls_evals, ls_evals);
+      st_c(&inf->rounds, st->rounds);
+      st_c(&inf->obj_first, obj_first);
+      st_c(&inf->obj_last, obj_last);
     }
-    for (int t = 0; t < TV; ++t) st->alpha[t] = alpha[t];
-    st->phi = phi;
-    st->slope = slope;
-    st->dnorm = dnorm;
-    st->iters = iters;
-    st->ls_evals = ls_evals;
-    st->flags = flags;
-    st->ls_tried = ls_tried;
-    st->phase = ph;
-    crom_step_info inf;
-    inf.flags = flags;
-    inf.iters = iters;
-    inf.ls_evals = ls_evals;
-    inf.rounds = st->rounds;
-    inf.obj_first = st->obj_first;
-    inf.obj_last = st->obj_last;
-    a.info[inst] = inf;
   }
   __syncthreads();
   for (int w = threadIdx.x; w < NWORD; w += nth)
-    reinterpret_cast<uint64_t*>(gst)[w] = reinterpret_cast<const uint64_t*>(st)[w];
+    st_c(reinterpret_cast<uint64_t*>(gst) + w, reinterpret_cast<const uint64_t*>(st)[w]);
+  if (threadIdx.x == 0) {
+    st_c(wsp<uint32_t>(a, a.L.inst_cnt) + inst, 0u);
+    if (!s_done) atomicAdd(reinterpret_cast<unsigned long long*>(wsp<int64_t>(a, a.L.act_phase) + p + 1), 1ull);
+  }
+  wait_mem();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicAdd(reinterpret_cast<unsigned long long*>(wsp<uint64_t>(a, a.L.sync) + SYNC_SOLVED), 1ull);
   __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // The persistent step kernel (cooperative launch: every workgroup resident).
 // ---------------------------------------------------------------------------
-template <class S, int NW, int PREC>
+constexpr int64_t SPIN_MAX = int64_t(1) << 21;  // bounded waits: ~2e6 polls of ~1 us
+
+template <class S, int NW, int PREC, int PF>
 __global__ __launch_bounds__(NW * 64) void step_kernel(StepArgs a, int max_rounds) {
+  using EJ = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC, PF>;
+  using ET = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, S::R>, 1, NW, PREC, PF>;
+  constexpr int PAR = EJ::LDS_BYTES > ET::LDS_BYTES ? EJ::LDS_BYTES : ET::LDS_BYTES;
   extern __shared__ __align__(16) char lds[];
-  cg::grid_group grid = cg::this_grid();
+  __shared__ int s_last, s_abort, s_ph;
+  __shared__ int64_t s_act;
+  __shared__ double qdl[TV * RMAX];
+  float* par = reinterpret_cast<float*>(lds + PAR);
+  EJ::PC::load(par, a.params, a.pi, a.depth, NW * 64);
+  __syncthreads();
   const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
   const int32_t* blk_inst = wsp<int32_t>(a, a.L.blk_inst);
-  const GNState* state = wsp<GNState>(a, a.L.state);
-  int64_t* active = wsp<int64_t>(a, a.L.active);
-
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) eval_jets_batch<S, NW, PREC>(a, lds, blk);
-  grid.sync();
-  for (int inst = blockIdx.x; inst < a.n_inst; inst += gridDim.x)
-    solve_instance<S::R>(a, lds, inst, max_rounds == 0);
-  grid.sync();
-  for (int round = 0; round < max_rounds; ++round) {
-    if (__hip_atomic_load(active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+  const int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
+  GNState* state = wsp<GNState>(a, a.L.state);
+  uint32_t* inst_cnt = wsp<uint32_t>(a, a.L.inst_cnt);
+  int64_t* act_phase = wsp<int64_t>(a, a.L.act_phase);
+  uint64_t* sync = wsp<uint64_t>(a, a.L.sync);
+  uint64_t target = 0;
+  bool aborted = false;
+  for (int p = 0; p <= max_rounds && !aborted; ++p) {
+    if (threadIdx.x == 0) s_act = ld_c(act_phase + p);  // stable: written only by phase p-1 solves
+    __syncthreads();
+    const int64_t act = s_act;
+    __syncthreads();
+    if (act == 0) break;
+    target += (uint64_t)act;
+    trace_mark(a, 4 * p);
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
       const int inst = blk_inst[blk];
-      const int ph = __hip_atomic_load(&state[inst].phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (ph == PH_TRIALS || ph == PH_REJAC) eval_trials_batch<S, NW, PREC>(a, lds, blk, inst);
+      if (p == 0) {
+        eval_jets_batch<S, NW, PREC, PF>(a, lds, par, blk);
+      } else {
+        if (threadIdx.x == 0) s_ph = ld_c(&state[inst].phase);  // stable until this batch arrives
+        __syncthreads();
+        const int ph = s_ph;
+        __syncthreads();
+        if (ph != PH_TRIALS && ph != PH_REJAC) continue;
+        eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, (p == 1 && blk == blockIdx.x) ? 40 : -1);
+      }
+      // arrival: the partials of this batch are complete in memory
+      if (p == 1 && blk == blockIdx.x) trace_mark(a, 44);
+      wait_mem();
+      __syncthreads();
+      if (p == 1 && blk == blockIdx.x) trace_mark(a, 45);
+      if (threadIdx.x == 0) {
+        const uint32_t nb = (uint32_t)(first_blk[inst + 1] - first_blk[inst]);
+        const uint32_t old = atomicAdd(inst_cnt + inst, 1u);
+        s_last = (old + 1 == nb);
+      }
+      __syncthreads();
+      const bool last = s_last != 0;
+      __syncthreads();  // every thread has read s_last before thread 0 may write it again
+      if (p == 1 && blk == blockIdx.x) trace_mark(a, 46);
+      if (last) solve_instance<S::R>(a, lds, inst, p, p == max_rounds);
+      if (p == 1 && blk == blockIdx.x) trace_mark(a, 47);
     }
-    grid.sync();
-    for (int inst = blockIdx.x; inst < a.n_inst; inst += gridDim.x)
-      solve_instance<S::R>(a, lds, inst, round == max_rounds - 1);
-    grid.sync();
+    trace_mark(a, 4 * p + 1);
+    // wait until every instance active in this phase has been solved
+    if (threadIdx.x == 0) {
+      int64_t spins = 0;
+      while (ld_c(sync + SYNC_SOLVED) < target) {
+        if (ld_c(sync + SYNC_ABORT) != 0 || ++spins > SPIN_MAX) {
+          st_c(sync + SYNC_ABORT, (uint64_t)1);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      s_abort = ld_c(sync + SYNC_ABORT) != 0;
+    }
+    __syncthreads();
+    aborted = s_abort != 0;
+    trace_mark(a, 4 * p + 2);
+  }
+  if (aborted && blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < a.n_inst; i += blockDim.x) {
+      if (ld_c(&state[i].phase) != PH_DONE)
+        st_c(&a.info[i].flags, ld_c(&a.info[i].flags) | CROM_FLAG_ABORTED);
+    }
   }
 }
 
-template <class S, int NW, int PREC>
+template <class S, int NW, int PREC, int PF>
 static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
-  using EJ = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC>;
-  using ET = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, S::R>, 1, NW, PREC>;
-  constexpr int LDS = EJ::LDS_BYTES > ET::LDS_BYTES ? EJ::LDS_BYTES : ET::LDS_BYTES;
-  static_assert(LDS <= 160 * 1024, "LDS");
+  using EJ = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC, PF>;
+  using ET = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, S::R>, 1, NW, PREC, PF>;
+  constexpr int PAR = EJ::LDS_BYTES > ET::LDS_BYTES ? EJ::LDS_BYTES : ET::LDS_BYTES;
+  const int lds_bytes = PAR + EJ::PC::bytes(a.depth);
+  if (lds_bytes + (int)sizeof(double) * TV * RMAX + 64 > LDS_MAX)
+    return fail(CROM_ERR_UNSUPPORTED, "network too deep for the step kernel's LDS");
   static_assert(PT * S::R * 8 + PT * TV * 8 <= EJ::ACT_REGION, "staging fits");
   static_assert(PT * S::R * 8 + PT * TV * 8 <= ET::ACT_REGION, "staging fits");
-  static_assert(sizeof(GNState) + 16 + (NW * 64 + S::R * (S::R + 1) / 2 + S::R + TV) * 8 <= LDS,
-                "solve scratch fits");
+  static_assert(sizeof(GNState) + 16 +
+                    (NW * 64 + S::R * (S::R + 1) / 2 + S::R + TV + S::R * S::R + S::R) * 8 <= PAR,
+                "solve scratch fits below the parameter cache");
   static_assert(NW * 64 >= S::R * (S::R + 1) / 2 + S::R + TV, "one thread per reduced entry");
-  auto k = step_kernel<S, NW, PREC>;
-  static int resident = 0;
-  if (!resident) {
-    crom_status s = set_lds(k, LDS);
+  auto k = step_kernel<S, NW, PREC, PF>;
+  static int resident = 0, resident_lds = -1;
+  if (resident_lds != lds_bytes) {
+    crom_status s = set_lds(k, LDS_MAX - (int)sizeof(double) * TV * RMAX - 64);
     if (s != CROM_OK) return s;
     int dev = 0, per_cu = 0, ncu = 0;
     s = hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (s == CROM_OK) s = hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "attr");
     if (s == CROM_OK)
-      s = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, NW * 64, LDS), "occupancy");
+      s = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, NW * 64, lds_bytes), "occupancy");
     if (s != CROM_OK) return s;
     if (per_cu < 1) return fail(CROM_ERR_UNSUPPORTED, "step kernel does not fit on a compute unit");
     resident = per_cu * ncu;
+    resident_lds = lds_bytes;
   }
-  hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(SETUP_THREADS), 0, st, a);
   crom_status s = hip_check(hipGetLastError(), "setup launch");
   if (s != CROM_OK) return s;
-  int64_t g = a.L.nblk_max > a.n_inst ? a.L.nblk_max : a.n_inst;
+  int64_t g = a.L.nblk_max;
   if (g > resident) g = resident;
   if (g < 1) g = 1;
   void* args[] = {&a, &max_rounds};
   return hip_check(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k), dim3((unsigned)g),
-                                              dim3(NW * 64), args, LDS, st),
+                                              dim3(NW * 64), args, lds_bytes, st),
                    "step launch");
 }
 
-template <class S, int NW>
+// Waves per workgroup and weight prefetch per precision, chosen so that the
+// persistent kernel stays clear of register spills: bfloat16 fragments are
+// half the size, so BF16 and BF16_PURE afford eight waves with prefetch.
+template <class S, int NWB, int NWF>
 static crom_status step_prec(int prec, const StepArgs& a, int rounds, hipStream_t st) {
   switch (prec) {
-    case CROM_PREC_FP32: return launch_step<S, NW, PREC_FP32>(a, rounds, st);
-    case CROM_PREC_BF16: return launch_step<S, NW, PREC_BF16>(a, rounds, st);
-    case CROM_PREC_BF16_PURE: return launch_step<S, NW, PREC_BF16_PURE>(a, rounds, st);
-    default: return launch_step<S, NW, PREC_BF16X3>(a, rounds, st);
+    case CROM_PREC_FP32: return launch_step<S, NWF, PREC_FP32, 0>(a, rounds, st);
+    case CROM_PREC_BF16: return launch_step<S, NWB, PREC_BF16, 1>(a, rounds, st);
+    case CROM_PREC_BF16_PURE: return launch_step<S, NWB, PREC_BF16_PURE, 1>(a, rounds, st);
+    default: return launch_step<S, NWF, PREC_BF16X3, 0>(a, rounds, st);
   }
 }
 
@@ -594,7 +812,14 @@ static crom_status step_prec(int prec, const StepArgs& a, int rounds, hipStream_
 
 using namespace crom;
 
+static uint64_t* g_step_trace = nullptr;
+
 extern "C" {
+
+/* Debugging aid: when `buf` (device, 128 uint64) is not NULL, every later
+ * crom_step call writes the wall-clock tick at each phase boundary of its
+ * first and last workgroup into it (slots 0..63 and 64..127). */
+void crom_debug_step_trace(uint64_t* buf) { g_step_trace = buf; }
 
 crom_status crom_step_workspace(const crom_net* net, int32_t n_inst, int64_t total_samples,
                                 size_t* bytes) {
@@ -662,14 +887,16 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
   a.tol = opts->tol_step;
   a.armijo_c = opts->armijo_c;
   a.shrink = opts->ls_shrink;
+  a.trace = g_step_trace;
   // Enough rounds for max_iter accepted steps, each after the longest line
   // search (ceil((ls_max + 1) / TV) rounds) and one re-linearisation.
-  const int worst = opts->max_iter * (1 + (opts->ls_max + TV) / TV) + 1;
-  const int rounds = opts->linearized ? 0 : (opts->max_rounds > 0 ? opts->max_rounds : worst);
+  const int64_t worst = (int64_t)opts->max_iter * (1 + (opts->ls_max + TV) / TV) + 1;
+  int64_t rounds = opts->linearized ? 0 : (opts->max_rounds > 0 ? opts->max_rounds : worst);
+  if (rounds > MAXP) rounds = MAXP;
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (shape_id(net->m, net->r, net->d, net->width)) {
-    case SHAPE_1D: return step_prec<Shape<32, 1, 3, 1>, 2>(net->precision, a, rounds, st);
-    case SHAPE_2D: return step_prec<Shape<128, 2, 8, 1>, 4>(net->precision, a, rounds, st);
+    case SHAPE_1D: return step_prec<Shape<32, 1, 3, 1>, 2, 2>(net->precision, a, (int)rounds, st);
+    case SHAPE_2D: return step_prec<Shape<128, 2, 8, 1>, 8, 4>(net->precision, a, (int)rounds, st);
     default: return fail(CROM_ERR_UNSUPPORTED, "shape");
   }
 }
