@@ -71,6 +71,48 @@ def cpu_baseline(wl, nodes, n_steps: int):
             "latent_steps_per_s": n_steps / dt}
 
 
+def batched_leg(args, crom, torch, dev):
+    """Batched rollout: 512 instances of 2D heat, mu_i ~ U(0.1, 1), sample
+    counts S_i ~ U{200..2000} drawn without replacement from the interior
+    nodes of a 128 x 128 lattice, r = 8, dt = 1e-4; all instances advance
+    together in one step launch.  Gauss-Newton (5 iterations, tol 1e-6) and
+    the linearised inversion are timed separately."""
+    from workloads import Batched2D
+    wb = Batched2D(seed=args.seed)
+    dec = crom.Decoder.from_layers(wb.layers, wb.m, precision=args.prec, device=dev)
+    st = crom.Stepper(dec, wb.offsets, torch.from_numpy(wb.samples).to(dev))
+    nu = torch.from_numpy(wb.mu).to(dev)
+    out = {"workload": f"{wb.n_inst} instances, S_i in [{wb.s_min},{wb.s_max}], total samples "
+                       f"{int(wb.offsets[-1])}", "steps": args.batched_steps}
+    total = int(wb.offsets[-1])
+    for name, opts in (("gn", crom.GNOptions(max_iter=5, tol_step=TOL_STEP)),
+                       ("lls", crom.GNOptions(max_iter=1, linearized=True))):
+        q = [torch.from_numpy(wb.q0.copy()).to(dev), torch.empty(wb.n_inst, R, dtype=torch.float64, device=dev)]
+        for i in range(3):
+            st.step(q[i % 2], nu, wb.dt, opts, q_next=q[(i + 1) % 2])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        flop = 0.0
+        infos = []
+        e0.record()
+        for i in range(args.batched_steps):
+            st.step(q[i % 2], nu, wb.dt, opts, q_next=q[(i + 1) % 2])
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / args.batched_steps
+        inf = st.info()  # iteration counts of the last step stand for all
+        flop = sum(step_flops(int(wb.offsets[k + 1] - wb.offsets[k]), int(inf["iters"][k]),
+                              int(inf["ls_evals"][k])) for k in range(wb.n_inst))
+        if opts.linearized:
+            flop = total * (FLOP_POINT_EVAL)
+        achieved = flop / t / 1e12
+        out[name] = {"ms_per_step": t * 1e3, "instance_steps_per_s": wb.n_inst / t,
+                     "point_evals_per_s": flop / FLOP_POINT_EVAL / t,
+                     "achieved_tflops": achieved, "frac_of_peak": achieved / PEAK[args.prec],
+                     "gn_iters_mean": float(inf["iters"].mean()), "ls_evals_mean": float(inf["ls_evals"].mean())}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +121,7 @@ def main():
     ap.add_argument("--prec", default="bf16", choices=sorted(PEAK))
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--batched-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU: the instances of a batch are independent and the "
@@ -164,6 +207,7 @@ def main():
     torch.cuda.synchronize()
     lls_steps_per_s = args.steps / (time.perf_counter() - t1)
 
+    batched = batched_leg(args, crom, torch, dev) if args.batched_steps > 0 else None
     cpu = cpu_baseline(wl, nodes, args.cpu_steps) if args.cpu_steps > 0 else None
     its = np.array([int(i["iters"]) for i in infos])
     lse = np.array([int(i["ls_evals"]) for i in infos])
@@ -183,6 +227,7 @@ def main():
         "step_ms_avg": t_step.mean() * 1e3, "decode_ms_avg": t_dec.mean() * 1e3,
         "gn_iters_mean": float(its.mean()), "ls_evals_mean": float(lse.mean()),
         "roofline": roof,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -215,6 +215,27 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
 const double* crom_step_targets(const crom_net* net, int32_t n_inst, int64_t total_samples,
                                 const void* ws);
 
+/* ---------------------------------------------------------------------------
+ * Full-order FP64 finite-difference heat solver: the snapshot generator, the
+ * judge of reduced-order rollouts and the fallback for failed steps (Sec.
+ * "Thermodynamics / Full-order Model" and "Image Processing / Full-order
+ * Model": 3-point / 5-point Laplacian, forward Euler, boundary held at 0).
+ *   dim      1 or 2
+ *   shape    host [dim]: nodes per axis (nx) or (nx, ny), boundary included
+ *   n_grid   independent fields, stored one after another:
+ *            u [n_grid][nx] or [n_grid][nx][ny] (index [i_x][i_y]), FP64
+ *   nu       diffusivity: [n_grid] (nu_per_node = 0) or one per node (1)
+ *   dx, dt   node spacing (both axes) and substep
+ *   steps    substeps; each is u <- u + (dt nu) * Lap_h u on interior nodes,
+ *            evaluated in that order without fused multiply-add, and 0 on
+ *            the boundary (input boundary values are ignored)
+ *   u        in/out; scratch: a second buffer of the same size
+ * Stability (nu dt / dx^2 <= 1/2 in 1D, 1/4 in 2D) is the caller's
+ * responsibility. */
+crom_status crom_fd_heat(int32_t dim, const int64_t* shape, int64_t n_grid, const double* nu,
+                         int32_t nu_per_node, double dx, double dt, int64_t steps, double* u,
+                         double* scratch, void* stream);
+
 /* Debugging aid: when buf (device memory, 128 uint64) is not NULL, every
  * later crom_step writes the GPU wall-clock tick (100 MHz) at each phase
  * boundary of its step kernel's first and last workgroup into it: slots

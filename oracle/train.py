@@ -1,0 +1,115 @@
+"""Training of the manifold parameterisation in FP64 (test infrastructure only).
+
+Sec. "Manifold Construction", eq. "loss": the encoder maps a snapshot
+vec f(t) to a latent q = e(f); the decoder reconstructs the snapshot at every
+spatial sample, and both are fitted by minimising the squared reconstruction
+error.  Readings (Sec. "Training Details" leaves them open):
+* loss = mean over the batch's B snapshots and P points of (g(x_i, q_b) - u_b(x_i))^2;
+* encoder q = E2 ELU(E1 u + c1) + c2 (two dense layers, ELU; the paper's
+  convolutional encoder is discretisation-specific and the workload fixes a
+  dense one);
+* Adam (Kingma & Ba) with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 and bias
+  correction.
+
+Gradients are taken by the reverse-mode chain rule written out layer by
+layer: with a_l = ELU(z_l), dL/dz_l = dL/da_l * ELU'(z_l), dL/dW_l = sum over
+points of dL/dz_l a_{l-1}^T, dL/db_l = sum dL/dz_l, dL/da_{l-1} = W_l^T dL/dz_l.
+"""
+from __future__ import annotations
+
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+from .mlp import as_f64, elu, elu_d1
+
+Layer = Tuple[np.ndarray, np.ndarray]
+
+
+def mlp_forward(layers: Sequence[Layer], a0: np.ndarray):
+    """Hidden ELU layers and a linear output; returns (output, [(z_l, a_l)]) with
+    a_0 = the input (rows are samples)."""
+    acts = [(None, a0)]
+    a = a0
+    for W, b in layers[:-1]:
+        z = a @ W.T + b
+        a = elu(z)
+        acts.append((z, a))
+    W, b = layers[-1]
+    return a @ W.T + b, acts
+
+
+def mlp_backward(layers: Sequence[Layer], acts, d_out: np.ndarray):
+    """Reverse mode through mlp_forward: returns ([(dW_l, db_l)], d_input)."""
+    grads: List[Layer] = [None] * len(layers)
+    W, b = layers[-1]
+    a_prev = acts[-1][1]
+    grads[-1] = (d_out.T @ a_prev, d_out.sum(axis=0))
+    d_a = d_out @ W
+    for l in range(len(layers) - 2, -1, -1):
+        z, _ = acts[l + 1]
+        d_z = d_a * elu_d1(z)
+        a_prev = acts[l][1]
+        grads[l] = (d_z.T @ a_prev, d_z.sum(axis=0))
+        d_a = d_z @ layers[l][0]
+    return grads, d_a
+
+
+def encode(enc: Sequence[Layer], u: np.ndarray) -> np.ndarray:
+    """q [B, r] for snapshots u [B, P]."""
+    q, _ = mlp_forward(as_f64(enc), np.asarray(u, dtype=np.float64))
+    return q
+
+
+def loss_and_grads(dec: Sequence[Layer], enc: Sequence[Layer], x: np.ndarray, u: np.ndarray):
+    """Reconstruction loss of eq. "loss" and its gradients.
+
+    dec: decoder layers (input [x; q], m = x.shape[1]); enc: encoder layers
+    (input the P snapshot values); x [P, m] points; u [B, P] snapshots.
+    Returns (loss, dec_grads, enc_grads, q)."""
+    dec, enc = as_f64(dec), as_f64(enc)
+    x = np.asarray(x, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    B, P = u.shape
+    q, enc_acts = mlp_forward(enc, u)
+    r = q.shape[1]
+    # decoder at every (snapshot, point): rows ordered snapshot-major
+    a0 = np.concatenate([np.tile(x, (B, 1)), np.repeat(q, P, axis=0)], axis=1)
+    g, dec_acts = mlp_forward(dec, a0)
+    resid = g[:, 0] - u.reshape(-1) if g.shape[1] == 1 else (g - u.reshape(-1, 1))
+    loss = float(np.mean(resid ** 2))
+    d_g = (2.0 / resid.size) * resid.reshape(g.shape)
+    dec_grads, d_a0 = mlp_backward(dec, dec_acts, d_g)
+    m = x.shape[1]
+    d_q = d_a0[:, m:].reshape(B, P, r).sum(axis=1)
+    enc_grads, _ = mlp_backward(enc, enc_acts, d_q)
+    return loss, dec_grads, enc_grads, q
+
+
+class Adam:
+    """Adam with bias correction over a list of arrays (updated in place)."""
+
+    def __init__(self, params: Sequence[np.ndarray], lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.params = list(params)
+        self.lr, self.b1, self.b2, self.eps = lr, b1, b2, eps
+        self.m = [np.zeros_like(p) for p in self.params]
+        self.v = [np.zeros_like(p) for p in self.params]
+        self.t = 0
+
+    def step(self, grads: Sequence[np.ndarray]):
+        self.t += 1
+        c1 = 1.0 - self.b1 ** self.t
+        c2 = 1.0 - self.b2 ** self.t
+        for p, g, m, v in zip(self.params, grads, self.m, self.v):
+            m *= self.b1
+            m += (1.0 - self.b1) * g
+            v *= self.b2
+            v += (1.0 - self.b2) * g * g
+            p -= self.lr * (m / c1) / (np.sqrt(v / c2) + self.eps)
+
+
+def flatten(layers: Sequence[Layer]) -> List[np.ndarray]:
+    out = []
+    for W, b in layers:
+        out += [W, b]
+    return out

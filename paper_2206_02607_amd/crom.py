@@ -78,8 +78,10 @@ def lib():
         L.crom_step.argtypes = [POINTER(CromNet), POINTER(CromPDE), c_int32, c_void_p, c_int64,
                                 c_void_p, c_void_p, c_void_p, c_void_p, POINTER(CromGNOpts),
                                 c_void_p, c_void_p, c_size_t, c_void_p]
+        L.crom_fd_heat.argtypes = [c_int32, POINTER(c_int64), c_int64, c_void_p, c_int32, c_double,
+                                   c_double, c_int64, c_void_p, c_void_p, c_void_p]
         for name in ("crom_net_pack", "crom_decode", "crom_decode_jac", "crom_decode_jac_x",
-                     "crom_decode_jac_q", "crom_step_workspace", "crom_step"):
+                     "crom_decode_jac_q", "crom_step_workspace", "crom_step", "crom_fd_heat"):
             getattr(L, name).restype = c_int32
         _lib = L
     return _lib
@@ -292,3 +294,22 @@ class Stepper:
         p = lib().crom_step_targets(ctypes.byref(net), self.n_inst, self.total, c_void_p(self.ws_ptr))
         start = off + (p - self.ws_ptr)
         return self.ws[start:start + 8 * n].view(torch.float64).reshape(self.total, self.dec.d)
+
+
+def fd_heat(u, nu, dx: float, dt: float, steps: int, scratch=None):
+    """Full-order FP64 heat solver on device fields u [n_grid, nx] or
+    [n_grid, nx, ny] (in place; returns u).  nu: one value per field or one
+    per node."""
+    torch = _torch()
+    if u.dtype != torch.float64 or not u.is_contiguous():
+        raise CromError("u must be a contiguous float64 tensor")
+    dim = u.dim() - 1
+    shape = (c_int64 * dim)(*u.shape[1:])
+    nu = torch.as_tensor(nu, dtype=torch.float64, device=u.device).contiguous()
+    per_node = int(nu.numel() == u.numel())
+    if not per_node and nu.numel() != u.shape[0]:
+        raise CromError("nu must hold one value per field or per node")
+    scratch = torch.empty_like(u) if scratch is None else scratch
+    _check(lib().crom_fd_heat(dim, shape, u.shape[0], _ptr(nu), per_node, dx, dt, steps, _ptr(u),
+                              _ptr(scratch), _stream()), "crom_fd_heat")
+    return u

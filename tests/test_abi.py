@@ -20,7 +20,7 @@ def _declared():
 def test_header_symbols_exported():
     L = crom.lib()
     names = _declared()
-    assert len(names) >= 11
+    assert len(names) >= 13
     for n in names:
         assert hasattr(L, n), n
 

@@ -1,0 +1,106 @@
+"""Pins for the training oracle (no GPU): central finite differences of the
+loss on sampled parameters (decoder, encoder), an independent torch.float64
+autograd computation of every gradient, and Adam's first step in closed
+form."""
+import numpy as np
+import pytest
+
+from oracle import train
+from workloads import rng, xavier_mlp
+
+
+def _problem(seed=0, B=3, P=11, m=2, r=3, w=8, depth=3, enc_hidden=6):
+    g = rng(seed)
+    dec = [(W.astype(np.float64), b.astype(np.float64)) for W, b in xavier_mlp(g, m, r, 1, w, depth, 0.3)]
+    enc = [(W.astype(np.float64), b.astype(np.float64)) for W, b in xavier_mlp(g, P, 0, r, enc_hidden, 1, 0.3)]
+    x = g.uniform(0, 1, size=(P, m))
+    u = g.uniform(-1, 1, size=(B, P))
+    return dec, enc, x, u
+
+
+def test_gradients_vs_central_fd():
+    dec, enc, x, u = _problem()
+    loss, dg, eg, _ = train.loss_and_grads(dec, enc, x, u)
+    g = rng(5)
+    h = 1e-6
+    for layers, grads in ((dec, dg), (enc, eg)):
+        for li in range(len(layers)):
+            for which in (0, 1):
+                arr = layers[li][which]
+                for _ in range(3):
+                    idx = tuple(g.integers(0, s) for s in arr.shape)
+                    old = arr[idx]
+                    arr[idx] = old + h
+                    lp = train.loss_and_grads(dec, enc, x, u)[0]
+                    arr[idx] = old - h
+                    lm = train.loss_and_grads(dec, enc, x, u)[0]
+                    arr[idx] = old
+                    fd = (lp - lm) / (2 * h)
+                    assert abs(grads[li][which][idx] - fd) <= 1e-6 * max(1.0, abs(fd)), (li, which, idx)
+
+
+def test_gradients_vs_autograd_float64():
+    torch = pytest.importorskip("torch")
+    dec, enc, x, u = _problem(seed=1, B=2, P=7)
+    loss, dg, eg, q = train.loss_and_grads(dec, enc, x, u)
+    T = lambda a: torch.tensor(a, dtype=torch.float64, requires_grad=True)  # noqa: E731
+    tdec = [(T(W), T(b)) for W, b in dec]
+    tenc = [(T(W), T(b)) for W, b in enc]
+
+    def mlp(layers, a):
+        for W, b in layers[:-1]:
+            a = torch.nn.functional.elu(a @ W.T + b)
+        return a @ layers[-1][0].T + layers[-1][1]
+
+    tu = torch.tensor(u)
+    tq = mlp(tenc, tu)
+    B, P = u.shape
+    a0 = torch.cat([torch.tensor(x).repeat(B, 1), tq.repeat_interleave(P, dim=0)], dim=1)
+    tg = mlp(tdec, a0)
+    tl = ((tg[:, 0] - tu.reshape(-1)) ** 2).mean()
+    tl.backward()
+    assert abs(tl.item() - loss) <= 1e-14 * max(1.0, loss)
+    np.testing.assert_allclose(tq.detach().numpy(), q, rtol=1e-13, atol=1e-15)
+    for (W, b), (gW, gb) in zip(tdec + tenc, dg + eg):
+        np.testing.assert_allclose(W.grad.numpy(), gW, rtol=1e-11, atol=1e-14)
+        np.testing.assert_allclose(b.grad.numpy(), gb, rtol=1e-11, atol=1e-14)
+
+
+def test_adam_first_step_closed_form():
+    # After one step from m = v = 0: delta = -lr * g / (|g| + eps) elementwise.
+    p = np.array([1.0, -2.0, 0.5, 0.0])
+    g = np.array([0.3, -1e-3, 2.0, 0.0])
+    opt = train.Adam([p], lr=1e-3)
+    opt.step([g])
+    expect = np.array([1.0, -2.0, 0.5, 0.0]) - 1e-3 * g / (np.abs(g) + 1e-8)
+    np.testing.assert_allclose(p, expect, rtol=1e-12, atol=1e-15)
+
+
+def test_adam_second_step_by_hand():
+    p = np.array([0.2])
+    opt = train.Adam([p], lr=0.1)
+    opt.step([np.array([1.0])])
+    opt.step([np.array([-3.0])])
+    m1, v1 = 0.1 * 1.0, 0.001 * 1.0
+    m2, v2 = 0.9 * m1 + 0.1 * -3.0, 0.999 * v1 + 0.001 * 9.0
+    p1 = 0.2 - 0.1 * (m1 / 0.1) / (np.sqrt(v1 / 0.001) + 1e-8)
+    p2 = p1 - 0.1 * (m2 / (1 - 0.81)) / (np.sqrt(v2 / (1 - 0.999 ** 2)) + 1e-8)
+    np.testing.assert_allclose(p, [p2], rtol=1e-13)
+
+
+def test_training_reduces_loss():
+    # Fitting a family of sine snapshots: a few hundred Adam steps lower the
+    # reconstruction loss (the optimisation itself, not a parity claim).
+    g = rng(7)
+    P, m, r = 24, 1, 2
+    x = np.linspace(0, 1, P)[:, None]
+    amps = g.uniform(-1, 1, size=(8, 2))
+    u = amps[:, :1] * np.sin(np.pi * x[:, 0]) + amps[:, 1:] * np.sin(2 * np.pi * x[:, 0])
+    dec = [(W.astype(np.float64), b.astype(np.float64)) for W, b in xavier_mlp(g, m, r, 1, 16, 3)]
+    enc = [(W.astype(np.float64), b.astype(np.float64)) for W, b in xavier_mlp(g, P, 0, r, 16, 1)]
+    opt = train.Adam(train.flatten(dec) + train.flatten(enc), lr=3e-3)
+    l0 = train.loss_and_grads(dec, enc, x, u)[0]
+    for _ in range(300):
+        loss, dg, eg, _ = train.loss_and_grads(dec, enc, x, u)
+        opt.step(train.flatten(dg) + train.flatten(eg))
+    assert loss < 0.2 * l0
