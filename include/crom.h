@@ -236,6 +236,78 @@ crom_status crom_fd_heat(int32_t dim, const int64_t* shape, int64_t n_grid, cons
                          int32_t nu_per_node, double dx, double dt, int64_t steps, double* u,
                          double* scratch, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Training of the manifold parameterisation (Sec. "Manifold Construction",
+ * eq. "loss"; Sec. "Training Details").  A batch holds B snapshots u_b of P
+ * points with d values each, at the shared points x [P][m].  The encoder
+ * maps a snapshot to its latent, q_b = E2 ELU(E1 u_b + c1) + c2, the decoder
+ * is evaluated at every (snapshot, point) pair, and the loss is
+ *   L = mean over b, p, o of (g(x_p, q_b)_o - u_b(x_p)_o)^2.
+ * Gradients are the exact reverse-mode derivatives of L (written out layer
+ * by layer, no tape).  In CROM_PREC_FP32 every product is FP32; in the
+ * bfloat16 modes the hidden-layer products, the encoder's first layer and
+ * the stored activations use bfloat16 operands with FP32 accumulation, and
+ * the first and output layers, the loss and every sum over points are
+ * FP32/FP64.  Sums run in a fixed order: results are deterministic.
+ * The decoder must have one of the compiled shapes; the packed weights are
+ * not used (crom_train_step refreshes them when given a buffer).
+ * ------------------------------------------------------------------------- */
+
+/* Encoder description: params FP32, natural layout
+ *   E1 [hidden][n_in], c1 [hidden], E2 [r][hidden], c2 [r],
+ * with n_in = P * d (a snapshot [P][d], point-major) and r = the net's r. */
+typedef struct {
+  int32_t n_in, hidden, r, _pad;
+  float* params;
+} crom_encoder;
+
+/* Number of FP32 values in an encoder's params (0 on invalid sizes). */
+size_t crom_encoder_param_count(int32_t n_in, int32_t hidden, int32_t r);
+
+/* Workspace bytes for crom_train_grads / crom_train_step with B snapshots
+ * (host out-parameter). */
+crom_status crom_train_workspace(const crom_net* net, const crom_encoder* enc, int32_t B,
+                                 size_t* bytes);
+
+/* Loss and gradients for one batch.
+ *   u         [B][P][d] FP32 snapshots;  x [P][m] FP32 points
+ *   grad_dec  [crom_net_param_count] out, the decoder's natural layout
+ *   grad_enc  [crom_encoder_param_count] out, the encoder's layout
+ *   loss      [1] FP32 out;  q_out NULL or [B][r] FP32 out (the latents)
+ *   ws        workspace of crom_train_workspace bytes */
+crom_status crom_train_grads(const crom_net* net, const crom_encoder* enc, const float* u,
+                             const float* x, int32_t B, float* grad_dec, float* grad_enc,
+                             float* loss, float* q_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Adam (Kingma & Ba) with bias correction on n FP32 values, step t >= 1:
+ *   m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;
+ *   p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * m and v start at 0 (caller-owned, n values each). */
+crom_status crom_adam_step(float* params, const float* grad, float* m, float* v, int64_t n,
+                           int64_t t, float lr, float beta1, float beta2, float eps,
+                           void* stream);
+
+/* One training step: crom_train_grads, then Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8) on the FP32 master parameters of the decoder (net->params, which
+ * this call updates in place) and of the encoder, then, when `packed` is not
+ * NULL, crom_net_pack into it.  dec_grad/enc_grad are caller buffers of the
+ * gradient sizes; dec_m, dec_v, enc_m, enc_v are the Adam moments. */
+crom_status crom_train_step(const crom_net* net, void* packed, float* dec_grad, float* dec_m,
+                            float* dec_v, const crom_encoder* enc, float* enc_grad, float* enc_m,
+                            float* enc_v, int64_t t, const float* u, const float* x, int32_t B,
+                            float lr, float* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of the decoder (the backward of crom_decode over
+ * B latents): with G[b][p][o] = g(x_p, q_b)_o and a cotangent dg [B][P][d],
+ *   grad_params = sum dg . dG/dparams   (natural layout, overwritten)
+ *   grad_q [B][r] = sum over p, o of dg . dG/dq_b.
+ * q [B][r] FP32.  The forward activations are recomputed, in the net's
+ * precision, into the workspace (crom_decode_vjp_workspace bytes). */
+crom_status crom_decode_vjp_workspace(const crom_net* net, int32_t B, int64_t P, size_t* bytes);
+crom_status crom_decode_vjp(const crom_net* net, const float* x, int64_t P, const float* q,
+                            int32_t B, const float* dg, float* grad_params, float* grad_q,
+                            void* ws, size_t ws_bytes, void* stream);
+
 /* Debugging aid: when buf (device memory, 128 uint64) is not NULL, every
  * later crom_step writes the GPU wall-clock tick (100 MHz) at each phase
  * boundary of its step kernel's first and last workgroup into it: slots

@@ -4,7 +4,9 @@ Sec. "Manifold Construction", eq. "loss": the encoder maps a snapshot
 vec f(t) to a latent q = e(f); the decoder reconstructs the snapshot at every
 spatial sample, and both are fitted by minimising the squared reconstruction
 error.  Readings (Sec. "Training Details" leaves them open):
-* loss = mean over the batch's B snapshots and P points of (g(x_i, q_b) - u_b(x_i))^2;
+* loss = mean over the batch's B snapshots, P points and d output values of
+  (g(x_i, q_b) - u_b(x_i))^2; a snapshot of a d-valued field is the vector
+  of its P points' values, point-major ([P][d] flattened);
 * encoder q = E2 ELU(E1 u + c1) + c2 (two dense layers, ELU; the paper's
   convolutional encoder is discretisation-specific and the workload fixes a
   dense one);
@@ -65,20 +67,21 @@ def loss_and_grads(dec: Sequence[Layer], enc: Sequence[Layer], x: np.ndarray, u:
     """Reconstruction loss of eq. "loss" and its gradients.
 
     dec: decoder layers (input [x; q], m = x.shape[1]); enc: encoder layers
-    (input the P snapshot values); x [P, m] points; u [B, P] snapshots.
+    (input the P * d snapshot values); x [P, m] points; u [B, P * d]
+    snapshots, point-major.
     Returns (loss, dec_grads, enc_grads, q)."""
     dec, enc = as_f64(dec), as_f64(enc)
     x = np.asarray(x, dtype=np.float64)
     u = np.asarray(u, dtype=np.float64)
-    B, P = u.shape
+    B, P = u.shape[0], x.shape[0]
     q, enc_acts = mlp_forward(enc, u)
     r = q.shape[1]
     # decoder at every (snapshot, point): rows ordered snapshot-major
     a0 = np.concatenate([np.tile(x, (B, 1)), np.repeat(q, P, axis=0)], axis=1)
     g, dec_acts = mlp_forward(dec, a0)
-    resid = g[:, 0] - u.reshape(-1) if g.shape[1] == 1 else (g - u.reshape(-1, 1))
+    resid = g - u.reshape(B * P, g.shape[1])
     loss = float(np.mean(resid ** 2))
-    d_g = (2.0 / resid.size) * resid.reshape(g.shape)
+    d_g = (2.0 / resid.size) * resid
     dec_grads, d_a0 = mlp_backward(dec, dec_acts, d_g)
     m = x.shape[1]
     d_q = d_a0[:, m:].reshape(B, P, r).sum(axis=1)

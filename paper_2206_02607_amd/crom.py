@@ -41,6 +41,11 @@ class CromGNOpts(Structure):
                 ("ls_shrink", c_double)]
 
 
+class CromEncoder(Structure):
+    _fields_ = [("n_in", c_int32), ("hidden", c_int32), ("r", c_int32), ("_pad", c_int32),
+                ("params", c_void_p)]
+
+
 INFO_DTYPE = np.dtype([("flags", "<i4"), ("iters", "<i4"), ("ls_evals", "<i4"), ("rounds", "<i4"),
                        ("obj_first", "<f8"), ("obj_last", "<f8")])
 
@@ -80,8 +85,27 @@ def lib():
                                 c_void_p, c_void_p, c_size_t, c_void_p]
         L.crom_fd_heat.argtypes = [c_int32, POINTER(c_int64), c_int64, c_void_p, c_int32, c_double,
                                    c_double, c_int64, c_void_p, c_void_p, c_void_p]
+        L.crom_encoder_param_count.restype = c_size_t
+        L.crom_encoder_param_count.argtypes = [c_int32] * 3
+        L.crom_train_workspace.argtypes = [POINTER(CromNet), POINTER(CromEncoder), c_int32,
+                                           POINTER(c_size_t)]
+        L.crom_train_grads.argtypes = [POINTER(CromNet), POINTER(CromEncoder), c_void_p, c_void_p,
+                                       c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       c_size_t, c_void_p]
+        L.crom_adam_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int64,
+                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     c_void_p]
+        L.crom_train_step.argtypes = [POINTER(CromNet), c_void_p, c_void_p, c_void_p, c_void_p,
+                                      POINTER(CromEncoder), c_void_p, c_void_p, c_void_p, c_int64,
+                                      c_void_p, c_void_p, c_int32, ctypes.c_float, c_void_p,
+                                      c_void_p, c_size_t, c_void_p]
+        L.crom_decode_vjp_workspace.argtypes = [POINTER(CromNet), c_int32, c_int64, POINTER(c_size_t)]
+        L.crom_decode_vjp.argtypes = [POINTER(CromNet), c_void_p, c_int64, c_void_p, c_int32,
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
         for name in ("crom_net_pack", "crom_decode", "crom_decode_jac", "crom_decode_jac_x",
-                     "crom_decode_jac_q", "crom_step_workspace", "crom_step", "crom_fd_heat"):
+                     "crom_decode_jac_q", "crom_step_workspace", "crom_step", "crom_fd_heat",
+                     "crom_train_workspace", "crom_train_grads", "crom_adam_step", "crom_train_step",
+                     "crom_decode_vjp_workspace", "crom_decode_vjp"):
             getattr(L, name).restype = c_int32
         _lib = L
     return _lib
@@ -221,6 +245,113 @@ class Decoder:
         _check(lib().crom_decode_jac_q(ctypes.byref(net), _ptr(x), P, _ptr(q), _ptr(g), _ptr(gq),
                                        _stream()), "crom_decode_jac_q")
         return g, gq
+
+
+def decode_vjp(dec: "Decoder", x, q, dg):
+    """Backward of the decoder over B latents: q [B, r] FP32, dg [B, P, d]
+    cotangent of g(x_p, q_b).  Returns (grad_params [n_params], grad_q [B, r])."""
+    torch = _torch()
+    x = x.to(dtype=torch.float32).contiguous()
+    q = q.to(device=x.device, dtype=torch.float32).contiguous()
+    dg = dg.to(device=x.device, dtype=torch.float32).contiguous()
+    B, P = q.shape[0], x.shape[0]
+    if q.dim() != 2 or q.shape[1] != dec.r or dg.numel() != B * P * dec.d:
+        raise CromError("q must be [B, r] and dg [B, P, d]")
+    net = dec._net(packed=False)
+    nbytes = c_size_t(0)
+    _check(lib().crom_decode_vjp_workspace(ctypes.byref(net), B, P, ctypes.byref(nbytes)),
+           "crom_decode_vjp_workspace")
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=x.device)
+    gp = torch.empty_like(dec.params)
+    gq = torch.empty(B, dec.r, dtype=torch.float32, device=x.device)
+    _check(lib().crom_decode_vjp(ctypes.byref(net), _ptr(x), P, _ptr(q), B, _ptr(dg), _ptr(gp),
+                                 _ptr(gq), _ptr(ws), nbytes.value, _stream()), "crom_decode_vjp")
+    return gp, gq
+
+
+def encoder_param_count(n_in: int, hidden: int, r: int) -> int:
+    return int(lib().crom_encoder_param_count(n_in, hidden, r))
+
+
+class Trainer:
+    """Encoder + decoder training on the GPU (crom_train_grads / crom_train_step).
+
+    dec: the Decoder whose FP32 params are the master copy (updated in place,
+    packed weights refreshed after every step); enc_params: the encoder's FP32
+    parameters [E1, c1, E2, c2] (updated in place); x [P, m] the snapshot
+    points; B the batch size."""
+
+    def __init__(self, dec: "Decoder", enc_params, hidden: int, x, B: int):
+        torch = _torch()
+        self.dec, self.hidden, self.B = dec, hidden, B
+        self.x = x.to(dtype=torch.float32).contiguous()
+        self.P = self.x.shape[0]
+        self.n_in = self.P * dec.d
+        ne = encoder_param_count(self.n_in, hidden, dec.r)
+        if isinstance(enc_params, np.ndarray):
+            enc_params = torch.from_numpy(np.ascontiguousarray(enc_params, dtype=np.float32))
+        self.enc_params = enc_params.to(device=self.x.device, dtype=torch.float32).contiguous()
+        if self.enc_params.numel() != ne:
+            raise CromError(f"expected {ne} encoder parameters, got {self.enc_params.numel()}")
+        dev = self.x.device
+        nbytes = c_size_t(0)
+        _check(lib().crom_train_workspace(ctypes.byref(dec._net(packed=False)), ctypes.byref(self._enc()),
+                                          B, ctypes.byref(nbytes)), "crom_train_workspace")
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        nd = dec.params.numel()
+        self.grad_dec = torch.zeros(nd, dtype=torch.float32, device=dev)
+        self.grad_enc = torch.zeros(ne, dtype=torch.float32, device=dev)
+        self.m_dec = torch.zeros(nd, dtype=torch.float32, device=dev)
+        self.v_dec = torch.zeros(nd, dtype=torch.float32, device=dev)
+        self.m_enc = torch.zeros(ne, dtype=torch.float32, device=dev)
+        self.v_enc = torch.zeros(ne, dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.q = torch.zeros(B, dec.r, dtype=torch.float32, device=dev)
+        self.t = 0
+
+    def _enc(self) -> CromEncoder:
+        return CromEncoder(self.n_in, self.hidden, self.dec.r, 0, self.enc_params.data_ptr())
+
+    def _u(self, u):
+        torch = _torch()
+        u = u.to(device=self.x.device, dtype=torch.float32).contiguous()
+        if u.numel() != self.B * self.n_in:
+            raise CromError(f"u must hold B x P x d = {self.B * self.n_in} values")
+        return u
+
+    def grads(self, u):
+        """Loss and gradients of one batch u [B, P(, d)] without an update.
+        Returns (loss [1], grad_dec, grad_enc, q [B, r]) (views of internal buffers)."""
+        u = self._u(u)
+        net, enc = self.dec._net(packed=False), self._enc()
+        _check(lib().crom_train_grads(ctypes.byref(net), ctypes.byref(enc), _ptr(u), _ptr(self.x),
+                                      self.B, _ptr(self.grad_dec), _ptr(self.grad_enc), _ptr(self.loss),
+                                      _ptr(self.q), _ptr(self.ws), self.ws.numel(), _stream()),
+               "crom_train_grads")
+        return self.loss, self.grad_dec, self.grad_enc, self.q
+
+    def step(self, u, lr: float = 1e-3):
+        """One Adam step on batch u; returns the batch loss (device tensor [1])
+        measured before the update."""
+        u = self._u(u)
+        self.t += 1
+        net, enc = self.dec._net(packed=False), self._enc()
+        _check(lib().crom_train_step(ctypes.byref(net), _ptr(self.dec.packed), _ptr(self.grad_dec),
+                                     _ptr(self.m_dec), _ptr(self.v_dec), ctypes.byref(enc),
+                                     _ptr(self.grad_enc), _ptr(self.m_enc), _ptr(self.v_enc), self.t,
+                                     _ptr(u), _ptr(self.x), self.B, lr, _ptr(self.loss), _ptr(self.ws),
+                                     self.ws.numel(), _stream()), "crom_train_step")
+        return self.loss
+
+    def encode(self, u):
+        """Latents of the snapshots u [B, P(, d)] (runs the batch's forward and backward)."""
+        return self.grads(u)[3].clone()
+
+
+def adam_step(params, grad, m, v, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update of FP32 device tensors."""
+    _check(lib().crom_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), t, lr,
+                                beta1, beta2, eps, _stream()), "crom_adam_step")
 
 
 @dataclass

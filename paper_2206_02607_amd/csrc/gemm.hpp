@@ -1,0 +1,154 @@
+// LDS-tiled matrix-core GEMM with fused epilogues, the building block of the
+// training kernels:  C[M][N] = op(A)[M][K] * op(B)[K][N]  (+ epilogue)
+//   op(A)(m, k) = TA ? A[k * lda + m] : A[m * lda + k]
+//   op(B)(k, n) = TB ? B[n * ldb + k] : B[k * ldb + n]
+// T = __bf16 (v_mfma_f32_16x16x32_bf16) or float (v_mfma_f32_16x16x4_f32);
+// accumulation is FP32.  Block tile 64 x 64, four waves of 32 x 32.  Split-K
+// writes FP32 partial tiles that a second kernel sums in a fixed order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace crom {
+
+enum { EPI_NONE = 0, EPI_BIAS_ELU = 1, EPI_DELU = 2, EPI_BIAS = 3 };
+
+struct GemmArgs {
+  int M, N, K;
+  const void* A;
+  int64_t lda;
+  const void* B;
+  int64_t ldb;
+  float* C;         // FP32 result (may be NULL)
+  int64_t ldc;
+  __bf16* Cb;       // bfloat16 copy of the result (may be NULL)
+  int64_t ldcb;
+  const float* bias;  // EPI_BIAS_ELU / EPI_BIAS: + bias[n]
+  const void* gate;   // EPI_DELU: result *= ELU'(z) read from the stored a = ELU(z)
+  int64_t ldg;
+  int kchunk;         // split-K: K range of blockIdx.z (multiple of the K tile)
+  float* part;        // split-K: partial tiles [gridDim.z][M][N]
+  int accumulate;     // C += result (FP32 output only)
+};
+
+template <class T>
+__device__ __forceinline__ float to_f(T v) { return (float)v; }
+
+// ELU'(z) from a = ELU(z): 1 where a > 0, a + 1 = e^z otherwise.
+__device__ __forceinline__ float elu_d1_from_a(float a) { return a > 0.0f ? 1.0f : a + 1.0f; }
+
+template <class T, bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+  typedef __bf16 bf16x8_ __attribute__((ext_vector_type(8)));
+  typedef float f32x4_ __attribute__((ext_vector_type(4)));
+  constexpr bool BF = sizeof(T) == 2;
+  constexpr int BK = BF ? 32 : 16;
+  constexpr int LDK = BK + (BF ? 8 : 4);  // padded row (k contiguous) against bank conflicts
+  __shared__ __align__(16) T As[64 * LDK];
+  __shared__ __align__(16) T Bs[64 * LDK];
+  const T* A = static_cast<const T*>(g.A);
+  const T* B = static_cast<const T*>(g.B);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int kbeg = blockIdx.z * g.kchunk;
+  const int kend = min(g.K, kbeg + g.kchunk);
+  f32x4_ acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_{0.0f, 0.0f, 0.0f, 0.0f};
+
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    // stage the tiles, zero outside the matrix
+    for (int idx = tid; idx < 64 * BK; idx += 256) {
+      int r, k;
+      if (TA) { k = idx / 64; r = idx % 64; } else { r = idx / BK; k = idx % BK; }
+      const int gm = m0 + r, gk = k0 + k;
+      T v = T(0.0f);
+      if (gm < g.M && gk < kend) v = TA ? A[(int64_t)gk * g.lda + gm] : A[(int64_t)gm * g.lda + gk];
+      As[r * LDK + k] = v;
+    }
+    for (int idx = tid; idx < 64 * BK; idx += 256) {
+      int c, k;
+      if (TB) { c = idx / BK; k = idx % BK; } else { k = idx / 64; c = idx % 64; }
+      const int gn = n0 + c, gk = k0 + k;
+      T v = T(0.0f);
+      if (gn < g.N && gk < kend) v = TB ? B[(int64_t)gn * g.ldb + gk] : B[(int64_t)gk * g.ldb + gn];
+      Bs[c * LDK + k] = v;
+    }
+    __syncthreads();
+    if constexpr (BF) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const bf16x8_ af = *reinterpret_cast<const bf16x8_*>(&As[(wr + i * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const bf16x8_ bfr = *reinterpret_cast<const bf16x8_*>(&Bs[(wc + j * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, acc[i][j], 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 4) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const float af = to_f(As[(wr + i * 16 + (lane & 15)) * LDK + ks + (lane >> 4)]);
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const float bfr = to_f(Bs[(wc + j * 16 + (lane & 15)) * LDK + ks + (lane >> 4)]);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bfr, acc[i][j], 0, 0, 0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // epilogue: lane holds column (lane & 15), rows 4 * (lane >> 4) + v
+  const T* gate = static_cast<const T*>(g.gate);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wr + i * 16 + 4 * (lane >> 4) + v;
+        const int n = n0 + wc + j * 16 + (lane & 15);
+        if (m >= g.M || n >= g.N) continue;
+        float x = acc[i][j][v];
+        if (g.part) {
+          g.part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = x;
+          continue;
+        }
+        if constexpr (EPI == EPI_BIAS_ELU) {
+          x += g.bias[n];
+          x = x > 0.0f ? x : __expf(x) - 1.0f;
+        } else if constexpr (EPI == EPI_BIAS) {
+          x += g.bias[n];
+        } else if constexpr (EPI == EPI_DELU) {
+          x *= elu_d1_from_a(to_f(gate[(int64_t)m * g.ldg + n]));
+        }
+        if (g.C) {
+          float* c = &g.C[(int64_t)m * g.ldc + n];
+          *c = g.accumulate ? *c + x : x;
+        }
+        if (g.Cb) g.Cb[(int64_t)m * g.ldcb + n] = (__bf16)x;
+      }
+}
+
+// Sum of split-K partials in split order, then the epilogue-free store.
+__global__ void splitk_reduce_kernel(const float* __restrict__ part, int splits, int M, int N,
+                                     float* C, int64_t ldc, int accumulate) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)M * N;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + e];
+    const int m = (int)(e / N), n = (int)(e % N);
+    float* c = &C[(int64_t)m * ldc + n];
+    *c = accumulate ? *c + s : s;
+  }
+}
+
+}  // namespace crom

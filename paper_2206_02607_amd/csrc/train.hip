@@ -1,0 +1,629 @@
+// Training of the manifold parameterisation (Sec. "Manifold Construction",
+// eq. "loss"; Sec. "Training Details"): encoder q_b = E2 ELU(E1 u_b + c1) + c2,
+// decoder g(x_p, q_b) at every point of every snapshot of the batch, loss =
+// mean (g - u)^2, gradients by the reverse-mode chain rule written out layer
+// by layer, and Adam with bias correction on FP32 master parameters.
+//
+// The decoder's rows are (snapshot, point) pairs, snapshot-major: row
+// b * P + p.  Layer activations a_l = ELU(z_l) are kept for the backward
+// pass (ELU'(z) is recovered from a: 1 where a > 0, a + 1 otherwise).  The
+// matrix products run on the matrix cores through gemm.hpp, in bfloat16 with
+// FP32 accumulation (FP32 when the net's precision is FP32); the first layer
+// (K = m + r), the output layer and every reduction over rows are plain
+// FP32 kernels with a fixed summation order.
+#include "common.hpp"
+#include "gemm.hpp"
+
+namespace crom {
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void convert_kernel(const float* __restrict__ a, T* __restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (T)a[i];
+}
+
+// c[b][u] = b1[u] + sum_k W1[u][m + k] q[b][k]  (FP64 accumulation)
+__global__ void fold_kernel(const float* __restrict__ W1, const float* __restrict__ b1, const float* __restrict__ q,
+                            int B, int W, int m, int r, float* __restrict__ c) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B * W; i += gridDim.x * blockDim.x) {
+    const int b = i / W, u = i % W;
+    double s = b1[u];
+    for (int k = 0; k < r; ++k) s += (double)W1[u * (m + r) + m + k] * q[b * r + k];
+    c[i] = (float)s;
+  }
+}
+
+// a1[row][u] = ELU(sum_i W1[u][i] x[p][i] + c[b][u]),  row = b * P + p
+template <class T>
+__global__ void layer1_kernel(const float* __restrict__ W1, const float* __restrict__ c, const float* __restrict__ x,
+                              int64_t P, int64_t rows, int W, int m, int r, T* __restrict__ a1) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows * W; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = i / W;
+    const int u = (int)(i % W);
+    const int64_t b = row / P, p = row - b * P;
+    float z = c[b * W + u];
+    for (int k = 0; k < m; ++k) z += W1[u * (m + r) + k] * x[p * m + k];
+    a1[i] = (T)(z > 0.0f ? z : __expf(z) - 1.0f);
+  }
+}
+
+// g[row][o] = sum_u Wout[o][u] a[row][u] + bout[o]: one wave per row
+template <class T>
+__global__ void output_kernel(const T* __restrict__ a, const float* __restrict__ Wout, const float* __restrict__ bout,
+                              int64_t rows, int W, int D, float* __restrict__ g) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 64; row < rows;
+       row += ((int64_t)gridDim.x * blockDim.x) / 64) {
+    for (int o = 0; o < D; ++o) {
+      float s = 0.0f;
+      for (int u = lane; u < W; u += 64) s += Wout[o * W + u] * (float)a[row * W + u];
+      for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+      if (lane == 0) g[row * D + o] = s + bout[o];
+    }
+  }
+}
+
+// dg = 2 (g - u) / n and per-block partial sums of (g - u)^2
+__global__ void mse_kernel(const float* __restrict__ g, const float* __restrict__ u, int64_t n,
+                           float* __restrict__ dg, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float e = g[i] - u[i];
+    dg[i] = 2.0f * e / (float)n;
+    s += (double)e * e;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void mse_final_kernel(const double* __restrict__ part, int nb, int64_t n, float* loss) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += part[i];
+    *loss = (float)(s / (double)n);
+  }
+}
+
+// dz[row][u] = (sum_o dg[row][o] Wout[o][u]) * ELU'(a[row][u])
+template <class T>
+__global__ void dz_last_kernel(const float* __restrict__ dg, const float* __restrict__ Wout, const T* __restrict__ a,
+                               int64_t rows, int W, int D, T* __restrict__ dz) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows * W; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = i / W;
+    const int u = (int)(i % W);
+    float s = 0.0f;
+    for (int o = 0; o < D; ++o) s += dg[row * D + o] * Wout[o * W + u];
+    dz[i] = (T)(s * elu_d1_from_a((float)a[i]));
+  }
+}
+
+// Weighted column sums over row segments, in two fixed-order passes.
+//   out[seg][k][col] = sum over rows of the segment of w_k(row) X[row][col]
+// with w_0 = 1 and w_k = wt[row % wmod][k - 1] (k = 1..nw-1, stride wstride).
+// Pass 1: block (col tile, segment, chunk) sums its rows; pass 2 adds chunks.
+template <class T>
+__global__ void colsum_kernel(const T* __restrict__ X, int64_t ldx, int cols, int64_t seg_rows, int chunks,
+                              const float* __restrict__ wt, int64_t wmod, int wstride, int nw,
+                              double* __restrict__ part) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  const int seg = blockIdx.y, ch = blockIdx.z;
+  const int64_t per = (seg_rows + chunks - 1) / chunks;
+  const int64_t r0 = ch * per, r1 = min(seg_rows, r0 + per);
+  if (col >= cols) return;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t r = r0; r < r1; ++r) {
+    const int64_t row = seg * seg_rows + r;
+    const double v = (double)(float)X[row * ldx + col];
+    s[0] += v;
+    for (int k = 1; k < nw; ++k) s[k] += v * (double)wt[(row % wmod) * wstride + (k - 1)];
+  }
+  for (int k = 0; k < nw; ++k) part[(((int64_t)seg * chunks + ch) * nw + k) * cols + col] = s[k];
+}
+
+__global__ void colsum_final_kernel(const double* __restrict__ part, int segs, int chunks, int nw, int cols,
+                                    double* __restrict__ out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < segs * nw * cols; i += gridDim.x * blockDim.x) {
+    const int seg = i / (nw * cols), rem = i % (nw * cols);
+    double s = 0.0;
+    for (int ch = 0; ch < chunks; ++ch) s += part[((int64_t)seg * chunks + ch) * nw * cols + rem];
+    out[i] = s;
+  }
+}
+
+// First-layer gradients from the per-snapshot sums S[b][0][u] = sum_p dz1,
+// S[b][1 + i][u] = sum_p dz1 x_p[i] (i < m):
+//   dW1[u][i] = sum_b S[b][1+i][u]; dW1[u][m+k] = sum_b S[b][0][u] q[b][k];
+//   db1[u] = sum_b S[b][0][u];  dq[b][k] = sum_u S[b][0][u] W1[u][m+k]
+__global__ void layer1_grad_kernel(const double* __restrict__ S, const float* __restrict__ q, const float* __restrict__ W1,
+                                   int B, int W, int m, int r, float* __restrict__ dW1, float* __restrict__ db1,
+                                   float* __restrict__ dq) {
+  const int nw = 1 + m;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < W * (m + r) + W + B * r; i += gridDim.x * blockDim.x) {
+    if (i < W * (m + r)) {
+      const int u = i / (m + r), k = i % (m + r);
+      double s = 0.0;
+      for (int b = 0; b < B; ++b)
+        s += k < m ? S[((int64_t)b * nw + 1 + k) * W + u] : S[((int64_t)b * nw) * W + u] * (double)q[b * r + (k - m)];
+      dW1[i] = (float)s;
+    } else if (i < W * (m + r) + W) {
+      const int u = i - W * (m + r);
+      double s = 0.0;
+      for (int b = 0; b < B; ++b) s += S[((int64_t)b * nw) * W + u];
+      db1[u] = (float)s;
+    } else {
+      const int j = i - W * (m + r) - W, b = j / r, k = j % r;
+      double s = 0.0;
+      for (int u = 0; u < W; ++u) s += S[((int64_t)b * nw) * W + u] * (double)W1[u * (m + r) + m + k];
+      dq[j] = (float)s;
+    }
+  }
+}
+
+__global__ void d2f_kernel(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
+// Adam with bias correction (Kingma & Ba), FP32 state.
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                            float c1, float c2) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side plumbing
+// ---------------------------------------------------------------------------
+static unsigned grid_for(int64_t n, int threads = 256) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > 16384) b = 16384;
+  return (unsigned)b;
+}
+
+template <class T, bool TA, bool TB, int EPI>
+static crom_status gemm(GemmArgs g, hipStream_t st) {
+  constexpr int BK = sizeof(T) == 2 ? 32 : 16;
+  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, 1);
+  if (g.part) {
+    // split K so that there are a few hundred blocks
+    const int64_t tiles = (int64_t)grid.x * grid.y;
+    int splits = (int)((512 + tiles - 1) / tiles);
+    const int maxs = (g.K + BK - 1) / BK;
+    if (splits > maxs) splits = maxs;
+    if (splits > 64) splits = 64;
+    if (splits < 1) splits = 1;
+    int kc = (g.K + splits - 1) / splits;
+    kc = (kc + BK - 1) / BK * BK;
+    splits = (g.K + kc - 1) / kc;
+    g.kchunk = kc;
+    grid.z = splits;
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_NONE>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for((int64_t)g.M * g.N)), dim3(256), 0, st, g.part,
+                       splits, g.M, g.N, g.C, g.ldc, g.accumulate);
+  } else {
+    g.kchunk = g.K;
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI>), grid, dim3(256), 0, st, g);
+  }
+  return hip_check(hipGetLastError(), "gemm launch");
+}
+
+static GemmArgs gemm_args(int M, int N, int K, const void* A, int64_t lda, const void* B, int64_t ldb) {
+  GemmArgs g{};
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.A = A;
+  g.lda = lda;
+  g.B = B;
+  g.ldb = ldb;
+  return g;
+}
+
+// Workspace carving (256-byte aligned pieces).
+struct Carve {
+  char* base;
+  size_t off;
+  template <class U>
+  U* take(size_t count) {
+    U* p = reinterpret_cast<U*>(base ? base + off : nullptr);
+    off = (off + count * sizeof(U) + 255) & ~size_t(255);
+    return p;
+  }
+};
+
+constexpr int COLSUM_CHUNKS = 64;
+constexpr int MSE_BLOCKS = 1024;
+
+// The decoder's forward and backward over B snapshots x P points.  q: [B][r]
+// FP32 latents.  dg_in: when not NULL the caller's dL/dg [B*P][D] (no loss);
+// otherwise u [B][P] gives the MSE loss and dL/dg.  Writes grad_dec (natural
+// parameter layout) and dq [B][r].
+template <class T>
+struct DecoderPass {
+  T *a[16], *dz0, *dz1, *wt[16];
+  float *c, *g, *dg, *part;
+  double *cpart, *csum, *mpart;
+  static size_t bytes(const crom_net* n, int B, int64_t P) {
+    Carve cv{nullptr, 0};
+    DecoderPass d;
+    d.carve(cv, n, B, P);
+    return cv.off;
+  }
+  void carve(Carve& cv, const crom_net* n, int B, int64_t P) {
+    const int64_t rows = (int64_t)B * P;
+    const int W = n->width, depth = n->depth, D = n->d;
+    for (int l = 0; l < depth; ++l) a[l] = cv.take<T>((size_t)rows * W);
+    dz0 = cv.take<T>((size_t)rows * W);
+    dz1 = cv.take<T>((size_t)rows * W);
+    for (int l = 1; l < depth; ++l) wt[l] = cv.take<T>((size_t)W * W);
+    c = cv.take<float>((size_t)B * W);
+    g = cv.take<float>((size_t)rows * D);
+    dg = cv.take<float>((size_t)rows * D);
+    part = cv.take<float>((size_t)64 * W * W);
+    const int nw = 1 + n->m > D ? 1 + n->m : D;
+    cpart = cv.take<double>((size_t)B * COLSUM_CHUNKS * (nw > 1 + D ? nw : 1 + D) * W);
+    csum = cv.take<double>((size_t)B * (nw > 1 + D ? nw : 1 + D) * W);
+    mpart = cv.take<double>(MSE_BLOCKS);
+  }
+};
+
+template <class T>
+static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int64_t P, const float* q,
+                                   const float* u, const float* dg_in, float* grad, float* dq, float* loss,
+                                   DecoderPass<T>& ws, hipStream_t st) {
+  const int W = n->width, depth = n->depth, D = n->d, m = n->m, r = n->r;
+  const int64_t rows = (int64_t)B * P;
+  const ParamIndex pi = param_index(m, r, D, W, depth);
+  const float* prm = n->params;
+  crom_status s = CROM_OK;
+  // weights in the GEMM precision
+  for (int l = 1; l < depth; ++l)
+    hipLaunchKernelGGL((convert_kernel<T>), dim3(grid_for((int64_t)W * W)), dim3(256), 0, st, prm + pi.w[l], ws.wt[l],
+                       (int64_t)W * W);
+  // ---- forward ----
+  hipLaunchKernelGGL(fold_kernel, dim3(grid_for((int64_t)B * W)), dim3(256), 0, st, prm + pi.w[0], prm + pi.b[0], q,
+                     B, W, m, r, ws.c);
+  hipLaunchKernelGGL((layer1_kernel<T>), dim3(grid_for(rows * W)), dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows,
+                     W, m, r, ws.a[0]);
+  for (int l = 1; l < depth; ++l) {
+    GemmArgs g = gemm_args((int)rows, W, W, ws.a[l - 1], W, ws.wt[l], W);
+    g.bias = prm + pi.b[l];
+    if constexpr (sizeof(T) == 2) {
+      g.Cb = reinterpret_cast<__bf16*>(ws.a[l]);
+      g.ldcb = W;
+    } else {
+      g.C = reinterpret_cast<float*>(ws.a[l]);
+      g.ldc = W;
+    }
+    if ((s = gemm<T, false, true, EPI_BIAS_ELU>(g, st)) != CROM_OK) return s;
+  }
+  hipLaunchKernelGGL((output_kernel<T>), dim3(grid_for(rows * 64)), dim3(256), 0, st, ws.a[depth - 1],
+                     prm + pi.w[depth], prm + pi.b[depth], rows, W, D, ws.g);
+  const float* dg = dg_in;
+  if (!dg_in) {
+    hipLaunchKernelGGL(mse_kernel, dim3(MSE_BLOCKS), dim3(256), 0, st, ws.g, u, rows * D, ws.dg, ws.mpart);
+    hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(64), 0, st, ws.mpart, MSE_BLOCKS, rows * D, loss);
+    dg = ws.dg;
+  }
+  // ---- backward: output layer ----
+  {
+    // dWout[o][u] = sum_rows dg[row][o] a[row][u]; dbout[o] = sum dg[row][o]
+    // (column sums of a weighted by dg, and of dg itself)
+    const dim3 gg((W + 255) / 256, 1, COLSUM_CHUNKS);
+    hipLaunchKernelGGL((colsum_kernel<T>), gg, dim3(256), 0, st, ws.a[depth - 1], (int64_t)W, W, rows, COLSUM_CHUNKS,
+                       dg, rows, D, 1 + D, ws.cpart);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(grid_for((int64_t)(1 + D) * W)), dim3(256), 0, st, ws.cpart, 1,
+                       COLSUM_CHUNKS, 1 + D, W, ws.csum);
+    // csum[1 + o][u] = dWout[o][u]
+    hipLaunchKernelGGL(d2f_kernel, dim3(grid_for((int64_t)D * W)), dim3(256), 0, st, ws.csum + W, grad + pi.w[depth],
+                       (int64_t)D * W);
+    const dim3 gb((D + 255) / 256, 1, COLSUM_CHUNKS);
+    hipLaunchKernelGGL((colsum_kernel<float>), gb, dim3(256), 0, st, dg, (int64_t)D, D, rows, COLSUM_CHUNKS,
+                       nullptr, (int64_t)1, 0, 1, ws.cpart);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(1), dim3(256), 0, st, ws.cpart, 1, COLSUM_CHUNKS, 1, D, ws.csum);
+    hipLaunchKernelGGL(d2f_kernel, dim3(1), dim3(64), 0, st, ws.csum, grad + pi.b[depth], (int64_t)D);
+    hipLaunchKernelGGL((dz_last_kernel<T>), dim3(grid_for(rows * W)), dim3(256), 0, st, dg, prm + pi.w[depth],
+                       ws.a[depth - 1], rows, W, D, ws.dz0);
+  }
+  // ---- hidden layers ----
+  T* dz = ws.dz0;
+  T* dzn = ws.dz1;
+  for (int l = depth - 1; l >= 1; --l) {
+    // dW_l = dz^T a_{l-1}  (split over rows)
+    GemmArgs gw = gemm_args(W, W, (int)rows, dz, W, ws.a[l - 1], W);
+    gw.C = grad + pi.w[l];
+    gw.ldc = W;
+    gw.part = ws.part;
+    if ((s = gemm<T, true, false, EPI_NONE>(gw, st)) != CROM_OK) return s;
+    // db_l = column sums of dz
+    const dim3 gg((W + 255) / 256, 1, COLSUM_CHUNKS);
+    hipLaunchKernelGGL((colsum_kernel<T>), gg, dim3(256), 0, st, dz, (int64_t)W, W, rows, COLSUM_CHUNKS, nullptr,
+                       (int64_t)1, 0, 1, ws.cpart);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(grid_for(W)), dim3(256), 0, st, ws.cpart, 1, COLSUM_CHUNKS, 1, W,
+                       ws.csum);
+    hipLaunchKernelGGL(d2f_kernel, dim3(grid_for(W)), dim3(256), 0, st, ws.csum, grad + pi.b[l], (int64_t)W);
+    // dz_{l-1} = (dz W_l) * ELU'(a_{l-1})
+    GemmArgs gd = gemm_args((int)rows, W, W, dz, W, ws.wt[l], W);
+    gd.gate = ws.a[l - 1];
+    gd.ldg = W;
+    if constexpr (sizeof(T) == 2) {
+      gd.Cb = reinterpret_cast<__bf16*>(dzn);
+      gd.ldcb = W;
+    } else {
+      gd.C = reinterpret_cast<float*>(dzn);
+      gd.ldc = W;
+    }
+    if ((s = gemm<T, false, false, EPI_DELU>(gd, st)) != CROM_OK) return s;
+    T* t = dz;
+    dz = dzn;
+    dzn = t;
+  }
+  // ---- first layer: per-snapshot sums of dz1 and of dz1 * x_i ----
+  {
+    const int nw = 1 + m;
+    const dim3 gg((W + 255) / 256, B, COLSUM_CHUNKS);
+    hipLaunchKernelGGL((colsum_kernel<T>), gg, dim3(256), 0, st, dz, (int64_t)W, W, P, COLSUM_CHUNKS, x, P, m, nw,
+                       ws.cpart);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(grid_for((int64_t)B * nw * W)), dim3(256), 0, st, ws.cpart, B,
+                       COLSUM_CHUNKS, nw, W, ws.csum);
+    hipLaunchKernelGGL(layer1_grad_kernel, dim3(grid_for((int64_t)W * (m + r) + W + B * r)), dim3(256), 0, st,
+                       ws.csum, q, prm + pi.w[0], B, W, m, r, grad + pi.w[0], grad + pi.b[0], dq);
+  }
+  return hip_check(hipGetLastError(), "decoder backward");
+}
+
+// Encoder: E1 [hidden][n_in], c1 [hidden], E2 [r][hidden], c2 [r] (FP32).
+template <class T>
+struct EncoderPass {
+  T *e1, *ub, *h, *dh;
+  float *q, *dq, *h32;
+  double *cpart, *csum;
+  void carve(Carve& cv, const crom_encoder* e, int B) {
+    e1 = cv.take<T>((size_t)e->hidden * e->n_in);
+    ub = cv.take<T>((size_t)B * e->n_in);
+    h = cv.take<T>((size_t)B * e->hidden);
+    dh = cv.take<T>((size_t)B * e->hidden);
+    q = cv.take<float>((size_t)B * e->r);
+    dq = cv.take<float>((size_t)B * e->r);
+    h32 = cv.take<float>((size_t)B * e->hidden);
+    // column sums over the batch of dz1 [B][hidden] and of dq [B][r]
+    const int cols = e->hidden > e->r ? e->hidden : e->r;
+    cpart = cv.take<double>((size_t)COLSUM_CHUNKS * cols);
+    csum = cv.take<double>((size_t)cols);
+  }
+};
+
+static ParamIndex enc_index(const crom_encoder* e) {
+  ParamIndex pi{};
+  pi.w[0] = 0;
+  pi.b[0] = (int64_t)e->hidden * e->n_in;
+  pi.w[1] = pi.b[0] + e->hidden;
+  pi.b[1] = pi.w[1] + (int64_t)e->r * e->hidden;
+  return pi;
+}
+
+template <class T>
+static crom_status encoder_fwd(const crom_encoder* e, const float* u, int B, EncoderPass<T>& ws, hipStream_t st) {
+  const ParamIndex pi = enc_index(e);
+  const float* prm = e->params;
+  hipLaunchKernelGGL((convert_kernel<T>), dim3(grid_for((int64_t)e->hidden * e->n_in)), dim3(256), 0, st, prm,
+                     ws.e1, (int64_t)e->hidden * e->n_in);
+  hipLaunchKernelGGL((convert_kernel<T>), dim3(grid_for((int64_t)B * e->n_in)), dim3(256), 0, st, u, ws.ub,
+                     (int64_t)B * e->n_in);
+  // h = ELU(u E1^T + c1)  [B][hidden], kept in T (for the GEMM) and FP32
+  GemmArgs g = gemm_args(B, e->hidden, e->n_in, ws.ub, e->n_in, ws.e1, e->n_in);
+  g.bias = prm + pi.b[0];
+  g.C = ws.h32;
+  g.ldc = e->hidden;
+  crom_status s = gemm<T, false, true, EPI_BIAS_ELU>(g, st);
+  if (s != CROM_OK) return s;
+  hipLaunchKernelGGL((convert_kernel<T>), dim3(grid_for((int64_t)B * e->hidden)), dim3(256), 0, st, ws.h32, ws.h,
+                     (int64_t)B * e->hidden);
+  // q = h E2^T + c2 (FP32 product of the FP32 activations)
+  GemmArgs g2 = gemm_args(B, e->r, e->hidden, ws.h32, e->hidden, prm + pi.w[1], e->hidden);
+  g2.bias = prm + pi.b[1];
+  g2.C = ws.q;
+  g2.ldc = e->r;
+  return gemm<float, false, true, EPI_BIAS>(g2, st);
+}
+
+template <class T>
+static crom_status encoder_bwd(const crom_encoder* e, int B, const float* dq, float* grad, EncoderPass<T>& ws,
+                               float* split_part, hipStream_t st) {
+  const ParamIndex pi = enc_index(e);
+  const float* prm = e->params;
+  crom_status s;
+  // dE2 = dq^T h  [r][hidden], dc2 = sum_b dq
+  {
+    GemmArgs g = gemm_args(e->r, e->hidden, B, dq, e->r, ws.h32, e->hidden);
+    g.C = grad + pi.w[1];
+    g.ldc = e->hidden;
+    if ((s = gemm<float, true, false, EPI_NONE>(g, st)) != CROM_OK) return s;
+    const dim3 gg((e->r + 255) / 256, 1, 1);
+    hipLaunchKernelGGL((colsum_kernel<float>), gg, dim3(256), 0, st, dq, (int64_t)e->r, e->r, (int64_t)B, 1, nullptr,
+                       (int64_t)1, 0, 1, ws.cpart);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(1), dim3(256), 0, st, ws.cpart, 1, 1, 1, e->r, ws.csum);
+    hipLaunchKernelGGL(d2f_kernel, dim3(1), dim3(64), 0, st, ws.csum, grad + pi.b[1], (int64_t)e->r);
+  }
+  // dz1 = (dq E2) * ELU'(h)  [B][hidden]
+  {
+    GemmArgs g = gemm_args(B, e->hidden, e->r, dq, e->r, prm + pi.w[1], e->hidden);
+    g.gate = ws.h32;
+    g.ldg = e->hidden;
+    g.C = ws.h32;  // h is consumed by the gate in the same element: safe in place
+    g.ldc = e->hidden;
+    if ((s = gemm<float, false, false, EPI_DELU>(g, st)) != CROM_OK) return s;
+  }
+  hipLaunchKernelGGL((convert_kernel<T>), dim3(grid_for((int64_t)B * e->hidden)), dim3(256), 0, st, ws.h32, ws.dh,
+                     (int64_t)B * e->hidden);
+  // dE1 = dz1^T u  [hidden][n_in];  dc1 = sum_b dz1
+  {
+    GemmArgs g = gemm_args(e->hidden, e->n_in, B, ws.dh, e->hidden, ws.ub, e->n_in);
+    g.C = grad + pi.w[0];
+    g.ldc = e->n_in;
+    if ((s = gemm<T, true, false, EPI_NONE>(g, st)) != CROM_OK) return s;
+    const dim3 gg((e->hidden + 255) / 256, 1, 1);
+    hipLaunchKernelGGL((colsum_kernel<float>), gg, dim3(256), 0, st, ws.h32, (int64_t)e->hidden, e->hidden,
+                       (int64_t)B, 1, nullptr, (int64_t)1, 0, 1, ws.cpart);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(grid_for(e->hidden)), dim3(256), 0, st, ws.cpart, 1, 1, 1, e->hidden,
+                       ws.csum);
+    hipLaunchKernelGGL(d2f_kernel, dim3(grid_for(e->hidden)), dim3(256), 0, st, ws.csum, grad + pi.b[0],
+                       (int64_t)e->hidden);
+  }
+  (void)split_part;
+  return hip_check(hipGetLastError(), "encoder backward");
+}
+
+static bool bf_mode(const crom_net* n) { return n->precision != CROM_PREC_FP32; }
+
+template <class T>
+static size_t train_bytes_t(const crom_net* n, const crom_encoder* e, int B) {
+  Carve cv{nullptr, 0};
+  DecoderPass<T> d;
+  d.carve(cv, n, B, e->n_in / n->d);
+  EncoderPass<T> en;
+  en.carve(cv, e, B);
+  return cv.off + 256;
+}
+
+static crom_status check_enc(const crom_net* n, const crom_encoder* e) {
+  if (!e || !e->params) return fail(CROM_ERR_INVALID_ARG, "encoder and its params are required");
+  if (e->n_in < 1 || e->hidden < 1 || e->r != n->r || e->n_in % n->d != 0)
+    return fail(CROM_ERR_INVALID_ARG, "encoder shape: r must match the net and n_in = P * d");
+  return CROM_OK;
+}
+
+template <class T>
+static crom_status train_grads_t(const crom_net* n, const crom_encoder* e, const float* u, const float* x, int B,
+                                 float* grad_dec, float* grad_enc, float* loss, float* q_out, void* ws,
+                                 hipStream_t st) {
+  Carve cv{reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255)), 0};
+  const int64_t P = e->n_in / n->d;
+  DecoderPass<T> d;
+  d.carve(cv, n, B, P);
+  EncoderPass<T> en;
+  en.carve(cv, e, B);
+  crom_status s = encoder_fwd<T>(e, u, B, en, st);
+  if (s != CROM_OK) return s;
+  s = decoder_fwd_bwd<T>(n, x, B, P, en.q, u, nullptr, grad_dec, en.dq, loss, d, st);
+  if (s != CROM_OK) return s;
+  s = encoder_bwd<T>(e, B, en.dq, grad_enc, en, d.part, st);
+  if (s != CROM_OK) return s;
+  if (q_out) s = hip_check(hipMemcpyAsync(q_out, en.q, sizeof(float) * B * e->r, hipMemcpyDeviceToDevice, st), "q copy");
+  return s;
+}
+
+}  // namespace crom
+
+using namespace crom;
+
+extern "C" {
+
+size_t crom_encoder_param_count(int32_t n_in, int32_t hidden, int32_t r) {
+  if (n_in < 1 || hidden < 1 || r < 1) return 0;
+  return (size_t)hidden * n_in + hidden + (size_t)r * hidden + r;
+}
+
+crom_status crom_train_workspace(const crom_net* net, const crom_encoder* enc, int32_t B, size_t* bytes) {
+  crom_status s = check_net(net, false);
+  if (s != CROM_OK) return s;
+  if ((s = check_enc(net, enc)) != CROM_OK) return s;
+  if (B < 1 || !bytes) return fail(CROM_ERR_INVALID_ARG, "B >= 1 and bytes are required");
+  *bytes = bf_mode(net) ? train_bytes_t<__bf16>(net, enc, B) : train_bytes_t<float>(net, enc, B);
+  return CROM_OK;
+}
+
+crom_status crom_train_grads(const crom_net* net, const crom_encoder* enc, const float* u, const float* x, int32_t B,
+                             float* grad_dec, float* grad_enc, float* loss, float* q_out, void* ws, size_t ws_bytes,
+                             void* stream) {
+  crom_status s = check_net(net, false);
+  if (s != CROM_OK) return s;
+  if ((s = check_enc(net, enc)) != CROM_OK) return s;
+  if (B < 1 || !u || !x || !grad_dec || !grad_enc || !loss || !ws)
+    return fail(CROM_ERR_INVALID_ARG, "u, x, gradients, loss and ws are required");
+  size_t need = 0;
+  crom_train_workspace(net, enc, B, &need);
+  if (ws_bytes < need) return fail(CROM_ERR_WORKSPACE, "workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return bf_mode(net) ? train_grads_t<__bf16>(net, enc, u, x, B, grad_dec, grad_enc, loss, q_out, ws, st)
+                      : train_grads_t<float>(net, enc, u, x, B, grad_dec, grad_enc, loss, q_out, ws, st);
+}
+
+crom_status crom_adam_step(float* params, const float* grad, float* m, float* v, int64_t n, int64_t t, float lr,
+                           float beta1, float beta2, float eps, void* stream) {
+  if (n < 0 || t < 1) return fail(CROM_ERR_INVALID_ARG, "n >= 0 and t >= 1");
+  if (n == 0) return CROM_OK;
+  if (!params || !grad || !m || !v) return fail(CROM_ERR_INVALID_ARG, "params, grad, m and v are required");
+  const float c1 = (float)(1.0 - pow((double)beta1, (double)t));
+  const float c2 = (float)(1.0 - pow((double)beta2, (double)t));
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), params, grad, m,
+                     v, n, lr, beta1, beta2, eps, c1, c2);
+  return hip_check(hipGetLastError(), "adam launch");
+}
+
+crom_status crom_train_step(const crom_net* net, void* packed, float* dec_grad, float* dec_m, float* dec_v,
+                            const crom_encoder* enc, float* enc_grad, float* enc_m, float* enc_v, int64_t t,
+                            const float* u, const float* x, int32_t B, float lr, float* loss, void* ws,
+                            size_t ws_bytes, void* stream) {
+  crom_status s = crom_train_grads(net, enc, u, x, B, dec_grad, enc_grad, loss, nullptr, ws, ws_bytes, stream);
+  if (s != CROM_OK) return s;
+  if (!dec_m || !dec_v || !enc_m || !enc_v) return fail(CROM_ERR_INVALID_ARG, "Adam moments are required");
+  const int64_t nd = (int64_t)crom_net_param_count(net->m, net->r, net->d, net->width, net->depth);
+  const int64_t ne = (int64_t)crom_encoder_param_count(enc->n_in, enc->hidden, enc->r);
+  s = crom_adam_step(const_cast<float*>(net->params), dec_grad, dec_m, dec_v, nd, t, lr, 0.9f, 0.999f, 1e-8f, stream);
+  if (s != CROM_OK) return s;
+  s = crom_adam_step(enc->params, enc_grad, enc_m, enc_v, ne, t, lr, 0.9f, 0.999f, 1e-8f, stream);
+  if (s != CROM_OK) return s;
+  if (packed) return crom_net_pack(net, packed, stream);
+  return CROM_OK;
+}
+
+crom_status crom_decode_vjp_workspace(const crom_net* net, int32_t B, int64_t P, size_t* bytes) {
+  crom_status s = check_net(net, false);
+  if (s != CROM_OK) return s;
+  if (B < 1 || P < 1 || !bytes) return fail(CROM_ERR_INVALID_ARG, "B >= 1, P >= 1 and bytes are required");
+  *bytes = (bf_mode(net) ? DecoderPass<__bf16>::bytes(net, B, P) : DecoderPass<float>::bytes(net, B, P)) + 256;
+  return CROM_OK;
+}
+
+crom_status crom_decode_vjp(const crom_net* net, const float* x, int64_t P, const float* q, int32_t B,
+                            const float* dg, float* grad_params, float* grad_q, void* ws, size_t ws_bytes,
+                            void* stream) {
+  crom_status s = check_net(net, false);
+  if (s != CROM_OK) return s;
+  if (B < 1 || P < 1) return fail(CROM_ERR_INVALID_ARG, "B >= 1 and P >= 1");
+  if (!x || !q || !dg || !grad_params || !grad_q || !ws)
+    return fail(CROM_ERR_INVALID_ARG, "x, q, dg, grad_params, grad_q and ws are required");
+  size_t need = 0;
+  crom_decode_vjp_workspace(net, B, P, &need);
+  if (ws_bytes < need) return fail(CROM_ERR_WORKSPACE, "workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carve cv{reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255)), 0};
+  if (bf_mode(net)) {
+    DecoderPass<__bf16> d;
+    d.carve(cv, net, B, P);
+    return decoder_fwd_bwd<__bf16>(net, x, B, P, q, nullptr, dg, grad_params, grad_q, nullptr, d, st);
+  }
+  DecoderPass<float> d;
+  d.carve(cv, net, B, P);
+  return decoder_fwd_bwd<float>(net, x, B, P, q, nullptr, dg, grad_params, grad_q, nullptr, d, st);
+}
+
+}  // extern "C"

@@ -9,17 +9,19 @@ from oracle import train
 from workloads import rng, xavier_mlp
 
 
-def _problem(seed=0, B=3, P=11, m=2, r=3, w=8, depth=3, enc_hidden=6):
+def _problem(seed=0, B=3, P=11, m=2, r=3, w=8, depth=3, enc_hidden=6, d=1):
     g = rng(seed)
-    dec = [(W.astype(np.float64), b.astype(np.float64)) for W, b in xavier_mlp(g, m, r, 1, w, depth, 0.3)]
-    enc = [(W.astype(np.float64), b.astype(np.float64)) for W, b in xavier_mlp(g, P, 0, r, enc_hidden, 1, 0.3)]
+    dec = [(W.astype(np.float64), b.astype(np.float64)) for W, b in xavier_mlp(g, m, r, d, w, depth, 0.3)]
+    enc = [(W.astype(np.float64), b.astype(np.float64))
+           for W, b in xavier_mlp(g, P * d, 0, r, enc_hidden, 1, 0.3)]
     x = g.uniform(0, 1, size=(P, m))
-    u = g.uniform(-1, 1, size=(B, P))
+    u = g.uniform(-1, 1, size=(B, P * d))
     return dec, enc, x, u
 
 
-def test_gradients_vs_central_fd():
-    dec, enc, x, u = _problem()
+@pytest.mark.parametrize("d", [1, 3])
+def test_gradients_vs_central_fd(d):
+    dec, enc, x, u = _problem(d=d)
     loss, dg, eg, _ = train.loss_and_grads(dec, enc, x, u)
     g = rng(5)
     h = 1e-6
@@ -39,9 +41,10 @@ def test_gradients_vs_central_fd():
                     assert abs(grads[li][which][idx] - fd) <= 1e-6 * max(1.0, abs(fd)), (li, which, idx)
 
 
-def test_gradients_vs_autograd_float64():
+@pytest.mark.parametrize("d", [1, 3])
+def test_gradients_vs_autograd_float64(d):
     torch = pytest.importorskip("torch")
-    dec, enc, x, u = _problem(seed=1, B=2, P=7)
+    dec, enc, x, u = _problem(seed=1, B=2, P=7, d=d)
     loss, dg, eg, q = train.loss_and_grads(dec, enc, x, u)
     T = lambda a: torch.tensor(a, dtype=torch.float64, requires_grad=True)  # noqa: E731
     tdec = [(T(W), T(b)) for W, b in dec]
@@ -54,10 +57,10 @@ def test_gradients_vs_autograd_float64():
 
     tu = torch.tensor(u)
     tq = mlp(tenc, tu)
-    B, P = u.shape
+    B, P = u.shape[0], x.shape[0]
     a0 = torch.cat([torch.tensor(x).repeat(B, 1), tq.repeat_interleave(P, dim=0)], dim=1)
     tg = mlp(tdec, a0)
-    tl = ((tg[:, 0] - tu.reshape(-1)) ** 2).mean()
+    tl = ((tg - tu.reshape(B * P, -1)) ** 2).mean()
     tl.backward()
     assert abs(tl.item() - loss) <= 1e-14 * max(1.0, loss)
     np.testing.assert_allclose(tq.detach().numpy(), q, rtol=1e-13, atol=1e-15)
