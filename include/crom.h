@@ -297,6 +297,15 @@ crom_status crom_train_step(const crom_net* net, void* packed, float* dec_grad, 
                             float* enc_v, int64_t t, const float* u, const float* x, int32_t B,
                             float lr, float* loss, void* ws, size_t ws_bytes, void* stream);
 
+/* Encoder forward only: q [B][r] FP32 = E2 ELU(E1 u_b + c1) + c2 for
+ * snapshots u [B][P][d], in the arithmetic crom_train_grads uses for the
+ * net's precision (the latent of an initial field, Sec. "Manifold
+ * Construction").  ws: crom_encode_workspace bytes. */
+crom_status crom_encode_workspace(const crom_net* net, const crom_encoder* enc, int32_t B,
+                                  size_t* bytes);
+crom_status crom_encode(const crom_net* net, const crom_encoder* enc, const float* u, int32_t B,
+                        float* q, void* ws, size_t ws_bytes, void* stream);
+
 /* Vector-Jacobian product of the decoder (the backward of crom_decode over
  * B latents): with G[b][p][o] = g(x_p, q_b)_o and a cotangent dg [B][P][d],
  *   grad_params = sum dg . dG/dparams   (natural layout, overwritten)

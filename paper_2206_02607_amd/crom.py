@@ -99,13 +99,18 @@ def lib():
                                       POINTER(CromEncoder), c_void_p, c_void_p, c_void_p, c_int64,
                                       c_void_p, c_void_p, c_int32, ctypes.c_float, c_void_p,
                                       c_void_p, c_size_t, c_void_p]
+        L.crom_encode_workspace.argtypes = [POINTER(CromNet), POINTER(CromEncoder), c_int32,
+                                            POINTER(c_size_t)]
+        L.crom_encode.argtypes = [POINTER(CromNet), POINTER(CromEncoder), c_void_p, c_int32, c_void_p,
+                                  c_void_p, c_size_t, c_void_p]
         L.crom_decode_vjp_workspace.argtypes = [POINTER(CromNet), c_int32, c_int64, POINTER(c_size_t)]
         L.crom_decode_vjp.argtypes = [POINTER(CromNet), c_void_p, c_int64, c_void_p, c_int32,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
         for name in ("crom_net_pack", "crom_decode", "crom_decode_jac", "crom_decode_jac_x",
                      "crom_decode_jac_q", "crom_step_workspace", "crom_step", "crom_fd_heat",
                      "crom_train_workspace", "crom_train_grads", "crom_adam_step", "crom_train_step",
-                     "crom_decode_vjp_workspace", "crom_decode_vjp"):
+                     "crom_decode_vjp_workspace", "crom_decode_vjp", "crom_encode_workspace",
+                     "crom_encode"):
             getattr(L, name).restype = c_int32
         _lib = L
     return _lib
@@ -344,8 +349,22 @@ class Trainer:
         return self.loss
 
     def encode(self, u):
-        """Latents of the snapshots u [B, P(, d)] (runs the batch's forward and backward)."""
-        return self.grads(u)[3].clone()
+        """Latents q [n, r] FP32 of the snapshots u [n, P(, d)], any n >= 1
+        (encoder forward only, crom_encode)."""
+        torch = _torch()
+        u = u.to(device=self.x.device, dtype=torch.float32).contiguous()
+        n = u.numel() // self.n_in
+        if n < 1 or u.numel() != n * self.n_in:
+            raise CromError(f"u must hold n x {self.n_in} values")
+        net, enc = self.dec._net(packed=False), self._enc()
+        nbytes = c_size_t(0)
+        _check(lib().crom_encode_workspace(ctypes.byref(net), ctypes.byref(enc), n, ctypes.byref(nbytes)),
+               "crom_encode_workspace")
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.x.device)
+        q = torch.empty(n, self.dec.r, dtype=torch.float32, device=self.x.device)
+        _check(lib().crom_encode(ctypes.byref(net), ctypes.byref(enc), _ptr(u), n, _ptr(q), _ptr(ws),
+                                 nbytes.value, _stream()), "crom_encode")
+        return q
 
 
 def adam_step(params, grad, m, v, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):

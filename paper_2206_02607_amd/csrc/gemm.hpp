@@ -3,7 +3,8 @@
 //   op(A)(m, k) = TA ? A[k * lda + m] : A[m * lda + k]
 //   op(B)(k, n) = TB ? B[n * ldb + k] : B[k * ldb + n]
 // T = __bf16 (v_mfma_f32_16x16x32_bf16) or float (v_mfma_f32_16x16x4_f32);
-// accumulation is FP32.  Block tile 64 x 64, four waves of 32 x 32.  Split-K
+// accumulation is FP32.  Block tile 64 x 64 (K tile 64 in bfloat16, 32 in FP32), four waves of
+// 32 x 32.  Split-K
 // writes FP32 partial tiles that a second kernel sums in a fixed order.
 #pragma once
 
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   typedef __bf16 bf16x8_ __attribute__((ext_vector_type(8)));
   typedef float f32x4_ __attribute__((ext_vector_type(4)));
   constexpr bool BF = sizeof(T) == 2;
-  constexpr int BK = BF ? 32 : 16;
+  constexpr int BK = BF ? 64 : 32;
   constexpr int LDK = BK + (BF ? 8 : 4);  // padded row (k contiguous) against bank conflicts
   __shared__ __align__(16) T As[64 * LDK];
   __shared__ __align__(16) T Bs[64 * LDK];
@@ -60,33 +61,85 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_{0.0f, 0.0f, 0.0f, 0.0f};
 
+  constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte load
+  typedef T vec_t __attribute__((ext_vector_type(VEC)));
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // stage the tiles, zero outside the matrix
-    for (int idx = tid; idx < 64 * BK; idx += 256) {
-      int r, k;
-      if (TA) { k = idx / 64; r = idx % 64; } else { r = idx / BK; k = idx % BK; }
-      const int gm = m0 + r, gk = k0 + k;
-      T v = T(0.0f);
-      if (gm < g.M && gk < kend) v = TA ? A[(int64_t)gk * g.lda + gm] : A[(int64_t)gm * g.lda + gk];
-      As[r * LDK + k] = v;
+    // Stage the A tile (rows m, k) and the B tile (columns n, k) into LDS,
+    // k contiguous, with 16-byte loads along each operand's contiguous
+    // direction; ragged edges (and unaligned rows) load element by element
+    // and fill zeros outside the matrix.
+    if constexpr (!TA) {
+      for (int v = tid; v < 64 * BK / VEC; v += 256) {
+        const int r = v / (BK / VEC), kk = (v % (BK / VEC)) * VEC;
+        const int gm = m0 + r, gk = k0 + kk;
+        const T* src = A + (int64_t)gm * g.lda + gk;
+        if (gm < g.M && gk + VEC <= kend && ((uintptr_t)src & 15) == 0) {
+          *reinterpret_cast<vec_t*>(&As[r * LDK + kk]) = *reinterpret_cast<const vec_t*>(src);
+        } else {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i)
+            As[r * LDK + kk + i] = (gm < g.M && gk + i < kend) ? src[i] : T(0.0f);
+        }
+      }
+    } else {
+      for (int v = tid; v < BK * 64 / VEC; v += 256) {
+        const int k = v / (64 / VEC), rr = (v % (64 / VEC)) * VEC;
+        const int gk = k0 + k, gm = m0 + rr;
+        const T* src = A + (int64_t)gk * g.lda + gm;
+        if (gk < kend && gm + VEC <= g.M && ((uintptr_t)src & 15) == 0) {
+          const vec_t e = *reinterpret_cast<const vec_t*>(src);
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) As[(rr + i) * LDK + k] = e[i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i)
+            As[(rr + i) * LDK + k] = (gk < kend && gm + i < g.M) ? src[i] : T(0.0f);
+        }
+      }
     }
-    for (int idx = tid; idx < 64 * BK; idx += 256) {
-      int c, k;
-      if (TB) { c = idx / BK; k = idx % BK; } else { k = idx / 64; c = idx % 64; }
-      const int gn = n0 + c, gk = k0 + k;
-      T v = T(0.0f);
-      if (gn < g.N && gk < kend) v = TB ? B[(int64_t)gn * g.ldb + gk] : B[(int64_t)gk * g.ldb + gn];
-      Bs[c * LDK + k] = v;
+    if constexpr (TB) {
+      for (int v = tid; v < 64 * BK / VEC; v += 256) {
+        const int c = v / (BK / VEC), kk = (v % (BK / VEC)) * VEC;
+        const int gn = n0 + c, gk = k0 + kk;
+        const T* src = B + (int64_t)gn * g.ldb + gk;
+        if (gn < g.N && gk + VEC <= kend && ((uintptr_t)src & 15) == 0) {
+          *reinterpret_cast<vec_t*>(&Bs[c * LDK + kk]) = *reinterpret_cast<const vec_t*>(src);
+        } else {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i)
+            Bs[c * LDK + kk + i] = (gn < g.N && gk + i < kend) ? src[i] : T(0.0f);
+        }
+      }
+    } else {
+      for (int v = tid; v < BK * 64 / VEC; v += 256) {
+        const int k = v / (64 / VEC), cc = (v % (64 / VEC)) * VEC;
+        const int gk = k0 + k, gn = n0 + cc;
+        const T* src = B + (int64_t)gk * g.ldb + gn;
+        if (gk < kend && gn + VEC <= g.N && ((uintptr_t)src & 15) == 0) {
+          const vec_t e = *reinterpret_cast<const vec_t*>(src);
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) Bs[(cc + i) * LDK + k] = e[i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i)
+            Bs[(cc + i) * LDK + k] = (gk < kend && gn + i < g.N) ? src[i] : T(0.0f);
+        }
+      }
     }
     __syncthreads();
     if constexpr (BF) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const bf16x8_ af = *reinterpret_cast<const bf16x8_*>(&As[(wr + i * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
+      for (int ks = 0; ks < BK; ks += 32) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const bf16x8_ bfr = *reinterpret_cast<const bf16x8_*>(&Bs[(wc + j * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, acc[i][j], 0, 0, 0);
+        for (int i = 0; i < 2; ++i) {
+          const bf16x8_ af =
+              *reinterpret_cast<const bf16x8_*>(&As[(wr + i * 16 + (lane & 15)) * LDK + ks + 8 * (lane >> 4)]);
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const bf16x8_ bfr =
+                *reinterpret_cast<const bf16x8_*>(&Bs[(wc + j * 16 + (lane & 15)) * LDK + ks + 8 * (lane >> 4)]);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, acc[i][j], 0, 0, 0);
+          }
         }
       }
     } else {
@@ -138,14 +191,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       }
 }
 
-// Sum of split-K partials in split order, then the epilogue-free store.
+// Sum of split-K partials in split order, then the epilogue (none, bias,
+// or bias + ELU) and the FP32 store.
 __global__ void splitk_reduce_kernel(const float* __restrict__ part, int splits, int M, int N,
-                                     float* C, int64_t ldc, int accumulate) {
+                                     float* C, int64_t ldc, int accumulate, int epi,
+                                     const float* __restrict__ bias) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)M * N;
        e += (int64_t)gridDim.x * blockDim.x) {
     float s = 0.0f;
     for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + e];
     const int m = (int)(e / N), n = (int)(e % N);
+    if (epi == EPI_BIAS || epi == EPI_BIAS_ELU) s += bias[n];
+    if (epi == EPI_BIAS_ELU) s = s > 0.0f ? s : __expf(s) - 1.0f;
     float* c = &C[(int64_t)m * ldc + n];
     *c = accumulate ? *c + s : s;
   }

@@ -85,12 +85,20 @@ __global__ void mse_kernel(const float* __restrict__ g, const float* __restrict_
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void mse_final_kernel(const double* __restrict__ part, int nb, int64_t n, float* loss) {
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < nb; ++i) s += part[i];
-    *loss = (float)(s / (double)n);
+// loss = sum of the block partials / n: each thread adds a strided quarter
+// of them, then a fixed-order tree.
+__global__ __launch_bounds__(256) void mse_final_kernel(const double* __restrict__ part, int nb, int64_t n,
+                                                         float* loss) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *loss = (float)(sh[0] / (double)n);
 }
 
 // dz[row][u] = (sum_o dg[row][o] Wout[o][u]) * ELU'(a[row][u])
@@ -108,35 +116,107 @@ __global__ void dz_last_kernel(const float* __restrict__ dg, const float* __rest
 
 // Weighted column sums over row segments, in two fixed-order passes.
 //   out[seg][k][col] = sum over rows of the segment of w_k(row) X[row][col]
-// with w_0 = 1 and w_k = wt[row % wmod][k - 1] (k = 1..nw-1, stride wstride).
-// Pass 1: block (col tile, segment, chunk) sums its rows; pass 2 adds chunks.
-template <class T>
-__global__ void colsum_kernel(const T* __restrict__ X, int64_t ldx, int cols, int64_t seg_rows, int chunks,
-                              const float* __restrict__ wt, int64_t wmod, int wstride, int nw,
-                              double* __restrict__ part) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  const int seg = blockIdx.y, ch = blockIdx.z;
-  const int64_t per = (seg_rows + chunks - 1) / chunks;
-  const int64_t r0 = ch * per, r1 = min(seg_rows, r0 + per);
-  if (col >= cols) return;
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t r = r0; r < r1; ++r) {
-    const int64_t row = seg * seg_rows + r;
-    const double v = (double)(float)X[row * ldx + col];
-    s[0] += v;
-    for (int k = 1; k < nw; ++k) s[k] += v * (double)wt[(row % wmod) * wstride + (k - 1)];
+// with w_0 = 1 and w_k = wt[(row % wmod) * wstride + k - 1] (k = 1..nw-1).
+// Pass 1: block (chunk, seg) sums `chunk_rows` rows of its segment.  Its
+// threads split into row groups; a thread adds the rows of its group for
+// VEC consecutive columns (VEC = 16 bytes of X when the rows are aligned,
+// else 1), in FP32, then the groups are added in group order in FP64.
+// Pass 2 adds the chunks in a fixed order.
+template <class T, int VEC>
+__global__ __launch_bounds__(256) void colsum_kernel(const T* __restrict__ X, int64_t ldx, int cols,
+                                                     int64_t seg_rows, int chunk_rows,
+                                                     const float* __restrict__ wt, int64_t wmod, int wstride,
+                                                     int nw, double* __restrict__ part) {
+  __shared__ double sh[4][256];
+  typedef T vec_t __attribute__((ext_vector_type(VEC)));
+  const int ch = blockIdx.x, seg = blockIdx.y, chunks = gridDim.x;
+  const int64_t r0 = (int64_t)ch * chunk_rows;
+  const int64_t r1 = min(seg_rows, r0 + chunk_rows);
+  const int tid = threadIdx.x;
+  for (int c0 = 0; c0 < cols; c0 += 256 * VEC) {
+    const int cw = min(256 * VEC, cols - c0);       // columns of this pass
+    const int tpr = (cw + VEC - 1) / VEC;           // threads per row
+    const int G = 256 / tpr;                        // row groups
+    const int cv = tid % tpr, rg = tid / tpr;
+    const int col = c0 + cv * VEC;
+    float s[4][VEC];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) s[k][e] = 0.0f;
+    if (rg < G) {
+#pragma unroll 4
+      for (int64_t r = r0 + rg; r < r1; r += G) {
+        const int64_t row = seg * seg_rows + r;
+        float v[VEC];
+        if constexpr (VEC > 1) {
+          const vec_t x = *reinterpret_cast<const vec_t*>(&X[row * ldx + col]);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) v[e] = (float)x[e];
+        } else {
+          v[0] = (float)X[row * ldx + col];
+        }
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) s[0][e] += v[e];
+        for (int k = 1; k < nw; ++k) {
+          const float w = wt[(row % wmod) * wstride + (k - 1)];
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) s[k][e] += v[e] * w;
+        }
+      }
+    }
+    for (int e = 0; e < VEC; ++e) {
+      for (int k = 0; k < nw; ++k) sh[k][tid] = rg < G ? (double)s[k][e] : 0.0;
+      __syncthreads();
+      if (tid < tpr && c0 + tid * VEC + e < cols) {
+        for (int k = 0; k < nw; ++k) {
+          double a = 0.0;
+          for (int q = 0; q < G; ++q) a += sh[k][q * tpr + tid];
+          part[(((int64_t)seg * chunks + ch) * nw + k) * cols + c0 + tid * VEC + e] = a;
+        }
+      }
+      __syncthreads();
+    }
   }
-  for (int k = 0; k < nw; ++k) part[(((int64_t)seg * chunks + ch) * nw + k) * cols + col] = s[k];
 }
 
-__global__ void colsum_final_kernel(const double* __restrict__ part, int segs, int chunks, int nw, int cols,
-                                    double* __restrict__ out) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < segs * nw * cols; i += gridDim.x * blockDim.x) {
-    const int seg = i / (nw * cols), rem = i % (nw * cols);
-    double s = 0.0;
-    for (int ch = 0; ch < chunks; ++ch) s += part[((int64_t)seg * chunks + ch) * nw * cols + rem];
-    out[i] = s;
+// Pass 2: out[seg][k][col] = sum over chunks, in chunk order within each of
+// 4 interleaved lanes, then the 4 lanes in order.
+__global__ __launch_bounds__(256) void colsum_final_kernel(const double* __restrict__ part, int segs, int chunks,
+                                                           int nw, int cols, double* __restrict__ out) {
+  __shared__ double sh[4][64];
+  const int n_out = nw * cols;
+  const int o = blockIdx.x * 64 + (threadIdx.x & 63), lane4 = threadIdx.x >> 6, seg = blockIdx.y;
+  double a = 0.0;
+  if (o < n_out) {
+#pragma unroll 8
+    for (int c = lane4; c < chunks; c += 4) a += part[((int64_t)seg * chunks + c) * n_out + o];
   }
+  sh[lane4][threadIdx.x & 63] = a;
+  __syncthreads();
+  if (threadIdx.x < 64 && o < n_out)
+    out[(int64_t)seg * n_out + o] = ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
+}
+
+// Column sums of X [segs * seg_rows][cols] (leading dimension ldx) per
+// segment, weighted as in colsum_kernel, into out [segs][nw][cols] (FP64).
+template <class T>
+static void colsum(const T* X, int64_t ldx, int cols, int segs, int64_t seg_rows, const float* wt, int64_t wmod,
+                   int wstride, int nw, double* part, int max_chunks, double* out, hipStream_t st) {
+  int chunks = (int)((seg_rows + 255) / 256);
+  const int cap = max(1, max_chunks / segs);
+  if (chunks > cap) chunks = cap;
+  if (chunks < 1) chunks = 1;
+  const int chunk_rows = (int)((seg_rows + chunks - 1) / chunks);
+  constexpr int VEC = 16 / (int)sizeof(T);
+  if (cols % VEC == 0 && ldx % VEC == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0)
+    hipLaunchKernelGGL((colsum_kernel<T, VEC>), dim3(chunks, segs), dim3(256), 0, st, X, ldx, cols, seg_rows,
+                       chunk_rows, wt, wmod, wstride, nw, part);
+  else
+    hipLaunchKernelGGL((colsum_kernel<T, 1>), dim3(chunks, segs), dim3(256), 0, st, X, ldx, cols, seg_rows,
+                       chunk_rows, wt, wmod, wstride, nw, part);
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((nw * cols + 63) / 64, segs), dim3(256), 0, st, part, segs, chunks,
+                     nw, cols, out);
 }
 
 // First-layer gradients from the per-snapshot sums S[b][0][u] = sum_p dz1,
@@ -199,7 +279,7 @@ static unsigned grid_for(int64_t n, int threads = 256) {
 
 template <class T, bool TA, bool TB, int EPI>
 static crom_status gemm(GemmArgs g, hipStream_t st) {
-  constexpr int BK = sizeof(T) == 2 ? 32 : 16;
+  constexpr int BK = sizeof(T) == 2 ? 64 : 32;  // the kernel's K tile
   dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, 1);
   if (g.part) {
     // split K so that there are a few hundred blocks
@@ -214,9 +294,10 @@ static crom_status gemm(GemmArgs g, hipStream_t st) {
     splits = (g.K + kc - 1) / kc;
     g.kchunk = kc;
     grid.z = splits;
+    if (EPI == EPI_DELU) return fail(CROM_ERR_INVALID_ARG, "split-K carries no gate");
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_NONE>), grid, dim3(256), 0, st, g);
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for((int64_t)g.M * g.N)), dim3(256), 0, st, g.part,
-                       splits, g.M, g.N, g.C, g.ldc, g.accumulate);
+                       splits, g.M, g.N, g.C, g.ldc, g.accumulate, EPI, g.bias);
   } else {
     g.kchunk = g.K;
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI>), grid, dim3(256), 0, st, g);
@@ -248,7 +329,7 @@ struct Carve {
   }
 };
 
-constexpr int COLSUM_CHUNKS = 64;
+constexpr int COLSUM_CHUNKS = 256;  // partial sums per column sum at most
 constexpr int MSE_BLOCKS = 1024;
 
 // The decoder's forward and backward over B snapshots x P points.  q: [B][r]
@@ -278,8 +359,9 @@ struct DecoderPass {
     dg = cv.take<float>((size_t)rows * D);
     part = cv.take<float>((size_t)64 * W * W);
     const int nw = 1 + n->m > D ? 1 + n->m : D;
-    cpart = cv.take<double>((size_t)B * COLSUM_CHUNKS * (nw > 1 + D ? nw : 1 + D) * W);
-    csum = cv.take<double>((size_t)B * (nw > 1 + D ? nw : 1 + D) * W);
+    const int nmax = nw > 1 + D ? nw : 1 + D;
+    cpart = cv.take<double>((size_t)(B > COLSUM_CHUNKS ? B : COLSUM_CHUNKS) * nmax * W);
+    csum = cv.take<double>((size_t)B * nmax * W);
     mpart = cv.take<double>(MSE_BLOCKS);
   }
 };
@@ -319,25 +401,18 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
   const float* dg = dg_in;
   if (!dg_in) {
     hipLaunchKernelGGL(mse_kernel, dim3(MSE_BLOCKS), dim3(256), 0, st, ws.g, u, rows * D, ws.dg, ws.mpart);
-    hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(64), 0, st, ws.mpart, MSE_BLOCKS, rows * D, loss);
+    hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(256), 0, st, ws.mpart, MSE_BLOCKS, rows * D, loss);
     dg = ws.dg;
   }
   // ---- backward: output layer ----
   {
     // dWout[o][u] = sum_rows dg[row][o] a[row][u]; dbout[o] = sum dg[row][o]
     // (column sums of a weighted by dg, and of dg itself)
-    const dim3 gg((W + 255) / 256, 1, COLSUM_CHUNKS);
-    hipLaunchKernelGGL((colsum_kernel<T>), gg, dim3(256), 0, st, ws.a[depth - 1], (int64_t)W, W, rows, COLSUM_CHUNKS,
-                       dg, rows, D, 1 + D, ws.cpart);
-    hipLaunchKernelGGL(colsum_final_kernel, dim3(grid_for((int64_t)(1 + D) * W)), dim3(256), 0, st, ws.cpart, 1,
-                       COLSUM_CHUNKS, 1 + D, W, ws.csum);
+    colsum<T>(ws.a[depth - 1], W, W, 1, rows, dg, rows, D, 1 + D, ws.cpart, COLSUM_CHUNKS, ws.csum, st);
     // csum[1 + o][u] = dWout[o][u]
     hipLaunchKernelGGL(d2f_kernel, dim3(grid_for((int64_t)D * W)), dim3(256), 0, st, ws.csum + W, grad + pi.w[depth],
                        (int64_t)D * W);
-    const dim3 gb((D + 255) / 256, 1, COLSUM_CHUNKS);
-    hipLaunchKernelGGL((colsum_kernel<float>), gb, dim3(256), 0, st, dg, (int64_t)D, D, rows, COLSUM_CHUNKS,
-                       nullptr, (int64_t)1, 0, 1, ws.cpart);
-    hipLaunchKernelGGL(colsum_final_kernel, dim3(1), dim3(256), 0, st, ws.cpart, 1, COLSUM_CHUNKS, 1, D, ws.csum);
+    colsum<float>(dg, D, D, 1, rows, nullptr, 1, 0, 1, ws.cpart, COLSUM_CHUNKS, ws.csum, st);
     hipLaunchKernelGGL(d2f_kernel, dim3(1), dim3(64), 0, st, ws.csum, grad + pi.b[depth], (int64_t)D);
     hipLaunchKernelGGL((dz_last_kernel<T>), dim3(grid_for(rows * W)), dim3(256), 0, st, dg, prm + pi.w[depth],
                        ws.a[depth - 1], rows, W, D, ws.dz0);
@@ -353,11 +428,7 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
     gw.part = ws.part;
     if ((s = gemm<T, true, false, EPI_NONE>(gw, st)) != CROM_OK) return s;
     // db_l = column sums of dz
-    const dim3 gg((W + 255) / 256, 1, COLSUM_CHUNKS);
-    hipLaunchKernelGGL((colsum_kernel<T>), gg, dim3(256), 0, st, dz, (int64_t)W, W, rows, COLSUM_CHUNKS, nullptr,
-                       (int64_t)1, 0, 1, ws.cpart);
-    hipLaunchKernelGGL(colsum_final_kernel, dim3(grid_for(W)), dim3(256), 0, st, ws.cpart, 1, COLSUM_CHUNKS, 1, W,
-                       ws.csum);
+    colsum<T>(dz, W, W, 1, rows, nullptr, 1, 0, 1, ws.cpart, COLSUM_CHUNKS, ws.csum, st);
     hipLaunchKernelGGL(d2f_kernel, dim3(grid_for(W)), dim3(256), 0, st, ws.csum, grad + pi.b[l], (int64_t)W);
     // dz_{l-1} = (dz W_l) * ELU'(a_{l-1})
     GemmArgs gd = gemm_args((int)rows, W, W, dz, W, ws.wt[l], W);
@@ -378,11 +449,7 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
   // ---- first layer: per-snapshot sums of dz1 and of dz1 * x_i ----
   {
     const int nw = 1 + m;
-    const dim3 gg((W + 255) / 256, B, COLSUM_CHUNKS);
-    hipLaunchKernelGGL((colsum_kernel<T>), gg, dim3(256), 0, st, dz, (int64_t)W, W, P, COLSUM_CHUNKS, x, P, m, nw,
-                       ws.cpart);
-    hipLaunchKernelGGL(colsum_final_kernel, dim3(grid_for((int64_t)B * nw * W)), dim3(256), 0, st, ws.cpart, B,
-                       COLSUM_CHUNKS, nw, W, ws.csum);
+    colsum<T>(dz, W, W, B, P, x, P, m, nw, ws.cpart, COLSUM_CHUNKS, ws.csum, st);
     hipLaunchKernelGGL(layer1_grad_kernel, dim3(grid_for((int64_t)W * (m + r) + W + B * r)), dim3(256), 0, st,
                        ws.csum, q, prm + pi.w[0], B, W, m, r, grad + pi.w[0], grad + pi.b[0], dq);
   }
@@ -393,7 +460,7 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
 template <class T>
 struct EncoderPass {
   T *e1, *ub, *h, *dh;
-  float *q, *dq, *h32;
+  float *q, *dq, *h32, *kpart;
   double *cpart, *csum;
   void carve(Carve& cv, const crom_encoder* e, int B) {
     e1 = cv.take<T>((size_t)e->hidden * e->n_in);
@@ -403,6 +470,7 @@ struct EncoderPass {
     q = cv.take<float>((size_t)B * e->r);
     dq = cv.take<float>((size_t)B * e->r);
     h32 = cv.take<float>((size_t)B * e->hidden);
+    kpart = cv.take<float>((size_t)64 * B * e->hidden);
     // column sums over the batch of dz1 [B][hidden] and of dq [B][r]
     const int cols = e->hidden > e->r ? e->hidden : e->r;
     cpart = cv.take<double>((size_t)COLSUM_CHUNKS * cols);
@@ -432,6 +500,7 @@ static crom_status encoder_fwd(const crom_encoder* e, const float* u, int B, Enc
   g.bias = prm + pi.b[0];
   g.C = ws.h32;
   g.ldc = e->hidden;
+  g.part = ws.kpart;  // few rows, long K: split K over blocks
   crom_status s = gemm<T, false, true, EPI_BIAS_ELU>(g, st);
   if (s != CROM_OK) return s;
   hipLaunchKernelGGL((convert_kernel<T>), dim3(grid_for((int64_t)B * e->hidden)), dim3(256), 0, st, ws.h32, ws.h,
@@ -456,10 +525,7 @@ static crom_status encoder_bwd(const crom_encoder* e, int B, const float* dq, fl
     g.C = grad + pi.w[1];
     g.ldc = e->hidden;
     if ((s = gemm<float, true, false, EPI_NONE>(g, st)) != CROM_OK) return s;
-    const dim3 gg((e->r + 255) / 256, 1, 1);
-    hipLaunchKernelGGL((colsum_kernel<float>), gg, dim3(256), 0, st, dq, (int64_t)e->r, e->r, (int64_t)B, 1, nullptr,
-                       (int64_t)1, 0, 1, ws.cpart);
-    hipLaunchKernelGGL(colsum_final_kernel, dim3(1), dim3(256), 0, st, ws.cpart, 1, 1, 1, e->r, ws.csum);
+    colsum<float>(dq, e->r, e->r, 1, B, nullptr, 1, 0, 1, ws.cpart, COLSUM_CHUNKS, ws.csum, st);
     hipLaunchKernelGGL(d2f_kernel, dim3(1), dim3(64), 0, st, ws.csum, grad + pi.b[1], (int64_t)e->r);
   }
   // dz1 = (dq E2) * ELU'(h)  [B][hidden]
@@ -479,11 +545,7 @@ static crom_status encoder_bwd(const crom_encoder* e, int B, const float* dq, fl
     g.C = grad + pi.w[0];
     g.ldc = e->n_in;
     if ((s = gemm<T, true, false, EPI_NONE>(g, st)) != CROM_OK) return s;
-    const dim3 gg((e->hidden + 255) / 256, 1, 1);
-    hipLaunchKernelGGL((colsum_kernel<float>), gg, dim3(256), 0, st, ws.h32, (int64_t)e->hidden, e->hidden,
-                       (int64_t)B, 1, nullptr, (int64_t)1, 0, 1, ws.cpart);
-    hipLaunchKernelGGL(colsum_final_kernel, dim3(grid_for(e->hidden)), dim3(256), 0, st, ws.cpart, 1, 1, 1, e->hidden,
-                       ws.csum);
+    colsum<float>(ws.h32, e->hidden, e->hidden, 1, B, nullptr, 1, 0, 1, ws.cpart, COLSUM_CHUNKS, ws.csum, st);
     hipLaunchKernelGGL(d2f_kernel, dim3(grid_for(e->hidden)), dim3(256), 0, st, ws.csum, grad + pi.b[0],
                        (int64_t)e->hidden);
   }
@@ -593,6 +655,44 @@ crom_status crom_train_step(const crom_net* net, void* packed, float* dec_grad, 
   if (s != CROM_OK) return s;
   if (packed) return crom_net_pack(net, packed, stream);
   return CROM_OK;
+}
+
+crom_status crom_encode_workspace(const crom_net* net, const crom_encoder* enc, int32_t B, size_t* bytes) {
+  crom_status s = check_net(net, false);
+  if (s != CROM_OK) return s;
+  if ((s = check_enc(net, enc)) != CROM_OK) return s;
+  if (B < 1 || !bytes) return fail(CROM_ERR_INVALID_ARG, "B >= 1 and bytes are required");
+  Carve cv{nullptr, 0};
+  if (bf_mode(net)) {
+    EncoderPass<__bf16> en;
+    en.carve(cv, enc, B);
+  } else {
+    EncoderPass<float> en;
+    en.carve(cv, enc, B);
+  }
+  *bytes = cv.off + 256;
+  return CROM_OK;
+}
+
+crom_status crom_encode(const crom_net* net, const crom_encoder* enc, const float* u, int32_t B, float* q, void* ws,
+                        size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  crom_status s = crom_encode_workspace(net, enc, B, &need);
+  if (s != CROM_OK) return s;
+  if (!u || !q || !ws) return fail(CROM_ERR_INVALID_ARG, "u, q and ws are required");
+  if (ws_bytes < need) return fail(CROM_ERR_WORKSPACE, "workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carve cv{reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255)), 0};
+  if (bf_mode(net)) {
+    EncoderPass<__bf16> en;
+    en.carve(cv, enc, B);
+    if ((s = encoder_fwd<__bf16>(enc, u, B, en, st)) != CROM_OK) return s;
+    return hip_check(hipMemcpyAsync(q, en.q, sizeof(float) * B * enc->r, hipMemcpyDeviceToDevice, st), "q copy");
+  }
+  EncoderPass<float> en;
+  en.carve(cv, enc, B);
+  if ((s = encoder_fwd<float>(enc, u, B, en, st)) != CROM_OK) return s;
+  return hip_check(hipMemcpyAsync(q, en.q, sizeof(float) * B * enc->r, hipMemcpyDeviceToDevice, st), "q copy");
 }
 
 crom_status crom_decode_vjp_workspace(const crom_net* net, int32_t B, int64_t P, size_t* bytes) {

@@ -1,0 +1,185 @@
+"""2D heat end to end on the GPU: full-order FP64 snapshots, decoder
+training, latent rollout and its error against the full-order solution.
+
+Every computation runs in the library (crom_fd_heat, crom_train_step,
+crom_encode, crom_step, crom_decode); this module only sequences the calls
+(Sec. "Manifold Construction" for the training data and loss, Sec. "Method:
+Latent Space Dynamics" for the rollout, the image-diffusion experiment's
+full-order model for the snapshots)."""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import crom
+
+
+def fd_snapshots(u0: np.ndarray, mus: Sequence[float], times: Sequence[float], dx: float, dt_fd: float,
+                 device="cuda") -> torch.Tensor:
+    """FP64 fields [n_mu, n_times, nx, ny] of u_t = mu Lap u from the shared
+    initial field u0 [nx, ny], recorded at `times` (multiples of dt_fd)."""
+    n_mu = len(mus)
+    u = torch.from_numpy(np.ascontiguousarray(u0, dtype=np.float64)).to(device)
+    u = u.unsqueeze(0).repeat(n_mu, 1, 1).contiguous()
+    nu = torch.as_tensor(np.asarray(mus, dtype=np.float64), device=device)
+    scratch = torch.empty_like(u)
+    out = torch.empty(n_mu, len(times), *u0.shape, dtype=torch.float64, device=device)
+    t_prev = 0
+    for k, t in enumerate(times):
+        steps = int(round(t / dt_fd))
+        if steps < t_prev:
+            raise ValueError("times must be non-decreasing")
+        crom.fd_heat(u, nu, dx, dt_fd, steps - t_prev, scratch)
+        out[:, k] = u
+        t_prev = steps
+    return out
+
+
+# Learning-rate schedule of Sec. "Training Details": 10, 5, 2, 1, 0.5 and
+# 0.2 times a base rate, in equal stages (the base rate 1e-4 makes the
+# first stage 1e-3).
+LR_STAGES = (10.0, 5.0, 2.0, 1.0, 0.5, 0.2)
+
+
+def lr_at(step: int, steps: int, base: float = 1e-4) -> float:
+    return base * LR_STAGES[min(len(LR_STAGES) - 1, step * len(LR_STAGES) // max(1, steps))]
+
+
+@dataclass
+class Standardization:
+    """Affine maps to the standardized training variables (Sec. "Training
+    Details"): u_s = (u - u_mean) / u_std over the whole training set,
+    x_s = (x - x_mean) / x_std per coordinate over the nodes."""
+    u_mean: float
+    u_std: float
+    x_mean: np.ndarray
+    x_std: np.ndarray
+
+    @classmethod
+    def of(cls, snaps: torch.Tensor, nodes: torch.Tensor) -> "Standardization":
+        u = snaps.to(torch.float64)
+        x = nodes.to(torch.float64)
+        return cls(float(u.mean()), float(u.std()), x.mean(dim=0).cpu().numpy(), x.std(dim=0).cpu().numpy())
+
+    def data(self, snaps: torch.Tensor) -> torch.Tensor:
+        return ((snaps.to(torch.float64) - self.u_mean) / self.u_std).to(torch.float32).contiguous()
+
+    def points(self, nodes: torch.Tensor) -> torch.Tensor:
+        xm = torch.as_tensor(self.x_mean, device=nodes.device)
+        xs = torch.as_tensor(self.x_std, device=nodes.device)
+        return ((nodes.to(torch.float64) - xm) / xs).to(torch.float32).contiguous()
+
+    def fold(self, dec: crom.Decoder, enc_params: torch.Tensor, n_in: int, hidden: int) -> None:
+        """Rewrite the trained decoder and encoder (in place, FP32) so that
+        they act on physical points and fields:  g(x, q) = u_std * g_s(x_s, q)
+        + u_mean and e(u) = e_s(u_s).  Exact up to rounding."""
+        m, r, w = dec.m, dec.r, dec.width
+        p = dec.params.detach()
+        with torch.no_grad():
+            W1 = p[: w * (m + r)].view(w, m + r)
+            b1 = p[w * (m + r): w * (m + r) + w]
+            xm = torch.as_tensor(self.x_mean, dtype=torch.float64, device=p.device)
+            xs = torch.as_tensor(self.x_std, dtype=torch.float64, device=p.device)
+            Wx = W1[:, :m].to(torch.float64)
+            b1.copy_((b1.to(torch.float64) - Wx @ (xm / xs)).to(torch.float32))
+            W1[:, :m].copy_((Wx / xs).to(torch.float32))
+            d = dec.d
+            out_w = p[p.numel() - d - d * w: p.numel() - d]
+            out_b = p[p.numel() - d:]
+            out_w.mul_(self.u_std)
+            out_b.copy_((out_b.to(torch.float64) * self.u_std + self.u_mean).to(torch.float32))
+            E1 = enc_params[: hidden * n_in].view(hidden, n_in)
+            c1 = enc_params[hidden * n_in: hidden * n_in + hidden]
+            c1.copy_((c1.to(torch.float64) - E1.to(torch.float64).sum(dim=1) * (self.u_mean / self.u_std))
+                     .to(torch.float32))
+            E1.div_(self.u_std)
+        dec.pack()
+
+
+def train(trainer: crom.Trainer, snaps: torch.Tensor, steps: int, base_lr: float = 1e-4, seed: int = 0,
+          log_every: int = 0) -> np.ndarray:
+    """Adam steps over shuffled batches of the snapshot rows snaps [N, P]
+    (FP32 on the device; each epoch is a seeded permutation, a short last
+    batch rolls into the next epoch), with the staged learning rate.
+    Returns the batch losses."""
+    gen = np.random.Generator(np.random.PCG64(seed))
+    N, B = snaps.shape[0], trainer.B
+    order = np.empty(0, dtype=np.int64)
+    losses = torch.empty(steps, dtype=torch.float32, device=snaps.device)
+    for s in range(steps):
+        if order.size < B:
+            order = np.concatenate([order, gen.permutation(N)])
+        idx, order = order[:B], order[B:]
+        batch = snaps[torch.from_numpy(idx).to(snaps.device)]
+        losses[s] = trainer.step(batch, lr_at(s, steps, base_lr))[0]
+        if log_every and (s + 1) % log_every == 0:
+            print(f"  train step {s + 1}: loss {losses[s].item():.3e}", flush=True)
+    return losses.cpu().numpy()
+
+
+@dataclass
+class Rollout:
+    steps: List[int]
+    q: List[np.ndarray]        # [n_inst, r] at each recorded step
+    flags: List[np.ndarray]    # OR of the step flags up to each recorded step
+    iters: float               # mean Gauss-Newton iterations per step
+
+
+def rollout(dec: crom.Decoder, q0: np.ndarray, y: np.ndarray, mus: Sequence[float], dt: float, n_steps: int,
+            opts: crom.GNOptions, record: Sequence[int]) -> Rollout:
+    """Latent steps for len(mus) instances sharing the samples y [S, m],
+    from q0 [n_inst, r]; records q after the steps listed in `record`."""
+    n = len(mus)
+    S = y.shape[0]
+    offsets = np.arange(n + 1, dtype=np.int64) * S
+    yy = torch.from_numpy(np.tile(np.asarray(y, np.float32), (n, 1))).to(dec.params.device)
+    st = crom.Stepper(dec, offsets, yy)
+    q = torch.from_numpy(np.asarray(q0, np.float64).reshape(n, dec.r)).to(dec.params.device)
+    q_next = torch.empty_like(q)
+    flags = np.zeros(n, dtype=np.int32)
+    out = Rollout([], [], [], 0.0)
+    rec = set(record)
+    iters = 0
+    if 0 in rec:
+        out.steps.append(0)
+        out.q.append(q.cpu().numpy())
+        out.flags.append(flags.copy())
+    for k in range(1, n_steps + 1):
+        st.step(q, mus, dt, opts, q_next)
+        q, q_next = q_next, q
+        if k in rec:
+            inf = st.info()
+            flags |= inf["flags"]
+            iters += int(inf["iters"].sum())
+            out.steps.append(k)
+            out.q.append(q.cpu().numpy())
+            out.flags.append(flags.copy())
+    out.iters = iters / max(1, len([k for k in out.steps if k > 0])) / n
+    return out
+
+
+def decode_fields(dec: crom.Decoder, nodes: torch.Tensor, q: np.ndarray) -> torch.Tensor:
+    """Decoded fields [n_inst, P] at the nodes for latents q [n_inst, r]."""
+    out = torch.empty(q.shape[0], nodes.shape[0], dtype=torch.float32, device=nodes.device)
+    for i in range(q.shape[0]):
+        dec.decode(nodes, torch.from_numpy(np.asarray(q[i], np.float64)), out=out[i].view(-1, 1))
+    return out
+
+
+def rel_error(approx: torch.Tensor, ref: torch.Tensor) -> np.ndarray:
+    """Relative L2 error per row: |approx - ref| / |ref|."""
+    a = approx.to(torch.float64)
+    r = ref.to(torch.float64).reshape(a.shape)
+    return ((a - r).norm(dim=1) / r.norm(dim=1)).cpu().numpy()
+
+
+def spacetime_error(approx: Sequence[torch.Tensor], ref: Sequence[torch.Tensor]) -> np.ndarray:
+    """Relative L2 error over a trajectory, per instance:
+    sqrt(sum_t |a_t - r_t|^2) / sqrt(sum_t |r_t|^2), for lists of [n_inst, P]."""
+    num = sum(((a.to(torch.float64) - r.to(torch.float64).reshape(a.shape)) ** 2).sum(dim=1)
+              for a, r in zip(approx, ref))
+    den = sum((r.to(torch.float64).reshape(a.shape) ** 2).sum(dim=1) for a, r in zip(approx, ref))
+    return (num.sqrt() / den.sqrt()).cpu().numpy()

@@ -1,0 +1,98 @@
+"""2D heat end to end on the GPU (GPU): FP64 finite-difference snapshots,
+decoder and encoder trained by the library's own kernels, latent rollouts
+judged by the FP64 finite-difference solution.
+
+* Gain of training: the trained network's rollout error (space-time relative
+  L2 over the recorded states) is a few percent, the untrained network's
+  (same architecture, same initial weights, no training) is about 100%.
+* Precision: rollouts of the same trained network with the FP32 and the
+  BF16 decoder arithmetic reach the same error (the rollout error is the
+  network's approximation error, far above either arithmetic's).
+The training here is shortened (a few thousand Adam steps) to keep the test
+quick; the full schedule is what the benchmark runs."""
+import numpy as np
+import pytest
+
+from workloads import Train2D
+
+pytestmark = pytest.mark.gpu
+
+TRAIN_STEPS = 8000
+
+
+@pytest.fixture(scope="module")
+def trained(cuda):
+    import torch
+    from paper_2206_02607_amd import crom, heat2d
+    w = Train2D()
+    u0 = w.initial_field()
+    snaps = heat2d.fd_snapshots(u0, w.mu, w.times, w.dx, w.dt_fd, cuda)
+    rows = snaps.reshape(-1, w.grid * w.grid)
+    nodes = torch.from_numpy(w.nodes).to(cuda)
+    sd = heat2d.Standardization.of(rows, nodes)
+    enc0 = np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in w.enc_layers]).astype(np.float32)
+    nets = {}
+    for name, steps in (("trained", TRAIN_STEPS), ("untrained", 0)):
+        dec = crom.Decoder.from_layers(w.layers, w.m, precision="bf16", device=cuda)
+        T = crom.Trainer(dec, enc0.copy(), w.enc_hidden, sd.points(nodes), w.batch)
+        losses = heat2d.train(T, sd.data(rows), steps, seed=1) if steps else None
+        sd.fold(dec, T.enc_params, T.n_in, T.hidden)
+        q0 = T.encode(torch.from_numpy(u0.astype(np.float32)).to(cuda).reshape(1, -1))
+        nets[name] = (dec, q0.cpu().numpy().astype(np.float64), losses)
+    mus = np.concatenate([w.mu_test, w.mu[:2]])
+    record = [0, 125, 250, 375, 500]
+    ref = heat2d.fd_snapshots(u0, mus, [k * w.dt for k in record], w.dx, w.dt_fd, cuda)
+    refs = [ref[:, k].reshape(len(mus), -1) for k in range(len(record))]
+    return w, nodes, nets, mus, record, refs, rows
+
+
+def _rollout_error(w, nodes, dec, q0, mus, record, refs, linearized):
+    from paper_2206_02607_amd import crom, heat2d
+    opts = crom.GNOptions(max_iter=5, linearized=linearized, tol_step=1e-6)
+    ro = heat2d.rollout(dec, np.tile(q0, (len(mus), 1)), w.nodes[w.sample_idx], mus, w.dt, record[-1], opts,
+                        record)
+    fields = [heat2d.decode_fields(dec, nodes, q) for q in ro.q]
+    return heat2d.spacetime_error(fields, refs), ro
+
+
+def test_training_converges(trained):
+    _, _, nets, _, _, _, _ = trained
+    losses = nets["trained"][2]
+    print("loss", losses[:50].mean(), losses[-50:].mean())
+    assert losses[-200:].mean() < 2e-3 * losses[:50].mean()
+
+
+def test_initial_field_reconstruction(trained):
+    """Decoding the encoder's latent of the initial field reproduces it to a
+    few percent (the encoder and decoder are used in physical units, after
+    the standardization was folded into their weights)."""
+    from paper_2206_02607_amd import heat2d
+    w, nodes, nets, _, _, _, rows = trained
+    dec, q0, _ = nets["trained"]
+    err = heat2d.rel_error(heat2d.decode_fields(dec, nodes, q0), rows[0:1])[0]
+    print("initial-field reconstruction", err)
+    assert err < 0.05
+
+
+@pytest.mark.parametrize("linearized", [0, 1])
+def test_trained_vs_untrained_rollout(trained, linearized):
+    w, nodes, nets, mus, record, refs, _ = trained
+    e_t, ro_t = _rollout_error(w, nodes, nets["trained"][0], nets["trained"][1], mus, record, refs, linearized)
+    e_u, _ = _rollout_error(w, nodes, nets["untrained"][0], nets["untrained"][1], mus, record, refs, linearized)
+    print("space-time rollout error: trained", e_t.round(4), "untrained", e_u.round(3), "GN iters", ro_t.iters)
+    assert np.all(np.isfinite(e_t))
+    assert e_t.max() < 0.08
+    assert e_u.min() > 0.5
+    assert e_t.max() < 0.1 * e_u.min()
+
+
+def test_bf16_and_fp32_reach_equal_rollout_error(trained):
+    from paper_2206_02607_amd import crom
+    w, nodes, nets, mus, record, refs, _ = trained
+    dec, q0, _ = nets["trained"]
+    errs = {}
+    for prec in ("fp32", "bf16"):
+        d = crom.Decoder(dec.params.detach().clone(), dec.m, dec.r, dec.d, dec.width, dec.depth, prec, nodes.device)
+        errs[prec], _ = _rollout_error(w, nodes, d, q0, mus, record, refs, 1)
+    print("LLS rollout error fp32", errs["fp32"].round(5), "bf16", errs["bf16"].round(5))
+    assert np.abs(errs["fp32"] - errs["bf16"]).max() < 0.1 * errs["fp32"].min()

@@ -222,3 +222,73 @@ class Batched2D:
         self.samples = np.concatenate(pts, axis=0).astype(np.float32)
         self.layers = xavier_mlp(g, self.m, self.r, self.d, self.width, self.depth)
         self.q0 = g.uniform(-1.0, 1.0, size=(self.n_inst, self.r))
+
+
+@dataclass
+class Train2D:
+    """Decoder training on 2D heat snapshots: unit square, 128 x 128 nodes,
+    n_mu = 40 training diffusivities mu ~ U(0.1, 1) (and 4 held-out ones),
+    one initial field shared by every mu, snapshots at 5 times in [0, 0.05]
+    (200 snapshots); encoder 16,384 -> 256 -> 8, decoder (x in R^2, q in R^8)
+    -> 5 ELU layers of width 128 -> 1; batches of 16 snapshots, Adam lr 1e-3.
+    The initial field is a window sin(pi x) sin(pi y) times a sum of Gaussian
+    bumps (centres in [0.25, 0.75]^2, widths U(0.06, 0.12), amplitudes
+    +-U(0.5, 1)), zero on the boundary.  The reduced-order rollout steps
+    with dt = 1e-4 at n_samples interior nodes drawn without replacement."""
+    seed: int = 0
+    grid: int = 128
+    n_mu: int = 40
+    n_mu_test: int = 4
+    times: Tuple[float, ...] = (0.0, 0.0125, 0.025, 0.0375, 0.05)
+    dt_fd: float = 1e-5
+    n_bumps: int = 4
+    batch: int = 16
+    lr: float = 1e-3
+    enc_hidden: int = 256
+    m: int = 2
+    r: int = 8
+    d: int = 1
+    width: int = 128
+    depth: int = 5
+    dt: float = 1e-4
+    n_samples: int = 500
+    mu: np.ndarray = field(init=False)
+    mu_test: np.ndarray = field(init=False)
+    centres: np.ndarray = field(init=False)
+    widths: np.ndarray = field(init=False)
+    amps: np.ndarray = field(init=False)
+    layers: List[Layer] = field(init=False)
+    enc_layers: List[Layer] = field(init=False)
+    sample_idx: np.ndarray = field(init=False)
+
+    def __post_init__(self):
+        g = rng(self.seed)
+        self.mu = g.uniform(0.1, 1.0, size=self.n_mu)
+        self.mu_test = g.uniform(0.1, 1.0, size=self.n_mu_test)
+        self.centres = g.uniform(0.25, 0.75, size=(self.n_bumps, 2))
+        self.widths = g.uniform(0.06, 0.12, size=self.n_bumps)
+        self.amps = g.uniform(0.5, 1.0, size=self.n_bumps) * g.choice([-1.0, 1.0], size=self.n_bumps)
+        self.layers = xavier_mlp(g, self.m, self.r, self.d, self.width, self.depth)
+        self.enc_layers = xavier_mlp(g, self.grid * self.grid, 0, self.r, self.enc_hidden, 1)
+        n_int = (self.grid - 2) ** 2
+        idx = g.choice(n_int, size=self.n_samples, replace=False)
+        self.sample_idx = np.sort((1 + idx // (self.grid - 2)) * self.grid + 1 + idx % (self.grid - 2))
+
+    @property
+    def nodes(self) -> np.ndarray:
+        return grid_points_2d(self.grid, self.grid)
+
+    @property
+    def dx(self) -> float:
+        return 1.0 / (self.grid - 1)
+
+    def initial_field(self) -> np.ndarray:
+        """The initial field on the nodes, [grid, grid] float64 (index [i_x][i_y])."""
+        xs = np.linspace(0.0, 1.0, self.grid)
+        X, Y = np.meshgrid(xs, xs, indexing="ij")
+        u = np.zeros_like(X)
+        for (cx, cy), w, a in zip(self.centres, self.widths, self.amps):
+            u += a * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2.0 * w * w))
+        u *= np.sin(np.pi * X) * np.sin(np.pi * Y)
+        u[0, :] = u[-1, :] = u[:, 0] = u[:, -1] = 0.0
+        return u
