@@ -16,6 +16,14 @@ gradient entries, Laplacian, 8 latent-Jacobian entries; 1,576,448
 algorithmic FLOP) and the step's algorithmic decoder work is counted in
 that unit.  latent_steps_per_s is reported beside it.
 
+Beside it: the linearised inversion's steps/s on the same rollout; the
+decoder training step (16 snapshots x 16,384 points, encoder 16,384 -> 256
+-> 8) timed in BF16 and FP32, then a BF16 training run on FP64
+finite-difference snapshots; the batched rollout of 512 instances with that
+trained network in BF16 and FP32 arithmetic, with the rollout error of a
+subset judged by the FP64 finite-difference solver (the BF16-vs-FP32
+speedup at equal rollout error); and the FP64 oracle timed on the host.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec bf16|fp32|bf16x3|bf16pure]
 """
 from __future__ import annotations
@@ -71,45 +79,156 @@ def cpu_baseline(wl, nodes, n_steps: int):
             "latent_steps_per_s": n_steps / dt}
 
 
-def batched_leg(args, crom, torch, dev):
+def train_flops(B: int, P: int, m: int, r: int, d: int, width: int, depth: int, n_in: int, hidden: int) -> float:
+    """Algorithmic FLOP of one training step (forward, backward; Adam and the
+    loss are O(parameters) and O(B P) and left out): every multiply-add of the
+    decoder at B * P points and of the encoder on B snapshots, counted once."""
+    rows = B * P
+    hid = (depth - 1) * width * width
+    dec_fwd = rows * (m * width + hid + width * d) + B * r * width
+    dec_bwd = rows * (2 * width * d + 2 * hid + m * width) + B * r * width
+    enc = B * (n_in * hidden + hidden * r) + B * (hidden * r + r * hidden + n_in * hidden)
+    return 2.0 * (dec_fwd + dec_bwd + enc)
+
+
+def train_leg(args, crom, torch, dev):
+    """Decoder training (16 x 16,384-point batches of 2D heat snapshots from
+    the FP64 finite-difference solver; encoder 16,384 -> 256 -> 8): the
+    training step timed in BF16 and FP32, then a BF16 training run of
+    --train-steps steps whose network the batched leg uses."""
+    from paper_2206_02607_amd import heat2d
+    from workloads import Train2D
+    w = Train2D(seed=args.seed)
+    u0 = w.initial_field()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e[0].record()
+    snaps = heat2d.fd_snapshots(u0, w.mu, w.times, w.dx, w.dt_fd, dev)
+    e[1].record()
+    torch.cuda.synchronize()
+    rows = snaps.reshape(-1, w.grid * w.grid)
+    nodes = torch.from_numpy(w.nodes).to(dev)
+    sd = heat2d.Standardization.of(rows, nodes)
+    data, xs = sd.data(rows), sd.points(nodes)
+    enc0 = np.concatenate([np.concatenate([Wm.ravel(), b.ravel()]) for Wm, b in w.enc_layers]).astype(np.float32)
+    P = w.grid * w.grid
+    fl = train_flops(w.batch, P, w.m, w.r, w.d, w.width, w.depth, P * w.d, w.enc_hidden)
+    out = {"workload": f"{w.n_mu} diffusivities x {len(w.times)} times = {rows.shape[0]} FP64 snapshots of "
+                       f"{w.grid}x{w.grid} nodes; batch {w.batch} snapshots ({w.batch * P} decoder points); "
+                       f"encoder {P}->{w.enc_hidden}->{w.r}",
+           "fd_snapshots_ms": e[0].elapsed_time(e[1]), "flop_per_step": fl}
+
+    def make(prec):
+        dec = crom.Decoder.from_layers(w.layers, w.m, precision=prec, device=dev)
+        return dec, crom.Trainer(dec, enc0.copy(), w.enc_hidden, xs, w.batch)
+
+    for prec in ("bf16", "fp32"):
+        dec, T = make(prec)
+        for _ in range(3):
+            T.step(data[:w.batch], 1e-4)
+        torch.cuda.synchronize()
+        e[0].record()
+        for k in range(args.train_time_steps):
+            T.step(data[(k % 12) * w.batch:(k % 12 + 1) * w.batch], 1e-4)
+        e[1].record()
+        torch.cuda.synchronize()
+        t = e[0].elapsed_time(e[1]) * 1e-3 / args.train_time_steps
+        out[prec] = {"ms_per_step": t * 1e3, "steps_per_s": 1.0 / t, "achieved_tflops": fl / t / 1e12,
+                     "frac_of_peak": fl / t / 1e12 / PEAK[prec]}
+    if args.train_steps <= 0:
+        return out, None
+    dec, T = make("bf16")
+    t0 = time.perf_counter()
+    losses = heat2d.train(T, data, args.train_steps, seed=1)
+    torch.cuda.synchronize()
+    out["run"] = {"steps": args.train_steps, "seconds": time.perf_counter() - t0,
+                  "loss_first50": float(losses[:50].mean()), "loss_last50": float(losses[-50:].mean()),
+                  "schedule": "lr = 1e-4 x (10, 5, 2, 1, 0.5, 0.2) in equal stages, standardized data"}
+    sd.fold(dec, T.enc_params, T.n_in, T.hidden)
+    q0 = T.encode(torch.from_numpy(u0.astype(np.float32)).to(dev).reshape(1, -1)).cpu().numpy()[0]
+    err0 = heat2d.rel_error(heat2d.decode_fields(dec, nodes, q0[None].astype(np.float64)),
+                            torch.from_numpy(u0).to(dev).reshape(1, -1))[0]
+    out["run"]["initial_field_error"] = float(err0)
+    return out, {"params": dec.params.detach().clone(), "q0": q0.astype(np.float64), "w": w, "u0": u0,
+                 "nodes": nodes}
+
+
+def batched_leg(args, crom, torch, dev, trained=None):
     """Batched rollout: 512 instances of 2D heat, mu_i ~ U(0.1, 1), sample
     counts S_i ~ U{200..2000} drawn without replacement from the interior
     nodes of a 128 x 128 lattice, r = 8, dt = 1e-4; all instances advance
     together in one step launch.  Gauss-Newton (5 iterations, tol 1e-6) and
-    the linearised inversion are timed separately."""
+    the linearised inversion are timed separately.  With a trained network
+    (the training leg's) every instance starts from the encoded initial field,
+    both BF16 and FP32 decoder arithmetic are timed, and the rollout error of
+    the first --judge instances over 500 steps is measured against the FP64
+    finite-difference solution (space-time relative L2 at 5 recorded states)."""
+    from paper_2206_02607_amd import heat2d
     from workloads import Batched2D
     wb = Batched2D(seed=args.seed)
-    dec = crom.Decoder.from_layers(wb.layers, wb.m, precision=args.prec, device=dev)
-    st = crom.Stepper(dec, wb.offsets, torch.from_numpy(wb.samples).to(dev))
-    nu = torch.from_numpy(wb.mu).to(dev)
-    out = {"workload": f"{wb.n_inst} instances, S_i in [{wb.s_min},{wb.s_max}], total samples "
-                       f"{int(wb.offsets[-1])}", "steps": args.batched_steps}
+    params = trained["params"] if trained else crom.flatten_layers(wb.layers)
+    q_init = np.tile(trained["q0"], (wb.n_inst, 1)) if trained else wb.q0
     total = int(wb.offsets[-1])
-    for name, opts in (("gn", crom.GNOptions(max_iter=5, tol_step=TOL_STEP)),
-                       ("lls", crom.GNOptions(max_iter=1, linearized=True))):
-        q = [torch.from_numpy(wb.q0.copy()).to(dev), torch.empty(wb.n_inst, R, dtype=torch.float64, device=dev)]
-        for i in range(3):
-            st.step(q[i % 2], nu, wb.dt, opts, q_next=q[(i + 1) % 2])
+    out = {"workload": f"{wb.n_inst} instances, S_i in [{wb.s_min},{wb.s_max}], total samples {total}",
+           "net": "trained (training leg)" if trained else "Xavier-uniform, untrained",
+           "steps": args.batched_steps}
+    nu = torch.from_numpy(wb.mu).to(dev)
+    record = [0, 125, 250, 375, 500]
+    nj = min(args.judge, wb.n_inst) if trained else 0
+    if nj:
+        w = trained["w"]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        ref = heat2d.fd_snapshots(trained["u0"], wb.mu[:nj], [k * wb.dt for k in record], w.dx, w.dt_fd, dev)
+        e[1].record()
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        flop = 0.0
-        infos = []
-        e0.record()
-        for i in range(args.batched_steps):
-            st.step(q[i % 2], nu, wb.dt, opts, q_next=q[(i + 1) % 2])
-        e1.record()
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) * 1e-3 / args.batched_steps
-        inf = st.info()  # iteration counts of the last step stand for all
-        flop = sum(step_flops(int(wb.offsets[k + 1] - wb.offsets[k]), int(inf["iters"][k]),
-                              int(inf["ls_evals"][k])) for k in range(wb.n_inst))
-        if opts.linearized:
-            flop = total * (FLOP_POINT_EVAL)
-        achieved = flop / t / 1e12
-        out[name] = {"ms_per_step": t * 1e3, "instance_steps_per_s": wb.n_inst / t,
-                     "point_evals_per_s": flop / FLOP_POINT_EVAL / t,
-                     "achieved_tflops": achieved, "frac_of_peak": achieved / PEAK[args.prec],
-                     "gn_iters_mean": float(inf["iters"].mean()), "ls_evals_mean": float(inf["ls_evals"].mean())}
+        refs = [ref[:, k].reshape(nj, -1) for k in range(len(record))]
+        out["fd_judge"] = {"instances": nj, "ms": e[0].elapsed_time(e[1]),
+                           "substeps": int(round(record[-1] * wb.dt / w.dt_fd))}
+    precs = (args.prec, "fp32") if trained and args.prec != "fp32" else (args.prec,)
+    for prec in precs:
+        dec = crom.Decoder(params, wb.m, wb.r, wb.d, wb.width, wb.depth, prec, dev)
+        st = crom.Stepper(dec, wb.offsets, torch.from_numpy(wb.samples).to(dev))
+        res = {}
+        for name, opts in (("gn", crom.GNOptions(max_iter=5, tol_step=TOL_STEP)),
+                           ("lls", crom.GNOptions(max_iter=1, linearized=True))):
+            q = [torch.from_numpy(np.asarray(q_init, np.float64).copy()).to(dev),
+                 torch.empty(wb.n_inst, R, dtype=torch.float64, device=dev)]
+            for i in range(3):
+                st.step(q[i % 2], nu, wb.dt, opts, q_next=q[(i + 1) % 2])
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(args.batched_steps):
+                st.step(q[i % 2], nu, wb.dt, opts, q_next=q[(i + 1) % 2])
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3 / args.batched_steps
+            inf = st.info()  # iteration counts of the last step stand for all
+            flop = sum(step_flops(int(wb.offsets[k + 1] - wb.offsets[k]), int(inf["iters"][k]),
+                                  int(inf["ls_evals"][k])) for k in range(wb.n_inst))
+            if opts.linearized:
+                flop = total * FLOP_POINT_EVAL
+            achieved = flop / t / 1e12
+            r = {"ms_per_step": t * 1e3, "instance_steps_per_s": wb.n_inst / t,
+                 "point_evals_per_s": flop / FLOP_POINT_EVAL / t,
+                 "achieved_tflops": achieved, "frac_of_peak": achieved / PEAK[prec],
+                 "gn_iters_mean": float(inf["iters"].mean()), "ls_evals_mean": float(inf["ls_evals"].mean())}
+            if nj:
+                ro = heat2d.rollout(dec, np.tile(trained["q0"], (nj, 1)), wb.samples[:int(wb.offsets[nj])],
+                                    wb.mu[:nj], wb.dt, record[-1], opts, record, offsets=wb.offsets[:nj + 1])
+                fields = [heat2d.decode_fields(dec, trained["nodes"], qq) for qq in ro.q]
+                err = heat2d.spacetime_error(fields, refs)
+                r["rollout_error_mean"] = float(err.mean())
+                r["rollout_error_max"] = float(err.max())
+            res[name] = r
+        out[prec] = res
+    if len(precs) == 2:
+        a, b = precs
+        out["precision_study"] = {
+            name: {"speedup_" + a + "_vs_fp32": out[b][name]["ms_per_step"] / out[a][name]["ms_per_step"],
+                   "rollout_error_" + a: out[a][name].get("rollout_error_mean"),
+                   "rollout_error_fp32": out[b][name].get("rollout_error_mean")}
+            for name in ("gn", "lls")}
     return out
 
 
@@ -122,6 +241,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--batched-steps", type=int, default=20)
+    ap.add_argument("--train-time-steps", type=int, default=50)
+    ap.add_argument("--train-steps", type=int, default=8000,
+                    help="BF16 training run whose network the batched leg rolls out (0: untrained)")
+    ap.add_argument("--judge", type=int, default=8, help="instances whose rollout error the FD solver judges")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU: the instances of a batch are independent and the "
@@ -207,7 +330,8 @@ def main():
     torch.cuda.synchronize()
     lls_steps_per_s = args.steps / (time.perf_counter() - t1)
 
-    batched = batched_leg(args, crom, torch, dev) if args.batched_steps > 0 else None
+    training, trained = train_leg(args, crom, torch, dev) if args.train_time_steps > 0 else (None, None)
+    batched = batched_leg(args, crom, torch, dev, trained) if args.batched_steps > 0 else None
     cpu = cpu_baseline(wl, nodes, args.cpu_steps) if args.cpu_steps > 0 else None
     its = np.array([int(i["iters"]) for i in infos])
     lse = np.array([int(i["ls_evals"]) for i in infos])
@@ -227,6 +351,7 @@ def main():
         "step_ms_avg": t_step.mean() * 1e3, "decode_ms_avg": t_dec.mean() * 1e3,
         "gn_iters_mean": float(its.mean()), "ls_evals_mean": float(lse.mean()),
         "roofline": roof,
+        "training": training,
         "batched": batched,
         "cpu_baseline": cpu,
     }

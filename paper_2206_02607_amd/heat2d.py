@@ -129,14 +129,17 @@ class Rollout:
 
 
 def rollout(dec: crom.Decoder, q0: np.ndarray, y: np.ndarray, mus: Sequence[float], dt: float, n_steps: int,
-            opts: crom.GNOptions, record: Sequence[int]) -> Rollout:
-    """Latent steps for len(mus) instances sharing the samples y [S, m],
-    from q0 [n_inst, r]; records q after the steps listed in `record`."""
+            opts: crom.GNOptions, record: Sequence[int], offsets: Optional[np.ndarray] = None) -> Rollout:
+    """Latent steps for len(mus) instances from q0 [n_inst, r]; records q
+    after the steps listed in `record`.  Samples: y [S, m] shared by every
+    instance, or with `offsets` [n_inst + 1] the CSR rows of y per instance."""
     n = len(mus)
-    S = y.shape[0]
-    offsets = np.arange(n + 1, dtype=np.int64) * S
-    yy = torch.from_numpy(np.tile(np.asarray(y, np.float32), (n, 1))).to(dec.params.device)
-    st = crom.Stepper(dec, offsets, yy)
+    if offsets is None:
+        S = y.shape[0]
+        offsets = np.arange(n + 1, dtype=np.int64) * S
+        y = np.tile(np.asarray(y, np.float32), (n, 1))
+    yy = torch.from_numpy(np.asarray(y, np.float32)).to(dec.params.device)
+    st = crom.Stepper(dec, np.asarray(offsets, np.int64), yy)
     q = torch.from_numpy(np.asarray(q0, np.float64).reshape(n, dec.r)).to(dec.params.device)
     q_next = torch.empty_like(q)
     flags = np.zeros(n, dtype=np.int32)
