@@ -137,11 +137,21 @@ crom_status crom_decode_jac_q(const crom_net* net, const float* x, int64_t P, co
  * Latent step for a batch of independent instances.
  * ------------------------------------------------------------------------- */
 
-enum { CROM_PDE_HEAT = 0 };
+enum { CROM_PDE_HEAT = 0, CROM_PDE_NEOHOOKEAN = 1 };
 
-/* PDE of the instances.  HEAT: u_t = nu * Laplacian(u) with forward Euler,
- * f_{n+1}(y) = g(y, q_n) + dt * nu * Laplacian_x g(y, q_n); coef = nu
- * [n_inst] FP64 (device).  Needs d == 1. */
+/* PDE of the instances.
+ * HEAT: u_t = nu * Laplacian(u) with forward Euler,
+ *   f_{n+1}(y) = g(y, q_n) + dt * nu * Laplacian_x g(y, q_n); coef = nu
+ *   [n_inst] FP64 (device).  Needs d == 1.
+ * NEOHOOKEAN: elastodynamics rho0 phi_tt = div P(F) + rho0 B of the
+ *   displacement u = g(X, q) (phi = X + u, Sec. "Solid Mechanics"), with
+ *   F = I + du/dX, P = mu (F - F^-T) + lam ln(det F) F^-T, div P taken
+ *   through the decoder's x-Hessian, the velocity from the tangent space
+ *   v_n = (dg/dq)(q_n - q_prev)/dt (q_prev NULL: at rest), and symplectic
+ *   Euler at the samples: v+ = v_n + dt (div P / rho0 + B), target
+ *   u+ = u + dt v+.  coef [n_inst][6] FP64 = lam, mu, rho0, Bx, By, Bz.
+ *   Needs m == 3 and d == 3 (the (3, 16, 3, 256) decoder).  A sample with
+ *   det F <= 0 makes its instance NONFINITE. */
 typedef struct {
   int32_t kind, _pad;
   double dt;
@@ -198,6 +208,8 @@ crom_status crom_step_workspace(const crom_net* net, int32_t n_inst, int64_t tot
  *                             instance needs r <= d * S_i samples)
  *   y       [total_samples][m] FP32 sample points
  *   clamp   NULL or [total_samples] uint8: 1 = Dirichlet sample, target 0
+ *   q_prev  NEOHOOKEAN: NULL or [n_inst][r] FP64, the previous step's latent
+ *           (ignored for HEAT)
  *   q_n     [n_inst][r] FP64;  q_next [n_inst][r] FP64 out (must not alias q_n)
  *   info    [n_inst] crom_step_info out
  *   ws      workspace of at least crom_step_workspace bytes, 256-byte aligned
@@ -206,7 +218,7 @@ crom_status crom_step_workspace(const crom_net* net, int32_t n_inst, int64_t tot
  * instance's q_next holds the last accepted iterate. */
 crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
                       const int64_t* offsets, int64_t total_samples, const float* y,
-                      const uint8_t* clamp, const double* q_n, double* q_next,
+                      const uint8_t* clamp, const double* q_prev, const double* q_n, double* q_next,
                       const crom_gn_opts* opts, crom_step_info* info, void* ws, size_t ws_bytes,
                       void* stream);
 
@@ -214,6 +226,13 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
  * workspace used by crom_step (NULL on invalid arguments). */
 const double* crom_step_targets(const crom_net* net, int32_t n_inst, int64_t total_samples,
                                 const void* ws);
+
+/* Device pointer to the FP64 increments rho_0 = f_{n+1} - g(q_n)
+ * [total_samples][d] of the last crom_step in this workspace, formed
+ * directly (heat: dt nu Laplacian g; neo-Hookean: dt v_{n+1}; a clamped
+ * sample: -g).  NULL on invalid arguments. */
+const double* crom_step_increments(const crom_net* net, int32_t n_inst, int64_t total_samples,
+                                   const void* ws);
 
 /* ---------------------------------------------------------------------------
  * Full-order FP64 finite-difference heat solver: the snapshot generator, the

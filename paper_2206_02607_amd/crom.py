@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libcrom.so")
 
 PREC_FP32, PREC_BF16, PREC_BF16_PURE, PREC_BF16X3 = 0, 1, 2, 3
 D2_NONE, D2_LAPLACIAN, D2_HESSIAN = 0, 1, 2
-PDE_HEAT = 0
+PDE_HEAT, PDE_NEOHOOKEAN = 0, 1
 FLAG_MAXITER, FLAG_SINGULAR, FLAG_NONFINITE, FLAG_LS_FAIL, FLAG_ABORTED = 1, 2, 4, 8, 16
 _PREC_NAMES = {"fp32": PREC_FP32, "bf16": PREC_BF16, "bf16pure": PREC_BF16_PURE, "bf16x3": PREC_BF16X3}
 
@@ -80,8 +80,10 @@ def lib():
         L.crom_step_workspace.argtypes = [POINTER(CromNet), c_int32, c_int64, POINTER(c_size_t)]
         L.crom_step_targets.restype = c_void_p
         L.crom_step_targets.argtypes = [POINTER(CromNet), c_int32, c_int64, c_void_p]
+        L.crom_step_increments.restype = c_void_p
+        L.crom_step_increments.argtypes = [POINTER(CromNet), c_int32, c_int64, c_void_p]
         L.crom_step.argtypes = [POINTER(CromNet), POINTER(CromPDE), c_int32, c_void_p, c_int64,
-                                c_void_p, c_void_p, c_void_p, c_void_p, POINTER(CromGNOpts),
+                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(CromGNOpts),
                                 c_void_p, c_void_p, c_size_t, c_void_p]
         L.crom_fd_heat.argtypes = [c_int32, POINTER(c_int64), c_int64, c_void_p, c_int32, c_double,
                                    c_double, c_int64, c_void_p, c_void_p, c_void_p]
@@ -392,9 +394,10 @@ class Stepper:
     """Reusable latent-step launcher for a fixed batch layout (instances,
     CSR sample offsets, sample points): owns the workspace."""
 
-    def __init__(self, dec: Decoder, offsets, y, clamp=None):
+    def __init__(self, dec: Decoder, offsets, y, clamp=None, pde: str = "heat"):
         torch = _torch()
         self.dec = dec
+        self.kind = {"heat": PDE_HEAT, "neohookean": PDE_NEOHOOKEAN}[pde]
         off = torch.as_tensor(offsets, dtype=torch.int64)
         self.n_inst = int(off.numel() - 1)
         self.total = int(off[-1].item())
@@ -414,36 +417,50 @@ class Stepper:
         self.info_buf = torch.zeros(self.n_inst * INFO_DTYPE.itemsize, dtype=torch.uint8,
                                     device=dec.params.device)
 
-    def step(self, q_n, nu, dt: float, opts: GNOptions = GNOptions(), q_next=None):
+    def step(self, q_n, coef, dt: float, opts: GNOptions = GNOptions(), q_next=None, q_prev=None):
+        """One latent step.  coef: heat, nu (one value or one per instance);
+        neo-Hookean, (lam, mu, rho0, Bx, By, Bz) (one row or one per
+        instance).  q_prev: neo-Hookean, the previous latents (None: at rest)."""
         torch = _torch()
         dev = self.dec.params.device
         q_n = q_n.to(device=dev, dtype=torch.float64).contiguous()
-        nu = torch.as_tensor(nu, dtype=torch.float64, device=dev).reshape(-1).expand(self.n_inst).contiguous()
+        per = 1 if self.kind == PDE_HEAT else 6
+        coef = torch.as_tensor(coef, dtype=torch.float64, device=dev).reshape(-1, per)
+        coef = coef.expand(self.n_inst, per).contiguous()
+        if q_prev is not None:
+            q_prev = q_prev.to(device=dev, dtype=torch.float64).contiguous()
         if q_next is None:
             q_next = torch.empty_like(q_n)
         net = self.dec._net()
-        pde = CromPDE(PDE_HEAT, 0, float(dt), nu.data_ptr())
+        pde = CromPDE(self.kind, 0, float(dt), coef.data_ptr())
         o = opts.c_struct()
-        self._nu = nu  # keep alive until the stream has consumed it
+        self._coef, self._q_prev = coef, q_prev  # keep alive until the stream has consumed them
         _check(lib().crom_step(ctypes.byref(net), ctypes.byref(pde), self.n_inst, _ptr(self.offsets),
-                               self.total, _ptr(self.y), _ptr(self.clamp), _ptr(q_n), _ptr(q_next),
-                               ctypes.byref(o), self.info_buf.data_ptr(), self.ws_ptr, self.ws_bytes,
-                               _stream()), "crom_step")
+                               self.total, _ptr(self.y), _ptr(self.clamp), _ptr(q_prev), _ptr(q_n),
+                               _ptr(q_next), ctypes.byref(o), self.info_buf.data_ptr(), self.ws_ptr,
+                               self.ws_bytes, _stream()), "crom_step")
         return q_next
 
     def info(self) -> np.ndarray:
         """Per-instance outcome of the last step (synchronises)."""
         return np.frombuffer(self.info_buf.cpu().numpy().tobytes(), dtype=INFO_DTYPE)
 
-    def targets(self):
-        """FP64 targets f_{n+1} [total, d] of the last step (a view into the workspace)."""
+    def _ws_view(self, fn):
         torch = _torch()
         n = self.total * self.dec.d
         off = self.ws_ptr - self.ws.data_ptr()
         net = self.dec._net()
-        p = lib().crom_step_targets(ctypes.byref(net), self.n_inst, self.total, c_void_p(self.ws_ptr))
+        p = fn(ctypes.byref(net), self.n_inst, self.total, c_void_p(self.ws_ptr))
         start = off + (p - self.ws_ptr)
         return self.ws[start:start + 8 * n].view(torch.float64).reshape(self.total, self.dec.d)
+
+    def targets(self):
+        """FP64 targets f_{n+1} [total, d] of the last step (a view into the workspace)."""
+        return self._ws_view(lib().crom_step_targets)
+
+    def increments(self):
+        """FP64 increments rho_0 = f_{n+1} - g(q_n) [total, d] of the last step (a view)."""
+        return self._ws_view(lib().crom_step_increments)
 
 
 def fd_heat(u, nu, dx: float, dt: float, steps: int, scratch=None):

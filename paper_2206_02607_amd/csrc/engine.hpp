@@ -87,16 +87,15 @@ struct Cols {
          : c < Q0 ? (D2_ == D2_LAP ? CK_LAP : CK_HESS)
                   : CK_QT;
   }
-  // Hessian column c -> (i, j) of the upper triangle i <= j (row-major).
+  // Hessian column c -> (i, j) of the upper triangle i <= j (row-major),
+  // in closed form for m <= 3 (rows start at 0, m, 2m - 1), so that an
+  // unrolled loop index folds to a constant register index.
+  static_assert(M_ <= 3, "Hessian entry map written for m <= 3");
   __host__ __device__ static constexpr int hess_i(int c) {
-    int k = c - D0 + HB_, i = 0, n = M_;
-    while (k >= n) { k -= n; ++i; --n; }
-    return i;
+    return (c - D0 + HB_) < M_ ? 0 : ((c - D0 + HB_) < 2 * M_ - 1 ? 1 : 2);
   }
   __host__ __device__ static constexpr int hess_j(int c) {
-    int k = c - D0 + HB_, i = 0, n = M_;
-    while (k >= n) { k -= n; ++i; --n; }
-    return i + k;
+    return hess_i(c) + (c - D0 + HB_) - (hess_i(c) == 0 ? 0 : (hess_i(c) == 1 ? M_ : 2 * M_ - 1));
   }
 };
 
@@ -201,12 +200,17 @@ struct Engine {
   // Prefetch the next layer's weight fragments while computing this one,
   // unless the two register sets would crowd out the accumulators.
   static constexpr int FRAG_REGS = MT * KQ * 4 * (NSPL > 0 ? 2 : 1);
-  static constexpr bool PREFETCH = PF >= 0 ? PF == 1 : 2 * FRAG_REGS + MT * NT * 4 <= 320;
+  // A layer's fragments beyond 64 registers (width 256) are streamed: each
+  // K-block's fragments are loaded one block ahead of their products
+  // instead of holding the whole layer.
+  static constexpr bool STREAM = FRAG_REGS > 64;
+  static constexpr bool PREFETCH = !STREAM && (PF >= 0 ? PF == 1 : 2 * FRAG_REGS + MT * NT * 4 <= 320);
   static constexpr int TG = 4;  // operand loads allowed to run ahead of their products
 
+  static constexpr int KH = STREAM ? 1 : KQ;  // fragments held per layer
   struct Frags {
-    AFrag hi[MT][KQ];
-    AFrag lo[MT][NLO];
+    AFrag hi[MT][KH];
+    AFrag lo[MT][STREAM ? 1 : NLO];
   };
 
   static __host__ __device__ constexpr int lo_tile(int b, int c) {
@@ -215,6 +219,7 @@ struct Engine {
 
   static __device__ __forceinline__ void load_frags(Frags& f, const char* __restrict__ packed, int h,
                                                     int wave, int lane) {
+    if constexpr (STREAM) return;
     const AFrag* wf = reinterpret_cast<const AFrag*>(packed + (size_t)h * Packing<S, PREC>::LAYER_BYTES);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -391,16 +396,46 @@ struct Engine {
         acc[mt][t] = isval ? bv : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
       }
     }
+    // streamed fragments: sh/sl hold K-block kb, nh/nl the next one
+    const AFrag* wfs = reinterpret_cast<const AFrag*>(packed + (size_t)h * Packing<S, PREC>::LAYER_BYTES);
+    constexpr int LO = MTILES * KQ * 64;
+    AFrag sh[MT], sl[MT], nh[MT], nl[MT];
+    if constexpr (STREAM) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        sh[mt] = wfs[((wave * MT + mt) * KQ + 0) * 64 + lane];
+        if constexpr (NSPL > 0) sl[mt] = wfs[LO + ((wave * MT + mt) * KQ + 0) * 64 + lane];
+      }
+    }
+#define CROM_FRAG_HI(mt, kb) (STREAM ? sh[mt] : cur.hi[mt][(kb) % KH])
+#define CROM_FRAG_LO(mt, kb) (STREAM ? sl[mt] : cur.lo[mt][(kb) % KH])
+#define CROM_STREAM_NEXT(kb)                                                                     \
+    if constexpr (STREAM) {                                                                      \
+      if ((kb) + 1 < KQ) {                                                                       \
+        _Pragma("unroll") for (int mt = 0; mt < MT; ++mt) {                                      \
+          nh[mt] = wfs[((wave * MT + mt) * KQ + (kb) + 1) * 64 + lane];                          \
+          if constexpr (NSPL > 0) nl[mt] = wfs[LO + ((wave * MT + mt) * KQ + (kb) + 1) * 64 + lane]; \
+        }                                                                                        \
+      }                                                                                          \
+    }
+#define CROM_STREAM_SHIFT()                                                                      \
+    if constexpr (STREAM) {                                                                      \
+      _Pragma("unroll") for (int mt = 0; mt < MT; ++mt) {                                        \
+        sh[mt] = nh[mt];                                                                         \
+        if constexpr (NSPL > 0) sl[mt] = nl[mt];                                                 \
+      }                                                                                          \
+    }
     if constexpr (PREC == PREC_FP32) {
       const f32x4* act = reinterpret_cast<const f32x4*>(lds);
 #pragma unroll
       for (int kq = 0; kq < KQ; ++kq) {
+        CROM_STREAM_NEXT(kq)
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const f32x4 bfr = act[(t * KQ + kq) * 64 + lane];
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
-            const f32x4 a = cur.hi[mt][kq];
+            const f32x4 a = CROM_FRAG_HI(mt, kq);
             acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], bfr[0], acc[mt][t], 0, 0, 0);
             acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], bfr[1], acc[mt][t], 0, 0, 0);
             acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], bfr[2], acc[mt][t], 0, 0, 0);
@@ -411,17 +446,19 @@ struct Engine {
         // keep the next k-block's operand loads from being hoisted above this
         // one's products: hoisting all of them would exhaust the registers
         __builtin_amdgcn_sched_barrier(0);
+        CROM_STREAM_SHIFT()
       }
     } else {
       const bf16x8* act = reinterpret_cast<const bf16x8*>(lds);
 #pragma unroll
       for (int kb = 0; kb < KQ; ++kb) {
+        CROM_STREAM_NEXT(kb)
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const bf16x8 bfr = act[(t * KQ + kb) * 64 + lane];
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt)
-            acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.hi[mt][kb], bfr, acc[mt][t], 0, 0, 0);
+            acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(CROM_FRAG_HI(mt, kb), bfr, acc[mt][t], 0, 0, 0);
           if ((t + 1) % TG == 0) __builtin_amdgcn_sched_barrier(0);  // bound the run-ahead
         }
         if constexpr (NSPL > 0) {
@@ -435,15 +472,20 @@ struct Engine {
               const bf16x8 bl = act[(lo_tile(b, c) * KQ + kb) * 64 + lane];
 #pragma unroll
               for (int mt = 0; mt < MT; ++mt) {
-                acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.hi[mt][kb], bl, acc[mt][t], 0, 0, 0);
-                acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.lo[mt][kb], bh, acc[mt][t], 0, 0, 0);
+                acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(CROM_FRAG_HI(mt, kb), bl, acc[mt][t], 0, 0, 0);
+                acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(CROM_FRAG_LO(mt, kb), bh, acc[mt][t], 0, 0, 0);
               }
             }
           }
         }
         __builtin_amdgcn_sched_barrier(0);  // as above
+        CROM_STREAM_SHIFT()
       }
     }
+#undef CROM_FRAG_HI
+#undef CROM_FRAG_LO
+#undef CROM_STREAM_NEXT
+#undef CROM_STREAM_SHIFT
     __syncthreads();  // every wave has read this layer's activations
     const bool last = (h == depth - 2);
 #pragma unroll

@@ -19,6 +19,14 @@
 //   solves that instance at once: fixed-order sum of its partials, Armijo
 //   test of the trials, Cholesky of J^T J, next direction.  A phase ends
 //   when every instance that was active in it has been solved.
+// Neo-Hookean elastodynamics (d = 3, m = 3) runs the same inversion after
+// two preparatory launches: the decoder's value, x-gradient, x-Hessian and
+// latent Jacobian at q_n for every sample (engine passes with each batch's
+// own latent, Hessian and Jacobian in chunks that fit the LDS), then the
+// per-sample FP64 update (F = I + du/dX, div P through the Hessian,
+// velocity from the latent Jacobian, symplectic Euler) giving
+// rho_0 = u_{n+1} - u(q_n) = dt v_{n+1} directly; phase 0 then only sums
+// the partials of the stored Jacobian and rho_0.
 // The residual is the paper's f_{n+1} - g(q) written incrementally: over a
 // time step g moves by a small fraction of its size, and a difference
 // carried through the network keeps its rounding error relative to itself,
@@ -36,6 +44,10 @@
 #include <stddef.h>
 
 #include "common.hpp"
+
+#ifndef CROM_ELASTIC_NW
+#define CROM_ELASTIC_NW 4
+#endif
 
 namespace crom {
 
@@ -57,9 +69,21 @@ struct GNState {
 
 struct WsLayout {
   size_t blk_start, blk_inst, first_blk, nblk, sync, act_phase, inst_cnt, targets, rho0, partials,
-      state, total;
+      state, jets, total;
   int64_t nblk_max;
   int nred;
+  int nj;  // FP32 values per sample in the jets buffer (0: none)
+};
+
+// Per-sample decoder derivatives kept for the elastic update (d = 3, m = 3):
+// value [d], du/dX [d][m], Hessian upper triangle [d][m(m+1)/2], du/dq [d][r].
+struct JetsLayout {
+  int d, m, r, nh;
+  __host__ __device__ int val(int k) const { return k; }
+  __host__ __device__ int grad(int k, int l) const { return d + k * m + l; }
+  __host__ __device__ int hess(int k, int h) const { return d + d * m + k * nh + h; }
+  __host__ __device__ int jac(int k, int i) const { return d + d * m + d * nh + k * r + i; }
+  __host__ __device__ int count() const { return d + d * m + d * nh + d * r; }
 };
 
 // sync words (one 256-byte line each): solved count, abort flag
@@ -67,8 +91,9 @@ enum { SYNC_SOLVED = 0, SYNC_ABORT = 32 };
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-static WsLayout ws_layout(int r, int d, int n_inst, int64_t total) {
+static WsLayout ws_layout(int r, int d, int m, int n_inst, int64_t total) {
   WsLayout L{};
+  L.nj = d == 3 ? JetsLayout{d, m, r, m * (m + 1) / 2}.count() : 0;
   L.nblk_max = total / PT + n_inst;
   L.nred = r * (r + 1) / 2 + r + TV;
   size_t o = 0;
@@ -83,6 +108,7 @@ static WsLayout ws_layout(int r, int d, int n_inst, int64_t total) {
   L.rho0 = o;      o = align256(o + 8 * (size_t)total * d);
   L.partials = o;  o = align256(o + 8 * (size_t)L.nblk_max * L.nred);
   L.state = o;     o = align256(o + sizeof(GNState) * (size_t)n_inst);
+  L.jets = o;      o = align256(o + 4 * (size_t)total * L.nj);
   L.total = o;
   return L;
 }
@@ -98,6 +124,7 @@ struct StepArgs {
   const uint8_t* clamp;
   const double* coef;
   double dt;
+  const double* q_prev;  // elastic: latent of the previous step (NULL: at rest)
   const double* q_n;
   double* q_next;
   crom_step_info* info;
@@ -253,10 +280,11 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(StepArgs a) {
   }
 }
 
-// Partial sums of one batch from per-point J rows and residuals staged in LDS
-// (jd [PT][R], rho [PT][TV], both FP64; invalid points hold zeros), stored
-// device-coherently for the solving workgroup.
-template <int R>
+// Partial sums of one batch from J rows and residuals staged in LDS (jd
+// [ROWS][R], rho [ROWS][TV], both FP64, one row per sample and output value;
+// invalid rows hold zeros), stored device-coherently for the solving
+// workgroup.
+template <int R, int ROWS = PT>
 __device__ __forceinline__ void batch_partials(const double* jd, const double* rho, double* out) {
   constexpr int NA = R * (R + 1) / 2;
   constexpr int NRED = NA + R + TV;
@@ -266,13 +294,13 @@ __device__ __forceinline__ void batch_partials(const double* jd, const double* r
       int a = 0, rem = e, n = R;
       while (rem >= n) { rem -= n; ++a; --n; }
       const int b = a + rem;
-      for (int i = 0; i < PT; ++i) s += jd[i * R + a] * jd[i * R + b];
+      for (int i = 0; i < ROWS; ++i) s += jd[i * R + a] * jd[i * R + b];
     } else if (e < NA + R) {
       const int k = e - NA;
-      for (int i = 0; i < PT; ++i) s += jd[i * R + k] * rho[i * TV];
+      for (int i = 0; i < ROWS; ++i) s += jd[i * R + k] * rho[i * TV];
     } else {
       const int t = e - NA - R;
-      for (int i = 0; i < PT; ++i) s += 0.5 * rho[i * TV + t] * rho[i * TV + t];
+      for (int i = 0; i < ROWS; ++i) s += 0.5 * rho[i * TV + t] * rho[i * TV + t];
     }
     st_c(out + e, s);
   }
@@ -356,6 +384,203 @@ __device__ void eval_trials_batch(const StepArgs& a, char* lds, const float* par
 }
 
 // ---------------------------------------------------------------------------
+// Neo-Hookean elastodynamics (d = 3, m = 3).
+// ---------------------------------------------------------------------------
+enum { PK_HEAT = 0, PK_ELASTIC = 1 };
+
+// Latent-tangent chunk of the elastic passes (their activations must fit
+// the LDS at width 256: bfloat16 operands take half the room of FP32).
+template <int PREC>
+struct ElasticChunks {
+  static constexpr int QC = PREC == PREC_FP32 ? 4 : 8;
+  static constexpr int HC = 3;
+};
+
+// One engine pass at q_n over one batch, writing the pass's columns of
+// every valid sample into the jets buffer.
+template <class S, class C, int NW, int PREC>
+__device__ void jets_pass_batch(const StepArgs& a, char* lds, const float* par, int64_t blk, int qb) {
+  using E = Engine<S, C, 1, NW, PREC, 0>;
+  constexpr int D = S::D, CC = C::C, NT = E::NT;
+  const JetsLayout J{D, S::M, S::R, S::M * (S::M + 1) / 2};
+  const int inst = wsp<int32_t>(a, a.L.blk_inst)[blk];
+  const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
+  const int64_t rem = a.offsets[inst + 1] - first;
+  const int n_valid = rem < PT ? (int)rem : PT;
+  E::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * S::R, S::R, nullptr, 0, par);
+  __syncthreads();
+  E::run(lds, par, a.packed, a.depth, qb);
+  const float* res = reinterpret_cast<const float*>(lds + E::RES_OFF);
+  float* jets = wsp<float>(a, a.L.jets);
+  for (int e = threadIdx.x; e < n_valid * D * CC; e += blockDim.x) {
+    const int i = e / (D * CC), oo = (e / CC) % D, c = e % CC;
+    const float v = res[(oo * NT + c) * PT + i];
+    float* row = jets + (first + i) * a.L.nj;
+    const int k = C::kind(c);
+    if (k == CK_VAL) row[J.val(oo)] = v;
+    else if (k == CK_XT) row[J.grad(oo, c - C::X0)] = v;
+    else if (k == CK_HESS) row[J.hess(oo, C::HB + (c - C::D0))] = v;
+    else if (k == CK_QT) row[J.jac(oo, qb + (c - C::Q0))] = v;
+  }
+  __syncthreads();
+}
+
+template <class S, class C, int NW, int PREC>
+__global__ __launch_bounds__(NW * 64) void jets_pass_kernel(StepArgs a, int qb) {
+  using E = Engine<S, C, 1, NW, PREC, 0>;
+  extern __shared__ __align__(16) char lds[];
+  const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
+  if ((int64_t)blockIdx.x >= nblk) return;
+  float* par = reinterpret_cast<float*>(lds + E::LDS_BYTES);
+  E::PC::load(par, a.params, a.pi, a.depth, NW * 64);
+  __syncthreads();
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) jets_pass_batch<S, C, NW, PREC>(a, lds, par, blk, qb);
+}
+
+// FP64 update at one sample: rho_0 = u_{n+1} - u(q_n) and the target.
+//   F = I + du/dX, P = mu (F - F^-T) + lam ln J F^-T,
+//   (div P)_i = sum_{j,k,l} dP_ij/dF_kl d2u_k/dX_l dX_j with
+//   dP_ij/dF_kl = mu d_ik d_jl + (mu - lam ln J) Fi_jk Fi_li + lam Fi_lk Fi_ji,
+//   v_n = (du/dq)(q_n - q_prev)/dt, v+ = v_n + dt (div P / rho0 + B),
+//   rho_0 = dt v+ (or -u on a clamped sample).
+// coef per instance: lam, mu, rho0, Bx, By, Bz.
+template <int R>
+__global__ __launch_bounds__(64) void elastic_targets_kernel(StepArgs a) {
+  const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
+  const JetsLayout JL{3, 3, R, 6};
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int i = threadIdx.x;
+    const int inst = wsp<int32_t>(a, a.L.blk_inst)[blk];
+    const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
+    const int64_t rem = a.offsets[inst + 1] - first;
+    if (i >= PT || i >= rem) continue;
+    const int64_t p = first + i;
+    const float* row = wsp<float>(a, a.L.jets) + p * a.L.nj;
+    const double* cf = a.coef + (int64_t)inst * 6;
+    const double lam = cf[0], mu = cf[1], rho = cf[2];
+    double u[3], F[3][3], H[3][3][3];
+    for (int k = 0; k < 3; ++k) {
+      u[k] = row[JL.val(k)];
+      for (int l = 0; l < 3; ++l) F[k][l] = (k == l ? 1.0 : 0.0) + (double)row[JL.grad(k, l)];
+      for (int l = 0, h = 0; l < 3; ++l)
+        for (int j = l; j < 3; ++j, ++h) H[k][l][j] = H[k][j][l] = row[JL.hess(k, h)];
+    }
+    // inverse by cofactors
+    const double c00 = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+    const double c01 = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+    const double c02 = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+    const double det = F[0][0] * c00 + F[0][1] * c01 + F[0][2] * c02;
+    double Fi[3][3];
+    Fi[0][0] = c00 / det;
+    Fi[1][0] = c01 / det;
+    Fi[2][0] = c02 / det;
+    Fi[0][1] = (F[0][2] * F[2][1] - F[0][1] * F[2][2]) / det;
+    Fi[1][1] = (F[0][0] * F[2][2] - F[0][2] * F[2][0]) / det;
+    Fi[2][1] = (F[0][1] * F[2][0] - F[0][0] * F[2][1]) / det;
+    Fi[0][2] = (F[0][1] * F[1][2] - F[0][2] * F[1][1]) / det;
+    Fi[1][2] = (F[0][2] * F[1][0] - F[0][0] * F[1][2]) / det;
+    Fi[2][2] = (F[0][0] * F[1][1] - F[0][1] * F[1][0]) / det;
+    const double lnJ = log(det);  // NaN for det <= 0: reported as NONFINITE by the solve
+    double qdot[R];
+    for (int r = 0; r < R; ++r)
+      qdot[r] = a.q_prev ? (a.q_n[(int64_t)inst * R + r] - a.q_prev[(int64_t)inst * R + r]) / a.dt : 0.0;
+    const bool clamped = a.clamp && a.clamp[p];
+    double* rho0 = wsp<double>(a, a.L.rho0) + p * 3;
+    double* tg = wsp<double>(a, a.L.targets) + p * 3;
+    for (int ii = 0; ii < 3; ++ii) {
+      double div = 0.0;
+      for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k)
+          for (int l = 0; l < 3; ++l) {
+            const double A = (ii == k && j == l ? mu : 0.0) + (mu - lam * lnJ) * Fi[j][k] * Fi[l][ii] +
+                             lam * Fi[l][k] * Fi[j][ii];
+            div += A * H[k][l][j];
+          }
+      double v = 0.0;
+      for (int r = 0; r < R; ++r) v += (double)row[JL.jac(ii, r)] * qdot[r];
+      const double vn = v + a.dt * (div / rho + cf[3 + ii]);
+      const double inc = clamped ? -u[ii] : a.dt * vn;
+      rho0[ii] = inc;
+      tg[ii] = clamped ? 0.0 : u[ii] + inc;
+    }
+  }
+}
+
+// Phase 0 of the elastic step: the partials of the stored Jacobian at q_n
+// and of rho_0 (no decoder evaluation).
+template <class S>
+__device__ void eval_init_elastic(const StepArgs& a, double* jd, int64_t blk) {
+  constexpr int R = S::R, D = S::D, ROWS = PT * D;
+  const JetsLayout JL{D, S::M, R, S::M * (S::M + 1) / 2};
+  double* rho = jd + ROWS * R;
+  const int inst = wsp<int32_t>(a, a.L.blk_inst)[blk];
+  const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
+  const int64_t rem = a.offsets[inst + 1] - first;
+  const int n_valid = rem < PT ? (int)rem : PT;
+  const float* jets = wsp<float>(a, a.L.jets);
+  const double* rho0 = wsp<double>(a, a.L.rho0);
+  for (int e = threadIdx.x; e < ROWS * R; e += blockDim.x) {
+    const int row = e / R, k = e % R, i = row / D, oo = row % D;
+    jd[e] = i < n_valid ? (double)jets[(first + i) * a.L.nj + JL.jac(oo, k)] : 0.0;
+  }
+  for (int e = threadIdx.x; e < ROWS * TV; e += blockDim.x) {
+    const int row = e / TV, t = e % TV, i = row / D;
+    rho[e] = (t == 0 && i < n_valid) ? rho0[first * D + row] : 0.0;
+  }
+  __syncthreads();
+  batch_partials<R, ROWS>(jd, rho, wsp<double>(a, a.L.partials) + blk * a.L.nred);
+  __syncthreads();
+}
+
+// Trial phases of the elastic step: the decoder differences at the TV trial
+// latents (one pass), then the Jacobian at the first trial in chunks of QC
+// latent directions (value, the first difference and the chunk's tangents,
+// which the engine takes at the first difference column's latent).
+template <class S, int NW, int PREC, int PF>
+__device__ void eval_trials_elastic(const StepArgs& a, char* lds, double* jd, const float* par, double* qdl,
+                                    int64_t blk, int inst) {
+  constexpr int R = S::R, D = S::D, ROWS = PT * D;
+  constexpr int QC = ElasticChunks<PREC>::QC;
+  using CT = Cols<S::M, R, 1, TV, false, D2_NONE, 0>;
+  using ET = Engine<S, CT, 1, NW, PREC, PF>;
+  using CQ = Cols<S::M, R, 1, 1, false, D2_NONE, QC>;
+  using EQ = Engine<S, CQ, 1, NW, PREC, PF>;
+  double* rho = jd + ROWS * R;
+  const GNState* st = wsp<GNState>(a, a.L.state) + inst;
+  for (int i = threadIdx.x; i < TV * R; i += blockDim.x) qdl[i] = ld_c(&st->qd[i / R][i % R]);
+  __syncthreads();
+  const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
+  const int64_t rem = a.offsets[inst + 1] - first;
+  const int n_valid = rem < PT ? (int)rem : PT;
+  const double* qn = a.q_n + (int64_t)inst * R;
+  ET::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
+  __syncthreads();
+  ET::run(lds, par, a.packed, a.depth, 0);
+  {
+    const float* res = reinterpret_cast<const float*>(lds + ET::RES_OFF);
+    const double* rho0 = wsp<double>(a, a.L.rho0);
+    for (int e = threadIdx.x; e < ROWS * TV; e += blockDim.x) {
+      const int row = e / TV, t = e % TV, i = row / D, oo = row % D;
+      rho[e] = i < n_valid ? rho0[first * D + row] - (double)res[(oo * ET::NT + CT::F0 + t) * PT + i] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int qb = 0; qb < R; qb += QC) {
+    EQ::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
+    __syncthreads();
+    EQ::run(lds, par, a.packed, a.depth, qb);
+    const float* res = reinterpret_cast<const float*>(lds + EQ::RES_OFF);
+    for (int e = threadIdx.x; e < ROWS * QC; e += blockDim.x) {
+      const int row = e / QC, c = e % QC, i = row / D, oo = row % D;
+      jd[row * R + qb + c] = i < n_valid ? (double)res[(oo * EQ::NT + CQ::Q0 + c) * PT + i] : 0.0;
+    }
+    __syncthreads();
+  }
+  batch_partials<R, ROWS>(jd, rho, wsp<double>(a, a.L.partials) + blk * a.L.nred);
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // Small dense algebra on one wave (64 lanes), FP64.
 // A symmetric R x R matrix is held one element per lane and slot: element
 // e = lane + 64 * slot is (i, k) = (e / R, e % R).  fetch(x, i, k) returns
@@ -408,20 +633,26 @@ __device__ bool wave_chol_solve(const double* up, const double* b, double& xk) {
     if (!(isfinite(d) && d > thresh)) return false;  // uniform across the wave
     const double ljj = sqrt(d);
     const double inv = 1.0 / ljj;
+    // every slot's new value from the matrix before this column's update
+    // (with r * r > 64 a lane holds several slots, and a slot written early
+    // would otherwise be fetched by the later ones)
+    double nv[WaveMat<R>::NE];
 #pragma unroll
     for (int s = 0; s < WaveMat<R>::NE; ++s) {
       const int e = lane + 64 * s;
       const int i = e / R, k = e % R;
       const double lij = A.fetch(i < R ? i : 0, j) * inv;
-      const double lkj = A.fetch(k, j) * inv;
+      const double lkj = A.fetch(k < R ? k : 0, j) * inv;
       double val = A.v[s];
       if (e < R * R) {
         if (i > j && k > j) val -= lij * lkj;
         else if (k == j && i > j) val = lij;
         else if (i == j && k == j) val = ljj;
       }
-      A.v[s] = val;
+      nv[s] = val;
     }
+#pragma unroll
+    for (int s = 0; s < WaveMat<R>::NE; ++s) A.v[s] = nv[s];
   }
   // lane i holds row i of the substitutions
   const int i = lane;
@@ -671,17 +902,38 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
 // ---------------------------------------------------------------------------
 constexpr int64_t SPIN_MAX = int64_t(1) << 21;  // bounded waits: ~2e6 polls of ~1 us
 
+// Engines and LDS layout of the persistent kernel per PDE kind: the
+// engines' activation regions share the start of the dynamic LDS; the
+// elastic kind keeps its J rows and residuals (FP64) above them; the
+// parameter cache comes last, at PAR.
+template <class S, int NW, int PREC, int PF, int KIND>
+struct StepTraits {
+  using E0 = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC, PF>;
+  using E1 = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, S::R>, 1, NW, PREC, PF>;
+  static constexpr int ENG = E0::LDS_BYTES > E1::LDS_BYTES ? E0::LDS_BYTES : E1::LDS_BYTES;
+  static constexpr int JD_OFF = ENG;
+  static constexpr int PAR = ENG;
+};
 template <class S, int NW, int PREC, int PF>
+struct StepTraits<S, NW, PREC, PF, PK_ELASTIC> {
+  using E0 = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, 0>, 1, NW, PREC, PF>;
+  using E1 = Engine<S, Cols<S::M, S::R, 1, 1, false, D2_NONE, ElasticChunks<PREC>::QC>, 1, NW, PREC, PF>;
+  static constexpr int ENG = E0::LDS_BYTES > E1::LDS_BYTES ? E0::LDS_BYTES : E1::LDS_BYTES;
+  static constexpr int JD_OFF = (ENG + 15) / 16 * 16;
+  static constexpr int PAR = JD_OFF + PT * S::D * (S::R + TV) * 8;
+};
+
+template <class S, int NW, int PREC, int PF, int KIND>
 __global__ __launch_bounds__(NW * 64) void step_kernel(StepArgs a, int max_rounds) {
-  using EJ = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC, PF>;
-  using ET = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, S::R>, 1, NW, PREC, PF>;
-  constexpr int PAR = EJ::LDS_BYTES > ET::LDS_BYTES ? EJ::LDS_BYTES : ET::LDS_BYTES;
+  using T = StepTraits<S, NW, PREC, PF, KIND>;
+  constexpr int PAR = T::PAR;
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_last, s_abort, s_ph;
   __shared__ int64_t s_act;
   __shared__ double qdl[TV * RMAX];
   float* par = reinterpret_cast<float*>(lds + PAR);
-  EJ::PC::load(par, a.params, a.pi, a.depth, NW * 64);
+  double* jd = reinterpret_cast<double*>(lds + T::JD_OFF);
+  T::E0::PC::load(par, a.params, a.pi, a.depth, NW * 64);
   __syncthreads();
   const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
   const int32_t* blk_inst = wsp<int32_t>(a, a.L.blk_inst);
@@ -703,14 +955,18 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepArgs a, int max_round
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
       const int inst = blk_inst[blk];
       if (p == 0) {
-        eval_jets_batch<S, NW, PREC, PF>(a, lds, par, blk);
+        if constexpr (KIND == PK_HEAT) eval_jets_batch<S, NW, PREC, PF>(a, lds, par, blk);
+        else eval_init_elastic<S>(a, jd, blk);
       } else {
         if (threadIdx.x == 0) s_ph = ld_c(&state[inst].phase);  // stable until this batch arrives
         __syncthreads();
         const int ph = s_ph;
         __syncthreads();
         if (ph != PH_TRIALS && ph != PH_REJAC) continue;
-        eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, (p == 1 && blk == blockIdx.x) ? 40 : -1);
+        if constexpr (KIND == PK_HEAT)
+          eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, (p == 1 && blk == blockIdx.x) ? 40 : -1);
+        else
+          eval_trials_elastic<S, NW, PREC, PF>(a, lds, jd, par, qdl, blk, inst);
       }
       // arrival: the partials of this batch are complete in memory
       if (p == 1 && blk == blockIdx.x) trace_mark(a, 44);
@@ -754,21 +1010,60 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepArgs a, int max_round
   }
 }
 
-template <class S, int NW, int PREC, int PF>
+// One engine pass of the elastic preparation over every batch.
+template <class S, class C, int NW, int PREC>
+static crom_status launch_jets_pass(const StepArgs& a, int qb, hipStream_t st) {
+  using E = Engine<S, C, 1, NW, PREC, 0>;
+  const int lds_bytes = E::LDS_BYTES + E::PC::bytes(a.depth);
+  if (lds_bytes > LDS_MAX) return fail(CROM_ERR_UNSUPPORTED, "network too deep for the LDS");
+  auto k = jets_pass_kernel<S, C, NW, PREC>;
+  crom_status s = set_lds(k, lds_bytes);
+  if (s != CROM_OK) return s;
+  int64_t g = a.L.nblk_max;
+  if (g > 65535) g = 65535;
+  hipLaunchKernelGGL(k, dim3((unsigned)g), dim3(NW * 64), lds_bytes, st, a, qb);
+  return hip_check(hipGetLastError(), "jets pass launch");
+}
+
+// Value, x-gradient, x-Hessian (in chunks of HC entries, each pass
+// recomputing the x tangents its entries need) and latent Jacobian (chunks
+// of QC) at q_n, then the FP64 update of every sample.
+template <class S, int NW, int PREC, int HB = 0>
+static crom_status elastic_prepare(const StepArgs& a, hipStream_t st) {
+  constexpr int NH = S::M * (S::M + 1) / 2, HC = ElasticChunks<PREC>::HC, QC = ElasticChunks<PREC>::QC;
+  if constexpr (HB < NH) {
+    constexpr int n = NH - HB < HC ? NH - HB : HC;
+    crom_status s = launch_jets_pass<S, Cols<S::M, S::R, 1, 0, true, D2_HESS, 0, HB, n>, NW, PREC>(a, 0, st);
+    if (s != CROM_OK) return s;
+    return elastic_prepare<S, NW, PREC, HB + HC>(a, st);
+  } else {
+    for (int qb = 0; qb < S::R; qb += QC) {
+      crom_status s = launch_jets_pass<S, Cols<S::M, S::R, 1, 0, false, D2_NONE, QC>, NW, PREC>(a, qb, st);
+      if (s != CROM_OK) return s;
+    }
+    int64_t g = a.L.nblk_max;
+    if (g > 65535) g = 65535;
+    hipLaunchKernelGGL(elastic_targets_kernel<S::R>, dim3((unsigned)g), dim3(64), 0, st, a);
+    return hip_check(hipGetLastError(), "elastic targets launch");
+  }
+}
+
+template <class S, int NW, int PREC, int PF, int KIND = PK_HEAT>
 static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
-  using EJ = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC, PF>;
-  using ET = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, S::R>, 1, NW, PREC, PF>;
-  constexpr int PAR = EJ::LDS_BYTES > ET::LDS_BYTES ? EJ::LDS_BYTES : ET::LDS_BYTES;
-  const int lds_bytes = PAR + EJ::PC::bytes(a.depth);
+  using T = StepTraits<S, NW, PREC, PF, KIND>;
+  constexpr int PAR = T::PAR;
+  const int lds_bytes = PAR + T::E0::PC::bytes(a.depth);
   if (lds_bytes + (int)sizeof(double) * TV * RMAX + 64 > LDS_MAX)
     return fail(CROM_ERR_UNSUPPORTED, "network too deep for the step kernel's LDS");
-  static_assert(PT * S::R * 8 + PT * TV * 8 <= EJ::ACT_REGION, "staging fits");
-  static_assert(PT * S::R * 8 + PT * TV * 8 <= ET::ACT_REGION, "staging fits");
+  if constexpr (KIND == PK_HEAT) {
+    static_assert(PT * S::R * 8 + PT * TV * 8 <= T::E0::ACT_REGION, "staging fits");
+    static_assert(PT * S::R * 8 + PT * TV * 8 <= T::E1::ACT_REGION, "staging fits");
+  }
   static_assert(sizeof(GNState) + 16 +
                     (NW * 64 + S::R * (S::R + 1) / 2 + S::R + TV + S::R * S::R + S::R) * 8 <= PAR,
                 "solve scratch fits below the parameter cache");
   static_assert(NW * 64 >= S::R * (S::R + 1) / 2 + S::R + TV, "one thread per reduced entry");
-  auto k = step_kernel<S, NW, PREC, PF>;
+  auto k = step_kernel<S, NW, PREC, PF, KIND>;
   static int resident = 0, resident_lds = -1;
   if (resident_lds != lds_bytes) {
     crom_status s = set_lds(k, LDS_MAX - (int)sizeof(double) * TV * RMAX - 64);
@@ -786,6 +1081,10 @@ static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
   hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(SETUP_THREADS), 0, st, a);
   crom_status s = hip_check(hipGetLastError(), "setup launch");
   if (s != CROM_OK) return s;
+  if constexpr (KIND == PK_ELASTIC) {
+    s = elastic_prepare<S, NW, PREC>(a, st);
+    if (s != CROM_OK) return s;
+  }
   int64_t g = a.L.nblk_max;
   if (g > resident) g = resident;
   if (g < 1) g = 1;
@@ -808,6 +1107,17 @@ static crom_status step_prec(int prec, const StepArgs& a, int rounds, hipStream_
   }
 }
 
+// The elastic step at width 256 (weight fragments streamed per K-block).
+template <class S, int NW>
+static crom_status step_prec_elastic(int prec, const StepArgs& a, int rounds, hipStream_t st) {
+  switch (prec) {
+    case CROM_PREC_FP32: return launch_step<S, NW, PREC_FP32, 0, PK_ELASTIC>(a, rounds, st);
+    case CROM_PREC_BF16: return launch_step<S, NW, PREC_BF16, 0, PK_ELASTIC>(a, rounds, st);
+    case CROM_PREC_BF16_PURE: return launch_step<S, NW, PREC_BF16_PURE, 0, PK_ELASTIC>(a, rounds, st);
+    default: return launch_step<S, NW, PREC_BF16X3, 0, PK_ELASTIC>(a, rounds, st);
+  }
+}
+
 }  // namespace crom
 
 using namespace crom;
@@ -827,27 +1137,36 @@ crom_status crom_step_workspace(const crom_net* net, int32_t n_inst, int64_t tot
   if (s != CROM_OK) return s;
   if (!bytes) return fail(CROM_ERR_INVALID_ARG, "bytes is NULL");
   if (n_inst < 0 || total_samples < 0) return fail(CROM_ERR_INVALID_ARG, "negative size");
-  *bytes = ws_layout(net->r, net->d, n_inst, total_samples).total;
+  *bytes = ws_layout(net->r, net->d, net->m, n_inst, total_samples).total;
   return CROM_OK;
 }
 
 const double* crom_step_targets(const crom_net* net, int32_t n_inst, int64_t total_samples,
                                 const void* ws) {
   if (!net || !ws || n_inst < 0 || total_samples < 0) return nullptr;
-  WsLayout L = ws_layout(net->r, net->d, n_inst, total_samples);
+  WsLayout L = ws_layout(net->r, net->d, net->m, n_inst, total_samples);
   return reinterpret_cast<const double*>(static_cast<const char*>(ws) + L.targets);
+}
+
+const double* crom_step_increments(const crom_net* net, int32_t n_inst, int64_t total_samples,
+                                   const void* ws) {
+  if (!net || !ws || n_inst < 0 || total_samples < 0) return nullptr;
+  WsLayout L = ws_layout(net->r, net->d, net->m, n_inst, total_samples);
+  return reinterpret_cast<const double*>(static_cast<const char*>(ws) + L.rho0);
 }
 
 crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
                       const int64_t* offsets, int64_t total_samples, const float* y,
-                      const uint8_t* clamp, const double* q_n, double* q_next,
+                      const uint8_t* clamp, const double* q_prev, const double* q_n, double* q_next,
                       const crom_gn_opts* opts, crom_step_info* info, void* ws, size_t ws_bytes,
                       void* stream) {
   crom_status s = check_net(net, true);
   if (s != CROM_OK) return s;
   if (!pde || !opts) return fail(CROM_ERR_INVALID_ARG, "pde and opts are required");
-  if (pde->kind != CROM_PDE_HEAT) return fail(CROM_ERR_UNSUPPORTED, "pde kind");
-  if (net->d != 1) return fail(CROM_ERR_UNSUPPORTED, "the heat step needs d == 1");
+  if (pde->kind != CROM_PDE_HEAT && pde->kind != CROM_PDE_NEOHOOKEAN) return fail(CROM_ERR_UNSUPPORTED, "pde kind");
+  if (pde->kind == CROM_PDE_HEAT && net->d != 1) return fail(CROM_ERR_UNSUPPORTED, "the heat step needs d == 1");
+  if (pde->kind == CROM_PDE_NEOHOOKEAN && (net->d != 3 || net->m != 3))
+    return fail(CROM_ERR_UNSUPPORTED, "the elastic step needs m == 3 and d == 3");
   if (net->r > RMAX) return fail(CROM_ERR_UNSUPPORTED, "r > 16");
   if (n_inst < 0 || total_samples < 0) return fail(CROM_ERR_INVALID_ARG, "negative size");
   if (n_inst == 0) return CROM_OK;
@@ -859,7 +1178,7 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
       !(opts->ls_shrink > 0.0 && opts->ls_shrink < 1.0) || !(opts->armijo_c >= 0.0))
     return fail(CROM_ERR_INVALID_ARG, "gn opts out of range");
   if (!(pde->dt > 0.0)) return fail(CROM_ERR_INVALID_ARG, "dt must be positive");
-  WsLayout L = ws_layout(net->r, net->d, n_inst, total_samples);
+  WsLayout L = ws_layout(net->r, net->d, net->m, n_inst, total_samples);
   if (!ws || ws_bytes < L.total) return fail(CROM_ERR_WORKSPACE, "workspace too small");
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(CROM_ERR_WORKSPACE, "workspace not 256-byte aligned");
   if (L.nblk_max > 0x7fffffff) return fail(CROM_ERR_INVALID_ARG, "too many samples");
@@ -876,6 +1195,7 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
   a.clamp = clamp;
   a.coef = pde->coef;
   a.dt = pde->dt;
+  a.q_prev = pde->kind == CROM_PDE_NEOHOOKEAN ? q_prev : nullptr;
   a.q_n = q_n;
   a.q_next = q_next;
   a.info = info;
@@ -897,6 +1217,7 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
   switch (shape_id(net->m, net->r, net->d, net->width)) {
     case SHAPE_1D: return step_prec<Shape<32, 1, 3, 1>, 2, 2>(net->precision, a, (int)rounds, st);
     case SHAPE_2D: return step_prec<Shape<128, 2, 8, 1>, 8, 4>(net->precision, a, (int)rounds, st);
+    case SHAPE_3D: return step_prec_elastic<Shape<256, 3, 16, 3>, CROM_ELASTIC_NW>(net->precision, a, (int)rounds, st);
     default: return fail(CROM_ERR_UNSUPPORTED, "shape");
   }
 }

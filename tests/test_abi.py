@@ -70,7 +70,7 @@ def test_step_validation():
         a = dict(args)
         a.update(kw)
         return L.crom_step(ctypes.byref(net or _net()), ctypes.byref(pde_), 4, a["offsets"], a["total"],
-                           a["y"], a["clamp"], a["qn"], a["qnext"], ctypes.byref(opts_), a["info"],
+                           a["y"], a["clamp"], None, a["qn"], a["qnext"], ctypes.byref(opts_), a["info"],
                            a["ws"], a["wsb"], None)
 
     assert call(wsb=n.value - 1) == 3
@@ -81,6 +81,7 @@ def test_step_validation():
     assert call(opts_=bad) == 1
     assert call(pde_=crom.CromPDE(0, 0, -1.0, 1 << 22)) == 1
     assert call(pde_=crom.CromPDE(5, 0, 1e-4, 1 << 22)) == 2
+    assert call(pde_=crom.CromPDE(1, 0, 1e-4, 1 << 22)) == 2  # neo-Hookean needs m == d == 3
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

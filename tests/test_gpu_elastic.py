@@ -1,0 +1,176 @@
+"""Parity of the neo-Hookean latent step (crom_step with CROM_PDE_NEOHOOKEAN)
+with the FP64 oracle (GPU).
+
+Config-3 decoder (X in R^3, q in R^16) -> 6 x ELU width 256 -> 3, 500
+samples of the 64 x 16 x 16 bar, the samples on the face X_1 = 0 clamped.
+The per-sample increments rho_0 = u_{n+1} - u(q_n) are read back directly
+(crom_step_increments: the step forms them without a subtraction of two
+nearby values).  Two cases separate the
+terms: with B = 0 and q_prev = q_n the increment is dt^2 div P / rho0 alone
+(the stress divergence through the network Hessian); the full case adds the
+tangent-space velocity and gravity.  Tolerances (normwise): FP32 1e-4 on
+the divergence (FP32 Hessians are good to about 1e-5), 1e-5 on the full
+increment (the FP32 decoder bar; its latent-Jacobian velocity term carries
+about 1e-6); BF16 3e-2 on the divergence
+(bfloat16 Hessian columns carry about 1e-2) and 1e-3 on the full increment.
+The step's latent update is compared against the oracle's within a bound
+set by the conditioning of J^T J."""
+import numpy as np
+import pytest
+
+from conftest import normwise_rel
+from oracle import elastic, mlp
+from oracle.inversion import GNOptions
+from workloads import Elastic3D, rng
+
+pytestmark = pytest.mark.gpu
+
+TOL_DIV = {"fp32": 1e-4, "bf16": 3e-2}
+TOL_FULL = {"fp32": 1e-5, "bf16": 1e-3}
+
+
+def _setup(prec, cuda, zero_out=False):
+    import torch
+    from paper_2206_02607_amd import crom
+    w = Elastic3D()
+    layers = [(np.asarray(W, np.float32), np.asarray(b, np.float32)) for W, b in w.layers]
+    if zero_out:
+        layers[-1] = (np.zeros_like(layers[-1][0]), np.zeros_like(layers[-1][1]))
+    X = w.nodes[w.sample_idx].astype(np.float32)
+    clamp = (X[:, 0] == 0.0).astype(np.uint8)
+    dec = crom.Decoder.from_layers(layers, 3, precision=prec, device=cuda)
+    return w, layers, X, clamp, dec
+
+
+def _coef(w, B):
+    return np.array([w.lam, w.mu, w.rho0, *B], dtype=np.float64)
+
+
+def _run(dec, X, clamp, coef, q_n, q_prev, dt, opts, cuda, n_inst=1):
+    """One step; returns (q_next, targets, info, increments) on the host."""
+    import torch
+    from paper_2206_02607_amd import crom
+    S = X.shape[0]
+    offsets = np.arange(n_inst + 1, dtype=np.int64) * S
+    st = crom.Stepper(dec, offsets, torch.from_numpy(np.tile(X, (n_inst, 1))).to(cuda),
+                      torch.from_numpy(np.tile(clamp, n_inst)).to(cuda), pde="neohookean")
+    qn = torch.from_numpy(np.atleast_2d(q_n)).to(cuda)
+    qp = None if q_prev is None else torch.from_numpy(np.atleast_2d(q_prev)).to(cuda)
+    q1 = st.step(qn, torch.from_numpy(np.atleast_2d(coef)).to(cuda), dt, opts, q_prev=qp)
+    torch.cuda.synchronize()
+    return q1.cpu().numpy(), st.targets().cpu().numpy(), st.info(), st.increments().cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_stress_divergence_increment(cuda, prec):
+    from paper_2206_02607_amd import crom
+    w, layers, X, clamp, dec = _setup(prec, cuda)
+    dt = w.dt
+    coef = _coef(w, (0.0, 0.0, 0.0))
+    _, tg, _, inc = _run(dec, X, clamp, coef, w.q0, w.q0, dt, crom.GNOptions(max_iter=1, linearized=True), cuda)
+    _, ref = elastic.elastic_targets(mlp.MLPDecoder(layers, 3), X.astype(np.float64), w.q0, w.q0, w.lam, w.mu,
+                                     w.rho0, (0.0, 0.0, 0.0), dt, clamp)
+    free = clamp == 0
+    err = normwise_rel(inc[free], ref[free])
+    print(f"{prec} dt^2 div P / rho0: max {np.abs(ref[free]).max():.3e}, normwise error {err:.2e}")
+    assert err <= TOL_DIV[prec]
+    assert np.all(tg[clamp == 1] == 0.0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_full_increment(cuda, prec):
+    from paper_2206_02607_amd import crom
+    w, layers, X, clamp, dec = _setup(prec, cuda)
+    q_prev = w.q0 - 0.01 * rng(3).uniform(-1, 1, size=w.r)
+    coef = _coef(w, w.gravity)
+    _, tg, _, inc = _run(dec, X, clamp, coef, w.q0, q_prev, w.dt, crom.GNOptions(max_iter=1, linearized=True), cuda)
+    _, ref = elastic.elastic_targets(mlp.MLPDecoder(layers, 3), X.astype(np.float64), w.q0, q_prev, w.lam, w.mu,
+                                     w.rho0, w.gravity, w.dt, clamp)
+    err = normwise_rel(inc, ref)
+    print(f"{prec} full increment: max {np.abs(ref).max():.3e}, normwise error {err:.2e}")
+    assert err <= TOL_FULL[prec]
+
+
+def _q_bound(layers, X, q, eps):
+    J = mlp.decode_jets(layers, X.astype(np.float64), q, 3)[3].reshape(-1, q.size)
+    s = np.linalg.svd(J, compute_uv=False)
+    return 10.0 * (s[0] / s[-1]) * eps
+
+
+@pytest.mark.parametrize("linearized", [1, 0])
+def test_step_parity_fp32(cuda, linearized):
+    """The latent update q_{n+1} - q_n against the oracle's step."""
+    from paper_2206_02607_amd import crom
+    w, layers, X, clamp, dec = _setup("fp32", cuda)
+    q_prev = w.q0 - 0.01 * rng(4).uniform(-1, 1, size=w.r)
+    coef = _coef(w, w.gravity)
+    opts = dict(max_iter=5, linearized=bool(linearized), tol_step=1e-10)
+    q1, _, info, _ = _run(dec, X, clamp, coef, w.q0, q_prev, w.dt, crom.GNOptions(**opts), cuda)
+    ref, rinfo, _ = elastic.elastic_step(mlp.MLPDecoder(layers, 3), X.astype(np.float64), w.q0, q_prev, w.lam,
+                                         w.mu, w.rho0, w.gravity, w.dt, GNOptions(**opts), clamp)
+    dq, dq_ref = q1[0] - w.q0, ref - w.q0
+    err = normwise_rel(dq, dq_ref)
+    bound = _q_bound(layers, X, w.q0, 1e-6)
+    print(f"linearized={linearized}: |dq| {np.abs(dq_ref).max():.3e} error {err:.2e} bound {bound:.2e} "
+          f"flags {info['flags'][0]} iters {info['iters'][0]} (oracle {rinfo.flags} {rinfo.iters})")
+    assert err <= max(bound, 1e-4)
+    assert info["flags"][0] & ~crom.FLAG_MAXITER == 0
+
+
+def test_free_fall(cuda):
+    """Zero output layer: u = 0, F = I, div P = 0, J = 0; the targets are
+    dt^2 B on free samples and 0 on clamped ones, and the singular normal
+    equations leave q unchanged with SINGULAR."""
+    from paper_2206_02607_amd import crom
+    w, layers, X, clamp, dec = _setup("fp32", cuda, zero_out=True)
+    coef = _coef(w, w.gravity)
+    q1, tg, info, _ = _run(dec, X, clamp, coef, w.q0, w.q0 - 0.3, w.dt, crom.GNOptions(max_iter=5), cuda)
+    expect = np.tile(w.dt * w.dt * np.asarray(w.gravity), (X.shape[0], 1))
+    expect[clamp == 1] = 0.0
+    np.testing.assert_allclose(tg, expect, rtol=1e-15, atol=0)
+    assert info["flags"][0] & crom.FLAG_SINGULAR
+    np.testing.assert_array_equal(q1[0], w.q0)
+
+
+def test_batched_equals_single(cuda):
+    from paper_2206_02607_amd import crom
+    w, layers, X, clamp, dec = _setup("bf16", cuda)
+    g = rng(5)
+    n = 3
+    qn = w.q0[None] + 0.05 * g.uniform(-1, 1, size=(n, w.r))
+    qp = qn - 0.01 * g.uniform(-1, 1, size=(n, w.r))
+    coef = np.stack([_coef(w, (0.0, 0.0, -9.81 * (1 + i))) for i in range(n)])
+    opts = crom.GNOptions(max_iter=5, tol_step=1e-8)
+    qb, tb, ib, _ = _run(dec, X, clamp, coef, qn, qp, w.dt, opts, cuda, n_inst=n)
+    S = X.shape[0]
+    for i in range(n):
+        q1, t1, i1, _ = _run(dec, X, clamp, coef[i], qn[i], qp[i], w.dt, opts, cuda)
+        np.testing.assert_array_equal(qb[i], q1[0])
+        np.testing.assert_array_equal(tb[i * S:(i + 1) * S], t1)
+        assert ib[i].tobytes() == i1[0].tobytes()
+
+
+def test_three_step_rollout_fp32(cuda):
+    """Three linearised steps with the velocity carried by q_prev follow the
+    oracle's rollout (the same update applied three times in FP64)."""
+    import torch
+    from paper_2206_02607_amd import crom
+    w, layers, X, clamp, dec = _setup("fp32", cuda)
+    coef = _coef(w, w.gravity)
+    S = X.shape[0]
+    st = crom.Stepper(dec, [0, S], torch.from_numpy(X).to(cuda), torch.from_numpy(clamp).to(cuda), pde="neohookean")
+    opts = dict(max_iter=1, linearized=True)
+    q_prev = torch.from_numpy(w.q0[None].copy()).to(cuda)
+    q = q_prev.clone()
+    oq_prev, oq = w.q0.copy(), w.q0.copy()
+    odec = mlp.MLPDecoder(layers, 3)
+    for k in range(3):
+        q_next = st.step(q, torch.from_numpy(coef[None]).to(cuda), w.dt, crom.GNOptions(**opts), q_prev=q_prev)
+        assert st.info()["flags"][0] == 0
+        q_prev, q = q, q_next.clone()
+        on, _, _ = elastic.elastic_step(odec, X.astype(np.float64), oq, oq_prev, w.lam, w.mu, w.rho0, w.gravity,
+                                        w.dt, GNOptions(**opts), clamp)
+        oq_prev, oq = oq, on
+        err = normwise_rel(q[0].cpu().numpy() - w.q0, oq - w.q0)
+        print(f"step {k + 1}: |q - q0| {np.abs(oq - w.q0).max():.3e} error {err:.2e}")
+        assert err <= 3 * _q_bound(layers, X, w.q0, 1e-6)

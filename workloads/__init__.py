@@ -145,8 +145,9 @@ class Heat2D:
 class Elastic3D:
     """Neo-Hookean bar of 64 x 16 x 16 material points (spacing h = 1/15),
     lambda = 1e4, mu = 4e3, rho0 = 1000, gravity (0, 0, -9.81); decoder
-    (X in R^3, q in R^16) -> 6 ELU layers of width 256 -> 3 (displacement);
-    500 samples drawn from the nodes; the face X_1 = 0 is clamped."""
+    (X in R^3, q in R^16) -> 6 ELU layers of width 256 -> 3 (displacement),
+    Xavier-uniform with the output layer scaled by out_scale; 500 samples
+    drawn from the nodes; the samples on the face X_1 = 0 are clamped."""
     seed: int = 0
     nx: int = 64
     ny: int = 16
@@ -170,6 +171,9 @@ class Elastic3D:
     def __post_init__(self):
         g = rng(self.seed)
         self.layers = xavier_mlp(g, self.m, self.r, self.d, self.width, self.depth)
+        # displacements of order out_scale: small strains, det F near 1
+        W, b = self.layers[-1]
+        self.layers[-1] = ((W * self.out_scale).astype(np.float32), (b * self.out_scale).astype(np.float32))
         n_nodes = self.nx * self.ny * self.nz
         self.sample_idx = np.sort(g.choice(n_nodes, size=self.n_samples, replace=False))
         self.q0 = g.uniform(-0.1, 0.1, size=self.r)
