@@ -232,6 +232,117 @@ def batched_leg(args, crom, torch, dev, trained=None):
     return out
 
 
+def config1_leg(args, crom, torch, dev):
+    """1D heat (nu = 0.5, decoder (1 + 3) -> 5 x 32 -> 1, 20 samples, dt =
+    1e-5): a 1000-step Gauss-Newton rollout in FP32 on the GPU, the same
+    rollout by the FP64 oracle on one host thread, and their difference."""
+    from oracle import mlp, step as ostep
+    from oracle.inversion import GNOptions
+    from workloads import Heat1D
+    w = Heat1D(seed=args.seed)
+    dec = crom.Decoder.from_layers(w.layers, w.m, precision="fp32", device=dev)
+    st = crom.Stepper(dec, [0, w.n_samples], torch.from_numpy(w.samples).to(dev))
+    opts = crom.GNOptions(max_iter=w.max_iter, tol_step=TOL_STEP)
+    q0 = np.asarray(w.ic, dtype=np.float64).copy()  # a generic starting latent (r = 3)
+    q = [torch.from_numpy(q0[None].copy()).to(dev), torch.empty(1, w.r, dtype=torch.float64, device=dev)]
+    nu = torch.tensor([w.nu], dtype=torch.float64, device=dev)
+    for i in range(10):
+        st.step(q[i % 2], nu, w.dt, opts, q_next=q[(i + 1) % 2])
+    q[0].copy_(torch.from_numpy(q0[None].copy()))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.c1_steps):
+        st.step(q[i % 2], nu, w.dt, opts, q_next=q[(i + 1) % 2])
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    q_gpu = q[args.c1_steps % 2].cpu().numpy()[0]
+    out = {"workload": f"1D heat, nu {w.nu}, {w.n_samples} samples, dt {w.dt}, {args.c1_steps} GN steps "
+                       f"(<= {w.max_iter} iterations), FP32",
+           "gpu_s": t_gpu, "us_per_step": t_gpu / args.c1_steps * 1e6,
+           "latent_steps_per_s": args.c1_steps / t_gpu}
+    if args.c1_cpu:
+        from threadpoolctl import threadpool_limits
+        odec = mlp.MLPDecoder(w.layers, w.m)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            qs, _ = ostep.heat_rollout(odec, w.samples.astype(np.float64), q0, w.nu, w.dt, args.c1_steps,
+                                       GNOptions(max_iter=w.max_iter, tol_step=TOL_STEP))
+            t_cpu = time.perf_counter() - t0
+        out["oracle_cpu_s_1_thread"] = t_cpu
+        out["gpu_vs_oracle_q_maxdiff"] = float(np.abs(q_gpu - qs[-1]).max())
+        out["q_final_maxabs"] = float(np.abs(qs[-1]).max())
+    return out
+
+
+def config3_leg(args, crom, torch, dev):
+    """3D neo-Hookean bar (decoder (3 + 16) -> 6 x ELU 256 -> 3, 500 samples
+    of the 64 x 16 x 16 nodes, the face X_1 = 0 clamped, lam 1e4, mu 4e3,
+    rho0 1000, gravity, dt 1e-3): one instance's latent step from a fixed
+    state (Gauss-Newton with 5 iterations, and linearised), repeated, and the
+    full-field decode of 16,384 nodes.  A point-eval is one sample through all 26 columns (value, 3
+    gradient, 6 Hessian, 16 latent entries; 17,080,832 FLOP)."""
+    from workloads import Elastic3D
+    w = Elastic3D(seed=args.seed)
+    X = w.nodes[w.sample_idx].astype(np.float32)
+    clamp = (X[:, 0] == 0.0).astype(np.uint8)
+    W3, D3, M3, R3 = 256, 6, 3, 16
+    f_val = 2 * (M3 * W3 + (D3 - 1) * W3 * W3 + W3 * 3)
+    f_tan = 2 * ((D3 - 1) * W3 * W3 + W3 * 3)
+    f_pe = f_val + 25 * f_tan
+    coef = torch.tensor([[w.lam, w.mu, w.rho0, *w.gravity]], dtype=torch.float64, device=dev)
+    nodes = torch.from_numpy(w.nodes).to(dev)
+    out = {"workload": f"neo-Hookean bar 64x16x16, {len(X)} samples, dt {w.dt}", "flop_per_point_eval": f_pe}
+    for prec in (args.prec, "fp32") if args.prec != "fp32" else ("fp32",):
+        dec = crom.Decoder.from_layers(w.layers, w.m, precision=prec, device=dev)
+        st = crom.Stepper(dec, [0, len(X)], torch.from_numpy(X).to(dev), torch.from_numpy(clamp).to(dev),
+                          pde="neohookean")
+        res = {}
+        for name, opts in (("gn", crom.GNOptions(max_iter=5, tol_step=TOL_STEP)),
+                           ("lls", crom.GNOptions(max_iter=1, linearized=True))):
+            # every timed step starts from the same state (the untrained bar's
+            # rollout would wander into degenerate latents within a few steps)
+            q = torch.from_numpy(w.q0[None].copy()).to(dev)
+            q_prev = q - 1e-3
+            q_next = torch.empty_like(q)
+            for _ in range(3):
+                st.step(q, coef, w.dt, opts, q_next=q_next, q_prev=q_prev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.c3_steps):
+                st.step(q, coef, w.dt, opts, q_next=q_next, q_prev=q_prev)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / args.c3_steps
+            inf = st.info()[0]
+            fl = len(X) * (f_pe + (int(inf["ls_evals"]) + int(inf["iters"]) * R3) * f_tan) if not opts.linearized \
+                else len(X) * f_pe
+            res[name] = {"ms_per_step": t * 1e3, "latent_steps_per_s": 1.0 / t, "point_evals_per_s": fl / f_pe / t,
+                         "achieved_tflops": fl / t / 1e12, "frac_of_peak": fl / t / 1e12 / PEAK[prec],
+                         "gn_iters_last": int(inf["iters"]), "flags_last": int(inf["flags"])}
+        g = torch.empty(len(nodes), 3, dtype=torch.float32, device=dev)
+        qd = torch.from_numpy(w.q0).to(dev)
+        for _ in range(3):
+            dec.decode(nodes, qd, out=g)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            dec.decode(nodes, qd, out=g)
+        e1.record()
+        torch.cuda.synchronize()
+        td = e0.elapsed_time(e1) * 1e-3 / 20
+        res["full_field_decode"] = {"ms": td * 1e3, "achieved_tflops": len(nodes) * f_val / td / 1e12}
+        out[prec] = res
+    if args.c3_cpu:
+        from oracle import elastic, mlp
+        from oracle.inversion import GNOptions
+        odec = mlp.MLPDecoder(w.layers, w.m)
+        t0 = time.perf_counter()
+        elastic.elastic_step(odec, X.astype(np.float64), w.q0, w.q0, w.lam, w.mu, w.rho0, w.gravity, w.dt,
+                             GNOptions(max_iter=5, tol_step=TOL_STEP), clamp)
+        out["oracle_cpu_s_per_gn_step"] = time.perf_counter() - t0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +356,10 @@ def main():
     ap.add_argument("--train-steps", type=int, default=8000,
                     help="BF16 training run whose network the batched leg rolls out (0: untrained)")
     ap.add_argument("--judge", type=int, default=8, help="instances whose rollout error the FD solver judges")
+    ap.add_argument("--c1-steps", type=int, default=1000, help="1D heat rollout length (0: skip)")
+    ap.add_argument("--c1-cpu", type=int, default=1, help="time the oracle's 1D rollout too")
+    ap.add_argument("--c3-steps", type=int, default=20, help="3D elastic steps timed (0: skip)")
+    ap.add_argument("--c3-cpu", type=int, default=0, help="time one oracle elastic step too (about 30 s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU: the instances of a batch are independent and the "
@@ -330,6 +445,8 @@ def main():
     torch.cuda.synchronize()
     lls_steps_per_s = args.steps / (time.perf_counter() - t1)
 
+    c1 = config1_leg(args, crom, torch, dev) if args.c1_steps > 0 else None
+    c3 = config3_leg(args, crom, torch, dev) if args.c3_steps > 0 else None
     training, trained = train_leg(args, crom, torch, dev) if args.train_time_steps > 0 else (None, None)
     batched = batched_leg(args, crom, torch, dev, trained) if args.batched_steps > 0 else None
     cpu = cpu_baseline(wl, nodes, args.cpu_steps) if args.cpu_steps > 0 else None
@@ -351,6 +468,8 @@ def main():
         "step_ms_avg": t_step.mean() * 1e3, "decode_ms_avg": t_dec.mean() * 1e3,
         "gn_iters_mean": float(its.mean()), "ls_evals_mean": float(lse.mean()),
         "roofline": roof,
+        "heat1d": c1,
+        "elastic3d": c3,
         "training": training,
         "batched": batched,
         "cpu_baseline": cpu,
