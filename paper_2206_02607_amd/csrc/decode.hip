@@ -88,9 +88,33 @@ struct DecodeArgs {
   float* dgdq;
 };
 
-template <class S, class C, int NB, int NW, int PREC>
-__global__ __launch_bounds__(NW * 64) void decode_kernel(DecodeArgs a) {
-  using E = Engine<S, C, NB, NW, PREC>;
+// Launch shape of the decode kernels per decoder width and arithmetic:
+// waves per workgroup, weight fragments (-1: by register estimate, 2:
+// streamed one K-block ahead) and the waves per SIMD the register
+// allocation must leave room for.  Measured on the 12-column 2D BF16 decode
+// (1M points): 4 waves holding a layer's fragments 381 TFLOP/s (380
+// registers, one workgroup per CU); 8 waves held to 128 registers 553;
+// 4 waves (two M-tiles each, so every activation fragment read from LDS
+// feeds two products) with streamed fragments held to 256 registers 633
+// (two workgroups per CU); 2 waves 488.
+template <class S, int PREC>
+struct DecodeTune {
+  static constexpr int NW = S::W <= 32 ? 2 : (S::W <= 128 ? 4 : 8);
+  static constexpr int PF = -1;
+  static constexpr int WPE = 1;
+};
+template <>
+struct DecodeTune<Shape<128, 2, 8, 1>, PREC_BF16> {
+  static constexpr int NW = 4, PF = 2, WPE = 2;
+};
+template <>
+struct DecodeTune<Shape<128, 2, 8, 1>, PREC_BF16_PURE> {
+  static constexpr int NW = 4, PF = 2, WPE = 2;
+};
+
+template <class S, class C, int NB, int NW, int PREC, int PF, int WPE>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void decode_kernel(DecodeArgs a) {
+  using E = Engine<S, C, NB, NW, PREC, PF>;
   extern __shared__ __align__(16) char lds[];
   const int64_t first = (int64_t)blockIdx.x * E::NPTS;
   const int64_t rem = a.P - first;
@@ -128,14 +152,16 @@ __global__ __launch_bounds__(NW * 64) void decode_kernel(DecodeArgs a) {
   }
 }
 
-template <class S, class C, int NB, int NW, int PREC>
+template <class S, class C, int NB, int PREC>
 static crom_status launch_decode(const DecodeArgs& a, hipStream_t st) {
-  using E = Engine<S, C, NB, NW, PREC>;
+  using T = DecodeTune<S, PREC>;
+  constexpr int NW = T::NW;
+  using E = Engine<S, C, NB, NW, PREC, T::PF>;
   const int lds_bytes = E::LDS_BYTES + E::PC::bytes(a.depth);
   if (lds_bytes > LDS_MAX) {
     return fail(CROM_ERR_UNSUPPORTED, "column set does not fit in LDS at this width/precision/depth");
   } else {
-    auto k = decode_kernel<S, C, NB, NW, PREC>;
+    auto k = decode_kernel<S, C, NB, NW, PREC, T::PF, T::WPE>;
     static bool attr = false;
     if (!attr) {
       crom_status s = set_lds(k, LDS_MAX);
@@ -155,10 +181,10 @@ template <class S, int NW, int PREC, bool XT, int D2, int NQ, int HB = 0,
 static crom_status run_pass(const DecodeArgs& a, hipStream_t st) {
   if constexpr (!XT && D2 == D2_NONE && NQ == 0) {
     using C = Cols<S::M, S::R, 1, 0, false, D2_NONE, 0>;
-    return launch_decode<S, C, 4, NW, PREC>(a, st);  // 64 points per workgroup
+    return launch_decode<S, C, 4, PREC>(a, st);  // 64 points per workgroup
   } else {
     using C = Cols<S::M, S::R, 1, 0, XT, D2, NQ, HB, NH>;
-    return launch_decode<S, C, 1, NW, PREC>(a, st);
+    return launch_decode<S, C, 1, PREC>(a, st);
   }
 }
 

@@ -170,7 +170,8 @@ struct ParamCache {
 // several engines share one cache).
 // PF: 1 prefetches the next layer's weight fragments into a second register
 // set during this layer's products, 0 loads each layer's fragments when the
-// layer starts, -1 chooses by a register estimate.
+// layer starts, 2 streams them one K-block ahead of their products, -1
+// chooses by a register estimate.
 template <class S, class C, int NB, int NW, int PREC, int PF = -1>
 struct Engine {
   static constexpr int W = S::W, M = S::M, R = S::R, D = S::D;
@@ -203,7 +204,7 @@ struct Engine {
   // A layer's fragments beyond 64 registers (width 256) are streamed: each
   // K-block's fragments are loaded one block ahead of their products
   // instead of holding the whole layer.
-  static constexpr bool STREAM = FRAG_REGS > 64;
+  static constexpr bool STREAM = FRAG_REGS > 64 || PF == 2;
   static constexpr bool PREFETCH = !STREAM && (PF >= 0 ? PF == 1 : 2 * FRAG_REGS + MT * NT * 4 <= 320);
   static constexpr int TG = 4;  // operand loads allowed to run ahead of their products
 
@@ -453,30 +454,26 @@ struct Engine {
 #pragma unroll
       for (int kb = 0; kb < KQ; ++kb) {
         CROM_STREAM_NEXT(kb)
+        // per column: its hi fragment feeds the hi*hi product and, on a split
+        // column, the lo*hi product too; the lo fragment feeds hi*lo
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
+          const int b = t / CC, c = t % CC;
           const bf16x8 bfr = act[(t * KQ + kb) * 64 + lane];
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt)
             acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(CROM_FRAG_HI(mt, kb), bfr, acc[mt][t], 0, 0, 0);
-          if ((t + 1) % TG == 0) __builtin_amdgcn_sched_barrier(0);  // bound the run-ahead
-        }
-        if constexpr (NSPL > 0) {
-#pragma unroll
-          for (int b = 0; b < NB; ++b) {
-#pragma unroll
-            for (int c = 0; c < CC; ++c) {
-              if (!is_split<C, PREC>(c)) continue;
-              const int t = b * CC + c;
-              const bf16x8 bh = act[(t * KQ + kb) * 64 + lane];
+          if constexpr (NSPL > 0) {
+            if (is_split<C, PREC>(c)) {
               const bf16x8 bl = act[(lo_tile(b, c) * KQ + kb) * 64 + lane];
 #pragma unroll
               for (int mt = 0; mt < MT; ++mt) {
                 acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(CROM_FRAG_HI(mt, kb), bl, acc[mt][t], 0, 0, 0);
-                acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(CROM_FRAG_LO(mt, kb), bh, acc[mt][t], 0, 0, 0);
+                acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(CROM_FRAG_LO(mt, kb), bfr, acc[mt][t], 0, 0, 0);
               }
             }
           }
+          if ((t + 1) % TG == 0) __builtin_amdgcn_sched_barrier(0);  // bound the run-ahead
         }
         __builtin_amdgcn_sched_barrier(0);  // as above
         CROM_STREAM_SHIFT()

@@ -45,8 +45,28 @@
 
 #include "common.hpp"
 
+// Launch shapes of the step kernels (waves, weight fragments, waves per SIMD
+// left room for); the linearised step is measured like the decode kernels.
 #ifndef CROM_ELASTIC_NW
 #define CROM_ELASTIC_NW 4
+#endif
+#ifndef CROM_STEP2D_NW
+#define CROM_STEP2D_NW 8
+#endif
+#ifndef CROM_STEP2D_PF
+#define CROM_STEP2D_PF 1
+#endif
+#ifndef CROM_STEP2D_WPE
+#define CROM_STEP2D_WPE 1
+#endif
+#ifndef CROM_LIN_WPE
+#define CROM_LIN_WPE 2
+#endif
+#ifndef CROM_LIN_PF
+#define CROM_LIN_PF 2
+#endif
+#ifndef CROM_LIN_NW
+#define CROM_LIN_NW 4
 #endif
 
 namespace crom {
@@ -923,8 +943,9 @@ struct StepTraits<S, NW, PREC, PF, PK_ELASTIC> {
   static constexpr int PAR = JD_OFF + PT * S::D * (S::R + TV) * 8;
 };
 
-template <class S, int NW, int PREC, int PF, int KIND>
-__global__ __launch_bounds__(NW * 64) void step_kernel(StepArgs a, int max_rounds) {
+template <class S, int NW, int PREC, int PF, int KIND, int WPE>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void step_kernel(StepArgs a,
+                                                                                          int max_rounds) {
   using T = StepTraits<S, NW, PREC, PF, KIND>;
   constexpr int PAR = T::PAR;
   extern __shared__ __align__(16) char lds[];
@@ -1010,6 +1031,92 @@ __global__ __launch_bounds__(NW * 64) void step_kernel(StepArgs a, int max_round
   }
 }
 
+// ---------------------------------------------------------------------------
+// The linearised heat step (Sec. "Linearization") without the persistent
+// protocol: one kernel evaluates every batch and stores its partial sums,
+// then one wave per instance sums them in batch order and solves.  Each
+// instance's result depends only on its own batches, so a batch of
+// instances reproduces each instance run alone bit for bit.
+// ---------------------------------------------------------------------------
+template <class S, int NW, int PREC, int PF, int WPE>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void lls_jets_kernel(StepArgs a) {
+  using E = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC, PF>;
+  extern __shared__ __align__(16) char lds[];
+  const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
+  if ((int64_t)blockIdx.x >= nblk) return;
+  float* par = reinterpret_cast<float*>(lds + E::LDS_BYTES);
+  E::PC::load(par, a.params, a.pi, a.depth, NW * 64);
+  __syncthreads();
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) eval_jets_batch<S, NW, PREC, PF>(a, lds, par, blk);
+}
+
+template <int R>
+__global__ __launch_bounds__(64) void lls_solve_kernel(StepArgs a) {
+  constexpr int NA = R * (R + 1) / 2;
+  constexpr int NRED = NA + R + TV;
+  static_assert(NRED <= 64, "one lane per reduced entry");
+  __shared__ double red[NRED];
+  const int inst = blockIdx.x, lane = threadIdx.x;
+  const int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
+  const int32_t b0 = first_blk[inst], b1 = first_blk[inst + 1];
+  if (b0 == b1) return;  // no samples: the setup kernel already reported it
+  const double* part = wsp<double>(a, a.L.partials);
+  if (lane < NRED) {
+    double acc = 0.0;
+    for (int32_t b = b0; b < b1; ++b) acc += part[(int64_t)b * NRED + lane];
+    red[lane] = acc;
+  }
+  __syncthreads();
+  const double phi = red[NA + R];
+  bool finite = isfinite(phi);
+  for (int e = 0; e < NA + R; ++e) finite &= (bool)isfinite(red[e]);
+  int flags = 0, iters = 0;
+  const double* qn = a.q_n + (int64_t)inst * R;
+  double qk = lane < R ? qn[lane] : 0.0;
+  if (!finite) {
+    flags = CROM_FLAG_NONFINITE;
+  } else {
+    double xk = 0.0;
+    if (!wave_chol_solve<R>(red, red + NA, xk)) {
+      flags = CROM_FLAG_SINGULAR;
+    } else {
+      qk += xk;
+      iters = 1;
+    }
+  }
+  if (lane < R) a.q_next[(int64_t)inst * R + lane] = qk;
+  if (lane == 0) {
+    crom_step_info inf;
+    inf.flags = flags;
+    inf.iters = iters;
+    inf.ls_evals = 0;
+    inf.rounds = 0;
+    inf.obj_first = phi;
+    inf.obj_last = phi;
+    a.info[inst] = inf;
+  }
+}
+
+template <class S, int NW, int PREC, int PF, int WPE>
+static crom_status launch_lls(StepArgs a, hipStream_t st) {
+  using E = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC, PF>;
+  const int lds_bytes = E::LDS_BYTES + E::PC::bytes(a.depth);
+  if (lds_bytes > LDS_MAX) return fail(CROM_ERR_UNSUPPORTED, "network too deep for the LDS");
+  static_assert(PT * S::R * 8 + PT * TV * 8 <= E::ACT_REGION, "staging fits");
+  auto k = lls_jets_kernel<S, NW, PREC, PF, WPE>;
+  crom_status s = set_lds(k, lds_bytes);
+  if (s != CROM_OK) return s;
+  hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(SETUP_THREADS), 0, st, a);
+  if ((s = hip_check(hipGetLastError(), "setup launch")) != CROM_OK) return s;
+  int64_t g = a.L.nblk_max;
+  if (g > 4096) g = 4096;  // each workgroup loads the parameters once for its batches
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k, dim3((unsigned)g), dim3(NW * 64), lds_bytes, st, a);
+  if ((s = hip_check(hipGetLastError(), "lls launch")) != CROM_OK) return s;
+  hipLaunchKernelGGL(lls_solve_kernel<S::R>, dim3((unsigned)a.n_inst), dim3(64), 0, st, a);
+  return hip_check(hipGetLastError(), "lls solve launch");
+}
+
 // One engine pass of the elastic preparation over every batch.
 template <class S, class C, int NW, int PREC>
 static crom_status launch_jets_pass(const StepArgs& a, int qb, hipStream_t st) {
@@ -1048,7 +1155,7 @@ static crom_status elastic_prepare(const StepArgs& a, hipStream_t st) {
   }
 }
 
-template <class S, int NW, int PREC, int PF, int KIND = PK_HEAT>
+template <class S, int NW, int PREC, int PF, int KIND = PK_HEAT, int WPE = 1>
 static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
   using T = StepTraits<S, NW, PREC, PF, KIND>;
   constexpr int PAR = T::PAR;
@@ -1063,7 +1170,7 @@ static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
                     (NW * 64 + S::R * (S::R + 1) / 2 + S::R + TV + S::R * S::R + S::R) * 8 <= PAR,
                 "solve scratch fits below the parameter cache");
   static_assert(NW * 64 >= S::R * (S::R + 1) / 2 + S::R + TV, "one thread per reduced entry");
-  auto k = step_kernel<S, NW, PREC, PF, KIND>;
+  auto k = step_kernel<S, NW, PREC, PF, KIND, WPE>;
   static int resident = 0, resident_lds = -1;
   if (resident_lds != lds_bytes) {
     crom_status s = set_lds(k, LDS_MAX - (int)sizeof(double) * TV * RMAX - 64);
@@ -1097,12 +1204,23 @@ static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
 // Waves per workgroup and weight prefetch per precision, chosen so that the
 // persistent kernel stays clear of register spills: bfloat16 fragments are
 // half the size, so BF16 and BF16_PURE afford eight waves with prefetch.
-template <class S, int NWB, int NWF>
+template <class S, int NWB, int NWF, int PFB = 1, int WPEB = 1>
 static crom_status step_prec(int prec, const StepArgs& a, int rounds, hipStream_t st) {
+  if (a.linearized) {
+    // four waves with two M-tiles each and streamed weights: the measured
+    // best for the 12-column engine (two workgroups per CU)
+    constexpr int NWL = S::MTILES < CROM_LIN_NW ? S::MTILES : CROM_LIN_NW;
+    switch (prec) {
+      case CROM_PREC_FP32: return launch_lls<S, NWF, PREC_FP32, 0, 1>(a, st);
+      case CROM_PREC_BF16: return launch_lls<S, NWL, PREC_BF16, CROM_LIN_PF, CROM_LIN_WPE>(a, st);
+      case CROM_PREC_BF16_PURE: return launch_lls<S, NWL, PREC_BF16_PURE, CROM_LIN_PF, CROM_LIN_WPE>(a, st);
+      default: return launch_lls<S, NWF, PREC_BF16X3, 0, 1>(a, st);
+    }
+  }
   switch (prec) {
     case CROM_PREC_FP32: return launch_step<S, NWF, PREC_FP32, 0>(a, rounds, st);
-    case CROM_PREC_BF16: return launch_step<S, NWB, PREC_BF16, 1>(a, rounds, st);
-    case CROM_PREC_BF16_PURE: return launch_step<S, NWB, PREC_BF16_PURE, 1>(a, rounds, st);
+    case CROM_PREC_BF16: return launch_step<S, NWB, PREC_BF16, PFB, PK_HEAT, WPEB>(a, rounds, st);
+    case CROM_PREC_BF16_PURE: return launch_step<S, NWB, PREC_BF16_PURE, PFB, PK_HEAT, WPEB>(a, rounds, st);
     default: return launch_step<S, NWF, PREC_BF16X3, 0>(a, rounds, st);
   }
 }
@@ -1216,7 +1334,9 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (shape_id(net->m, net->r, net->d, net->width)) {
     case SHAPE_1D: return step_prec<Shape<32, 1, 3, 1>, 2, 2>(net->precision, a, (int)rounds, st);
-    case SHAPE_2D: return step_prec<Shape<128, 2, 8, 1>, 8, 4>(net->precision, a, (int)rounds, st);
+    case SHAPE_2D:
+      return step_prec<Shape<128, 2, 8, 1>, CROM_STEP2D_NW, 4, CROM_STEP2D_PF, CROM_STEP2D_WPE>(net->precision, a,
+                                                                                         (int)rounds, st);
     case SHAPE_3D: return step_prec_elastic<Shape<256, 3, 16, 3>, CROM_ELASTIC_NW>(net->precision, a, (int)rounds, st);
     default: return fail(CROM_ERR_UNSUPPORTED, "shape");
   }
