@@ -353,7 +353,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--train-time-steps", type=int, default=50)
-    ap.add_argument("--train-steps", type=int, default=8000,
+    ap.add_argument("--train-steps", type=int, default=20000,
                     help="BF16 training run whose network the batched leg rolls out (0: untrained)")
     ap.add_argument("--judge", type=int, default=8, help="instances whose rollout error the FD solver judges")
     ap.add_argument("--c1-steps", type=int, default=1000, help="1D heat rollout length (0: skip)")

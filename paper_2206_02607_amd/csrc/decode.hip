@@ -116,12 +116,14 @@ template <class S, class C, int NB, int NW, int PREC, int PF, int WPE>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void decode_kernel(DecodeArgs a) {
   using E = Engine<S, C, NB, NW, PREC, PF>;
   extern __shared__ __align__(16) char lds[];
-  const int64_t first = (int64_t)blockIdx.x * E::NPTS;
+  float* par = reinterpret_cast<float*>(lds + E::LDS_BYTES);
+  E::PC::load(par, a.params, a.pi, a.depth, E::THREADS);  // once for all of this workgroup's batches
+  __syncthreads();
+  const int64_t nbatch = (a.P + E::NPTS - 1) / E::NPTS;
+  for (int64_t bi = blockIdx.x; bi < nbatch; bi += gridDim.x) {
+  const int64_t first = bi * E::NPTS;
   const int64_t rem = a.P - first;
   const int n_valid = rem < E::NPTS ? (int)rem : E::NPTS;
-  float* par = reinterpret_cast<float*>(lds + E::LDS_BYTES);
-  E::PC::load(par, a.params, a.pi, a.depth, E::THREADS);
-  __syncthreads();
   E::stage(lds, a.x, first, n_valid, a.q, S::R, nullptr, 0, par);
   __syncthreads();
   E::run(lds, par, a.packed, a.depth, a.qb);
@@ -150,6 +152,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       a.dgdq[(p * D + oo) * R + a.qb + (c - C::Q0)] = v;
     }
   }
+  __syncthreads();  // res is read before the next batch may overwrite the LDS
+  }
 }
 
 template <class S, class C, int NB, int PREC>
@@ -168,8 +172,11 @@ static crom_status launch_decode(const DecodeArgs& a, hipStream_t st) {
       if (s != CROM_OK) return s;
       attr = true;
     }
-    const int64_t blocks = (a.P + E::NPTS - 1) / E::NPTS;
+    int64_t blocks = (a.P + E::NPTS - 1) / E::NPTS;
     if (blocks > 0x7fffffff) return fail(CROM_ERR_INVALID_ARG, "P too large");
+    // a few workgroups per CU, each looping over batches with its parameter
+    // cache loaded once
+    if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(E::THREADS), lds_bytes, st, a);
     return hip_check(hipGetLastError(), "decode launch");
   }

@@ -191,20 +191,31 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       }
 }
 
-// Sum of split-K partials in split order, then the epilogue (none, bias,
-// or bias + ELU) and the FP32 store.
-__global__ void splitk_reduce_kernel(const float* __restrict__ part, int splits, int M, int N,
-                                     float* C, int64_t ldc, int accumulate, int epi,
-                                     const float* __restrict__ bias) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)M * N;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    float s = 0.0f;
-    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + e];
+// Sum of split-K partials, then the epilogue (none, bias, or bias + ELU)
+// and the FP32 store.  A block takes 64 outputs; each of its 4 lanes per
+// output adds the splits z = lane, lane + 4, ... in order, and the 4 lane
+// sums are added in lane order (a fixed order: the result is deterministic).
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ part, int splits, int M, int N,
+                                                            float* C, int64_t ldc, int accumulate, int epi,
+                                                            const float* __restrict__ bias) {
+  __shared__ float sh[4][64];
+  const int64_t MN = (int64_t)M * N;
+  const int64_t e = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int l4 = threadIdx.x >> 6;
+  float s = 0.0f;
+  if (e < MN) {
+#pragma unroll 8
+    for (int z = l4; z < splits; z += 4) s += part[(int64_t)z * MN + e];
+  }
+  sh[l4][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (threadIdx.x < 64 && e < MN) {
+    float t = ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
     const int m = (int)(e / N), n = (int)(e % N);
-    if (epi == EPI_BIAS || epi == EPI_BIAS_ELU) s += bias[n];
-    if (epi == EPI_BIAS_ELU) s = s > 0.0f ? s : __expf(s) - 1.0f;
+    if (epi == EPI_BIAS || epi == EPI_BIAS_ELU) t += bias[n];
+    if (epi == EPI_BIAS_ELU) t = t > 0.0f ? t : __expf(t) - 1.0f;
     float* c = &C[(int64_t)m * ldc + n];
-    *c = accumulate ? *c + s : s;
+    *c = accumulate ? *c + t : t;
   }
 }
 

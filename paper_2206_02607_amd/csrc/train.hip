@@ -16,6 +16,8 @@
 
 namespace crom {
 
+constexpr int MAX_SPLITS = 256;  // split-K partial tiles at most
+
 // ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
@@ -284,10 +286,10 @@ static crom_status gemm(GemmArgs g, hipStream_t st) {
   if (g.part) {
     // split K so that there are a few hundred blocks
     const int64_t tiles = (int64_t)grid.x * grid.y;
-    int splits = (int)((512 + tiles - 1) / tiles);
+    int splits = (int)((1024 + tiles - 1) / tiles);
     const int maxs = (g.K + BK - 1) / BK;
     if (splits > maxs) splits = maxs;
-    if (splits > 64) splits = 64;
+    if (splits > MAX_SPLITS) splits = MAX_SPLITS;
     if (splits < 1) splits = 1;
     int kc = (g.K + splits - 1) / splits;
     kc = (kc + BK - 1) / BK * BK;
@@ -296,8 +298,8 @@ static crom_status gemm(GemmArgs g, hipStream_t st) {
     grid.z = splits;
     if (EPI == EPI_DELU) return fail(CROM_ERR_INVALID_ARG, "split-K carries no gate");
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_NONE>), grid, dim3(256), 0, st, g);
-    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for((int64_t)g.M * g.N)), dim3(256), 0, st, g.part,
-                       splits, g.M, g.N, g.C, g.ldc, g.accumulate, EPI, g.bias);
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)(((int64_t)g.M * g.N + 63) / 64)), dim3(256), 0, st,
+                       g.part, splits, g.M, g.N, g.C, g.ldc, g.accumulate, EPI, g.bias);
   } else {
     g.kchunk = g.K;
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI>), grid, dim3(256), 0, st, g);
@@ -357,7 +359,7 @@ struct DecoderPass {
     c = cv.take<float>((size_t)B * W);
     g = cv.take<float>((size_t)rows * D);
     dg = cv.take<float>((size_t)rows * D);
-    part = cv.take<float>((size_t)64 * W * W);
+    part = cv.take<float>((size_t)MAX_SPLITS * W * W);
     const int nw = 1 + n->m > D ? 1 + n->m : D;
     const int nmax = nw > 1 + D ? nw : 1 + D;
     cpart = cv.take<double>((size_t)(B > COLSUM_CHUNKS ? B : COLSUM_CHUNKS) * nmax * W);
@@ -470,7 +472,7 @@ struct EncoderPass {
     q = cv.take<float>((size_t)B * e->r);
     dq = cv.take<float>((size_t)B * e->r);
     h32 = cv.take<float>((size_t)B * e->hidden);
-    kpart = cv.take<float>((size_t)64 * B * e->hidden);
+    kpart = cv.take<float>((size_t)MAX_SPLITS * B * e->hidden);
     // column sums over the batch of dz1 [B][hidden] and of dq [B][r]
     const int cols = e->hidden > e->r ? e->hidden : e->r;
     cpart = cv.take<double>((size_t)COLSUM_CHUNKS * cols);
