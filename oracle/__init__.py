@@ -17,6 +17,7 @@ step       the three-stage latent step and rollouts
 elastic    neo-Hookean stress, its derivative and the explicit elastic update
 train      encoder/decoder reverse-mode gradients, MSE loss, Adam
 pod        POD basis baseline (the method without the learned decoder)
+sampling   robust greedy selection of the integration samples
 
 Parity status of each function is stated in its docstring; every function
 here is pinned by tests under ``tests/`` that do not call the GPU.
