@@ -47,6 +47,35 @@ TOL_STEP = 1e-6   # Gauss-Newton step tolerance, relative to 1 + |q| (both sides
 PEAK = {"bf16": 2500.0, "bf16x3": 2500.0, "bf16pure": 2500.0, "fp32": 157.3}  # TFLOP/s, dense
 
 
+def source_hash() -> str:
+    """sha256 of the kernel sources and the C header (identifies the build a
+    hardware-counter measurement was taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2206_02607_amd", "csrc")
+    for name in sorted(os.listdir(src)) + ["../../include/crom.h"]:
+        path = os.path.normpath(os.path.join(src, name))
+        if path.endswith((".hip", ".hpp", ".h")):
+            with open(path, "rb") as f:
+                h.update(os.path.basename(path).encode() + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    when it was taken on the current sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_2d_heat.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
 def step_flops(S: int, iters: int, ls_evals: int) -> float:
     """Algorithmic decoder FLOP of one latent step: the 12-column evaluation
     at q_n, then per Gauss-Newton iteration the r latent tangents at the new
@@ -360,6 +389,8 @@ def main():
     ap.add_argument("--c1-cpu", type=int, default=1, help="time the oracle's 1D rollout too")
     ap.add_argument("--c3-steps", type=int, default=20, help="3D elastic steps timed (0: skip)")
     ap.add_argument("--c3-cpu", type=int, default=0, help="time one oracle elastic step too (about 30 s)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="copy this many MiB once, untimed (a known-size kernel for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU: the instances of a batch are independent and the "
@@ -391,6 +422,12 @@ def main():
         if ev is not None:
             ev[2].record()
 
+    if args.copy_probe_mib > 0:
+        src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for i in range(args.warmup):
         one(i)
     torch.cuda.synchronize()
@@ -426,7 +463,8 @@ def main():
     t_avg, fl = cand[name]
     achieved = fl / t_avg / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.prec], "unit": "TFLOP/s",
-            "frac": achieved / PEAK[args.prec], "traffic": None,
+            "frac": achieved / PEAK[args.prec],
+            "traffic": measured_traffic({"decode": "decode_kernel", "step": "step_kernel"}[name]),
             "kernel": {"decode": "decode_kernel (full field, value column)",
                        "step": "step_kernel (cooperative latent step)"}[name],
             "avg_ms": t_avg * 1e3, "flop_per_launch": fl,

@@ -47,6 +47,10 @@
 
 // Launch shapes of the step kernels (waves, weight fragments, waves per SIMD
 // left room for); the linearised step is measured like the decode kernels.
+// Gauss-Newton problems with more batches than this run as round kernels.
+#ifndef ROUNDS_MIN_BATCHES
+#define ROUNDS_MIN_BATCHES 1024
+#endif
 #ifndef CROM_ELASTIC_NW
 #define CROM_ELASTIC_NW 4
 #endif
@@ -1117,6 +1121,85 @@ static crom_status launch_lls(StepArgs a, hipStream_t st) {
   return hip_check(hipGetLastError(), "lls solve launch");
 }
 
+// ---------------------------------------------------------------------------
+// Gauss-Newton for large batches as a sequence of kernels (one pass over the
+// active batches per round, then one workgroup per instance deciding), in
+// place of the persistent kernel's serial batches and per-batch handshake.
+// The batch evaluations, their engine configuration and the solve (same
+// code, same thread count, same summation order) are those of the
+// persistent kernel, so every instance gets the same bits on either path.
+// Rounds without an active instance return at once.
+// ---------------------------------------------------------------------------
+template <class S, int NW, int PREC, int PF, int WPE>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void gn_round_kernel(StepArgs a,
+                                                                                              int p) {
+  using T = StepTraits<S, NW, PREC, PF, PK_HEAT>;
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int s_ph;
+  __shared__ double qdl[TV * RMAX];
+  if (ld_c(wsp<int64_t>(a, a.L.act_phase) + p) == 0) return;  // uniform: nothing active in this round
+  const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
+  if ((int64_t)blockIdx.x >= nblk) return;
+  float* par = reinterpret_cast<float*>(lds + T::PAR);
+  T::E0::PC::load(par, a.params, a.pi, a.depth, NW * 64);
+  __syncthreads();
+  const int32_t* blk_inst = wsp<int32_t>(a, a.L.blk_inst);
+  const GNState* state = wsp<GNState>(a, a.L.state);
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int inst = blk_inst[blk];
+    if (p == 0) {
+      eval_jets_batch<S, NW, PREC, PF>(a, lds, par, blk);
+    } else {
+      if (threadIdx.x == 0) s_ph = ld_c(&state[inst].phase);
+      __syncthreads();
+      const int ph = s_ph;
+      __syncthreads();
+      if (ph != PH_TRIALS && ph != PH_REJAC) continue;
+      eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, -1);
+    }
+  }
+}
+
+template <int R, int NTH>
+__global__ __launch_bounds__(NTH) void gn_solve_kernel(StepArgs a, int p, int is_last) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int s_ph;
+  const int inst = blockIdx.x;
+  const int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
+  if (first_blk[inst] == first_blk[inst + 1]) return;  // no samples: reported by the setup kernel
+  if (threadIdx.x == 0) s_ph = ld_c(&wsp<GNState>(a, a.L.state)[inst].phase);
+  __syncthreads();
+  const int ph = s_ph;
+  const bool active = p == 0 ? ph == PH_INIT : (ph == PH_TRIALS || ph == PH_REJAC);
+  if (!active) return;
+  solve_instance<R>(a, lds, inst, p, is_last != 0);
+}
+
+template <class S, int NW, int PREC, int PF, int WPE>
+static crom_status launch_gn_rounds(StepArgs a, int max_rounds, hipStream_t st) {
+  using T = StepTraits<S, NW, PREC, PF, PK_HEAT>;
+  const int lds_bytes = T::PAR + T::E0::PC::bytes(a.depth);
+  if (lds_bytes + (int)sizeof(double) * TV * RMAX + 64 > LDS_MAX)
+    return fail(CROM_ERR_UNSUPPORTED, "network too deep for the step kernel's LDS");
+  constexpr int NRED = S::R * (S::R + 1) / 2 + S::R + TV;
+  constexpr int SOLVE_LDS =
+      (int)((sizeof(GNState) + 15) / 16 * 16) + ((NW * 64) / NRED + 1) * NRED * 8 + 64;
+  auto kr = gn_round_kernel<S, NW, PREC, PF, WPE>;
+  auto ks = gn_solve_kernel<S::R, NW * 64>;
+  crom_status s = set_lds(kr, lds_bytes);
+  if (s != CROM_OK) return s;
+  hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(SETUP_THREADS), 0, st, a);
+  if ((s = hip_check(hipGetLastError(), "setup launch")) != CROM_OK) return s;
+  int64_t g = a.L.nblk_max;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  for (int p = 0; p <= max_rounds; ++p) {
+    hipLaunchKernelGGL(kr, dim3((unsigned)g), dim3(NW * 64), lds_bytes, st, a, p);
+    hipLaunchKernelGGL(ks, dim3((unsigned)a.n_inst), dim3(NW * 64), SOLVE_LDS, st, a, p, (int)(p == max_rounds));
+  }
+  return hip_check(hipGetLastError(), "round launches");
+}
+
 // One engine pass of the elastic preparation over every batch.
 template <class S, class C, int NW, int PREC>
 static crom_status launch_jets_pass(const StepArgs& a, int qb, hipStream_t st) {
@@ -1215,6 +1298,14 @@ static crom_status step_prec(int prec, const StepArgs& a, int rounds, hipStream_
       case CROM_PREC_BF16: return launch_lls<S, NWL, PREC_BF16, CROM_LIN_PF, CROM_LIN_WPE>(a, st);
       case CROM_PREC_BF16_PURE: return launch_lls<S, NWL, PREC_BF16_PURE, CROM_LIN_PF, CROM_LIN_WPE>(a, st);
       default: return launch_lls<S, NWF, PREC_BF16X3, 0, 1>(a, st);
+    }
+  }
+  if (a.L.nblk_max > ROUNDS_MIN_BATCHES) {
+    switch (prec) {
+      case CROM_PREC_FP32: return launch_gn_rounds<S, NWF, PREC_FP32, 0, 1>(a, rounds, st);
+      case CROM_PREC_BF16: return launch_gn_rounds<S, NWB, PREC_BF16, PFB, WPEB>(a, rounds, st);
+      case CROM_PREC_BF16_PURE: return launch_gn_rounds<S, NWB, PREC_BF16_PURE, PFB, WPEB>(a, rounds, st);
+      default: return launch_gn_rounds<S, NWF, PREC_BF16X3, 0, 1>(a, rounds, st);
     }
   }
   switch (prec) {

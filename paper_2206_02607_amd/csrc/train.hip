@@ -38,33 +38,47 @@ __global__ void fold_kernel(const float* __restrict__ W1, const float* __restric
   }
 }
 
-// a1[row][u] = ELU(sum_i W1[u][i] x[p][i] + c[b][u]),  row = b * P + p
+// a1[row][u] = ELU(sum_i W1[u][i] x[p][i] + c[b][u]),  row = b * P + p.
+// A thread takes 8 consecutive units of one row (W is a multiple of 8).
 template <class T>
 __global__ void layer1_kernel(const float* __restrict__ W1, const float* __restrict__ c, const float* __restrict__ x,
                               int64_t P, int64_t rows, int W, int m, int r, T* __restrict__ a1) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows * W; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = i / W;
-    const int u = (int)(i % W);
+  typedef T vec8 __attribute__((ext_vector_type(8)));
+  const int G = W / 8;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows * G; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = i / G;
+    const int u0 = (int)(i - row * G) * 8;
     const int64_t b = row / P, p = row - b * P;
-    float z = c[b * W + u];
-    for (int k = 0; k < m; ++k) z += W1[u * (m + r) + k] * x[p * m + k];
-    a1[i] = (T)(z > 0.0f ? z : __expf(z) - 1.0f);
+    float xv[3] = {0.0f, 0.0f, 0.0f};
+    for (int k = 0; k < m; ++k) xv[k] = x[p * m + k];
+    vec8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int u = u0 + e;
+      float z = c[b * W + u];
+      for (int k = 0; k < m; ++k) z += W1[u * (m + r) + k] * xv[k];
+      o[e] = (T)(z > 0.0f ? z : __expf(z) - 1.0f);
+    }
+    *reinterpret_cast<vec8*>(&a1[row * W + u0]) = o;
   }
 }
 
-// g[row][o] = sum_u Wout[o][u] a[row][u] + bout[o]: one wave per row
+// g[row][o] = sum_u Wout[o][u] a[row][u] + bout[o]: one thread per row,
+// 8 units per load, in unit order.
 template <class T>
 __global__ void output_kernel(const T* __restrict__ a, const float* __restrict__ Wout, const float* __restrict__ bout,
                               int64_t rows, int W, int D, float* __restrict__ g) {
-  const int lane = threadIdx.x & 63;
-  for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 64; row < rows;
-       row += ((int64_t)gridDim.x * blockDim.x) / 64) {
-    for (int o = 0; o < D; ++o) {
-      float s = 0.0f;
-      for (int u = lane; u < W; u += 64) s += Wout[o * W + u] * (float)a[row * W + u];
-      for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-      if (lane == 0) g[row * D + o] = s + bout[o];
+  typedef T vec8 __attribute__((ext_vector_type(8)));
+  for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    float s[3] = {0.0f, 0.0f, 0.0f};
+    for (int u0 = 0; u0 < W; u0 += 8) {
+      const vec8 v = *reinterpret_cast<const vec8*>(&a[row * W + u0]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        for (int o = 0; o < D; ++o) s[o] += Wout[o * W + u0 + e] * (float)v[e];
     }
+    for (int o = 0; o < D; ++o) g[row * D + o] = s[o] + bout[o];
   }
 }
 
@@ -103,16 +117,27 @@ __global__ __launch_bounds__(256) void mse_final_kernel(const double* __restrict
   if (threadIdx.x == 0) *loss = (float)(sh[0] / (double)n);
 }
 
-// dz[row][u] = (sum_o dg[row][o] Wout[o][u]) * ELU'(a[row][u])
+// dz[row][u] = (sum_o dg[row][o] Wout[o][u]) * ELU'(a[row][u]); 8 units
+// of one row per thread.
 template <class T>
 __global__ void dz_last_kernel(const float* __restrict__ dg, const float* __restrict__ Wout, const T* __restrict__ a,
                                int64_t rows, int W, int D, T* __restrict__ dz) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows * W; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = i / W;
-    const int u = (int)(i % W);
-    float s = 0.0f;
-    for (int o = 0; o < D; ++o) s += dg[row * D + o] * Wout[o * W + u];
-    dz[i] = (T)(s * elu_d1_from_a((float)a[i]));
+  typedef T vec8 __attribute__((ext_vector_type(8)));
+  const int G = W / 8;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows * G; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = i / G;
+    const int u0 = (int)(i - row * G) * 8;
+    float d[3] = {0.0f, 0.0f, 0.0f};
+    for (int o = 0; o < D; ++o) d[o] = dg[row * D + o];
+    const vec8 av = *reinterpret_cast<const vec8*>(&a[row * W + u0]);
+    vec8 out;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float s = 0.0f;
+      for (int o = 0; o < D; ++o) s += d[o] * Wout[o * W + u0 + e];
+      out[e] = (T)(s * elu_d1_from_a((float)av[e]));
+    }
+    *reinterpret_cast<vec8*>(&dz[row * W + u0]) = out;
   }
 }
 
@@ -384,8 +409,8 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
   // ---- forward ----
   hipLaunchKernelGGL(fold_kernel, dim3(grid_for((int64_t)B * W)), dim3(256), 0, st, prm + pi.w[0], prm + pi.b[0], q,
                      B, W, m, r, ws.c);
-  hipLaunchKernelGGL((layer1_kernel<T>), dim3(grid_for(rows * W)), dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows,
-                     W, m, r, ws.a[0]);
+  hipLaunchKernelGGL((layer1_kernel<T>), dim3(grid_for(rows * W / 8)), dim3(256), 0, st, prm + pi.w[0], ws.c, x, P,
+                     rows, W, m, r, ws.a[0]);
   for (int l = 1; l < depth; ++l) {
     GemmArgs g = gemm_args((int)rows, W, W, ws.a[l - 1], W, ws.wt[l], W);
     g.bias = prm + pi.b[l];
@@ -398,7 +423,7 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
     }
     if ((s = gemm<T, false, true, EPI_BIAS_ELU>(g, st)) != CROM_OK) return s;
   }
-  hipLaunchKernelGGL((output_kernel<T>), dim3(grid_for(rows * 64)), dim3(256), 0, st, ws.a[depth - 1],
+  hipLaunchKernelGGL((output_kernel<T>), dim3(grid_for(rows)), dim3(256), 0, st, ws.a[depth - 1],
                      prm + pi.w[depth], prm + pi.b[depth], rows, W, D, ws.g);
   const float* dg = dg_in;
   if (!dg_in) {
@@ -416,7 +441,7 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
                        (int64_t)D * W);
     colsum<float>(dg, D, D, 1, rows, nullptr, 1, 0, 1, ws.cpart, COLSUM_CHUNKS, ws.csum, st);
     hipLaunchKernelGGL(d2f_kernel, dim3(1), dim3(64), 0, st, ws.csum, grad + pi.b[depth], (int64_t)D);
-    hipLaunchKernelGGL((dz_last_kernel<T>), dim3(grid_for(rows * W)), dim3(256), 0, st, dg, prm + pi.w[depth],
+    hipLaunchKernelGGL((dz_last_kernel<T>), dim3(grid_for(rows * W / 8)), dim3(256), 0, st, dg, prm + pi.w[depth],
                        ws.a[depth - 1], rows, W, D, ws.dz0);
   }
   // ---- hidden layers ----

@@ -183,3 +183,27 @@ def test_rollout_heat1d_matches_oracle(cuda):
     e = _dg_err(wl.layers, 1, wl.samples, q0, qg.cpu().numpy()[0], qo)
     print(f"50-step rollout dg err {e:.2e}")
     assert e <= 1e-3
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_round_kernels_match_persistent(cuda, prec):
+    """Large batches (more than 1,024 sample batches) run Gauss-Newton as
+    round kernels, small ones in the persistent kernel; both evaluate the
+    same batches with the same engine and solve each instance in the same
+    order, so a large batch reproduces each instance run alone bit for bit."""
+    import torch
+    from paper_2206_02607_amd import crom
+    wb = Batched2D(seed=3, n_inst=12, s_min=1400, s_max=1600)
+    assert int(wb.offsets[-1]) // 16 + wb.n_inst > 1024  # the round-kernel path
+    dec = crom.Decoder.from_layers(wb.layers, wb.m, precision=prec, device=cuda)
+    opts = crom.GNOptions(max_iter=5, tol_step=1e-8)
+    st = crom.Stepper(dec, wb.offsets, torch.from_numpy(wb.samples).to(cuda))
+    qb = st.step(torch.from_numpy(wb.q0).to(cuda), torch.from_numpy(wb.mu).to(cuda), wb.dt, opts).cpu().numpy()
+    ib = st.info()
+    assert np.all(ib["iters"] >= 1)
+    for i in range(wb.n_inst):
+        lo, hi = int(wb.offsets[i]), int(wb.offsets[i + 1])
+        s1 = crom.Stepper(dec, [0, hi - lo], torch.from_numpy(wb.samples[lo:hi]).to(cuda))
+        q1 = s1.step(torch.from_numpy(wb.q0[i:i + 1]).to(cuda), torch.tensor([wb.mu[i]]), wb.dt, opts).cpu().numpy()
+        np.testing.assert_array_equal(qb[i], q1[0])
+        assert ib[i].tobytes() == s1.info()[0].tobytes()
