@@ -336,6 +336,109 @@ crom_status crom_decode_vjp(const crom_net* net, const float* x, int64_t P, cons
                             int32_t B, const float* dg, float* grad_params, float* grad_q,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Robust selection of the integration samples (Appendix "Robust Sampling",
+ * Alg. "Robust sampling"): a greedy precomputation that grows a set M of
+ * integration samples, drawn from the P nodes x_i of the full-order
+ * discretisation, until the latent dynamics run with M reproduce the
+ * full-order solution of every training parameter mu_k at the final time.
+ *
+ * Residual vector of a set (the algorithm's Calculate_Residual): with
+ * q_end(mu_k) the latent after the rollout of parameter k with samples M,
+ *   res[i] = sum_k | g(x_i, q_end(mu_k)) - f(x_i, t_end; mu_k) |_2
+ * and its metric (the algorithm's Metric) mean_i res[i] + max_i res[i].
+ * Rankings: a NaN residual or metric ranks above every number in the
+ * largest-residual ranking and below every number in the smallest-metric
+ * choice; ties go to the lower node index and to the earlier candidate. */
+
+/* Residual vectors and metrics of n_set sample sets whose final latents are
+ * given (the decode of every node and the comparison run fused in one
+ * kernel; the decoded fields are not stored).
+ *   nodes  [P][m] FP32 node coordinates
+ *   q      [n_set][n_mu][r] FP64 final latents (set s, parameter k)
+ *   ref    [n_mu][P][d] FP64 full-order field at the final time
+ *   res    [n_set][P] FP64 out, metric [n_set] FP64 out (may be NULL)
+ * Sum over k in increasing order; P >= 1, n_set >= 1, n_mu >= 1. */
+crom_status crom_sampling_residual(const crom_net* net, const float* nodes, int64_t P, int32_t n_set,
+                                   int32_t n_mu, const double* q, const double* ref, double* res,
+                                   double* metric, void* stream);
+
+/* The n nodes outside the set with the largest residuals (the algorithm's
+ * Max_Indices), in ranking order.
+ *   res    [P] FP64 residual vector
+ *   member NULL or [P] uint8: 1 = node already in the set (never a candidate)
+ *   cand   [n] int32 out; entries past the number of eligible nodes are -1
+ * 1 <= n <= CROM_SAMPLING_MAX_TRY. */
+enum { CROM_SAMPLING_MAX_TRY = 64 };
+crom_status crom_sampling_candidates(const double* res, int64_t P, const uint8_t* member, int32_t n,
+                                     int32_t* cand, void* stream);
+
+/* Options of the greedy loop (host struct).
+ *   n_try        candidates per round, 1 .. CROM_SAMPLING_MAX_TRY (the
+ *                appendix uses 10)
+ *   max_samples  the loop also stops when the set holds this many nodes
+ *                (n_init <= max_samples <= P)
+ *   n_steps      latent steps from the initial latents to the final time
+ *   target       the loop stops once the metric is below this value */
+typedef struct {
+  int32_t n_try, max_samples;
+  int64_t n_steps;
+  double target;
+} crom_sampling_opts;
+
+/* Outcome of crom_robust_sampling (host struct). */
+typedef struct {
+  int32_t n_samples; /* nodes in the returned set                          */
+  int32_t reached;   /* 1 when its metric is below the target              */
+  int32_t rounds;    /* greedy rounds run (nodes added)                    */
+  int32_t _pad;
+  double metric;     /* metric of the returned set                         */
+} crom_sampling_result;
+
+/* Workspace bytes of crom_robust_sampling (host out-parameter `bytes`). */
+crom_status crom_sampling_workspace(const crom_net* net, int32_t pde_kind, int32_t n_mu, int64_t P,
+                                    const crom_sampling_opts* opts, size_t* bytes);
+
+/* The greedy loop.  Each round runs, as one batch of crom_step calls, the
+ * rollouts of n_try x n_mu instances (candidate c with parameter k), each
+ * with the samples M + {candidate}, then their residual vectors; the host
+ * reads the n_try metrics back (one synchronisation per round) and appends
+ * the best candidate.  The residual vector of the chosen set is kept as the
+ * next round's (it is the same computation).
+ *   pde         kind, dt and coef [n_mu][n_coef] per training parameter
+ *               (as for crom_step; every instance of parameter k uses row k)
+ *   nodes       [P][m] FP32;  node_clamp NULL or [P] uint8 (Dirichlet node:
+ *               target 0 when it is a sample)
+ *   ref         [n_mu][P][d] FP64 full-order field at step n_steps
+ *   q0          [n_mu][r] FP64 initial latents (neo-Hookean: at rest)
+ *   gn          inversion options of every step (host)
+ *   samples     host [max_samples] int32: in, the first n_init entries are
+ *               the initial set (distinct node indices); out, the set in the
+ *               order the nodes joined it
+ *   result      host out
+ *   trace_cand, trace_metric  NULL or host [max_samples - n_init][n_try]:
+ *               each round's candidates and their metrics (-1 / NaN past
+ *               the round's candidate count)
+ * The initial set needs r <= d * n_init.  A rollout step that fails keeps
+ * its last iterate (crom_step's convention); the residual then measures
+ * it.  Unlike the other calls this one synchronises the stream every
+ * round. */
+crom_status crom_robust_sampling(const crom_net* net, const crom_pde* pde, int32_t n_mu, const float* nodes,
+                                 int64_t P, const uint8_t* node_clamp, const double* ref, const double* q0,
+                                 const crom_gn_opts* gn, const crom_sampling_opts* opts, int32_t* samples,
+                                 int32_t n_init, crom_sampling_result* result, int32_t* trace_cand,
+                                 double* trace_metric, void* ws, size_t ws_bytes, void* stream);
+
+/* Benchmark support.  crom_kernel_timer(1) starts a record on the calling
+ * host thread (dropping any earlier one): every later crom_step on this
+ * thread then records a pair of HIP events on its stream, right after its
+ * set-up launch and right after its last launch, so that the pair brackets
+ * the step's compute kernels.  crom_kernel_timer(0) stops recording.
+ * crom_kernel_timer_read waits for the recorded events and returns the
+ * summed milliseconds of the pairs and their number. */
+crom_status crom_kernel_timer(int32_t on);
+crom_status crom_kernel_timer_read(double* total_ms, int64_t* count);
+
 /* Debugging aid: when buf (device memory, 128 uint64) is not NULL, every
  * later crom_step writes the GPU wall-clock tick (100 MHz) at each phase
  * boundary of its step kernel's first and last workgroup into it: slots

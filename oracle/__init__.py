@@ -16,7 +16,6 @@ inversion  Cholesky, Gauss-Newton with backtracking, linearised inversion
 step       the three-stage latent step and rollouts
 elastic    neo-Hookean stress, its derivative and the explicit elastic update
 train      encoder/decoder reverse-mode gradients, MSE loss, Adam
-pod        POD basis baseline (the method without the learned decoder)
 sampling   robust greedy selection of the integration samples
 
 Parity status of each function is stated in its docstring; every function

@@ -46,6 +46,15 @@ class CromEncoder(Structure):
                 ("params", c_void_p)]
 
 
+class CromSamplingOpts(Structure):
+    _fields_ = [("n_try", c_int32), ("max_samples", c_int32), ("n_steps", c_int64), ("target", c_double)]
+
+
+class CromSamplingResult(Structure):
+    _fields_ = [("n_samples", c_int32), ("reached", c_int32), ("rounds", c_int32), ("_pad", c_int32),
+                ("metric", c_double)]
+
+
 INFO_DTYPE = np.dtype([("flags", "<i4"), ("iters", "<i4"), ("ls_evals", "<i4"), ("rounds", "<i4"),
                        ("obj_first", "<f8"), ("obj_last", "<f8")])
 
@@ -108,6 +117,21 @@ def lib():
         L.crom_decode_vjp_workspace.argtypes = [POINTER(CromNet), c_int32, c_int64, POINTER(c_size_t)]
         L.crom_decode_vjp.argtypes = [POINTER(CromNet), c_void_p, c_int64, c_void_p, c_int32,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+        L.crom_sampling_residual.argtypes = [POINTER(CromNet), c_void_p, c_int64, c_int32, c_int32, c_void_p,
+                                             c_void_p, c_void_p, c_void_p, c_void_p]
+        L.crom_sampling_candidates.argtypes = [c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_void_p]
+        L.crom_sampling_workspace.argtypes = [POINTER(CromNet), c_int32, c_int32, c_int64,
+                                              POINTER(CromSamplingOpts), POINTER(c_size_t)]
+        L.crom_robust_sampling.argtypes = [POINTER(CromNet), POINTER(CromPDE), c_int32, c_void_p, c_int64,
+                                           c_void_p, c_void_p, c_void_p, POINTER(CromGNOpts),
+                                           POINTER(CromSamplingOpts), c_void_p, c_int32,
+                                           POINTER(CromSamplingResult), c_void_p, c_void_p, c_void_p, c_size_t,
+                                           c_void_p]
+        L.crom_kernel_timer.argtypes = [c_int32]
+        L.crom_kernel_timer_read.argtypes = [POINTER(c_double), POINTER(c_int64)]
+        for name in ("crom_sampling_residual", "crom_sampling_candidates", "crom_sampling_workspace",
+                     "crom_robust_sampling", "crom_kernel_timer", "crom_kernel_timer_read"):
+            getattr(L, name).restype = c_int32
         for name in ("crom_net_pack", "crom_decode", "crom_decode_jac", "crom_decode_jac_x",
                      "crom_decode_jac_q", "crom_step_workspace", "crom_step", "crom_fd_heat",
                      "crom_train_workspace", "crom_train_grads", "crom_adam_step", "crom_train_step",
@@ -480,3 +504,115 @@ def fd_heat(u, nu, dx: float, dt: float, steps: int, scratch=None):
     _check(lib().crom_fd_heat(dim, shape, u.shape[0], _ptr(nu), per_node, dx, dt, steps, _ptr(u),
                               _ptr(scratch), _stream()), "crom_fd_heat")
     return u
+
+
+# ---------------------------------------------------------------------------
+# Robust sample selection (Appendix "Robust Sampling").
+# ---------------------------------------------------------------------------
+SAMPLING_MAX_TRY = 64
+
+
+def sampling_residual(dec: Decoder, nodes, q, ref):
+    """Residual vectors and metrics of sample sets from their final latents:
+    nodes [P, m] FP32, q [n_set, n_mu, r] FP64, ref [n_mu, P, d] FP64 (all on
+    the device).  Returns (res [n_set, P], metric [n_set]) FP64 tensors."""
+    torch = _torch()
+    dev = dec.params.device
+    nodes = nodes.to(device=dev, dtype=torch.float32).contiguous()
+    q = q.to(device=dev, dtype=torch.float64).contiguous()
+    ref = ref.to(device=dev, dtype=torch.float64).contiguous()
+    n_set, n_mu = int(q.shape[0]), int(q.shape[1])
+    P = int(nodes.shape[0])
+    if q.shape[2] != dec.r or ref.numel() != n_mu * P * dec.d:
+        raise CromError("q must be [n_set, n_mu, r] and ref [n_mu, P, d]")
+    res = torch.empty(n_set, P, dtype=torch.float64, device=dev)
+    metric = torch.empty(n_set, dtype=torch.float64, device=dev)
+    net = dec._net()
+    _check(lib().crom_sampling_residual(ctypes.byref(net), _ptr(nodes), P, n_set, n_mu, _ptr(q), _ptr(ref),
+                                        _ptr(res), _ptr(metric), _stream()), "crom_sampling_residual")
+    return res, metric
+
+
+def sampling_candidates(res, n: int, member=None):
+    """The n nodes outside `member` (uint8 mask or None) with the largest
+    residuals res [P] (FP64, device); -1 past the eligible nodes."""
+    torch = _torch()
+    res = res.to(torch.float64).contiguous()
+    if member is not None:
+        member = member.to(device=res.device, dtype=torch.uint8).contiguous()
+    cand = torch.empty(n, dtype=torch.int32, device=res.device)
+    _check(lib().crom_sampling_candidates(_ptr(res), res.numel(), _ptr(member), n, _ptr(cand), _stream()),
+           "crom_sampling_candidates")
+    return cand
+
+
+@dataclass
+class SamplingResult:
+    samples: np.ndarray            # the set, in the order the nodes joined it
+    metric: float                  # mean + max of its residual vector
+    reached: bool                  # metric < target
+    rounds: int
+    candidates: Optional[np.ndarray] = None   # [rounds, n_try] per round (-1 padded)
+    metrics: Optional[np.ndarray] = None      # [rounds, n_try] per round (NaN padded)
+
+
+def robust_sampling(dec: Decoder, nodes, ref, q0, coef, dt: float, init, n_steps: int, target: float,
+                    n_try: int = 10, max_samples: Optional[int] = None, opts: "GNOptions" = None,
+                    pde: str = "heat", node_clamp=None, trace: bool = False) -> SamplingResult:
+    """Greedy selection of integration samples from the nodes [P, m]
+    (crom_robust_sampling).  ref [n_mu, P, d] full-order field at step
+    n_steps per training parameter; q0 [n_mu, r] initial latents; coef per
+    parameter (heat: nu [n_mu]; neo-Hookean: [n_mu, 6]); init: initial node
+    indices."""
+    torch = _torch()
+    dev = dec.params.device
+    kind = {"heat": PDE_HEAT, "neohookean": PDE_NEOHOOKEAN}[pde]
+    nodes = nodes.to(device=dev, dtype=torch.float32).contiguous()
+    P = int(nodes.shape[0])
+    ref = ref.to(device=dev, dtype=torch.float64).contiguous()
+    q0 = torch.as_tensor(q0, dtype=torch.float64).to(dev).reshape(-1, dec.r).contiguous()
+    n_mu = int(q0.shape[0])
+    per = 1 if kind == PDE_HEAT else 6
+    coef = torch.as_tensor(coef, dtype=torch.float64).to(dev).reshape(n_mu, per).contiguous()
+    if node_clamp is not None:
+        node_clamp = node_clamp.to(device=dev, dtype=torch.uint8).contiguous()
+    init = np.asarray(init, dtype=np.int32).ravel()
+    max_samples = int(max_samples if max_samples is not None else P)
+    o = CromSamplingOpts(int(n_try), max_samples, int(n_steps), float(target))
+    net = dec._net()
+    nbytes = c_size_t(0)
+    _check(lib().crom_sampling_workspace(ctypes.byref(net), kind, n_mu, P, ctypes.byref(o), ctypes.byref(nbytes)),
+           "crom_sampling_workspace")
+    ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+    ws_ptr = (ws.data_ptr() + 255) // 256 * 256
+    samples = np.zeros(max_samples, dtype=np.int32)
+    samples[:init.size] = init
+    rounds_max = max(1, max_samples - init.size)
+    tc = np.full((rounds_max, n_try), -1, dtype=np.int32) if trace else None
+    tm = np.full((rounds_max, n_try), np.nan) if trace else None
+    g = (opts or GNOptions()).c_struct()
+    pd = CromPDE(kind, 0, float(dt), coef.data_ptr())
+    out = CromSamplingResult()
+    _check(lib().crom_robust_sampling(ctypes.byref(net), ctypes.byref(pd), n_mu, _ptr(nodes), P, _ptr(node_clamp),
+                                      _ptr(ref), _ptr(q0), ctypes.byref(g), ctypes.byref(o),
+                                      samples.ctypes.data_as(c_void_p), int(init.size), ctypes.byref(out),
+                                      None if tc is None else tc.ctypes.data_as(c_void_p),
+                                      None if tm is None else tm.ctypes.data_as(c_void_p),
+                                      ws_ptr, int(nbytes.value), _stream()), "crom_robust_sampling")
+    n = int(out.n_samples)
+    return SamplingResult(samples[:n].copy(), float(out.metric), bool(out.reached), int(out.rounds),
+                          None if tc is None else tc[:out.rounds].copy(),
+                          None if tm is None else tm[:out.rounds].copy())
+
+
+def kernel_timer(on: bool) -> None:
+    """Start (dropping any earlier record) or stop recording the compute
+    kernels of every crom_step on this thread (crom_kernel_timer)."""
+    _check(lib().crom_kernel_timer(int(bool(on))), "crom_kernel_timer")
+
+
+def kernel_timer_read() -> Tuple[float, int]:
+    """(summed milliseconds, number of steps) of the record (synchronises)."""
+    ms, n = c_double(0.0), c_int64(0)
+    _check(lib().crom_kernel_timer_read(ctypes.byref(ms), ctypes.byref(n)), "crom_kernel_timer_read")
+    return float(ms.value), int(n.value)

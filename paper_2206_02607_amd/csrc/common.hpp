@@ -15,6 +15,10 @@ namespace crom {
 
 void set_error(const char* fmt, ...);
 
+// Records a HIP event on `st` when crom_kernel_timer is on for this host
+// thread (a step calls it after its set-up launch and after its last launch).
+void timer_mark(hipStream_t st);
+
 inline crom_status fail(crom_status s, const char* msg) {
   set_error("%s", msg);
   return s;

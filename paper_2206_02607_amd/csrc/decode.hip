@@ -3,7 +3,10 @@
 // gradient").
 #include <stdarg.h>
 
+#include <vector>
+
 #include "common.hpp"
+#include "tune.hpp"
 
 namespace crom {
 
@@ -16,6 +19,30 @@ void set_error(const char* fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   g_err = buf;
+}
+
+// Benchmark timing (crom_kernel_timer): event pairs recorded around the
+// launches that follow a step's set-up kernel, per host thread.
+struct KernelTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // reused across records; pairs (2i, 2i + 1)
+  size_t used = 0;
+};
+static thread_local KernelTimer g_timer;
+
+void timer_mark(hipStream_t st) {
+  KernelTimer& t = g_timer;
+  if (!t.on) return;
+  if (t.used == t.ev.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+      t.on = false;
+      t.used = 0;
+      return;
+    }
+    t.ev.push_back(e);
+  }
+  if (hipEventRecord(t.ev[t.used], st) == hipSuccess) ++t.used;
 }
 
 crom_status check_net(const crom_net* net, bool need_packed) {
@@ -86,30 +113,6 @@ struct DecodeArgs {
   float* dgdx;
   float* d2g;
   float* dgdq;
-};
-
-// Launch shape of the decode kernels per decoder width and arithmetic:
-// waves per workgroup, weight fragments (-1: by register estimate, 2:
-// streamed one K-block ahead) and the waves per SIMD the register
-// allocation must leave room for.  Measured on the 12-column 2D BF16 decode
-// (1M points): 4 waves holding a layer's fragments 381 TFLOP/s (380
-// registers, one workgroup per CU); 8 waves held to 128 registers 553;
-// 4 waves (two M-tiles each, so every activation fragment read from LDS
-// feeds two products) with streamed fragments held to 256 registers 633
-// (two workgroups per CU); 2 waves 488.
-template <class S, int PREC>
-struct DecodeTune {
-  static constexpr int NW = S::W <= 32 ? 2 : (S::W <= 128 ? 4 : 8);
-  static constexpr int PF = -1;
-  static constexpr int WPE = 1;
-};
-template <>
-struct DecodeTune<Shape<128, 2, 8, 1>, PREC_BF16> {
-  static constexpr int NW = 4, PF = 2, WPE = 2;
-};
-template <>
-struct DecodeTune<Shape<128, 2, 8, 1>, PREC_BF16_PURE> {
-  static constexpr int NW = 4, PF = 2, WPE = 2;
 };
 
 template <class S, class C, int NB, int NW, int PREC, int PF, int WPE>
@@ -303,6 +306,32 @@ using namespace crom;
 extern "C" {
 
 const char* crom_last_error(void) { return g_err.c_str(); }
+
+crom_status crom_kernel_timer(int32_t on) {
+  g_timer.on = on != 0;
+  if (on) g_timer.used = 0;
+  return CROM_OK;
+}
+
+crom_status crom_kernel_timer_read(double* total_ms, int64_t* count) {
+  if (!total_ms || !count) return fail(CROM_ERR_INVALID_ARG, "total_ms and count are required");
+  KernelTimer& t = g_timer;
+  const size_t pairs = t.used / 2;
+  double sum = 0.0;
+  if (pairs > 0) {
+    crom_status s = hip_check(hipEventSynchronize(t.ev[2 * pairs - 1]), "hipEventSynchronize");
+    if (s != CROM_OK) return s;
+  }
+  for (size_t i = 0; i < pairs; ++i) {
+    float ms = 0.0f;
+    crom_status s = hip_check(hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]), "hipEventElapsedTime");
+    if (s != CROM_OK) return s;
+    sum += ms;
+  }
+  *total_ms = sum;
+  *count = (int64_t)pairs;
+  return CROM_OK;
+}
 
 size_t crom_net_param_count(int32_t m, int32_t r, int32_t d, int32_t width, int32_t depth) {
   if (m < 1 || r < 0 || d < 1 || width < 1 || depth < 1) return 0;

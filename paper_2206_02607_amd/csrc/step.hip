@@ -1115,9 +1115,11 @@ static crom_status launch_lls(StepArgs a, hipStream_t st) {
   int64_t g = a.L.nblk_max;
   if (g > 4096) g = 4096;  // each workgroup loads the parameters once for its batches
   if (g < 1) g = 1;
+  timer_mark(st);
   hipLaunchKernelGGL(k, dim3((unsigned)g), dim3(NW * 64), lds_bytes, st, a);
   if ((s = hip_check(hipGetLastError(), "lls launch")) != CROM_OK) return s;
   hipLaunchKernelGGL(lls_solve_kernel<S::R>, dim3((unsigned)a.n_inst), dim3(64), 0, st, a);
+  timer_mark(st);
   return hip_check(hipGetLastError(), "lls solve launch");
 }
 
@@ -1193,10 +1195,12 @@ static crom_status launch_gn_rounds(StepArgs a, int max_rounds, hipStream_t st) 
   int64_t g = a.L.nblk_max;
   if (g > 4096) g = 4096;
   if (g < 1) g = 1;
+  timer_mark(st);
   for (int p = 0; p <= max_rounds; ++p) {
     hipLaunchKernelGGL(kr, dim3((unsigned)g), dim3(NW * 64), lds_bytes, st, a, p);
     hipLaunchKernelGGL(ks, dim3((unsigned)a.n_inst), dim3(NW * 64), SOLVE_LDS, st, a, p, (int)(p == max_rounds));
   }
+  timer_mark(st);
   return hip_check(hipGetLastError(), "round launches");
 }
 
@@ -1271,6 +1275,7 @@ static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
   hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(SETUP_THREADS), 0, st, a);
   crom_status s = hip_check(hipGetLastError(), "setup launch");
   if (s != CROM_OK) return s;
+  timer_mark(st);
   if constexpr (KIND == PK_ELASTIC) {
     s = elastic_prepare<S, NW, PREC>(a, st);
     if (s != CROM_OK) return s;
@@ -1279,9 +1284,11 @@ static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
   if (g > resident) g = resident;
   if (g < 1) g = 1;
   void* args[] = {&a, &max_rounds};
-  return hip_check(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k), dim3((unsigned)g),
-                                              dim3(NW * 64), args, lds_bytes, st),
-                   "step launch");
+  s = hip_check(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k), dim3((unsigned)g),
+                                           dim3(NW * 64), args, lds_bytes, st),
+                "step launch");
+  timer_mark(st);
+  return s;
 }
 
 // Waves per workgroup and weight prefetch per precision, chosen so that the

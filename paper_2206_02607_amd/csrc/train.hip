@@ -39,24 +39,37 @@ __global__ void fold_kernel(const float* __restrict__ W1, const float* __restric
 }
 
 // a1[row][u] = ELU(sum_i W1[u][i] x[p][i] + c[b][u]),  row = b * P + p.
-// A thread takes 8 consecutive units of one row (W is a multiple of 8).
-template <class T>
-__global__ void layer1_kernel(const float* __restrict__ W1, const float* __restrict__ c, const float* __restrict__ x,
-                              int64_t P, int64_t rows, int W, int m, int r, T* __restrict__ a1) {
+// A thread takes 8 consecutive units of one row (W is a multiple of 8); the
+// x-columns of W1 are staged in LDS, and every load of a thread is issued
+// before its arithmetic (m is a compile-time constant).
+constexpr int EW_MAX_W = 256;  // widest layer of the compiled shapes
+constexpr int EW_MAX_MD = 3;   // largest m and d
+
+template <class T, int M>
+__global__ __launch_bounds__(256) void layer1_kernel(const float* __restrict__ W1, const float* __restrict__ c,
+                                                     const float* __restrict__ x, int64_t P, int64_t rows, int W,
+                                                     int r, T* __restrict__ a1) {
   typedef T vec8 __attribute__((ext_vector_type(8)));
+  __shared__ float wx[EW_MAX_W * M];
+  for (int i = threadIdx.x; i < W * M; i += blockDim.x) wx[i] = W1[(i / M) * (M + r) + i % M];
+  __syncthreads();
   const int G = W / 8;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows * G; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t row = i / G;
     const int u0 = (int)(i - row * G) * 8;
     const int64_t b = row / P, p = row - b * P;
-    float xv[3] = {0.0f, 0.0f, 0.0f};
-    for (int k = 0; k < m; ++k) xv[k] = x[p * m + k];
+    float xv[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) xv[k] = x[p * M + k];
+    const float4 c0 = *reinterpret_cast<const float4*>(&c[b * W + u0]);
+    const float4 c1 = *reinterpret_cast<const float4*>(&c[b * W + u0 + 4]);
+    const float cz[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
     vec8 o;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int u = u0 + e;
-      float z = c[b * W + u];
-      for (int k = 0; k < m; ++k) z += W1[u * (m + r) + k] * xv[k];
+      float z = cz[e];
+#pragma unroll
+      for (int k = 0; k < M; ++k) z += wx[(u0 + e) * M + k] * xv[k];
       o[e] = (T)(z > 0.0f ? z : __expf(z) - 1.0f);
     }
     *reinterpret_cast<vec8*>(&a1[row * W + u0]) = o;
@@ -64,20 +77,28 @@ __global__ void layer1_kernel(const float* __restrict__ W1, const float* __restr
 }
 
 // g[row][o] = sum_u Wout[o][u] a[row][u] + bout[o]: one thread per row,
-// 8 units per load, in unit order.
-template <class T>
-__global__ void output_kernel(const T* __restrict__ a, const float* __restrict__ Wout, const float* __restrict__ bout,
-                              int64_t rows, int W, int D, float* __restrict__ g) {
+// 8 units per load, in unit order; Wout staged in LDS.
+template <class T, int D>
+__global__ __launch_bounds__(256) void output_kernel(const T* __restrict__ a, const float* __restrict__ Wout,
+                                                     const float* __restrict__ bout, int64_t rows, int W,
+                                                     float* __restrict__ g) {
   typedef T vec8 __attribute__((ext_vector_type(8)));
+  __shared__ float wo[EW_MAX_W * D];
+  for (int i = threadIdx.x; i < W * D; i += blockDim.x) wo[i] = Wout[i];
+  __syncthreads();
   for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < rows;
        row += (int64_t)gridDim.x * blockDim.x) {
-    float s[3] = {0.0f, 0.0f, 0.0f};
+    float s[D];
+#pragma unroll
+    for (int o = 0; o < D; ++o) s[o] = 0.0f;
     for (int u0 = 0; u0 < W; u0 += 8) {
       const vec8 v = *reinterpret_cast<const vec8*>(&a[row * W + u0]);
 #pragma unroll
       for (int e = 0; e < 8; ++e)
-        for (int o = 0; o < D; ++o) s[o] += Wout[o * W + u0 + e] * (float)v[e];
+#pragma unroll
+        for (int o = 0; o < D; ++o) s[o] += wo[o * W + u0 + e] * (float)v[e];
     }
+#pragma unroll
     for (int o = 0; o < D; ++o) g[row * D + o] = s[o] + bout[o];
   }
 }
@@ -118,23 +139,29 @@ __global__ __launch_bounds__(256) void mse_final_kernel(const double* __restrict
 }
 
 // dz[row][u] = (sum_o dg[row][o] Wout[o][u]) * ELU'(a[row][u]); 8 units
-// of one row per thread.
-template <class T>
-__global__ void dz_last_kernel(const float* __restrict__ dg, const float* __restrict__ Wout, const T* __restrict__ a,
-                               int64_t rows, int W, int D, T* __restrict__ dz) {
+// of one row per thread, Wout staged in LDS.
+template <class T, int D>
+__global__ __launch_bounds__(256) void dz_last_kernel(const float* __restrict__ dg, const float* __restrict__ Wout,
+                                                      const T* __restrict__ a, int64_t rows, int W,
+                                                      T* __restrict__ dz) {
   typedef T vec8 __attribute__((ext_vector_type(8)));
+  __shared__ float wo[EW_MAX_W * D];
+  for (int i = threadIdx.x; i < W * D; i += blockDim.x) wo[i] = Wout[i];
+  __syncthreads();
   const int G = W / 8;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows * G; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t row = i / G;
     const int u0 = (int)(i - row * G) * 8;
-    float d[3] = {0.0f, 0.0f, 0.0f};
+    float d[D];
+#pragma unroll
     for (int o = 0; o < D; ++o) d[o] = dg[row * D + o];
     const vec8 av = *reinterpret_cast<const vec8*>(&a[row * W + u0]);
     vec8 out;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       float s = 0.0f;
-      for (int o = 0; o < D; ++o) s += d[o] * Wout[o * W + u0 + e];
+#pragma unroll
+      for (int o = 0; o < D; ++o) s += d[o] * wo[o * W + u0 + e];
       out[e] = (T)(s * elu_d1_from_a((float)av[e]));
     }
     *reinterpret_cast<vec8*>(&dz[row * W + u0]) = out;
@@ -356,7 +383,7 @@ struct Carve {
   }
 };
 
-constexpr int COLSUM_CHUNKS = 256;  // partial sums per column sum at most
+constexpr int COLSUM_CHUNKS = 2048;  // partial sums per column sum at most
 constexpr int MSE_BLOCKS = 1024;
 
 // The decoder's forward and backward over B snapshots x P points.  q: [B][r]
@@ -409,8 +436,13 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
   // ---- forward ----
   hipLaunchKernelGGL(fold_kernel, dim3(grid_for((int64_t)B * W)), dim3(256), 0, st, prm + pi.w[0], prm + pi.b[0], q,
                      B, W, m, r, ws.c);
-  hipLaunchKernelGGL((layer1_kernel<T>), dim3(grid_for(rows * W / 8)), dim3(256), 0, st, prm + pi.w[0], ws.c, x, P,
-                     rows, W, m, r, ws.a[0]);
+  if (W > EW_MAX_W || W % 8 != 0 || m > EW_MAX_MD || D > EW_MAX_MD) return fail(CROM_ERR_UNSUPPORTED, "training shape");
+  {
+    const dim3 grid(grid_for(rows * W / 8));
+    if (m == 1) hipLaunchKernelGGL((layer1_kernel<T, 1>), grid, dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows, W, r, ws.a[0]);
+    else if (m == 2) hipLaunchKernelGGL((layer1_kernel<T, 2>), grid, dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows, W, r, ws.a[0]);
+    else hipLaunchKernelGGL((layer1_kernel<T, 3>), grid, dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows, W, r, ws.a[0]);
+  }
   for (int l = 1; l < depth; ++l) {
     GemmArgs g = gemm_args((int)rows, W, W, ws.a[l - 1], W, ws.wt[l], W);
     g.bias = prm + pi.b[l];
@@ -423,8 +455,12 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
     }
     if ((s = gemm<T, false, true, EPI_BIAS_ELU>(g, st)) != CROM_OK) return s;
   }
-  hipLaunchKernelGGL((output_kernel<T>), dim3(grid_for(rows)), dim3(256), 0, st, ws.a[depth - 1],
-                     prm + pi.w[depth], prm + pi.b[depth], rows, W, D, ws.g);
+  if (D == 1)
+    hipLaunchKernelGGL((output_kernel<T, 1>), dim3(grid_for(rows)), dim3(256), 0, st, ws.a[depth - 1],
+                       prm + pi.w[depth], prm + pi.b[depth], rows, W, ws.g);
+  else
+    hipLaunchKernelGGL((output_kernel<T, 3>), dim3(grid_for(rows)), dim3(256), 0, st, ws.a[depth - 1],
+                       prm + pi.w[depth], prm + pi.b[depth], rows, W, ws.g);
   const float* dg = dg_in;
   if (!dg_in) {
     hipLaunchKernelGGL(mse_kernel, dim3(MSE_BLOCKS), dim3(256), 0, st, ws.g, u, rows * D, ws.dg, ws.mpart);
@@ -441,8 +477,12 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
                        (int64_t)D * W);
     colsum<float>(dg, D, D, 1, rows, nullptr, 1, 0, 1, ws.cpart, COLSUM_CHUNKS, ws.csum, st);
     hipLaunchKernelGGL(d2f_kernel, dim3(1), dim3(64), 0, st, ws.csum, grad + pi.b[depth], (int64_t)D);
-    hipLaunchKernelGGL((dz_last_kernel<T>), dim3(grid_for(rows * W / 8)), dim3(256), 0, st, dg, prm + pi.w[depth],
-                       ws.a[depth - 1], rows, W, D, ws.dz0);
+    if (D == 1)
+      hipLaunchKernelGGL((dz_last_kernel<T, 1>), dim3(grid_for(rows * W / 8)), dim3(256), 0, st, dg,
+                         prm + pi.w[depth], ws.a[depth - 1], rows, W, ws.dz0);
+    else
+      hipLaunchKernelGGL((dz_last_kernel<T, 3>), dim3(grid_for(rows * W / 8)), dim3(256), 0, st, dg,
+                         prm + pi.w[depth], ws.a[depth - 1], rows, W, ws.dz0);
   }
   // ---- hidden layers ----
   T* dz = ws.dz0;

@@ -1,6 +1,8 @@
 """The C-ABI library loads, exports every entry point the header declares,
 and rejects bad arguments on the host before touching a GPU (no GPU)."""
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -82,6 +84,50 @@ def test_step_validation():
     assert call(pde_=crom.CromPDE(0, 0, -1.0, 1 << 22)) == 1
     assert call(pde_=crom.CromPDE(5, 0, 1e-4, 1 << 22)) == 2
     assert call(pde_=crom.CromPDE(1, 0, 1e-4, 1 << 22)) == 2  # neo-Hookean needs m == d == 3
+
+
+def test_sampling_validation():
+    L = crom.lib()
+    net = _net()  # (2, 8, 1, 128): r = 8, d = 1
+    n = ctypes.c_size_t(0)
+
+    def ws_query(n_try=10, max_samples=64, n_steps=500, kind=0, n_mu=40, P=16384):
+        o = crom.CromSamplingOpts(n_try, max_samples, n_steps, 0.1)
+        return L.crom_sampling_workspace(ctypes.byref(net), kind, n_mu, P, ctypes.byref(o), ctypes.byref(n))
+
+    assert ws_query() == 0 and n.value > 11 * 16384 * 8
+    assert ws_query(n_try=0) == 1
+    assert ws_query(n_try=crom.SAMPLING_MAX_TRY + 1) == 1
+    assert ws_query(max_samples=16385) == 1
+    assert ws_query(n_steps=0) == 1
+    assert ws_query(kind=7) == 1
+    assert ws_query(n_mu=0) == 1
+    assert ws_query() == 0
+    wsb = n.value
+    pde = crom.CromPDE(0, 0, 1e-4, 1 << 22)
+    gn = crom.GNOptions().c_struct()
+    o = crom.CromSamplingOpts(10, 64, 500, 0.1)
+    res = crom.CromSamplingResult()
+
+    def call(init, ws=1 << 28, wsb_=wsb, pde_=pde):
+        s = np.zeros(64, dtype=np.int32)
+        s[:len(init)] = init
+        return L.crom_robust_sampling(ctypes.byref(net), ctypes.byref(pde_), 40, 1 << 21, 16384, None, 1 << 23,
+                                      1 << 24, ctypes.byref(gn), ctypes.byref(o), s.ctypes.data_as(ctypes.c_void_p),
+                                      len(init), ctypes.byref(res), None, None, ws, wsb_, None)
+
+    good = list(range(0, 160, 10))
+    assert call(good[:7]) == 1                     # r = 8 needs 8 samples
+    assert call(good[:7] + [good[0]]) == 1        # repeated node
+    assert call(good[:7] + [16384]) == 1          # node out of range
+    assert call(good, wsb_=wsb - 1) == 3
+    assert call(good, ws=(1 << 28) + 8) == 3
+    assert call(good, pde_=crom.CromPDE(0, 0, 1e-4, None)) == 1
+    assert L.crom_sampling_candidates(1 << 20, 100, None, 0, 1 << 21, None) == 1
+    assert L.crom_sampling_candidates(1 << 20, 100, None, crom.SAMPLING_MAX_TRY + 1, 1 << 21, None) == 1
+    assert L.crom_sampling_residual(ctypes.byref(net), 1 << 20, 0, 1, 1, 1, 1, 1, None, None) == 1
+    assert L.crom_sampling_residual(ctypes.byref(net), 1 << 20, 10, 0, 1, 1, 1, 1, None, None) == 1
+    assert L.crom_sampling_residual(ctypes.byref(net), 1 << 20, 10, 1, 1, 1, 1, None, None, None) == 1
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

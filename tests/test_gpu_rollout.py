@@ -98,3 +98,35 @@ def test_bf16_and_fp32_reach_equal_rollout_error(trained):
         errs[prec], _ = _rollout_error(w, nodes, d, q0, mus, record, refs, 1)
     print("LLS rollout error fp32", errs["fp32"].round(5), "bf16", errs["bf16"].round(5))
     assert np.abs(errs["fp32"] - errs["bf16"]).max() < 0.1 * errs["fp32"].min()
+
+
+def test_robust_sampling_beats_random_sets(trained):
+    """Appendix "Robust Sampling": greedy selection from 12 random interior
+    nodes to 24 (10 candidates per round, the final-time residual summed
+    over 10 training diffusivities) ends with a lower metric (mean + max of
+    the residual vector) than each of four random interior sets of 24
+    nodes."""
+    import torch
+    from paper_2206_02607_amd import crom
+    w, nodes, nets, _, _, _, rows = trained
+    dec, q0, _ = nets["trained"]
+    ks = np.arange(0, w.n_mu, 4)
+    n_mu = len(ks)
+    nt = len(w.times)
+    ref = rows.reshape(w.n_mu, nt, -1)[ks, nt - 1].to(torch.float64).reshape(n_mu, -1, 1).contiguous()
+    n_steps = int(round(w.times[-1] / w.dt))
+    gi = np.arange(w.grid)
+    edge = (gi == 0) | (gi == w.grid - 1)
+    clamp = (edge[:, None] | edge[None, :]).reshape(-1).astype(np.uint8)
+    interior = np.flatnonzero(clamp == 0)
+    g = np.random.Generator(np.random.PCG64(21))
+    opts = crom.GNOptions(max_iter=1, linearized=True)
+    args = (dec, nodes, ref, np.tile(q0, (n_mu, 1)), w.mu[ks], w.dt)
+    kw = dict(opts=opts, node_clamp=torch.from_numpy(clamp).to(nodes.device))
+    greedy = crom.robust_sampling(*args, g.choice(interior, 12, replace=False), n_steps, target=0.0, n_try=10,
+                                  max_samples=24, **kw)
+    rand = [crom.robust_sampling(*args, g.choice(interior, 24, replace=False), n_steps, target=0.0,
+                                 max_samples=24, **kw).metric for _ in range(4)]
+    print("greedy metric", greedy.metric, "samples", greedy.samples.tolist(), "random sets", np.round(rand, 4))
+    assert greedy.rounds == 12
+    assert greedy.metric < min(rand)
