@@ -48,16 +48,15 @@ PEAK = {"bf16": 2500.0, "bf16x3": 2500.0, "bf16pure": 2500.0, "fp32": 157.3}  # 
 
 
 def source_hash() -> str:
-    """sha256 of the kernel sources and the C header (identifies the build a
-    hardware-counter measurement was taken on)."""
+    """sha256 of the sources the step and decode kernels are built from (a
+    hardware-counter measurement holds only for the build it was taken on)."""
     import hashlib
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_2206_02607_amd", "csrc")
-    for name in sorted(os.listdir(src)) + ["../../include/crom.h"]:
+    for name in ("common.hpp", "engine.hpp", "tune.hpp", "decode.hip", "step.hip", "../../include/crom.h"):
         path = os.path.normpath(os.path.join(src, name))
-        if path.endswith((".hip", ".hpp", ".h")):
-            with open(path, "rb") as f:
-                h.update(os.path.basename(path).encode() + f.read())
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode() + f.read())
     return h.hexdigest()
 
 
@@ -531,7 +530,7 @@ def main():
             "frac": achieved / PEAK[args.prec],
             "traffic": measured_traffic({"decode": "decode_kernel", "step": "step_kernel"}[name]),
             "kernel": {"decode": "decode_kernel (full field, value column)",
-                       "step": "step_kernel (cooperative latent step)"}[name],
+                       "step": "step_kernel (persistent latent step)"}[name],
             "avg_ms": t_avg * 1e3, "flop_per_launch": fl,
             "other": {k: {"avg_ms": v[0] * 1e3, "achieved_tflops": v[1] / v[0] / 1e12}
                       for k, v in cand.items() if k != name}}

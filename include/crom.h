@@ -171,8 +171,8 @@ typedef struct {
  *              256).  A round evaluates 4 line-search trials (or
  *              re-linearises after a shortened step); an instance still
  *              running after the last round ends with CROM_FLAG_MAXITER.
- * The step runs as one cooperative kernel whose workgroups are all resident
- * on the GPU; it loops until every instance has finished. */
+ * The step runs as one persistent kernel whose grid fits on the GPU at
+ * once; it loops until every instance has finished. */
 typedef struct {
   int32_t max_iter, linearized, ls_max, max_rounds;
   double tol_step, armijo_c, ls_shrink;

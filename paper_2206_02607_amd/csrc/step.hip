@@ -4,8 +4,8 @@
 //
 // Two launches per step, both on the caller's stream with no host sync:
 //   setup   block map (16-sample batches of every instance), state init
-//   step    one persistent kernel (cooperative launch, so that every
-//           workgroup is resident) running phases:
+//   step    one persistent kernel (its grid never exceeds the workgroups
+//           the device holds at once) running phases:
 //     phase 0      eval_jets: value, x tangents, Laplacian and latent
 //                  Jacobian at q_n; heat update f_{n+1} = g + dt nu Lap g
 //                  (FP64); residual rho_0 = f_{n+1} - g(q_n) = dt nu Lap g,
@@ -57,8 +57,12 @@
 #ifndef CROM_STEP2D_NW
 #define CROM_STEP2D_NW 8
 #endif
+// 2D BF16 step kernel: 8 waves with weight fragments streamed one K-block
+// ahead (held-and-prefetched fragments spilled 124 bytes per lane; single
+// instance at 2,000 samples: 0.212 ms prefetched, 0.207 ms streamed, 0.206
+// ms loaded per layer with 20 bytes of spill; 4 waves 0.26-0.27 ms).
 #ifndef CROM_STEP2D_PF
-#define CROM_STEP2D_PF 1
+#define CROM_STEP2D_PF 2
 #endif
 #ifndef CROM_STEP2D_WPE
 #define CROM_STEP2D_WPE 1
@@ -90,6 +94,22 @@ struct GNState {
   double obj_first, obj_last;
   int32_t phase, iters, ls_evals, flags, ls_tried, rounds;
 };
+
+// 8-byte words of GNState that the set-up kernel writes for every instance
+// (the phase and its flags); the rest of the state is formed by the first
+// solve from q_n, so the set-up stays short for large batches.
+constexpr int GN_W_OBJ = (int)(offsetof(GNState, obj_first) / 8);
+constexpr int GN_W_PHASE = (int)(offsetof(GNState, phase) / 8);    // phase and iters share this word
+constexpr int GN_W_FLAGS = (int)(offsetof(GNState, ls_evals) / 8);  // ls_evals and flags
+
+// Word w of an instance's state before its first solve.
+__device__ __forceinline__ uint64_t gn_initial_word(int w, const double* q_n, int r, bool empty) {
+  if (w < RMAX) return w < r ? (uint64_t)__double_as_longlong(q_n[w]) : 0;  // q[] occupies the first RMAX words
+  if (w == GN_W_OBJ || w == GN_W_OBJ + 1) return (uint64_t)__double_as_longlong(__builtin_nan(""));
+  if (w == GN_W_PHASE) return (uint64_t)(uint32_t)(empty ? PH_DONE : PH_INIT);  // iters = 0 in the high half
+  if (w == GN_W_FLAGS) return empty ? ((uint64_t)(uint32_t)CROM_FLAG_SINGULAR << 32) : 0;  // ls_evals = 0, flags
+  return 0;
+}
 
 struct WsLayout {
   size_t blk_start, blk_inst, first_blk, nblk, sync, act_phase, inst_cnt, targets, rho0, partials,
@@ -271,27 +291,13 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(StepArgs a) {
     blk_start[b] = base + (int64_t)(b - fbp[lo]) * PT;
     blk_inst[b] = lo;
   }
-  // state: one 8-byte word per thread step
-  constexpr int NWORD = sizeof(GNState) / 8;
-  constexpr int W_OBJ = (int)(offsetof(GNState, obj_first) / 8);
-  constexpr int W_PHASE = (int)(offsetof(GNState, phase) / 8);  // phase and iters share this word
-  constexpr int W_FLAGS = (int)(offsetof(GNState, ls_evals) / 8);  // ls_evals and flags
-  for (int64_t w = tid; w < (int64_t)a.n_inst * NWORD; w += SETUP_THREADS) {
-    const int i = (int)(w / NWORD), k = (int)(w % NWORD);
-    uint64_t* word = reinterpret_cast<uint64_t*>(st + i) + k;
+  // state: the phase and flags words of every instance (the first solve
+  // forms the rest)
+  for (int i = tid; i < a.n_inst; i += SETUP_THREADS) {
     const bool empty = fbp[i + 1] == fbp[i];
-    uint64_t v = 0;
-    if (k < RMAX) {  // q[] occupies the first RMAX words
-      const double d = k < a.r ? a.q_n[(int64_t)i * a.r + k] : 0.0;
-      v = __double_as_longlong(d);
-    } else if (k == W_OBJ || k == W_OBJ + 1) {
-      v = __double_as_longlong(__builtin_nan(""));
-    } else if (k == W_PHASE) {
-      v = (uint64_t)(uint32_t)(empty ? PH_DONE : PH_INIT);  // iters = 0 in the high half
-    } else if (k == W_FLAGS) {
-      v = empty ? ((uint64_t)(uint32_t)CROM_FLAG_SINGULAR << 32) : 0;  // ls_evals = 0, flags
-    }
-    *word = v;
+    uint64_t* words = reinterpret_cast<uint64_t*>(st + i);
+    words[GN_W_PHASE] = gn_initial_word(GN_W_PHASE, nullptr, a.r, empty);
+    words[GN_W_FLAGS] = gn_initial_word(GN_W_FLAGS, nullptr, a.r, empty);
   }
   for (int i = tid; i < a.n_inst; i += SETUP_THREADS) {
     if (fbp[i + 1] != fbp[i]) continue;
@@ -374,14 +380,16 @@ __device__ void eval_jets_batch(const StepArgs& a, char* lds, const float* par, 
 
 template <class S, int NW, int PREC, int PF>
 __device__ void eval_trials_batch(const StepArgs& a, char* lds, const float* par, double* qdl,
-                                  int64_t blk, int inst, int mb) {
+                                  int64_t blk, int inst, int mb, bool have_qdl) {
   constexpr int R = S::R;
   using C = Cols<S::M, R, 1, TV, false, D2_NONE, R>;
   using E = Engine<S, C, 1, NW, PREC, PF>;
   const GNState* st = wsp<GNState>(a, a.L.state) + inst;
   if (mb >= 0) trace_mark(a, mb);
-  for (int i = threadIdx.x; i < TV * R; i += blockDim.x) qdl[i] = ld_c(&st->qd[i / R][i % R]);
-  __syncthreads();
+  if (!have_qdl) {
+    for (int i = threadIdx.x; i < TV * R; i += blockDim.x) qdl[i] = ld_c(&st->qd[i / R][i % R]);
+    __syncthreads();
+  }
   if (mb >= 0) trace_mark(a, mb + 1);
   const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
   const int64_t rem = a.offsets[inst + 1] - first;
@@ -562,7 +570,7 @@ __device__ void eval_init_elastic(const StepArgs& a, double* jd, int64_t blk) {
 // which the engine takes at the first difference column's latent).
 template <class S, int NW, int PREC, int PF>
 __device__ void eval_trials_elastic(const StepArgs& a, char* lds, double* jd, const float* par, double* qdl,
-                                    int64_t blk, int inst) {
+                                    int64_t blk, int inst, bool have_qdl) {
   constexpr int R = S::R, D = S::D, ROWS = PT * D;
   constexpr int QC = ElasticChunks<PREC>::QC;
   using CT = Cols<S::M, R, 1, TV, false, D2_NONE, 0>;
@@ -571,8 +579,10 @@ __device__ void eval_trials_elastic(const StepArgs& a, char* lds, double* jd, co
   using EQ = Engine<S, CQ, 1, NW, PREC, PF>;
   double* rho = jd + ROWS * R;
   const GNState* st = wsp<GNState>(a, a.L.state) + inst;
-  for (int i = threadIdx.x; i < TV * R; i += blockDim.x) qdl[i] = ld_c(&st->qd[i / R][i % R]);
-  __syncthreads();
+  if (!have_qdl) {
+    for (int i = threadIdx.x; i < TV * R; i += blockDim.x) qdl[i] = ld_c(&st->qd[i / R][i % R]);
+    __syncthreads();
+  }
   const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
   const int64_t rem = a.offsets[inst + 1] - first;
   const int n_valid = rem < PT ? (int)rem : PT;
@@ -724,8 +734,13 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
   const int NS = nth / NRED;  // strided subsets per entry
   double* red = sub + NS * NRED;
   __shared__ int s_done;
-  for (int w = threadIdx.x; w < NWORD; w += nth)
-    reinterpret_cast<uint64_t*>(st)[w] = ld_c(reinterpret_cast<const uint64_t*>(gst) + w);
+  if (p == 0) {  // the state before the first solve, formed from q_n
+    for (int w = threadIdx.x; w < NWORD; w += nth)
+      reinterpret_cast<uint64_t*>(st)[w] = gn_initial_word(w, a.q_n + (int64_t)inst * R, R, false);
+  } else {
+    for (int w = threadIdx.x; w < NWORD; w += nth)
+      reinterpret_cast<uint64_t*>(st)[w] = ld_c(reinterpret_cast<const uint64_t*>(gst) + w);
+  }
   __syncthreads();
   const int phase = st->phase;
   const int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
@@ -922,7 +937,12 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
 }
 
 // ---------------------------------------------------------------------------
-// The persistent step kernel (cooperative launch: every workgroup resident).
+// The persistent step kernel.  The launch takes at most as many workgroups as
+// the device holds at once (occupancy query), so on an otherwise idle stream
+// every workgroup is resident; every wait is bounded (SPIN_MAX), so a
+// workgroup that is not resident makes the step end with ABORTED instead of
+// hanging.  A plain launch: the cooperative launch API measured 18 us more
+// per step in dispatch.
 // ---------------------------------------------------------------------------
 constexpr int64_t SPIN_MAX = int64_t(1) << 21;  // bounded waits: ~2e6 polls of ~1 us
 
@@ -970,9 +990,19 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
   uint64_t target = 0;
   bool aborted = false;
   for (int p = 0; p <= max_rounds && !aborted; ++p) {
+    // One memory round trip for the round's active count and, for this
+    // workgroup's first batch, its instance's phase and trial offsets (all
+    // final once the previous phase's solves are counted).
+    const bool pre = p > 0 && (int64_t)blockIdx.x < nblk;
+    const int inst0 = pre ? blk_inst[blockIdx.x] : 0;
     if (threadIdx.x == 0) s_act = ld_c(act_phase + p);  // stable: written only by phase p-1 solves
+    if (pre) {
+      if (threadIdx.x == blockDim.x - 1) s_ph = ld_c(&state[inst0].phase);
+      for (int i = threadIdx.x; i < TV * S::R; i += blockDim.x) qdl[i] = ld_c(&state[inst0].qd[i / S::R][i % S::R]);
+    }
     __syncthreads();
     const int64_t act = s_act;
+    const int ph0 = s_ph;
     __syncthreads();
     if (act == 0) break;
     target += (uint64_t)act;
@@ -983,15 +1013,19 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
         if constexpr (KIND == PK_HEAT) eval_jets_batch<S, NW, PREC, PF>(a, lds, par, blk);
         else eval_init_elastic<S>(a, jd, blk);
       } else {
-        if (threadIdx.x == 0) s_ph = ld_c(&state[inst].phase);  // stable until this batch arrives
-        __syncthreads();
-        const int ph = s_ph;
-        __syncthreads();
+        const bool first = blk == blockIdx.x;  // phase and trial offsets preloaded
+        int ph = ph0;
+        if (!first) {
+          if (threadIdx.x == 0) s_ph = ld_c(&state[inst].phase);  // stable until this batch arrives
+          __syncthreads();
+          ph = s_ph;
+          __syncthreads();
+        }
         if (ph != PH_TRIALS && ph != PH_REJAC) continue;
         if constexpr (KIND == PK_HEAT)
-          eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, (p == 1 && blk == blockIdx.x) ? 40 : -1);
+          eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, (p == 1 && first) ? 40 : -1, first);
         else
-          eval_trials_elastic<S, NW, PREC, PF>(a, lds, jd, par, qdl, blk, inst);
+          eval_trials_elastic<S, NW, PREC, PF>(a, lds, jd, par, qdl, blk, inst, first);
       }
       // arrival: the partials of this batch are complete in memory
       if (p == 1 && blk == blockIdx.x) trace_mark(a, 44);
@@ -1157,7 +1191,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       const int ph = s_ph;
       __syncthreads();
       if (ph != PH_TRIALS && ph != PH_REJAC) continue;
-      eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, -1);
+      eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, -1, false);
     }
   }
 }
@@ -1284,8 +1318,8 @@ static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
   if (g > resident) g = resident;
   if (g < 1) g = 1;
   void* args[] = {&a, &max_rounds};
-  s = hip_check(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k), dim3((unsigned)g),
-                                           dim3(NW * 64), args, lds_bytes, st),
+  s = hip_check(hipLaunchKernel(reinterpret_cast<const void*>(k), dim3((unsigned)g), dim3(NW * 64), args, lds_bytes,
+                                st),
                 "step launch");
   timer_mark(st);
   return s;

@@ -331,6 +331,46 @@ static unsigned grid_for(int64_t n, int threads = 256) {
   return (unsigned)b;
 }
 
+// The square hidden-layer products in bfloat16 at widths whose weights fit
+// a wave's registers go through rowgemm_kernel; returns false otherwise.
+template <bool FWD>
+static bool row_gemm(int W, const void* X, const void* Wt, const float* bias, const void* gate, void* C,
+                     int64_t rows, hipStream_t st, crom_status* s) {
+  RowGemmArgs g{static_cast<const __bf16*>(X), static_cast<const __bf16*>(Wt), bias,
+                static_cast<const __bf16*>(gate), static_cast<__bf16*>(C), rows};
+  const int64_t tiles = (rows + 15) / 16;
+  int64_t blocks = (tiles + 3) / 4;
+  if (blocks > 1024) blocks = 1024;  // four workgroups of four waves per CU, looping over row tiles
+  if (blocks < 1) blocks = 1;
+  if (W == 128) hipLaunchKernelGGL((rowgemm_kernel<128, FWD>), dim3((unsigned)blocks), dim3(256), 0, st, g);
+  else if (W == 32) hipLaunchKernelGGL((rowgemm_kernel<32, FWD>), dim3((unsigned)blocks), dim3(256), 0, st, g);
+  else return false;
+  *s = hip_check(hipGetLastError(), "row gemm launch");
+  return true;
+}
+
+// dW = X^T Y over `rows` rows for the 128-wide hidden layers in bfloat16:
+// wgrad_kernel partials (at most MAX_SPLITS workgroups), then their sum in
+// workgroup order.  Returns false for other widths.
+static bool wgrad(int W, const void* X, const void* Y, int64_t rows, float* part, float* dW, hipStream_t st,
+                  crom_status* s) {
+  if (W != 128) return false;
+  constexpr int KS = 32;
+  int64_t nblk = (rows + KS - 1) / KS;
+  if (nblk > MAX_SPLITS) nblk = MAX_SPLITS;
+  if (nblk < 1) nblk = 1;
+  int64_t per = (rows + nblk - 1) / nblk;
+  per = (per + KS - 1) / KS * KS;
+  nblk = per > 0 ? (rows + per - 1) / per : 1;
+  if (nblk < 1) nblk = 1;
+  hipLaunchKernelGGL((wgrad_kernel<128>), dim3((unsigned)nblk), dim3(256), 0, st, static_cast<const __bf16*>(X),
+                     static_cast<const __bf16*>(Y), rows, per, part);
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((W * W + 63) / 64)), dim3(256), 0, st, part, (int)nblk,
+                     W, W, dW, (int64_t)W, 0, (int)EPI_NONE, nullptr);
+  *s = hip_check(hipGetLastError(), "weight gradient launch");
+  return true;
+}
+
 template <class T, bool TA, bool TB, int EPI>
 static crom_status gemm(GemmArgs g, hipStream_t st) {
   constexpr int BK = sizeof(T) == 2 ? 64 : 32;  // the kernel's K tile
@@ -444,6 +484,12 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
     else hipLaunchKernelGGL((layer1_kernel<T, 3>), grid, dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows, W, r, ws.a[0]);
   }
   for (int l = 1; l < depth; ++l) {
+    if constexpr (sizeof(T) == 2) {
+      if (row_gemm<true>(W, ws.a[l - 1], ws.wt[l], prm + pi.b[l], nullptr, ws.a[l], rows, st, &s)) {
+        if (s != CROM_OK) return s;
+        continue;
+      }
+    }
     GemmArgs g = gemm_args((int)rows, W, W, ws.a[l - 1], W, ws.wt[l], W);
     g.bias = prm + pi.b[l];
     if constexpr (sizeof(T) == 2) {
@@ -489,15 +535,33 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
   T* dzn = ws.dz1;
   for (int l = depth - 1; l >= 1; --l) {
     // dW_l = dz^T a_{l-1}  (split over rows)
-    GemmArgs gw = gemm_args(W, W, (int)rows, dz, W, ws.a[l - 1], W);
-    gw.C = grad + pi.w[l];
-    gw.ldc = W;
-    gw.part = ws.part;
-    if ((s = gemm<T, true, false, EPI_NONE>(gw, st)) != CROM_OK) return s;
+    bool wg = false;
+    if constexpr (sizeof(T) == 2) {
+      wg = wgrad(W, dz, ws.a[l - 1], rows, ws.part, grad + pi.w[l], st, &s);
+      if (s != CROM_OK) return s;
+    }
+    if (!wg) {
+      GemmArgs gw = gemm_args(W, W, (int)rows, dz, W, ws.a[l - 1], W);
+      gw.C = grad + pi.w[l];
+      gw.ldc = W;
+      gw.part = ws.part;
+      if ((s = gemm<T, true, false, EPI_NONE>(gw, st)) != CROM_OK) return s;
+    }
     // db_l = column sums of dz
     colsum<T>(dz, W, W, 1, rows, nullptr, 1, 0, 1, ws.cpart, COLSUM_CHUNKS, ws.csum, st);
     hipLaunchKernelGGL(d2f_kernel, dim3(grid_for(W)), dim3(256), 0, st, ws.csum, grad + pi.b[l], (int64_t)W);
     // dz_{l-1} = (dz W_l) * ELU'(a_{l-1})
+    bool done = false;
+    if constexpr (sizeof(T) == 2) {
+      done = row_gemm<false>(W, dz, ws.wt[l], nullptr, ws.a[l - 1], dzn, rows, st, &s);
+      if (s != CROM_OK) return s;
+    }
+    if (done) {
+      T* t = dz;
+      dz = dzn;
+      dzn = t;
+      continue;
+    }
     GemmArgs gd = gemm_args((int)rows, W, W, dz, W, ws.wt[l], W);
     gd.gate = ws.a[l - 1];
     gd.ldg = W;
