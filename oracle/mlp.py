@@ -10,6 +10,11 @@ Readings taken where the paper is silent:
 * input order a_0 = [x; q] (x first); no output activation;
 * ELU with alpha = 1; at z = 0 the exponential branch is taken, so
   ELU(0) = 0, ELU'(0) = 1 and ELU''(0) = 1.
+* The sine activation (Sec. "Network Details" names SIREN as the
+  alternative): a_l = sin(z_l), with the SIREN frequency omega_0 folded
+  into the weights and biases (a layer sin(omega_0 (W a + b)) is
+  sin(W' a + b') with W' = omega_0 W, b' = omega_0 b), so s' = cos and
+  s'' = -sin.
 
 Derivatives follow the forward chain rule of Alg. "Network gradient"
 (Sec. "Network Gradients via Direct Differentiation"): each layer maps the
@@ -46,6 +51,21 @@ def elu_d2(z):
     return np.where(z > 0, 0.0, np.exp(np.minimum(z, 0.0)))
 
 
+def sine(z):
+    return np.sin(z)
+
+
+def sine_d1(z):
+    return np.cos(z)
+
+
+def sine_d2(z):
+    return -np.sin(z)
+
+
+ACTIVATIONS = {"elu": (elu, elu_d1, elu_d2), "sine": (sine, sine_d1, sine_d2)}
+
+
 def _inputs(x, q):
     x = np.asarray(x, dtype=np.float64)
     if x.ndim == 1:
@@ -54,36 +74,39 @@ def _inputs(x, q):
     return np.concatenate([x, np.broadcast_to(q, (x.shape[0], q.size))], axis=1)
 
 
-def preactivations(layers: Sequence[Layer], x, q) -> List[np.ndarray]:
+def preactivations(layers: Sequence[Layer], x, q, act: str = "elu") -> List[np.ndarray]:
     """Hidden pre-activations z_1..z_H at every point (used by tests to keep
     finite-difference probes away from the ELU kink)."""
+    s0 = ACTIVATIONS[act][0]
     layers = as_f64(layers)
     a = _inputs(x, q)
     zs = []
     for W, b in layers[:-1]:
         z = a @ W.T + b
         zs.append(z)
-        a = elu(z)
+        a = s0(z)
     return zs
 
 
-def decode(layers: Sequence[Layer], x, q) -> np.ndarray:
+def decode(layers: Sequence[Layer], x, q, act: str = "elu") -> np.ndarray:
     """g(x_p, q) at every point: x [P, m], q [r] -> g [P, d]."""
+    s0 = ACTIVATIONS[act][0]
     layers = as_f64(layers)
     a = _inputs(x, q)
     for W, b in layers[:-1]:
-        a = elu(a @ W.T + b)
+        a = s0(a @ W.T + b)
     W, b = layers[-1]
     return a @ W.T + b
 
 
-def decode_jets(layers: Sequence[Layer], x, q, m: int):
+def decode_jets(layers: Sequence[Layer], x, q, m: int, act: str = "elu"):
     """Value and exact derivatives by forward-mode propagation.
 
     Returns (g [P,d], dg/dx [P,d,m], d2g/dx2 [P,d,m,m], dg/dq [P,d,r]).
     Tangents are carried for every network input (the m coordinates and the
     r latent entries); second-order tangents for the m coordinates only.
     """
+    s0, d1, d2 = ACTIVATIONS[act]
     layers = as_f64(layers)
     a = _inputs(x, q)
     P, n0 = a.shape
@@ -96,9 +119,9 @@ def decode_jets(layers: Sequence[Layer], x, q, m: int):
         z = a @ W.T + b
         dz = np.einsum("uk,pki->pui", W, da)
         ddz = np.einsum("uk,pkij->puij", W, dda)
-        s1 = elu_d1(z)
-        s2 = elu_d2(z)
-        a = elu(z)
+        s1 = d1(z)
+        s2 = d2(z)
+        a = s0(z)
         dzx = dz[:, :, :m]
         dda = (s2[:, :, None, None] * dzx[:, :, :, None] * dzx[:, :, None, :]
                + s1[:, :, None, None] * ddz)
@@ -126,24 +149,25 @@ def hessian_packed(hess: np.ndarray) -> np.ndarray:
 class MLPDecoder:
     """Adapter giving the latent step the decoder quantities it needs."""
 
-    def __init__(self, layers: Sequence[Layer], m: int):
+    def __init__(self, layers: Sequence[Layer], m: int, act: str = "elu"):
         self.layers = as_f64(layers)
         self.m = m
+        self.act = act
         self.r = self.layers[0][0].shape[1] - m
         self.d = self.layers[-1][0].shape[0]
 
     def value(self, y, q):
-        return decode(self.layers, y, q)
+        return decode(self.layers, y, q, self.act)
 
     def jac_q(self, y, q):
-        return decode_jets(self.layers, y, q, self.m)[3]
+        return decode_jets(self.layers, y, q, self.m, self.act)[3]
 
     def value_jac_q(self, y, q):
-        g, _, _, J = decode_jets(self.layers, y, q, self.m)
+        g, _, _, J = decode_jets(self.layers, y, q, self.m, self.act)
         return g, J
 
     def jets(self, y, q):
-        return decode_jets(self.layers, y, q, self.m)
+        return decode_jets(self.layers, y, q, self.m, self.act)
 
     def laplacian(self, y, q):
-        return laplacian(decode_jets(self.layers, y, q, self.m)[2])
+        return laplacian(decode_jets(self.layers, y, q, self.m, self.act)[2])

@@ -174,3 +174,75 @@ def test_elu_tie_reading():
     np.testing.assert_array_equal(mlp.elu(z), [np.expm1(-1.0), 0.0, 2.0])
     np.testing.assert_array_equal(mlp.elu_d1(z), [np.exp(-1.0), 1.0, 1.0])
     np.testing.assert_array_equal(mlp.elu_d2(z), [np.exp(-1.0), 1.0, 0.0])
+
+
+# ---- sine activation (SIREN) -------------------------------------------------
+
+def test_sine_one_layer_closed_form():
+    """g = sum_u w_u sin(A_u [x; q] + c_u) + b: gradient, Hessian and latent
+    Jacobian written out (cos and -sin of the pre-activations)."""
+    from workloads import siren_mlp
+    g = rng(21)
+    m, r = 2, 3
+    layers = siren_mlp(g, m, r, 1, 16, 1)
+    x = g.uniform(-1, 1, size=(7, m))
+    q = g.uniform(-1, 1, size=r)
+    A, c = [np.asarray(t, np.float64) for t in layers[0]]
+    w, b = [np.asarray(t, np.float64) for t in layers[1]]
+    z = np.concatenate([x, np.tile(q, (7, 1))], axis=1) @ A.T + c
+    val, gx, hx, gq = mlp.decode_jets(layers, x, q, m, act="sine")
+    np.testing.assert_allclose(val[:, 0], np.sin(z) @ w[0] + b[0], rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(gx[:, 0], (np.cos(z) * w[0]) @ A[:, :m], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(gq[:, 0], (np.cos(z) * w[0]) @ A[:, m:], rtol=1e-12, atol=1e-12)
+    H = -np.einsum("pu,u,ui,uj->pij", np.sin(z), w[0], A[:, :m], A[:, :m])
+    np.testing.assert_allclose(hx[:, 0], H, rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(mlp.laplacian(hx)[:, 0], np.trace(H, axis1=1, axis2=2), rtol=1e-11, atol=1e-11)
+
+
+def test_sine_autograd_witness_float64():
+    torch = pytest.importorskip("torch")
+    from workloads import siren_mlp
+    g = rng(22)
+    m, r, d = 2, 3, 2
+    layers = siren_mlp(g, m, r, d, 12, 3)
+    x = g.uniform(-1, 1, size=(4, m))
+    q = g.uniform(-1, 1, size=r)
+    Ws = [(torch.tensor(W, dtype=torch.float64), torch.tensor(b, dtype=torch.float64)) for W, b in layers]
+
+    def net(a):
+        for W, b in Ws[:-1]:
+            a = torch.sin(a @ W.T + b)
+        W, b = Ws[-1]
+        return a @ W.T + b
+
+    val, gx, hx, gq = mlp.decode_jets(layers, x, q, m, act="sine")
+    for p in range(x.shape[0]):
+        a0 = torch.tensor(np.concatenate([x[p], q]))
+        np.testing.assert_allclose(val[p], net(a0).detach().numpy(), rtol=1e-12, atol=1e-12)
+        jac = torch.autograd.functional.jacobian(net, a0).numpy()
+        np.testing.assert_allclose(gx[p], jac[:, :m], rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(gq[p], jac[:, m:], rtol=1e-10, atol=1e-10)
+        for o in range(d):
+            Hh = torch.autograd.functional.hessian(lambda v: net(v)[o], a0).numpy()
+            np.testing.assert_allclose(hx[p, o], Hh[:m, :m], rtol=1e-9, atol=1e-9)
+
+
+def test_sine_derivatives_vs_central_fd():
+    """Smooth everywhere: no kink to avoid."""
+    from workloads import siren_mlp
+    g = rng(23)
+    m, r = 2, 4
+    layers = siren_mlp(g, m, r, 1, 16, 3)
+    x = g.uniform(-1, 1, size=(5, m))
+    q = g.uniform(-1, 1, size=r)
+    _, gx, hx, _ = mlp.decode_jets(layers, x, q, m, act="sine")
+    h = 1e-5
+    for i in range(m):
+        e = np.zeros(m)
+        e[i] = h
+        fd = (mlp.decode(layers, x + e, q, "sine") - mlp.decode(layers, x - e, q, "sine")) / (2 * h)
+        np.testing.assert_allclose(gx[:, :, i], fd, rtol=1e-6, atol=1e-6 * np.abs(fd).max())
+        gp = mlp.decode_jets(layers, x + e, q, m, act="sine")[1]
+        gm = mlp.decode_jets(layers, x - e, q, m, act="sine")[1]
+        np.testing.assert_allclose(hx[:, :, :, i], (gp - gm) / (2 * h), rtol=1e-5,
+                                   atol=1e-6 * np.abs(hx).max())

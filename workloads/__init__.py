@@ -52,6 +52,32 @@ def xavier_mlp(gen: np.random.Generator, m: int, r: int, d: int, width: int,
     return layers
 
 
+def siren_mlp(gen: np.random.Generator, m: int, r: int, d: int, width: int,
+              depth: int, omega0: float = 30.0) -> List[Layer]:
+    """SIREN initialisation (Sitzmann et al. 2020, the paper's default
+    omega_0 = 30), drawn layer by layer, with omega_0 folded into the sine
+    layers' weights and biases (the network computes sin(W a + b)):
+    first layer W ~ omega_0 U(-1/n_in, 1/n_in), hidden layers
+    W ~ U(-sqrt(6/n_in), sqrt(6/n_in)), biases of sine layers
+    omega_0 U(-1/sqrt(n_in), 1/sqrt(n_in)); the linear output layer
+    W ~ U(-sqrt(6/n_in)/omega_0, sqrt(6/n_in)/omega_0), b ~ U(-1/sqrt(n_in), 1/sqrt(n_in))."""
+    sizes = layer_sizes(m, r, d, width, depth)
+    layers: List[Layer] = []
+    last = len(sizes) - 2
+    for l, (n_in, n_out) in enumerate(zip(sizes[:-1], sizes[1:])):
+        if l == 0:
+            a = omega0 / n_in
+        elif l < last:
+            a = np.sqrt(6.0 / n_in)
+        else:
+            a = np.sqrt(6.0 / n_in) / omega0
+        W = gen.uniform(-a, a, size=(n_out, n_in)).astype(np.float32)
+        bb = 1.0 / np.sqrt(n_in) * (omega0 if l < last else 1.0)
+        b = gen.uniform(-bb, bb, size=n_out).astype(np.float32)
+        layers.append((W, b))
+    return layers
+
+
 def uniform_points(gen: np.random.Generator, n: int, m: int,
                    lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
     return gen.uniform(lo, hi, size=(n, m)).astype(np.float32)
