@@ -318,6 +318,65 @@ def sampling_leg(args, crom, torch, dev, trained):
                                 "frac_of_peak": flop_res / t_res / 1e12 / PEAK[args.prec]}}
 
 
+def siren_leg(args, crom, torch, dev):
+    """The sine-activated decoder (SIREN, omega_0 = 30 folded into the
+    weights) of the 2D shape, inputs in [-1, 1]^2: full-field value decode of
+    the 256 x 256 grid, the 12-column decode at the same nodes, and the
+    single-instance Gauss-Newton heat step at 2,000 samples, in BF16 and
+    FP32 (the ELU numbers of the same shapes are the main line's)."""
+    from workloads import Heat2D, rng, siren_mlp
+    wl = Heat2D(seed=args.seed)
+    layers = siren_mlp(rng(args.seed + 11), wl.m, wl.r, wl.d, wl.width, wl.depth)
+    nodes = torch.from_numpy((2.0 * wl.nodes - 1.0).astype(np.float32)).to(dev)
+    samples = torch.from_numpy((2.0 * wl.samples - 1.0).astype(np.float32)).to(dev)
+    q0 = torch.from_numpy(wl.q0).to(dev)
+    P = nodes.shape[0]
+    out = {"net": "SIREN (2 + 8) -> 5 x sine width 128 -> 1, omega_0 = 30, seeded SIREN initialisation"}
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for prec in (args.prec, "fp32"):
+        dec = crom.Decoder.from_layers(layers, wl.m, precision=prec, device=dev, act="sine")
+        g = torch.empty(P, 1, dtype=torch.float32, device=dev)
+        for _ in range(3):
+            dec.decode(nodes, q0, out=g)
+        e[0].record()
+        for _ in range(20):
+            dec.decode(nodes, q0, out=g)
+        e[1].record()
+        torch.cuda.synchronize()
+        t_val = e[0].elapsed_time(e[1]) * 1e-3 / 20
+        for _ in range(2):
+            dec.decode_jac(nodes, q0, dx=True, d2=crom.D2_LAPLACIAN, dq=True)
+        e[0].record()
+        for _ in range(10):
+            dec.decode_jac(nodes, q0, dx=True, d2=crom.D2_LAPLACIAN, dq=True)
+        e[1].record()
+        torch.cuda.synchronize()
+        t_jac = e[0].elapsed_time(e[1]) * 1e-3 / 10
+        st = crom.Stepper(dec, [0, wl.n_samples], samples)
+        nu = torch.tensor([wl.mu], dtype=torch.float64, device=dev)
+        opts = crom.GNOptions(max_iter=5, tol_step=TOL_STEP)
+        q = [q0[None].clone(), torch.empty(1, R, dtype=torch.float64, device=dev)]
+        for i in range(5):
+            st.step(q[i % 2], nu, wl.dt, opts, q_next=q[(i + 1) % 2])
+        torch.cuda.synchronize()
+        crom.kernel_timer(True)
+        e[0].record()
+        n_steps = 50
+        for i in range(n_steps):
+            st.step(q[i % 2], nu, wl.dt, opts, q_next=q[(i + 1) % 2])
+        e[1].record()
+        torch.cuda.synchronize()
+        crom.kernel_timer(False)
+        k_ms, k_n = crom.kernel_timer_read()
+        inf = st.info()[0]
+        out[prec] = {"value_decode_ms": t_val * 1e3, "value_decode_tflops": P * FLOP_VALUE_COL / t_val / 1e12,
+                     "jac_decode_ms": t_jac * 1e3, "jac_decode_tflops": P * FLOP_POINT_EVAL / t_jac / 1e12,
+                     "gn_step_ms": e[0].elapsed_time(e[1]) / n_steps, "gn_step_kernel_ms": k_ms / max(1, k_n),
+                     "gn_iters_last": int(inf["iters"]), "ls_evals_last": int(inf["ls_evals"]),
+                     "flags_last": int(inf["flags"])}
+    return out
+
+
 def config1_leg(args, crom, torch, dev):
     """1D heat (nu = 0.5, decoder (1 + 3) -> 5 x 32 -> 1, 20 samples, dt =
     1e-5): a 1000-step Gauss-Newton rollout in FP32 on the GPU, the same
@@ -446,6 +505,7 @@ def main():
     ap.add_argument("--c1-cpu", type=int, default=1, help="time the oracle's 1D rollout too")
     ap.add_argument("--c3-steps", type=int, default=20, help="3D elastic steps timed (0: skip)")
     ap.add_argument("--c3-cpu", type=int, default=0, help="time one oracle elastic step too (about 30 s)")
+    ap.add_argument("--siren", type=int, default=1, help="time the sine-activated decoder and step (0: skip)")
     ap.add_argument("--sampling-rounds", type=int, default=32,
                     help="greedy sample-selection rounds with the trained network (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -552,6 +612,7 @@ def main():
     training, trained = train_leg(args, crom, torch, dev) if args.train_time_steps > 0 else (None, None)
     batched = batched_leg(args, crom, torch, dev, trained) if args.batched_steps > 0 else None
     sampling = sampling_leg(args, crom, torch, dev, trained) if trained and args.sampling_rounds > 0 else None
+    siren = siren_leg(args, crom, torch, dev) if args.siren else None
     cpu = cpu_baseline(wl, nodes, args.cpu_steps) if args.cpu_steps > 0 else None
     its = np.array([int(i["iters"]) for i in infos])
     lse = np.array([int(i["ls_evals"]) for i in infos])
@@ -577,6 +638,7 @@ def main():
         "training": training,
         "batched": batched,
         "sampling": sampling,
+        "siren": siren,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

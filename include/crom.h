@@ -85,14 +85,23 @@ enum {
  * params: FP32, natural layout, layer by layer for l = 1 .. depth+1:
  *   W_l [n_l][n_{l-1}] row-major, then b_l [n_l], with n_0 = m + r
  *   (input order [x; q]: x first), n_1..n_depth = width, n_{depth+1} = d.
- *   Hidden layers use ELU with alpha = 1 (ELU(z) = z for z > 0, e^z - 1
- *   otherwise; z = 0 takes the exponential branch); the output layer is
- *   linear.
+ *   The output layer is linear.
+ * act: the hidden layers' activation (Sec. "Network Details": ELU or
+ *   SIREN):
+ *   CROM_ACT_ELU   ELU with alpha = 1 (ELU(z) = z for z > 0, e^z - 1
+ *                  otherwise; z = 0 takes the exponential branch)
+ *   CROM_ACT_SINE  sin(z), the SIREN layer with its frequency omega_0
+ *                  folded into W_l and b_l (sin(omega_0 (W a + b)) is
+ *                  sin(W' a + b') with W' = omega_0 W, b' = omega_0 b).
+ *                  Supported by the decode calls and the heat step for
+ *                  the (1, 3, 1, 32) and (2, 8, 1, 128) shapes in FP32 and
+ *                  BF16; other calls return CROM_ERR_UNSUPPORTED.
  * packed: the fragment-ordered copy of the hidden-to-hidden weights that
  *   crom_net_pack writes (crom_net_packed_bytes long).  It must be
  *   refreshed after params change. */
+enum { CROM_ACT_ELU = 0, CROM_ACT_SINE = 1 };
 typedef struct {
-  int32_t m, r, d, width, depth, precision;
+  int32_t m, r, d, width, depth, precision, act, _pad;
   const float* params;
   const void* packed;
 } crom_net;

@@ -21,14 +21,16 @@ LIB_PATH = os.path.join(_HERE, "libcrom.so")
 PREC_FP32, PREC_BF16, PREC_BF16_PURE, PREC_BF16X3 = 0, 1, 2, 3
 D2_NONE, D2_LAPLACIAN, D2_HESSIAN = 0, 1, 2
 PDE_HEAT, PDE_NEOHOOKEAN = 0, 1
+ACT_ELU, ACT_SINE = 0, 1
+_ACT_NAMES = {"elu": ACT_ELU, "sine": ACT_SINE}
 FLAG_MAXITER, FLAG_SINGULAR, FLAG_NONFINITE, FLAG_LS_FAIL, FLAG_ABORTED = 1, 2, 4, 8, 16
 _PREC_NAMES = {"fp32": PREC_FP32, "bf16": PREC_BF16, "bf16pure": PREC_BF16_PURE, "bf16x3": PREC_BF16X3}
 
 
 class CromNet(Structure):
     _fields_ = [("m", c_int32), ("r", c_int32), ("d", c_int32), ("width", c_int32),
-                ("depth", c_int32), ("precision", c_int32), ("params", c_void_p),
-                ("packed", c_void_p)]
+                ("depth", c_int32), ("precision", c_int32), ("act", c_int32), ("_pad", c_int32),
+                ("params", c_void_p), ("packed", c_void_p)]
 
 
 class CromPDE(Structure):
@@ -185,10 +187,11 @@ class Decoder:
     fragment copy for the chosen precision."""
 
     def __init__(self, params, m: int, r: int, d: int, width: int, depth: int,
-                 precision="bf16", device="cuda"):
+                 precision="bf16", device="cuda", act="elu"):
         torch = _torch()
         self.m, self.r, self.d, self.width, self.depth = m, r, d, width, depth
         self.precision = _PREC_NAMES[precision] if isinstance(precision, str) else int(precision)
+        self.act = _ACT_NAMES[act] if isinstance(act, str) else int(act)
         n = param_count(m, r, d, width, depth)
         if isinstance(params, np.ndarray):
             params = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32))
@@ -201,13 +204,13 @@ class Decoder:
         self.pack()
 
     @classmethod
-    def from_layers(cls, layers, m: int, precision="bf16", device="cuda"):
+    def from_layers(cls, layers, m: int, precision="bf16", device="cuda", act="elu"):
         r = layers[0][0].shape[1] - m
         return cls(flatten_layers(layers), m, r, layers[-1][0].shape[0], layers[0][0].shape[0],
-                   len(layers) - 1, precision, device)
+                   len(layers) - 1, precision, device, act)
 
     def _net(self, packed=True) -> CromNet:
-        return CromNet(self.m, self.r, self.d, self.width, self.depth, self.precision,
+        return CromNet(self.m, self.r, self.d, self.width, self.depth, self.precision, self.act, 0,
                        self.params.data_ptr(), self.packed.data_ptr() if packed else None)
 
     def pack(self) -> None:

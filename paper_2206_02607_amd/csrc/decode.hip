@@ -53,6 +53,10 @@ crom_status check_net(const crom_net* net, bool need_packed) {
                 "unsupported (m, r, d, width); compiled: (1,3,1,32), (2,8,1,128), (3,16,3,256)");
   if (net->precision < CROM_PREC_FP32 || net->precision > CROM_PREC_BF16X3)
     return fail(CROM_ERR_UNSUPPORTED, "unknown precision");
+  if (net->act != CROM_ACT_ELU && net->act != CROM_ACT_SINE) return fail(CROM_ERR_UNSUPPORTED, "unknown activation");
+  if (net->act == CROM_ACT_SINE &&
+      ((net->precision != CROM_PREC_FP32 && net->precision != CROM_PREC_BF16) || shape_id(net->m, net->r, net->d, net->width) == SHAPE_3D))
+    return fail(CROM_ERR_UNSUPPORTED, "sine activation: shapes (1,3,1,32) and (2,8,1,128), FP32 or BF16");
   if (!net->params) return fail(CROM_ERR_INVALID_ARG, "net->params is NULL");
   if (need_packed && net->depth > 1 && !net->packed)
     return fail(CROM_ERR_INVALID_ARG, "net->packed is NULL (call crom_net_pack)");
@@ -252,6 +256,10 @@ static crom_status decode_shape(const DecodeArgs& a0, bool xt, int d2, bool qt, 
 
 template <class S, int NW>
 static crom_status decode_prec(int prec, const DecodeArgs& a, bool xt, int d2, bool qt, hipStream_t st) {
+  if constexpr (S::ACT == ACT_SINE) {  // FP32 and BF16 only (checked by check_net)
+    if (prec == CROM_PREC_FP32) return decode_shape<S, NW, PREC_FP32, 4, 3>(a, xt, d2, qt, st);
+    return decode_shape<S, NW, PREC_BF16, 8, 3>(a, xt, d2, qt, st);
+  }
   switch (prec) {
     case CROM_PREC_FP32: return decode_shape<S, NW, PREC_FP32, 4, 3>(a, xt, d2, qt, st);
     case CROM_PREC_BF16: return decode_shape<S, NW, PREC_BF16, 8, 3>(a, xt, d2, qt, st);
@@ -292,8 +300,12 @@ static crom_status decode_any(const crom_net* net, const float* x, int64_t P, co
   const bool qt = dgdq != nullptr;
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (shape_id(net->m, net->r, net->d, net->width)) {
-    case SHAPE_1D: return decode_prec<Shape<32, 1, 3, 1>, 2>(net->precision, a, xt, d2, qt, st);
-    case SHAPE_2D: return decode_prec<Shape<128, 2, 8, 1>, 4>(net->precision, a, xt, d2, qt, st);
+    case SHAPE_1D:
+      if (net->act == CROM_ACT_SINE) return decode_prec<Shape<32, 1, 3, 1, ACT_SINE>, 2>(net->precision, a, xt, d2, qt, st);
+      return decode_prec<Shape<32, 1, 3, 1>, 2>(net->precision, a, xt, d2, qt, st);
+    case SHAPE_2D:
+      if (net->act == CROM_ACT_SINE) return decode_prec<Shape<128, 2, 8, 1, ACT_SINE>, 4>(net->precision, a, xt, d2, qt, st);
+      return decode_prec<Shape<128, 2, 8, 1>, 4>(net->precision, a, xt, d2, qt, st);
     case SHAPE_3D: return decode_prec<Shape<256, 3, 16, 3>, 8>(net->precision, a, xt, d2, qt, st);
     default: return fail(CROM_ERR_UNSUPPORTED, "shape");
   }

@@ -4,16 +4,19 @@
 // What is computed (Sec. "Network Details"; Alg. "Network gradient" of
 // Sec. "Network Gradients via Direct Differentiation", extended to second
 // order in x and to the latent directions):
-//   z_l = W_l a_{l-1} + b_l,  a_l = ELU(z_l)          value column
+//   z_l = W_l a_{l-1} + b_l,  a_l = s(z_l)            value column
 //   dz_l = W_l da_{l-1},      da_l = s1(z_l) dz_l      tangent columns (x_i, q_k)
 //   D2z_l = W_l D2a_{l-1},    D2a_l = s2(z_l) dz_i dz_j + s1(z_l) D2z_l
-// with s1 = ELU', s2 = ELU''; the Laplacian column carries sum_i of the
+// with s = ELU (s1 = ELU', s2 = ELU'') or, for SIREN networks (Sec.
+// "Network Details"), s = sin (s1 = cos, s2 = -sin, the frequency omega_0
+// folded into the weights); the Laplacian column carries sum_i of the
 // diagonal second derivatives in one column (s2 * sum_i dz_i^2 + s1 * D2z).
 // Difference columns carry g(x, q_t) - g(x, q_b) for latents q_t near the
 // value column's latent q_b, layer by layer as
-//   Dz_l = W_l Da_{l-1},      Da_l = ELU(z_l + Dz_l) - ELU(z_l),
-// evaluated without cancellation (e^z expm1(Dz) on the exponential branch),
-// so their rounding error is relative to the difference itself.  The latent
+//   Dz_l = W_l Da_{l-1},      Da_l = s(z_l + Dz_l) - s(z_l),
+// evaluated without cancellation (e^z expm1(Dz) on ELU's exponential
+// branch; 2 cos(z + Dz/2) sin(Dz/2) for the sine), so their rounding error
+// is relative to the difference itself.  The latent
 // tangents then belong to the first difference column's latent
 // (z_l + Dz_l); without difference columns, to the value column's.
 // The first layer is folded: W_1 [x; q] + b_1 = W_1x x + c with the per-
@@ -56,10 +59,11 @@ constexpr int PT = 16;  // points per N-tile
 enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_BF16_PURE = 2, PREC_BF16X3 = 3 };
 enum { CK_VAL = 0, CK_DIFF = 1, CK_XT = 2, CK_LAP = 3, CK_HESS = 4, CK_QT = 5 };
 enum { D2_NONE = 0, D2_LAP = 1, D2_HESS = 2 };
+enum { ACT_ELU = 0, ACT_SINE = 1 };  // hidden-layer activation (CROM_ACT_*)
 
-template <int W_, int M_, int R_, int D_>
+template <int W_, int M_, int R_, int D_, int ACT_ = ACT_ELU>
 struct Shape {
-  static constexpr int W = W_, M = M_, R = R_, D = D_;
+  static constexpr int W = W_, M = M_, R = R_, D = D_, ACT = ACT_;
   static constexpr int MTILES = W_ / 16;
   static constexpr int N0 = M_ + R_;
 };
@@ -135,6 +139,25 @@ __device__ __forceinline__ float elu_exp(float z) { return __expf(z > 0.0f ? 0.0
 __device__ __forceinline__ float expm1_acc(float x) {
   const float p = x * (1.0f + x * (0.5f + x * (1.0f / 6 + x * (1.0f / 24 + x * (1.0f / 120)))));
   return fabsf(x) < 0.03125f ? p : __expf(x) - 1.0f;
+}
+
+// Sine and cosine for the SIREN epilogue: a Cody-Waite reduction of x to
+// [-pi, pi] (2 pi as a float plus its remainder, each product by one fused
+// multiply-add), then the hardware approximations, which are accurate on
+// that interval; the full-range library routines would more than double the
+// registers of the engine's epilogue.
+__device__ __forceinline__ float reduce_2pi(float x) {
+  const float k = rintf(x * 0.159154943f);
+  const float r = fmaf(-k, 6.28318548f, x);
+  return fmaf(-k, -1.74845553e-07f, r);
+}
+__device__ __forceinline__ float sin_r(float x) { return __sinf(reduce_2pi(x)); }
+__device__ __forceinline__ float cos_r(float x) { return __cosf(reduce_2pi(x)); }
+// sin(h) with an error relative to h for small h (Taylor series through
+// h^5 for |h| < 1/32: relative error below 1e-11).
+__device__ __forceinline__ float sin_small(float h) {
+  const float h2 = h * h;
+  return fabsf(h) < 0.03125f ? h * (1.0f - h2 * (1.0f / 6) * (1.0f - h2 * (1.0f / 20))) : sin_r(h);
 }
 
 // Small parameters, staged once into LDS by every workgroup (FP32):
@@ -265,6 +288,10 @@ struct Engine {
   // ---- epilogue ---------------------------------------------------------
   // In place on z[t] for one (unit, lane) across all tiles.
   static __device__ __forceinline__ void epilogue(float (&z)[NT]) {
+    if constexpr (S::ACT == ACT_SINE) {
+      epilogue_sine(z);
+      return;
+    }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       float* zb = &z[b * CC];
@@ -308,6 +335,46 @@ struct Engine {
         zb[c] = zz > 0.0f ? zz : elu_exp(zz) - 1.0f;
       }
       zb[0] = pos0 ? z0 : e0 - 1.0f;
+    }
+  }
+
+  // The same column rules with s = sin: s1 = cos, s2 = -sin, differences
+  // sin(z + Dz) - sin(z) = 2 cos(z + Dz/2) sin(Dz/2).
+  static __device__ __forceinline__ void epilogue_sine(float (&z)[NT]) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      float* zb = &z[b * CC];
+      const float z0 = zb[0];
+      const float r0 = reduce_2pi(z0);
+      const float sn0 = __sinf(r0), cs0 = __cosf(r0);
+      const float s1 = cs0, s2 = -sn0;
+      float st = s1;  // tangent scale: at the base latent, or at difference column 0's
+#pragma unroll
+      for (int c = C::F0; c < C::X0; ++c) {
+        const float dz = zb[c];
+        zb[c] = 2.0f * cos_r(z0 + 0.5f * dz) * sin_small(0.5f * dz);
+        if (c == C::F0) st = cos_r(z0 + dz);
+      }
+      if constexpr (C::D2 == D2_LAP) {
+        float sq = 0.0f;
+#pragma unroll
+        for (int i = 0; i < C::NX; ++i) sq += zb[C::X0 + i] * zb[C::X0 + i];
+        zb[C::D0] = s1 * zb[C::D0] + s2 * sq;
+      } else if constexpr (C::D2 == D2_HESS) {
+#pragma unroll
+        for (int c = C::D0; c < C::Q0; ++c) {
+          const float zi = zb[C::X0 + C::hess_i(c)];
+          const float zj = zb[C::X0 + C::hess_j(c)];
+          zb[c] = s1 * zb[c] + s2 * zi * zj;
+        }
+      }
+#pragma unroll
+      for (int c = C::X0; c < C::D0; ++c) zb[c] = s1 * zb[c];
+#pragma unroll
+      for (int c = C::Q0; c < CC; ++c) zb[c] = st * zb[c];
+#pragma unroll
+      for (int c = 1; c < C::NV; ++c) zb[c] = sin_r(zb[c]);
+      zb[0] = sn0;
     }
   }
 

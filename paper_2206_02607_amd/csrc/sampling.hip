@@ -349,6 +349,7 @@ crom_status crom_sampling_residual(const crom_net* net, const float* nodes, int6
                                    const double* q, const double* ref, double* res, double* metric, void* stream) {
   crom_status s = check_net(net, true);
   if (s != CROM_OK) return s;
+  if (net->act != CROM_ACT_ELU) return fail(CROM_ERR_UNSUPPORTED, "sample selection: ELU networks");
   if (P < 1) return fail(CROM_ERR_INVALID_ARG, "P must be >= 1");
   if (n_set < 1 || n_set > 65535) return fail(CROM_ERR_INVALID_ARG, "n_set must be in [1, 65535]");
   if (n_mu < 1) return fail(CROM_ERR_INVALID_ARG, "n_mu must be >= 1");
@@ -385,6 +386,7 @@ crom_status crom_robust_sampling(const crom_net* net, const crom_pde* pde, int32
                                  double* trace_metric, void* ws, size_t ws_bytes, void* stream) {
   crom_status s = check_net(net, true);
   if (s != CROM_OK) return s;
+  if (net->act != CROM_ACT_ELU) return fail(CROM_ERR_UNSUPPORTED, "sample selection: ELU networks");
   if (!pde || !pde->coef) return fail(CROM_ERR_INVALID_ARG, "pde and pde->coef are required");
   if (!nodes || !ref || !q0 || !gn || !samples || !result || !ws)
     return fail(CROM_ERR_INVALID_ARG, "nodes, ref, q0, gn, samples, result and ws are required");

@@ -80,7 +80,10 @@
 namespace crom {
 
 constexpr int RMAX = 16;
-constexpr int TV = 4;        // line-search trials per round
+#ifndef CROM_TRIALS
+#define CROM_TRIALS 4
+#endif
+constexpr int TV = CROM_TRIALS;  // line-search trials per round
 constexpr int MAXP = 256;    // bound on the phases of one step
 enum { PH_INIT = 0, PH_TRIALS = 1, PH_REJAC = 2, PH_DONE = 3 };
 
@@ -734,6 +737,10 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
   const int NS = nth / NRED;  // strided subsets per entry
   double* red = sub + NS * NRED;
   __shared__ int s_done;
+  // The state and the batch partials are independent: their loads are all
+  // issued before the first wait (one memory round trip, not two).
+  const int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
+  const int32_t b0 = first_blk[inst], b1 = first_blk[inst + 1];
   if (p == 0) {  // the state before the first solve, formed from q_n
     for (int w = threadIdx.x; w < NWORD; w += nth)
       reinterpret_cast<uint64_t*>(st)[w] = gn_initial_word(w, a.q_n + (int64_t)inst * R, R, false);
@@ -741,10 +748,6 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
     for (int w = threadIdx.x; w < NWORD; w += nth)
       reinterpret_cast<uint64_t*>(st)[w] = ld_c(reinterpret_cast<const uint64_t*>(gst) + w);
   }
-  __syncthreads();
-  const int phase = st->phase;
-  const int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
-  const int32_t b0 = first_blk[inst], b1 = first_blk[inst + 1];
   const double* part = wsp<double>(a, a.L.partials);
   if (threadIdx.x < NS * NRED) {
     const int e = threadIdx.x % NRED, sl = threadIdx.x / NRED;
@@ -762,6 +765,7 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
     sub[sl * NRED + e] = acc;
   }
   __syncthreads();
+  const int phase = st->phase;
   if (threadIdx.x < NRED) {
     double s = 0.0;
     for (int sl = 0; sl < NS; ++sl) s += sub[sl * NRED + threadIdx.x];
@@ -1330,31 +1334,36 @@ static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
 // half the size, so BF16 and BF16_PURE afford eight waves with prefetch.
 template <class S, int NWB, int NWF, int PFB = 1, int WPEB = 1>
 static crom_status step_prec(int prec, const StepArgs& a, int rounds, hipStream_t st) {
+  // sine networks: FP32 and BF16 only (checked by check_net)
+  constexpr bool ALL = S::ACT == ACT_ELU;
   if (a.linearized) {
     // four waves with two M-tiles each and streamed weights: the measured
     // best for the 12-column engine (two workgroups per CU)
     constexpr int NWL = S::MTILES < CROM_LIN_NW ? S::MTILES : CROM_LIN_NW;
-    switch (prec) {
-      case CROM_PREC_FP32: return launch_lls<S, NWF, PREC_FP32, 0, 1>(a, st);
-      case CROM_PREC_BF16: return launch_lls<S, NWL, PREC_BF16, CROM_LIN_PF, CROM_LIN_WPE>(a, st);
-      case CROM_PREC_BF16_PURE: return launch_lls<S, NWL, PREC_BF16_PURE, CROM_LIN_PF, CROM_LIN_WPE>(a, st);
-      default: return launch_lls<S, NWF, PREC_BF16X3, 0, 1>(a, st);
+    if (prec == CROM_PREC_FP32) return launch_lls<S, NWF, PREC_FP32, 0, 1>(a, st);
+    if (prec == CROM_PREC_BF16) return launch_lls<S, NWL, PREC_BF16, CROM_LIN_PF, CROM_LIN_WPE>(a, st);
+    if constexpr (ALL) {
+      if (prec == CROM_PREC_BF16_PURE) return launch_lls<S, NWL, PREC_BF16_PURE, CROM_LIN_PF, CROM_LIN_WPE>(a, st);
+      return launch_lls<S, NWF, PREC_BF16X3, 0, 1>(a, st);
     }
+    return fail(CROM_ERR_UNSUPPORTED, "precision");
   }
   if (a.L.nblk_max > ROUNDS_MIN_BATCHES) {
-    switch (prec) {
-      case CROM_PREC_FP32: return launch_gn_rounds<S, NWF, PREC_FP32, 0, 1>(a, rounds, st);
-      case CROM_PREC_BF16: return launch_gn_rounds<S, NWB, PREC_BF16, PFB, WPEB>(a, rounds, st);
-      case CROM_PREC_BF16_PURE: return launch_gn_rounds<S, NWB, PREC_BF16_PURE, PFB, WPEB>(a, rounds, st);
-      default: return launch_gn_rounds<S, NWF, PREC_BF16X3, 0, 1>(a, rounds, st);
+    if (prec == CROM_PREC_FP32) return launch_gn_rounds<S, NWF, PREC_FP32, 0, 1>(a, rounds, st);
+    if (prec == CROM_PREC_BF16) return launch_gn_rounds<S, NWB, PREC_BF16, PFB, WPEB>(a, rounds, st);
+    if constexpr (ALL) {
+      if (prec == CROM_PREC_BF16_PURE) return launch_gn_rounds<S, NWB, PREC_BF16_PURE, PFB, WPEB>(a, rounds, st);
+      return launch_gn_rounds<S, NWF, PREC_BF16X3, 0, 1>(a, rounds, st);
     }
+    return fail(CROM_ERR_UNSUPPORTED, "precision");
   }
-  switch (prec) {
-    case CROM_PREC_FP32: return launch_step<S, NWF, PREC_FP32, 0>(a, rounds, st);
-    case CROM_PREC_BF16: return launch_step<S, NWB, PREC_BF16, PFB, PK_HEAT, WPEB>(a, rounds, st);
-    case CROM_PREC_BF16_PURE: return launch_step<S, NWB, PREC_BF16_PURE, PFB, PK_HEAT, WPEB>(a, rounds, st);
-    default: return launch_step<S, NWF, PREC_BF16X3, 0>(a, rounds, st);
+  if (prec == CROM_PREC_FP32) return launch_step<S, NWF, PREC_FP32, 0>(a, rounds, st);
+  if (prec == CROM_PREC_BF16) return launch_step<S, NWB, PREC_BF16, PFB, PK_HEAT, WPEB>(a, rounds, st);
+  if constexpr (ALL) {
+    if (prec == CROM_PREC_BF16_PURE) return launch_step<S, NWB, PREC_BF16_PURE, PFB, PK_HEAT, WPEB>(a, rounds, st);
+    return launch_step<S, NWF, PREC_BF16X3, 0>(a, rounds, st);
   }
+  return fail(CROM_ERR_UNSUPPORTED, "precision");
 }
 
 // The elastic step at width 256 (weight fragments streamed per K-block).
@@ -1465,8 +1474,13 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
   if (rounds > MAXP) rounds = MAXP;
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (shape_id(net->m, net->r, net->d, net->width)) {
-    case SHAPE_1D: return step_prec<Shape<32, 1, 3, 1>, 2, 2>(net->precision, a, (int)rounds, st);
+    case SHAPE_1D:
+      if (net->act == CROM_ACT_SINE) return step_prec<Shape<32, 1, 3, 1, ACT_SINE>, 2, 2>(net->precision, a, (int)rounds, st);
+      return step_prec<Shape<32, 1, 3, 1>, 2, 2>(net->precision, a, (int)rounds, st);
     case SHAPE_2D:
+      if (net->act == CROM_ACT_SINE)
+        return step_prec<Shape<128, 2, 8, 1, ACT_SINE>, CROM_STEP2D_NW, 4, CROM_STEP2D_PF, CROM_STEP2D_WPE>(
+            net->precision, a, (int)rounds, st);
       return step_prec<Shape<128, 2, 8, 1>, CROM_STEP2D_NW, 4, CROM_STEP2D_PF, CROM_STEP2D_WPE>(net->precision, a,
                                                                                          (int)rounds, st);
     case SHAPE_3D: return step_prec_elastic<Shape<256, 3, 16, 3>, CROM_ELASTIC_NW>(net->precision, a, (int)rounds, st);

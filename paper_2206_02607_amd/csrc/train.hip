@@ -737,6 +737,7 @@ size_t crom_encoder_param_count(int32_t n_in, int32_t hidden, int32_t r) {
 crom_status crom_train_workspace(const crom_net* net, const crom_encoder* enc, int32_t B, size_t* bytes) {
   crom_status s = check_net(net, false);
   if (s != CROM_OK) return s;
+  if (net->act != CROM_ACT_ELU) return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks");
   if ((s = check_enc(net, enc)) != CROM_OK) return s;
   if (B < 1 || !bytes) return fail(CROM_ERR_INVALID_ARG, "B >= 1 and bytes are required");
   *bytes = bf_mode(net) ? train_bytes_t<__bf16>(net, enc, B) : train_bytes_t<float>(net, enc, B);
@@ -748,6 +749,7 @@ crom_status crom_train_grads(const crom_net* net, const crom_encoder* enc, const
                              void* stream) {
   crom_status s = check_net(net, false);
   if (s != CROM_OK) return s;
+  if (net->act != CROM_ACT_ELU) return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks");
   if ((s = check_enc(net, enc)) != CROM_OK) return s;
   if (B < 1 || !u || !x || !grad_dec || !grad_enc || !loss || !ws)
     return fail(CROM_ERR_INVALID_ARG, "u, x, gradients, loss and ws are required");
@@ -791,6 +793,7 @@ crom_status crom_train_step(const crom_net* net, void* packed, float* dec_grad, 
 crom_status crom_encode_workspace(const crom_net* net, const crom_encoder* enc, int32_t B, size_t* bytes) {
   crom_status s = check_net(net, false);
   if (s != CROM_OK) return s;
+  if (net->act != CROM_ACT_ELU) return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks");
   if ((s = check_enc(net, enc)) != CROM_OK) return s;
   if (B < 1 || !bytes) return fail(CROM_ERR_INVALID_ARG, "B >= 1 and bytes are required");
   Carve cv{nullptr, 0};
@@ -829,6 +832,7 @@ crom_status crom_encode(const crom_net* net, const crom_encoder* enc, const floa
 crom_status crom_decode_vjp_workspace(const crom_net* net, int32_t B, int64_t P, size_t* bytes) {
   crom_status s = check_net(net, false);
   if (s != CROM_OK) return s;
+  if (net->act != CROM_ACT_ELU) return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks");
   if (B < 1 || P < 1 || !bytes) return fail(CROM_ERR_INVALID_ARG, "B >= 1, P >= 1 and bytes are required");
   *bytes = (bf_mode(net) ? DecoderPass<__bf16>::bytes(net, B, P) : DecoderPass<float>::bytes(net, B, P)) + 256;
   return CROM_OK;
@@ -839,6 +843,7 @@ crom_status crom_decode_vjp(const crom_net* net, const float* x, int64_t P, cons
                             void* stream) {
   crom_status s = check_net(net, false);
   if (s != CROM_OK) return s;
+  if (net->act != CROM_ACT_ELU) return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks");
   if (B < 1 || P < 1) return fail(CROM_ERR_INVALID_ARG, "B >= 1 and P >= 1");
   if (!x || !q || !dg || !grad_params || !grad_q || !ws)
     return fail(CROM_ERR_INVALID_ARG, "x, q, dg, grad_params, grad_q and ws are required");

@@ -30,5 +30,9 @@ template <>
 struct DecodeTune<Shape<128, 2, 8, 1>, PREC_BF16_PURE> {
   static constexpr int NW = 4, PF = 2, WPE = 2;
 };
+template <>
+struct DecodeTune<Shape<128, 2, 8, 1, ACT_SINE>, PREC_BF16> {
+  static constexpr int NW = 4, PF = 2, WPE = 2;
+};
 
 }  // namespace crom

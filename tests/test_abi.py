@@ -37,7 +37,7 @@ def test_param_count_formula():
 
 
 def _net(**kw):
-    base = dict(m=2, r=8, d=1, width=128, depth=5, precision=1, params=1 << 20, packed=1 << 21)
+    base = dict(m=2, r=8, d=1, width=128, depth=5, precision=1, act=0, _pad=0, params=1 << 20, packed=1 << 21)
     base.update(kw)
     return crom.CromNet(*[base[k] for k, _ in crom.CromNet._fields_])
 
@@ -56,6 +56,21 @@ def test_host_validation_before_launch():
     assert L.crom_decode_jac(ctypes.byref(_net()), 1, 10, 1, 0, 1, None, 1, None, None) == 1
     assert L.crom_decode_jac(ctypes.byref(_net()), 1, 10, 1, 1, 1, None, None, None, None) == 1
     assert L.crom_decode_jac_q(ctypes.byref(_net()), 1, 10, 1, 1, None, None) == 1
+
+
+def test_activation_validation():
+    L = crom.lib()
+    assert L.crom_decode(ctypes.byref(_net(act=2)), 1, 10, 1, 1, None) == 2
+    assert b"activation" in L.crom_last_error()
+    # sine: (1,3,1,32) and (2,8,1,128) in FP32 or BF16 only
+    assert L.crom_decode(ctypes.byref(_net(act=1, precision=2)), 1, 10, 1, 1, None) == 2
+    assert L.crom_decode(ctypes.byref(_net(act=1, m=3, r=16, d=3, width=256, depth=6)), 1, 10, 1, 1, None) == 2
+    assert L.crom_decode(ctypes.byref(_net(act=1)), 1, 0, 1, 1, None) == 0  # P = 0: accepted, nothing to do
+    n = ctypes.c_size_t(0)
+    enc = crom.CromEncoder(16384, 256, 8, 0, 1 << 22)
+    assert L.crom_train_workspace(ctypes.byref(_net(act=1)), ctypes.byref(enc), 16, ctypes.byref(n)) == 2
+    assert b"ELU" in L.crom_last_error()
+    assert L.crom_sampling_residual(ctypes.byref(_net(act=1)), 1 << 20, 10, 1, 1, 1, 1, 1, None, None) == 2
 
 
 def test_step_validation():
