@@ -13,9 +13,13 @@ error.  Readings (Sec. "Training Details" leaves them open):
 * Adam (Kingma & Ba) with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 and bias
   correction.
 
+* a SIREN decoder (sine hidden layers, omega_0 folded into the weights)
+  trains on the same loss; the encoder stays ELU.
+
 Gradients are taken by the reverse-mode chain rule written out layer by
-layer: with a_l = ELU(z_l), dL/dz_l = dL/da_l * ELU'(z_l), dL/dW_l = sum over
-points of dL/dz_l a_{l-1}^T, dL/db_l = sum dL/dz_l, dL/da_{l-1} = W_l^T dL/dz_l.
+layer: with a_l = s(z_l), dL/dz_l = dL/da_l * s'(z_l), dL/dW_l = sum over
+points of dL/dz_l a_{l-1}^T, dL/db_l = sum dL/dz_l, dL/da_{l-1} = W_l^T dL/dz_l
+(s = ELU or sin, s' = ELU' or cos).
 """
 from __future__ import annotations
 
@@ -23,26 +27,28 @@ from typing import List, Sequence, Tuple
 
 import numpy as np
 
-from .mlp import as_f64, elu, elu_d1
+from .mlp import ACTIVATIONS, as_f64
 
 Layer = Tuple[np.ndarray, np.ndarray]
 
 
-def mlp_forward(layers: Sequence[Layer], a0: np.ndarray):
-    """Hidden ELU layers and a linear output; returns (output, [(z_l, a_l)]) with
-    a_0 = the input (rows are samples)."""
+def mlp_forward(layers: Sequence[Layer], a0: np.ndarray, act: str = "elu"):
+    """Hidden layers (ELU or sine) and a linear output; returns (output,
+    [(z_l, a_l)]) with a_0 = the input (rows are samples)."""
+    s0 = ACTIVATIONS[act][0]
     acts = [(None, a0)]
     a = a0
     for W, b in layers[:-1]:
         z = a @ W.T + b
-        a = elu(z)
+        a = s0(z)
         acts.append((z, a))
     W, b = layers[-1]
     return a @ W.T + b, acts
 
 
-def mlp_backward(layers: Sequence[Layer], acts, d_out: np.ndarray):
+def mlp_backward(layers: Sequence[Layer], acts, d_out: np.ndarray, act: str = "elu"):
     """Reverse mode through mlp_forward: returns ([(dW_l, db_l)], d_input)."""
+    s1 = ACTIVATIONS[act][1]
     grads: List[Layer] = [None] * len(layers)
     W, b = layers[-1]
     a_prev = acts[-1][1]
@@ -50,7 +56,7 @@ def mlp_backward(layers: Sequence[Layer], acts, d_out: np.ndarray):
     d_a = d_out @ W
     for l in range(len(layers) - 2, -1, -1):
         z, _ = acts[l + 1]
-        d_z = d_a * elu_d1(z)
+        d_z = d_a * s1(z)
         a_prev = acts[l][1]
         grads[l] = (d_z.T @ a_prev, d_z.sum(axis=0))
         d_a = d_z @ layers[l][0]
@@ -63,7 +69,8 @@ def encode(enc: Sequence[Layer], u: np.ndarray) -> np.ndarray:
     return q
 
 
-def loss_and_grads(dec: Sequence[Layer], enc: Sequence[Layer], x: np.ndarray, u: np.ndarray):
+def loss_and_grads(dec: Sequence[Layer], enc: Sequence[Layer], x: np.ndarray, u: np.ndarray,
+                   dec_act: str = "elu"):
     """Reconstruction loss of eq. "loss" and its gradients.
 
     dec: decoder layers (input [x; q], m = x.shape[1]); enc: encoder layers
@@ -78,11 +85,11 @@ def loss_and_grads(dec: Sequence[Layer], enc: Sequence[Layer], x: np.ndarray, u:
     r = q.shape[1]
     # decoder at every (snapshot, point): rows ordered snapshot-major
     a0 = np.concatenate([np.tile(x, (B, 1)), np.repeat(q, P, axis=0)], axis=1)
-    g, dec_acts = mlp_forward(dec, a0)
+    g, dec_acts = mlp_forward(dec, a0, dec_act)
     resid = g - u.reshape(B * P, g.shape[1])
     loss = float(np.mean(resid ** 2))
     d_g = (2.0 / resid.size) * resid
-    dec_grads, d_a0 = mlp_backward(dec, dec_acts, d_g)
+    dec_grads, d_a0 = mlp_backward(dec, dec_acts, d_g, dec_act)
     m = x.shape[1]
     d_q = d_a0[:, m:].reshape(B, P, r).sum(axis=1)
     enc_grads, _ = mlp_backward(enc, enc_acts, d_q)

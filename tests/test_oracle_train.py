@@ -107,3 +107,59 @@ def test_training_reduces_loss():
         loss, dg, eg, _ = train.loss_and_grads(dec, enc, x, u)
         opt.step(train.flatten(dg) + train.flatten(eg))
     assert loss < 0.2 * l0
+
+
+def _siren_problem(seed=2, B=2, P=7, m=2, r=3, w=8, depth=3, enc_hidden=6):
+    from workloads import siren_mlp
+    g = rng(seed)
+    dec = [(W.astype(np.float64), b.astype(np.float64)) for W, b in siren_mlp(g, m, r, 1, w, depth)]
+    enc = [(W.astype(np.float64), b.astype(np.float64)) for W, b in xavier_mlp(g, P, 0, r, enc_hidden, 1, 0.3)]
+    x = g.uniform(-1, 1, size=(P, m))
+    u = g.uniform(-1, 1, size=(B, P))
+    return dec, enc, x, u
+
+
+def test_siren_gradients_vs_central_fd():
+    dec, enc, x, u = _siren_problem()
+    loss, dg, eg, _ = train.loss_and_grads(dec, enc, x, u, dec_act="sine")
+    g = rng(6)
+    h = 1e-6
+    for layers, grads in ((dec, dg), (enc, eg)):
+        for li in range(len(layers)):
+            for which in (0, 1):
+                arr = layers[li][which]
+                for _ in range(3):
+                    idx = tuple(g.integers(0, s) for s in arr.shape)
+                    old = arr[idx]
+                    arr[idx] = old + h
+                    lp = train.loss_and_grads(dec, enc, x, u, dec_act="sine")[0]
+                    arr[idx] = old - h
+                    lm = train.loss_and_grads(dec, enc, x, u, dec_act="sine")[0]
+                    arr[idx] = old
+                    fd = (lp - lm) / (2 * h)
+                    assert abs(grads[li][which][idx] - fd) <= 1e-6 * max(1.0, abs(fd)), (li, which, idx)
+
+
+def test_siren_gradients_vs_autograd_float64():
+    torch = pytest.importorskip("torch")
+    dec, enc, x, u = _siren_problem(seed=3)
+    loss, dg, eg, q = train.loss_and_grads(dec, enc, x, u, dec_act="sine")
+    T = lambda a: torch.tensor(a, dtype=torch.float64, requires_grad=True)  # noqa: E731
+    tdec = [(T(W), T(b)) for W, b in dec]
+    tenc = [(T(W), T(b)) for W, b in enc]
+
+    def mlp(layers, a, act):
+        for W, b in layers[:-1]:
+            a = act(a @ W.T + b)
+        return a @ layers[-1][0].T + layers[-1][1]
+
+    tu = torch.tensor(u)
+    tq = mlp(tenc, tu, torch.nn.functional.elu)
+    B, P = u.shape[0], x.shape[0]
+    a0 = torch.cat([torch.tensor(x).repeat(B, 1), tq.repeat_interleave(P, dim=0)], dim=1)
+    tl = ((mlp(tdec, a0, torch.sin) - tu.reshape(B * P, -1)) ** 2).mean()
+    tl.backward()
+    assert abs(tl.item() - loss) <= 1e-14 * max(1.0, loss)
+    for (W, b), (gW, gb) in zip(tdec + tenc, dg + eg):
+        np.testing.assert_allclose(W.grad.numpy(), gW, rtol=1e-10, atol=1e-13)
+        np.testing.assert_allclose(b.grad.numpy(), gb, rtol=1e-10, atol=1e-13)
