@@ -15,6 +15,7 @@ heat       heat-equation update at samples, FD full-order solvers, closed forms
 inversion  Cholesky, Gauss-Newton with backtracking, linearised inversion
 step       the three-stage latent step and rollouts
 elastic    neo-Hookean stress, its derivative and the explicit elastic update
+fem        corotated stress, tetrahedron forces on the samples' one-ring, FE update
 train      encoder/decoder reverse-mode gradients, MSE loss, Adam
 sampling   robust greedy selection of the integration samples
 

@@ -100,6 +100,39 @@ def grid_points_3d(nx: int, ny: int, nz: int, h: float) -> np.ndarray:
     return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1).astype(np.float32)
 
 
+def box_tet_mesh(nx: int, ny: int, nz: int, h: float, jitter: float = 0.0,
+                 gen: np.random.Generator = None) -> Tuple[np.ndarray, np.ndarray]:
+    """Tetrahedral mesh of a box of (nx x ny x nz) vertices with spacing h.
+
+    Vertices [nx*ny*nz, 3] float32 in the order of ``grid_points_3d``
+    (index (i*ny + j)*nz + k); each cube of 8 neighbouring vertices is split
+    into six tetrahedra that share its diagonal from corner (0,0,0) to
+    (1,1,1), one for each order in which the path between them steps along
+    the three axes; tets [6 (nx-1)(ny-1)(nz-1), 4] int32, listed cube by cube
+    with the four vertices in path order.  ``jitter > 0`` moves every vertex
+    not on the boundary by U(-jitter h, jitter h) per axis (drawn from
+    ``gen``), so the tetrahedra differ in shape and size."""
+    X = grid_points_3d(nx, ny, nz, h).astype(np.float64)
+    if jitter > 0:
+        idx = np.arange(nx * ny * nz)
+        i, j, k = idx // (ny * nz), (idx // nz) % ny, idx % nz
+        inner = (i > 0) & (i < nx - 1) & (j > 0) & (j < ny - 1) & (k > 0) & (k < nz - 1)
+        X[inner] += gen.uniform(-jitter * h, jitter * h, size=(int(inner.sum()), 3))
+    orders = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    ci, cj, ck = np.meshgrid(np.arange(nx - 1), np.arange(ny - 1), np.arange(nz - 1), indexing="ij")
+    base = np.stack([ci.ravel(), cj.ravel(), ck.ravel()], axis=1)
+    tets = []
+    for c in base:
+        for order in orders:
+            p = c.copy()
+            path = [p.copy()]
+            for ax in order:
+                p[ax] += 1
+                path.append(p.copy())
+            tets.append([(a * ny + b) * nz + e for a, b, e in path])
+    return X.astype(np.float32), np.asarray(tets, dtype=np.int32)
+
+
 # --------------------------------------------------------------------------
 # Workload recipes.  Each returns plain arrays; none evaluates the method.
 # --------------------------------------------------------------------------
@@ -211,6 +244,53 @@ class Elastic3D:
     @property
     def nodes(self) -> np.ndarray:
         return grid_points_3d(self.nx, self.ny, self.nz, self.h)
+
+
+@dataclass
+class Corotated3D:
+    """Falling bar with finite-element forces: the bar of 64 x 16 x 16
+    vertices (spacing h = 1/15) as a tetrahedral mesh (``box_tet_mesh``, six
+    tetrahedra per cube, interior vertices jittered by up to 0.15 h);
+    corotated elasticity with the paper's gravity-impact parameters
+    mu ~ U(6e4, 7e4) per instance and lam = 0, rho0 = 1000, gravity
+    (0, 0, -9.81), dt = 1e-3; decoder as the neo-Hookean bar's (Xavier-uniform,
+    output scaled by out_scale); n_samples sample vertices per instance drawn
+    without replacement, none clamped (the body falls freely)."""
+    seed: int = 0
+    nx: int = 64
+    ny: int = 16
+    nz: int = 16
+    jitter: float = 0.15
+    n_samples: int = 500
+    n_inst: int = 1
+    m: int = 3
+    r: int = 16
+    d: int = 3
+    width: int = 256
+    depth: int = 6
+    lam: float = 0.0
+    mu_range: Tuple[float, float] = (6e4, 7e4)
+    rho0: float = 1000.0
+    gravity: Tuple[float, float, float] = (0.0, 0.0, -9.81)
+    dt: float = 1e-3
+    out_scale: float = 1e-2
+    layers: List[Layer] = field(init=False)
+    X: np.ndarray = field(init=False)
+    tets: np.ndarray = field(init=False)
+    samples: List[np.ndarray] = field(init=False)
+    mu: np.ndarray = field(init=False)
+    q0: np.ndarray = field(init=False)
+
+    def __post_init__(self):
+        g = rng(self.seed)
+        self.layers = xavier_mlp(g, self.m, self.r, self.d, self.width, self.depth)
+        W, b = self.layers[-1]
+        self.layers[-1] = ((W * self.out_scale).astype(np.float32), (b * self.out_scale).astype(np.float32))
+        self.X, self.tets = box_tet_mesh(self.nx, self.ny, self.nz, 1.0 / 15.0, self.jitter, g)
+        n = self.X.shape[0]
+        self.samples = [np.sort(g.choice(n, size=self.n_samples, replace=False)) for _ in range(self.n_inst)]
+        self.mu = g.uniform(*self.mu_range, size=self.n_inst)
+        self.q0 = g.uniform(-0.1, 0.1, size=(self.n_inst, self.r))
 
 
 @dataclass
