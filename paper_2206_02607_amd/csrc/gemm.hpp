@@ -203,16 +203,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 // loop over row tiles with the next tile's operands loaded ahead; few
 // registers, so many waves per CU keep memory busy.  Same operands, K order
 // and epilogue arithmetic as gemm_kernel.
+// Sine (SIREN) networks: the forward writes a = sin(z) and the derivative
+// cos(z) (G), and the backward's gate is that stored derivative.
 struct RowGemmArgs {
   const __bf16* X;     // [rows][W]
   const __bf16* Wt;    // [W][W] bfloat16 copy of the layer weight (out, in)
   const float* bias;   // forward
-  const __bf16* gate;  // backward: stored a = ELU(z) of the layer below
+  const __bf16* gate;  // backward: stored a = ELU(z) (ELU) or cos(z) (sine) of the layer below
   __bf16* C;           // [rows][W]
   int64_t rows;
+  __bf16* G;           // forward, sine: cos(z) [rows][W]
 };
 
-template <int W, bool FWD>
+template <int W, bool FWD, bool SINE = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void rowgemm_kernel(RowGemmArgs g) {
   typedef __bf16 bf16x8_ __attribute__((ext_vector_type(8)));
   typedef __bf16 bf16x4_ __attribute__((ext_vector_type(4)));
@@ -280,19 +283,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
 #pragma unroll
       for (int i = 0; i < MT; ++i) {
         const int m0 = 16 * i + 4 * lg;  // this lane's 4 consecutive units
-        bf16x4_ o;
+        bf16x4_ o, oc;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           float x = acc[i][v];
-          if constexpr (FWD) {
+          if constexpr (FWD && SINE) {
+            const float rz = reduce_2pi(x + sb[m0 + v]);
+            x = __sinf(rz);
+            oc[v] = (__bf16)__cosf(rz);
+          } else if constexpr (FWD) {
             x += sb[m0 + v];
             x = x > 0.0f ? x : __expf(x) - 1.0f;
+          } else if constexpr (SINE) {
+            x *= (float)gv[i][v];
           } else {
             x *= elu_d1_from_a((float)gv[i][v]);
           }
           o[v] = (__bf16)x;
         }
         *reinterpret_cast<bf16x4_*>(&g.C[row * W + m0]) = o;
+        if constexpr (FWD && SINE) *reinterpret_cast<bf16x4_*>(&g.G[row * W + m0]) = oc;
       }
     }
   }

@@ -45,10 +45,11 @@ __global__ void fold_kernel(const float* __restrict__ W1, const float* __restric
 constexpr int EW_MAX_W = 256;  // widest layer of the compiled shapes
 constexpr int EW_MAX_MD = 3;   // largest m and d
 
-template <class T, int M>
+// Sine networks (SINE): a1 = sin(z), and g1 = cos(z) for the backward.
+template <class T, int M, bool SINE = false>
 __global__ __launch_bounds__(256) void layer1_kernel(const float* __restrict__ W1, const float* __restrict__ c,
                                                      const float* __restrict__ x, int64_t P, int64_t rows, int W,
-                                                     int r, T* __restrict__ a1) {
+                                                     int r, T* __restrict__ a1, T* __restrict__ g1) {
   typedef T vec8 __attribute__((ext_vector_type(8)));
   __shared__ float wx[EW_MAX_W * M];
   for (int i = threadIdx.x; i < W * M; i += blockDim.x) wx[i] = W1[(i / M) * (M + r) + i % M];
@@ -64,15 +65,22 @@ __global__ __launch_bounds__(256) void layer1_kernel(const float* __restrict__ W
     const float4 c0 = *reinterpret_cast<const float4*>(&c[b * W + u0]);
     const float4 c1 = *reinterpret_cast<const float4*>(&c[b * W + u0 + 4]);
     const float cz[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-    vec8 o;
+    vec8 o, oc;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       float z = cz[e];
 #pragma unroll
       for (int k = 0; k < M; ++k) z += wx[(u0 + e) * M + k] * xv[k];
-      o[e] = (T)(z > 0.0f ? z : __expf(z) - 1.0f);
+      if constexpr (SINE) {
+        const float rz = reduce_2pi(z);
+        o[e] = (T)__sinf(rz);
+        oc[e] = (T)__cosf(rz);
+      } else {
+        o[e] = (T)(z > 0.0f ? z : __expf(z) - 1.0f);
+      }
     }
     *reinterpret_cast<vec8*>(&a1[row * W + u0]) = o;
+    if constexpr (SINE) *reinterpret_cast<vec8*>(&g1[row * W + u0]) = oc;
   }
 }
 
@@ -140,7 +148,8 @@ __global__ __launch_bounds__(256) void mse_final_kernel(const double* __restrict
 
 // dz[row][u] = (sum_o dg[row][o] Wout[o][u]) * ELU'(a[row][u]); 8 units
 // of one row per thread, Wout staged in LDS.
-template <class T, int D>
+// Sine networks (SINE): `a` holds the stored cos(z) and scales dz directly.
+template <class T, int D, bool SINE = false>
 __global__ __launch_bounds__(256) void dz_last_kernel(const float* __restrict__ dg, const float* __restrict__ Wout,
                                                       const T* __restrict__ a, int64_t rows, int W,
                                                       T* __restrict__ dz) {
@@ -162,7 +171,7 @@ __global__ __launch_bounds__(256) void dz_last_kernel(const float* __restrict__ 
       float s = 0.0f;
 #pragma unroll
       for (int o = 0; o < D; ++o) s += d[o] * wo[o * W + u0 + e];
-      out[e] = (T)(s * elu_d1_from_a((float)av[e]));
+      out[e] = (T)(SINE ? s * (float)av[e] : s * elu_d1_from_a((float)av[e]));
     }
     *reinterpret_cast<vec8*>(&dz[row * W + u0]) = out;
   }
@@ -335,14 +344,16 @@ static unsigned grid_for(int64_t n, int threads = 256) {
 // a wave's registers go through rowgemm_kernel; returns false otherwise.
 template <bool FWD>
 static bool row_gemm(int W, const void* X, const void* Wt, const float* bias, const void* gate, void* C,
-                     int64_t rows, hipStream_t st, crom_status* s) {
+                     int64_t rows, hipStream_t st, crom_status* s, bool sine = false, void* G = nullptr) {
   RowGemmArgs g{static_cast<const __bf16*>(X), static_cast<const __bf16*>(Wt), bias,
-                static_cast<const __bf16*>(gate), static_cast<__bf16*>(C), rows};
+                static_cast<const __bf16*>(gate), static_cast<__bf16*>(C), rows, static_cast<__bf16*>(G)};
   const int64_t tiles = (rows + 15) / 16;
   int64_t blocks = (tiles + 3) / 4;
   if (blocks > 1024) blocks = 1024;  // four workgroups of four waves per CU, looping over row tiles
   if (blocks < 1) blocks = 1;
-  if (W == 128) hipLaunchKernelGGL((rowgemm_kernel<128, FWD>), dim3((unsigned)blocks), dim3(256), 0, st, g);
+  if (W == 128 && sine) hipLaunchKernelGGL((rowgemm_kernel<128, FWD, true>), dim3((unsigned)blocks), dim3(256), 0, st, g);
+  else if (W == 32 && sine) hipLaunchKernelGGL((rowgemm_kernel<32, FWD, true>), dim3((unsigned)blocks), dim3(256), 0, st, g);
+  else if (W == 128) hipLaunchKernelGGL((rowgemm_kernel<128, FWD>), dim3((unsigned)blocks), dim3(256), 0, st, g);
   else if (W == 32) hipLaunchKernelGGL((rowgemm_kernel<32, FWD>), dim3((unsigned)blocks), dim3(256), 0, st, g);
   else return false;
   *s = hip_check(hipGetLastError(), "row gemm launch");
@@ -433,6 +444,7 @@ constexpr int MSE_BLOCKS = 1024;
 template <class T>
 struct DecoderPass {
   T *a[16], *dz0, *dz1, *wt[16];
+  T* gt[16];  // sine networks: cos(z_l) of each hidden layer
   float *c, *g, *dg, *part;
   double *cpart, *csum, *mpart;
   static size_t bytes(const crom_net* n, int B, int64_t P) {
@@ -445,6 +457,7 @@ struct DecoderPass {
     const int64_t rows = (int64_t)B * P;
     const int W = n->width, depth = n->depth, D = n->d;
     for (int l = 0; l < depth; ++l) a[l] = cv.take<T>((size_t)rows * W);
+    for (int l = 0; l < depth; ++l) gt[l] = n->act == CROM_ACT_SINE ? cv.take<T>((size_t)rows * W) : nullptr;
     dz0 = cv.take<T>((size_t)rows * W);
     dz1 = cv.take<T>((size_t)rows * W);
     for (int l = 1; l < depth; ++l) wt[l] = cv.take<T>((size_t)W * W);
@@ -468,6 +481,7 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
   const int64_t rows = (int64_t)B * P;
   const ParamIndex pi = param_index(m, r, D, W, depth);
   const float* prm = n->params;
+  const bool sine = n->act == CROM_ACT_SINE;  // bfloat16 row kernels only (checked at entry)
   crom_status s = CROM_OK;
   // weights in the GEMM precision
   for (int l = 1; l < depth; ++l)
@@ -479,13 +493,20 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
   if (W > EW_MAX_W || W % 8 != 0 || m > EW_MAX_MD || D > EW_MAX_MD) return fail(CROM_ERR_UNSUPPORTED, "training shape");
   {
     const dim3 grid(grid_for(rows * W / 8));
-    if (m == 1) hipLaunchKernelGGL((layer1_kernel<T, 1>), grid, dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows, W, r, ws.a[0]);
-    else if (m == 2) hipLaunchKernelGGL((layer1_kernel<T, 2>), grid, dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows, W, r, ws.a[0]);
-    else hipLaunchKernelGGL((layer1_kernel<T, 3>), grid, dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows, W, r, ws.a[0]);
+    T* g1 = ws.gt[0];
+    if (sine) {
+      if (m == 1) hipLaunchKernelGGL((layer1_kernel<T, 1, true>), grid, dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows, W, r, ws.a[0], g1);
+      else if (m == 2) hipLaunchKernelGGL((layer1_kernel<T, 2, true>), grid, dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows, W, r, ws.a[0], g1);
+      else hipLaunchKernelGGL((layer1_kernel<T, 3, true>), grid, dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows, W, r, ws.a[0], g1);
+    } else {
+      if (m == 1) hipLaunchKernelGGL((layer1_kernel<T, 1>), grid, dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows, W, r, ws.a[0], g1);
+      else if (m == 2) hipLaunchKernelGGL((layer1_kernel<T, 2>), grid, dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows, W, r, ws.a[0], g1);
+      else hipLaunchKernelGGL((layer1_kernel<T, 3>), grid, dim3(256), 0, st, prm + pi.w[0], ws.c, x, P, rows, W, r, ws.a[0], g1);
+    }
   }
   for (int l = 1; l < depth; ++l) {
     if constexpr (sizeof(T) == 2) {
-      if (row_gemm<true>(W, ws.a[l - 1], ws.wt[l], prm + pi.b[l], nullptr, ws.a[l], rows, st, &s)) {
+      if (row_gemm<true>(W, ws.a[l - 1], ws.wt[l], prm + pi.b[l], nullptr, ws.a[l], rows, st, &s, sine, ws.gt[l])) {
         if (s != CROM_OK) return s;
         continue;
       }
@@ -523,7 +544,13 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
                        (int64_t)D * W);
     colsum<float>(dg, D, D, 1, rows, nullptr, 1, 0, 1, ws.cpart, COLSUM_CHUNKS, ws.csum, st);
     hipLaunchKernelGGL(d2f_kernel, dim3(1), dim3(64), 0, st, ws.csum, grad + pi.b[depth], (int64_t)D);
-    if (D == 1)
+    if (sine && D == 1)
+      hipLaunchKernelGGL((dz_last_kernel<T, 1, true>), dim3(grid_for(rows * W / 8)), dim3(256), 0, st, dg,
+                         prm + pi.w[depth], ws.gt[depth - 1], rows, W, ws.dz0);
+    else if (sine)
+      hipLaunchKernelGGL((dz_last_kernel<T, 3, true>), dim3(grid_for(rows * W / 8)), dim3(256), 0, st, dg,
+                         prm + pi.w[depth], ws.gt[depth - 1], rows, W, ws.dz0);
+    else if (D == 1)
       hipLaunchKernelGGL((dz_last_kernel<T, 1>), dim3(grid_for(rows * W / 8)), dim3(256), 0, st, dg,
                          prm + pi.w[depth], ws.a[depth - 1], rows, W, ws.dz0);
     else
@@ -553,7 +580,7 @@ static crom_status decoder_fwd_bwd(const crom_net* n, const float* x, int B, int
     // dz_{l-1} = (dz W_l) * ELU'(a_{l-1})
     bool done = false;
     if constexpr (sizeof(T) == 2) {
-      done = row_gemm<false>(W, dz, ws.wt[l], nullptr, ws.a[l - 1], dzn, rows, st, &s);
+      done = row_gemm<false>(W, dz, ws.wt[l], nullptr, sine ? ws.gt[l - 1] : ws.a[l - 1], dzn, rows, st, &s, sine);
       if (s != CROM_OK) return s;
     }
     if (done) {
@@ -737,7 +764,9 @@ size_t crom_encoder_param_count(int32_t n_in, int32_t hidden, int32_t r) {
 crom_status crom_train_workspace(const crom_net* net, const crom_encoder* enc, int32_t B, size_t* bytes) {
   crom_status s = check_net(net, false);
   if (s != CROM_OK) return s;
-  if (net->act != CROM_ACT_ELU) return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks");
+  if (net->act != CROM_ACT_ELU &&
+      (net->act != CROM_ACT_SINE || net->precision == CROM_PREC_FP32 || (net->width != 32 && net->width != 128)))
+    return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks, or sine networks of width 32 or 128 in bfloat16");
   if ((s = check_enc(net, enc)) != CROM_OK) return s;
   if (B < 1 || !bytes) return fail(CROM_ERR_INVALID_ARG, "B >= 1 and bytes are required");
   *bytes = bf_mode(net) ? train_bytes_t<__bf16>(net, enc, B) : train_bytes_t<float>(net, enc, B);
@@ -749,7 +778,9 @@ crom_status crom_train_grads(const crom_net* net, const crom_encoder* enc, const
                              void* stream) {
   crom_status s = check_net(net, false);
   if (s != CROM_OK) return s;
-  if (net->act != CROM_ACT_ELU) return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks");
+  if (net->act != CROM_ACT_ELU &&
+      (net->act != CROM_ACT_SINE || net->precision == CROM_PREC_FP32 || (net->width != 32 && net->width != 128)))
+    return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks, or sine networks of width 32 or 128 in bfloat16");
   if ((s = check_enc(net, enc)) != CROM_OK) return s;
   if (B < 1 || !u || !x || !grad_dec || !grad_enc || !loss || !ws)
     return fail(CROM_ERR_INVALID_ARG, "u, x, gradients, loss and ws are required");
@@ -793,7 +824,9 @@ crom_status crom_train_step(const crom_net* net, void* packed, float* dec_grad, 
 crom_status crom_encode_workspace(const crom_net* net, const crom_encoder* enc, int32_t B, size_t* bytes) {
   crom_status s = check_net(net, false);
   if (s != CROM_OK) return s;
-  if (net->act != CROM_ACT_ELU) return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks");
+  if (net->act != CROM_ACT_ELU &&
+      (net->act != CROM_ACT_SINE || net->precision == CROM_PREC_FP32 || (net->width != 32 && net->width != 128)))
+    return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks, or sine networks of width 32 or 128 in bfloat16");
   if ((s = check_enc(net, enc)) != CROM_OK) return s;
   if (B < 1 || !bytes) return fail(CROM_ERR_INVALID_ARG, "B >= 1 and bytes are required");
   Carve cv{nullptr, 0};
@@ -832,7 +865,9 @@ crom_status crom_encode(const crom_net* net, const crom_encoder* enc, const floa
 crom_status crom_decode_vjp_workspace(const crom_net* net, int32_t B, int64_t P, size_t* bytes) {
   crom_status s = check_net(net, false);
   if (s != CROM_OK) return s;
-  if (net->act != CROM_ACT_ELU) return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks");
+  if (net->act != CROM_ACT_ELU &&
+      (net->act != CROM_ACT_SINE || net->precision == CROM_PREC_FP32 || (net->width != 32 && net->width != 128)))
+    return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks, or sine networks of width 32 or 128 in bfloat16");
   if (B < 1 || P < 1 || !bytes) return fail(CROM_ERR_INVALID_ARG, "B >= 1, P >= 1 and bytes are required");
   *bytes = (bf_mode(net) ? DecoderPass<__bf16>::bytes(net, B, P) : DecoderPass<float>::bytes(net, B, P)) + 256;
   return CROM_OK;
@@ -843,7 +878,9 @@ crom_status crom_decode_vjp(const crom_net* net, const float* x, int64_t P, cons
                             void* stream) {
   crom_status s = check_net(net, false);
   if (s != CROM_OK) return s;
-  if (net->act != CROM_ACT_ELU) return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks");
+  if (net->act != CROM_ACT_ELU &&
+      (net->act != CROM_ACT_SINE || net->precision == CROM_PREC_FP32 || (net->width != 32 && net->width != 128)))
+    return fail(CROM_ERR_UNSUPPORTED, "training kernels: ELU networks, or sine networks of width 32 or 128 in bfloat16");
   if (B < 1 || P < 1) return fail(CROM_ERR_INVALID_ARG, "B >= 1 and P >= 1");
   if (!x || !q || !dg || !grad_params || !grad_q || !ws)
     return fail(CROM_ERR_INVALID_ARG, "x, q, dg, grad_params, grad_q and ws are required");

@@ -68,8 +68,9 @@ def test_activation_validation():
     assert L.crom_decode(ctypes.byref(_net(act=1)), 1, 0, 1, 1, None) == 0  # P = 0: accepted, nothing to do
     n = ctypes.c_size_t(0)
     enc = crom.CromEncoder(16384, 256, 8, 0, 1 << 22)
-    assert L.crom_train_workspace(ctypes.byref(_net(act=1)), ctypes.byref(enc), 16, ctypes.byref(n)) == 2
+    assert L.crom_train_workspace(ctypes.byref(_net(act=1, precision=0)), ctypes.byref(enc), 16, ctypes.byref(n)) == 2
     assert b"ELU" in L.crom_last_error()
+    assert L.crom_train_workspace(ctypes.byref(_net(act=1)), ctypes.byref(enc), 16, ctypes.byref(n)) == 0
     assert L.crom_sampling_residual(ctypes.byref(_net(act=1)), 1 << 20, 10, 1, 1, 1, 1, 1, None, None) == 2
 
 

@@ -272,3 +272,77 @@ def test_training_reduces_loss(cuda):
     losses = [T.step(ut, lr=1e-3).item() for _ in range(300)]
     print("loss", losses[0], losses[-1])
     assert np.mean(losses[-20:]) < 0.2 * np.mean(losses[:20])
+
+
+@pytest.mark.parametrize("shape", ["1d", "2d"])
+def test_train_grads_siren(cuda, shape):
+    """SIREN decoder (sine hidden layers; the bfloat16 row kernels store cos z
+    beside sin z for the backward) with an ELU encoder, at the bfloat16-held
+    weights.
+
+    Two checks.  (1) The decoder's gradients against the oracle's reverse
+    mode taken at the GPU's own latents q, to the bfloat16 tolerance 2e-2.
+    (2) Loss, latents and every gradient against the oracle end to end, to
+    5e-2: the latents carry the encoder's bfloat16 error (about 1.5e-3
+    normwise), and the first sine layer multiplies it by weights of size up
+    to omega_0 / (m + r), shifting its pre-activations by about 1e-2 rad; the
+    sums over rows that form the first-layer gradients cancel by a factor of
+    about 14 (sum of magnitudes over magnitude of the sum, measured on these
+    inputs).  A model of the kernels' bfloat16 roundings in float64 gives
+    3.6e-2 on the first bias gradient of the 1D decoder and 1.6e-2 in 2D."""
+    import torch
+    from paper_2206_02607_amd import crom
+    from workloads import siren_mlp
+    B, P = 3, 300
+    m, r, d, w, depth = SHAPES[shape]
+    g = rng(13)
+    dec = siren_mlp(g, m, r, d, w, depth)
+    enc = xavier_mlp(g, P * d, 0, r, 40, 1, bias_scale=0.2)
+    x = g.uniform(-1, 1, size=(P, m))
+    u = g.uniform(-1, 1, size=(B, P * d)).astype(np.float32)
+    D = crom.Decoder.from_layers(dec, m, precision="bf16", device=cuda, act="sine")
+    T = crom.Trainer(D, _flat(enc), 40, torch.from_numpy(x).to(cuda), B)
+    loss, gd, ge, q = T.grads(torch.from_numpy(u).to(cuda))
+    torch.cuda.synchronize()
+    rl, rgd, rge, rq = train.loss_and_grads(*_as_held(dec, enc, "bf16"), x, u, dec_act="sine")
+    errs = {"loss": abs(loss.item() - rl) / rl, "q": normwise_rel(q.cpu().numpy(), rq)}
+    for name, got, ref, layers in (("dec", gd, rgd, dec), ("enc", ge, rge, enc)):
+        for li, ((gW, gb), (rW, rb)) in enumerate(zip(_split(got.cpu().numpy(), layers), ref)):
+            errs[f"{name}W{li}"] = normwise_rel(gW, rW)
+            errs[f"{name}b{li}"] = normwise_rel(gb, rb)
+    print("siren", shape, {k: f"{v:.1e}" for k, v in errs.items()})
+    bad = {k: v for k, v in errs.items() if not v <= 5e-2}
+    assert not bad, bad
+    # (1) the decoder alone, at the latents the GPU formed
+    held_dec = _as_held(dec, enc, "bf16")[0]
+    qg = q.cpu().numpy().astype(np.float64)
+    a0 = np.concatenate([np.tile(x, (B, 1)), np.repeat(qg, P, axis=0)], axis=1)
+    out, acts = train.mlp_forward(held_dec, a0, "sine")
+    resid = out - u.reshape(B * P, d).astype(np.float64)
+    qgrads, _ = train.mlp_backward(held_dec, acts, (2.0 / resid.size) * resid, "sine")
+    derr = {}
+    for li, ((gW, gb), (rW, rb)) in enumerate(zip(_split(gd.cpu().numpy(), dec), qgrads)):
+        derr[f"W{li}"] = normwise_rel(gW, rW)
+        derr[f"b{li}"] = normwise_rel(gb, rb)
+    print("siren decoder at the GPU latents", {k: f"{v:.1e}" for k, v in derr.items()})
+    bad = {k: v for k, v in derr.items() if not v <= TOL["bf16"]}
+    assert not bad, bad
+
+
+def test_siren_training_reduces_loss(cuda):
+    import torch
+    from paper_2206_02607_amd import crom
+    from workloads import siren_mlp
+    B, P = 4, 256
+    m, r, d, w, depth = SHAPES["2d"]
+    g = rng(14)
+    dec = siren_mlp(g, m, r, d, w, depth)
+    enc = xavier_mlp(g, P, 0, r, 40, 1, bias_scale=0.2)
+    x = g.uniform(-1, 1, size=(P, m))
+    u = (np.sin(3 * x[:, 0])[None] * g.uniform(0.5, 1, size=(B, 1))).astype(np.float32)
+    D = crom.Decoder.from_layers(dec, m, precision="bf16", device=cuda, act="sine")
+    T = crom.Trainer(D, _flat(enc), 40, torch.from_numpy(x).to(cuda), B)
+    ut = torch.from_numpy(u).to(cuda)
+    losses = [T.step(ut, 1e-4)[0].item() for _ in range(200)]
+    print("siren loss", losses[0], losses[-1])
+    assert losses[-1] < 0.1 * losses[0]
