@@ -323,7 +323,8 @@ def siren_leg(args, crom, torch, dev):
     weights) of the 2D shape, inputs in [-1, 1]^2: full-field value decode of
     the 256 x 256 grid, the 12-column decode at the same nodes, and the
     single-instance Gauss-Newton heat step at 2,000 samples, in BF16 and
-    FP32 (the ELU numbers of the same shapes are the main line's)."""
+    FP32, and (BF16) one training step of the 2D training workload with the
+    SIREN decoder (the ELU numbers of the same shapes are the main line's)."""
     from workloads import Heat2D, rng, siren_mlp
     wl = Heat2D(seed=args.seed)
     layers = siren_mlp(rng(args.seed + 11), wl.m, wl.r, wl.d, wl.width, wl.depth)
@@ -369,9 +370,28 @@ def siren_leg(args, crom, torch, dev):
         crom.kernel_timer(False)
         k_ms, k_n = crom.kernel_timer_read()
         inf = st.info()[0]
+        gn_ms = e[0].elapsed_time(e[1]) / n_steps
+        train_ms = None
+        if prec != "fp32":  # the sine training path runs on the bfloat16 row kernels
+            from workloads import Train2D
+            w2 = Train2D(seed=args.seed)
+            xs = torch.from_numpy((2.0 * w2.nodes - 1.0).astype(np.float32)).to(dev)
+            enc0 = np.concatenate([np.concatenate([Wm.ravel(), b.ravel()]) for Wm, b in w2.enc_layers]).astype(np.float32)
+            tdec = crom.Decoder.from_layers(layers, wl.m, precision=prec, device=dev, act="sine")
+            T = crom.Trainer(tdec, enc0, w2.enc_hidden, xs, w2.batch)
+            ub = torch.randn(w2.batch, xs.shape[0], device=dev) * 0.5
+            for _ in range(3):
+                T.step(ub, 1e-4)
+            e[0].record()
+            for _ in range(20):
+                T.step(ub, 1e-4)
+            e[1].record()
+            torch.cuda.synchronize()
+            train_ms = e[0].elapsed_time(e[1]) / 20
         out[prec] = {"value_decode_ms": t_val * 1e3, "value_decode_tflops": P * FLOP_VALUE_COL / t_val / 1e12,
+                     "train_step_ms": train_ms,
                      "jac_decode_ms": t_jac * 1e3, "jac_decode_tflops": P * FLOP_POINT_EVAL / t_jac / 1e12,
-                     "gn_step_ms": e[0].elapsed_time(e[1]) / n_steps, "gn_step_kernel_ms": k_ms / max(1, k_n),
+                     "gn_step_ms": gn_ms, "gn_step_kernel_ms": k_ms / max(1, k_n),
                      "gn_iters_last": int(inf["iters"]), "ls_evals_last": int(inf["ls_evals"]),
                      "flags_last": int(inf["flags"])}
     return out
@@ -488,6 +508,50 @@ def config3_leg(args, crom, torch, dev):
     return out
 
 
+def fe_leg(args, crom, torch, dev):
+    """Corotated elasticity with finite-element forces: the falling bar of
+    64 x 16 x 16 vertices as 85,050 jittered linear tetrahedra, 500 sample
+    vertices and their one-ring, decoder (3 + 16) -> 6 x ELU 256 -> 3,
+    mu ~ U(6e4, 7e4), lam = 0, rho0 1000, gravity, dt 1e-3: one instance's
+    latent step from a fixed state (Gauss-Newton with 5 iterations, and
+    linearised), repeated; the library's kernel timer gives the span from
+    the set-up launch to the end of the inversion (ring decode, sample
+    Jacobian, FE forces, inversion)."""
+    from workloads import Corotated3D
+    w = Corotated3D(seed=args.seed)
+    sm = crom.FEStencil(w.X, w.tets, w.samples, dev)
+    coef = torch.tensor([[w.lam, w.mu[0], w.rho0, *w.gravity]], dtype=torch.float64, device=dev)
+    out = {"workload": f"corotated FE bar 64x16x16 ({w.tets.shape[0]} tetrahedra), {w.n_samples} samples, "
+                       f"one-ring {sm.n_ring} vertices, {sm.n_inc} sample-tetrahedron pairs, dt {w.dt}"}
+    for prec in (args.prec, "fp32") if args.prec != "fp32" else ("fp32",):
+        dec = crom.Decoder.from_layers(w.layers, w.m, precision=prec, device=dev)
+        st = crom.Stepper(dec, sm.offsets, sm.y, pde="corotated_fe", mesh=sm)
+        res = {}
+        for name, opts in (("gn", crom.GNOptions(max_iter=5, tol_step=TOL_STEP)),
+                           ("lls", crom.GNOptions(max_iter=1, linearized=True))):
+            q = torch.from_numpy(w.q0.copy()).to(dev)
+            q_prev = q - 1e-3
+            q_next = torch.empty_like(q)
+            for _ in range(3):
+                st.step(q, coef, w.dt, opts, q_next=q_next, q_prev=q_prev)
+            torch.cuda.synchronize()
+            crom.kernel_timer(True)
+            t0 = time.perf_counter()
+            for _ in range(args.fe_steps):
+                st.step(q, coef, w.dt, opts, q_next=q_next, q_prev=q_prev)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / args.fe_steps
+            crom.kernel_timer(False)
+            k_ms, k_n = crom.kernel_timer_read()
+            inf = st.info()[0]
+            res[name] = {"ms_per_step": t * 1e3, "latent_steps_per_s": 1.0 / t,
+                         "kernels_ms_per_step": k_ms / max(1, k_n),
+                         "gn_iters_last": int(inf["iters"]), "ls_evals_last": int(inf["ls_evals"]),
+                         "flags_last": int(inf["flags"])}
+        out[prec] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -505,6 +569,7 @@ def main():
     ap.add_argument("--c1-cpu", type=int, default=1, help="time the oracle's 1D rollout too")
     ap.add_argument("--c3-steps", type=int, default=20, help="3D elastic steps timed (0: skip)")
     ap.add_argument("--c3-cpu", type=int, default=0, help="time one oracle elastic step too (about 30 s)")
+    ap.add_argument("--fe-steps", type=int, default=20, help="corotated FE steps timed (0: skip)")
     ap.add_argument("--siren", type=int, default=1, help="time the sine-activated decoder and step (0: skip)")
     ap.add_argument("--sampling-rounds", type=int, default=32,
                     help="greedy sample-selection rounds with the trained network (0: skip)")
@@ -613,6 +678,7 @@ def main():
     batched = batched_leg(args, crom, torch, dev, trained) if args.batched_steps > 0 else None
     sampling = sampling_leg(args, crom, torch, dev, trained) if trained and args.sampling_rounds > 0 else None
     siren = siren_leg(args, crom, torch, dev) if args.siren else None
+    fe = fe_leg(args, crom, torch, dev) if args.fe_steps > 0 else None
     cpu = cpu_baseline(wl, nodes, args.cpu_steps) if args.cpu_steps > 0 else None
     its = np.array([int(i["iters"]) for i in infos])
     lse = np.array([int(i["ls_evals"]) for i in infos])
@@ -639,6 +705,7 @@ def main():
         "batched": batched,
         "sampling": sampling,
         "siren": siren,
+        "corotated_fe": fe,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -95,7 +95,9 @@ enum {
  *                  sin(W' a + b') with W' = omega_0 W, b' = omega_0 b).
  *                  Supported by the decode calls and the heat step for
  *                  the (1, 3, 1, 32) and (2, 8, 1, 128) shapes in FP32 and
- *                  BF16; other calls return CROM_ERR_UNSUPPORTED.
+ *                  BF16, and by the training calls in the bfloat16 modes
+ *                  (the forward stores cos(z) beside sin(z) for the
+ *                  backward); other calls return CROM_ERR_UNSUPPORTED.
  * packed: the fragment-ordered copy of the hidden-to-hidden weights that
  *   crom_net_pack writes (crom_net_packed_bytes long).  It must be
  *   refreshed after params change. */
@@ -146,7 +148,61 @@ crom_status crom_decode_jac_q(const crom_net* net, const float* x, int64_t P, co
  * Latent step for a batch of independent instances.
  * ------------------------------------------------------------------------- */
 
-enum { CROM_PDE_HEAT = 0, CROM_PDE_NEOHOOKEAN = 1 };
+enum { CROM_PDE_HEAT = 0, CROM_PDE_NEOHOOKEAN = 1, CROM_PDE_COROTATED_FE = 2 };
+
+/* Finite-element stencil of the samples for CROM_PDE_COROTATED_FE (appendix,
+ * Sec. "Solid Mechanics / Reduced-order Model": the forces on a sample come
+ * from the linear tetrahedra incident on it, so the decoder is evaluated at
+ * their vertices, the samples' one-ring).  All arrays are device memory
+ * owned by the caller; the host struct is read during the call only.
+ *   n_ring        ring vertices of all instances together
+ *   max_ring      the largest instance's ring size (sizes the ring decode's
+ *                 grid; a larger ring makes its instance NONFINITE)
+ *   ring_offsets  [n_inst+1] int64 CSR: instance i's ring vertices are
+ *                 ring_offsets[i] .. ring_offsets[i+1]-1 (the samples'
+ *                 own vertices included)
+ *   ring_X        [n_ring][3] FP32 rest positions (the decoder's inputs)
+ *   n_inc         (sample, incident tetrahedron) pairs of all samples
+ *   inc_offsets   [total_samples+1] int64 CSR: sample p's pairs are
+ *                 inc_offsets[p] .. inc_offsets[p+1]-1; every sample needs
+ *                 all of its incident tetrahedra (the lumped mass is their
+ *                 volume) and at least one
+ *   inc_tets      [n_inc][4] int32: the tetrahedron's vertices as indices
+ *                 into its instance's ring range (0 .. ring size - 1), in
+ *                 the mesh's vertex order
+ *   inc_corner    [n_inc] int8: which of the four is the sample's vertex
+ *   ring_u        [n_ring][3] FP32 out: u = g(X, q_n) at the ring vertices
+ * Stencil data that breaks these rules (a range that is not CSR, an index
+ * outside the ring, a corner outside 0..3) is caught in the kernels and
+ * makes the instance NONFINITE; nothing outside the arrays is read. */
+typedef struct {
+  int64_t n_ring, max_ring, n_inc;
+  const int64_t* ring_offsets;
+  const float* ring_X;
+  const int64_t* inc_offsets;
+  const int32_t* inc_tets;
+  const int8_t* inc_corner;
+  float* ring_u;
+} crom_fe_mesh;
+
+/* Builds the stencil of crom_fe_mesh on the host (the same section): for
+ * each sample vertex, every tetrahedron that contains it (ascending index),
+ * and for each instance its ring, the sorted vertices of those tetrahedra.
+ *   n_vert, n_tet, tets  the mesh: tets [n_tet][4] int32 vertex indices
+ *   n_inst, sample_offsets [n_inst+1] int64 CSR (sample_offsets[0] = 0),
+ *   sample_vert [total] int32  each instance's sample vertices
+ * Outputs (host): n_ring, max_ring, n_inc; and, when ring_offsets is not
+ * NULL, ring_offsets [n_inst+1], ring_vert [n_ring] (mesh vertex of each
+ * ring entry, so ring_X = X[ring_vert]), inc_offsets [total+1], inc_tets
+ * [n_inc][4] (ring-local indices) and inc_corner [n_inc].  Call once with
+ * ring_offsets = NULL for the sizes, then with arrays of those sizes.
+ * Errors: CROM_ERR_INVALID_ARG for an index out of range, a tetrahedron
+ * with a repeated vertex, offsets that are not CSR, or a sample vertex that
+ * no tetrahedron contains. */
+crom_status crom_fe_stencil(int64_t n_vert, int64_t n_tet, const int32_t* tets, int32_t n_inst,
+                            const int64_t* sample_offsets, const int32_t* sample_vert, int64_t* n_ring,
+                            int64_t* max_ring, int64_t* n_inc, int64_t* ring_offsets, int32_t* ring_vert,
+                            int64_t* inc_offsets, int32_t* inc_tets, int8_t* inc_corner);
 
 /* PDE of the instances.
  * HEAT: u_t = nu * Laplacian(u) with forward Euler,
@@ -160,11 +216,26 @@ enum { CROM_PDE_HEAT = 0, CROM_PDE_NEOHOOKEAN = 1 };
  *   Euler at the samples: v+ = v_n + dt (div P / rho0 + B), target
  *   u+ = u + dt v+.  coef [n_inst][6] FP64 = lam, mu, rho0, Bx, By, Bz.
  *   Needs m == 3 and d == 3 (the (3, 16, 3, 256) decoder).  A sample with
- *   det F <= 0 makes its instance NONFINITE. */
+ *   det F <= 0 makes its instance NONFINITE.
+ * COROTATED_FE: the same elastodynamics with corotated linear elasticity
+ *   and finite-element forces (appendix, Sec. "Solid Mechanics"): the
+ *   decoder gives the deformed positions x = X + g(X, q_n) of the ring
+ *   vertices (`mesh`); per incident tetrahedron D_m = [X_a - X_4], F =
+ *   I + [u_a - u_4] D_m^-1, R the rotation of the polar decomposition
+ *   F = R S, P = 2 mu (F - R) + lam (tr(R^T F) - 3) R (the derivative of the
+ *   corotated energy mu |F - R|^2 + lam/2 tr(R^T F - I)^2), vertex forces
+ *   [f_1 f_2 f_3] = -(|det D_m| / 6) P D_m^-T, f_4 = -(f_1 + f_2 + f_3);
+ *   the force on a sample is the sum over its incident tetrahedra, its
+ *   lumped mass rho0 / 4 of their volume; then v+ = v_n + dt (f / m + B)
+ *   and u+ = u + dt v+ as for NEOHOOKEAN.  coef [n_inst][6] FP64 = lam,
+ *   mu, rho0, Bx, By, Bz.  Needs the (3, 16, 3, 256) decoder and at most
+ *   65535 instances.  A tetrahedron with det F <= 0 makes its instance
+ *   NONFINITE. */
 typedef struct {
   int32_t kind, _pad;
   double dt;
   const double* coef;
+  const crom_fe_mesh* mesh; /* COROTATED_FE: host pointer; ignored otherwise */
 } crom_pde;
 
 /* Inversion options (host struct).
@@ -177,7 +248,7 @@ typedef struct {
  *   ls_shrink  s in (0, 1)
  *   max_rounds evaluation rounds after the first, 0 = enough for max_iter
  *              iterations that each need the longest line search (at most
- *              256).  A round evaluates 4 line-search trials (or
+ *              256).  A round evaluates one line-search trial (or
  *              re-linearises after a shortened step); an instance still
  *              running after the last round ends with CROM_FLAG_MAXITER.
  * The step runs as one persistent kernel whose grid fits on the GPU at
@@ -217,8 +288,8 @@ crom_status crom_step_workspace(const crom_net* net, int32_t n_inst, int64_t tot
  *                             instance needs r <= d * S_i samples)
  *   y       [total_samples][m] FP32 sample points
  *   clamp   NULL or [total_samples] uint8: 1 = Dirichlet sample, target 0
- *   q_prev  NEOHOOKEAN: NULL or [n_inst][r] FP64, the previous step's latent
- *           (ignored for HEAT)
+ *   q_prev  NEOHOOKEAN, COROTATED_FE: NULL or [n_inst][r] FP64, the previous
+ *           step's latent (ignored for HEAT)
  *   q_n     [n_inst][r] FP64;  q_next [n_inst][r] FP64 out (must not alias q_n)
  *   info    [n_inst] crom_step_info out
  *   ws      workspace of at least crom_step_workspace bytes, 256-byte aligned

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libcrom.so")
 
 PREC_FP32, PREC_BF16, PREC_BF16_PURE, PREC_BF16X3 = 0, 1, 2, 3
 D2_NONE, D2_LAPLACIAN, D2_HESSIAN = 0, 1, 2
-PDE_HEAT, PDE_NEOHOOKEAN = 0, 1
+PDE_HEAT, PDE_NEOHOOKEAN, PDE_COROTATED_FE = 0, 1, 2
 ACT_ELU, ACT_SINE = 0, 1
 _ACT_NAMES = {"elu": ACT_ELU, "sine": ACT_SINE}
 FLAG_MAXITER, FLAG_SINGULAR, FLAG_NONFINITE, FLAG_LS_FAIL, FLAG_ABORTED = 1, 2, 4, 8, 16
@@ -34,7 +34,13 @@ class CromNet(Structure):
 
 
 class CromPDE(Structure):
-    _fields_ = [("kind", c_int32), ("_pad", c_int32), ("dt", c_double), ("coef", c_void_p)]
+    _fields_ = [("kind", c_int32), ("_pad", c_int32), ("dt", c_double), ("coef", c_void_p), ("mesh", c_void_p)]
+
+
+class CromFEMesh(Structure):
+    _fields_ = [("n_ring", c_int64), ("max_ring", c_int64), ("n_inc", c_int64), ("ring_offsets", c_void_p),
+                ("ring_X", c_void_p), ("inc_offsets", c_void_p), ("inc_tets", c_void_p),
+                ("inc_corner", c_void_p), ("ring_u", c_void_p)]
 
 
 class CromGNOpts(Structure):
@@ -129,10 +135,13 @@ def lib():
                                            POINTER(CromSamplingOpts), c_void_p, c_int32,
                                            POINTER(CromSamplingResult), c_void_p, c_void_p, c_void_p, c_size_t,
                                            c_void_p]
+        L.crom_fe_stencil.argtypes = [c_int64, c_int64, c_void_p, c_int32, c_void_p, c_void_p,
+                                      POINTER(c_int64), POINTER(c_int64), POINTER(c_int64), c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_void_p]
         L.crom_kernel_timer.argtypes = [c_int32]
         L.crom_kernel_timer_read.argtypes = [POINTER(c_double), POINTER(c_int64)]
         for name in ("crom_sampling_residual", "crom_sampling_candidates", "crom_sampling_workspace",
-                     "crom_robust_sampling", "crom_kernel_timer", "crom_kernel_timer_read"):
+                     "crom_robust_sampling", "crom_kernel_timer", "crom_kernel_timer_read", "crom_fe_stencil"):
             getattr(L, name).restype = c_int32
         for name in ("crom_net_pack", "crom_decode", "crom_decode_jac", "crom_decode_jac_x",
                      "crom_decode_jac_q", "crom_step_workspace", "crom_step", "crom_fd_heat",
@@ -417,14 +426,67 @@ class GNOptions:
                           self.tol_step, self.armijo_c, self.ls_shrink)
 
 
+class FEStencil:
+    """Finite-element stencil of each instance's sample vertices on a
+    tetrahedral mesh (crom_fe_stencil on the host), uploaded in the layout
+    crom_fe_mesh takes.
+
+    X [V, 3] rest positions, tets [T, 4] vertex indices, samples: one array
+    of sample vertex indices per instance.  Attributes: offsets and y (the
+    samples' CSR offsets and positions, for Stepper), ring_vert (mesh vertex
+    of each ring entry, host), ring_u (the decoded ring displacement a step
+    writes, device)."""
+
+    def __init__(self, X, tets, samples: Sequence, device):
+        torch = _torch()
+        X = np.ascontiguousarray(np.asarray(X, dtype=np.float32))
+        tets = np.ascontiguousarray(np.asarray(tets, dtype=np.int32))
+        sv = [np.asarray(sm, dtype=np.int32) for sm in samples]
+        soff = np.zeros(len(sv) + 1, dtype=np.int64)
+        soff[1:] = np.cumsum([len(a) for a in sv])
+        svert = np.ascontiguousarray(np.concatenate(sv) if sv else np.zeros(0, np.int32))
+        n_ring, max_ring, n_inc = c_int64(0), c_int64(0), c_int64(0)
+        args = (X.shape[0], tets.shape[0], tets.ctypes.data, len(sv), soff.ctypes.data, svert.ctypes.data,
+                ctypes.byref(n_ring), ctypes.byref(max_ring), ctypes.byref(n_inc))
+        _check(lib().crom_fe_stencil(*args, None, None, None, None, None), "crom_fe_stencil")
+        ring_off = np.zeros(len(sv) + 1, dtype=np.int64)
+        ring_vert = np.zeros(n_ring.value, dtype=np.int32)
+        inc_off = np.zeros(int(soff[-1]) + 1, dtype=np.int64)
+        inc_tets = np.zeros((n_inc.value, 4), dtype=np.int32)
+        inc_corner = np.zeros(n_inc.value, dtype=np.int8)
+        _check(lib().crom_fe_stencil(*args, ring_off.ctypes.data, ring_vert.ctypes.data, inc_off.ctypes.data,
+                                     inc_tets.ctypes.data, inc_corner.ctypes.data), "crom_fe_stencil")
+        self.n_ring, self.max_ring, self.n_inc = n_ring.value, max_ring.value, n_inc.value
+        self.ring_vert = ring_vert
+        self.sample_vert = svert
+        to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        self.offsets = to(soff)
+        self.y = to(X[svert])
+        self.ring_offsets = to(ring_off)
+        self.ring_X = to(X[ring_vert])
+        self.inc_offsets = to(inc_off)
+        self.inc_tets = to(inc_tets)
+        self.inc_corner = to(inc_corner)
+        self.ring_u = torch.zeros(max(self.n_ring, 1), 3, dtype=torch.float32, device=device)
+
+    def c_struct(self) -> CromFEMesh:
+        return CromFEMesh(self.n_ring, self.max_ring, self.n_inc, _ptr(self.ring_offsets), _ptr(self.ring_X),
+                          _ptr(self.inc_offsets), _ptr(self.inc_tets), _ptr(self.inc_corner), _ptr(self.ring_u))
+
+
 class Stepper:
     """Reusable latent-step launcher for a fixed batch layout (instances,
-    CSR sample offsets, sample points): owns the workspace."""
+    CSR sample offsets, sample points): owns the workspace.  pde "heat",
+    "neohookean" or "corotated_fe" (then `mesh` is the FEStencil whose
+    offsets and y these are)."""
 
-    def __init__(self, dec: Decoder, offsets, y, clamp=None, pde: str = "heat"):
+    def __init__(self, dec: Decoder, offsets, y, clamp=None, pde: str = "heat", mesh: "FEStencil" = None):
         torch = _torch()
         self.dec = dec
-        self.kind = {"heat": PDE_HEAT, "neohookean": PDE_NEOHOOKEAN}[pde]
+        self.kind = {"heat": PDE_HEAT, "neohookean": PDE_NEOHOOKEAN, "corotated_fe": PDE_COROTATED_FE}[pde]
+        if (self.kind == PDE_COROTATED_FE) != (mesh is not None):
+            raise CromError("the finite-element step, and only it, takes a mesh stencil")
+        self.mesh = mesh
         off = torch.as_tensor(offsets, dtype=torch.int64)
         self.n_inst = int(off.numel() - 1)
         self.total = int(off[-1].item())
@@ -446,8 +508,9 @@ class Stepper:
 
     def step(self, q_n, coef, dt: float, opts: GNOptions = GNOptions(), q_next=None, q_prev=None):
         """One latent step.  coef: heat, nu (one value or one per instance);
-        neo-Hookean, (lam, mu, rho0, Bx, By, Bz) (one row or one per
-        instance).  q_prev: neo-Hookean, the previous latents (None: at rest)."""
+        neo-Hookean and corotated, (lam, mu, rho0, Bx, By, Bz) (one row or one
+        per instance).  q_prev: the elastic kinds, the previous latents (None:
+        at rest)."""
         torch = _torch()
         dev = self.dec.params.device
         q_n = q_n.to(device=dev, dtype=torch.float64).contiguous()
@@ -459,7 +522,8 @@ class Stepper:
         if q_next is None:
             q_next = torch.empty_like(q_n)
         net = self.dec._net()
-        pde = CromPDE(self.kind, 0, float(dt), coef.data_ptr())
+        fm = self.mesh.c_struct() if self.mesh is not None else None
+        pde = CromPDE(self.kind, 0, float(dt), coef.data_ptr(), ctypes.addressof(fm) if fm is not None else None)
         o = opts.c_struct()
         self._coef, self._q_prev = coef, q_prev  # keep alive until the stream has consumed them
         _check(lib().crom_step(ctypes.byref(net), ctypes.byref(pde), self.n_inst, _ptr(self.offsets),
@@ -594,7 +658,7 @@ def robust_sampling(dec: Decoder, nodes, ref, q0, coef, dt: float, init, n_steps
     tc = np.full((rounds_max, n_try), -1, dtype=np.int32) if trace else None
     tm = np.full((rounds_max, n_try), np.nan) if trace else None
     g = (opts or GNOptions()).c_struct()
-    pd = CromPDE(kind, 0, float(dt), coef.data_ptr())
+    pd = CromPDE(kind, 0, float(dt), coef.data_ptr(), None)
     out = CromSamplingResult()
     _check(lib().crom_robust_sampling(ctypes.byref(net), ctypes.byref(pd), n_mu, _ptr(nodes), P, _ptr(node_clamp),
                                       _ptr(ref), _ptr(q0), ctypes.byref(g), ctypes.byref(o),

@@ -12,9 +12,10 @@
 //                  formed directly; per-batch partial sums of J^T J, J^T rho
 //                  and 1/2 rho^T rho (FP64)
 //     phase p > 0  eval_trials: the decoder differences g(q_t) - g(q_n) at
-//                  four line-search trials q_t = q + alpha_t delta and the
-//                  Jacobian at the first; rho_t = rho_0 - (g(q_t) - g(q_n)),
-//                  with the same partial sums
+//                  the round's line-search trials q_t = q + alpha_t delta
+//                  (TV of them, one by default) and the Jacobian at the
+//                  first; rho_t = rho_0 - (g(q_t) - g(q_n)), with the same
+//                  partial sums
 //   The workgroup that completes the last batch of an instance in a phase
 //   solves that instance at once: fixed-order sum of its partials, Armijo
 //   test of the trials, Cholesky of J^T J, next direction.  A phase ends
@@ -80,10 +81,17 @@
 namespace crom {
 
 constexpr int RMAX = 16;
+// Line-search trials evaluated per round.  More trials per round cut the
+// rounds an instance needs when the line search backtracks, at the price of
+// wider evaluations in every round.  Measured (BF16): the single-instance 2D
+// heat step at 2,000 samples, where almost every first trial is accepted,
+// takes 0.157 ms with one trial per round and 0.203 ms with four; the batch
+// of 512 trained instances, which backtrack (11.5 trials per instance and
+// step), takes 24.8 ms with one and 21.6 ms with four.
 #ifndef CROM_TRIALS
-#define CROM_TRIALS 4
+#define CROM_TRIALS 1
 #endif
-constexpr int TV = CROM_TRIALS;  // line-search trials per round
+constexpr int TV = CROM_TRIALS;
 constexpr int MAXP = 256;    // bound on the phases of one step
 enum { PH_INIT = 0, PH_TRIALS = 1, PH_REJAC = 2, PH_DONE = 3 };
 
@@ -160,6 +168,18 @@ static WsLayout ws_layout(int r, int d, int m, int n_inst, int64_t total) {
   return L;
 }
 
+// Finite-element stencil of the samples (CROM_PDE_COROTATED_FE: on = 1).
+struct FeArgs {
+  int on;
+  const int64_t* ring_offsets;  // [n_inst + 1] CSR over the ring vertices
+  const float* ring_X;          // [n_ring][3] rest positions
+  const int64_t* inc_offsets;   // [total + 1] CSR of each sample's tetrahedra
+  const int32_t* inc_tets;      // [n_inc][4] instance-local ring indices
+  const int8_t* inc_corner;     // [n_inc] the sample's own vertex, 0..3
+  float* ring_u;                // [n_ring][3] decoded displacement at q_n
+  int64_t n_ring, max_ring, n_inc;
+};
+
 struct StepArgs {
   const float* params;
   const char* packed;
@@ -180,6 +200,7 @@ struct StepArgs {
   int max_iter, linearized, ls_max;
   double tol, armijo_c, shrink;
   uint64_t* trace;  // optional phase timestamps (see crom_debug_step_trace)
+  FeArgs fe;
 };
 
 template <class T>
@@ -537,6 +558,215 @@ __global__ __launch_bounds__(64) void elastic_targets_kernel(StepArgs a) {
       const double inc = clamped ? -u[ii] : a.dt * vn;
       rho0[ii] = inc;
       tg[ii] = clamped ? 0.0 : u[ii] + inc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Corotated elasticity with finite-element forces (appendix, Sec. "Solid
+// Mechanics": linear tetrahedra, the deformation gradient from the linear
+// basis, forces accumulated from the tetrahedra incident on each sample).
+// ---------------------------------------------------------------------------
+
+// Displacement u = g(X, q_n) at the ring vertices of every instance (value
+// column only): blockIdx.y is the instance, the x-blocks stride over its
+// 16-vertex batches.  An instance whose ring range is not a valid CSR range
+// of [0, n_ring] is skipped; its targets then come out NaN.
+template <class S, int NW, int PREC>
+__global__ __launch_bounds__(NW * 64) void ring_decode_kernel(StepArgs a) {
+  using C = Cols<S::M, S::R, 1, 0, false, D2_NONE, 0>;
+  using E = Engine<S, C, 1, NW, PREC, 0>;
+  extern __shared__ __align__(16) char lds[];
+  const int inst = blockIdx.y;
+  const int64_t lo = a.fe.ring_offsets[inst], hi = a.fe.ring_offsets[inst + 1];
+  if (!(lo >= 0 && hi >= lo && hi <= a.fe.n_ring)) return;
+  const int64_t nb = (hi - lo + PT - 1) / PT;
+  if ((int64_t)blockIdx.x >= nb) return;
+  float* par = reinterpret_cast<float*>(lds + E::LDS_BYTES);
+  E::PC::load(par, a.params, a.pi, a.depth, NW * 64);
+  __syncthreads();
+  const double* q = a.q_n + (int64_t)inst * S::R;
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int64_t first = lo + b * PT;
+    const int n_valid = hi - first < PT ? (int)(hi - first) : PT;
+    E::stage(lds, a.fe.ring_X, first, n_valid, q, S::R, nullptr, 0, par);
+    __syncthreads();
+    E::run(lds, par, a.packed, a.depth, 0);
+    const float* res = reinterpret_cast<const float*>(lds + E::RES_OFF);
+    for (int e = threadIdx.x; e < n_valid * S::D; e += blockDim.x) {
+      const int i = e / S::D, oo = e % S::D;
+      a.fe.ring_u[(first + i) * S::D + oo] = res[(oo * E::NT + 0) * PT + i];
+    }
+    __syncthreads();
+  }
+}
+
+// Cofactor matrix c of a 3 x 3 matrix x (x^-T = c / det x); returns det x.
+__device__ __forceinline__ double cofactors3(const double x[3][3], double c[3][3]) {
+  c[0][0] = x[1][1] * x[2][2] - x[1][2] * x[2][1];
+  c[0][1] = x[1][2] * x[2][0] - x[1][0] * x[2][2];
+  c[0][2] = x[1][0] * x[2][1] - x[1][1] * x[2][0];
+  c[1][0] = x[0][2] * x[2][1] - x[0][1] * x[2][2];
+  c[1][1] = x[0][0] * x[2][2] - x[0][2] * x[2][0];
+  c[1][2] = x[0][1] * x[2][0] - x[0][0] * x[2][1];
+  c[2][0] = x[0][1] * x[1][2] - x[0][2] * x[1][1];
+  c[2][1] = x[0][2] * x[1][0] - x[0][0] * x[1][2];
+  c[2][2] = x[0][0] * x[1][1] - x[0][1] * x[1][0];
+  return x[0][0] * c[0][0] + x[0][1] * c[0][1] + x[0][2] * c[0][2];
+}
+
+// Rotation factor R of the polar decomposition F = R S by Newton's iteration
+// X <- (g X + X^-T / g) / 2 with the determinant scaling g = (det X)^(-1/3)
+// (N. J. Higham, "Computing the polar decomposition - with applications",
+// SIAM J. Sci. Stat. Comput. 7, 1986).  The iteration keeps det X > 0 and
+// converges quadratically; once successive iterates agree to 1e-9 one more
+// unscaled step brings them to rounding level.  det F <= 0 (no proper
+// rotation factor) gives NaN.
+__device__ void polar_rotation(const double F[3][3], double R[3][3]) {
+  double x[3][3], c[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) x[i][j] = F[i][j];
+  bool polish = false;
+  for (int it = 0; it < 40; ++it) {
+    const double det = cofactors3(x, c);
+    if (!(det > 0.0)) {
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) R[i][j] = __builtin_nan("");
+      return;
+    }
+    const double g = polish ? 1.0 : 1.0 / cbrt(det);
+    const double h = 0.5 / (g * det), hg = 0.5 * g;
+    double dmax = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double v = hg * x[i][j] + h * c[i][j];
+        dmax = fmax(dmax, fabs(v - x[i][j]));
+        x[i][j] = v;
+      }
+    if (polish) break;
+    if (dmax < 1e-9) polish = true;
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) R[i][j] = x[i][j];
+}
+
+// Force of one tetrahedron on one of its vertices and the tetrahedron's
+// volume.  X, u: the four vertices' rest positions and displacements.
+//   D_m = [X_a - X_3]_{a<3}, G = [u_a - u_3]_{a<3} D_m^-1, F = I + G,
+//   P = 2 mu (F - R) + lam (tr(R^T F) - 3) R,  H = -(|det D_m| / 6) P D_m^-T;
+// the force on corner c < 3 is column c of H, on corner 3 minus their sum.
+__device__ void tet_force(const double X[4][3], const double u[4][3], int corner, double lam, double mu,
+                          double f[3], double* vol) {
+  double Dm[3][3], Du[3][3], cm[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < 3; ++a) {
+      Dm[i][a] = X[a][i] - X[3][i];
+      Du[i][a] = u[a][i] - u[3][i];
+    }
+  const double det = cofactors3(Dm, cm);  // D_m^-1 = cm^T / det, D_m^-T = cm / det
+  double F[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int a = 0; a < 3; ++a) s += Du[i][a] * cm[j][a];
+      F[i][j] = (i == j ? 1.0 : 0.0) + s / det;
+    }
+  double R[3][3];
+  polar_rotation(F, R);
+  double tr = -3.0;
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) tr += R[k][i] * F[k][i];
+  double P[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P[i][j] = 2.0 * mu * (F[i][j] - R[i][j]) + lam * tr * R[i][j];
+  const double v = fabs(det) / 6.0;
+  *vol = v;
+  // H[i][a] = -v sum_k P[i][k] D_m^-T[k][a] = -(v / det) sum_k P[i][k] cm[k][a]
+  for (int i = 0; i < 3; ++i) {
+    double hs[3];
+    for (int a = 0; a < 3; ++a) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += P[i][k] * cm[k][a];
+      hs[a] = -(v / det) * s;
+    }
+    f[i] = corner < 3 ? hs[corner] : -(hs[0] + hs[1] + hs[2]);
+  }
+}
+
+// FP64 update at the samples from finite-element forces: one wave per
+// sample, its lanes over the sample's incident tetrahedra; the sample's
+// force and incident volume are summed across the wave in a fixed order.
+//   m = rho0 (incident volume) / 4,  v_n = (du/dq)(q_n - q_prev)/dt,
+//   v+ = v_n + dt (f / m + B),  rho_0 = dt v+ (a clamped sample: -u).
+// Invalid stencil data (a ring or incidence range that is not a CSR range,
+// a ring larger than max_ring, an index outside the instance's ring, a
+// corner outside 0..3, a sample without tetrahedra) gives NaN, which the
+// solve reports as a non-finite instance.
+constexpr int FE_WAVES = 4;
+template <int R>
+__global__ __launch_bounds__(FE_WAVES * 64) void fe_targets_kernel(StepArgs a) {
+  const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
+  const JetsLayout JL{3, 3, R, 6};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double qnan = __builtin_nan("");
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int inst = wsp<int32_t>(a, a.L.blk_inst)[blk];
+    const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
+    const int64_t rem = a.offsets[inst + 1] - first;
+    const int n_valid = rem < PT ? (int)rem : PT;
+    const int64_t rlo = a.fe.ring_offsets[inst], rhi = a.fe.ring_offsets[inst + 1];
+    const bool ring_ok = rlo >= 0 && rhi > rlo && rhi <= a.fe.n_ring && rhi - rlo <= a.fe.max_ring;
+    const double* cf = a.coef + (int64_t)inst * 6;
+    const double lam = cf[0], mu = cf[1], rho = cf[2];
+    for (int i = wave; i < n_valid; i += FE_WAVES) {
+      const int64_t p = first + i;
+      const int64_t elo = a.fe.inc_offsets[p], ehi = a.fe.inc_offsets[p + 1];
+      bool ok = ring_ok && elo >= 0 && ehi > elo && ehi <= a.fe.n_inc;
+      double fs[3] = {0.0, 0.0, 0.0}, vs = 0.0;
+      if (ok) {
+        for (int64_t e = elo + lane; e < ehi; e += 64) {
+          const int corner = a.fe.inc_corner[e];
+          bool good = corner >= 0 && corner < 4;
+          double X[4][3], u[4][3];
+          for (int k = 0; k < 4; ++k) {
+            const int32_t v = a.fe.inc_tets[e * 4 + k];
+            const bool in = v >= 0 && (int64_t)v < rhi - rlo;
+            good = good && in;
+            const int64_t g = rlo + (in ? v : 0);
+            for (int j = 0; j < 3; ++j) {
+              X[k][j] = (double)a.fe.ring_X[g * 3 + j];
+              u[k][j] = (double)a.fe.ring_u[g * 3 + j];
+            }
+          }
+          double f[3], vol;
+          tet_force(X, u, good ? corner : 0, lam, mu, f, &vol);
+          for (int j = 0; j < 3; ++j) fs[j] += good ? f[j] : qnan;
+          vs += vol;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        for (int j = 0; j < 3; ++j) fs[j] += __shfl_xor(fs[j], off);
+        vs += __shfl_xor(vs, off);
+      }
+      if (lane == 0) {
+        const float* row = wsp<float>(a, a.L.jets) + p * a.L.nj;
+        const double mass = ok ? rho * vs / 4.0 : qnan;
+        const bool clamped = a.clamp && a.clamp[p];
+        double* rho0 = wsp<double>(a, a.L.rho0) + p * 3;
+        double* tg = wsp<double>(a, a.L.targets) + p * 3;
+        for (int k = 0; k < 3; ++k) {
+          double v = 0.0;
+          if (a.q_prev)
+            for (int r = 0; r < R; ++r)
+              v += (double)row[JL.jac(k, r)] *
+                   ((a.q_n[(int64_t)inst * R + r] - a.q_prev[(int64_t)inst * R + r]) / a.dt);
+          const double uk = row[JL.val(k)];
+          const double vn = v + a.dt * (fs[k] / mass + cf[3 + k]);
+          const double inc = clamped ? -uk : a.dt * vn;
+          rho0[k] = inc;
+          tg[k] = clamped ? 0.0 : uk + inc;
+        }
+      }
     }
   }
 }
@@ -1092,23 +1322,48 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) eval_jets_batch<S, NW, PREC, PF>(a, lds, par, blk);
 }
 
+// The instance's batch partials are summed by the whole workgroup: entry e
+// by NS strided subsets of the batches (subset s takes batches b0 + s,
+// b0 + s + NS, ...), each with UNR loads in flight, then the subsets in
+// order; a fixed order for any batch layout.  One wave then solves.
+constexpr int LLS_SOLVE_THREADS = 256;
 template <int R>
-__global__ __launch_bounds__(64) void lls_solve_kernel(StepArgs a) {
+__global__ __launch_bounds__(LLS_SOLVE_THREADS) void lls_solve_kernel(StepArgs a) {
   constexpr int NA = R * (R + 1) / 2;
   constexpr int NRED = NA + R + TV;
+  constexpr int NS = LLS_SOLVE_THREADS / NRED;
+  constexpr int UNR = 8;
   static_assert(NRED <= 64, "one lane per reduced entry");
+  __shared__ double sub[NS * NRED];
   __shared__ double red[NRED];
   const int inst = blockIdx.x, lane = threadIdx.x;
   const int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
   const int32_t b0 = first_blk[inst], b1 = first_blk[inst + 1];
   if (b0 == b1) return;  // no samples: the setup kernel already reported it
   const double* part = wsp<double>(a, a.L.partials);
-  if (lane < NRED) {
+  if (threadIdx.x < NS * NRED) {
+    const int e = threadIdx.x % NRED, sl = threadIdx.x / NRED;
     double acc = 0.0;
-    for (int32_t b = b0; b < b1; ++b) acc += part[(int64_t)b * NRED + lane];
-    red[lane] = acc;
+    for (int32_t base = b0 + sl; base < b1; base += UNR * NS) {
+      double v[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {  // clamped, branch-free: all loads issue at once
+        const int32_t b = base + u * NS;
+        v[u] = part[(int64_t)(b < b1 ? b : b0) * NRED + e];
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) acc += (base + u * NS < b1) ? v[u] : 0.0;
+    }
+    sub[sl * NRED + e] = acc;
   }
   __syncthreads();
+  if (threadIdx.x < NRED) {
+    double acc = 0.0;
+    for (int sl = 0; sl < NS; ++sl) acc += sub[sl * NRED + threadIdx.x];
+    red[threadIdx.x] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
   const double phi = red[NA + R];
   bool finite = isfinite(phi);
   for (int e = 0; e < NA + R; ++e) finite &= (bool)isfinite(red[e]);
@@ -1156,7 +1411,7 @@ static crom_status launch_lls(StepArgs a, hipStream_t st) {
   timer_mark(st);
   hipLaunchKernelGGL(k, dim3((unsigned)g), dim3(NW * 64), lds_bytes, st, a);
   if ((s = hip_check(hipGetLastError(), "lls launch")) != CROM_OK) return s;
-  hipLaunchKernelGGL(lls_solve_kernel<S::R>, dim3((unsigned)a.n_inst), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(lls_solve_kernel<S::R>, dim3((unsigned)a.n_inst), dim3(LLS_SOLVE_THREADS), 0, st, a);
   timer_mark(st);
   return hip_check(hipGetLastError(), "lls solve launch");
 }
@@ -1280,6 +1535,34 @@ static crom_status elastic_prepare(const StepArgs& a, hipStream_t st) {
   }
 }
 
+// Finite-element preparation: the ring decode at q_n, the samples' value and
+// latent Jacobian (chunks of QC), then the per-sample update.
+template <class S, int NW, int PREC>
+static crom_status fe_prepare(const StepArgs& a, hipStream_t st) {
+  constexpr int QC = ElasticChunks<PREC>::QC;
+  using E = Engine<S, Cols<S::M, S::R, 1, 0, false, D2_NONE, 0>, 1, NW, PREC, 0>;
+  if (a.fe.max_ring > 0) {
+    const int lds_bytes = E::LDS_BYTES + E::PC::bytes(a.depth);
+    if (lds_bytes > LDS_MAX) return fail(CROM_ERR_UNSUPPORTED, "network too deep for the LDS");
+    auto k = ring_decode_kernel<S, NW, PREC>;
+    crom_status s = set_lds(k, lds_bytes);
+    if (s != CROM_OK) return s;
+    int64_t gx = (a.fe.max_ring + PT - 1) / PT;
+    if (gx > 65535) gx = 65535;
+    hipLaunchKernelGGL(k, dim3((unsigned)gx, (unsigned)a.n_inst), dim3(NW * 64), lds_bytes, st, a);
+    s = hip_check(hipGetLastError(), "ring decode launch");
+    if (s != CROM_OK) return s;
+  }
+  for (int qb = 0; qb < S::R; qb += QC) {
+    crom_status s = launch_jets_pass<S, Cols<S::M, S::R, 1, 0, false, D2_NONE, QC>, NW, PREC>(a, qb, st);
+    if (s != CROM_OK) return s;
+  }
+  int64_t g = a.L.nblk_max;
+  if (g > 65535) g = 65535;
+  hipLaunchKernelGGL(fe_targets_kernel<S::R>, dim3((unsigned)g), dim3(FE_WAVES * 64), 0, st, a);
+  return hip_check(hipGetLastError(), "finite-element targets launch");
+}
+
 template <class S, int NW, int PREC, int PF, int KIND = PK_HEAT, int WPE = 1>
 static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
   using T = StepTraits<S, NW, PREC, PF, KIND>;
@@ -1315,7 +1598,7 @@ static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
   if (s != CROM_OK) return s;
   timer_mark(st);
   if constexpr (KIND == PK_ELASTIC) {
-    s = elastic_prepare<S, NW, PREC>(a, st);
+    s = a.fe.on ? fe_prepare<S, NW, PREC>(a, st) : elastic_prepare<S, NW, PREC>(a, st);
     if (s != CROM_OK) return s;
   }
   int64_t g = a.L.nblk_max;
@@ -1422,10 +1705,22 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
   crom_status s = check_net(net, true);
   if (s != CROM_OK) return s;
   if (!pde || !opts) return fail(CROM_ERR_INVALID_ARG, "pde and opts are required");
-  if (pde->kind != CROM_PDE_HEAT && pde->kind != CROM_PDE_NEOHOOKEAN) return fail(CROM_ERR_UNSUPPORTED, "pde kind");
+  if (pde->kind != CROM_PDE_HEAT && pde->kind != CROM_PDE_NEOHOOKEAN && pde->kind != CROM_PDE_COROTATED_FE)
+    return fail(CROM_ERR_UNSUPPORTED, "pde kind");
   if (pde->kind == CROM_PDE_HEAT && net->d != 1) return fail(CROM_ERR_UNSUPPORTED, "the heat step needs d == 1");
-  if (pde->kind == CROM_PDE_NEOHOOKEAN && (net->d != 3 || net->m != 3))
-    return fail(CROM_ERR_UNSUPPORTED, "the elastic step needs m == 3 and d == 3");
+  const bool elastic = pde->kind == CROM_PDE_NEOHOOKEAN || pde->kind == CROM_PDE_COROTATED_FE;
+  if (elastic && (net->d != 3 || net->m != 3))
+    return fail(CROM_ERR_UNSUPPORTED, "the elastic steps need m == 3 and d == 3");
+  const crom_fe_mesh* mesh = pde->kind == CROM_PDE_COROTATED_FE ? pde->mesh : nullptr;
+  if (pde->kind == CROM_PDE_COROTATED_FE) {
+    if (!mesh) return fail(CROM_ERR_INVALID_ARG, "the finite-element step needs pde->mesh");
+    if (mesh->n_ring < 0 || mesh->max_ring < 0 || mesh->n_inc < 0 || mesh->max_ring > mesh->n_ring)
+      return fail(CROM_ERR_INVALID_ARG, "mesh sizes out of range");
+    if (!mesh->ring_offsets || !mesh->inc_offsets || (mesh->n_ring > 0 && (!mesh->ring_X || !mesh->ring_u)) ||
+        (mesh->n_inc > 0 && (!mesh->inc_tets || !mesh->inc_corner)))
+      return fail(CROM_ERR_INVALID_ARG, "mesh arrays are required");
+    if (n_inst > 65535) return fail(CROM_ERR_UNSUPPORTED, "the finite-element step takes at most 65535 instances");
+  }
   if (net->r > RMAX) return fail(CROM_ERR_UNSUPPORTED, "r > 16");
   if (n_inst < 0 || total_samples < 0) return fail(CROM_ERR_INVALID_ARG, "negative size");
   if (n_inst == 0) return CROM_OK;
@@ -1454,7 +1749,19 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
   a.clamp = clamp;
   a.coef = pde->coef;
   a.dt = pde->dt;
-  a.q_prev = pde->kind == CROM_PDE_NEOHOOKEAN ? q_prev : nullptr;
+  a.q_prev = elastic ? q_prev : nullptr;
+  if (mesh) {
+    a.fe.ring_offsets = mesh->ring_offsets;
+    a.fe.ring_X = mesh->ring_X;
+    a.fe.inc_offsets = mesh->inc_offsets;
+    a.fe.inc_tets = mesh->inc_tets;
+    a.fe.inc_corner = mesh->inc_corner;
+    a.fe.ring_u = mesh->ring_u;
+    a.fe.n_ring = mesh->n_ring;
+    a.fe.max_ring = mesh->max_ring;
+    a.fe.n_inc = mesh->n_inc;
+    a.fe.on = 1;
+  }
   a.q_n = q_n;
   a.q_next = q_next;
   a.info = info;
