@@ -149,3 +149,42 @@ def gauss_newton(value_fn, value_jac_fn, target: np.ndarray, q0: np.ndarray,
     else:
         info.flags |= MAXITER
     return q, info
+
+
+def gauss_newton_from_guess(value_fn, value_jac_fn, target: np.ndarray, q_n: np.ndarray, q_guess,
+                            opts: GNOptions):
+    """Gauss-Newton with a second candidate starting point (Sec. "Initial
+    Guess for the Nonlinear Solver": the previous latent is the natural start;
+    where the field changes a lot over a step, an encoder's latent for the
+    updated field can be the better one).
+
+    Readings (the paper gives no rule for combining the two):
+    * the guess is considered only when q_n is not already a stationary
+      point: the normal equations at q_n are finite and solvable and their
+      step is not negligible (the stopping test of ``gauss_newton``);
+    * the guess replaces q_n as the start when its objective is finite and
+      strictly smaller than q_n's; otherwise Gauss-Newton runs from q_n as
+      without a guess;
+    * the linearised variant (one step from q_n) ignores the guess;
+    * obj_first stays the objective at q_n.
+    Returns (q, GNInfo, used_guess)."""
+    if q_guess is None or opts.linearized:
+        q, info = gauss_newton(value_fn, value_jac_fn, target, q_n, opts)
+        return q, info, False
+    target = np.asarray(target, dtype=np.float64).ravel()
+    q_n = np.asarray(q_n, dtype=np.float64)
+    g, J = value_jac_fn(q_n)
+    A, b, phi = normal_equations(J, target - g)
+    usable = np.isfinite(phi) and np.all(np.isfinite(A)) and np.all(np.isfinite(b))
+    L = cholesky(A) if usable else None
+    if L is not None:
+        delta = chol_solve(L, b)
+        if float(np.linalg.norm(delta)) > opts.tol_step * (1.0 + float(np.linalg.norm(q_n))):
+            rg = target - value_fn(np.asarray(q_guess, dtype=np.float64))
+            phig = 0.5 * float(rg @ rg)
+            if np.isfinite(phig) and phig < phi:
+                q, info = gauss_newton(value_fn, value_jac_fn, target, q_guess, opts)
+                info.obj_first = phi
+                return q, info, True
+    q, info = gauss_newton(value_fn, value_jac_fn, target, q_n, opts)
+    return q, info, False

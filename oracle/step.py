@@ -16,7 +16,7 @@ from __future__ import annotations
 import numpy as np
 
 from .heat import rom_heat_targets
-from .inversion import GNOptions, gauss_newton
+from .inversion import GNOptions, gauss_newton, gauss_newton_from_guess
 
 
 def invert(decoder, y, target: np.ndarray, q0: np.ndarray, opts: GNOptions):
@@ -51,3 +51,31 @@ def heat_rollout(decoder, y, q0: np.ndarray, nu: float, dt: float, steps: int,
         qs.append(q)
         infos.append(info)
     return np.stack(qs), infos
+
+
+def heat_step_from_guess(decoder, y, q_n: np.ndarray, q_guess, nu: float, dt: float, opts: GNOptions,
+                         clamp=None):
+    """heat_step with a second candidate start (``gauss_newton_from_guess``).
+    Returns (q_next, info, f_next, used_guess)."""
+    g = decoder.value(y, q_n)
+    f_next = rom_heat_targets(g, decoder.laplacian(y, q_n), nu, dt, clamp)
+
+    def value_fn(q):
+        return decoder.value(y, q).ravel()
+
+    def value_jac_fn(q):
+        gg, J = decoder.value_jac_q(y, q)
+        return gg.ravel(), J.reshape(-1, J.shape[-1])
+
+    q, info, used = gauss_newton_from_guess(value_fn, value_jac_fn, f_next, q_n, q_guess, opts)
+    return q, info, f_next, used
+
+
+def encoder_guess(decoder, encode_fn, nodes, q_n: np.ndarray, nu: float, dt: float) -> np.ndarray:
+    """The encoder's latent for the updated field (Sec. "Initial Guess for
+    the Nonlinear Solver"): the heat update g + dt nu Laplacian(g) of the
+    decoded field at every node (the full-order node set, not only the
+    samples), passed through the training encoder ``encode_fn`` ([B, P] ->
+    [B, r])."""
+    f = rom_heat_targets(decoder.value(nodes, q_n), decoder.laplacian(nodes, q_n), nu, dt)
+    return np.asarray(encode_fn(f.reshape(1, -1)), dtype=np.float64)[0]

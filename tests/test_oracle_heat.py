@@ -140,3 +140,19 @@ def test_energy_balance_1d_modes():
     lhs = (integral(u1) - integral(u0)) / (steps * dt)
     mid = heat.fd_heat1d(u0, nu, dx, dt, steps // 2)
     assert abs(lhs - flux(mid)) < 1e-3 * max(1.0, abs(lhs))
+
+
+def test_encoder_guess_of_sine_modes_is_the_modal_euler_update():
+    """With the analytic sine-mode decoder and the least-squares projection
+    onto its modes as the encoder, the guess is the exact modal forward-Euler
+    update q_k (1 - dt nu (k pi)^2)."""
+    from oracle.step import encoder_guess
+    dec = heat.SineModes1D(4)
+    x = np.linspace(0.0, 1.0, 101)[:, None]
+    B, _ = dec._basis(x)
+    P = np.linalg.pinv(B)
+    q = np.array([0.7, -0.4, 0.25, 0.1])
+    nu, dt = 0.5, 1e-3
+    guess = encoder_guess(dec, lambda f: f @ P.T, x, q, nu, dt)
+    k = np.arange(1, 5)
+    np.testing.assert_allclose(guess, q * (1.0 - dt * nu * (k * np.pi) ** 2), rtol=1e-12, atol=1e-14)

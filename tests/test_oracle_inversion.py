@@ -13,6 +13,7 @@ import numpy as np
 
 from oracle import inversion, mlp, step
 from oracle.inversion import GNOptions
+from workloads import rng
 
 
 def _gen(seed):
@@ -175,3 +176,93 @@ def test_nonfinite_flag():
 
     q1, info = step.invert(Bad(), np.zeros((3, 1)), np.ones((3, 1)), np.array([1.0]), GNOptions())
     assert info.flags & inversion.NONFINITE
+
+
+# ---------------------------------------------------------------------------
+# Gauss-Newton with a second candidate start (initial guess)
+# ---------------------------------------------------------------------------
+
+def _exp_model(g, N=30, r=3):
+    """value(q) = exp(G q) (elementwise), a smooth nonlinear model whose
+    Gauss-Newton from a far start needs many iterations."""
+    G = g.uniform(-1, 1, size=(N, r))
+    q_star = g.uniform(-1, 1, size=r)
+    target = np.exp(G @ q_star)
+
+    def value_fn(q):
+        return np.exp(G @ q)
+
+    def value_jac_fn(q):
+        v = np.exp(G @ q)
+        return v, v[:, None] * G
+
+    return value_fn, value_jac_fn, target, q_star
+
+
+def test_guess_better_start_is_used():
+    g = rng(71)
+    vf, vjf, target, q_star = _exp_model(g)
+    q_n = q_star + 1.5
+    opts = GNOptions(max_iter=3, tol_step=1e-12)
+    plain, pinfo = inversion.gauss_newton(vf, vjf, target, q_n, opts)
+    guess = q_star + 1e-3 * g.uniform(-1, 1, size=q_star.size)
+    q, info, used = inversion.gauss_newton_from_guess(vf, vjf, target, q_n, guess, opts)
+    ref, rinfo = inversion.gauss_newton(vf, vjf, target, guess, opts)
+    assert used
+    np.testing.assert_array_equal(q, ref)
+    assert info.iters == rinfo.iters and info.ls_evals == rinfo.ls_evals
+    r_n = target - vf(q_n)
+    assert info.obj_first == 0.5 * float(r_n @ r_n)
+    # from the far start three iterations do not get there; from the guess they do
+    assert np.abs(q - q_star).max() < 1e-9 < np.abs(plain - q_star).max()
+
+
+def test_guess_worse_start_changes_nothing():
+    g = rng(72)
+    vf, vjf, target, q_star = _exp_model(g)
+    q_n = q_star + 0.05
+    opts = GNOptions(max_iter=5, tol_step=1e-12)
+    plain, pinfo = inversion.gauss_newton(vf, vjf, target, q_n, opts)
+    q, info, used = inversion.gauss_newton_from_guess(vf, vjf, target, q_n, q_star + 2.0, opts)
+    assert not used
+    np.testing.assert_array_equal(q, plain)
+    assert (info.iters, info.ls_evals, info.flags) == (pinfo.iters, pinfo.ls_evals, pinfo.flags)
+
+
+def test_guess_ignored_when_linearised_or_stationary():
+    g = rng(73)
+    N, r = 20, 4
+    G = g.normal(size=(N, r))
+    t = g.normal(size=N)
+    q_star = np.linalg.lstsq(G, t, rcond=None)[0]
+
+    def vf(q):
+        return G @ q
+
+    def vjf(q):
+        return G @ q, G
+
+    lin = GNOptions(max_iter=1, linearized=True)
+    q_n = q_star + 0.3
+    q, info, used = inversion.gauss_newton_from_guess(vf, vjf, t, q_n, q_star, lin)
+    ref, _ = inversion.gauss_newton(vf, vjf, t, q_n, lin)
+    assert not used
+    np.testing.assert_array_equal(q, ref)
+    # q_n already the minimiser: the guess (no better anyway) is not evaluated
+    q, info, used = inversion.gauss_newton_from_guess(vf, vjf, t, q_star, q_star + 1e-3, GNOptions())
+    assert not used and info.iters == 0
+    np.testing.assert_array_equal(q, q_star)
+
+
+def test_guess_exact_minimiser_needs_no_iteration():
+    """Latent-linear model: the exact least-squares solution as the guess is
+    accepted and Gauss-Newton stops there at once."""
+    g = rng(74)
+    N, r = 25, 3
+    G = g.normal(size=(N, r))
+    t = g.normal(size=N)
+    q_star = np.linalg.lstsq(G, t, rcond=None)[0]
+    q, info, used = inversion.gauss_newton_from_guess(lambda q: G @ q, lambda q: (G @ q, G), t,
+                                                      q_star + 1.0, q_star, GNOptions(tol_step=1e-10))
+    assert used and info.iters == 0
+    np.testing.assert_allclose(q, q_star, atol=1e-14)
