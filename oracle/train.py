@@ -7,9 +7,9 @@ error.  Readings (Sec. "Training Details" leaves them open):
 * loss = mean over the batch's B snapshots, P points and d output values of
   (g(x_i, q_b) - u_b(x_i))^2; a snapshot of a d-valued field is the vector
   of its P points' values, point-major ([P][d] flattened);
-* encoder q = E2 ELU(E1 u + c1) + c2 (two dense layers, ELU; the paper's
-  convolutional encoder is discretisation-specific and the workload fixes a
-  dense one);
+* encoder q = E2 ELU(E1 u + c1) + c2 (two dense layers, ELU; the training
+  workload fixes a dense one), or the paper's convolutional encoder
+  (``enc_kind="conv"``, readings with ``conv_lengths``);
 * Adam (Kingma & Ba) with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 and bias
   correction.
 
@@ -63,6 +63,106 @@ def mlp_backward(layers: Sequence[Layer], acts, d_out: np.ndarray, act: str = "e
     return grads, d_a
 
 
+# ---------------------------------------------------------------------------
+# Convolutional encoder (Sec. "Network Details"): a snapshot is a 1D vector
+# of its N points with d channels; 1D convolutions of kernel 6 and stride 4
+# with d output channels are applied until the length is the smallest one
+# not below 32 / d; the result is flattened to one channel, a dense layer
+# maps it to 32 values and a last dense layer to r.
+# Readings: no padding (length L -> floor((L - 6) / 4) + 1); ELU after every
+# convolution and after the 32-wide layer, the last layer linear (as the
+# decoder's output); flattening is channel-major (value (c, j) at c * L + j);
+# the width of the dense layer is a parameter (the paper's is 32).
+# ---------------------------------------------------------------------------
+
+CONV_K, CONV_S = 6, 4
+
+
+def conv_lengths(n: int, d: int) -> List[int]:
+    """Output lengths of the convolution stack for N = n points, d channels."""
+    out, L = [], n
+    while L >= CONV_K:
+        nxt = (L - CONV_K) // CONV_S + 1
+        if nxt * d < 32:
+            break
+        out.append(nxt)
+        L = nxt
+    return out
+
+
+def conv1d(x: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """y[b, o, j] = b[o] + sum_{c, k} W[o, c, k] x[b, c, 4 j + k]."""
+    L = x.shape[2]
+    n_out = (L - CONV_K) // CONV_S + 1
+    y = np.zeros((x.shape[0], W.shape[0], n_out))
+    for k in range(CONV_K):
+        xs = x[:, :, k:k + CONV_S * (n_out - 1) + 1:CONV_S]  # [B, C, n_out]: x[b, c, 4 j + k]
+        y += np.einsum("oc,bcj->boj", W[:, :, k], xs)
+    return y + b[None, :, None]
+
+
+def conv1d_backward(x: np.ndarray, W: np.ndarray, dy: np.ndarray):
+    """Reverse mode of conv1d: (dx, dW, db) for the output cotangent dy."""
+    n_out = dy.shape[2]
+    dx = np.zeros_like(x)
+    dW = np.zeros_like(W)
+    for k in range(CONV_K):
+        sl = slice(k, k + CONV_S * (n_out - 1) + 1, CONV_S)
+        dW[:, :, k] = np.einsum("boj,bcj->oc", dy, x[:, :, sl])
+        dx[:, :, sl] += np.einsum("boj,oc->bcj", dy, W[:, :, k])
+    return dx, dW, dy.sum(axis=(0, 2))
+
+
+def conv_encoder_init(gen, n: int, d: int, r: int, hidden: int = 32) -> List[Layer]:
+    """Layers [(W [d, d, 6], b [d])..., (E1 [hidden, L d], c1), (E2 [r, hidden], c2)],
+    Xavier-uniform (fan_in = d * 6 for the convolutions), biases U(-0.1, 0.1)
+    so that every bias path carries a value; float32."""
+    layers: List[Layer] = []
+    for _ in conv_lengths(n, d):
+        a = np.sqrt(6.0 / (d * CONV_K + d * CONV_K))
+        layers.append((gen.uniform(-a, a, size=(d, d, CONV_K)).astype(np.float32),
+                       gen.uniform(-0.1, 0.1, size=d).astype(np.float32)))
+    L = conv_lengths(n, d)[-1] if conv_lengths(n, d) else n
+    for n_in, n_out in ((L * d, hidden), (hidden, r)):
+        a = np.sqrt(6.0 / (n_in + n_out))
+        layers.append((gen.uniform(-a, a, size=(n_out, n_in)).astype(np.float32),
+                       gen.uniform(-0.1, 0.1, size=n_out).astype(np.float32)))
+    return layers
+
+
+def conv_encoder_forward(enc: Sequence[Layer], u: np.ndarray, d: int):
+    """q [B, r] for snapshots u [B, N d] (point-major), and the activations."""
+    enc = as_f64(enc)
+    B = u.shape[0]
+    x = np.asarray(u, dtype=np.float64).reshape(B, -1, d).transpose(0, 2, 1)  # [B, d, N]
+    elu = ACTIVATIONS["elu"][0]
+    acts = [(None, x)]
+    for W, b in enc[:-2]:
+        z = conv1d(x, W, b)
+        x = elu(z)
+        acts.append((z, x))
+    flat = x.reshape(B, -1)
+    q, dense_acts = mlp_forward(enc[-2:], flat)
+    return q, (acts, dense_acts)
+
+
+def conv_encoder_backward(enc: Sequence[Layer], state, dq: np.ndarray):
+    """Gradients [(dW, db)...] of every layer for the cotangent dq [B, r]."""
+    enc = as_f64(enc)
+    acts, dense_acts = state
+    dense_grads, d_flat = mlp_backward(enc[-2:], dense_acts, dq)
+    d1 = ACTIVATIONS["elu"][1]
+    x_last = acts[-1][1]
+    d_a = d_flat.reshape(x_last.shape)
+    grads: List[Layer] = [None] * (len(enc) - 2)
+    for l in range(len(enc) - 3, -1, -1):
+        z, _ = acts[l + 1]
+        d_z = d_a * d1(z)
+        d_a, dW, db = conv1d_backward(acts[l][1], enc[l][0], d_z)
+        grads[l] = (dW, db)
+    return grads + list(dense_grads)
+
+
 def encode(enc: Sequence[Layer], u: np.ndarray) -> np.ndarray:
     """q [B, r] for snapshots u [B, P]."""
     q, _ = mlp_forward(as_f64(enc), np.asarray(u, dtype=np.float64))
@@ -70,7 +170,7 @@ def encode(enc: Sequence[Layer], u: np.ndarray) -> np.ndarray:
 
 
 def loss_and_grads(dec: Sequence[Layer], enc: Sequence[Layer], x: np.ndarray, u: np.ndarray,
-                   dec_act: str = "elu"):
+                   dec_act: str = "elu", enc_kind: str = "dense"):
     """Reconstruction loss of eq. "loss" and its gradients.
 
     dec: decoder layers (input [x; q], m = x.shape[1]); enc: encoder layers
@@ -81,7 +181,11 @@ def loss_and_grads(dec: Sequence[Layer], enc: Sequence[Layer], x: np.ndarray, u:
     x = np.asarray(x, dtype=np.float64)
     u = np.asarray(u, dtype=np.float64)
     B, P = u.shape[0], x.shape[0]
-    q, enc_acts = mlp_forward(enc, u)
+    d_out = dec[-1][0].shape[0]
+    if enc_kind == "conv":
+        q, enc_state = conv_encoder_forward(enc, u, d_out)
+    else:
+        q, enc_acts = mlp_forward(enc, u)
     r = q.shape[1]
     # decoder at every (snapshot, point): rows ordered snapshot-major
     a0 = np.concatenate([np.tile(x, (B, 1)), np.repeat(q, P, axis=0)], axis=1)
@@ -92,7 +196,10 @@ def loss_and_grads(dec: Sequence[Layer], enc: Sequence[Layer], x: np.ndarray, u:
     dec_grads, d_a0 = mlp_backward(dec, dec_acts, d_g, dec_act)
     m = x.shape[1]
     d_q = d_a0[:, m:].reshape(B, P, r).sum(axis=1)
-    enc_grads, _ = mlp_backward(enc, enc_acts, d_q)
+    if enc_kind == "conv":
+        enc_grads = conv_encoder_backward(enc, enc_state, d_q)
+    else:
+        enc_grads, _ = mlp_backward(enc, enc_acts, d_q)
     return loss, dec_grads, enc_grads, q
 
 

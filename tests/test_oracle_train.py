@@ -163,3 +163,97 @@ def test_siren_gradients_vs_autograd_float64():
     for (W, b), (gW, gb) in zip(tdec + tenc, dg + eg):
         np.testing.assert_allclose(W.grad.numpy(), gW, rtol=1e-10, atol=1e-13)
         np.testing.assert_allclose(b.grad.numpy(), gb, rtol=1e-10, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Convolutional encoder
+# ---------------------------------------------------------------------------
+
+def test_conv_lengths_follow_the_rule():
+    # 16,384 points, one channel: 16384 -> 4095 -> 1023 -> 255 -> 63 (the
+    # next, 15, would fall below 32)
+    assert train.conv_lengths(16384, 1) == [4095, 1023, 255, 63]
+    # three channels: down to 15 (45 values), not 3 (9 values)
+    assert train.conv_lengths(16384, 3) == [4095, 1023, 255, 63, 15]
+    # 40 points: one convolution would already leave 9 < 32 values
+    assert train.conv_lengths(40, 1) == []
+
+
+def test_conv1d_against_torch():
+    torch = pytest.importorskip("torch")
+    g = rng(31)
+    x = g.normal(size=(3, 2, 53))
+    W = g.normal(size=(2, 2, 6))
+    b = g.normal(size=2)
+    y = train.conv1d(x, W, b)
+    tx = torch.tensor(x, requires_grad=True)
+    tW = torch.tensor(W, requires_grad=True)
+    tb = torch.tensor(b, requires_grad=True)
+    ty = torch.nn.functional.conv1d(tx, tW, tb, stride=4)
+    np.testing.assert_allclose(y, ty.detach().numpy(), rtol=1e-13, atol=1e-13)
+    dy = g.normal(size=y.shape)
+    ty.backward(torch.tensor(dy))
+    dx, dW, db = train.conv1d_backward(x, W, dy)
+    np.testing.assert_allclose(dx, tx.grad.numpy(), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(dW, tW.grad.numpy(), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(db, tb.grad.numpy(), rtol=1e-12, atol=1e-13)
+
+
+def _conv_problem(seed=3, B=2, P=300, m=2, r=3, w=8, depth=3, d=1):
+    g = rng(seed)
+    dec = [(W.astype(np.float64), b.astype(np.float64)) for W, b in xavier_mlp(g, m, r, d, w, depth, 0.3)]
+    enc = [(W.astype(np.float64), b.astype(np.float64)) for W, b in train.conv_encoder_init(g, P, d, r, 7)]
+    x = g.uniform(0, 1, size=(P, m))
+    u = g.uniform(-1, 1, size=(B, P * d))
+    return dec, enc, x, u
+
+
+@pytest.mark.parametrize("d", [1, 3])
+def test_conv_encoder_gradients_vs_autograd_float64(d):
+    torch = pytest.importorskip("torch")
+    dec, enc, x, u = _conv_problem(d=d)
+    loss, dg, eg, q = train.loss_and_grads(dec, enc, x, u, enc_kind="conv")
+    T = lambda a: torch.tensor(a, dtype=torch.float64, requires_grad=True)  # noqa: E731
+    tdec = [(T(W), T(b)) for W, b in dec]
+    tenc = [(T(W), T(b)) for W, b in enc]
+    F = torch.nn.functional
+    B, P = u.shape[0], x.shape[0]
+    tu = torch.tensor(u)
+    a = tu.reshape(B, P, d).permute(0, 2, 1)
+    for W, b in tenc[:-2]:
+        a = F.elu(F.conv1d(a, W, b, stride=4))
+    h = F.elu(a.reshape(B, -1) @ tenc[-2][0].T + tenc[-2][1])
+    tq = h @ tenc[-1][0].T + tenc[-1][1]
+    a0 = torch.cat([torch.tensor(x).repeat(B, 1), tq.repeat_interleave(P, dim=0)], dim=1)
+    z = a0
+    for W, b in tdec[:-1]:
+        z = F.elu(z @ W.T + b)
+    tg = z @ tdec[-1][0].T + tdec[-1][1]
+    tl = ((tg - tu.reshape(B * P, -1)) ** 2).mean()
+    tl.backward()
+    assert abs(tl.item() - loss) <= 1e-14 * max(1.0, loss)
+    np.testing.assert_allclose(tq.detach().numpy(), q, rtol=1e-13, atol=1e-15)
+    assert len(eg) == len(train.conv_lengths(P, d)) + 2
+    for (W, b), (gW, gb) in zip(tdec + tenc, dg + eg):
+        np.testing.assert_allclose(W.grad.numpy(), gW, rtol=1e-11, atol=1e-14)
+        np.testing.assert_allclose(b.grad.numpy(), gb, rtol=1e-11, atol=1e-14)
+
+
+def test_conv_encoder_gradients_vs_central_fd():
+    dec, enc, x, u = _conv_problem(seed=4, d=3)
+    loss, dg, eg, _ = train.loss_and_grads(dec, enc, x, u, enc_kind="conv")
+    g = rng(6)
+    h = 1e-6
+    for li in range(len(enc)):
+        for which in (0, 1):
+            arr = enc[li][which]
+            for _ in range(3):
+                idx = tuple(g.integers(0, s) for s in arr.shape)
+                old = arr[idx]
+                arr[idx] = old + h
+                lp = train.loss_and_grads(dec, enc, x, u, enc_kind="conv")[0]
+                arr[idx] = old - h
+                lm = train.loss_and_grads(dec, enc, x, u, enc_kind="conv")[0]
+                arr[idx] = old
+                fd = (lp - lm) / (2 * h)
+                assert abs(eg[li][which][idx] - fd) <= 1e-6 * max(1.0, abs(fd)), (li, which, idx)
