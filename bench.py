@@ -162,6 +162,23 @@ def train_leg(args, crom, torch, dev):
         t = e[0].elapsed_time(e[1]) * 1e-3 / args.train_time_steps
         out[prec] = {"ms_per_step": t * 1e3, "steps_per_s": 1.0 / t, "achieved_tflops": fl / t / 1e12,
                      "frac_of_peak": fl / t / 1e12 / PEAK[prec]}
+    # the paper's convolutional encoder (16,384 -> 4095 -> 1023 -> 255 -> 63,
+    # dense 32, r), seeded uniform parameters: the step time with it
+    from workloads import rng as _rng
+    n_conv = crom.encoder_param_count(P * w.d, 32, w.r, "conv", w.d)
+    enc_conv = _rng(args.seed + 5).uniform(-0.1, 0.1, size=n_conv).astype(np.float32)
+    decc = crom.Decoder.from_layers(w.layers, w.m, precision="bf16", device=dev)
+    Tc = crom.Trainer(decc, enc_conv, 32, xs, w.batch, enc_kind="conv")
+    for _ in range(3):
+        Tc.step(data[:w.batch], 1e-4)
+    torch.cuda.synchronize()
+    e[0].record()
+    for k in range(args.train_time_steps):
+        Tc.step(data[(k % 12) * w.batch:(k % 12 + 1) * w.batch], 1e-4)
+    e[1].record()
+    torch.cuda.synchronize()
+    out["bf16_conv_encoder"] = {"ms_per_step": e[0].elapsed_time(e[1]) / args.train_time_steps,
+                                "encoder_params": n_conv}
     if args.train_steps <= 0:
         return out, None
     dec, T = make("bf16")

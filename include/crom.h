@@ -302,6 +302,25 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
                       const crom_gn_opts* opts, crom_step_info* info, void* ws, size_t ws_bytes,
                       void* stream);
 
+/* crom_step with a second candidate starting point for the Gauss-Newton
+ * inversion (Sec. "Initial Guess for the Nonlinear Solver": where the field
+ * changes a lot over one step, a latent from an encoder of the updated field
+ * can start the solver closer to the minimum than q_n).
+ *   q_init  [n_inst][r] FP64 device, one guess per instance (NULL: crom_step);
+ *           must not alias q_next
+ * After the first evaluation at q_n, an instance whose Gauss-Newton step at
+ * q_n is computable and not negligible spends one evaluation round on its
+ * guess (the value and J there); a strictly smaller objective makes the
+ * guess the start, otherwise the line search from q_n proceeds exactly as in
+ * crom_step (the result is then bit-identical, with one more round).  The
+ * linearised variant ignores the guess.  info.obj_first stays the objective
+ * at q_n; an accepted guess is not counted in info.iters. */
+crom_status crom_step_guess(const crom_net* net, const crom_pde* pde, int32_t n_inst,
+                            const int64_t* offsets, int64_t total_samples, const float* y,
+                            const uint8_t* clamp, const double* q_prev, const double* q_n,
+                            const double* q_init, double* q_next, const crom_gn_opts* opts,
+                            crom_step_info* info, void* ws, size_t ws_bytes, void* stream);
+
 /* Device pointer to the FP64 targets f_{n+1} [total_samples][d] inside a
  * workspace used by crom_step (NULL on invalid arguments). */
 const double* crom_step_targets(const crom_net* net, int32_t n_inst, int64_t total_samples,
@@ -352,16 +371,31 @@ crom_status crom_fd_heat(int32_t dim, const int64_t* shape, int64_t n_grid, cons
  * not used (crom_train_step refreshes them when given a buffer).
  * ------------------------------------------------------------------------- */
 
-/* Encoder description: params FP32, natural layout
- *   E1 [hidden][n_in], c1 [hidden], E2 [r][hidden], c2 [r],
- * with n_in = P * d (a snapshot [P][d], point-major) and r = the net's r. */
+/* Encoder description: n_in = P * d (a snapshot [P][d], point-major), r =
+ * the net's r, params FP32.
+ * CROM_ENC_DENSE: q = E2 ELU(E1 u + c1) + c2, params
+ *   E1 [hidden][n_in], c1 [hidden], E2 [r][hidden], c2 [r].
+ * CROM_ENC_CONV (Sec. "Network Details"): the snapshot as a 1D vector of
+ *   P points with d channels; 1D convolutions of kernel 6 and stride 4 with
+ *   d output channels (no padding, L -> (L - 6) / 4 + 1, ELU) applied while
+ *   the result keeps at least 32 values (L d >= 32); the last one's output
+ *   flattened channel-major (value (c, j) at c L + j); then
+ *   h = ELU(E1 . + c1) of `hidden` values (the paper's 32) and
+ *   q = E2 h + c2.  Params: per convolution W [d][d][6], b [d]; then
+ *   E1 [hidden][L d], c1 [hidden], E2 [r][hidden], c2 [r].  Needs room for
+ *   one convolution.  Its arithmetic is FP32 in every precision mode. */
+enum { CROM_ENC_DENSE = 0, CROM_ENC_CONV = 1 };
 typedef struct {
-  int32_t n_in, hidden, r, _pad;
+  int32_t n_in, hidden, r, kind;
   float* params;
 } crom_encoder;
 
-/* Number of FP32 values in an encoder's params (0 on invalid sizes). */
+/* Number of FP32 values in a dense encoder's params (0 on invalid sizes). */
 size_t crom_encoder_param_count(int32_t n_in, int32_t hidden, int32_t r);
+
+/* Number of FP32 values in a convolutional encoder's params for P points
+ * with d channels (0 on invalid sizes or when no convolution fits). */
+size_t crom_conv_encoder_param_count(int64_t P, int32_t d, int32_t hidden, int32_t r);
 
 /* Workspace bytes for crom_train_grads / crom_train_step with B snapshots
  * (host out-parameter). */
@@ -404,6 +438,21 @@ crom_status crom_encode_workspace(const crom_net* net, const crom_encoder* enc, 
                                   size_t* bytes);
 crom_status crom_encode(const crom_net* net, const crom_encoder* enc, const float* u, int32_t B,
                         float* q, void* ws, size_t ws_bytes, void* stream);
+
+/* Encoder-based initial guess for the heat step (Sec. "Initial Guess for
+ * the Nonlinear Solver"): the updated field at every node,
+ * f_i = g(x, q_n,i) + dt nu_i Laplacian g(x, q_n,i), FP32, passed through the
+ * training encoder (crom_encode's arithmetic), as FP64 latents for
+ * crom_step_guess.
+ *   nodes [P][m] FP32, the full node set the encoder was trained on (its
+ *   n_in = P * d); q_n [n_inst][r] FP64; nu [n_inst] FP64 (device);
+ *   q_guess [n_inst][r] FP64 out; ws: crom_heat_guess_workspace bytes.
+ * Needs d == 1 and m <= 2. */
+crom_status crom_heat_guess_workspace(const crom_net* net, const crom_encoder* enc, int32_t n_inst, int64_t P,
+                                      size_t* bytes);
+crom_status crom_heat_guess(const crom_net* net, const crom_encoder* enc, const float* nodes, int64_t P,
+                            int32_t n_inst, const double* q_n, const double* nu, double dt, double* q_guess,
+                            void* ws, size_t ws_bytes, void* stream);
 
 /* Vector-Jacobian product of the decoder (the backward of crom_decode over
  * B latents): with G[b][p][o] = g(x_p, q_b)_o and a cotangent dg [B][P][d],

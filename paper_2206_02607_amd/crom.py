@@ -50,7 +50,7 @@ class CromGNOpts(Structure):
 
 
 class CromEncoder(Structure):
-    _fields_ = [("n_in", c_int32), ("hidden", c_int32), ("r", c_int32), ("_pad", c_int32),
+    _fields_ = [("n_in", c_int32), ("hidden", c_int32), ("r", c_int32), ("kind", c_int32),
                 ("params", c_void_p)]
 
 
@@ -138,10 +138,20 @@ def lib():
         L.crom_fe_stencil.argtypes = [c_int64, c_int64, c_void_p, c_int32, c_void_p, c_void_p,
                                       POINTER(c_int64), POINTER(c_int64), POINTER(c_int64), c_void_p,
                                       c_void_p, c_void_p, c_void_p, c_void_p]
+        L.crom_conv_encoder_param_count.restype = c_size_t
+        L.crom_conv_encoder_param_count.argtypes = [c_int64, c_int32, c_int32, c_int32]
+        L.crom_step_guess.argtypes = [POINTER(CromNet), POINTER(CromPDE), c_int32, c_void_p, c_int64,
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      POINTER(CromGNOpts), c_void_p, c_void_p, c_size_t, c_void_p]
+        L.crom_heat_guess_workspace.argtypes = [POINTER(CromNet), POINTER(CromEncoder), c_int32, c_int64,
+                                                POINTER(c_size_t)]
+        L.crom_heat_guess.argtypes = [POINTER(CromNet), POINTER(CromEncoder), c_void_p, c_int64, c_int32,
+                                      c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_size_t, c_void_p]
         L.crom_kernel_timer.argtypes = [c_int32]
         L.crom_kernel_timer_read.argtypes = [POINTER(c_double), POINTER(c_int64)]
         for name in ("crom_sampling_residual", "crom_sampling_candidates", "crom_sampling_workspace",
-                     "crom_robust_sampling", "crom_kernel_timer", "crom_kernel_timer_read", "crom_fe_stencil"):
+                     "crom_robust_sampling", "crom_kernel_timer", "crom_kernel_timer_read", "crom_fe_stencil", "crom_step_guess", "crom_heat_guess_workspace",
+                     "crom_heat_guess"):
             getattr(L, name).restype = c_int32
         for name in ("crom_net_pack", "crom_decode", "crom_decode_jac", "crom_decode_jac_x",
                      "crom_decode_jac_q", "crom_step_workspace", "crom_step", "crom_fd_heat",
@@ -312,7 +322,15 @@ def decode_vjp(dec: "Decoder", x, q, dg):
     return gp, gq
 
 
-def encoder_param_count(n_in: int, hidden: int, r: int) -> int:
+ENC_DENSE, ENC_CONV = 0, 1
+_ENC_NAMES = {"dense": ENC_DENSE, "conv": ENC_CONV}
+
+
+def encoder_param_count(n_in: int, hidden: int, r: int, kind: str = "dense", d: int = 1) -> int:
+    """FP32 parameters of an encoder: dense (n_in inputs) or convolutional
+    (n_in = P d values of P points with d channels)."""
+    if kind == "conv":
+        return int(lib().crom_conv_encoder_param_count(n_in // d, d, hidden, r))
     return int(lib().crom_encoder_param_count(n_in, hidden, r))
 
 
@@ -321,16 +339,18 @@ class Trainer:
 
     dec: the Decoder whose FP32 params are the master copy (updated in place,
     packed weights refreshed after every step); enc_params: the encoder's FP32
-    parameters [E1, c1, E2, c2] (updated in place); x [P, m] the snapshot
-    points; B the batch size."""
+    parameters in the layout of its kind (dense [E1, c1, E2, c2]; "conv" the
+    convolutions' [W, b] then [E1, c1, E2, c2]; updated in place); x [P, m]
+    the snapshot points; B the batch size."""
 
-    def __init__(self, dec: "Decoder", enc_params, hidden: int, x, B: int):
+    def __init__(self, dec: "Decoder", enc_params, hidden: int, x, B: int, enc_kind: str = "dense"):
         torch = _torch()
         self.dec, self.hidden, self.B = dec, hidden, B
         self.x = x.to(dtype=torch.float32).contiguous()
         self.P = self.x.shape[0]
         self.n_in = self.P * dec.d
-        ne = encoder_param_count(self.n_in, hidden, dec.r)
+        self.enc_kind = _ENC_NAMES[enc_kind]
+        ne = encoder_param_count(self.n_in, hidden, dec.r, enc_kind, dec.d)
         if isinstance(enc_params, np.ndarray):
             enc_params = torch.from_numpy(np.ascontiguousarray(enc_params, dtype=np.float32))
         self.enc_params = enc_params.to(device=self.x.device, dtype=torch.float32).contiguous()
@@ -353,7 +373,7 @@ class Trainer:
         self.t = 0
 
     def _enc(self) -> CromEncoder:
-        return CromEncoder(self.n_in, self.hidden, self.dec.r, 0, self.enc_params.data_ptr())
+        return CromEncoder(self.n_in, self.hidden, self.dec.r, self.enc_kind, self.enc_params.data_ptr())
 
     def _u(self, u):
         torch = _torch()
@@ -403,6 +423,30 @@ class Trainer:
         _check(lib().crom_encode(ctypes.byref(net), ctypes.byref(enc), _ptr(u), n, _ptr(q), _ptr(ws),
                                  nbytes.value, _stream()), "crom_encode")
         return q
+
+
+def heat_guess(dec: "Decoder", enc_params, hidden: int, nodes, q_n, nu, dt: float, enc_kind: str = "dense"):
+    """Encoder-based initial guesses [n, r] FP64 for the heat step
+    (crom_heat_guess): the encoder (FP32 params [E1, c1, E2, c2], n_in =
+    P * d) applied to g + dt nu Laplacian g over all nodes [P, m] for each
+    latent q_n [n, r]; nu one value or one per instance."""
+    torch = _torch()
+    dev = dec.params.device
+    nodes = nodes.to(device=dev, dtype=torch.float32).contiguous()
+    q_n = torch.as_tensor(q_n, dtype=torch.float64, device=dev).reshape(-1, dec.r).contiguous()
+    n, P = q_n.shape[0], nodes.shape[0]
+    nu = torch.as_tensor(nu, dtype=torch.float64, device=dev).reshape(-1).expand(n).contiguous()
+    enc_params = torch.as_tensor(enc_params, dtype=torch.float32, device=dev).contiguous()
+    enc = CromEncoder(P * dec.d, hidden, dec.r, _ENC_NAMES[enc_kind], enc_params.data_ptr())
+    net = dec._net()
+    nbytes = c_size_t(0)
+    _check(lib().crom_heat_guess_workspace(ctypes.byref(net), ctypes.byref(enc), n, P, ctypes.byref(nbytes)),
+           "crom_heat_guess_workspace")
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    out = torch.empty(n, dec.r, dtype=torch.float64, device=dev)
+    _check(lib().crom_heat_guess(ctypes.byref(net), ctypes.byref(enc), _ptr(nodes), P, n, _ptr(q_n), _ptr(nu),
+                                 float(dt), _ptr(out), _ptr(ws), nbytes.value, _stream()), "crom_heat_guess")
+    return out
 
 
 def adam_step(params, grad, m, v, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
@@ -506,11 +550,12 @@ class Stepper:
         self.info_buf = torch.zeros(self.n_inst * INFO_DTYPE.itemsize, dtype=torch.uint8,
                                     device=dec.params.device)
 
-    def step(self, q_n, coef, dt: float, opts: GNOptions = GNOptions(), q_next=None, q_prev=None):
+    def step(self, q_n, coef, dt: float, opts: GNOptions = GNOptions(), q_next=None, q_prev=None, q_init=None):
         """One latent step.  coef: heat, nu (one value or one per instance);
         neo-Hookean and corotated, (lam, mu, rho0, Bx, By, Bz) (one row or one
         per instance).  q_prev: the elastic kinds, the previous latents (None:
-        at rest)."""
+        at rest).  q_init: a second candidate start per instance
+        (crom_step_guess; None: crom_step)."""
         torch = _torch()
         dev = self.dec.params.device
         q_n = q_n.to(device=dev, dtype=torch.float64).contiguous()
@@ -526,10 +571,18 @@ class Stepper:
         pde = CromPDE(self.kind, 0, float(dt), coef.data_ptr(), ctypes.addressof(fm) if fm is not None else None)
         o = opts.c_struct()
         self._coef, self._q_prev = coef, q_prev  # keep alive until the stream has consumed them
-        _check(lib().crom_step(ctypes.byref(net), ctypes.byref(pde), self.n_inst, _ptr(self.offsets),
-                               self.total, _ptr(self.y), _ptr(self.clamp), _ptr(q_prev), _ptr(q_n),
-                               _ptr(q_next), ctypes.byref(o), self.info_buf.data_ptr(), self.ws_ptr,
-                               self.ws_bytes, _stream()), "crom_step")
+        if q_init is None:
+            _check(lib().crom_step(ctypes.byref(net), ctypes.byref(pde), self.n_inst, _ptr(self.offsets),
+                                   self.total, _ptr(self.y), _ptr(self.clamp), _ptr(q_prev), _ptr(q_n),
+                                   _ptr(q_next), ctypes.byref(o), self.info_buf.data_ptr(), self.ws_ptr,
+                                   self.ws_bytes, _stream()), "crom_step")
+            return q_next
+        q_init = q_init.to(device=dev, dtype=torch.float64).contiguous()
+        self._q_init = q_init
+        _check(lib().crom_step_guess(ctypes.byref(net), ctypes.byref(pde), self.n_inst, _ptr(self.offsets),
+                                     self.total, _ptr(self.y), _ptr(self.clamp), _ptr(q_prev), _ptr(q_n),
+                                     _ptr(q_init), _ptr(q_next), ctypes.byref(o), self.info_buf.data_ptr(),
+                                     self.ws_ptr, self.ws_bytes, _stream()), "crom_step_guess")
         return q_next
 
     def info(self) -> np.ndarray:

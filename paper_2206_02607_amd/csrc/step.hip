@@ -93,7 +93,14 @@ constexpr int RMAX = 16;
 #endif
 constexpr int TV = CROM_TRIALS;
 constexpr int MAXP = 256;    // bound on the phases of one step
-enum { PH_INIT = 0, PH_TRIALS = 1, PH_REJAC = 2, PH_DONE = 3 };
+// Instance phases: the first evaluation at q_n; line-search trials along a
+// direction; re-linearisation at an accepted iterate; the evaluation of an
+// initial guess (a second candidate start); finished.
+enum { PH_INIT = 0, PH_TRIALS = 1, PH_REJAC = 2, PH_DONE = 3, PH_GUESS = 4 };
+// phases whose rounds evaluate the trial latents (and J at the first)
+__host__ __device__ constexpr bool evaluates_trials(int ph) {
+  return ph == PH_TRIALS || ph == PH_REJAC || ph == PH_GUESS;
+}
 
 struct GNState {
   double q[RMAX];       // accepted iterate
@@ -193,6 +200,7 @@ struct StepArgs {
   double dt;
   const double* q_prev;  // elastic: latent of the previous step (NULL: at rest)
   const double* q_n;
+  const double* q_init;  // NULL or a second candidate start per instance
   double* q_next;
   crom_step_info* info;
   char* ws;
@@ -473,7 +481,9 @@ __device__ void jets_pass_batch(const StepArgs& a, char* lds, const float* par, 
     const float v = res[(oo * NT + c) * PT + i];
     float* row = jets + (first + i) * a.L.nj;
     const int k = C::kind(c);
-    if (k == CK_VAL) row[J.val(oo)] = v;
+    if (k == CK_VAL) {
+      if (blockIdx.y == 0) row[J.val(oo)] = v;  // every chunk computes it alike
+    }
     else if (k == CK_XT) row[J.grad(oo, c - C::X0)] = v;
     else if (k == CK_HESS) row[J.hess(oo, C::HB + (c - C::D0))] = v;
     else if (k == CK_QT) row[J.jac(oo, qb + (c - C::Q0))] = v;
@@ -490,7 +500,9 @@ __global__ __launch_bounds__(NW * 64) void jets_pass_kernel(StepArgs a, int qb) 
   float* par = reinterpret_cast<float*>(lds + E::LDS_BYTES);
   E::PC::load(par, a.params, a.pi, a.depth, NW * 64);
   __syncthreads();
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) jets_pass_batch<S, C, NW, PREC>(a, lds, par, blk, qb);
+  // blockIdx.y picks the chunk of latent directions (one launch for all)
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x)
+    jets_pass_batch<S, C, NW, PREC>(a, lds, par, blk, qb + (int)blockIdx.y * C::NQ);
 }
 
 // FP64 update at one sample: rho_0 = u_{n+1} - u(q_n) and the target.
@@ -694,8 +706,9 @@ __device__ void tet_force(const double X[4][3], const double u[4][3], int corner
 }
 
 // FP64 update at the samples from finite-element forces: one wave per
-// sample, its lanes over the sample's incident tetrahedra; the sample's
-// force and incident volume are summed across the wave in a fixed order.
+// sample (a workgroup takes FE_WAVES consecutive samples of a batch), its
+// lanes over the sample's incident tetrahedra; the sample's force and
+// incident volume are summed across the wave in a fixed order.
 //   m = rho0 (incident volume) / 4,  v_n = (du/dq)(q_n - q_prev)/dt,
 //   v+ = v_n + dt (f / m + B),  rho_0 = dt v+ (a clamped sample: -u).
 // Invalid stencil data (a ring or incidence range that is not a CSR range,
@@ -703,13 +716,17 @@ __device__ void tet_force(const double X[4][3], const double u[4][3], int corner
 // corner outside 0..3, a sample without tetrahedra) gives NaN, which the
 // solve reports as a non-finite instance.
 constexpr int FE_WAVES = 4;
+static_assert(PT % FE_WAVES == 0, "whole batches");
 template <int R>
 __global__ __launch_bounds__(FE_WAVES * 64) void fe_targets_kernel(StepArgs a) {
   const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
   const JetsLayout JL{3, 3, R, 6};
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double qnan = __builtin_nan("");
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+  constexpr int SUB = PT / FE_WAVES;  // workgroups per batch
+  for (int64_t gi = blockIdx.x; gi < nblk * SUB; gi += gridDim.x) {
+    const int64_t blk = gi / SUB;
+    const int i = (int)(gi % SUB) * FE_WAVES + wave;
     const int inst = wsp<int32_t>(a, a.L.blk_inst)[blk];
     const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
     const int64_t rem = a.offsets[inst + 1] - first;
@@ -718,7 +735,7 @@ __global__ __launch_bounds__(FE_WAVES * 64) void fe_targets_kernel(StepArgs a) {
     const bool ring_ok = rlo >= 0 && rhi > rlo && rhi <= a.fe.n_ring && rhi - rlo <= a.fe.max_ring;
     const double* cf = a.coef + (int64_t)inst * 6;
     const double lam = cf[0], mu = cf[1], rho = cf[2];
-    for (int i = wave; i < n_valid; i += FE_WAVES) {
+    if (i < n_valid) {
       const int64_t p = first + i;
       const int64_t elo = a.fe.inc_offsets[p], ehi = a.fe.inc_offsets[p + 1];
       bool ok = ring_ok && elo >= 0 && ehi > elo && ehi <= a.fe.n_inc;
@@ -1019,10 +1036,26 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
     double qk = lane < R ? st->q[lane] : 0.0;
     double dk = lane < R ? st->delta[lane] : 0.0;
     bool done = false, newdir = false;
-    int settrials = 0;  // 1: trials q + alpha_t delta; 2: every trial at q (re-linearise)
+    // 1: trials q + alpha_t delta; 2: every trial at q (re-linearise);
+    // 3: every trial at the initial guess
+    int settrials = 0;
     if (ph == PH_INIT) {
       obj_first = obj_last = phi = phit[0];
       newdir = true;
+    } else if (ph == PH_GUESS) {
+      // The round evaluated the guess (trial 0, with J there).  A strictly
+      // smaller objective makes it the start: the direction is formed from
+      // this round's partials.  Otherwise the line search along the
+      // direction found at q_n (kept in the state) goes ahead.
+      if (isfinite(phit[0]) && phit[0] < phi) {
+        qk = lane < R ? st->qt[0][lane] : 0.0;
+        phi = phit[0];
+        obj_last = phi;
+        newdir = true;
+      } else {
+        ph = PH_TRIALS;
+        settrials = 1;
+      }
     } else if (ph == PH_TRIALS) {
       int acc = -1;
       for (int t = 0; t < TV; ++t) {
@@ -1110,6 +1143,10 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
             }
             ph = PH_TRIALS;
             settrials = 1;
+            if (phase == PH_INIT && a.q_init) {  // evaluate the guess before any trial
+              ph = PH_GUESS;
+              settrials = 3;
+            }
           }
         }
       }
@@ -1127,7 +1164,12 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
     }
     // trial latents: lane t * R + k (TV * R <= 64)
     const double q_k = __shfl(qk, lane % R), d_k = __shfl(dk, lane % R);  // all lanes shuffle
-    if (!done && settrials && lane < TV * R) {
+    if (!done && settrials == 3 && lane < TV * R) {
+      const int t = lane / R, k = lane % R;
+      const double g = a.q_init[(int64_t)inst * R + k];
+      st->qt[t][k] = g;
+      st->qd[t][k] = g - qn0[k];
+    } else if (!done && settrials && lane < TV * R) {
       const int t = lane / R, k = lane % R;
       const double al = settrials == 1 ? alpha[t] : 0.0;
       st->qt[t][k] = q_k + al * d_k;
@@ -1255,7 +1297,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
           ph = s_ph;
           __syncthreads();
         }
-        if (ph != PH_TRIALS && ph != PH_REJAC) continue;
+        if (!evaluates_trials(ph)) continue;
         if constexpr (KIND == PK_HEAT)
           eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, (p == 1 && first) ? 40 : -1, first);
         else
@@ -1449,7 +1491,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       __syncthreads();
       const int ph = s_ph;
       __syncthreads();
-      if (ph != PH_TRIALS && ph != PH_REJAC) continue;
+      if (!evaluates_trials(ph)) continue;
       eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, -1, false);
     }
   }
@@ -1465,7 +1507,7 @@ __global__ __launch_bounds__(NTH) void gn_solve_kernel(StepArgs a, int p, int is
   if (threadIdx.x == 0) s_ph = ld_c(&wsp<GNState>(a, a.L.state)[inst].phase);
   __syncthreads();
   const int ph = s_ph;
-  const bool active = p == 0 ? ph == PH_INIT : (ph == PH_TRIALS || ph == PH_REJAC);
+  const bool active = p == 0 ? ph == PH_INIT : evaluates_trials(ph);
   if (!active) return;
   solve_instance<R>(a, lds, inst, p, is_last != 0);
 }
@@ -1499,7 +1541,7 @@ static crom_status launch_gn_rounds(StepArgs a, int max_rounds, hipStream_t st) 
 
 // One engine pass of the elastic preparation over every batch.
 template <class S, class C, int NW, int PREC>
-static crom_status launch_jets_pass(const StepArgs& a, int qb, hipStream_t st) {
+static crom_status launch_jets_pass(const StepArgs& a, int qb, hipStream_t st, int chunks = 1) {
   using E = Engine<S, C, 1, NW, PREC, 0>;
   const int lds_bytes = E::LDS_BYTES + E::PC::bytes(a.depth);
   if (lds_bytes > LDS_MAX) return fail(CROM_ERR_UNSUPPORTED, "network too deep for the LDS");
@@ -1508,7 +1550,7 @@ static crom_status launch_jets_pass(const StepArgs& a, int qb, hipStream_t st) {
   if (s != CROM_OK) return s;
   int64_t g = a.L.nblk_max;
   if (g > 65535) g = 65535;
-  hipLaunchKernelGGL(k, dim3((unsigned)g), dim3(NW * 64), lds_bytes, st, a, qb);
+  hipLaunchKernelGGL(k, dim3((unsigned)g, (unsigned)chunks), dim3(NW * 64), lds_bytes, st, a, qb);
   return hip_check(hipGetLastError(), "jets pass launch");
 }
 
@@ -1524,10 +1566,9 @@ static crom_status elastic_prepare(const StepArgs& a, hipStream_t st) {
     if (s != CROM_OK) return s;
     return elastic_prepare<S, NW, PREC, HB + HC>(a, st);
   } else {
-    for (int qb = 0; qb < S::R; qb += QC) {
-      crom_status s = launch_jets_pass<S, Cols<S::M, S::R, 1, 0, false, D2_NONE, QC>, NW, PREC>(a, qb, st);
-      if (s != CROM_OK) return s;
-    }
+    static_assert(S::R % QC == 0, "whole latent chunks");
+    crom_status s = launch_jets_pass<S, Cols<S::M, S::R, 1, 0, false, D2_NONE, QC>, NW, PREC>(a, 0, st, S::R / QC);
+    if (s != CROM_OK) return s;
     int64_t g = a.L.nblk_max;
     if (g > 65535) g = 65535;
     hipLaunchKernelGGL(elastic_targets_kernel<S::R>, dim3((unsigned)g), dim3(64), 0, st, a);
@@ -1553,11 +1594,10 @@ static crom_status fe_prepare(const StepArgs& a, hipStream_t st) {
     s = hip_check(hipGetLastError(), "ring decode launch");
     if (s != CROM_OK) return s;
   }
-  for (int qb = 0; qb < S::R; qb += QC) {
-    crom_status s = launch_jets_pass<S, Cols<S::M, S::R, 1, 0, false, D2_NONE, QC>, NW, PREC>(a, qb, st);
-    if (s != CROM_OK) return s;
-  }
-  int64_t g = a.L.nblk_max;
+  static_assert(S::R % QC == 0, "whole latent chunks");
+  crom_status s = launch_jets_pass<S, Cols<S::M, S::R, 1, 0, false, D2_NONE, QC>, NW, PREC>(a, 0, st, S::R / QC);
+  if (s != CROM_OK) return s;
+  int64_t g = a.L.nblk_max * (PT / FE_WAVES);
   if (g > 65535) g = 65535;
   hipLaunchKernelGGL(fe_targets_kernel<S::R>, dim3((unsigned)g), dim3(FE_WAVES * 64), 0, st, a);
   return hip_check(hipGetLastError(), "finite-element targets launch");
@@ -1697,11 +1737,11 @@ const double* crom_step_increments(const crom_net* net, int32_t n_inst, int64_t 
   return reinterpret_cast<const double*>(static_cast<const char*>(ws) + L.rho0);
 }
 
-crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
-                      const int64_t* offsets, int64_t total_samples, const float* y,
-                      const uint8_t* clamp, const double* q_prev, const double* q_n, double* q_next,
-                      const crom_gn_opts* opts, crom_step_info* info, void* ws, size_t ws_bytes,
-                      void* stream) {
+crom_status crom_step_guess(const crom_net* net, const crom_pde* pde, int32_t n_inst,
+                            const int64_t* offsets, int64_t total_samples, const float* y,
+                            const uint8_t* clamp, const double* q_prev, const double* q_n,
+                            const double* q_init, double* q_next, const crom_gn_opts* opts,
+                            crom_step_info* info, void* ws, size_t ws_bytes, void* stream) {
   crom_status s = check_net(net, true);
   if (s != CROM_OK) return s;
   if (!pde || !opts) return fail(CROM_ERR_INVALID_ARG, "pde and opts are required");
@@ -1728,6 +1768,7 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
     return fail(CROM_ERR_INVALID_ARG, "offsets, q_n, q_next, info and pde->coef are required");
   if (total_samples > 0 && !y) return fail(CROM_ERR_INVALID_ARG, "y is NULL");
   if (q_next == q_n) return fail(CROM_ERR_INVALID_ARG, "q_next must not alias q_n");
+  if (q_init && q_init == q_next) return fail(CROM_ERR_INVALID_ARG, "q_next must not alias q_init");
   if (opts->max_iter < 1 || opts->ls_max < 0 || opts->max_rounds < 0 || !(opts->tol_step >= 0.0) ||
       !(opts->ls_shrink > 0.0 && opts->ls_shrink < 1.0) || !(opts->armijo_c >= 0.0))
     return fail(CROM_ERR_INVALID_ARG, "gn opts out of range");
@@ -1763,6 +1804,7 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
     a.fe.on = 1;
   }
   a.q_n = q_n;
+  a.q_init = q_init;
   a.q_next = q_next;
   a.info = info;
   a.ws = static_cast<char*>(ws);
@@ -1776,7 +1818,7 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
   a.trace = g_step_trace;
   // Enough rounds for max_iter accepted steps, each after the longest line
   // search (ceil((ls_max + 1) / TV) rounds) and one re-linearisation.
-  const int64_t worst = (int64_t)opts->max_iter * (1 + (opts->ls_max + TV) / TV) + 1;
+  const int64_t worst = (int64_t)opts->max_iter * (1 + (opts->ls_max + TV) / TV) + 1 + (q_init ? 1 : 0);
   int64_t rounds = opts->linearized ? 0 : (opts->max_rounds > 0 ? opts->max_rounds : worst);
   if (rounds > MAXP) rounds = MAXP;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1793,6 +1835,15 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
     case SHAPE_3D: return step_prec_elastic<Shape<256, 3, 16, 3>, CROM_ELASTIC_NW>(net->precision, a, (int)rounds, st);
     default: return fail(CROM_ERR_UNSUPPORTED, "shape");
   }
+}
+
+crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
+                      const int64_t* offsets, int64_t total_samples, const float* y,
+                      const uint8_t* clamp, const double* q_prev, const double* q_n, double* q_next,
+                      const crom_gn_opts* opts, crom_step_info* info, void* ws, size_t ws_bytes,
+                      void* stream) {
+  return crom_step_guess(net, pde, n_inst, offsets, total_samples, y, clamp, q_prev, q_n, nullptr, q_next, opts,
+                         info, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -711,6 +711,273 @@ static crom_status encoder_bwd(const crom_encoder* e, int B, const float* dq, fl
   return hip_check(hipGetLastError(), "encoder backward");
 }
 
+// ---------------------------------------------------------------------------
+// Convolutional encoder (Sec. "Network Details"): the snapshot as a 1D vector
+// of its P points with d channels; 1D convolutions (kernel 6, stride 4, d
+// output channels, no padding, ELU) until the length is the smallest one not
+// below 32 / d; flattened channel-major; a dense layer of `hidden` values
+// (ELU) and a linear dense layer to r.  FP32 storage, FP32 products inside a
+// convolution window or a dense row, FP64 sums over the batch and over
+// positions for the weight gradients (fixed order: deterministic).
+// Parameters, FP32, in order: per convolution W [d][d][6], b [d]; then
+// E1 [hidden][L d], c1 [hidden], E2 [r][hidden], c2 [r].
+// ---------------------------------------------------------------------------
+constexpr int CONV_K = 6, CONV_S = 4, CONV_MAXL = 16;
+
+struct ConvShape {
+  int d, nl, hidden, r;
+  int64_t len[CONV_MAXL + 1];  // len[0] = P
+  int64_t w[CONV_MAXL], b[CONV_MAXL], e1, c1, e2, c2, count;
+};
+
+static ConvShape conv_shape(int64_t P, int d, int hidden, int r) {
+  ConvShape c{};
+  c.d = d;
+  c.hidden = hidden;
+  c.r = r;
+  c.len[0] = P;
+  int64_t L = P;
+  while (L >= CONV_K && c.nl < CONV_MAXL) {
+    const int64_t nxt = (L - CONV_K) / CONV_S + 1;
+    if (nxt * d < 32) break;
+    c.len[++c.nl] = nxt;
+    L = nxt;
+  }
+  int64_t o = 0;
+  for (int l = 0; l < c.nl; ++l) {
+    c.w[l] = o;
+    o += (int64_t)d * d * CONV_K;
+    c.b[l] = o;
+    o += d;
+  }
+  c.e1 = o;
+  o += (int64_t)hidden * L * d;
+  c.c1 = o;
+  o += hidden;
+  c.e2 = o;
+  o += (int64_t)r * hidden;
+  c.c2 = o;
+  o += r;
+  c.count = o;
+  return c;
+}
+
+__device__ __forceinline__ float elu_f(float z) { return z > 0.0f ? z : expm1f(z); }
+__device__ __forceinline__ float delu_from_act(float a) { return a > 0.0f ? 1.0f : a + 1.0f; }
+
+// y[b][o][j] = ELU(bias[o] + sum_{c,k} W[o][c][k] x(b, c, 4 j + k)), with
+// x(b, c, i) = x[b * xb + c * xc + i * xi].
+__global__ __launch_bounds__(256) void conv_fwd_kernel(const float* __restrict__ x, int64_t xb, int64_t xc,
+                                                      int64_t xi, const float* __restrict__ W,
+                                                      const float* __restrict__ bias, int B, int d, int64_t Lo,
+                                                      float* __restrict__ y) {
+  const int64_t total = (int64_t)B * d * Lo;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e % Lo, bo = e / Lo;
+    const int o = (int)(bo % d), b = (int)(bo / d);
+    float s = bias[o];
+    for (int c = 0; c < d; ++c) {
+      const float* xp = x + b * xb + c * xc + (CONV_S * j) * xi;
+      const float* wp = W + ((int64_t)o * d + c) * CONV_K;
+#pragma unroll
+      for (int k = 0; k < CONV_K; ++k) s += wp[k] * xp[k * xi];
+    }
+    y[e] = elu_f(s);
+  }
+}
+
+// out[b][o] = act(bias[o] + sum_i W[o][i] in[b][i])  (act: ELU or none)
+__global__ __launch_bounds__(256) void dense_fwd_kernel(const float* __restrict__ in, const float* __restrict__ W,
+                                                       const float* __restrict__ bias, int B, int64_t n_in,
+                                                       int n_out, int elu, float* __restrict__ out) {
+  const int64_t total = (int64_t)B * n_out;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int o = (int)(e % n_out);
+    const int64_t b = e / n_out;
+    float s = bias[o];
+    for (int64_t i = 0; i < n_in; ++i) s += W[o * n_in + i] * in[b * n_in + i];
+    out[e] = elu ? elu_f(s) : s;
+  }
+}
+
+// dW[o][i] = sum_b dy[b][o] x[b][i], db[o] = sum_b dy[b][o] (FP64 sums over b in order)
+__global__ __launch_bounds__(256) void dense_wgrad_kernel(const float* __restrict__ dy, const float* __restrict__ x,
+                                                         int B, int64_t n_in, int n_out, float* __restrict__ dW,
+                                                         float* __restrict__ db) {
+  const int64_t total = (int64_t)n_out * n_in + n_out;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    if (e < (int64_t)n_out * n_in) {
+      const int64_t o = e / n_in, i = e % n_in;
+      for (int b = 0; b < B; ++b) s += (double)dy[(int64_t)b * n_out + o] * (double)x[(int64_t)b * n_in + i];
+      dW[e] = (float)s;
+    } else {
+      const int64_t o = e - (int64_t)n_out * n_in;
+      for (int b = 0; b < B; ++b) s += (double)dy[(int64_t)b * n_out + o];
+      db[o] = (float)s;
+    }
+  }
+}
+
+// dx[b][i] = (sum_o dy[b][o] W[o][i]) * ELU'(a[b][i])  (a NULL: no gate)
+__global__ __launch_bounds__(256) void dense_dx_kernel(const float* __restrict__ dy, const float* __restrict__ W,
+                                                      const float* __restrict__ a, int B, int64_t n_in, int n_out,
+                                                      float* __restrict__ dx) {
+  const int64_t total = (int64_t)B * n_in;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % n_in, b = e / n_in;
+    float s = 0.0f;
+    for (int o = 0; o < n_out; ++o) s += dy[b * n_out + o] * W[(int64_t)o * n_in + i];
+    dx[e] = a ? s * delu_from_act(a[e]) : s;
+  }
+}
+
+// Weight and bias gradients of one convolution: block e < d*d*6 takes
+// W[o][c][k] = sum_{b,j} dz[b][o][j] x(b, c, 4 j + k), block d*d*6 + o the
+// bias sum_{b,j} dz[b][o][j]; each thread sums a fixed stride of the (b, j)
+// pairs in FP64, then a fixed-order tree in LDS.
+constexpr int CONV_RED = 256;
+__global__ __launch_bounds__(CONV_RED) void conv_wgrad_kernel(const float* __restrict__ dz, const float* __restrict__ x,
+                                                             int64_t xb, int64_t xc, int64_t xi, int B, int d,
+                                                             int64_t Lo, float* __restrict__ dW,
+                                                             float* __restrict__ db) {
+  __shared__ double red[CONV_RED];
+  const int e = blockIdx.x;
+  const int nw = d * d * CONV_K;
+  const int64_t n = (int64_t)B * Lo;
+  double s = 0.0;
+  if (e < nw) {
+    const int o = e / (d * CONV_K), c = (e / CONV_K) % d, k = e % CONV_K;
+    for (int64_t t = threadIdx.x; t < n; t += CONV_RED) {
+      const int64_t b = t / Lo, j = t % Lo;
+      s += (double)dz[(b * d + o) * Lo + j] * (double)x[b * xb + c * xc + (CONV_S * j + k) * xi];
+    }
+  } else {
+    const int o = e - nw;
+    for (int64_t t = threadIdx.x; t < n; t += CONV_RED) {
+      const int64_t b = t / Lo, j = t % Lo;
+      s += (double)dz[(b * d + o) * Lo + j];
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = CONV_RED / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (e < nw) dW[e] = (float)red[0];
+    else db[e - nw] = (float)red[0];
+  }
+}
+
+// Input gradient of one convolution, gated by the ELU of the layer below:
+// dzp[b][c][i] = ELU'(a[b][c][i]) sum_o sum_{k: i = 4 j + k, 0 <= j < Lo} dz[b][o][j] W[o][c][k]
+__global__ __launch_bounds__(256) void conv_dx_kernel(const float* __restrict__ dz, const float* __restrict__ W,
+                                                     const float* __restrict__ a, int B, int d, int64_t Li,
+                                                     int64_t Lo, float* __restrict__ dzp) {
+  const int64_t total = (int64_t)B * d * Li;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % Li, bc = e / Li;
+    const int c = (int)(bc % d);
+    const int64_t b = bc / d;
+    float s = 0.0f;
+    for (int k = (int)(i % CONV_S); k < CONV_K; k += CONV_S) {
+      const int64_t j = (i - k) / CONV_S;
+      if (i < k || j >= Lo) continue;
+      for (int o = 0; o < d; ++o) s += dz[(b * d + o) * Lo + j] * W[((int64_t)o * d + c) * CONV_K + k];
+    }
+    dzp[e] = s * delu_from_act(a[e]);
+  }
+}
+
+struct ConvPass {
+  float* a[CONV_MAXL + 1];  // a[l] = ELU(conv_l) [B][d][len[l]], l >= 1
+  float *h, *q, *dq, *dh, *dz[2];
+  void carve(Carve& cv, const ConvShape& c, int B) {
+    for (int l = 1; l <= c.nl; ++l) a[l] = cv.take<float>((size_t)B * c.d * c.len[l]);
+    const int64_t top = c.nl ? c.len[1] : c.len[0];
+    h = cv.take<float>((size_t)B * c.hidden);
+    dh = cv.take<float>((size_t)B * c.hidden);
+    q = cv.take<float>((size_t)B * c.r);
+    dq = cv.take<float>((size_t)B * c.r);
+    dz[0] = cv.take<float>((size_t)B * c.d * top);
+    dz[1] = cv.take<float>((size_t)B * c.d * top);
+  }
+};
+
+// Strides of the activation entering convolution l (l = 0: the snapshot
+// [B][P][d], point-major; else [B][d][len]).
+static void conv_in(const ConvShape& c, const float* u, const ConvPass& w, int l, const float** x, int64_t* xb,
+                    int64_t* xc, int64_t* xi) {
+  if (l == 0) {
+    *x = u;
+    *xb = c.len[0] * c.d;
+    *xc = 1;
+    *xi = c.d;
+  } else {
+    *x = w.a[l];
+    *xb = c.d * c.len[l];
+    *xc = c.len[l];
+    *xi = 1;
+  }
+}
+
+static crom_status conv_encoder_fwd(const ConvShape& c, const float* prm, const float* u, int B, ConvPass& w,
+                                    hipStream_t st) {
+  for (int l = 0; l < c.nl; ++l) {
+    const float* x;
+    int64_t xb, xc, xi;
+    conv_in(c, u, w, l, &x, &xb, &xc, &xi);
+    hipLaunchKernelGGL(conv_fwd_kernel, dim3(grid_for((int64_t)B * c.d * c.len[l + 1])), dim3(256), 0, st, x, xb,
+                       xc, xi, prm + c.w[l], prm + c.b[l], B, c.d, c.len[l + 1], w.a[l + 1]);
+  }
+  // the flattened top: [B][d][L] is [B][L d] channel-major; with no
+  // convolution the snapshot itself ([B][P d], point-major)
+  const float* flat = c.nl ? w.a[c.nl] : u;
+  const int64_t n_flat = c.len[c.nl] * c.d;
+  hipLaunchKernelGGL(dense_fwd_kernel, dim3(grid_for((int64_t)B * c.hidden)), dim3(256), 0, st, flat, prm + c.e1,
+                     prm + c.c1, B, n_flat, c.hidden, 1, w.h);
+  hipLaunchKernelGGL(dense_fwd_kernel, dim3(grid_for((int64_t)B * c.r)), dim3(256), 0, st, w.h, prm + c.e2,
+                     prm + c.c2, B, (int64_t)c.hidden, c.r, 0, w.q);
+  return hip_check(hipGetLastError(), "convolutional encoder forward");
+}
+
+static crom_status conv_encoder_bwd(const ConvShape& c, const float* prm, const float* u, int B, const float* dq,
+                                    float* grad, ConvPass& w, hipStream_t st) {
+  const float* flat = c.nl ? w.a[c.nl] : u;
+  const int64_t n_flat = c.len[c.nl] * c.d;
+  // last layer: dE2, dc2; dh = (dq E2) ELU'(h)
+  hipLaunchKernelGGL(dense_wgrad_kernel, dim3(grid_for((int64_t)c.r * c.hidden + c.r)), dim3(256), 0, st, dq, w.h, B,
+                     (int64_t)c.hidden, c.r, grad + c.e2, grad + c.c2);
+  hipLaunchKernelGGL(dense_dx_kernel, dim3(grid_for((int64_t)B * c.hidden)), dim3(256), 0, st, dq, prm + c.e2, w.h, B,
+                     (int64_t)c.hidden, c.r, w.dh);
+  // dense layer: dE1, dc1; the top convolution's output gradient
+  hipLaunchKernelGGL(dense_wgrad_kernel, dim3(grid_for((int64_t)c.hidden * n_flat + c.hidden)), dim3(256), 0, st, w.dh,
+                     flat, B, n_flat, c.hidden, grad + c.e1, grad + c.c1);
+  if (c.nl == 0) return hip_check(hipGetLastError(), "convolutional encoder backward");
+  hipLaunchKernelGGL(dense_dx_kernel, dim3(grid_for((int64_t)B * n_flat)), dim3(256), 0, st, w.dh, prm + c.e1,
+                     w.a[c.nl], B, n_flat, c.hidden, w.dz[0]);
+  int cur = 0;
+  for (int l = c.nl - 1; l >= 0; --l) {  // convolution l: len[l] -> len[l + 1]
+    const float* x;
+    int64_t xb, xc, xi;
+    conv_in(c, u, w, l, &x, &xb, &xc, &xi);
+    hipLaunchKernelGGL(conv_wgrad_kernel, dim3(c.d * c.d * CONV_K + c.d), dim3(CONV_RED), 0, st, w.dz[cur], x, xb, xc,
+                       xi, B, c.d, c.len[l + 1], grad + c.w[l], grad + c.b[l]);
+    if (l > 0) {
+      hipLaunchKernelGGL(conv_dx_kernel, dim3(grid_for((int64_t)B * c.d * c.len[l])), dim3(256), 0, st, w.dz[cur],
+                         prm + c.w[l], w.a[l], B, c.d, c.len[l], c.len[l + 1], w.dz[1 - cur]);
+      cur = 1 - cur;
+    }
+  }
+  return hip_check(hipGetLastError(), "convolutional encoder backward");
+}
+
+static ConvShape conv_of(const crom_net* n, const crom_encoder* e) {
+  return conv_shape(e->n_in / n->d, n->d, e->hidden, e->r);
+}
+
 static bool bf_mode(const crom_net* n) { return n->precision != CROM_PREC_FP32; }
 
 template <class T>
@@ -718,8 +985,13 @@ static size_t train_bytes_t(const crom_net* n, const crom_encoder* e, int B) {
   Carve cv{nullptr, 0};
   DecoderPass<T> d;
   d.carve(cv, n, B, e->n_in / n->d);
-  EncoderPass<T> en;
-  en.carve(cv, e, B);
+  if (e->kind == CROM_ENC_CONV) {
+    ConvPass cp;
+    cp.carve(cv, conv_of(n, e), B);
+  } else {
+    EncoderPass<T> en;
+    en.carve(cv, e, B);
+  }
   return cv.off + 256;
 }
 
@@ -727,6 +999,9 @@ static crom_status check_enc(const crom_net* n, const crom_encoder* e) {
   if (!e || !e->params) return fail(CROM_ERR_INVALID_ARG, "encoder and its params are required");
   if (e->n_in < 1 || e->hidden < 1 || e->r != n->r || e->n_in % n->d != 0)
     return fail(CROM_ERR_INVALID_ARG, "encoder shape: r must match the net and n_in = P * d");
+  if (e->kind != CROM_ENC_DENSE && e->kind != CROM_ENC_CONV) return fail(CROM_ERR_INVALID_ARG, "encoder kind");
+  if (e->kind == CROM_ENC_CONV && conv_of(n, e).nl < 1)
+    return fail(CROM_ERR_INVALID_ARG, "the convolutional encoder needs room for one convolution (P d values)");
   return CROM_OK;
 }
 
@@ -738,6 +1013,19 @@ static crom_status train_grads_t(const crom_net* n, const crom_encoder* e, const
   const int64_t P = e->n_in / n->d;
   DecoderPass<T> d;
   d.carve(cv, n, B, P);
+  if (e->kind == CROM_ENC_CONV) {
+    const ConvShape c = conv_of(n, e);
+    ConvPass cp;
+    cp.carve(cv, c, B);
+    crom_status s = conv_encoder_fwd(c, e->params, u, B, cp, st);
+    if (s != CROM_OK) return s;
+    s = decoder_fwd_bwd<T>(n, x, B, P, cp.q, u, nullptr, grad_dec, cp.dq, loss, d, st);
+    if (s != CROM_OK) return s;
+    s = conv_encoder_bwd(c, e->params, u, B, cp.dq, grad_enc, cp, st);
+    if (s != CROM_OK) return s;
+    if (q_out) s = hip_check(hipMemcpyAsync(q_out, cp.q, sizeof(float) * B * e->r, hipMemcpyDeviceToDevice, st), "q copy");
+    return s;
+  }
   EncoderPass<T> en;
   en.carve(cv, e, B);
   crom_status s = encoder_fwd<T>(e, u, B, en, st);
@@ -759,6 +1047,12 @@ extern "C" {
 size_t crom_encoder_param_count(int32_t n_in, int32_t hidden, int32_t r) {
   if (n_in < 1 || hidden < 1 || r < 1) return 0;
   return (size_t)hidden * n_in + hidden + (size_t)r * hidden + r;
+}
+
+size_t crom_conv_encoder_param_count(int64_t P, int32_t d, int32_t hidden, int32_t r) {
+  if (P < 1 || d < 1 || hidden < 1 || r < 1) return 0;
+  const ConvShape c = conv_shape(P, d, hidden, r);
+  return c.nl < 1 ? 0 : (size_t)c.count;
 }
 
 crom_status crom_train_workspace(const crom_net* net, const crom_encoder* enc, int32_t B, size_t* bytes) {
@@ -812,7 +1106,8 @@ crom_status crom_train_step(const crom_net* net, void* packed, float* dec_grad, 
   if (s != CROM_OK) return s;
   if (!dec_m || !dec_v || !enc_m || !enc_v) return fail(CROM_ERR_INVALID_ARG, "Adam moments are required");
   const int64_t nd = (int64_t)crom_net_param_count(net->m, net->r, net->d, net->width, net->depth);
-  const int64_t ne = (int64_t)crom_encoder_param_count(enc->n_in, enc->hidden, enc->r);
+  const int64_t ne = enc->kind == CROM_ENC_CONV ? conv_of(net, enc).count
+                                                : (int64_t)crom_encoder_param_count(enc->n_in, enc->hidden, enc->r);
   s = crom_adam_step(const_cast<float*>(net->params), dec_grad, dec_m, dec_v, nd, t, lr, 0.9f, 0.999f, 1e-8f, stream);
   if (s != CROM_OK) return s;
   s = crom_adam_step(enc->params, enc_grad, enc_m, enc_v, ne, t, lr, 0.9f, 0.999f, 1e-8f, stream);
@@ -830,7 +1125,10 @@ crom_status crom_encode_workspace(const crom_net* net, const crom_encoder* enc, 
   if ((s = check_enc(net, enc)) != CROM_OK) return s;
   if (B < 1 || !bytes) return fail(CROM_ERR_INVALID_ARG, "B >= 1 and bytes are required");
   Carve cv{nullptr, 0};
-  if (bf_mode(net)) {
+  if (enc->kind == CROM_ENC_CONV) {
+    ConvPass cp;
+    cp.carve(cv, conv_of(net, enc), B);
+  } else if (bf_mode(net)) {
     EncoderPass<__bf16> en;
     en.carve(cv, enc, B);
   } else {
@@ -850,6 +1148,13 @@ crom_status crom_encode(const crom_net* net, const crom_encoder* enc, const floa
   if (ws_bytes < need) return fail(CROM_ERR_WORKSPACE, "workspace too small");
   hipStream_t st = static_cast<hipStream_t>(stream);
   Carve cv{reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255)), 0};
+  if (enc->kind == CROM_ENC_CONV) {
+    const ConvShape c = conv_of(net, enc);
+    ConvPass cp;
+    cp.carve(cv, c, B);
+    if ((s = conv_encoder_fwd(c, enc->params, u, B, cp, st)) != CROM_OK) return s;
+    return hip_check(hipMemcpyAsync(q, cp.q, sizeof(float) * B * enc->r, hipMemcpyDeviceToDevice, st), "q copy");
+  }
   if (bf_mode(net)) {
     EncoderPass<__bf16> en;
     en.carve(cv, enc, B);

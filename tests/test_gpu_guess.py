@@ -1,0 +1,158 @@
+"""The Gauss-Newton inversion from an initial guess (crom_step_guess) and the
+encoder-based guess for the heat step (crom_heat_guess), against the FP64
+oracle (GPU).
+
+The 2D heat decoder (x in R^2, q in R^8) -> 5 x ELU 128 -> 1 with
+Xavier-uniform weights, 300 random samples.  Its latent Jacobian is badly
+conditioned, so as in the plain step's parity the Gauss-Newton result is
+compared on the decoded change at the samples and on the objective.
+* A guess worse than q_n leaves the step bit-identical to crom_step (one
+  more round).
+* A better guess (the oracle's converged solution, perturbed) is taken as
+  the start: the objective and the decoded change follow the oracle's step
+  from the same guess, and within two iterations it reaches the converged
+  objective, no higher than the same budget from q_n reaches.
+* A batch of instances with and without accepted guesses reproduces each
+  instance alone bit for bit.
+* The encoder guess: decoder value and Laplacian at every node of a 32 x 32
+  grid, the heat update, a dense encoder (1024 -> 40 -> 8): against the
+  oracle's encoder of the oracle's FP64 update, FP32 within 1e-4 (FP32
+  decoder values 1e-5 and sums of 1,024 FP32 products), BF16 within 3e-2
+  (bfloat16 encoder inputs and first-layer weights, as in training)."""
+import numpy as np
+import pytest
+
+from conftest import normwise_rel
+from oracle import mlp, step as ostep, train
+from oracle.inversion import GNOptions as OOpts
+from workloads import Heat2D, grid_points_2d, rng, xavier_mlp
+
+pytestmark = pytest.mark.gpu
+
+NU = 0.5
+
+
+@pytest.fixture(scope="module")
+def case():
+    wl = Heat2D(seed=3, bias_scale=0.1)
+    g = rng(61)
+    y = g.uniform(0.05, 0.95, size=(300, 2)).astype(np.float32)
+    return wl.layers, y, wl.q0
+
+
+def _stepper(cuda, layers, y, n=1, prec="fp32"):
+    import torch
+    from paper_2206_02607_amd import crom
+    dec = crom.Decoder.from_layers(layers, 2, precision=prec, device=cuda)
+    S = y.shape[0]
+    return crom.Stepper(dec, np.arange(n + 1) * S, torch.from_numpy(np.tile(y, (n, 1))).to(cuda))
+
+
+def _step(cuda, st, q_n, dt, q_init=None, **opt):
+    import torch
+    from paper_2206_02607_amd import crom
+    opt.setdefault("tol_step", 1e-10)
+    qn = torch.from_numpy(np.atleast_2d(q_n)).to(cuda)
+    qi = None if q_init is None else torch.from_numpy(np.atleast_2d(q_init)).to(cuda)
+    n = qn.shape[0]
+    q1 = st.step(qn, torch.full((n,), NU, dtype=torch.float64), dt, crom.GNOptions(**opt), q_init=qi)
+    torch.cuda.synchronize()
+    return q1.cpu().numpy(), st.info()
+
+
+def _converged(layers, y, q_n, dt, with_obj=False):
+    dec = mlp.MLPDecoder(layers, 2)
+    q, info, _ = ostep.heat_step(dec, y, q_n, NU, dt, OOpts(max_iter=40, tol_step=1e-13))
+    return (q, info.obj_last) if with_obj else q
+
+
+def test_worse_guess_changes_nothing(cuda, case):
+    layers, y, q0 = case
+    st = _stepper(cuda, layers, y)
+    dt = 1e-3
+    q_plain, i_plain = _step(cuda, st, q0, dt, max_iter=5)
+    q_g, i_g = _step(cuda, st, q0, dt, q_init=q0 + 1.0, max_iter=5)
+    np.testing.assert_array_equal(q_g, q_plain)
+    for k in ("flags", "iters", "ls_evals", "obj_first", "obj_last"):
+        assert i_g[k][0] == i_plain[k][0], k
+    assert i_g["rounds"][0] == i_plain["rounds"][0] + 1
+
+
+def test_better_guess_matches_oracle(cuda, case):
+    layers, y, q0 = case
+    st = _stepper(cuda, layers, y)
+    dt = 2e-2  # a large step: the field moves far from g(q_n)
+    q_star, obj_star = _converged(layers, y, q0, dt, with_obj=True)
+    guess = q_star + 1e-3 * rng(62).uniform(-1, 1, size=q0.size)
+    q_g, i_g = _step(cuda, st, q0, dt, q_init=guess, max_iter=2)
+    q_p, i_p = _step(cuda, st, q0, dt, max_iter=2)
+    dec = mlp.MLPDecoder(layers, 2)
+    qr, oinfo, _, used = ostep.heat_step_from_guess(dec, y, q0, guess, NU, dt, OOpts(max_iter=2, tol_step=1e-10))
+    assert used
+    g0 = dec.value(y, q0)
+    e_dg = normwise_rel(dec.value(y, q_g[0]) - g0, dec.value(y, qr) - g0)
+    print(f"guess: obj first {i_g['obj_first'][0]:.4e}/{oinfo.obj_first:.4e} last {i_g['obj_last'][0]:.4e}/"
+          f"{oinfo.obj_last:.4e} (from q_n {i_p['obj_last'][0]:.4e}), dg err {e_dg:.2e}, iters "
+          f"{i_g['iters'][0]}/{oinfo.iters}, rounds {i_g['rounds'][0]}")
+    # the plain step's Gauss-Newton bar for this conditioning (the objective,
+    # which the step determines well, is held to 1e-2 relative below)
+    assert e_dg <= 1e-2
+    assert abs(i_g["obj_first"][0] - oinfo.obj_first) <= 1e-4 * oinfo.obj_first
+    assert i_g["obj_last"][0] <= oinfo.obj_last * 1.01 + 1e-6 * oinfo.obj_first
+    # what the guess gains: two iterations from it reach the converged
+    # objective; the same budget from q_n ends no lower
+    print(f"converged objective {obj_star:.6e}")
+    assert i_g["obj_last"][0] <= obj_star * (1 + 1e-4)
+    assert i_g["obj_last"][0] <= i_p["obj_last"][0] * (1 + 1e-9)
+
+
+def test_batched_guesses_equal_single(cuda, case):
+    layers, y, q0 = case
+    dt = 2e-2
+    g = rng(63)
+    qn = q0[None] + 0.05 * g.uniform(-1, 1, size=(3, q0.size))
+    guesses = np.stack([_converged(layers, y, qn[0], dt) + 1e-3, qn[1] + 1.0, _converged(layers, y, qn[2], dt)])
+    stb = _stepper(cuda, layers, y, n=3, prec="bf16")
+    qb, ib = _step(cuda, stb, qn, dt, q_init=guesses, max_iter=3, tol_step=1e-6)
+    for i in range(3):
+        st1 = _stepper(cuda, layers, y, prec="bf16")
+        q1, i1 = _step(cuda, st1, qn[i], dt, q_init=guesses[i], max_iter=3, tol_step=1e-6)
+        np.testing.assert_array_equal(qb[i], q1[0])
+        assert ib[i].tobytes() == i1[0].tobytes()
+
+
+def _held(layers, enc, prec):
+    import torch
+
+    def bf(a):
+        return torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float32).numpy()
+    d = [(np.asarray(W, np.float32), np.asarray(b, np.float32)) for W, b in layers]
+    e = [(np.asarray(W, np.float32), np.asarray(b, np.float32)) for W, b in enc]
+    if prec != "fp32":
+        d = [d[0]] + [(bf(W), b) for W, b in d[1:-1]] + [d[-1]]
+        e = [(bf(e[0][0]), e[0][1])] + e[1:]
+    return d, e
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 3e-2)])
+def test_heat_guess_vs_oracle(cuda, case, prec, tol):
+    import torch
+    from paper_2206_02607_amd import crom
+    layers, _, q0 = case
+    nodes = grid_points_2d(32, 32)
+    g = rng(64)
+    enc = xavier_mlp(g, nodes.shape[0], 0, 8, 40, 1, bias_scale=0.2)
+    flat = np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in enc]).astype(np.float32)
+    dec = crom.Decoder.from_layers(layers, 2, precision=prec, device=cuda)
+    qn = np.stack([q0, q0 + 0.05 * g.uniform(-1, 1, size=q0.size)])
+    nus = np.array([0.3, 0.8])
+    dt = 1e-3
+    got = crom.heat_guess(dec, torch.from_numpy(flat).to(cuda), 40, torch.from_numpy(nodes).to(cuda),
+                          torch.from_numpy(qn).to(cuda), torch.from_numpy(nus).to(cuda), dt).cpu().numpy()
+    hd, he = _held(layers, enc, prec)
+    odec = mlp.MLPDecoder(hd, 2)
+    for i in range(2):
+        ref = ostep.encoder_guess(odec, lambda f: train.encode(he, f), nodes.astype(np.float64), qn[i], nus[i], dt)
+        err = normwise_rel(got[i], ref)
+        print(f"{prec} instance {i}: |q| {np.abs(ref).max():.3e} error {err:.2e}")
+        assert err <= tol

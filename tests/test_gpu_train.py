@@ -346,3 +346,61 @@ def test_siren_training_reduces_loss(cuda):
     losses = [T.step(ut, 1e-4)[0].item() for _ in range(200)]
     print("siren loss", losses[0], losses[-1])
     assert losses[-1] < 0.1 * losses[0]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("shape", ["2d", "3d"])
+def test_train_grads_conv_encoder(cuda, shape, prec):
+    """The paper's convolutional encoder (kernel 6, stride 4; 300 points:
+    one convolution to 74 for d = 1, two to 18 for d = 3; dense 32): loss,
+    latents and every gradient against the oracle.  The encoder's
+    arithmetic is FP32 in every mode; in the bfloat16 mode its gradients
+    inherit the decoder's bfloat16 latent cotangent (tolerance 2e-2)."""
+    import torch
+    from paper_2206_02607_amd import crom
+    m, r, d, w, depth = SHAPES[shape]
+    B, P = 3, 300
+    g = rng(15)
+    dec = xavier_mlp(g, m, r, d, w, depth, bias_scale=0.2)
+    enc = train.conv_encoder_init(g, P, d, r, 32)
+    x = uniform_points(g, P, m)
+    u = g.uniform(-1, 1, size=(B, P * d)).astype(np.float32)
+    D = crom.Decoder.from_layers(dec, m, precision=prec, device=cuda)
+    assert crom.encoder_param_count(P * d, 32, r, "conv", d) == _flat(enc).size
+    T = crom.Trainer(D, _flat(enc), 32, torch.from_numpy(x).to(cuda), B, enc_kind="conv")
+    loss, gd, ge, q = T.grads(torch.from_numpy(u).to(cuda))
+    q_only = T.encode(torch.from_numpy(u).to(cuda))
+    torch.cuda.synchronize()
+    held_dec, _ = _as_held(dec, None, prec)
+    enc64 = [(np.asarray(W, np.float32).astype(np.float64), np.asarray(b, np.float32).astype(np.float64))
+             for W, b in enc]
+    rl, rgd, rge, rq = train.loss_and_grads(held_dec, enc64, x, u, enc_kind="conv")
+    errs = {"loss": abs(loss.item() - rl) / rl, "q": normwise_rel(q.cpu().numpy(), rq),
+            "q_encode": normwise_rel(q_only.cpu().numpy(), rq)}
+    for name, got, ref, layers in (("dec", gd, rgd, dec), ("enc", ge, rge, enc)):
+        for li, ((gW, gb), (rW, rb)) in enumerate(zip(_split(got.cpu().numpy(), layers), ref)):
+            errs[f"{name}W{li}"] = normwise_rel(gW, rW)
+            errs[f"{name}b{li}"] = normwise_rel(gb, rb)
+    print(shape, prec, "conv encoder", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert errs["q"] <= 1e-5 and errs["q_encode"] <= 1e-5  # FP32 encoder in every mode
+    bad = {k: v for k, v in errs.items() if not v <= TOL[prec]}
+    assert not bad, bad
+
+
+def test_conv_encoder_training_reduces_loss(cuda):
+    import torch
+    from paper_2206_02607_amd import crom
+    m, r, d, w, depth = SHAPES["2d"]
+    B, P = 4, 256
+    g = rng(16)
+    dec = xavier_mlp(g, m, r, d, w, depth)
+    enc = train.conv_encoder_init(g, P, d, r, 32)
+    x = uniform_points(g, P, m)
+    amp = np.array([-0.8, -0.2, 0.4, 0.9], np.float32)
+    u = (amp[:, None] * (np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1]))[None, :]).astype(np.float32)
+    D = crom.Decoder.from_layers(dec, m, precision="bf16", device=cuda)
+    T = crom.Trainer(D, _flat(enc), 32, torch.from_numpy(x).to(cuda), B, enc_kind="conv")
+    ut = torch.from_numpy(u).to(cuda)
+    losses = [T.step(ut, lr=1e-3).item() for _ in range(300)]
+    print("conv encoder loss", losses[0], losses[-1])
+    assert np.mean(losses[-20:]) < 0.2 * np.mean(losses[:20])
