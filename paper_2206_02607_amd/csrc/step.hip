@@ -87,7 +87,8 @@ constexpr int RMAX = 16;
 // heat step at 2,000 samples, where almost every first trial is accepted,
 // takes 0.157 ms with one trial per round and 0.203 ms with four; the batch
 // of 512 trained instances, which backtrack (11.5 trials per instance and
-// step), takes 24.8 ms with one and 21.6 ms with four.
+// step), took 24.8 ms with one and 21.6 ms with four, and 22.9 ms with one
+// once its backtracking rounds dropped the Jacobian columns.
 #ifndef CROM_TRIALS
 #define CROM_TRIALS 1
 #endif
@@ -410,11 +411,13 @@ __device__ void eval_jets_batch(const StepArgs& a, char* lds, const float* par, 
   __syncthreads();
 }
 
-template <class S, int NW, int PREC, int PF>
+// WITH_J: also the latent Jacobian at the first trial (else its partials
+// JᵀJ and Jᵀρ come out zero and only the trial objectives count).
+template <class S, int NW, int PREC, int PF, bool WITH_J = true>
 __device__ void eval_trials_batch(const StepArgs& a, char* lds, const float* par, double* qdl,
                                   int64_t blk, int inst, int mb, bool have_qdl) {
   constexpr int R = S::R;
-  using C = Cols<S::M, R, 1, TV, false, D2_NONE, R>;
+  using C = Cols<S::M, R, 1, TV, false, D2_NONE, WITH_J ? R : 0>;
   using E = Engine<S, C, 1, NW, PREC, PF>;
   const GNState* st = wsp<GNState>(a, a.L.state) + inst;
   if (mb >= 0) trace_mark(a, mb);
@@ -440,7 +443,7 @@ __device__ void eval_trials_batch(const StepArgs& a, char* lds, const float* par
     const bool valid = i < n_valid;
     const double r0 = valid ? rho0[first + i] : 0.0;
     for (int t = 0; t < TV; ++t) rho[i * TV + t] = valid ? r0 - (double)res[(C::F0 + t) * PT + i] : 0.0;
-    for (int k = 0; k < R; ++k) jd[i * R + k] = valid ? (double)res[(C::Q0 + k) * PT + i] : 0.0;
+    for (int k = 0; k < R; ++k) jd[i * R + k] = (WITH_J && valid) ? (double)res[(C::Q0 + k) * PT + i] : 0.0;
   }
   __syncthreads();
   batch_partials<R>(jd, rho, wsp<double>(a, a.L.partials) + blk * a.L.nred);
@@ -971,7 +974,10 @@ __device__ bool wave_chol_solve(const double* up, const double* b, double& xk) {
 // spread over the lanes.  Finally the state goes back, the instance's
 // arrival counter is reset, and the phase's counters are advanced.
 // ---------------------------------------------------------------------------
-template <int R>
+// LAZY: the rounds after a rejected trial evaluated the objective only (no
+// Jacobian), so a trial accepted there is followed by a re-linearisation
+// round; otherwise every round carries J at its first trial.
+template <int R, bool LAZY = false>
 __device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bool is_last) {
   constexpr int NA = R * (R + 1) / 2;
   constexpr int NRED = NA + R + TV;
@@ -1094,8 +1100,8 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
         } else if (iters >= a.max_iter) {
           flags |= CROM_FLAG_MAXITER;
           done = true;
-        } else if (acc == 0) {
-          newdir = true;
+        } else if (acc == 0 && (!LAZY || ls_tried == 0)) {
+          newdir = true;  // J at the accepted trial came with this round
         } else {
           ph = PH_REJAC;
           settrials = 2;
@@ -1472,7 +1478,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
                                                                                               int p) {
   using T = StepTraits<S, NW, PREC, PF, PK_HEAT>;
   extern __shared__ __align__(16) char lds[];
-  __shared__ int s_ph;
+  __shared__ int s_ph, s_lt;
   __shared__ double qdl[TV * RMAX];
   if (ld_c(wsp<int64_t>(a, a.L.act_phase) + p) == 0) return;  // uniform: nothing active in this round
   const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
@@ -1487,12 +1493,20 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
     if (p == 0) {
       eval_jets_batch<S, NW, PREC, PF>(a, lds, par, blk);
     } else {
-      if (threadIdx.x == 0) s_ph = ld_c(&state[inst].phase);
+      if (threadIdx.x == 0) {
+        s_ph = ld_c(&state[inst].phase);
+        s_lt = ld_c(&state[inst].ls_tried);
+      }
       __syncthreads();
-      const int ph = s_ph;
+      const int ph = s_ph, lt = s_lt;
       __syncthreads();
       if (!evaluates_trials(ph)) continue;
-      eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, -1, false);
+      // a backtracking round (trials after a rejected one) needs only the
+      // objective: no latent tangents (the solve re-linearises on acceptance)
+      if (ph == PH_TRIALS && lt > 0)
+        eval_trials_batch<S, NW, PREC, PF, false>(a, lds, par, qdl, blk, inst, -1, false);
+      else
+        eval_trials_batch<S, NW, PREC, PF, true>(a, lds, par, qdl, blk, inst, -1, false);
     }
   }
 }
@@ -1509,7 +1523,7 @@ __global__ __launch_bounds__(NTH) void gn_solve_kernel(StepArgs a, int p, int is
   const int ph = s_ph;
   const bool active = p == 0 ? ph == PH_INIT : evaluates_trials(ph);
   if (!active) return;
-  solve_instance<R>(a, lds, inst, p, is_last != 0);
+  solve_instance<R, true>(a, lds, inst, p, is_last != 0);
 }
 
 template <class S, int NW, int PREC, int PF, int WPE>

@@ -209,3 +209,26 @@ def test_full_size_fe_kernel(cuda, prec):
           f"flags {info['flags'][0]} iters {info['iters'][0]}")
     assert err <= 1e-9
     assert info["flags"][0] & ~crom.FLAG_MAXITER == 0
+
+
+def test_full_size_batched_fe_kernel(cuda):
+    """Two instances of the bar (500 samples each, different sample sets and
+    shear moduli) in one step: each instance's increments against the
+    oracle on the GPU's own ring values."""
+    from paper_2206_02607_amd import crom
+    w = Corotated3D(n_inst=2, seed=3)
+    dec = crom.Decoder.from_layers(w.layers, 3, precision="bf16", device=cuda)
+    coef = np.stack([_coef(mu=w.mu[i], lam=w.lam) for i in range(2)])
+    _, info, inc, ring_u, sm = _run(crom, dec, w.X, w.tets, w.samples, coef, w.q0, None,
+                                    crom.GNOptions(max_iter=1, linearized=True), cuda)
+    roff = sm.ring_offsets.cpu().numpy()
+    off = sm.offsets.cpu().numpy()
+    for i in range(2):
+        a, b = roff[i], roff[i + 1]
+        look = _Lookup(w.X, sm.ring_vert[a:b], ring_u[a:b])
+        _, ref = fem.fem_targets(look, w.X, w.tets, w.samples[i], w.q0[i], None, w.lam, w.mu[i], w.rho0,
+                                 w.gravity, w.dt)
+        err = normwise_rel(inc[off[i]:off[i + 1]], ref)
+        print(f"instance {i}: ring {b - a} vertices, FE kernel error {err:.2e}, flags {info['flags'][i]}")
+        assert err <= 1e-9
+        assert info["flags"][i] == 0

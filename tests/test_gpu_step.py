@@ -190,7 +190,11 @@ def test_round_kernels_match_persistent(cuda, prec):
     """Large batches (more than 1,024 sample batches) run Gauss-Newton as
     round kernels, small ones in the persistent kernel; both evaluate the
     same batches with the same engine and solve each instance in the same
-    order, so a large batch reproduces each instance run alone bit for bit."""
+    order, so a large batch reproduces each instance run alone bit for bit
+    (iterates, flags, iterations, trials and objectives).  Only the round
+    count may differ: after a rejected trial the round kernels evaluate the
+    objective alone and re-linearise in a round of their own when a
+    shortened step is accepted."""
     import torch
     from paper_2206_02607_amd import crom
     wb = Batched2D(seed=3, n_inst=12, s_min=1400, s_max=1600)
@@ -206,4 +210,7 @@ def test_round_kernels_match_persistent(cuda, prec):
         s1 = crom.Stepper(dec, [0, hi - lo], torch.from_numpy(wb.samples[lo:hi]).to(cuda))
         q1 = s1.step(torch.from_numpy(wb.q0[i:i + 1]).to(cuda), torch.tensor([wb.mu[i]]), wb.dt, opts).cpu().numpy()
         np.testing.assert_array_equal(qb[i], q1[0])
-        assert ib[i].tobytes() == s1.info()[0].tobytes()
+        i1 = s1.info()[0]
+        for k in ("flags", "iters", "ls_evals", "obj_first", "obj_last"):
+            assert ib[i][k] == i1[k], k
+        assert ib[i]["rounds"] >= i1["rounds"]

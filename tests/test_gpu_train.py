@@ -404,3 +404,35 @@ def test_conv_encoder_training_reduces_loss(cuda):
     losses = [T.step(ut, lr=1e-3).item() for _ in range(300)]
     print("conv encoder loss", losses[0], losses[-1])
     assert np.mean(losses[-20:]) < 0.2 * np.mean(losses[:20])
+
+
+def test_conv_encoder_full_size(cuda):
+    """The training workload's size: 128 x 128 = 16,384 points per snapshot
+    (convolutions 16384 -> 4095 -> 1023 -> 255 -> 63, dense 32, r = 8), the
+    2D decoder, FP32, two snapshots: loss, latents and every gradient
+    against the oracle (1e-5)."""
+    import torch
+    from paper_2206_02607_amd import crom
+    from workloads import grid_points_2d
+    m, r, d, w, depth = SHAPES["2d"]
+    B = 2
+    x = grid_points_2d(128, 128)
+    P = x.shape[0]
+    g = rng(17)
+    dec = xavier_mlp(g, m, r, d, w, depth, bias_scale=0.2)
+    enc = train.conv_encoder_init(g, P, d, r, 32)
+    u = (np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1]))[None, :] * g.uniform(-1, 1, size=(B, 1))
+    u = (u + 0.1 * g.uniform(-1, 1, size=(B, P))).astype(np.float32)
+    D = crom.Decoder.from_layers(dec, m, precision="fp32", device=cuda)
+    T = crom.Trainer(D, _flat(enc), 32, torch.from_numpy(x).to(cuda), B, enc_kind="conv")
+    loss, gd, ge, q = T.grads(torch.from_numpy(u).to(cuda))
+    torch.cuda.synchronize()
+    rl, rgd, rge, rq = train.loss_and_grads(dec, enc, x, u, enc_kind="conv")
+    errs = {"loss": abs(loss.item() - rl) / rl, "q": normwise_rel(q.cpu().numpy(), rq)}
+    for name, got, ref, layers in (("dec", gd, rgd, dec), ("enc", ge, rge, enc)):
+        for li, ((gW, gb), (rW, rb)) in enumerate(zip(_split(got.cpu().numpy(), layers), ref)):
+            errs[f"{name}W{li}"] = normwise_rel(gW, rW)
+            errs[f"{name}b{li}"] = normwise_rel(gb, rb)
+    print("full size conv encoder", {k: f"{v:.1e}" for k, v in errs.items()})
+    bad = {k: v for k, v in errs.items() if not v <= TOL["fp32"]}
+    assert not bad, bad
