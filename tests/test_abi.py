@@ -100,6 +100,63 @@ def test_step_validation():
     assert call(pde_=crom.CromPDE(0, 0, -1.0, 1 << 22)) == 1
     assert call(pde_=crom.CromPDE(5, 0, 1e-4, 1 << 22)) == 2
     assert call(pde_=crom.CromPDE(1, 0, 1e-4, 1 << 22)) == 2  # neo-Hookean needs m == d == 3
+    assert call(pde_=crom.CromPDE(2, 0, 1e-4, 1 << 22)) == 2  # so does the FE step
+    # the initial-guess variant: q_init must not alias q_next
+    assert L.crom_step_guess(ctypes.byref(_net()), ctypes.byref(pde), 4, args["offsets"], args["total"], args["y"],
+                             None, None, args["qn"], args["qnext"], args["qnext"], ctypes.byref(opts), args["info"],
+                             args["ws"], args["wsb"], None) == 1
+
+
+def test_fe_step_validation():
+    L = crom.lib()
+    net = _net(m=3, r=16, d=3, width=256, depth=6)
+    n = ctypes.c_size_t(0)
+    assert L.crom_step_workspace(ctypes.byref(net), 1, 500, ctypes.byref(n)) == 0
+    opts = crom.GNOptions().c_struct()
+
+    def call(mesh):
+        pde = crom.CromPDE(2, 0, 1e-3, 1 << 22, None if mesh is None else ctypes.addressof(mesh))
+        return L.crom_step(ctypes.byref(net), ctypes.byref(pde), 1, 1 << 23, 500, 1 << 24, None, None, 1 << 25,
+                           1 << 26, ctypes.byref(opts), 1 << 27, 1 << 28, n.value, None)
+
+    def mesh(**kw):
+        f = dict(n_ring=6000, max_ring=6000, n_inc=10000, ring_offsets=1 << 29, ring_X=1 << 30, inc_offsets=1 << 31,
+                 inc_tets=1 << 32, inc_corner=1 << 33, ring_u=1 << 34)
+        f.update(kw)
+        return crom.CromFEMesh(**f)
+
+    assert call(None) == 1                        # the FE step needs its stencil
+    assert call(mesh(max_ring=6001)) == 1         # larger than the whole ring
+    assert call(mesh(n_inc=-1)) == 1
+    assert call(mesh(ring_u=None)) == 1
+    assert call(mesh(inc_corner=None)) == 1
+    assert call(mesh(ring_offsets=None)) == 1
+
+
+def test_heat_guess_and_encoder_validation():
+    L = crom.lib()
+    net = _net()  # (2, 8, 1, 128)
+    n = ctypes.c_size_t(0)
+    enc = crom.CromEncoder(16384, 256, 8, 0, 1 << 20)
+    assert L.crom_heat_guess_workspace(ctypes.byref(net), ctypes.byref(enc), 2, 16384, ctypes.byref(n)) == 0
+    assert n.value > 3 * 2 * 16384 * 4
+    assert L.crom_heat_guess_workspace(ctypes.byref(net), ctypes.byref(enc), 2, 1000, ctypes.byref(n)) == 1
+    assert L.crom_heat_guess_workspace(ctypes.byref(net), ctypes.byref(enc), 0, 16384, ctypes.byref(n)) == 1
+    bad_r = crom.CromEncoder(16384, 256, 4, 0, 1 << 20)
+    assert L.crom_heat_guess_workspace(ctypes.byref(net), ctypes.byref(bad_r), 2, 16384, ctypes.byref(n)) == 1
+    net3 = _net(m=3, r=16, d=3, width=256, depth=6)
+    enc3 = crom.CromEncoder(3 * 100, 32, 16, 0, 1 << 20)
+    assert L.crom_heat_guess_workspace(ctypes.byref(net3), ctypes.byref(enc3), 1, 100, ctypes.byref(n)) == 2
+    assert L.crom_heat_guess_workspace(ctypes.byref(net), ctypes.byref(enc), 2, 16384, ctypes.byref(n)) == 0
+    assert L.crom_heat_guess(ctypes.byref(net), ctypes.byref(enc), 1 << 21, 16384, 2, 1 << 22, 1 << 23, 1e-4,
+                             1 << 24, 1 << 25, n.value - 1, None) == 3
+    # encoder kinds: the paper's convolutional encoder for 16,384 points
+    # (four convolutions of 7 parameters, dense 63 -> 32, 32 -> 8)
+    assert L.crom_conv_encoder_param_count(16384, 1, 32, 8) == 4 * 7 + 32 * 63 + 32 + 8 * 32 + 8
+    assert L.crom_conv_encoder_param_count(40, 1, 32, 8) == 0   # no room for a convolution
+    for kind, n_in, want in ((7, 16384, 1), (1, 40, 1), (1, 16384, 0)):
+        e = crom.CromEncoder(n_in, 32, 8, kind, 1 << 20)
+        assert L.crom_train_workspace(ctypes.byref(net), ctypes.byref(e), 4, ctypes.byref(n)) == want, (kind, n_in)
 
 
 def test_sampling_validation():
