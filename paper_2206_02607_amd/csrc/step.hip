@@ -45,6 +45,7 @@
 #include <stddef.h>
 
 #include "common.hpp"
+#include "tune.hpp"
 
 // Launch shapes of the step kernels (waves, weight fragments, waves per SIMD
 // left room for); the linearised step is measured like the decode kernels.
@@ -455,11 +456,14 @@ __device__ void eval_trials_batch(const StepArgs& a, char* lds, const float* par
 // ---------------------------------------------------------------------------
 enum { PK_HEAT = 0, PK_ELASTIC = 1 };
 
-// Latent-tangent chunk of the elastic passes (their activations must fit
-// the LDS at width 256: bfloat16 operands take half the room of FP32).
+// Latent-tangent chunk of the elastic passes.  Four tangents per pass in
+// every precision: in bfloat16 eight would fit the LDS, but the step
+// kernel's trial evaluation then spills 864 bytes per lane (216 with four),
+// and the four-tangent passes measured faster (neo-Hookean bar, BF16 GN
+// step 2.29 -> 2.08 ms; FE bar 1.47 -> 1.35 ms).
 template <int PREC>
 struct ElasticChunks {
-  static constexpr int QC = PREC == PREC_FP32 ? 4 : 8;
+  static constexpr int QC = 4;
   static constexpr int HC = 3;
 };
 
@@ -585,32 +589,47 @@ __global__ __launch_bounds__(64) void elastic_targets_kernel(StepArgs a) {
 
 // Displacement u = g(X, q_n) at the ring vertices of every instance (value
 // column only): blockIdx.y is the instance, the x-blocks stride over its
-// 16-vertex batches.  An instance whose ring range is not a valid CSR range
-// of [0, n_ring] is skipped; its targets then come out NaN.
-template <class S, int NW, int PREC>
-__global__ __launch_bounds__(NW * 64) void ring_decode_kernel(StepArgs a) {
-  using C = Cols<S::M, S::R, 1, 0, false, D2_NONE, 0>;
-  using E = Engine<S, C, 1, NW, PREC, 0>;
+// passes of NB 16-vertex batches.  An instance whose ring range is not a
+// valid CSR range of [0, n_ring] is skipped; its targets then come out NaN.
+// Launch shape: in bfloat16 the full-field decode's (64 vertices and eight
+// waves per workgroup: the weights are read once per 64 vertices; 5,748
+// vertices 45 -> 33 us); in FP32 16 vertices and four waves (the wider
+// shape left most CUs idle at this size: 60 -> 89 us).
+template <class S, int PREC>
+struct RingTune {
+  static constexpr int NB = PREC == PREC_FP32 ? 1 : 4;
+  static constexpr int NW = PREC == PREC_FP32 ? 4 : DecodeTune<S, PREC>::NW;
+  static constexpr int PF = PREC == PREC_FP32 ? 0 : DecodeTune<S, PREC>::PF;
+};
+template <class S, int PREC>
+using RingEngine = Engine<S, Cols<S::M, S::R, 1, 0, false, D2_NONE, 0>, RingTune<S, PREC>::NB,
+                          RingTune<S, PREC>::NW, PREC, RingTune<S, PREC>::PF>;
+
+template <class S, int PREC>
+__global__ __launch_bounds__((RingTune<S, PREC>::NW * 64)) void ring_decode_kernel(StepArgs a) {
+  using E = RingEngine<S, PREC>;
   extern __shared__ __align__(16) char lds[];
   const int inst = blockIdx.y;
   const int64_t lo = a.fe.ring_offsets[inst], hi = a.fe.ring_offsets[inst + 1];
   if (!(lo >= 0 && hi >= lo && hi <= a.fe.n_ring)) return;
-  const int64_t nb = (hi - lo + PT - 1) / PT;
+  const int64_t nb = (hi - lo + E::NPTS - 1) / E::NPTS;
   if ((int64_t)blockIdx.x >= nb) return;
   float* par = reinterpret_cast<float*>(lds + E::LDS_BYTES);
-  E::PC::load(par, a.params, a.pi, a.depth, NW * 64);
+  E::PC::load(par, a.params, a.pi, a.depth, E::THREADS);
   __syncthreads();
   const double* q = a.q_n + (int64_t)inst * S::R;
   for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-    const int64_t first = lo + b * PT;
-    const int n_valid = hi - first < PT ? (int)(hi - first) : PT;
+    const int64_t first = lo + b * E::NPTS;
+    const int n_valid = hi - first < E::NPTS ? (int)(hi - first) : E::NPTS;
     E::stage(lds, a.fe.ring_X, first, n_valid, q, S::R, nullptr, 0, par);
     __syncthreads();
     E::run(lds, par, a.packed, a.depth, 0);
     const float* res = reinterpret_cast<const float*>(lds + E::RES_OFF);
-    for (int e = threadIdx.x; e < n_valid * S::D; e += blockDim.x) {
-      const int i = e / S::D, oo = e % S::D;
-      a.fe.ring_u[(first + i) * S::D + oo] = res[(oo * E::NT + 0) * PT + i];
+    // res[(oo * NT + t) * PT + j]: t the 16-vertex batch (one column each)
+    for (int e = threadIdx.x; e < S::D * E::NT * PT; e += E::THREADS) {
+      const int oo = e / (E::NT * PT), t = (e / PT) % E::NT, j = e % PT;
+      const int lp = t * PT + j;
+      if (lp < n_valid) a.fe.ring_u[(first + lp) * S::D + oo] = res[e];
     }
     __syncthreads();
   }
@@ -818,12 +837,13 @@ __device__ void eval_init_elastic(const StepArgs& a, double* jd, int64_t blk) {
 }
 
 // Trial phases of the elastic step: the decoder differences at the TV trial
-// latents (one pass), then the Jacobian at the first trial in chunks of QC
-// latent directions (value, the first difference and the chunk's tangents,
-// which the engine takes at the first difference column's latent).
+// latents (one pass), then, when `with_j`, the Jacobian at the first trial in
+// chunks of QC latent directions (value, the first difference and the
+// chunk's tangents, which the engine takes at the first difference column's
+// latent); without it the Jacobian partials come out zero.
 template <class S, int NW, int PREC, int PF>
 __device__ void eval_trials_elastic(const StepArgs& a, char* lds, double* jd, const float* par, double* qdl,
-                                    int64_t blk, int inst, bool have_qdl) {
+                                    int64_t blk, int inst, bool have_qdl, bool with_j) {
   constexpr int R = S::R, D = S::D, ROWS = PT * D;
   constexpr int QC = ElasticChunks<PREC>::QC;
   using CT = Cols<S::M, R, 1, TV, false, D2_NONE, 0>;
@@ -852,7 +872,11 @@ __device__ void eval_trials_elastic(const StepArgs& a, char* lds, double* jd, co
     }
   }
   __syncthreads();
-  for (int qb = 0; qb < R; qb += QC) {
+  if (!with_j) {
+    for (int e = threadIdx.x; e < ROWS * R; e += blockDim.x) jd[e] = 0.0;
+    __syncthreads();
+  }
+  for (int qb = 0; with_j && qb < R; qb += QC) {
     EQ::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
     __syncthreads();
     EQ::run(lds, par, a.packed, a.depth, qb);
@@ -1255,7 +1279,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
   using T = StepTraits<S, NW, PREC, PF, KIND>;
   constexpr int PAR = T::PAR;
   extern __shared__ __align__(16) char lds[];
-  __shared__ int s_last, s_abort, s_ph;
+  __shared__ int s_last, s_abort, s_ph, s_lt;
   __shared__ int64_t s_act;
   __shared__ double qdl[TV * RMAX];
   float* par = reinterpret_cast<float*>(lds + PAR);
@@ -1280,11 +1304,12 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
     if (threadIdx.x == 0) s_act = ld_c(act_phase + p);  // stable: written only by phase p-1 solves
     if (pre) {
       if (threadIdx.x == blockDim.x - 1) s_ph = ld_c(&state[inst0].phase);
+      if (KIND == PK_ELASTIC && threadIdx.x == blockDim.x - 2) s_lt = ld_c(&state[inst0].ls_tried);
       for (int i = threadIdx.x; i < TV * S::R; i += blockDim.x) qdl[i] = ld_c(&state[inst0].qd[i / S::R][i % S::R]);
     }
     __syncthreads();
     const int64_t act = s_act;
-    const int ph0 = s_ph;
+    const int ph0 = s_ph, lt0 = KIND == PK_ELASTIC ? s_lt : 0;
     __syncthreads();
     if (act == 0) break;
     target += (uint64_t)act;
@@ -1296,18 +1321,22 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
         else eval_init_elastic<S>(a, jd, blk);
       } else {
         const bool first = blk == blockIdx.x;  // phase and trial offsets preloaded
-        int ph = ph0;
+        int ph = ph0, lt = lt0;
         if (!first) {
-          if (threadIdx.x == 0) s_ph = ld_c(&state[inst].phase);  // stable until this batch arrives
+          if (threadIdx.x == 0) {
+            s_ph = ld_c(&state[inst].phase);  // stable until this batch arrives
+            if (KIND == PK_ELASTIC) s_lt = ld_c(&state[inst].ls_tried);
+          }
           __syncthreads();
           ph = s_ph;
+          lt = KIND == PK_ELASTIC ? s_lt : 0;
           __syncthreads();
         }
         if (!evaluates_trials(ph)) continue;
         if constexpr (KIND == PK_HEAT)
           eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, (p == 1 && first) ? 40 : -1, first);
-        else
-          eval_trials_elastic<S, NW, PREC, PF>(a, lds, jd, par, qdl, blk, inst, first);
+        else  // backtracking rounds evaluate the objective only (the solve re-linearises)
+          eval_trials_elastic<S, NW, PREC, PF>(a, lds, jd, par, qdl, blk, inst, first, !(ph == PH_TRIALS && lt > 0));
       }
       // arrival: the partials of this batch are complete in memory
       if (p == 1 && blk == blockIdx.x) trace_mark(a, 44);
@@ -1323,7 +1352,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       const bool last = s_last != 0;
       __syncthreads();  // every thread has read s_last before thread 0 may write it again
       if (p == 1 && blk == blockIdx.x) trace_mark(a, 46);
-      if (last) solve_instance<S::R>(a, lds, inst, p, p == max_rounds);
+      if (last) solve_instance<S::R, KIND == PK_ELASTIC>(a, lds, inst, p, p == max_rounds);
       if (p == 1 && blk == blockIdx.x) trace_mark(a, 47);
     }
     trace_mark(a, 4 * p + 1);
@@ -1595,16 +1624,16 @@ static crom_status elastic_prepare(const StepArgs& a, hipStream_t st) {
 template <class S, int NW, int PREC>
 static crom_status fe_prepare(const StepArgs& a, hipStream_t st) {
   constexpr int QC = ElasticChunks<PREC>::QC;
-  using E = Engine<S, Cols<S::M, S::R, 1, 0, false, D2_NONE, 0>, 1, NW, PREC, 0>;
+  using E = RingEngine<S, PREC>;
   if (a.fe.max_ring > 0) {
     const int lds_bytes = E::LDS_BYTES + E::PC::bytes(a.depth);
     if (lds_bytes > LDS_MAX) return fail(CROM_ERR_UNSUPPORTED, "network too deep for the LDS");
-    auto k = ring_decode_kernel<S, NW, PREC>;
+    auto k = ring_decode_kernel<S, PREC>;
     crom_status s = set_lds(k, lds_bytes);
     if (s != CROM_OK) return s;
-    int64_t gx = (a.fe.max_ring + PT - 1) / PT;
+    int64_t gx = (a.fe.max_ring + E::NPTS - 1) / E::NPTS;
     if (gx > 65535) gx = 65535;
-    hipLaunchKernelGGL(k, dim3((unsigned)gx, (unsigned)a.n_inst), dim3(NW * 64), lds_bytes, st, a);
+    hipLaunchKernelGGL(k, dim3((unsigned)gx, (unsigned)a.n_inst), dim3(E::THREADS), lds_bytes, st, a);
     s = hip_check(hipGetLastError(), "ring decode launch");
     if (s != CROM_OK) return s;
   }
