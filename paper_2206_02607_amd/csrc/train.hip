@@ -832,29 +832,32 @@ __global__ __launch_bounds__(256) void dense_dx_kernel(const float* __restrict__
   }
 }
 
-// Weight and bias gradients of one convolution: block e < d*d*6 takes
-// W[o][c][k] = sum_{b,j} dz[b][o][j] x(b, c, 4 j + k), block d*d*6 + o the
-// bias sum_{b,j} dz[b][o][j]; each thread sums a fixed stride of the (b, j)
-// pairs in FP64, then a fixed-order tree in LDS.
-constexpr int CONV_RED = 256;
+// Weight and bias gradients of one convolution, in two fixed-order stages.
+// Stage 1, block (e, chunk): e < d*d*6 takes W[o][c][k] =
+// sum_{b,j} dz[b][o][j] x(b, c, 4 j + k), e = d*d*6 + o the bias
+// sum_{b,j} dz[b][o][j], over the chunk's contiguous share of the (b, j)
+// pairs (each thread a fixed stride in FP64, then a tree in LDS) into
+// part[e][chunk].  Stage 2: each entry sums its chunks in order.
+constexpr int CONV_RED = 256, CONV_CHUNKS = 64;
 __global__ __launch_bounds__(CONV_RED) void conv_wgrad_kernel(const float* __restrict__ dz, const float* __restrict__ x,
                                                              int64_t xb, int64_t xc, int64_t xi, int B, int d,
-                                                             int64_t Lo, float* __restrict__ dW,
-                                                             float* __restrict__ db) {
+                                                             int64_t Lo, double* __restrict__ part) {
   __shared__ double red[CONV_RED];
-  const int e = blockIdx.x;
+  const int e = blockIdx.x, chunk = blockIdx.y;
   const int nw = d * d * CONV_K;
   const int64_t n = (int64_t)B * Lo;
+  const int64_t per = (n + CONV_CHUNKS - 1) / CONV_CHUNKS;
+  const int64_t t0 = chunk * per, t1 = t0 + per < n ? t0 + per : n;
   double s = 0.0;
   if (e < nw) {
     const int o = e / (d * CONV_K), c = (e / CONV_K) % d, k = e % CONV_K;
-    for (int64_t t = threadIdx.x; t < n; t += CONV_RED) {
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += CONV_RED) {
       const int64_t b = t / Lo, j = t % Lo;
       s += (double)dz[(b * d + o) * Lo + j] * (double)x[b * xb + c * xc + (CONV_S * j + k) * xi];
     }
   } else {
     const int o = e - nw;
-    for (int64_t t = threadIdx.x; t < n; t += CONV_RED) {
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += CONV_RED) {
       const int64_t b = t / Lo, j = t % Lo;
       s += (double)dz[(b * d + o) * Lo + j];
     }
@@ -865,9 +868,17 @@ __global__ __launch_bounds__(CONV_RED) void conv_wgrad_kernel(const float* __res
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    if (e < nw) dW[e] = (float)red[0];
-    else db[e - nw] = (float)red[0];
+  if (threadIdx.x == 0) part[(int64_t)e * CONV_CHUNKS + chunk] = red[0];
+}
+
+__global__ __launch_bounds__(64) void conv_wgrad_final_kernel(const double* __restrict__ part, int d,
+                                                             float* __restrict__ dW, float* __restrict__ db) {
+  const int nw = d * d * CONV_K;
+  for (int e = threadIdx.x; e < nw + d; e += blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < CONV_CHUNKS; ++c) s += part[(int64_t)e * CONV_CHUNKS + c];
+    if (e < nw) dW[e] = (float)s;
+    else db[e - nw] = (float)s;
   }
 }
 
@@ -894,7 +905,9 @@ __global__ __launch_bounds__(256) void conv_dx_kernel(const float* __restrict__ 
 struct ConvPass {
   float* a[CONV_MAXL + 1];  // a[l] = ELU(conv_l) [B][d][len[l]], l >= 1
   float *h, *q, *dq, *dh, *dz[2];
+  double* wpart;  // [d*d*6 + d][CONV_CHUNKS] weight-gradient partials
   void carve(Carve& cv, const ConvShape& c, int B) {
+    wpart = cv.take<double>((size_t)(c.d * c.d * CONV_K + c.d) * CONV_CHUNKS);
     for (int l = 1; l <= c.nl; ++l) a[l] = cv.take<float>((size_t)B * c.d * c.len[l]);
     const int64_t top = c.nl ? c.len[1] : c.len[0];
     h = cv.take<float>((size_t)B * c.hidden);
@@ -963,8 +976,10 @@ static crom_status conv_encoder_bwd(const ConvShape& c, const float* prm, const 
     const float* x;
     int64_t xb, xc, xi;
     conv_in(c, u, w, l, &x, &xb, &xc, &xi);
-    hipLaunchKernelGGL(conv_wgrad_kernel, dim3(c.d * c.d * CONV_K + c.d), dim3(CONV_RED), 0, st, w.dz[cur], x, xb, xc,
-                       xi, B, c.d, c.len[l + 1], grad + c.w[l], grad + c.b[l]);
+    hipLaunchKernelGGL(conv_wgrad_kernel, dim3(c.d * c.d * CONV_K + c.d, CONV_CHUNKS), dim3(CONV_RED), 0, st,
+                       w.dz[cur], x, xb, xc, xi, B, c.d, c.len[l + 1], w.wpart);
+    hipLaunchKernelGGL(conv_wgrad_final_kernel, dim3(1), dim3(64), 0, st, w.wpart, c.d, grad + c.w[l],
+                       grad + c.b[l]);
     if (l > 0) {
       hipLaunchKernelGGL(conv_dx_kernel, dim3(grid_for((int64_t)B * c.d * c.len[l])), dim3(256), 0, st, w.dz[cur],
                          prm + c.w[l], w.a[l], B, c.d, c.len[l], c.len[l + 1], w.dz[1 - cur]);

@@ -156,3 +156,40 @@ def test_heat_guess_vs_oracle(cuda, case, prec, tol):
         err = normwise_rel(got[i], ref)
         print(f"{prec} instance {i}: |q| {np.abs(ref).max():.3e} error {err:.2e}")
         assert err <= tol
+
+
+def test_guesses_in_round_kernels_match_persistent(cuda):
+    """A batch of more than 1,024 sample batches runs Gauss-Newton as round
+    kernels; with guesses (one accepted, one rejected, alternating) every
+    instance reproduces its single-instance persistent run bit for bit in
+    the iterate, flags, iterations, trials and objectives."""
+    import torch
+    from paper_2206_02607_amd import crom
+    from workloads import Batched2D
+    wb = Batched2D(seed=5, n_inst=12, s_min=1400, s_max=1600)
+    assert int(wb.offsets[-1]) // 16 + wb.n_inst > 1024  # the round-kernel path
+    dt = 5e-3
+    guesses = np.empty_like(wb.q0)
+    for i in range(wb.n_inst):
+        lo, hi = int(wb.offsets[i]), int(wb.offsets[i + 1])
+        if i % 2 == 0:
+            dec = mlp.MLPDecoder(wb.layers, wb.m)
+            guesses[i] = ostep.heat_step(dec, wb.samples[lo:hi].astype(np.float64), wb.q0[i], wb.mu[i], dt,
+                                         OOpts(max_iter=10, tol_step=1e-12))[0] + 1e-4
+        else:
+            guesses[i] = wb.q0[i] + 1.0
+    dec = crom.Decoder.from_layers(wb.layers, wb.m, precision="bf16", device=cuda)
+    opts = crom.GNOptions(max_iter=4, tol_step=1e-8)
+    st = crom.Stepper(dec, wb.offsets, torch.from_numpy(wb.samples).to(cuda))
+    qb = st.step(torch.from_numpy(wb.q0).to(cuda), torch.from_numpy(wb.mu).to(cuda), dt, opts,
+                 q_init=torch.from_numpy(guesses).to(cuda)).cpu().numpy()
+    ib = st.info()
+    for i in range(wb.n_inst):
+        lo, hi = int(wb.offsets[i]), int(wb.offsets[i + 1])
+        s1 = crom.Stepper(dec, [0, hi - lo], torch.from_numpy(wb.samples[lo:hi]).to(cuda))
+        q1 = s1.step(torch.from_numpy(wb.q0[i:i + 1]).to(cuda), torch.tensor([wb.mu[i]]), dt, opts,
+                     q_init=torch.from_numpy(guesses[i:i + 1]).to(cuda)).cpu().numpy()
+        np.testing.assert_array_equal(qb[i], q1[0])
+        i1 = s1.info()[0]
+        for k in ("flags", "iters", "ls_evals", "obj_first", "obj_last"):
+            assert ib[i][k] == i1[k], (i, k)
