@@ -194,7 +194,7 @@ def train_leg(args, crom, torch, dev):
                             torch.from_numpy(u0).to(dev).reshape(1, -1))[0]
     out["run"]["initial_field_error"] = float(err0)
     return out, {"params": dec.params.detach().clone(), "q0": q0.astype(np.float64), "w": w, "u0": u0,
-                 "nodes": nodes}
+                 "nodes": nodes, "enc": T.enc_params.detach().clone(), "hidden": T.hidden}
 
 
 def batched_leg(args, crom, torch, dev, trained=None):
@@ -525,6 +525,55 @@ def config3_leg(args, crom, torch, dev):
     return out
 
 
+def guess_leg(args, crom, torch, dev, trained):
+    """The encoder-based initial guess with the trained network and encoder:
+    the 4 held-out diffusivities from the encoded initial field, 500 random
+    interior samples of the 128 x 128 nodes, one step 20 times the rollout's
+    (dt = 2e-3, a large change of the field), Gauss-Newton with at most 3
+    iterations from q_n, and from the encoder's latent of the full-field
+    update (crom_heat_guess over all 16,384 nodes, then crom_step_guess),
+    with budgets of 1 and 3 iterations.  Reported per start: objective after
+    the step, iterations, and the objective at the start; the guess's own
+    cost is timed."""
+    from workloads import rng as _rng
+    w = trained["w"]
+    nodes = trained["nodes"].to(torch.float32)
+    P = nodes.shape[0]
+    g = _rng(args.seed + 9)
+    idx = np.arange(P).reshape(w.grid, w.grid)[1:-1, 1:-1].ravel()
+    samples = nodes[torch.from_numpy(np.sort(g.choice(idx, size=500, replace=False))).to(dev)].contiguous()
+    n = len(w.mu_test)
+    dt = 20 * w.dt
+    dec = crom.Decoder(trained["params"], w.m, w.r, w.d, w.width, w.depth, args.prec, dev)
+    st = crom.Stepper(dec, np.arange(n + 1) * 500, samples.repeat(n, 1))
+    nu = torch.from_numpy(np.asarray(w.mu_test, np.float64)).to(dev)
+    q_n = torch.from_numpy(np.tile(trained["q0"], (n, 1))).to(dev)
+    guess = crom.heat_guess(dec, trained["enc"], trained["hidden"], nodes, q_n, nu, dt)
+    for _ in range(3):
+        crom.heat_guess(dec, trained["enc"], trained["hidden"], nodes, q_n, nu, dt)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e[0].record()
+    for _ in range(10):
+        crom.heat_guess(dec, trained["enc"], trained["hidden"], nodes, q_n, nu, dt)
+    e[1].record()
+    torch.cuda.synchronize()
+    out = {"workload": f"{n} held-out diffusivities, 500 samples, one step of dt {dt}, Gauss-Newton <= 1 or 3 iterations",
+           "guess_ms": e[0].elapsed_time(e[1]) / 10}
+    for it in (1, 3):
+        opts = crom.GNOptions(max_iter=it, tol_step=TOL_STEP)
+        for name, q_init in (("from_q_n", None), ("from_encoder_guess", guess)):
+            st.step(q_n, nu, dt, opts, q_init=q_init)
+            inf = st.info()
+            out[f"{name}_{it}_iter"] = {"obj_last_mean": float(np.mean(inf["obj_last"])),
+                                        "obj_first_mean": float(np.mean(inf["obj_first"])),
+                                        "iters_mean": float(np.mean(inf["iters"])),
+                                        "flags": [int(f) for f in inf["flags"]]}
+    # the objective at the guess itself: a zero-iteration step from it
+    st.step(guess, nu, dt, crom.GNOptions(max_iter=1, linearized=True))
+    out["objective_at_guess_mean"] = float(np.mean(st.info()["obj_first"]))
+    return out
+
+
 def fe_leg(args, crom, torch, dev):
     """Corotated elasticity with finite-element forces: the falling bar of
     64 x 16 x 16 vertices as 85,050 jittered linear tetrahedra, 500 sample
@@ -694,6 +743,7 @@ def main():
     training, trained = train_leg(args, crom, torch, dev) if args.train_time_steps > 0 else (None, None)
     batched = batched_leg(args, crom, torch, dev, trained) if args.batched_steps > 0 else None
     sampling = sampling_leg(args, crom, torch, dev, trained) if trained and args.sampling_rounds > 0 else None
+    guess = guess_leg(args, crom, torch, dev, trained) if trained else None
     siren = siren_leg(args, crom, torch, dev) if args.siren else None
     fe = fe_leg(args, crom, torch, dev) if args.fe_steps > 0 else None
     cpu = cpu_baseline(wl, nodes, args.cpu_steps) if args.cpu_steps > 0 else None
@@ -721,6 +771,7 @@ def main():
         "training": training,
         "batched": batched,
         "sampling": sampling,
+        "encoder_guess": guess,
         "siren": siren,
         "corotated_fe": fe,
         "cpu_baseline": cpu,
