@@ -195,7 +195,7 @@ template <class S, int NW, int PREC, bool XT, int D2, int NQ, int HB = 0,
 static crom_status run_pass(const DecodeArgs& a, hipStream_t st) {
   if constexpr (!XT && D2 == D2_NONE && NQ == 0) {
     using C = Cols<S::M, S::R, 1, 0, false, D2_NONE, 0>;
-    return launch_decode<S, C, 4, PREC>(a, st);  // 64 points per workgroup
+    return launch_decode<S, C, DecodeTune<S, PREC>::NBV, PREC>(a, st);
   } else {
     using C = Cols<S::M, S::R, 1, 0, XT, D2, NQ, HB, NH>;
     return launch_decode<S, C, 1, PREC>(a, st);
