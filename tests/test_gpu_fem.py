@@ -232,3 +232,23 @@ def test_full_size_batched_fe_kernel(cuda):
         print(f"instance {i}: ring {b - a} vertices, FE kernel error {err:.2e}, flags {info['flags'][i]}")
         assert err <= 1e-9
         assert info["flags"][i] == 0
+
+
+def test_instance_without_samples(cuda, small):
+    """A batch whose middle instance has no samples: that instance ends at
+    once as SINGULAR with q_{n+1} = q_n, the others match their runs alone."""
+    from paper_2206_02607_amd import crom
+    layers, X, tets, samples, q0 = small
+    dec = crom.Decoder.from_layers(layers, 3, precision="fp32", device=cuda)
+    sets = [samples[:20], np.zeros(0, dtype=np.int64), samples[20:]]
+    g = rng(45)
+    qn = q0[None] + 0.02 * g.uniform(-1, 1, size=(3, q0.size))
+    coef = np.tile(_coef(), (3, 1))
+    opts = crom.GNOptions(max_iter=3, tol_step=1e-8)
+    qb, ib, incb, _, sm = _run(crom, dec, X, tets, sets, coef, qn, None, opts, cuda)
+    assert ib["flags"][1] == crom.FLAG_SINGULAR
+    np.testing.assert_array_equal(qb[1], qn[1])
+    for i in (0, 2):
+        q1, i1, _, _, _ = _run(crom, dec, X, tets, [sets[i]], coef[i], qn[i], None, opts, cuda)
+        np.testing.assert_array_equal(qb[i], q1[0])
+        assert ib[i].tobytes() == i1[0].tobytes()
