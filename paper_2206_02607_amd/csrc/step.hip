@@ -27,7 +27,13 @@
 // per-sample FP64 update (F = I + du/dX, div P through the Hessian,
 // velocity from the latent Jacobian, symplectic Euler) giving
 // rho_0 = u_{n+1} - u(q_n) = dt v_{n+1} directly; phase 0 then only sums
-// the partials of the stored Jacobian and rho_0.
+// the partials of the stored Jacobian and rho_0.  Corotated elasticity with
+// finite-element forces replaces the x-Hessian passes by a decode of the
+// samples' one-ring and a per-sample FP64 force assembly over the incident
+// tetrahedra (fe_prepare); the inversion is the same.  An optional initial
+// guess per instance costs one round (PH_GUESS) and becomes the start when
+// its objective is lower.  Large batches run the same phases as round
+// kernels (one evaluation launch and one solve launch per round).
 // The residual is the paper's f_{n+1} - g(q) written incrementally: over a
 // time step g moves by a small fraction of its size, and a difference
 // carried through the network keeps its rounding error relative to itself,
