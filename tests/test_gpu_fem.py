@@ -252,3 +252,34 @@ def test_instance_without_samples(cuda, small):
         q1, i1, _, _, _ = _run(crom, dec, X, tets, [sets[i]], coef[i], qn[i], None, opts, cuda)
         np.testing.assert_array_equal(qb[i], q1[0])
         assert ib[i].tobytes() == i1[0].tobytes()
+
+
+def test_initial_guess_in_fe_step(cuda, small):
+    """crom_step_guess on the FE step (the elastic persistent kernel): a
+    worse guess leaves the step bit-identical to crom_step (one more round);
+    the converged latent of a long run as the guess ends one iteration at
+    an objective no higher than three iterations from q_n reach."""
+    import torch
+    from paper_2206_02607_amd import crom
+    layers, X, tets, samples, q0 = small
+    dec = crom.Decoder.from_layers(layers, 3, precision="fp32", device=cuda)
+    sm = crom.FEStencil(X, tets, [samples], cuda)
+    st = crom.Stepper(dec, sm.offsets, sm.y, pde="corotated_fe", mesh=sm)
+    coef = torch.from_numpy(_coef()[None]).to(cuda)
+    qn = torch.from_numpy(q0[None]).to(cuda)
+    q_long = st.step(qn, coef, DT, crom.GNOptions(max_iter=20, tol_step=1e-12)).clone()
+    obj_long = st.info()["obj_last"][0]
+    q3 = st.step(qn, coef, DT, crom.GNOptions(max_iter=3, tol_step=1e-12)).cpu().numpy()
+    i3 = st.info()[0]
+    q_bad = st.step(qn, coef, DT, crom.GNOptions(max_iter=3, tol_step=1e-12), q_init=qn + 0.5).cpu().numpy()
+    ib = st.info()[0]
+    np.testing.assert_array_equal(q_bad, q3)
+    for k in ("flags", "iters", "ls_evals", "obj_first", "obj_last"):
+        assert ib[k] == i3[k], k
+    assert ib["rounds"] == i3["rounds"] + 1
+    st.step(qn, coef, DT, crom.GNOptions(max_iter=1, tol_step=1e-12), q_init=q_long)
+    ig = st.info()[0]
+    print(f"objective: q_n {i3['obj_first']:.4e}, 3 iterations {i3['obj_last']:.4e}, long run {obj_long:.4e}, "
+          f"1 iteration from the guess {ig['obj_last']:.4e}")
+    assert ig["obj_first"] == i3["obj_first"]
+    assert ig["obj_last"] <= i3["obj_last"] * (1 + 1e-9)
