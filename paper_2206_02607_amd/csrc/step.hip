@@ -139,7 +139,7 @@ __device__ __forceinline__ uint64_t gn_initial_word(int w, const double* q_n, in
 
 struct WsLayout {
   size_t blk_start, blk_inst, first_blk, nblk, sync, act_phase, inst_cnt, targets, rho0, partials,
-      state, jets, total;
+      state, jets, work, work_cnt, total;
   int64_t nblk_max;
   int nred;
   int nj;  // FP32 values per sample in the jets buffer (0: none)
@@ -179,6 +179,8 @@ static WsLayout ws_layout(int r, int d, int m, int n_inst, int64_t total) {
   L.partials = o;  o = align256(o + 8 * (size_t)L.nblk_max * L.nred);
   L.state = o;     o = align256(o + sizeof(GNState) * (size_t)n_inst);
   L.jets = o;      o = align256(o + 4 * (size_t)total * L.nj);
+  L.work = o;      o = align256(o + 4 * 2 * (size_t)L.nblk_max);  // round kernels: two batch lists
+  L.work_cnt = o;  o = align256(o + 16);
   L.total = o;
   return L;
 }
@@ -1008,7 +1010,7 @@ __device__ bool wave_chol_solve(const double* up, const double* b, double& xk) {
 // Jacobian), so a trial accepted there is followed by a re-linearisation
 // round; otherwise every round carries J at its first trial.
 template <int R, bool LAZY = false>
-__device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bool is_last) {
+__device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bool is_last) {
   constexpr int NA = R * (R + 1) / 2;
   constexpr int NRED = NA + R + TV;
   constexpr int NWORD = sizeof(GNState) / 8;
@@ -1243,9 +1245,11 @@ __device__ void solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
   }
   wait_mem();
   __syncthreads();
+  const bool cont = s_done == 0;
   if (threadIdx.x == 0)
     atomicAdd(reinterpret_cast<unsigned long long*>(wsp<uint64_t>(a, a.L.sync) + SYNC_SOLVED), 1ull);
   __syncthreads();
+  return cont;  // the instance takes part in the next round
 }
 
 // ---------------------------------------------------------------------------
@@ -1515,15 +1519,23 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_ph, s_lt;
   __shared__ double qdl[TV * RMAX];
+  // Round p >= 1 evaluates the batches that the solves of round p - 1 listed
+  // for their continuing instances (list p % 2); this round's solves fill
+  // the other list, whose count is cleared here (the solves run after this
+  // kernel on the same stream).  Round 0 evaluates every batch.
+  int64_t* work_cnt = wsp<int64_t>(a, a.L.work_cnt);
+  if (blockIdx.x == 0 && threadIdx.x == 0) work_cnt[(p + 1) % 2] = 0;
   if (ld_c(wsp<int64_t>(a, a.L.act_phase) + p) == 0) return;  // uniform: nothing active in this round
-  const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
+  const int64_t nblk = p == 0 ? *wsp<int64_t>(a, a.L.nblk) : work_cnt[p % 2];
   if ((int64_t)blockIdx.x >= nblk) return;
+  const int32_t* list = wsp<int32_t>(a, a.L.work) + (int64_t)(p % 2) * a.L.nblk_max;
   float* par = reinterpret_cast<float*>(lds + T::PAR);
   T::E0::PC::load(par, a.params, a.pi, a.depth, NW * 64);
   __syncthreads();
   const int32_t* blk_inst = wsp<int32_t>(a, a.L.blk_inst);
   const GNState* state = wsp<GNState>(a, a.L.state);
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+  for (int64_t it = blockIdx.x; it < nblk; it += gridDim.x) {
+    const int64_t blk = p == 0 ? it : (int64_t)list[it];
     const int inst = blk_inst[blk];
     if (p == 0) {
       eval_jets_batch<S, NW, PREC, PF>(a, lds, par, blk);
@@ -1558,7 +1570,17 @@ __global__ __launch_bounds__(NTH) void gn_solve_kernel(StepArgs a, int p, int is
   const int ph = s_ph;
   const bool active = p == 0 ? ph == PH_INIT : evaluates_trials(ph);
   if (!active) return;
-  solve_instance<R, true>(a, lds, inst, p, is_last != 0);
+  if (!solve_instance<R, true>(a, lds, inst, p, is_last != 0)) return;
+  // list this instance's batches for the next round (any order: each batch
+  // keeps its own partials slot and the solve sums them in batch order)
+  __shared__ int64_t s_base;
+  const int32_t b0 = first_blk[inst], b1 = first_blk[inst + 1];
+  if (threadIdx.x == 0)
+    s_base = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(wsp<int64_t>(a, a.L.work_cnt) + (p + 1) % 2),
+                                (unsigned long long)(b1 - b0));
+  __syncthreads();
+  int32_t* list = wsp<int32_t>(a, a.L.work) + (int64_t)((p + 1) % 2) * a.L.nblk_max;
+  for (int32_t i = threadIdx.x; i < b1 - b0; i += blockDim.x) list[s_base + i] = b0 + i;
 }
 
 template <class S, int NW, int PREC, int PF, int WPE>
