@@ -848,7 +848,10 @@ __device__ void eval_init_elastic(const StepArgs& a, double* jd, int64_t blk) {
 // latents (one pass), then, when `with_j`, the Jacobian at the first trial in
 // chunks of QC latent directions (value, the first difference and the
 // chunk's tangents, which the engine takes at the first difference column's
-// latent); without it the Jacobian partials come out zero.
+// latent); without it the Jacobian partials come out zero.  With one trial
+// per round the first chunk's difference column is the trial's (the same
+// column arithmetic), so a round with the Jacobian takes the residual from
+// that chunk and runs no separate trial pass.
 template <class S, int NW, int PREC, int PF>
 __device__ void eval_trials_elastic(const StepArgs& a, char* lds, double* jd, const float* par, double* qdl,
                                     int64_t blk, int inst, bool have_qdl, bool with_j) {
@@ -868,18 +871,19 @@ __device__ void eval_trials_elastic(const StepArgs& a, char* lds, double* jd, co
   const int64_t rem = a.offsets[inst + 1] - first;
   const int n_valid = rem < PT ? (int)rem : PT;
   const double* qn = a.q_n + (int64_t)inst * R;
-  ET::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
-  __syncthreads();
-  ET::run(lds, par, a.packed, a.depth, 0);
-  {
+  const double* rho0 = wsp<double>(a, a.L.rho0);
+  const bool merged = with_j && TV == 1;
+  if (!merged) {
+    ET::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
+    __syncthreads();
+    ET::run(lds, par, a.packed, a.depth, 0);
     const float* res = reinterpret_cast<const float*>(lds + ET::RES_OFF);
-    const double* rho0 = wsp<double>(a, a.L.rho0);
     for (int e = threadIdx.x; e < ROWS * TV; e += blockDim.x) {
       const int row = e / TV, t = e % TV, i = row / D, oo = row % D;
       rho[e] = i < n_valid ? rho0[first * D + row] - (double)res[(oo * ET::NT + CT::F0 + t) * PT + i] : 0.0;
     }
+    __syncthreads();
   }
-  __syncthreads();
   if (!with_j) {
     for (int e = threadIdx.x; e < ROWS * R; e += blockDim.x) jd[e] = 0.0;
     __syncthreads();
@@ -892,6 +896,12 @@ __device__ void eval_trials_elastic(const StepArgs& a, char* lds, double* jd, co
     for (int e = threadIdx.x; e < ROWS * QC; e += blockDim.x) {
       const int row = e / QC, c = e % QC, i = row / D, oo = row % D;
       jd[row * R + qb + c] = i < n_valid ? (double)res[(oo * EQ::NT + CQ::Q0 + c) * PT + i] : 0.0;
+    }
+    if (merged && qb == 0) {
+      for (int row = threadIdx.x; row < ROWS; row += blockDim.x) {
+        const int i = row / D, oo = row % D;
+        rho[row] = i < n_valid ? rho0[first * D + row] - (double)res[(oo * EQ::NT + CQ::F0) * PT + i] : 0.0;
+      }
     }
     __syncthreads();
   }
