@@ -139,7 +139,7 @@ __device__ __forceinline__ uint64_t gn_initial_word(int w, const double* q_n, in
 
 struct WsLayout {
   size_t blk_start, blk_inst, first_blk, nblk, sync, act_phase, inst_cnt, targets, rho0, partials,
-      state, jets, work, work_cnt, total;
+      state, jets, work, work_cnt, jbuf, bcnt, total;
   int64_t nblk_max;
   int nred;
   int nj;  // FP32 values per sample in the jets buffer (0: none)
@@ -181,6 +181,11 @@ static WsLayout ws_layout(int r, int d, int m, int n_inst, int64_t total) {
   L.jets = o;      o = align256(o + 4 * (size_t)total * L.nj);
   L.work = o;      o = align256(o + 4 * 2 * (size_t)L.nblk_max);  // round kernels: two batch lists
   L.work_cnt = o;  o = align256(o + 16);
+  // elastic step: each batch's Jacobian rows and residuals, assembled from
+  // the workgroups of its latent-tangent chunks, and their arrival counts
+  const size_t jrows = L.nj ? (size_t)PT * d * (r + TV) : 0;
+  L.jbuf = o;      o = align256(o + 8 * (size_t)L.nblk_max * jrows);
+  L.bcnt = o;      o = align256(o + (L.nj ? 4 * (size_t)L.nblk_max : 0));
   L.total = o;
   return L;
 }
@@ -332,6 +337,7 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(StepArgs a) {
     const int64_t base = in_lds ? lo_off[lo] : a.offsets[lo];
     blk_start[b] = base + (int64_t)(b - fbp[lo]) * PT;
     blk_inst[b] = lo;
+    if (a.L.nj) wsp<uint32_t>(a, a.L.bcnt)[b] = 0;
   }
   // state: the phase and flags words of every instance (the first solve
   // forms the rest)
@@ -844,23 +850,29 @@ __device__ void eval_init_elastic(const StepArgs& a, double* jd, int64_t blk) {
   __syncthreads();
 }
 
-// Trial phases of the elastic step: the decoder differences at the TV trial
-// latents (one pass), then, when `with_j`, the Jacobian at the first trial in
-// chunks of QC latent directions (value, the first difference and the
-// chunk's tangents, which the engine takes at the first difference column's
-// latent); without it the Jacobian partials come out zero.  With one trial
-// per round the first chunk's difference column is the trial's (the same
-// column arithmetic), so a round with the Jacobian takes the residual from
-// that chunk and runs no separate trial pass.
+// Trial phases of the elastic step, one latent-tangent chunk `ch` of one
+// batch per call.  A round without the Jacobian (after a rejected trial)
+// runs on chunk 0 alone: the decoder differences at the TV trial latents
+// (one pass), zero Jacobian partials.  A round with the Jacobian at the
+// first trial gives each chunk of QC latent directions its own workgroup
+// (value, the first difference and the chunk's tangents, which the engine
+// takes at the first difference column's latent); the chunks store their
+// Jacobian columns, chunk 0 also the residuals, and the last chunk to
+// arrive stages the whole batch and forms its partials.  With one trial
+// per round the residual comes from chunk 0's difference column (the same
+// column arithmetic as the trial pass).  Returns whether this workgroup
+// formed the batch's partials.
 template <class S, int NW, int PREC, int PF>
-__device__ void eval_trials_elastic(const StepArgs& a, char* lds, double* jd, const float* par, double* qdl,
-                                    int64_t blk, int inst, bool have_qdl, bool with_j) {
+__device__ bool eval_trials_elastic(const StepArgs& a, char* lds, double* jd, const float* par, double* qdl,
+                                    int64_t blk, int ch, int inst, bool have_qdl, bool with_j) {
   constexpr int R = S::R, D = S::D, ROWS = PT * D;
   constexpr int QC = ElasticChunks<PREC>::QC;
+  constexpr int NCH = R / QC;
   using CT = Cols<S::M, R, 1, TV, false, D2_NONE, 0>;
   using ET = Engine<S, CT, 1, NW, PREC, PF>;
   using CQ = Cols<S::M, R, 1, 1, false, D2_NONE, QC>;
   using EQ = Engine<S, CQ, 1, NW, PREC, PF>;
+  __shared__ int s_lastc;
   double* rho = jd + ROWS * R;
   const GNState* st = wsp<GNState>(a, a.L.state) + inst;
   if (!have_qdl) {
@@ -873,7 +885,7 @@ __device__ void eval_trials_elastic(const StepArgs& a, char* lds, double* jd, co
   const double* qn = a.q_n + (int64_t)inst * R;
   const double* rho0 = wsp<double>(a, a.L.rho0);
   const bool merged = with_j && TV == 1;
-  if (!merged) {
+  if (!merged && ch == 0) {
     ET::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
     __syncthreads();
     ET::run(lds, par, a.packed, a.depth, 0);
@@ -884,29 +896,49 @@ __device__ void eval_trials_elastic(const StepArgs& a, char* lds, double* jd, co
     }
     __syncthreads();
   }
+  double* part = wsp<double>(a, a.L.partials) + blk * a.L.nred;
   if (!with_j) {
     for (int e = threadIdx.x; e < ROWS * R; e += blockDim.x) jd[e] = 0.0;
     __syncthreads();
-  }
-  for (int qb = 0; with_j && qb < R; qb += QC) {
-    EQ::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
+    batch_partials<R, ROWS>(jd, rho, part);
     __syncthreads();
-    EQ::run(lds, par, a.packed, a.depth, qb);
-    const float* res = reinterpret_cast<const float*>(lds + EQ::RES_OFF);
-    for (int e = threadIdx.x; e < ROWS * QC; e += blockDim.x) {
-      const int row = e / QC, c = e % QC, i = row / D, oo = row % D;
-      jd[row * R + qb + c] = i < n_valid ? (double)res[(oo * EQ::NT + CQ::Q0 + c) * PT + i] : 0.0;
-    }
-    if (merged && qb == 0) {
-      for (int row = threadIdx.x; row < ROWS; row += blockDim.x) {
-        const int i = row / D, oo = row % D;
-        rho[row] = i < n_valid ? rho0[first * D + row] - (double)res[(oo * EQ::NT + CQ::F0) * PT + i] : 0.0;
-      }
-    }
-    __syncthreads();
+    return true;
   }
-  batch_partials<R, ROWS>(jd, rho, wsp<double>(a, a.L.partials) + blk * a.L.nred);
+  const int qb = ch * QC;
+  EQ::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
   __syncthreads();
+  EQ::run(lds, par, a.packed, a.depth, qb);
+  const float* res = reinterpret_cast<const float*>(lds + EQ::RES_OFF);
+  double* jg = wsp<double>(a, a.L.jbuf) + blk * (int64_t)(ROWS * (R + TV));  // [ROWS][R], then [ROWS][TV]
+  for (int e = threadIdx.x; e < ROWS * QC; e += blockDim.x) {
+    const int row = e / QC, c = e % QC, i = row / D, oo = row % D;
+    st_c(jg + row * R + qb + c, i < n_valid ? (double)res[(oo * EQ::NT + CQ::Q0 + c) * PT + i] : 0.0);
+  }
+  if (ch == 0) {
+    for (int e = threadIdx.x; e < ROWS * TV; e += blockDim.x) {
+      const int row = e / TV, i = row / D, oo = row % D;
+      const double v = !merged ? rho[e]
+                     : (i < n_valid ? rho0[first * D + row] - (double)res[(oo * EQ::NT + CQ::F0) * PT + i] : 0.0);
+      st_c(jg + ROWS * R + e, v);
+    }
+  }
+  // arrival of this chunk: its columns are complete in memory
+  wait_mem();
+  __syncthreads();
+  uint32_t* bcnt = wsp<uint32_t>(a, a.L.bcnt) + blk;
+  if (threadIdx.x == 0) s_lastc = atomicAdd(bcnt, 1u) + 1 == (uint32_t)NCH;
+  __syncthreads();
+  const bool last = s_lastc != 0;
+  __syncthreads();
+  if (!last) return false;
+  // every chunk has arrived: stage the batch and clear its count for the
+  // next round (whose chunks start only after this instance is solved)
+  for (int e = threadIdx.x; e < ROWS * (R + TV); e += blockDim.x) jd[e] = ld_c(jg + e);
+  if (threadIdx.x == 0) st_c(bcnt, 0u);
+  __syncthreads();
+  batch_partials<R, ROWS>(jd, rho, part);
+  __syncthreads();
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -1307,6 +1339,11 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
   T::E0::PC::load(par, a.params, a.pi, a.depth, NW * 64);
   __syncthreads();
   const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
+  // the elastic kind spreads a batch's latent-tangent chunks over NCH
+  // workgroups (work item w = batch w / NCH, chunk w % NCH)
+  constexpr int NCH = KIND == PK_ELASTIC ? S::R / ElasticChunks<PREC>::QC : 1;
+  static_assert(KIND != PK_ELASTIC || S::R % ElasticChunks<PREC>::QC == 0, "whole chunks");
+  const int64_t nwork = nblk * NCH;
   const int32_t* blk_inst = wsp<int32_t>(a, a.L.blk_inst);
   const int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
   GNState* state = wsp<GNState>(a, a.L.state);
@@ -1319,8 +1356,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
     // One memory round trip for the round's active count and, for this
     // workgroup's first batch, its instance's phase and trial offsets (all
     // final once the previous phase's solves are counted).
-    const bool pre = p > 0 && (int64_t)blockIdx.x < nblk;
-    const int inst0 = pre ? blk_inst[blockIdx.x] : 0;
+    const bool pre = p > 0 && (int64_t)blockIdx.x < nwork;
+    const int inst0 = pre ? blk_inst[blockIdx.x / NCH] : 0;
     if (threadIdx.x == 0) s_act = ld_c(act_phase + p);  // stable: written only by phase p-1 solves
     if (pre) {
       if (threadIdx.x == blockDim.x - 1) s_ph = ld_c(&state[inst0].phase);
@@ -1334,13 +1371,16 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
     if (act == 0) break;
     target += (uint64_t)act;
     trace_mark(a, 4 * p);
-    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+      const int64_t blk = w / NCH;
+      const int ch = (int)(w % NCH);
       const int inst = blk_inst[blk];
       if (p == 0) {
         if constexpr (KIND == PK_HEAT) eval_jets_batch<S, NW, PREC, PF>(a, lds, par, blk);
-        else eval_init_elastic<S>(a, jd, blk);
+        else if (ch == 0) eval_init_elastic<S>(a, jd, blk);
+        else continue;
       } else {
-        const bool first = blk == blockIdx.x;  // phase and trial offsets preloaded
+        const bool first = w == blockIdx.x;  // phase and trial offsets preloaded
         int ph = ph0, lt = lt0;
         if (!first) {
           if (threadIdx.x == 0) {
@@ -1355,14 +1395,17 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
         if (!evaluates_trials(ph)) continue;
         if constexpr (KIND == PK_HEAT)
           eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, (p == 1 && first) ? 40 : -1, first);
-        else  // backtracking rounds evaluate the objective only (the solve re-linearises)
-          eval_trials_elastic<S, NW, PREC, PF>(a, lds, jd, par, qdl, blk, inst, first, !(ph == PH_TRIALS && lt > 0));
+        else {  // backtracking rounds evaluate the objective only (the solve re-linearises)
+          const bool with_j = !(ph == PH_TRIALS && lt > 0);
+          if (!with_j && ch != 0) continue;
+          if (!eval_trials_elastic<S, NW, PREC, PF>(a, lds, jd, par, qdl, blk, ch, inst, first, with_j)) continue;
+        }
       }
       // arrival: the partials of this batch are complete in memory
-      if (p == 1 && blk == blockIdx.x) trace_mark(a, 44);
+      if (p == 1 && w == blockIdx.x) trace_mark(a, 44);
       wait_mem();
       __syncthreads();
-      if (p == 1 && blk == blockIdx.x) trace_mark(a, 45);
+      if (p == 1 && w == blockIdx.x) trace_mark(a, 45);
       if (threadIdx.x == 0) {
         const uint32_t nb = (uint32_t)(first_blk[inst + 1] - first_blk[inst]);
         const uint32_t old = atomicAdd(inst_cnt + inst, 1u);
@@ -1371,9 +1414,9 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       __syncthreads();
       const bool last = s_last != 0;
       __syncthreads();  // every thread has read s_last before thread 0 may write it again
-      if (p == 1 && blk == blockIdx.x) trace_mark(a, 46);
+      if (p == 1 && w == blockIdx.x) trace_mark(a, 46);
       if (last) solve_instance<S::R, KIND == PK_ELASTIC>(a, lds, inst, p, p == max_rounds);
-      if (p == 1 && blk == blockIdx.x) trace_mark(a, 47);
+      if (p == 1 && w == blockIdx.x) trace_mark(a, 47);
     }
     trace_mark(a, 4 * p + 1);
     // wait until every instance active in this phase has been solved
@@ -1722,7 +1765,7 @@ static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
     s = a.fe.on ? fe_prepare<S, NW, PREC>(a, st) : elastic_prepare<S, NW, PREC>(a, st);
     if (s != CROM_OK) return s;
   }
-  int64_t g = a.L.nblk_max;
+  int64_t g = a.L.nblk_max * (KIND == PK_ELASTIC ? S::R / ElasticChunks<PREC>::QC : 1);
   if (g > resident) g = resident;
   if (g < 1) g = 1;
   void* args[] = {&a, &max_rounds};
