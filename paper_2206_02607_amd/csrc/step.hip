@@ -969,8 +969,76 @@ struct WaveMat {
 // solves L y = b and L^T x = y.  A pivot (the value under the square root)
 // that is not finite or not above thresh = 1e-14 * max diag(A) fails the
 // factorisation (returns false).  On success lane k < R returns x_k.
+//
+// For r <= 8 every lane factors the whole matrix in registers from LDS
+// reads at uniform addresses (no cross-lane traffic), left-looking: column
+// j's pivot and entries subtract the earlier columns' products in the same
+// order as the right-looking updates, and the substitutions divide by the
+// same diagonal, so both forms give the same bits.  Not inlined: its 36
+// register-held entries then do not add to the registers live at the call.
+struct CholOut {
+  double x;
+  int ok;
+};
+template <int R>
+__device__ __attribute__((noinline)) CholOut lane_chol_solve(const double* up, const double* b) {
+  const int lane = threadIdx.x & 63;
+  double L[R][R];
+  double dmax = -1.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int k = i; k < R; ++k) {
+      const double v = up[i * R - i * (i - 1) / 2 + (k - i)];
+      L[k][i] = v;
+      if (i == k) dmax = fmax(dmax, v);
+    }
+  const double thresh = 1e-14 * dmax;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    double d = L[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+    if (!(isfinite(d) && d > thresh)) return CholOut{0.0, 0};  // uniform across the wave
+    const double ljj = sqrt(d);
+    const double inv = 1.0 / ljj;
+    L[j][j] = ljj;
+#pragma unroll
+    for (int i = j + 1; i < R; ++i) {
+      double v = L[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+      L[i][j] = v * inv;
+    }
+  }
+  double y[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) y[i] = b[i];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {  // L y = b
+    y[j] = y[j] / L[j][j];
+#pragma unroll
+    for (int i = j + 1; i < R; ++i) y[i] -= L[i][j] * y[j];
+  }
+#pragma unroll
+  for (int j = R - 1; j >= 0; --j) {  // L^T x = y
+    y[j] = y[j] / L[j][j];
+#pragma unroll
+    for (int i = 0; i < j; ++i) y[i] -= L[j][i] * y[j];
+  }
+  double x = 0.0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) x = lane == k ? y[k] : x;
+  return CholOut{x, 1};
+}
+
 template <int R>
 __device__ bool wave_chol_solve(const double* up, const double* b, double& xk) {
+  if constexpr (R <= 8) {
+    const CholOut o = lane_chol_solve<R>(up, b);
+    xk = o.x;
+    return o.ok != 0;
+  }
   const int lane = threadIdx.x & 63;
   WaveMat<R> A;
   double dmax = -1.0;
