@@ -150,6 +150,30 @@ def test_batched_equals_single(cuda):
         assert ib[i].tobytes() == i1[0].tobytes()
 
 
+def test_batched_beyond_resident_grid(cuda):
+    """Twelve instances (384 sample batches, 1,536 latent-tangent chunk work
+    items, several per resident workgroup and round): sampled instances
+    reproduce their single-instance steps bit for bit in the iterate,
+    targets and info.  The instances reject trials (5 to 10 trials for 4
+    iterations), so rounds with and without the Jacobian both occur."""
+    from paper_2206_02607_amd import crom
+    w, layers, X, clamp, dec = _setup("bf16", cuda)
+    g = rng(9)
+    n = 12
+    qn = w.q0[None] + 0.05 * g.uniform(-1, 1, size=(n, w.r))
+    qp = qn - 0.02 * g.uniform(-1, 1, size=(n, w.r))
+    coef = np.stack([_coef(w, (0.0, 0.0, -9.81 * (1 + 0.5 * i))) for i in range(n)])
+    opts = crom.GNOptions(max_iter=4, tol_step=1e-8)
+    qb, tb, ib, _ = _run(dec, X, clamp, coef, qn, qp, w.dt, opts, cuda, n_inst=n)
+    S = X.shape[0]
+    print(f"iterations {ib['iters'].tolist()}, trials {ib['ls_evals'].tolist()}, rounds {ib['rounds'].tolist()}")
+    for i in (0, 5, 11):
+        q1, t1, i1, _ = _run(dec, X, clamp, coef[i], qn[i], qp[i], w.dt, opts, cuda)
+        np.testing.assert_array_equal(qb[i], q1[0])
+        np.testing.assert_array_equal(tb[i * S:(i + 1) * S], t1)
+        assert ib[i].tobytes() == i1[0].tobytes()
+
+
 def test_three_step_rollout_fp32(cuda):
     """Three linearised steps with the velocity carried by q_prev follow the
     oracle's rollout (the same update applied three times in FP64)."""
