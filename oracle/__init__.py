@@ -16,7 +16,9 @@ inversion  Cholesky, Gauss-Newton with backtracking, linearised inversion
 step       the three-stage latent step and rollouts
 elastic    neo-Hookean stress, its derivative and the explicit elastic update
 fem        corotated stress, tetrahedron forces on the samples' one-ring, FE update
-train      encoder/decoder reverse-mode gradients, MSE loss, Adam
+train      encoder/decoder reverse-mode gradients, MSE loss, Adam, the
+           standardization of the training data and its fold into the networks
+pod        proper orthogonal decomposition baseline (linear basis, same step)
 sampling   robust greedy selection of the integration samples
 
 Parity status of each function is stated in its docstring; every function

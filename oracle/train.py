@@ -230,3 +230,61 @@ def flatten(layers: Sequence[Layer]) -> List[np.ndarray]:
     for W, b in layers:
         out += [W, b]
     return out
+
+
+# ---------------------------------------------------------------------------
+# Standardization (Sec. "Training Details"): the training fields are mapped
+# to zero mean and unit variance over the whole training set, and the
+# spatial coordinates of the ELU networks are standardized per axis over the
+# nodes.  Readings: the variance is the population variance (divide by the
+# number of values, so the standardized data has variance exactly 1); one
+# mean and one deviation for all field values (every output channel alike).
+# After training, the two affine maps are folded into the networks so that
+# the step runs in physical units:
+#   g(x, q) = u_std * g_s((x - x_mean) / x_std, q) + u_mean
+#   e(u)    = e_s((u - u_mean) / u_std)
+# Layer 1 of the decoder absorbs the coordinate map, the output layer the
+# field map, and the encoder's first layer (dense E1 or the first
+# convolution) the inverse field map.
+# ---------------------------------------------------------------------------
+
+def standardization(snaps: np.ndarray, nodes: np.ndarray):
+    """(u_mean, u_std, x_mean [m], x_std [m]) of the snapshot values (every
+    value of every snapshot) and of the node coordinates nodes [P, m]."""
+    u = np.asarray(snaps, dtype=np.float64).ravel()
+    x = np.asarray(nodes, dtype=np.float64)
+    u_mean = float(np.mean(u))
+    u_std = float(np.sqrt(np.mean((u - u_mean) ** 2)))
+    x_mean = np.mean(x, axis=0)
+    x_std = np.sqrt(np.mean((x - x_mean) ** 2, axis=0))
+    return u_mean, u_std, x_mean, x_std
+
+
+def fold_standardization(dec: Sequence[Layer], enc: Sequence[Layer], stats, m: int,
+                         enc_kind: str = "dense"):
+    """Decoder and encoder layers (FP64 copies) acting on physical points and
+    fields, for networks trained on standardized ones (the identities in the
+    section comment above).  ``stats`` is ``standardization``'s tuple; m is
+    the number of spatial inputs (the first m columns of W_1)."""
+    u_mean, u_std, x_mean, x_std = stats
+    x_mean = np.asarray(x_mean, dtype=np.float64)
+    x_std = np.asarray(x_std, dtype=np.float64)
+    dec = [(W.copy(), b.copy()) for W, b in as_f64(dec)]
+    enc = [(W.copy(), b.copy()) for W, b in as_f64(enc)]
+    # layer 1: W1x x_s = W1x diag(1/x_std) x - W1x (x_mean / x_std)
+    W1, b1 = dec[0]
+    b1 -= W1[:, :m] @ (x_mean / x_std)
+    W1[:, :m] /= x_std
+    # output layer: u_std (W h + b) + u_mean
+    Wo, bo = dec[-1]
+    dec[-1] = (Wo * u_std, bo * u_std + u_mean)
+    # encoder's first layer sees (u - u_mean) / u_std: its weights divide by
+    # u_std and its bias loses u_mean / u_std times the sum of each output's
+    # weights (over inputs, or over input channels and taps)
+    E, c = enc[0]
+    if enc_kind == "conv":
+        c -= (u_mean / u_std) * E.sum(axis=(1, 2))
+    else:
+        c -= (u_mean / u_std) * E.sum(axis=1)
+    enc[0] = (E / u_std, c)
+    return dec, enc
