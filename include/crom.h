@@ -430,6 +430,64 @@ crom_status crom_train_step(const crom_net* net, void* packed, float* dec_grad, 
                             float* enc_v, int64_t t, const float* u, const float* x, int32_t B,
                             float lr, float* loss, void* ws, size_t ws_bytes, void* stream);
 
+/* Standardization of the training data (Sec. "Training Details": the
+ * training fields have zero mean and unit variance, and the coordinates of
+ * ELU networks are standardized as well).  Population moments: the mean and
+ * the root mean squared deviation over every value.  Device struct. */
+typedef struct {
+  double u_mean, u_std;        /* over every value of every snapshot           */
+  double x_mean[3], x_std[3];  /* per coordinate axis over the nodes; axes past
+                                  m hold 0 and 1                             */
+} crom_standardization;
+
+/* Moments of the snapshots u [n_u] FP64 (any layout: every value counts
+ * alike) and of the nodes x [P][m] FP32, written to s (device).  One
+ * workgroup, fixed summation order (deterministic). */
+crom_status crom_standardization_of(const double* u, int64_t n_u, const float* x, int64_t P, int32_t m,
+                                    crom_standardization* s, void* stream);
+
+/* u_s [n_u] FP32 = (u - u_mean) / u_std and x_s [P][m] FP32 =
+ * (x - x_mean) / x_std, evaluated in FP64 and rounded once.  Either part may
+ * be skipped with n_u = 0 or P = 0. */
+crom_status crom_standardize(const crom_standardization* s, const double* u, int64_t n_u, float* u_s,
+                             const float* x, int64_t P, int32_t m, float* x_s, void* stream);
+
+/* Fold the standardization into networks trained on standardized data, in
+ * place, so that they act on physical points and fields:
+ *   g(x, q) = u_std g_s((x - x_mean) / x_std, q) + u_mean,   e(u) = e_s((u - u_mean) / u_std).
+ * The decoder's layer 1 coordinate columns divide by x_std and its bias
+ * loses W1x (x_mean / x_std); the output layer's weights and bias scale by
+ * u_std and the bias gains u_mean; the encoder's first layer (dense E1, or
+ * the first convolution) divides by u_std and its bias loses
+ * u_mean / u_std times the sum of each output's weights.  net->params (FP32)
+ * and enc->params are updated in place (enc may be NULL: decoder only); the
+ * packed weights must be refreshed with crom_net_pack afterwards. */
+crom_status crom_fold_standardization(const crom_net* net, const crom_encoder* enc, const crom_standardization* s,
+                                      void* stream);
+
+/* The whole training state in one caller-owned device blob, so that a
+ * training run is checkpointed and resumed by copying it (together with the
+ * Adam step t, which the caller keeps): the FP32 decoder parameters (the
+ * natural layout), their gradient buffer and Adam moments m and v, then the
+ * same four for the encoder, each section starting on a 256-byte boundary
+ * at the offsets below.  The blob is 256-byte aligned. */
+typedef struct {
+  size_t dec_params, dec_grad, dec_m, dec_v, enc_params, enc_grad, enc_m, enc_v, total;
+} crom_train_state_layout;
+
+/* Section offsets of the blob for this decoder and encoder (host out). */
+crom_status crom_train_state_offsets(const crom_net* net, const crom_encoder* enc, crom_train_state_layout* out);
+
+/* Bytes of the blob (0 on invalid arguments). */
+size_t crom_train_state_bytes(const crom_net* net, const crom_encoder* enc);
+
+/* crom_train_step on a state blob: the parameters, gradients and moments
+ * are the blob's sections (net->params and enc->params are ignored); packed
+ * (NULL or crom_net_packed_bytes) receives the packed decoder weights. */
+crom_status crom_train_step_state(const crom_net* net, const crom_encoder* enc, void* state, void* packed, int64_t t,
+                                  const float* u, const float* x, int32_t B, float lr, float* loss, void* ws,
+                                  size_t ws_bytes, void* stream);
+
 /* Encoder forward only: q [B][r] FP32 = E2 ELU(E1 u_b + c1) + c2 for
  * snapshots u [B][P][d], in the arithmetic crom_train_grads uses for the
  * net's precision (the latent of an initial field, Sec. "Manifold

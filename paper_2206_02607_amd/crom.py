@@ -54,6 +54,11 @@ class CromEncoder(Structure):
                 ("params", c_void_p)]
 
 
+class CromTrainStateLayout(Structure):
+    _fields_ = [(n, c_size_t) for n in ("dec_params", "dec_grad", "dec_m", "dec_v", "enc_params", "enc_grad",
+                                        "enc_m", "enc_v", "total")]
+
+
 class CromSamplingOpts(Structure):
     _fields_ = [("n_try", c_int32), ("max_samples", c_int32), ("n_steps", c_int64), ("target", c_double)]
 
@@ -147,11 +152,22 @@ def lib():
                                                 POINTER(c_size_t)]
         L.crom_heat_guess.argtypes = [POINTER(CromNet), POINTER(CromEncoder), c_void_p, c_int64, c_int32,
                                       c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_size_t, c_void_p]
+        L.crom_standardization_of.argtypes = [c_void_p, c_int64, c_void_p, c_int64, c_int32, c_void_p, c_void_p]
+        L.crom_standardize.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_int32,
+                                       c_void_p, c_void_p]
+        L.crom_fold_standardization.argtypes = [POINTER(CromNet), POINTER(CromEncoder), c_void_p, c_void_p]
+        L.crom_train_state_offsets.argtypes = [POINTER(CromNet), POINTER(CromEncoder), c_void_p]
+        L.crom_train_state_bytes.restype = c_size_t
+        L.crom_train_state_bytes.argtypes = [POINTER(CromNet), POINTER(CromEncoder)]
+        L.crom_train_step_state.argtypes = [POINTER(CromNet), POINTER(CromEncoder), c_void_p, c_void_p, c_int64,
+                                            c_void_p, c_void_p, c_int32, ctypes.c_float, c_void_p, c_void_p,
+                                            c_size_t, c_void_p]
         L.crom_kernel_timer.argtypes = [c_int32]
         L.crom_kernel_timer_read.argtypes = [POINTER(c_double), POINTER(c_int64)]
         for name in ("crom_sampling_residual", "crom_sampling_candidates", "crom_sampling_workspace",
                      "crom_robust_sampling", "crom_kernel_timer", "crom_kernel_timer_read", "crom_fe_stencil", "crom_step_guess", "crom_heat_guess_workspace",
-                     "crom_heat_guess"):
+                     "crom_heat_guess", "crom_standardization_of", "crom_standardize",
+                     "crom_fold_standardization", "crom_train_state_offsets", "crom_train_step_state"):
             getattr(L, name).restype = c_int32
         for name in ("crom_net_pack", "crom_decode", "crom_decode_jac", "crom_decode_jac_x",
                      "crom_decode_jac_q", "crom_step_workspace", "crom_step", "crom_fd_heat",
@@ -361,13 +377,27 @@ class Trainer:
         _check(lib().crom_train_workspace(ctypes.byref(dec._net(packed=False)), ctypes.byref(self._enc()),
                                           B, ctypes.byref(nbytes)), "crom_train_workspace")
         self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        # the training state blob (crom_train_state_offsets): the decoder's
+        # and encoder's parameters, gradients and Adam moments; the Decoder
+        # and this trainer hold views into it
+        lay = CromTrainStateLayout()
+        _check(lib().crom_train_state_offsets(ctypes.byref(dec._net(packed=False)), ctypes.byref(self._enc()),
+                                              ctypes.byref(lay)), "crom_train_state_offsets")
+        self.layout = lay
+        self._state_raw = torch.zeros(lay.total + 256, dtype=torch.uint8, device=dev)
+        a0 = (256 - self._state_raw.data_ptr() % 256) % 256
+        self.state = self._state_raw[a0:a0 + lay.total]
         nd = dec.params.numel()
-        self.grad_dec = torch.zeros(nd, dtype=torch.float32, device=dev)
-        self.grad_enc = torch.zeros(ne, dtype=torch.float32, device=dev)
-        self.m_dec = torch.zeros(nd, dtype=torch.float32, device=dev)
-        self.v_dec = torch.zeros(nd, dtype=torch.float32, device=dev)
-        self.m_enc = torch.zeros(ne, dtype=torch.float32, device=dev)
-        self.v_enc = torch.zeros(ne, dtype=torch.float32, device=dev)
+
+        def view(off, n):
+            return self.state[off:off + 4 * n].view(torch.float32)
+
+        view(lay.dec_params, nd).copy_(dec.params)
+        view(lay.enc_params, ne).copy_(self.enc_params)
+        dec.params = view(lay.dec_params, nd)
+        self.enc_params = view(lay.enc_params, ne)
+        self.grad_dec, self.m_dec, self.v_dec = view(lay.dec_grad, nd), view(lay.dec_m, nd), view(lay.dec_v, nd)
+        self.grad_enc, self.m_enc, self.v_enc = view(lay.enc_grad, ne), view(lay.enc_m, ne), view(lay.enc_v, ne)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.q = torch.zeros(B, dec.r, dtype=torch.float32, device=dev)
         self.t = 0
@@ -399,12 +429,25 @@ class Trainer:
         u = self._u(u)
         self.t += 1
         net, enc = self.dec._net(packed=False), self._enc()
-        _check(lib().crom_train_step(ctypes.byref(net), _ptr(self.dec.packed), _ptr(self.grad_dec),
-                                     _ptr(self.m_dec), _ptr(self.v_dec), ctypes.byref(enc),
-                                     _ptr(self.grad_enc), _ptr(self.m_enc), _ptr(self.v_enc), self.t,
-                                     _ptr(u), _ptr(self.x), self.B, lr, _ptr(self.loss), _ptr(self.ws),
-                                     self.ws.numel(), _stream()), "crom_train_step")
+        _check(lib().crom_train_step_state(ctypes.byref(net), ctypes.byref(enc), _ptr(self.state),
+                                           _ptr(self.dec.packed), self.t, _ptr(u), _ptr(self.x), self.B, lr,
+                                           _ptr(self.loss), _ptr(self.ws), self.ws.numel(), _stream()),
+               "crom_train_step_state")
         return self.loss
+
+    def checkpoint(self):
+        """(a copy of the state blob, the Adam step): everything a resumed
+        run needs besides the data order."""
+        return self.state.clone(), self.t
+
+    def restore(self, ckpt) -> None:
+        """Resume from a checkpoint (copies the blob in, re-packs the decoder)."""
+        blob, t = ckpt
+        if blob.numel() != self.state.numel():
+            raise CromError("checkpoint of another layout")
+        self.state.copy_(blob)
+        self.t = int(t)
+        self.dec.pack()
 
     def encode(self, u):
         """Latents q [n, r] FP32 of the snapshots u [n, P(, d)], any n >= 1
@@ -447,6 +490,58 @@ def heat_guess(dec: "Decoder", enc_params, hidden: int, nodes, q_n, nu, dt: floa
     _check(lib().crom_heat_guess(ctypes.byref(net), ctypes.byref(enc), _ptr(nodes), P, n, _ptr(q_n), _ptr(nu),
                                  float(dt), _ptr(out), _ptr(ws), nbytes.value, _stream()), "crom_heat_guess")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Standardization of the training data and its fold (Sec. "Training Details").
+# A crom_standardization is 8 doubles on the device: u_mean, u_std,
+# x_mean[3], x_std[3].
+# ---------------------------------------------------------------------------
+def standardization_of(u, x):
+    """Moments of the FP64 snapshots u (every value) and of the FP32 nodes
+    x [P, m]: a float64 device tensor of 8 values (crom_standardization)."""
+    torch = _torch()
+    u = u.to(dtype=torch.float64).contiguous()
+    x = x.to(device=u.device, dtype=torch.float32).contiguous()
+    s = torch.empty(8, dtype=torch.float64, device=u.device)
+    _check(lib().crom_standardization_of(_ptr(u), u.numel(), _ptr(x), x.shape[0], x.shape[1], _ptr(s), _stream()),
+           "crom_standardization_of")
+    return s
+
+
+def standardize(s, u=None, x=None):
+    """(u_s, x_s) FP32 standardized copies of u (FP64, any shape) and x
+    [P, m] (either may be None)."""
+    torch = _torch()
+    u_s = x_s = None
+    n_u, P, m = 0, 0, 1
+    if u is not None:
+        u = u.to(dtype=torch.float64).contiguous()
+        u_s = torch.empty(u.shape, dtype=torch.float32, device=u.device)
+        n_u = u.numel()
+    if x is not None:
+        x = x.to(dtype=torch.float32).contiguous()
+        x_s = torch.empty_like(x)
+        P, m = x.shape
+    _check(lib().crom_standardize(_ptr(s), _ptr(u), n_u, _ptr(u_s), _ptr(x), P, m, _ptr(x_s), _stream()),
+           "crom_standardize")
+    return u_s, x_s
+
+
+def fold_standardization(dec: "Decoder", s, enc_params=None, n_in: int = 0, hidden: int = 0,
+                         enc_kind: str = "dense") -> None:
+    """Folds the standardization s into the decoder and, when enc_params is
+    given (FP32 device params of an encoder of kind enc_kind with n_in = P d
+    inputs), into the encoder, in place; then re-packs the decoder."""
+    enc = None
+    if enc_params is not None:
+        if enc_params.dtype != _torch().float32 or not enc_params.is_cuda or not enc_params.is_contiguous():
+            raise CromError("encoder params must be a contiguous FP32 device tensor")
+        enc = CromEncoder(n_in, hidden, dec.r, _ENC_NAMES[enc_kind], enc_params.data_ptr())
+    net = dec._net(packed=False)
+    _check(lib().crom_fold_standardization(ctypes.byref(net), ctypes.byref(enc) if enc is not None else None,
+                                           _ptr(s), _stream()), "crom_fold_standardization")
+    dec.pack()
 
 
 def adam_step(params, grad, m, v, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):

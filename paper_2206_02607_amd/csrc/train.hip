@@ -1131,6 +1131,60 @@ crom_status crom_train_step(const crom_net* net, void* packed, float* dec_grad, 
   return CROM_OK;
 }
 
+static int64_t enc_count(const crom_net* net, const crom_encoder* enc) {
+  return enc->kind == CROM_ENC_CONV ? conv_of(net, enc).count
+                                    : (int64_t)crom_encoder_param_count(enc->n_in, enc->hidden, enc->r);
+}
+
+crom_status crom_train_state_offsets(const crom_net* net, const crom_encoder* enc, crom_train_state_layout* out) {
+  crom_status s = check_net(net, false);
+  if (s != CROM_OK) return s;
+  if ((s = check_enc(net, enc)) != CROM_OK) return s;
+  if (!out) return fail(CROM_ERR_INVALID_ARG, "out is NULL");
+  const size_t nd = 4 * crom_net_param_count(net->m, net->r, net->d, net->width, net->depth);
+  const size_t ne = 4 * (size_t)enc_count(net, enc);
+  size_t o = 0;
+  auto take = [&o](size_t n) {
+    const size_t at = o;
+    o = (o + n + 255) & ~size_t(255);
+    return at;
+  };
+  out->dec_params = take(nd);
+  out->dec_grad = take(nd);
+  out->dec_m = take(nd);
+  out->dec_v = take(nd);
+  out->enc_params = take(ne);
+  out->enc_grad = take(ne);
+  out->enc_m = take(ne);
+  out->enc_v = take(ne);
+  out->total = o;
+  return CROM_OK;
+}
+
+size_t crom_train_state_bytes(const crom_net* net, const crom_encoder* enc) {
+  crom_train_state_layout L;
+  return crom_train_state_offsets(net, enc, &L) == CROM_OK ? L.total : 0;
+}
+
+crom_status crom_train_step_state(const crom_net* net, const crom_encoder* enc, void* state, void* packed, int64_t t,
+                                  const float* u, const float* x, int32_t B, float lr, float* loss, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  crom_train_state_layout L;
+  crom_status s = crom_train_state_offsets(net, enc, &L);
+  if (s != CROM_OK) return s;
+  if (!state) return fail(CROM_ERR_INVALID_ARG, "state is NULL");
+  if (reinterpret_cast<uintptr_t>(state) & 255) return fail(CROM_ERR_INVALID_ARG, "state must be 256-byte aligned");
+  char* b = static_cast<char*>(state);
+  crom_net n = *net;
+  n.params = reinterpret_cast<const float*>(b + L.dec_params);
+  crom_encoder e = *enc;
+  e.params = reinterpret_cast<float*>(b + L.enc_params);
+  return crom_train_step(&n, packed, reinterpret_cast<float*>(b + L.dec_grad), reinterpret_cast<float*>(b + L.dec_m),
+                         reinterpret_cast<float*>(b + L.dec_v), &e, reinterpret_cast<float*>(b + L.enc_grad),
+                         reinterpret_cast<float*>(b + L.enc_m), reinterpret_cast<float*>(b + L.enc_v), t, u, x, B, lr,
+                         loss, ws, ws_bytes, stream);
+}
+
 crom_status crom_encode_workspace(const crom_net* net, const crom_encoder* enc, int32_t B, size_t* bytes) {
   crom_status s = check_net(net, false);
   if (s != CROM_OK) return s;

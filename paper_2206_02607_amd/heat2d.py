@@ -48,55 +48,39 @@ def lr_at(step: int, steps: int, base: float = 1e-4) -> float:
     return base * LR_STAGES[min(len(LR_STAGES) - 1, step * len(LR_STAGES) // max(1, steps))]
 
 
-@dataclass
 class Standardization:
-    """Affine maps to the standardized training variables (Sec. "Training
-    Details"): u_s = (u - u_mean) / u_std over the whole training set,
-    x_s = (x - x_mean) / x_std per coordinate over the nodes."""
-    u_mean: float
-    u_std: float
-    x_mean: np.ndarray
-    x_std: np.ndarray
+    """The standardization of the training data (Sec. "Training Details"):
+    u_s = (u - u_mean) / u_std over the whole training set, x_s =
+    (x - x_mean) / x_std per coordinate over the nodes (population moments).
+    The moments live on the device (crom_standardization); the library
+    computes them, applies them and folds them into the trained networks."""
+
+    def __init__(self, s: torch.Tensor, m: int):
+        self.s = s
+        self.m = m
 
     @classmethod
     def of(cls, snaps: torch.Tensor, nodes: torch.Tensor) -> "Standardization":
-        u = snaps.to(torch.float64)
-        x = nodes.to(torch.float64)
-        return cls(float(u.mean()), float(u.std()), x.mean(dim=0).cpu().numpy(), x.std(dim=0).cpu().numpy())
+        return cls(crom.standardization_of(snaps, nodes), nodes.shape[1])
+
+    def values(self) -> dict:
+        """The moments on the host (synchronises; for reports)."""
+        v = self.s.cpu().numpy()
+        return {"u_mean": float(v[0]), "u_std": float(v[1]), "x_mean": v[2:2 + self.m].copy(),
+                "x_std": v[5:5 + self.m].copy()}
 
     def data(self, snaps: torch.Tensor) -> torch.Tensor:
-        return ((snaps.to(torch.float64) - self.u_mean) / self.u_std).to(torch.float32).contiguous()
+        return crom.standardize(self.s, u=snaps)[0]
 
     def points(self, nodes: torch.Tensor) -> torch.Tensor:
-        xm = torch.as_tensor(self.x_mean, device=nodes.device)
-        xs = torch.as_tensor(self.x_std, device=nodes.device)
-        return ((nodes.to(torch.float64) - xm) / xs).to(torch.float32).contiguous()
+        return crom.standardize(self.s, x=nodes)[1]
 
-    def fold(self, dec: crom.Decoder, enc_params: torch.Tensor, n_in: int, hidden: int) -> None:
-        """Rewrite the trained decoder and encoder (in place, FP32) so that
-        they act on physical points and fields:  g(x, q) = u_std * g_s(x_s, q)
-        + u_mean and e(u) = e_s(u_s).  Exact up to rounding."""
-        m, r, w = dec.m, dec.r, dec.width
-        p = dec.params.detach()
-        with torch.no_grad():
-            W1 = p[: w * (m + r)].view(w, m + r)
-            b1 = p[w * (m + r): w * (m + r) + w]
-            xm = torch.as_tensor(self.x_mean, dtype=torch.float64, device=p.device)
-            xs = torch.as_tensor(self.x_std, dtype=torch.float64, device=p.device)
-            Wx = W1[:, :m].to(torch.float64)
-            b1.copy_((b1.to(torch.float64) - Wx @ (xm / xs)).to(torch.float32))
-            W1[:, :m].copy_((Wx / xs).to(torch.float32))
-            d = dec.d
-            out_w = p[p.numel() - d - d * w: p.numel() - d]
-            out_b = p[p.numel() - d:]
-            out_w.mul_(self.u_std)
-            out_b.copy_((out_b.to(torch.float64) * self.u_std + self.u_mean).to(torch.float32))
-            E1 = enc_params[: hidden * n_in].view(hidden, n_in)
-            c1 = enc_params[hidden * n_in: hidden * n_in + hidden]
-            c1.copy_((c1.to(torch.float64) - E1.to(torch.float64).sum(dim=1) * (self.u_mean / self.u_std))
-                     .to(torch.float32))
-            E1.div_(self.u_std)
-        dec.pack()
+    def fold(self, dec: crom.Decoder, enc_params: torch.Tensor, n_in: int, hidden: int,
+             enc_kind: str = "dense") -> None:
+        """Rewrite the trained decoder and encoder in place so that they act
+        on physical points and fields: g(x, q) = u_std g_s(x_s, q) + u_mean
+        and e(u) = e_s(u_s) (crom_fold_standardization; re-packs the decoder)."""
+        crom.fold_standardization(dec, self.s, enc_params, n_in, hidden, enc_kind)
 
 
 def train(trainer: crom.Trainer, snaps: torch.Tensor, steps: int, base_lr: float = 1e-4, seed: int = 0,

@@ -436,3 +436,69 @@ def test_conv_encoder_full_size(cuda):
     print("full size conv encoder", {k: f"{v:.1e}" for k, v in errs.items()})
     bad = {k: v for k, v in errs.items() if not v <= TOL["fp32"]}
     assert not bad, bad
+
+
+def test_train_grads_bf16_full_size(cuda):
+    """The bfloat16 gradient step at the size the benchmark times: 16
+    snapshots of the 128 x 128 nodes (262,144 decoder rows), dense encoder
+    16,384 -> 256 -> 8, against the oracle at the bfloat16-held weights, 2e-2
+    per tensor.  The snapshots are standardized smooth fields (products of
+    sine modes with seeded amplitudes and decay factors), the shape of the
+    training data."""
+    import torch
+    from workloads import Train2D
+    w = Train2D(seed=3)
+    x = w.nodes
+    P = x.shape[0]
+    g = rng(31)
+    k = np.arange(1, 5)
+    fields = []
+    for _ in range(w.batch):
+        a = g.uniform(-1, 1, size=(4, 4)) * np.exp(-g.uniform(0, 0.3) * (k[:, None] ** 2 + k[None, :] ** 2))
+        sx = np.sin(np.pi * np.outer(x[:, 0], k))
+        sy = np.sin(np.pi * np.outer(x[:, 1], k))
+        fields.append(np.einsum("pk,kl,pl->p", sx, a, sy))
+    u = np.stack(fields)
+    u = ((u - u.mean()) / u.std()).astype(np.float32)
+    xs = ((x - x.mean(axis=0)) / x.std(axis=0)).astype(np.float32)
+    dec, enc = w.layers, w.enc_layers
+    D, T = _trainer(dec, enc, xs, u, w.m, "bf16", cuda, hidden=w.enc_hidden)
+    loss, gd, ge, q = T.grads(torch.from_numpy(u).to(cuda))
+    torch.cuda.synchronize()
+    rl, rgd, rge, rq = train.loss_and_grads(*_as_held(dec, enc, "bf16"), xs, u)
+    errs = {"loss": abs(loss.item() - rl) / rl, "q": normwise_rel(q.cpu().numpy(), rq)}
+    for name, got, ref, layers in (("dec", gd, rgd, dec), ("enc", ge, rge, enc)):
+        for li, ((gW, gb), (rW, rb)) in enumerate(zip(_split(got.cpu().numpy(), layers), ref)):
+            errs[f"{name}W{li}"] = normwise_rel(gW, rW)
+            errs[f"{name}b{li}"] = normwise_rel(gb, rb)
+    print("bf16 full size", {k: f"{v:.1e}" for k, v in errs.items()})
+    bad = {k: v for k, v in errs.items() if not v <= TOL["bf16"]}
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_train_state_checkpoint_resume(cuda, prec):
+    """The training state is one blob (crom_train_state_offsets): a run
+    resumed from a copy of it and its Adam step reproduces the uninterrupted
+    run bit for bit (losses, parameters, moments)."""
+    import torch
+    dec, enc, x, u, m = _problem("2d", 13, 4, 257)
+    D, T = _trainer(dec, enc, x, u, m, prec, cuda)
+    batches = [torch.from_numpy(np.roll(u, k, axis=0).copy()).to(cuda) for k in range(7)]
+    for k in range(3):
+        T.step(batches[k], 1e-3)
+    ck = T.checkpoint()
+    run_a = [T.step(batches[k], 1e-3).clone() for k in range(3, 7)]
+    end_a = T.state.clone()
+    packed_a = D.packed.clone()
+    T.restore(ck)
+    run_b = [T.step(batches[k], 1e-3).clone() for k in range(3, 7)]
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(run_a, run_b))
+    assert torch.equal(end_a, T.state)
+    assert torch.equal(packed_a, D.packed)
+    # the blob's sections are the views the trainer and decoder use
+    lay = T.layout
+    nd = D.params.numel()
+    assert torch.equal(T.state[lay.dec_params:lay.dec_params + 4 * nd].view(torch.float32), D.params)
+    assert lay.total == len(T.state) and lay.dec_params == 0
