@@ -302,6 +302,24 @@ crom_status crom_step(const crom_net* net, const crom_pde* pde, int32_t n_inst,
                       const crom_gn_opts* opts, crom_step_info* info, void* ws, size_t ws_bytes,
                       void* stream);
 
+/* crom_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same step with the same kernels and results, its
+ * workspace a library-owned device array of crom_step_static_capacity()
+ * bytes (64 MiB) that each GPU the library runs on holds until the process
+ * ends.  A step whose crom_step_workspace exceeds it returns
+ * CROM_ERR_WORKSPACE before anything is enqueued.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other host threads) race and must be serialised by the caller; a call
+ * needs nothing cleared from the previous one.  The targets and increments
+ * of the last step are not exposed (crom_step_targets needs a caller
+ * workspace). */
+size_t crom_step_static_capacity(void);
+crom_status crom_step_static(const crom_net* net, const crom_pde* pde, int32_t n_inst, const int64_t* offsets,
+                             int64_t total_samples, const float* y, const uint8_t* clamp, const double* q_prev,
+                             const double* q_n, double* q_next, const crom_gn_opts* opts, crom_step_info* info,
+                             void* stream);
+
 /* crom_step with a second candidate starting point for the Gauss-Newton
  * inversion (Sec. "Initial Guess for the Nonlinear Solver": where the field
  * changes a lot over one step, a latent from an encoder of the updated field

@@ -162,12 +162,18 @@ def lib():
         L.crom_train_step_state.argtypes = [POINTER(CromNet), POINTER(CromEncoder), c_void_p, c_void_p, c_int64,
                                             c_void_p, c_void_p, c_int32, ctypes.c_float, c_void_p, c_void_p,
                                             c_size_t, c_void_p]
+        L.crom_step_static_capacity.restype = c_size_t
+        L.crom_step_static_capacity.argtypes = []
+        L.crom_step_static.argtypes = [POINTER(CromNet), POINTER(CromPDE), c_int32, c_void_p, c_int64, c_void_p,
+                                       c_void_p, c_void_p, c_void_p, c_void_p, POINTER(CromGNOpts), c_void_p,
+                                       c_void_p]
         L.crom_kernel_timer.argtypes = [c_int32]
         L.crom_kernel_timer_read.argtypes = [POINTER(c_double), POINTER(c_int64)]
         for name in ("crom_sampling_residual", "crom_sampling_candidates", "crom_sampling_workspace",
                      "crom_robust_sampling", "crom_kernel_timer", "crom_kernel_timer_read", "crom_fe_stencil", "crom_step_guess", "crom_heat_guess_workspace",
                      "crom_heat_guess", "crom_standardization_of", "crom_standardize",
-                     "crom_fold_standardization", "crom_train_state_offsets", "crom_train_step_state"):
+                     "crom_fold_standardization", "crom_train_state_offsets", "crom_train_step_state",
+                     "crom_step_static"):
             getattr(L, name).restype = c_int32
         for name in ("crom_net_pack", "crom_decode", "crom_decode_jac", "crom_decode_jac_x",
                      "crom_decode_jac_q", "crom_step_workspace", "crom_step", "crom_fd_heat",
@@ -678,6 +684,30 @@ class Stepper:
                                      self.total, _ptr(self.y), _ptr(self.clamp), _ptr(q_prev), _ptr(q_n),
                                      _ptr(q_init), _ptr(q_next), ctypes.byref(o), self.info_buf.data_ptr(),
                                      self.ws_ptr, self.ws_bytes, _stream()), "crom_step_guess")
+        return q_next
+
+    def step_static(self, q_n, coef, dt: float, opts: GNOptions = GNOptions(), q_next=None, q_prev=None):
+        """crom_step_static: the same step with the library's own workspace
+        (no allocation by the call; this object's workspace is not used)."""
+        torch = _torch()
+        dev = self.dec.params.device
+        q_n = q_n.to(device=dev, dtype=torch.float64).contiguous()
+        per = 1 if self.kind == PDE_HEAT else 6
+        coef = torch.as_tensor(coef, dtype=torch.float64, device=dev).reshape(-1, per)
+        coef = coef.expand(self.n_inst, per).contiguous()
+        if q_prev is not None:
+            q_prev = q_prev.to(device=dev, dtype=torch.float64).contiguous()
+        if q_next is None:
+            q_next = torch.empty_like(q_n)
+        net = self.dec._net()
+        fm = self.mesh.c_struct() if self.mesh is not None else None
+        pde = CromPDE(self.kind, 0, float(dt), coef.data_ptr(), ctypes.addressof(fm) if fm is not None else None)
+        o = opts.c_struct()
+        self._coef, self._q_prev = coef, q_prev
+        _check(lib().crom_step_static(ctypes.byref(net), ctypes.byref(pde), self.n_inst, _ptr(self.offsets),
+                                      self.total, _ptr(self.y), _ptr(self.clamp), _ptr(q_prev), _ptr(q_n),
+                                      _ptr(q_next), ctypes.byref(o), self.info_buf.data_ptr(), _stream()),
+               "crom_step_static")
         return q_next
 
     def info(self) -> np.ndarray:
