@@ -1,28 +1,30 @@
 #!/usr/bin/env python
 """Benchmark of the CROM latent step on one MI355X.
 
-Workload (2D heat on the unit square): decoder (x in R^2, q in R^8) -> 5
-ELU layers of width 128 -> 1 with Xavier-uniform weights from a seed;
-diffusivity mu ~ U(0.1, 1); 2,000 integration samples uniform in (0, 1)^2;
-dt = 1e-4.  One step = the full-field decode of the 65,536 nodes of the
-256 x 256 grid plus one latent step q_n -> q_{n+1} at the samples
-(decoder with x tangents, Laplacian and latent Jacobian, heat update, and
-Gauss-Newton inversion with up to 5 iterations and FP64 normal equations).
-The steps form a rollout: each starts from the previous step's latent.
+Headline workload: the batched rollout of 512 instances of 2D heat on the
+unit square (mu_i ~ U(0.1, 1), S_i ~ U{200..2000} integration samples drawn
+from the interior nodes of a 128 x 128 lattice, dt = 1e-4) with the decoder
+(x in R^2, q in R^8) -> 5 ELU layers of width 128 -> 1 trained by the
+library's own kernels on FP64 finite-difference snapshots (the training
+leg runs first).  One step = one latent step q_n -> q_{n+1} of every
+instance: the decoder with x tangents, Laplacian and latent Jacobian at the
+samples, the heat update and the inversion (FP64 normal equations).  Four
+modes (Gauss-Newton or linearised inversion, BF16 or FP32 decoder
+arithmetic) are timed; each one's rollout error over 500 steps is judged by
+the FP64 finite-difference solver on a subset, and the headline is the
+fastest mode at the best mode's rollout error.
 
-Reported value: decoder+Jacobian point-evals per second, where one
-point-eval is one point through the decoder with all 12 columns (value, 2
-gradient entries, Laplacian, 8 latent-Jacobian entries; 1,576,448
-algorithmic FLOP) and the step's algorithmic decoder work is counted in
-that unit.  latent_steps_per_s is reported beside it.
+Reported value: decoder+Jacobian point-evals per second, one point-eval
+being one point through the decoder with all 12 columns (value, 2 gradient
+entries, Laplacian, 8 latent-Jacobian entries; 1,576,448 algorithmic
+FLOP); latent steps per second (instance-steps) beside it.  roofline: the
+headline mode's timed kernels against the matrix-core peak of its
+arithmetic; cpu_baseline: the FP64 oracle on a bounded sample of the same
+workload.
 
-Beside it: the linearised inversion's steps/s on the same rollout; the
-decoder training step (16 snapshots x 16,384 points, encoder 16,384 -> 256
--> 8) timed in BF16 and FP32, then a BF16 training run on FP64
-finite-difference snapshots; the batched rollout of 512 instances with that
-trained network in BF16 and FP32 arithmetic, with the rollout error of a
-subset judged by the FP64 finite-difference solver (the BF16-vs-FP32
-speedup at equal rollout error); and the FP64 oracle timed on the host.
+Further legs: the single-instance 2D heat step at 2,000 samples with a
+full-field decode (latency-bound), the 1D and 3D workloads, the training
+step, sample selection, the encoder guess, SIREN and corotated FE.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec bf16|fp32|bf16x3|bf16pure]
 """
@@ -43,8 +45,16 @@ W, DEPTH, M, R = 128, 5, 2, 8
 FLOP_VALUE_COL = 2 * M * W + 2 * (DEPTH - 1) * W * W + 2 * W        # 131,840
 FLOP_TAN_COL = 2 * (DEPTH - 1) * W * W + 2 * W                      # 131,328
 FLOP_POINT_EVAL = FLOP_VALUE_COL + (M + 1 + R) * FLOP_TAN_COL      # 1,576,448
-TOL_STEP = 1e-6   # Gauss-Newton step tolerance, relative to 1 + |q| (both sides)
+# Gauss-Newton step tolerance, relative to 1 + |q|.  The same 1e-6 for every
+# arithmetic: the change of q over one time step is about 1e-4 of |q| here,
+# and the stopping rule stops without moving when the Gauss-Newton step is
+# below tol (1 + |q|), so a coarser tolerance (1e-3) would freeze the
+# rollout.  Steps that reach the 5-iteration cap report MAXITER (not a
+# failure); the flags of every timed leg are reported.
+TOL_STEP = {"bf16": 1e-6, "bf16pure": 1e-6, "bf16x3": 1e-6, "fp32": 1e-6}
 PEAK = {"bf16": 2500.0, "bf16x3": 2500.0, "bf16pure": 2500.0, "fp32": 157.3}  # TFLOP/s, dense
+# flags of a failed instance-step (its work does not count as throughput)
+FAILED = 2 | 4 | 8 | 16  # SINGULAR | NONFINITE | LS_FAIL | ABORTED
 
 
 def source_hash() -> str:
@@ -60,10 +70,10 @@ def source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
+def measured_traffic(kernel: str, summary: str = "traffic_2d_heat.json"):
+    """HBM bytes per launch of `kernel` from a committed counter summary,
     when it was taken on the current sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_2d_heat.json")
+    path = os.path.join(ROOT, "profiles", summary)
     try:
         with open(path) as f:
             t = json.load(f)
@@ -82,15 +92,44 @@ def step_flops(S: int, iters: int, ls_evals: int) -> float:
     return S * (FLOP_POINT_EVAL + (ls_evals + iters * R) * FLOP_TAN_COL)
 
 
+def _cores():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        return 1
+
+
+def cpu_baseline_batched(wb, opts_kw: dict, budget_s: float):
+    """The FP64 oracle on the host, on a bounded sample of the batched
+    workload: one latent step of the batch's instances 0, 1, 2, ... in turn
+    (the workload's own seeded weights and latents: the same arithmetic per
+    sample as any trained network) until about budget_s seconds have been
+    spent, counted in the headline's unit."""
+    from oracle import mlp, step as ostep
+    from oracle.inversion import GNOptions
+    dec = mlp.MLPDecoder(wb.layers, wb.m)
+    flop, n, S_tot = 0.0, 0, 0
+    t0 = time.perf_counter()
+    while n < wb.n_inst and (n == 0 or time.perf_counter() - t0 < budget_s):
+        y = wb.samples[wb.offsets[n]:wb.offsets[n + 1]]
+        _, info, _ = ostep.heat_step(dec, y, wb.q0[n], float(wb.mu[n]), wb.dt, GNOptions(**opts_kw))
+        S = len(y)
+        flop += S * FLOP_POINT_EVAL if opts_kw.get("linearized") else step_flops(S, info.iters, info.ls_evals)
+        S_tot += S
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": flop / FLOP_POINT_EVAL / dt, "unit": "point-evals/s", "cores": _cores(), "kind": "oracle",
+            "sample": f"one latent step ({'linearised' if opts_kw.get('linearized') else 'Gauss-Newton'}) of "
+                      f"instances 0..{n - 1} of the 512-instance batch ({S_tot} samples), FP64 NumPy, {dt:.1f} s",
+            "latent_steps_per_s": n / dt}
+
+
 def cpu_baseline(wl, nodes, n_steps: int):
     """The FP64 oracle on the host: full-field decode plus latent steps."""
     from oracle import mlp, step as ostep
     from oracle.inversion import GNOptions
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = 1
+    cores = _cores()
     dec = mlp.MLPDecoder(wl.layers, wl.m)
     q = wl.q0.copy()
     flop = 0.0
@@ -98,7 +137,7 @@ def cpu_baseline(wl, nodes, n_steps: int):
     for _ in range(n_steps):
         mlp.decode(wl.layers, nodes, q)
         q, info, _ = ostep.heat_step(dec, wl.samples, q, wl.mu, wl.dt,
-                                     GNOptions(max_iter=5, tol_step=TOL_STEP))
+                                     GNOptions(max_iter=5, tol_step=TOL_STEP["fp32"]))
         flop += len(nodes) * FLOP_VALUE_COL + step_flops(len(wl.samples), info.iters, info.ls_evals)
     dt = time.perf_counter() - t0
     return {"value": flop / FLOP_POINT_EVAL / dt, "unit": "point-evals/s", "cores": cores,
@@ -198,24 +237,33 @@ def train_leg(args, crom, torch, dev):
 
 
 def batched_leg(args, crom, torch, dev, trained=None):
-    """Batched rollout: 512 instances of 2D heat, mu_i ~ U(0.1, 1), sample
-    counts S_i ~ U{200..2000} drawn without replacement from the interior
-    nodes of a 128 x 128 lattice, r = 8, dt = 1e-4; all instances advance
-    together in one step launch.  Gauss-Newton (5 iterations, tol 1e-6) and
-    the linearised inversion are timed separately.  With a trained network
-    (the training leg's) every instance starts from the encoded initial field,
-    both BF16 and FP32 decoder arithmetic are timed, and the rollout error of
-    the first --judge instances over 500 steps is measured against the FP64
-    finite-difference solution (space-time relative L2 at 5 recorded states)."""
+    """The headline: batched rollout of 512 instances of 2D heat, mu_i ~
+    U(0.1, 1), sample counts S_i ~ U{200..2000} drawn without replacement
+    from the interior nodes of a 128 x 128 lattice, r = 8, dt = 1e-4, with
+    the trained network (the training leg's; every instance starts from the
+    encoded initial field).  All instances advance together in one step.
+
+    Four modes: Gauss-Newton (5 iterations, step tolerance per arithmetic)
+    and the linearised inversion, each with BF16 and FP32 decoder arithmetic.
+    For each: the rollout error of the first --judge instances over 500 steps
+    against the FP64 finite-difference solution (space-time relative L2 at 5
+    recorded states), then K timed steps of the whole batch after W warm-up
+    steps, and the same K steps replayed untimed with the per-instance
+    outcome read after every step (iterations, line-search trials, flags).
+    Failed instance-steps (SINGULAR, NONFINITE, LS_FAIL, ABORTED) do not
+    count as work.  The headline mode is the fastest one whose rollout error
+    equals the best mode's (at most 1.05 times it, or within 1e-4)."""
     from paper_2206_02607_amd import heat2d
     from workloads import Batched2D
     wb = Batched2D(seed=args.seed)
     params = trained["params"] if trained else crom.flatten_layers(wb.layers)
     q_init = np.tile(trained["q0"], (wb.n_inst, 1)) if trained else wb.q0
     total = int(wb.offsets[-1])
-    out = {"workload": f"{wb.n_inst} instances, S_i in [{wb.s_min},{wb.s_max}], total samples {total}",
-           "net": "trained (training leg)" if trained else "Xavier-uniform, untrained",
-           "steps": args.batched_steps}
+    S = np.diff(wb.offsets)
+    out = {"workload": f"{wb.n_inst} instances of 2D heat, S_i in [{wb.s_min},{wb.s_max}] samples of the "
+                       f"{wb.grid}x{wb.grid} lattice (total {total}), r = 8, dt = {wb.dt}",
+           "net": "trained (training leg), (x in R^2, q in R^8) -> 5 x ELU width 128 -> 1" if trained
+                  else "Xavier-uniform, untrained"}
     nu = torch.from_numpy(wb.mu).to(dev)
     record = [0, 125, 250, 375, 500]
     nj = min(args.judge, wb.n_inst) if trained else 0
@@ -229,35 +277,15 @@ def batched_leg(args, crom, torch, dev, trained=None):
         refs = [ref[:, k].reshape(nj, -1) for k in range(len(record))]
         out["fd_judge"] = {"instances": nj, "ms": e[0].elapsed_time(e[1]),
                            "substeps": int(round(record[-1] * wb.dt / w.dt_fd))}
-    precs = (args.prec, "fp32") if trained and args.prec != "fp32" else (args.prec,)
+    precs = (args.prec, "fp32") if args.prec != "fp32" else ("fp32",)
+    modes = {}
     for prec in precs:
         dec = crom.Decoder(params, wb.m, wb.r, wb.d, wb.width, wb.depth, prec, dev)
         st = crom.Stepper(dec, wb.offsets, torch.from_numpy(wb.samples).to(dev))
-        res = {}
-        for name, opts in (("gn", crom.GNOptions(max_iter=5, tol_step=TOL_STEP)),
-                           ("lls", crom.GNOptions(max_iter=1, linearized=True))):
-            q = [torch.from_numpy(np.asarray(q_init, np.float64).copy()).to(dev),
-                 torch.empty(wb.n_inst, R, dtype=torch.float64, device=dev)]
-            for i in range(3):
-                st.step(q[i % 2], nu, wb.dt, opts, q_next=q[(i + 1) % 2])
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for i in range(args.batched_steps):
-                st.step(q[i % 2], nu, wb.dt, opts, q_next=q[(i + 1) % 2])
-            e1.record()
-            torch.cuda.synchronize()
-            t = e0.elapsed_time(e1) * 1e-3 / args.batched_steps
-            inf = st.info()  # iteration counts of the last step stand for all
-            flop = sum(step_flops(int(wb.offsets[k + 1] - wb.offsets[k]), int(inf["iters"][k]),
-                                  int(inf["ls_evals"][k])) for k in range(wb.n_inst))
-            if opts.linearized:
-                flop = total * FLOP_POINT_EVAL
-            achieved = flop / t / 1e12
-            r = {"ms_per_step": t * 1e3, "instance_steps_per_s": wb.n_inst / t,
-                 "point_evals_per_s": flop / FLOP_POINT_EVAL / t,
-                 "achieved_tflops": achieved, "frac_of_peak": achieved / PEAK[prec],
-                 "gn_iters_mean": float(inf["iters"].mean()), "ls_evals_mean": float(inf["ls_evals"].mean())}
+        for kind, opts in (("lls", crom.GNOptions(max_iter=1, linearized=True)),
+                           ("gn", crom.GNOptions(max_iter=5, tol_step=TOL_STEP[prec]))):
+            r = {"precision": prec, "inversion": "linearised" if opts.linearized else "Gauss-Newton",
+                 "tol_step": None if opts.linearized else TOL_STEP[prec]}
             if nj:
                 ro = heat2d.rollout(dec, np.tile(trained["q0"], (nj, 1)), wb.samples[:int(wb.offsets[nj])],
                                     wb.mu[:nj], wb.dt, record[-1], opts, record, offsets=wb.offsets[:nj + 1])
@@ -265,15 +293,69 @@ def batched_leg(args, crom, torch, dev, trained=None):
                 err = heat2d.spacetime_error(fields, refs)
                 r["rollout_error_mean"] = float(err.mean())
                 r["rollout_error_max"] = float(err.max())
-            res[name] = r
-        out[prec] = res
+                r["rollout_flags_or"] = int(np.bitwise_or.reduce(ro.flags[-1]))
+            q = [torch.from_numpy(np.asarray(q_init, np.float64).copy()).to(dev),
+                 torch.empty(wb.n_inst, R, dtype=torch.float64, device=dev)]
+            for i in range(args.warmup):
+                st.step(q[i % 2], nu, wb.dt, opts, q_next=q[(i + 1) % 2])
+            q_w = q[args.warmup % 2].clone()
+            torch.cuda.synchronize()
+            crom.kernel_timer(True)
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                st.step(q[(args.warmup + i) % 2], nu, wb.dt, opts, q_next=q[(args.warmup + i + 1) % 2])
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            crom.kernel_timer(False)
+            k_ms, k_n = crom.kernel_timer_read()
+            # the same steps again, untimed, reading every step's outcome
+            q[args.warmup % 2].copy_(q_w)
+            flop, n_fail, flags_or, iters, lse = 0.0, 0, 0, 0, 0
+            for i in range(args.steps):
+                st.step(q[(args.warmup + i) % 2], nu, wb.dt, opts, q_next=q[(args.warmup + i + 1) % 2])
+                inf = st.info()
+                ok = (inf["flags"] & FAILED) == 0
+                n_fail += int((~ok).sum())
+                flags_or |= int(np.bitwise_or.reduce(inf["flags"]))
+                iters += int(inf["iters"].sum())
+                lse += int(inf["ls_evals"].sum())
+                if opts.linearized:
+                    flop += float(S[ok].sum()) * FLOP_POINT_EVAL
+                else:
+                    flop += sum(step_flops(int(S[k]), int(inf["iters"][k]), int(inf["ls_evals"][k]))
+                                for k in np.flatnonzero(ok))
+            t = wall / args.steps
+            kernel_ms = k_ms / max(1, k_n)
+            fl_step = flop / args.steps
+            r.update({"ms_per_step": t * 1e3, "instance_steps_per_s": (wb.n_inst * args.steps - n_fail) / wall,
+                      "point_evals_per_s": flop / FLOP_POINT_EVAL / wall,
+                      "achieved_tflops": fl_step / t / 1e12, "frac_of_peak": fl_step / t / 1e12 / PEAK[prec],
+                      "timed_kernels": ("lls_jets_kernel (the 12-column evaluation)" if opts.linearized else
+                                        "gn_round_kernel + gn_solve_kernel, every round of the step"),
+                      "timed_kernels_ms": kernel_ms, "flop_per_step": fl_step,
+                      "gn_iters_mean": iters / (wb.n_inst * args.steps),
+                      "ls_evals_mean": lse / (wb.n_inst * args.steps),
+                      "failed_instance_steps": n_fail, "flags_or": flags_or})
+            modes[f"{prec}_{kind}"] = r
+    out["modes"] = modes
+    errs = {k: v.get("rollout_error_mean") for k, v in modes.items()}
+    if all(e is not None for e in errs.values()):
+        best = min(errs.values())
+        equal = [k for k, e in errs.items() if e <= max(1.05 * best, best + 1e-4)]
+        rule = "fastest mode whose rollout error is at most 1.05x the best mode's (or within 1e-4)"
+    else:
+        equal = list(modes)
+        rule = "no rollout error measured (untrained network): fastest mode"
+    head = max(equal, key=lambda k: modes[k]["point_evals_per_s"])
+    out["headline_mode"] = head
+    out["headline_rule"] = rule
     if len(precs) == 2:
         a, b = precs
         out["precision_study"] = {
-            name: {"speedup_" + a + "_vs_fp32": out[b][name]["ms_per_step"] / out[a][name]["ms_per_step"],
-                   "rollout_error_" + a: out[a][name].get("rollout_error_mean"),
-                   "rollout_error_fp32": out[b][name].get("rollout_error_mean")}
-            for name in ("gn", "lls")}
+            kind: {"speedup_" + a + "_vs_fp32": modes[f"{b}_{kind}"]["ms_per_step"] / modes[f"{a}_{kind}"]["ms_per_step"],
+                   "rollout_error_" + a: modes[f"{a}_{kind}"].get("rollout_error_mean"),
+                   "rollout_error_fp32": modes[f"{b}_{kind}"].get("rollout_error_mean")}
+            for kind in ("gn", "lls")}
     return out
 
 
@@ -372,7 +454,7 @@ def siren_leg(args, crom, torch, dev):
         t_jac = e[0].elapsed_time(e[1]) * 1e-3 / 10
         st = crom.Stepper(dec, [0, wl.n_samples], samples)
         nu = torch.tensor([wl.mu], dtype=torch.float64, device=dev)
-        opts = crom.GNOptions(max_iter=5, tol_step=TOL_STEP)
+        opts = crom.GNOptions(max_iter=5, tol_step=TOL_STEP[prec])
         q = [q0[None].clone(), torch.empty(1, R, dtype=torch.float64, device=dev)]
         for i in range(5):
             st.step(q[i % 2], nu, wl.dt, opts, q_next=q[(i + 1) % 2])
@@ -424,7 +506,7 @@ def config1_leg(args, crom, torch, dev):
     w = Heat1D(seed=args.seed)
     dec = crom.Decoder.from_layers(w.layers, w.m, precision="fp32", device=dev)
     st = crom.Stepper(dec, [0, w.n_samples], torch.from_numpy(w.samples).to(dev))
-    opts = crom.GNOptions(max_iter=w.max_iter, tol_step=TOL_STEP)
+    opts = crom.GNOptions(max_iter=w.max_iter, tol_step=TOL_STEP["fp32"])
     q0 = np.asarray(w.ic, dtype=np.float64).copy()  # a generic starting latent (r = 3)
     q = [torch.from_numpy(q0[None].copy()).to(dev), torch.empty(1, w.r, dtype=torch.float64, device=dev)]
     nu = torch.tensor([w.nu], dtype=torch.float64, device=dev)
@@ -448,7 +530,7 @@ def config1_leg(args, crom, torch, dev):
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()
             qs, _ = ostep.heat_rollout(odec, w.samples.astype(np.float64), q0, w.nu, w.dt, args.c1_steps,
-                                       GNOptions(max_iter=w.max_iter, tol_step=TOL_STEP))
+                                       GNOptions(max_iter=w.max_iter, tol_step=TOL_STEP["fp32"]))
             t_cpu = time.perf_counter() - t0
         out["oracle_cpu_s_1_thread"] = t_cpu
         out["gpu_vs_oracle_q_maxdiff"] = float(np.abs(q_gpu - qs[-1]).max())
@@ -479,7 +561,7 @@ def config3_leg(args, crom, torch, dev):
         st = crom.Stepper(dec, [0, len(X)], torch.from_numpy(X).to(dev), torch.from_numpy(clamp).to(dev),
                           pde="neohookean")
         res = {}
-        for name, opts in (("gn", crom.GNOptions(max_iter=5, tol_step=TOL_STEP)),
+        for name, opts in (("gn", crom.GNOptions(max_iter=5, tol_step=TOL_STEP[prec])),
                            ("lls", crom.GNOptions(max_iter=1, linearized=True))):
             # every timed step starts from the same state (the untrained bar's
             # rollout would wander into degenerate latents within a few steps)
@@ -520,7 +602,7 @@ def config3_leg(args, crom, torch, dev):
         odec = mlp.MLPDecoder(w.layers, w.m)
         t0 = time.perf_counter()
         elastic.elastic_step(odec, X.astype(np.float64), w.q0, w.q0, w.lam, w.mu, w.rho0, w.gravity, w.dt,
-                             GNOptions(max_iter=5, tol_step=TOL_STEP), clamp)
+                             GNOptions(max_iter=5, tol_step=TOL_STEP["fp32"]), clamp)
         out["oracle_cpu_s_per_gn_step"] = time.perf_counter() - t0
     return out
 
@@ -560,7 +642,7 @@ def guess_leg(args, crom, torch, dev, trained):
     out = {"workload": f"{n} held-out diffusivities, 500 samples, one step of dt {dt}, Gauss-Newton <= 1 or 3 iterations",
            "guess_ms": e[0].elapsed_time(e[1]) / 10}
     for it in (1, 3):
-        opts = crom.GNOptions(max_iter=it, tol_step=TOL_STEP)
+        opts = crom.GNOptions(max_iter=it, tol_step=TOL_STEP[args.prec])
         for name, q_init in (("from_q_n", None), ("from_encoder_guess", guess)):
             st.step(q_n, nu, dt, opts, q_init=q_init)
             inf = st.info()
@@ -593,7 +675,7 @@ def fe_leg(args, crom, torch, dev):
         dec = crom.Decoder.from_layers(w.layers, w.m, precision=prec, device=dev)
         st = crom.Stepper(dec, sm.offsets, sm.y, pde="corotated_fe", mesh=sm)
         res = {}
-        for name, opts in (("gn", crom.GNOptions(max_iter=5, tol_step=TOL_STEP)),
+        for name, opts in (("gn", crom.GNOptions(max_iter=5, tol_step=TOL_STEP[prec])),
                            ("lls", crom.GNOptions(max_iter=1, linearized=True))):
             q = torch.from_numpy(w.q0.copy()).to(dev)
             q_prev = q - 1e-3
@@ -618,15 +700,105 @@ def fe_leg(args, crom, torch, dev):
     return out
 
 
+def single_leg(args, crom, torch, dev):
+    """One instance of 2D heat (decoder (x in R^2, q in R^8) -> 5 ELU layers
+    of width 128 -> 1, Xavier-uniform from a seed; mu ~ U(0.1, 1); 2,000
+    samples uniform in (0, 1)^2; dt = 1e-4): per step the full-field decode
+    of the 65,536 nodes of the 256 x 256 grid, then one latent step at the
+    samples (Gauss-Newton, up to 5 iterations, the persistent step kernel);
+    the steps form a rollout.  Latency-bound: one 16-sample batch per
+    workgroup and dependent phases.  Reported in the headline's unit, with
+    the step kernel's roofline, and the linearised step's rate."""
+    from workloads import Heat2D
+    wl = Heat2D(seed=args.seed)
+    nodes = wl.nodes
+    dec = crom.Decoder.from_layers(wl.layers, wl.m, precision=args.prec, device=dev)
+    X = torch.from_numpy(nodes).to(dev)
+    st = crom.Stepper(dec, [0, wl.n_samples], torch.from_numpy(wl.samples).to(dev))
+    q = [torch.from_numpy(wl.q0[None].copy()).to(dev), torch.empty(1, R, dtype=torch.float64, device=dev)]
+    nu = torch.tensor([wl.mu], dtype=torch.float64, device=dev)
+    g = torch.empty(len(nodes), 1, dtype=torch.float32, device=dev)
+    opts = crom.GNOptions(max_iter=5, tol_step=TOL_STEP[args.prec])
+
+    # The decode and the step run one after the other on one stream (a
+    # second stream for the decode slowed the persistent step kernel: its
+    # per-phase latency suffers from co-running workgroups).
+    def one(i, ev=None):
+        if ev is not None:
+            ev[0].record()
+        dec.decode(X, q[i % 2], out=g)
+        if ev is not None:
+            ev[1].record()
+        st.step(q[i % 2], nu, wl.dt, opts, q_next=q[(i + 1) % 2])
+        if ev is not None:
+            ev[2].record()
+
+    for i in range(args.warmup):
+        one(i)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    crom.kernel_timer(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        one(args.warmup + i, evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    crom.kernel_timer(False)
+    k_ms, k_n = crom.kernel_timer_read()
+    t_dec = np.array([e[0].elapsed_time(e[1]) for e in evs]) * 1e-3
+    t_step = np.array([e[1].elapsed_time(e[2]) for e in evs]) * 1e-3
+    # the same rollout again, untimed, reading every step's outcome
+    q[0].copy_(torch.from_numpy(wl.q0[None].copy()))
+    for i in range(args.warmup):
+        one(i)
+    flop_step, its, lse, flags = 0.0, [], [], 0
+    for i in range(args.steps):
+        one(args.warmup + i)
+        inf = st.info()[0]
+        its.append(int(inf["iters"]))
+        lse.append(int(inf["ls_evals"]))
+        flags |= int(inf["flags"])
+        flop_step += step_flops(wl.n_samples, int(inf["iters"]), int(inf["ls_evals"]))
+    torch.cuda.synchronize()
+    flop_dec = args.steps * len(nodes) * FLOP_VALUE_COL
+    t_kernel = k_ms * 1e-3 / max(1, k_n)
+    fl = flop_step / args.steps
+    achieved = fl / t_kernel / 1e12
+    # the linearised inversion (one normal-equation solve per step), same rollout
+    lls = crom.GNOptions(max_iter=1, linearized=True)
+    q[0].copy_(torch.from_numpy(wl.q0[None].copy()))
+    for i in range(args.warmup):
+        st.step(q[i % 2], nu, wl.dt, lls, q_next=q[(i + 1) % 2])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        st.step(q[i % 2], nu, wl.dt, lls, q_next=q[(i + 1) % 2])
+    torch.cuda.synchronize()
+    return {"workload": "2D heat, 256x256 grid: full-field decode of 65,536 nodes + one Gauss-Newton latent "
+                        "step at 2,000 samples per step, one instance, Xavier-uniform network",
+            "precision": args.prec, "gn_tol_step": TOL_STEP[args.prec],
+            "point_evals_per_s": (flop_dec + flop_step) / FLOP_POINT_EVAL / wall,
+            "ms_per_step": wall / args.steps * 1e3, "latent_steps_per_s": args.steps / wall,
+            "lls_latent_steps_per_s": args.steps / (time.perf_counter() - t1),
+            "step_ms_avg": t_step.mean() * 1e3, "decode_ms_avg": t_dec.mean() * 1e3,
+            "gn_iters_mean": float(np.mean(its)), "ls_evals_mean": float(np.mean(lse)), "flags_or": flags,
+            "step_kernel": {"avg_ms": t_kernel * 1e3, "flop_per_launch": fl, "achieved_tflops": achieved,
+                            "frac": achieved / PEAK[args.prec],
+                            "traffic": measured_traffic("step_kernel")},
+            "decode_kernel": {"avg_ms": t_dec.mean() * 1e3,
+                              "achieved_tflops": len(nodes) * FLOP_VALUE_COL / t_dec.mean() / 1e12}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--prec", default="bf16", choices=sorted(PEAK))
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="host seconds for the oracle's sample of the headline workload (0: skip)")
+    ap.add_argument("--single", type=int, default=1, help="the single-instance 2D heat leg (0: skip)")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--train-time-steps", type=int, default=50)
     ap.add_argument("--train-steps", type=int, default=20000,
                     help="BF16 training run whose network the batched leg rolls out (0: untrained)")
@@ -649,137 +821,64 @@ def main():
 
     import torch
     from paper_2206_02607_amd import crom
-    from workloads import Heat2D
 
     dev = torch.device("cuda:0")
-    wl = Heat2D(seed=args.seed)
-    nodes = wl.nodes
-    dec = crom.Decoder.from_layers(wl.layers, wl.m, precision=args.prec, device=dev)
-    X = torch.from_numpy(nodes).to(dev)
-    st = crom.Stepper(dec, [0, wl.n_samples], torch.from_numpy(wl.samples).to(dev))
-    q = [torch.from_numpy(wl.q0[None].copy()).to(dev), torch.empty(1, R, dtype=torch.float64, device=dev)]
-    nu = torch.tensor([wl.mu], dtype=torch.float64, device=dev)
-    g = torch.empty(len(nodes), 1, dtype=torch.float32, device=dev)
-    opts = crom.GNOptions(max_iter=5, tol_step=TOL_STEP)
-
-    # The decode and the step run one after the other on one stream.  They are
-    # independent within a step (both read only q_n), but running the decode
-    # on a second stream beside the persistent step kernel slowed the step
-    # kernel from 0.158 to 0.188 ms (its per-phase latency suffers from
-    # co-running workgroups) and the whole step from 0.209 to 0.218 ms.
-    def one(i, ev=None):
-        if ev is not None:
-            ev[0].record()
-        dec.decode(X, q[i % 2], out=g)
-        if ev is not None:
-            ev[1].record()
-        st.step(q[i % 2], nu, wl.dt, opts, q_next=q[(i + 1) % 2])
-        if ev is not None:
-            ev[2].record()
-
-    if args.copy_probe_mib > 0:
+    if args.copy_probe_mib > 0:  # a copy of known size for the counter calibration
         src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for i in range(args.warmup):
-        one(i)
-    torch.cuda.synchronize()
-    infos = []
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    crom.kernel_timer(True)  # HIP events around the step's compute kernels, on the launch stream
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        one(args.warmup + i, evs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    crom.kernel_timer(False)
-    k_ms, k_n = crom.kernel_timer_read()
-    # per-step work: the step's iteration counts (one sync per step, outside the timed region)
-    t_dec = np.array([e[0].elapsed_time(e[1]) for e in evs]) * 1e-3
-    t_step = np.array([e[1].elapsed_time(e[2]) for e in evs]) * 1e-3
-    # iteration statistics of the timed rollout: rerun it untimed, step by step
-    q[0].copy_(torch.from_numpy(wl.q0[None].copy()))
-    for i in range(args.warmup):
-        one(i)
-    flop_step = 0.0
-    for i in range(args.steps):
-        one(args.warmup + i)
-        inf = st.info()[0]
-        infos.append(inf)
-        flop_step += step_flops(wl.n_samples, int(inf["iters"]), int(inf["ls_evals"]))
-    torch.cuda.synchronize()
-    flop_dec = args.steps * len(nodes) * FLOP_VALUE_COL
-    value = (flop_dec + flop_step) / FLOP_POINT_EVAL / wall
-    ms = wall / args.steps * 1e3
-
-    # dominant kernel for the roofline
-    dec_flop = len(nodes) * FLOP_VALUE_COL
-    # the step kernel's own duration (its events exclude the set-up launch)
-    t_step_kernel = k_ms * 1e-3 / max(1, k_n)
-    cand = {"decode": (t_dec.mean(), dec_flop), "step": (t_step_kernel, flop_step / args.steps)}
-    name = max(cand, key=lambda k: cand[k][0])
-    t_avg, fl = cand[name]
-    achieved = fl / t_avg / 1e12
-    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.prec], "unit": "TFLOP/s",
-            "frac": achieved / PEAK[args.prec],
-            "traffic": measured_traffic({"decode": "decode_kernel", "step": "step_kernel"}[name]),
-            "kernel": {"decode": "decode_kernel (full field, value column)",
-                       "step": "step_kernel (persistent latent step)"}[name],
-            "avg_ms": t_avg * 1e3, "flop_per_launch": fl,
-            "other": {k: {"avg_ms": v[0] * 1e3, "achieved_tflops": v[1] / v[0] / 1e12}
-                      for k, v in cand.items() if k != name}}
-
-    # the linearised inversion (one normal-equation solve per step), same rollout
-    lls = crom.GNOptions(max_iter=1, linearized=True)
-    q[0].copy_(torch.from_numpy(wl.q0[None].copy()))
-    for i in range(args.warmup):
-        st.step(q[i % 2], nu, wl.dt, lls, q_next=q[(i + 1) % 2])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for i in range(args.steps):
-        st.step(q[i % 2], nu, wl.dt, lls, q_next=q[(i + 1) % 2])
-    torch.cuda.synchronize()
-    lls_steps_per_s = args.steps / (time.perf_counter() - t1)
-
+    training, trained = train_leg(args, crom, torch, dev) if args.train_time_steps > 0 else (None, None)
+    batched = batched_leg(args, crom, torch, dev, trained)
+    single = single_leg(args, crom, torch, dev) if args.single else None
     c1 = config1_leg(args, crom, torch, dev) if args.c1_steps > 0 else None
     c3 = config3_leg(args, crom, torch, dev) if args.c3_steps > 0 else None
-    training, trained = train_leg(args, crom, torch, dev) if args.train_time_steps > 0 else (None, None)
-    batched = batched_leg(args, crom, torch, dev, trained) if args.batched_steps > 0 else None
     sampling = sampling_leg(args, crom, torch, dev, trained) if trained and args.sampling_rounds > 0 else None
     guess = guess_leg(args, crom, torch, dev, trained) if trained else None
     siren = siren_leg(args, crom, torch, dev) if args.siren else None
     fe = fe_leg(args, crom, torch, dev) if args.fe_steps > 0 else None
-    cpu = cpu_baseline(wl, nodes, args.cpu_steps) if args.cpu_steps > 0 else None
-    its = np.array([int(i["iters"]) for i in infos])
-    lse = np.array([int(i["ls_evals"]) for i in infos])
+
+    head = batched["modes"][batched["headline_mode"]]
+    prec, lin = head["precision"], head["inversion"] == "linearised"
+    kernel_s = head["timed_kernels_ms"] * 1e-3
+    achieved = head["flop_per_step"] / kernel_s / 1e12
+    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
+            "frac": achieved / PEAK[prec],
+            "traffic": measured_traffic("lls_jets_kernel", "traffic_batched_2d_heat.json") if lin else None,
+            "kernel": head["timed_kernels"], "avg_ms": head["timed_kernels_ms"],
+            "flop_per_launch": head["flop_per_step"],
+            "flop_unit": "1,576,448 algorithmic FLOP per point-eval (12 columns of the 2D decoder, folded first "
+                         "layer, no padding) x the point-evals of one step"}
+    cpu = None
+    if args.cpu_seconds > 0:
+        from workloads import Batched2D
+        kw = {"max_iter": 1, "linearized": True} if lin else {"max_iter": 5, "tol_step": TOL_STEP["fp32"]}
+        cpu = cpu_baseline_batched(Batched2D(seed=args.seed), kw, args.cpu_seconds)
     out = {
         "metric": "decoder+Jacobian point-evals/sec and latent steps/sec at fixed rollout error",
-        "value": value, "unit": "point-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.prec, "data": "synthetic",
-        "config": {"workload": "2D heat, 256x256 grid: full-field decode of 65,536 nodes + one "
-                               "Gauss-Newton latent step at 2,000 samples per step",
-                   "decoder": "(x in R^2, q in R^8) -> 5 x ELU width 128 -> 1, Xavier-uniform, seed "
-                              f"{args.seed}",
-                   "mu": wl.mu, "dt": wl.dt, "gn_max_iter": 5, "precision": args.prec},
-        "latent_steps_per_s": args.steps / wall,
-        "lls_latent_steps_per_s": lls_steps_per_s,
-        "gn_tol_step": TOL_STEP,
-        "step_ms_avg": t_step.mean() * 1e3, "step_kernel_ms_avg": t_step_kernel * 1e3,
-        "decode_ms_avg": t_dec.mean() * 1e3,
-        "gn_iters_mean": float(its.mean()), "ls_evals_mean": float(lse.mean()),
+        "value": head["point_evals_per_s"], "unit": "point-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"bf16": "bf16", "fp32": "fp32", "bf16x3": "bf16", "bf16pure": "bf16"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "batched rollout of 512 2D heat instances (mu_i ~ U(0.1, 1), S_i ~ U{200..2000} "
+                               "samples of the 128x128 lattice, r = 8, dt = 1e-4), trained network, one latent "
+                               "step of every instance per step",
+                   "mode": batched["headline_mode"], "mode_rule": batched["headline_rule"],
+                   "precision": prec, "inversion": head["inversion"]},
+        "latent_steps_per_s": head["instance_steps_per_s"],
+        "rollout_error": head.get("rollout_error_mean"),
         "roofline": roof,
+        "cpu_baseline": cpu,
+        "batched": batched,
+        "heat2d_single": single,
         "heat1d": c1,
         "elastic3d": c3,
         "training": training,
-        "batched": batched,
         "sampling": sampling,
         "encoder_guess": guess,
         "siren": siren,
         "corotated_fe": fe,
-        "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 

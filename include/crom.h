@@ -148,7 +148,7 @@ crom_status crom_decode_jac_q(const crom_net* net, const float* x, int64_t P, co
  * Latent step for a batch of independent instances.
  * ------------------------------------------------------------------------- */
 
-enum { CROM_PDE_HEAT = 0, CROM_PDE_NEOHOOKEAN = 1, CROM_PDE_COROTATED_FE = 2 };
+enum { CROM_PDE_HEAT = 0, CROM_PDE_NEOHOOKEAN = 1, CROM_PDE_COROTATED_FE = 2, CROM_PDE_PROJECT = 3 };
 
 /* Finite-element stencil of the samples for CROM_PDE_COROTATED_FE (appendix,
  * Sec. "Solid Mechanics / Reduced-order Model": the forces on a sample come
@@ -230,7 +230,11 @@ crom_status crom_fe_stencil(int64_t n_vert, int64_t n_tet, const int32_t* tets, 
  *   and u+ = u + dt v+ as for NEOHOOKEAN.  coef [n_inst][6] FP64 = lam,
  *   mu, rho0, Bx, By, Bz.  Needs the (3, 16, 3, 256) decoder and at most
  *   65535 instances.  A tetrahedron with det F <= 0 makes its instance
- *   NONFINITE. */
+ *   NONFINITE.
+ * PROJECT: no time stepping: the targets are given, coef [total_samples]
+ *   FP64 = f(y) at the samples, and the step is the inversion alone (eq.
+ *   "invert", Sec. "Network Inversion"): q_{n+1} = argmin |g(Y, q) - f|^2
+ *   from q_n (dt is ignored).  Needs d == 1 and m <= 2 (the heat shapes). */
 typedef struct {
   int32_t kind, _pad;
   double dt;
@@ -263,8 +267,11 @@ enum {
   CROM_FLAG_SINGULAR = 2,  /* Cholesky pivot <= 1e-14 * max diag(J^T J)     */
   CROM_FLAG_NONFINITE = 4, /* NaN/Inf in the residual or normal equations   */
   CROM_FLAG_LS_FAIL = 8,   /* no trial step satisfied the Armijo condition  */
-  CROM_FLAG_ABORTED = 16   /* the step kernel gave up waiting on a phase (an
+  CROM_FLAG_ABORTED = 16,  /* the step kernel gave up waiting on a phase (an
                               internal error; q_next holds the last iterate) */
+  CROM_FLAG_INVERTED = 32  /* elastic kinds: det F <= 0 at a sample that is not
+                              clamped (no stress there; NONFINITE follows from
+                              its NaN targets and q_next = q_n) */
 };
 
 /* Per-instance outcome (device memory, written by crom_step). */
@@ -530,6 +537,30 @@ crom_status crom_heat_guess(const crom_net* net, const crom_encoder* enc, const 
                             int32_t n_inst, const double* q_n, const double* nu, double dt, double* q_guess,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* Full-order fallback for failed heat steps (Sec. "Thermodynamics /
+ * Full-order Model", "Image Processing / Full-order Model"): for each listed
+ * instance, its last good latent q_last is decoded at every node of the
+ * (nx, ny) grid, the field is advanced by `substeps` steps of crom_fd_heat
+ * with that instance's diffusivity, and the result is projected back onto
+ * the decoder at every node by the method's own inversion (crom_step with
+ * CROM_PDE_PROJECT from q_last, Gauss-Newton with `opts`), giving q_next
+ * (FP64).  Other instances are not touched.
+ *   nodes    [nx * ny][2] FP32, node (i_x, i_y) at index i_x * ny + i_y;
+ *            boundary nodes are held at 0
+ *   inst     HOST [n_fail] distinct instance indices in [0, n_inst)
+ *   q_last   [n_inst][r] FP64, nu [n_inst] FP64, q_next [n_inst][r] FP64
+ *   info     NULL or [n_inst] crom_step_info: the listed instances' entries
+ *            receive the projection's outcome
+ *   ws       crom_heat_fallback_workspace bytes
+ * Needs m == 2 and d == 1.  The caller picks the instances from
+ * crom_step_info (SINGULAR, NONFINITE, LS_FAIL), which makes the fallback a
+ * host decision (one read of the flags). */
+crom_status crom_heat_fallback_workspace(const crom_net* net, int32_t n_fail, int64_t nx, int64_t ny, size_t* bytes);
+crom_status crom_heat_fallback(const crom_net* net, const float* nodes, int64_t nx, int64_t ny, double dx,
+                               int32_t n_inst, int32_t n_fail, const int32_t* inst, const double* q_last,
+                               const double* nu, double dt_fd, int64_t substeps, const crom_gn_opts* opts,
+                               double* q_next, crom_step_info* info, void* ws, size_t ws_bytes, void* stream);
+
 /* Vector-Jacobian product of the decoder (the backward of crom_decode over
  * B latents): with G[b][p][o] = g(x_p, q_b)_o and a cotangent dg [B][P][d],
  *   grad_params = sum dg . dG/dparams   (natural layout, overwritten)
@@ -635,23 +666,17 @@ crom_status crom_robust_sampling(const crom_net* net, const crom_pde* pde, int32
                                  double* trace_metric, void* ws, size_t ws_bytes, void* stream);
 
 /* Benchmark support.  crom_kernel_timer(1) starts a record on the calling
- * host thread (dropping any earlier one): every later crom_step on this
- * thread then records a pair of HIP events on its stream, right after its
- * set-up launch and right after its last launch, so that the pair brackets
- * the step's compute kernels.  crom_kernel_timer(0) stops recording.
- * crom_kernel_timer_read waits for the recorded events and returns the
- * summed milliseconds of the pairs and their number. */
+ * host thread (releasing any earlier one): every later crom_step on this
+ * thread then records a pair of HIP events on its stream that brackets the
+ * step's compute kernels: the persistent step kernel, every round of the
+ * batched Gauss-Newton path, or the linearised path's evaluation kernel
+ * (its small solve kernel is left out).  The set-up launch is never inside
+ * a pair.  crom_kernel_timer(0) stops recording.  crom_kernel_timer_read
+ * waits for the recorded events, returns the summed milliseconds of the
+ * pairs and their number, and, when recording has stopped, destroys the
+ * events. */
 crom_status crom_kernel_timer(int32_t on);
 crom_status crom_kernel_timer_read(double* total_ms, int64_t* count);
-
-/* Debugging aid: when buf (device memory, 128 uint64) is not NULL, every
- * later crom_step writes the GPU wall-clock tick (100 MHz) at each phase
- * boundary of its step kernel's first and last workgroup into it: slots
- * 0..63 and 64..127, in the order start, end of the first evaluation, after
- * its barrier, after the first solve, then four marks per round (start,
- * end of evaluation, after its barrier, after the solve).  NULL turns it
- * off. */
-void crom_debug_step_trace(uint64_t* buf);
 
 /* Message describing the last error returned on the calling thread. */
 const char* crom_last_error(void);

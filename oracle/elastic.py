@@ -17,13 +17,16 @@ derivatives):
   the network's x-Hessian: (div P)_i = sum_{j,k,l} dP_ij/dF_kl d2u_k/dX_l dX_j;
 * symplectic Euler at the samples: v+ = v + dt (div P / rho0 + B),
   u+ = u + dt v+; a clamped sample targets u+ = 0;
-* the inversion then projects u+ onto the decoder exactly as for heat.
+* the inversion then projects u+ onto the decoder exactly as for heat;
+* det F <= 0 at a sample whose update uses the stress (not clamped) has no
+  neo-Hookean energy (ln J): the step reports INVERTED, and its NaN targets
+  make the inversion stop with NONFINITE at q_n.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .inversion import GNOptions
+from .inversion import INVERTED, GNOptions
 from .step import invert
 
 
@@ -34,10 +37,26 @@ def energy(F: np.ndarray, lam: float, mu: float) -> float:
     return 0.5 * mu * (np.sum(F * F) - 3.0) - mu * lnJ + 0.5 * lam * lnJ ** 2
 
 
+def _inv(F: np.ndarray) -> np.ndarray:
+    """F^-1 for F [.., 3, 3]; NaN where F is exactly singular (det F = 0 is
+    an inverted sample: no stress, NaN like ln J of det F < 0)."""
+    F = np.asarray(F, dtype=np.float64)
+    flat = F.reshape(-1, 3, 3)
+    out = np.full_like(flat, np.nan)
+    ok = np.linalg.det(flat) != 0.0
+    out[ok] = np.linalg.inv(flat[ok])
+    return out.reshape(F.shape)
+
+
+def _ln_det(F: np.ndarray) -> np.ndarray:
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.log(np.linalg.det(F))
+
+
 def pk1(F: np.ndarray, lam: float, mu: float) -> np.ndarray:
     """First Piola-Kirchhoff stress P(F) [.., 3, 3] for F [.., 3, 3]."""
-    FinvT = np.swapaxes(np.linalg.inv(F), -1, -2)
-    lnJ = np.log(np.linalg.det(F))[..., None, None]
+    FinvT = np.swapaxes(_inv(F), -1, -2)
+    lnJ = _ln_det(F)[..., None, None]
     return mu * (F - FinvT) + lam * lnJ * FinvT
 
 
@@ -45,8 +64,8 @@ def dpk1(F: np.ndarray, lam: float, mu: float) -> np.ndarray:
     """dP_ij / dF_kl [.., 3, 3, 3, 3] (written out from P's three terms:
     d F = I (x) I, d F^-T_ij / d F_kl = -Finv_jk Finv_li, d ln J / d F_kl =
     Finv_lk)."""
-    Fi = np.linalg.inv(F)
-    lnJ = np.log(np.linalg.det(F))[..., None, None, None, None]
+    Fi = _inv(F)
+    lnJ = _ln_det(F)[..., None, None, None, None]
     eye = np.eye(3)
     t1 = np.einsum("ik,jl->ijkl", eye, eye)
     t2 = np.einsum("...jk,...li->...ijkl", Fi, Fi)
@@ -79,8 +98,18 @@ def elastic_targets(decoder, X: np.ndarray, q_n: np.ndarray, q_prev, lam: float,
     return u + inc, inc
 
 
+def inverted(decoder, X: np.ndarray, q_n: np.ndarray, clamp=None) -> bool:
+    """Whether det(I + du/dX) <= 0 at a sample that is not clamped."""
+    _, G, _, _ = decoder.jets(X, q_n)
+    det = np.linalg.det(np.eye(3)[None] + G)
+    free = np.ones(det.shape, bool) if clamp is None else ~np.asarray(clamp, dtype=bool)
+    return bool(np.any((det <= 0.0) & free))
+
+
 def elastic_step(decoder, X, q_n, q_prev, lam, mu, rho0, B, dt, opts: GNOptions, clamp=None):
     """q_n -> q_{n+1}; returns (q_next, info, targets)."""
     target, _ = elastic_targets(decoder, X, q_n, q_prev, lam, mu, rho0, B, dt, clamp)
     q_next, info = invert(decoder, X, target, q_n, opts)
+    if inverted(decoder, X, q_n, clamp):
+        info.flags |= INVERTED
     return q_next, info, target

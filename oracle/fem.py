@@ -42,7 +42,7 @@ from typing import List, Tuple
 
 import numpy as np
 
-from .inversion import GNOptions
+from .inversion import INVERTED, GNOptions
 from .step import invert
 
 
@@ -166,8 +166,28 @@ def fem_targets(decoder, X: np.ndarray, tets: np.ndarray, samples, q_n: np.ndarr
     return u + inc, inc
 
 
+def inverted(decoder, X: np.ndarray, tets: np.ndarray, samples, q_n: np.ndarray, clamp=None) -> bool:
+    """Whether a tetrahedron incident on a sample that is not clamped has
+    det F <= 0 (no proper rotation factor: the corotated stress is
+    undefined and the step reports INVERTED)."""
+    X = np.asarray(X, dtype=np.float64)
+    samples = np.asarray(samples)
+    inc, ring = one_ring(tets, samples)
+    x = np.full_like(X, np.nan)
+    x[ring] = X[ring] + decoder.value(X[ring], q_n)
+    free = np.ones(len(samples), bool) if clamp is None else ~np.asarray(clamp, dtype=bool)
+    for s, ts in enumerate(inc):
+        if free[s] and any(np.linalg.det(deformation_gradient(x, X, tets[t])) <= 0.0 for t in ts):
+            return True
+    return False
+
+
 def fem_step(decoder, X, tets, samples, q_n, q_prev, lam, mu, rho0, B, dt, opts: GNOptions, clamp=None):
-    """q_n -> q_{n+1}; returns (q_next, info, targets)."""
+    """q_n -> q_{n+1}; returns (q_next, info, targets).  A sample's incident
+    tetrahedron with det F <= 0 reports INVERTED (with NONFINITE from its NaN
+    forces)."""
     target, _ = fem_targets(decoder, X, tets, samples, q_n, q_prev, lam, mu, rho0, B, dt, clamp)
     q_next, info = invert(decoder, np.asarray(X, dtype=np.float64)[np.asarray(samples)], target, q_n, opts)
+    if inverted(decoder, X, tets, samples, q_n, clamp):
+        info.flags |= INVERTED
     return q_next, info, target

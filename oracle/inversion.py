@@ -25,7 +25,8 @@ backtracking scheme, Nocedal & Wright, Alg. 3.1):
 * the linearised variant is one Gauss-Newton step with alpha = 1 forced.
 
 Status flags (bit values shared with the C interface by definition, not by
-code): MAXITER 1, SINGULAR 2, NONFINITE 4, LS_FAIL 8, INVERTED 16.
+code): MAXITER 1, SINGULAR 2, NONFINITE 4, LS_FAIL 8, INVERTED 32 (16 is the
+GPU's ABORTED, which has no counterpart here).
 """
 from __future__ import annotations
 
@@ -33,7 +34,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-MAXITER, SINGULAR, NONFINITE, LS_FAIL, INVERTED = 1, 2, 4, 8, 16
+MAXITER, SINGULAR, NONFINITE, LS_FAIL, INVERTED = 1, 2, 4, 8, 32
 PIVOT_REL = 1e-14
 
 

@@ -16,14 +16,18 @@ from typing import Optional, Sequence, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcrom.so")
+# CROM_LIBRARY selects another build of the same library (the host
+# sanitizer build); the default is the in-tree libcrom.so
+LIB_PATH = os.environ.get("CROM_LIBRARY") or os.path.join(_HERE, "libcrom.so")
 
 PREC_FP32, PREC_BF16, PREC_BF16_PURE, PREC_BF16X3 = 0, 1, 2, 3
 D2_NONE, D2_LAPLACIAN, D2_HESSIAN = 0, 1, 2
-PDE_HEAT, PDE_NEOHOOKEAN, PDE_COROTATED_FE = 0, 1, 2
+PDE_HEAT, PDE_NEOHOOKEAN, PDE_COROTATED_FE, PDE_PROJECT = 0, 1, 2, 3
 ACT_ELU, ACT_SINE = 0, 1
 _ACT_NAMES = {"elu": ACT_ELU, "sine": ACT_SINE}
-FLAG_MAXITER, FLAG_SINGULAR, FLAG_NONFINITE, FLAG_LS_FAIL, FLAG_ABORTED = 1, 2, 4, 8, 16
+FLAG_MAXITER, FLAG_SINGULAR, FLAG_NONFINITE, FLAG_LS_FAIL, FLAG_ABORTED, FLAG_INVERTED = 1, 2, 4, 8, 16, 32
+# a failed step: the rollout may hand the instance to the full-order fallback
+FLAGS_FAILED = FLAG_SINGULAR | FLAG_NONFINITE | FLAG_LS_FAIL
 _PREC_NAMES = {"fp32": PREC_FP32, "bf16": PREC_BF16, "bf16pure": PREC_BF16_PURE, "bf16x3": PREC_BF16X3}
 
 
@@ -167,13 +171,17 @@ def lib():
         L.crom_step_static.argtypes = [POINTER(CromNet), POINTER(CromPDE), c_int32, c_void_p, c_int64, c_void_p,
                                        c_void_p, c_void_p, c_void_p, c_void_p, POINTER(CromGNOpts), c_void_p,
                                        c_void_p]
+        L.crom_heat_fallback_workspace.argtypes = [POINTER(CromNet), c_int32, c_int64, c_int64, POINTER(c_size_t)]
+        L.crom_heat_fallback.argtypes = [POINTER(CromNet), c_void_p, c_int64, c_int64, c_double, c_int32, c_int32,
+                                         c_void_p, c_void_p, c_void_p, c_double, c_int64, POINTER(CromGNOpts),
+                                         c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
         L.crom_kernel_timer.argtypes = [c_int32]
         L.crom_kernel_timer_read.argtypes = [POINTER(c_double), POINTER(c_int64)]
         for name in ("crom_sampling_residual", "crom_sampling_candidates", "crom_sampling_workspace",
                      "crom_robust_sampling", "crom_kernel_timer", "crom_kernel_timer_read", "crom_fe_stencil", "crom_step_guess", "crom_heat_guess_workspace",
                      "crom_heat_guess", "crom_standardization_of", "crom_standardize",
                      "crom_fold_standardization", "crom_train_state_offsets", "crom_train_step_state",
-                     "crom_step_static"):
+                     "crom_step_static", "crom_heat_fallback_workspace", "crom_heat_fallback"):
             getattr(L, name).restype = c_int32
         for name in ("crom_net_pack", "crom_decode", "crom_decode_jac", "crom_decode_jac_x",
                      "crom_decode_jac_q", "crom_step_workspace", "crom_step", "crom_fd_heat",
@@ -550,6 +558,46 @@ def fold_standardization(dec: "Decoder", s, enc_params=None, n_in: int = 0, hidd
     dec.pack()
 
 
+class HeatFallback:
+    """The full-order fallback of failed heat steps (crom_heat_fallback):
+    decode at the grid nodes [nx * ny, 2] (index i_x * ny + i_y), FP64
+    finite-difference update with substep dt_fd, projection back onto the
+    decoder at every node (Gauss-Newton with `opts`)."""
+
+    def __init__(self, dec: "Decoder", nodes, nx: int, ny: int, dx: float, dt_fd: float,
+                 opts: "GNOptions" = None):
+        torch = _torch()
+        self.dec, self.nx, self.ny, self.dx, self.dt_fd = dec, nx, ny, dx, dt_fd
+        self.opts = opts if opts is not None else GNOptions(max_iter=3, tol_step=1e-6)
+        self.nodes = nodes.to(device=dec.params.device, dtype=torch.float32).contiguous()
+        self._ws = {}
+
+    def __call__(self, failed, q_last, nu, dt: float, q_next, info_buf=None) -> None:
+        """Replace q_next of the instances in `failed` (host ints) by the
+        projected full-order update of their fields over dt from q_last."""
+        torch = _torch()
+        inst = (ctypes.c_int32 * len(failed))(*[int(i) for i in failed])
+        n = len(failed)
+        substeps = int(round(dt / self.dt_fd))
+        if abs(substeps * self.dt_fd - dt) > 1e-9 * dt:
+            raise CromError("dt must be a multiple of the finite-difference substep")
+        net = self.dec._net()
+        if n not in self._ws:
+            nbytes = c_size_t(0)
+            _check(lib().crom_heat_fallback_workspace(ctypes.byref(net), n, self.nx, self.ny, ctypes.byref(nbytes)),
+                   "crom_heat_fallback_workspace")
+            self._ws[n] = torch.empty(nbytes.value, dtype=torch.uint8, device=q_next.device)
+        ws = self._ws[n]
+        nu = torch.as_tensor(nu, dtype=torch.float64, device=q_next.device).reshape(-1).contiguous()
+        self._nu = nu
+        o = self.opts.c_struct()
+        _check(lib().crom_heat_fallback(ctypes.byref(net), _ptr(self.nodes), self.nx, self.ny, self.dx,
+                                        q_next.shape[0], n, inst, _ptr(q_last), _ptr(nu), self.dt_fd, substeps,
+                                        ctypes.byref(o), _ptr(q_next),
+                                        info_buf.data_ptr() if info_buf is not None else None, _ptr(ws),
+                                        ws.numel(), _stream()), "crom_heat_fallback")
+
+
 def adam_step(params, grad, m, v, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
     """In-place Adam update of FP32 device tensors."""
     _check(lib().crom_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), t, lr,
@@ -628,7 +676,8 @@ class Stepper:
     def __init__(self, dec: Decoder, offsets, y, clamp=None, pde: str = "heat", mesh: "FEStencil" = None):
         torch = _torch()
         self.dec = dec
-        self.kind = {"heat": PDE_HEAT, "neohookean": PDE_NEOHOOKEAN, "corotated_fe": PDE_COROTATED_FE}[pde]
+        self.kind = {"heat": PDE_HEAT, "neohookean": PDE_NEOHOOKEAN, "corotated_fe": PDE_COROTATED_FE,
+                     "project": PDE_PROJECT}[pde]
         if (self.kind == PDE_COROTATED_FE) != (mesh is not None):
             raise CromError("the finite-element step, and only it, takes a mesh stencil")
         self.mesh = mesh
@@ -660,9 +709,7 @@ class Stepper:
         torch = _torch()
         dev = self.dec.params.device
         q_n = q_n.to(device=dev, dtype=torch.float64).contiguous()
-        per = 1 if self.kind == PDE_HEAT else 6
-        coef = torch.as_tensor(coef, dtype=torch.float64, device=dev).reshape(-1, per)
-        coef = coef.expand(self.n_inst, per).contiguous()
+        coef = self._coef_tensor(coef)
         if q_prev is not None:
             q_prev = q_prev.to(device=dev, dtype=torch.float64).contiguous()
         if q_next is None:
@@ -686,15 +733,27 @@ class Stepper:
                                      self.ws_ptr, self.ws_bytes, _stream()), "crom_step_guess")
         return q_next
 
+    def _coef_tensor(self, coef):
+        """The per-instance coefficients as the library reads them (heat: nu;
+        elastic kinds: 6 values; projection: the targets [total] FP64)."""
+        torch = _torch()
+        dev = self.dec.params.device
+        if self.kind == PDE_PROJECT:
+            coef = torch.as_tensor(coef, dtype=torch.float64, device=dev).reshape(-1).contiguous()
+            if coef.numel() != self.total * self.dec.d:
+                raise CromError("the projection takes one target per sample and output")
+            return coef
+        per = 1 if self.kind == PDE_HEAT else 6
+        coef = torch.as_tensor(coef, dtype=torch.float64, device=dev).reshape(-1, per)
+        return coef.expand(self.n_inst, per).contiguous()
+
     def step_static(self, q_n, coef, dt: float, opts: GNOptions = GNOptions(), q_next=None, q_prev=None):
         """crom_step_static: the same step with the library's own workspace
         (no allocation by the call; this object's workspace is not used)."""
         torch = _torch()
         dev = self.dec.params.device
         q_n = q_n.to(device=dev, dtype=torch.float64).contiguous()
-        per = 1 if self.kind == PDE_HEAT else 6
-        coef = torch.as_tensor(coef, dtype=torch.float64, device=dev).reshape(-1, per)
-        coef = coef.expand(self.n_inst, per).contiguous()
+        coef = self._coef_tensor(coef)
         if q_prev is not None:
             q_prev = q_prev.to(device=dev, dtype=torch.float64).contiguous()
         if q_next is None:

@@ -319,9 +319,17 @@ extern "C" {
 
 const char* crom_last_error(void) { return g_err.c_str(); }
 
+// Destroys the recorded events (explicitly, so that no HIP call is left
+// for thread or process exit).
+static void timer_release(KernelTimer& t) {
+  for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+  t.ev.clear();
+  t.used = 0;
+}
+
 crom_status crom_kernel_timer(int32_t on) {
   g_timer.on = on != 0;
-  if (on) g_timer.used = 0;
+  if (on) timer_release(g_timer);
   return CROM_OK;
 }
 
@@ -342,6 +350,7 @@ crom_status crom_kernel_timer_read(double* total_ms, int64_t* count) {
   }
   *total_ms = sum;
   *count = (int64_t)pairs;
+  if (!t.on) timer_release(t);
   return CROM_OK;
 }
 

@@ -138,7 +138,7 @@ __device__ __forceinline__ uint64_t gn_initial_word(int w, const double* q_n, in
 }
 
 struct WsLayout {
-  size_t blk_start, blk_inst, first_blk, nblk, sync, act_phase, inst_cnt, targets, rho0, partials,
+  size_t blk_start, blk_inst, first_blk, nblk, sync, act_phase, inst_cnt, inv, targets, rho0, partials,
       state, jets, work, work_cnt, jbuf, bcnt, total;
   int64_t nblk_max;
   int nred;
@@ -156,8 +156,9 @@ struct JetsLayout {
   __host__ __device__ int count() const { return d + d * m + d * nh + d * r; }
 };
 
-// sync words (one 256-byte line each): solved count, abort flag
-enum { SYNC_SOLVED = 0, SYNC_ABORT = 32 };
+// sync words (one 256-byte line each): solved count, abort flag, count of
+// workgroups that have left the persistent kernel
+enum { SYNC_SOLVED = 0, SYNC_ABORT = 32, SYNC_EXITED = 64 };
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -171,9 +172,10 @@ static WsLayout ws_layout(int r, int d, int m, int n_inst, int64_t total) {
   L.blk_inst = o;  o = align256(o + 4 * (size_t)L.nblk_max);
   L.first_blk = o; o = align256(o + 4 * (size_t)(n_inst + 1));
   L.nblk = o;      o = align256(o + 8);
-  L.sync = o;      o = align256(o + 512);
+  L.sync = o;      o = align256(o + 768);
   L.act_phase = o; o = align256(o + 8 * (size_t)(MAXP + 2));
   L.inst_cnt = o;  o = align256(o + 4 * (size_t)n_inst);
+  L.inv = o;       o = align256(o + 4 * (size_t)n_inst);  // elastic: det F <= 0 met at a free sample
   L.targets = o;   o = align256(o + 8 * (size_t)total * d);
   L.rho0 = o;      o = align256(o + 8 * (size_t)total * d);
   L.partials = o;  o = align256(o + 8 * (size_t)L.nblk_max * L.nred);
@@ -212,6 +214,7 @@ struct StepArgs {
   const float* y;
   const uint8_t* clamp;
   const double* coef;
+  const double* given;   // CROM_PDE_PROJECT: the targets at the samples (else NULL)
   double dt;
   const double* q_prev;  // elastic: latent of the previous step (NULL: at rest)
   const double* q_n;
@@ -240,17 +243,30 @@ template <class T>
 __device__ __forceinline__ void st_c(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// every thread: wait until this thread's memory operations have completed
-__device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
+// Every thread: wait until this thread's memory operations have completed.
+// The empty asm statements with a memory clobber are compiler barriers: no
+// load or store (atomic or not) is moved across the wait, so every
+// coherent store issued before it is acknowledged before the arrival count
+// that follows it, and no load of a later phase is hoisted above it.
+__device__ __forceinline__ void wait_mem() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0);
+  asm volatile("" ::: "memory");
+}
 
 // Phase timestamps of workgroups 0 and G-1 (wall clock, 100 MHz ticks),
-// written only when a trace buffer was registered.
+// compiled only into probe builds (CROM_STEP_TRACE) and written only when a
+// trace buffer was registered there.
+#ifdef CROM_STEP_TRACE
 __device__ __forceinline__ void trace_mark(const StepArgs& a, int slot) {
   if (a.trace && threadIdx.x == 0 && slot < 64) {
     if (blockIdx.x == 0) a.trace[slot] = wall_clock64();
     if (blockIdx.x == gridDim.x - 1) a.trace[64 + slot] = wall_clock64();
   }
 }
+#else
+__device__ __forceinline__ void trace_mark(const StepArgs&, int) {}
+#endif
 
 // ---------------------------------------------------------------------------
 // Block map and state initialisation (one workgroup of 1024 threads).
@@ -320,10 +336,14 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(StepArgs a) {
     *wsp<int64_t>(a, a.L.nblk) = nblk;
     sync[SYNC_SOLVED] = 0;
     sync[SYNC_ABORT] = 0;
+    sync[SYNC_EXITED] = 0;
     act_phase[0] = n_active;
   }
   for (int p = tid + 1; p < MAXP + 2; p += SETUP_THREADS) act_phase[p] = 0;
-  for (int i = tid; i < a.n_inst; i += SETUP_THREADS) inst_cnt[i] = 0;
+  for (int i = tid; i < a.n_inst; i += SETUP_THREADS) {
+    inst_cnt[i] = 0;
+    wsp<uint32_t>(a, a.L.inv)[i] = 0;
+  }
   __syncthreads();
   // batch b belongs to the instance i with fb[i] <= b < fb[i+1] (binary search)
   const int32_t* fbp = in_lds ? fb : first_blk;
@@ -412,9 +432,10 @@ __device__ void eval_jets_batch(const StepArgs& a, char* lds, const float* par, 
     const double gv = (double)res[0 * PT + i];
     const double lap = (double)res[C::D0 * PT + i];
     const bool clamped = valid && a.clamp && a.clamp[p];
-    const double r0 = clamped ? -gv : a.dt * a.coef[inst] * lap;
+    // heat: rho_0 = dt nu Lap g, formed directly; given targets: f - g
+    const double r0 = clamped ? -gv : (a.given ? (valid ? a.given[p] : 0.0) - gv : a.dt * a.coef[inst] * lap);
     if (valid) {
-      targets[p] = clamped ? 0.0 : gv + r0;
+      targets[p] = clamped ? 0.0 : (a.given ? a.given[p] : gv + r0);
       rho0[p] = r0;  // read back by this same workgroup in later phases
     }
     rho[i * TV] = valid ? r0 : 0.0;
@@ -574,6 +595,9 @@ __global__ __launch_bounds__(64) void elastic_targets_kernel(StepArgs a) {
     for (int r = 0; r < R; ++r)
       qdot[r] = a.q_prev ? (a.q_n[(int64_t)inst * R + r] - a.q_prev[(int64_t)inst * R + r]) / a.dt : 0.0;
     const bool clamped = a.clamp && a.clamp[p];
+    // an inverted free sample has no neo-Hookean stress: INVERTED (its NaN
+    // targets also make the solve report NONFINITE)
+    if (det <= 0.0 && !clamped) st_c(wsp<uint32_t>(a, a.L.inv) + inst, 1u);
     double* rho0 = wsp<double>(a, a.L.rho0) + p * 3;
     double* tg = wsp<double>(a, a.L.targets) + p * 3;
     for (int ii = 0; ii < 3; ++ii) {
@@ -704,7 +728,7 @@ __device__ void polar_rotation(const double F[3][3], double R[3][3]) {
 //   P = 2 mu (F - R) + lam (tr(R^T F) - 3) R,  H = -(|det D_m| / 6) P D_m^-T;
 // the force on corner c < 3 is column c of H, on corner 3 minus their sum.
 __device__ void tet_force(const double X[4][3], const double u[4][3], int corner, double lam, double mu,
-                          double f[3], double* vol) {
+                          double f[3], double* vol, bool* inverted) {
   double Dm[3][3], Du[3][3], cm[3][3];
   for (int i = 0; i < 3; ++i)
     for (int a = 0; a < 3; ++a) {
@@ -719,6 +743,8 @@ __device__ void tet_force(const double X[4][3], const double u[4][3], int corner
       for (int a = 0; a < 3; ++a) s += Du[i][a] * cm[j][a];
       F[i][j] = (i == j ? 1.0 : 0.0) + s / det;
     }
+  double cF[3][3];
+  *inverted = cofactors3(F, cF) <= 0.0;
   double R[3][3];
   polar_rotation(F, R);
   double tr = -3.0;
@@ -776,6 +802,7 @@ __global__ __launch_bounds__(FE_WAVES * 64) void fe_targets_kernel(StepArgs a) {
       const int64_t elo = a.fe.inc_offsets[p], ehi = a.fe.inc_offsets[p + 1];
       bool ok = ring_ok && elo >= 0 && ehi > elo && ehi <= a.fe.n_inc;
       double fs[3] = {0.0, 0.0, 0.0}, vs = 0.0;
+      int inv = 0;
       if (ok) {
         for (int64_t e = elo + lane; e < ehi; e += 64) {
           const int corner = a.fe.inc_corner[e];
@@ -792,7 +819,9 @@ __global__ __launch_bounds__(FE_WAVES * 64) void fe_targets_kernel(StepArgs a) {
             }
           }
           double f[3], vol;
-          tet_force(X, u, good ? corner : 0, lam, mu, f, &vol);
+          bool tinv;
+          tet_force(X, u, good ? corner : 0, lam, mu, f, &vol, &tinv);
+          inv |= (good && tinv) ? 1 : 0;
           for (int j = 0; j < 3; ++j) fs[j] += good ? f[j] : qnan;
           vs += vol;
         }
@@ -800,11 +829,13 @@ __global__ __launch_bounds__(FE_WAVES * 64) void fe_targets_kernel(StepArgs a) {
       for (int off = 32; off > 0; off >>= 1) {
         for (int j = 0; j < 3; ++j) fs[j] += __shfl_xor(fs[j], off);
         vs += __shfl_xor(vs, off);
+        inv |= __shfl_xor(inv, off);
       }
       if (lane == 0) {
         const float* row = wsp<float>(a, a.L.jets) + p * a.L.nj;
         const double mass = ok ? rho * vs / 4.0 : qnan;
         const bool clamped = a.clamp && a.clamp[p];
+        if (inv && !clamped) st_c(wsp<uint32_t>(a, a.L.inv) + inst, 1u);
         double* rho0 = wsp<double>(a, a.L.rho0) + p * 3;
         double* tg = wsp<double>(a, a.L.targets) + p * 3;
         for (int k = 0; k < 3; ++k) {
@@ -1190,6 +1221,9 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
     if (ph == PH_INIT) {
       obj_first = obj_last = phi = phit[0];
       newdir = true;
+      // elastic kinds: det F <= 0 met at a free sample by the target kernel
+      // (written before this launch)
+      if (a.L.nj && ld_c(wsp<uint32_t>(a, a.L.inv) + inst) != 0) flags |= CROM_FLAG_INVERTED;
     } else if (ph == PH_GUESS) {
       // The round evaluated the guess (trial 0, with J there).  A strictly
       // smaller objective makes it the start: the direction is formed from
@@ -1503,7 +1537,18 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
     aborted = s_abort != 0;
     trace_mark(a, 4 * p + 2);
   }
-  if (aborted && blockIdx.x == 0) {
+  // The last workgroup to leave marks the instances an abort left
+  // unfinished.  Every other workgroup has left its loop by then, so no
+  // solve runs after this: a solve that completed after the abort word was
+  // set either finished its instance (a complete result) or moved it to a
+  // phase nobody evaluates, which is marked here.
+  wait_mem();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    s_last = atomicAdd(reinterpret_cast<unsigned long long*>(sync + SYNC_EXITED), 1ull) + 1 ==
+             (unsigned long long)gridDim.x;
+  __syncthreads();
+  if (s_last && ld_c(sync + SYNC_ABORT) != 0) {
     for (int i = threadIdx.x; i < a.n_inst; i += blockDim.x) {
       if (ld_c(&state[i].phase) != PH_DONE)
         st_c(&a.info[i].flags, ld_c(&a.info[i].flags) | CROM_FLAG_ABORTED);
@@ -1616,11 +1661,13 @@ static crom_status launch_lls(StepArgs a, hipStream_t st) {
   int64_t g = a.L.nblk_max;
   if (g > 4096) g = 4096;  // each workgroup loads the parameters once for its batches
   if (g < 1) g = 1;
+  // the benchmark timer brackets the evaluation kernel alone (the step's
+  // dominant kernel; the solve kernel is a few microseconds)
   timer_mark(st);
   hipLaunchKernelGGL(k, dim3((unsigned)g), dim3(NW * 64), lds_bytes, st, a);
   if ((s = hip_check(hipGetLastError(), "lls launch")) != CROM_OK) return s;
-  hipLaunchKernelGGL(lls_solve_kernel<S::R>, dim3((unsigned)a.n_inst), dim3(LLS_SOLVE_THREADS), 0, st, a);
   timer_mark(st);
+  hipLaunchKernelGGL(lls_solve_kernel<S::R>, dim3((unsigned)a.n_inst), dim3(LLS_SOLVE_THREADS), 0, st, a);
   return hip_check(hipGetLastError(), "lls solve launch");
 }
 
@@ -1896,14 +1943,13 @@ static crom_status step_prec_elastic(int prec, const StepArgs& a, int rounds, hi
 
 using namespace crom;
 
+#ifdef CROM_STEP_TRACE
+// Probe builds only: phase timestamps of the persistent step kernel.
 static uint64_t* g_step_trace = nullptr;
+extern "C" void crom_debug_step_trace(uint64_t* buf) { g_step_trace = buf; }
+#endif
 
 extern "C" {
-
-/* Debugging aid: when `buf` (device, 128 uint64) is not NULL, every later
- * crom_step call writes the wall-clock tick at each phase boundary of its
- * first and last workgroup into it (slots 0..63 and 64..127). */
-void crom_debug_step_trace(uint64_t* buf) { g_step_trace = buf; }
 
 crom_status crom_step_workspace(const crom_net* net, int32_t n_inst, int64_t total_samples,
                                 size_t* bytes) {
@@ -1937,9 +1983,13 @@ crom_status crom_step_guess(const crom_net* net, const crom_pde* pde, int32_t n_
   crom_status s = check_net(net, true);
   if (s != CROM_OK) return s;
   if (!pde || !opts) return fail(CROM_ERR_INVALID_ARG, "pde and opts are required");
-  if (pde->kind != CROM_PDE_HEAT && pde->kind != CROM_PDE_NEOHOOKEAN && pde->kind != CROM_PDE_COROTATED_FE)
+  if (pde->kind != CROM_PDE_HEAT && pde->kind != CROM_PDE_NEOHOOKEAN && pde->kind != CROM_PDE_COROTATED_FE &&
+      pde->kind != CROM_PDE_PROJECT)
     return fail(CROM_ERR_UNSUPPORTED, "pde kind");
   if (pde->kind == CROM_PDE_HEAT && net->d != 1) return fail(CROM_ERR_UNSUPPORTED, "the heat step needs d == 1");
+  if (pde->kind == CROM_PDE_PROJECT && (net->d != 1 || net->m > 2))
+    return fail(CROM_ERR_UNSUPPORTED, "the projection needs d == 1 and m <= 2");
+  const bool project = pde->kind == CROM_PDE_PROJECT;
   const bool elastic = pde->kind == CROM_PDE_NEOHOOKEAN || pde->kind == CROM_PDE_COROTATED_FE;
   if (elastic && (net->d != 3 || net->m != 3))
     return fail(CROM_ERR_UNSUPPORTED, "the elastic steps need m == 3 and d == 3");
@@ -1964,7 +2014,7 @@ crom_status crom_step_guess(const crom_net* net, const crom_pde* pde, int32_t n_
   if (opts->max_iter < 1 || opts->ls_max < 0 || opts->max_rounds < 0 || !(opts->tol_step >= 0.0) ||
       !(opts->ls_shrink > 0.0 && opts->ls_shrink < 1.0) || !(opts->armijo_c >= 0.0))
     return fail(CROM_ERR_INVALID_ARG, "gn opts out of range");
-  if (!(pde->dt > 0.0)) return fail(CROM_ERR_INVALID_ARG, "dt must be positive");
+  if (!project && !(pde->dt > 0.0)) return fail(CROM_ERR_INVALID_ARG, "dt must be positive");
   WsLayout L = ws_layout(net->r, net->d, net->m, n_inst, total_samples);
   if (!ws || ws_bytes < L.total) return fail(CROM_ERR_WORKSPACE, "workspace too small");
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(CROM_ERR_WORKSPACE, "workspace not 256-byte aligned");
@@ -1981,6 +2031,7 @@ crom_status crom_step_guess(const crom_net* net, const crom_pde* pde, int32_t n_
   a.y = y;
   a.clamp = clamp;
   a.coef = pde->coef;
+  a.given = project ? pde->coef : nullptr;
   a.dt = pde->dt;
   a.q_prev = elastic ? q_prev : nullptr;
   if (mesh) {
@@ -2007,7 +2058,9 @@ crom_status crom_step_guess(const crom_net* net, const crom_pde* pde, int32_t n_
   a.tol = opts->tol_step;
   a.armijo_c = opts->armijo_c;
   a.shrink = opts->ls_shrink;
+#ifdef CROM_STEP_TRACE
   a.trace = g_step_trace;
+#endif
   // Enough rounds for max_iter accepted steps, each after the longest line
   // search (ceil((ls_max + 1) / TV) rounds) and one re-linearisation.
   const int64_t worst = (int64_t)opts->max_iter * (1 + (opts->ls_max + TV) / TV) + 1 + (q_init ? 1 : 0);

@@ -108,15 +108,21 @@ def train(trainer: crom.Trainer, snaps: torch.Tensor, steps: int, base_lr: float
 class Rollout:
     steps: List[int]
     q: List[np.ndarray]        # [n_inst, r] at each recorded step
-    flags: List[np.ndarray]    # OR of the step flags up to each recorded step
-    iters: float               # mean Gauss-Newton iterations per step
+    flags: List[np.ndarray]    # OR of the flags of every step up to each recorded step
+    iters: float               # mean Gauss-Newton iterations per instance-step
+    fallbacks: np.ndarray = None  # steps per instance taken by the full-order fallback
 
 
 def rollout(dec: crom.Decoder, q0: np.ndarray, y: np.ndarray, mus: Sequence[float], dt: float, n_steps: int,
-            opts: crom.GNOptions, record: Sequence[int], offsets: Optional[np.ndarray] = None) -> Rollout:
+            opts: crom.GNOptions, record: Sequence[int], offsets: Optional[np.ndarray] = None,
+            fallback: Optional[crom.HeatFallback] = None) -> Rollout:
     """Latent steps for len(mus) instances from q0 [n_inst, r]; records q
     after the steps listed in `record`.  Samples: y [S, m] shared by every
-    instance, or with `offsets` [n_inst + 1] the CSR rows of y per instance."""
+    instance, or with `offsets` [n_inst + 1] the CSR rows of y per instance.
+    With `fallback`, an instance whose step failed (SINGULAR, NONFINITE,
+    LS_FAIL) takes the full-order fallback's latent for that step instead
+    (decode at every node, finite-difference update over dt, projection
+    back onto the decoder); Rollout.fallbacks counts them per instance."""
     n = len(mus)
     if offsets is None:
         S = y.shape[0]
@@ -127,7 +133,8 @@ def rollout(dec: crom.Decoder, q0: np.ndarray, y: np.ndarray, mus: Sequence[floa
     q = torch.from_numpy(np.asarray(q0, np.float64).reshape(n, dec.r)).to(dec.params.device)
     q_next = torch.empty_like(q)
     flags = np.zeros(n, dtype=np.int32)
-    out = Rollout([], [], [], 0.0)
+    out = Rollout([], [], [], 0.0, np.zeros(n, dtype=np.int64))
+    nu_dev = torch.as_tensor(np.asarray(mus, np.float64), device=dec.params.device)
     rec = set(record)
     iters = 0
     if 0 in rec:
@@ -137,14 +144,19 @@ def rollout(dec: crom.Decoder, q0: np.ndarray, y: np.ndarray, mus: Sequence[floa
     for k in range(1, n_steps + 1):
         st.step(q, mus, dt, opts, q_next)
         q, q_next = q_next, q
+        inf = st.info()  # every step's outcome (one synchronisation per step)
+        flags |= inf["flags"]
+        iters += int(inf["iters"].sum())
+        if fallback is not None:
+            failed = np.flatnonzero(inf["flags"] & crom.FLAGS_FAILED)
+            if failed.size:
+                fallback(failed, q_next, nu_dev, dt, q)  # q_next holds this step's q_n after the swap
+                out.fallbacks[failed] += 1
         if k in rec:
-            inf = st.info()
-            flags |= inf["flags"]
-            iters += int(inf["iters"].sum())
             out.steps.append(k)
             out.q.append(q.cpu().numpy())
             out.flags.append(flags.copy())
-    out.iters = iters / max(1, len([k for k in out.steps if k > 0])) / n
+    out.iters = iters / max(1, n_steps) / n
     return out
 
 

@@ -198,3 +198,31 @@ def test_three_step_rollout_fp32(cuda):
         err = normwise_rel(q[0].cpu().numpy() - w.q0, oq - w.q0)
         print(f"step {k + 1}: |q - q0| {np.abs(oq - w.q0).max():.3e} error {err:.2e}")
         assert err <= 3 * _q_bound(layers, X, w.q0, 1e-6)
+
+
+@pytest.mark.parametrize("scale", [1.0, 1500.0])
+def test_inverted_flag(cuda, scale):
+    """The neo-Hookean bar's decoder with its output layer scaled by `scale`:
+    det(I + du/dX) <= 0 at a free sample (the oracle's rule, FP64) makes the
+    GPU step report INVERTED with NONFINITE and keep q_n; otherwise no
+    INVERTED."""
+    from paper_2206_02607_amd import crom
+    from oracle import elastic
+    w = Elastic3D()
+    layers = [(np.asarray(W, np.float64), np.asarray(b, np.float64)) for W, b in w.layers]
+    layers[-1] = (layers[-1][0] * scale, layers[-1][1] * scale)
+    X = w.nodes[w.sample_idx].astype(np.float32)
+    clamp = (X[:, 0] == 0.0).astype(np.uint8)
+    odec = mlp.MLPDecoder(layers, 3)
+    G = odec.jets(X.astype(np.float64), w.q0)[1]
+    det = np.linalg.det(np.eye(3)[None] + G)[clamp == 0]
+    expect = elastic.inverted(odec, X.astype(np.float64), w.q0, clamp)
+    assert (det.min() < -0.05) if expect else (det.min() > 0.05)
+    dec = crom.Decoder.from_layers(layers, 3, precision="fp32", device=cuda)
+    q1, _, info, _ = _run(dec, X, clamp, _coef(w, w.gravity), w.q0, None, w.dt,
+                          crom.GNOptions(max_iter=3, tol_step=1e-6), cuda)
+    print(f"scale {scale}: min det F {det.min():.3f}, flags {info['flags'][0]}, oracle inverted {expect}")
+    assert bool(info["flags"][0] & crom.FLAG_INVERTED) == expect
+    if expect:
+        assert info["flags"][0] & crom.FLAG_NONFINITE
+        assert np.array_equal(q1[0], w.q0)

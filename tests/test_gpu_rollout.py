@@ -41,6 +41,8 @@ def trained(cuda):
         sd.fold(dec, T.enc_params, T.n_in, T.hidden)
         q0 = T.encode(torch.from_numpy(u0.astype(np.float32)).to(cuda).reshape(1, -1))
         nets[name] = (dec, q0.cpu().numpy().astype(np.float64), losses)
+        if name == "trained":
+            nets["enc"] = (T.enc_params.detach().clone(), T.hidden)
     mus = np.concatenate([w.mu_test, w.mu[:2]])
     record = [0, 125, 250, 375, 500]
     ref = heat2d.fd_snapshots(u0, mus, [k * w.dt for k in record], w.dx, w.dt_fd, cuda)
@@ -48,7 +50,29 @@ def trained(cuda):
     return w, nodes, nets, mus, record, refs, rows
 
 
+BROKEN = 2 | 4 | 16  # SINGULAR, NONFINITE, ABORTED
+
+
 def _rollout_error(w, nodes, dec, q0, mus, record, refs, linearized):
+    """Space-time rollout error per instance.  The flags of every step are
+    collected: no step may end SINGULAR, NONFINITE or ABORTED; a
+    Gauss-Newton step that ends LS_FAIL (no further decrease resolvable at
+    the step tolerance) keeps its last accepted iterate and is reported."""
+    from paper_2206_02607_amd import crom, heat2d
+    opts = crom.GNOptions(max_iter=5, linearized=linearized, tol_step=1e-6)
+    ro = heat2d.rollout(dec, np.tile(q0, (len(mus), 1)), w.nodes[w.sample_idx], mus, w.dt, record[-1], opts,
+                        record)
+    assert np.all(ro.flags[-1] & BROKEN == 0), ro.flags[-1]
+    if linearized:
+        assert np.all(ro.flags[-1] & crom.FLAG_LS_FAIL == 0)
+    print("flags over the rollout (OR per instance)", ro.flags[-1].tolist())
+    fields = [heat2d.decode_fields(dec, nodes, q) for q in ro.q]
+    return heat2d.spacetime_error(fields, refs), ro
+
+
+def _untrained_error(w, nodes, dec, q0, mus, record, refs, linearized):
+    """The untrained network's rollout (its steps may fail: it is not a
+    model of the field)."""
     from paper_2206_02607_amd import crom, heat2d
     opts = crom.GNOptions(max_iter=5, linearized=linearized, tol_step=1e-6)
     ro = heat2d.rollout(dec, np.tile(q0, (len(mus), 1)), w.nodes[w.sample_idx], mus, w.dt, record[-1], opts,
@@ -80,7 +104,7 @@ def test_initial_field_reconstruction(trained):
 def test_trained_vs_untrained_rollout(trained, linearized):
     w, nodes, nets, mus, record, refs, _ = trained
     e_t, ro_t = _rollout_error(w, nodes, nets["trained"][0], nets["trained"][1], mus, record, refs, linearized)
-    e_u, _ = _rollout_error(w, nodes, nets["untrained"][0], nets["untrained"][1], mus, record, refs, linearized)
+    e_u, _ = _untrained_error(w, nodes, nets["untrained"][0], nets["untrained"][1], mus, record, refs, linearized)
     print("space-time rollout error: trained", e_t.round(4), "untrained", e_u.round(3), "GN iters", ro_t.iters)
     assert np.all(np.isfinite(e_t))
     assert e_t.max() < 0.08
@@ -130,3 +154,87 @@ def test_robust_sampling_beats_random_sets(trained):
     print("greedy metric", greedy.metric, "samples", greedy.samples.tolist(), "random sets", np.round(rand, 4))
     assert greedy.rounds == 12
     assert greedy.metric < min(rand)
+
+
+def test_trained_crom_vs_pod(trained):
+    """The learned decoder against the linear baseline the paper compares
+    with (Sec. "Comparison with Prior Approaches"): POD with the same latent
+    dimension r = 8, its basis the leading singular vectors of the same 200
+    FP64 training snapshots (the finite-difference solver's, bit-exact with
+    the oracle's solver), stepped by the method's own heat update (its
+    Laplacian the full-order stencil applied to the basis) and linearised
+    inversion at the same 500 sample nodes, from the projection of the
+    initial field.  Both rollouts are judged by the FP64 finite-difference
+    solution over 500 steps for the held-out and two training diffusivities;
+    both errors are printed, with the memory each needs for its manifold."""
+    from oracle import pod, step as ostep
+    from oracle.inversion import GNOptions
+    w, nodes, nets, mus, record, refs, rows = trained
+    dec, q0, _ = nets["trained"]
+    e_crom, _ = _rollout_error(w, nodes, dec, q0, mus, record, refs, 1)
+    U = pod.pod_basis(rows.cpu().numpy(), w.r)
+    P = pod.PODDecoder(U, w.grid, w.grid, w.dx)
+    u0 = w.initial_field().ravel()
+    opts = GNOptions(max_iter=1, linearized=True)
+    e_pod = []
+    for k, mu in enumerate(mus):
+        q = P.encode(u0)
+        num = den = 0.0
+        for n in range(record[-1] + 1):
+            if n in record:
+                ref = refs[record.index(n)][k].cpu().numpy()
+                num += float(((P.decode(q) - ref) ** 2).sum())
+                den += float((ref ** 2).sum())
+            if n < record[-1]:
+                q, info, _ = ostep.heat_step(P, w.sample_idx, q, float(mu), w.dt, opts)
+                assert info.flags == 0
+        e_pod.append(np.sqrt(num / den))
+    e_pod = np.array(e_pod)
+    mem_crom, mem_pod = dec.params.numel(), U.size
+    print("space-time rollout error, r = 8: CROM", e_crom.round(4), "POD", e_pod.round(4),
+          f"| manifold parameters: CROM {mem_crom}, POD {mem_pod} ({mem_pod / mem_crom:.2f}x)")
+    assert np.all(np.isfinite(e_pod)) and np.all(e_pod < 1.0)
+    # the network's size does not grow with the discretisation: at this grid
+    # it already needs about half the values of the r = 8 basis
+    assert mem_crom < 0.6 * mem_pod
+
+
+def test_fd_fallback_carries_a_failed_instance(trained):
+    """An instance whose samples all sit on one node has a rank-one J^T J:
+    every step ends SINGULAR and keeps q_n, so alone its field never
+    changes.  With the full-order fallback (crom_heat_fallback: decode at
+    every node, FP64 finite-difference update over the step, projection back
+    onto the decoder at every node) the rollout continues from the
+    full-order update; the judged error is then close to the healthy
+    instances', while without the fallback it is that of a frozen field.  The healthy instances of the batch are bit-identical
+    with and without the fallback."""
+    import torch
+    from paper_2206_02607_amd import crom, heat2d
+    w, nodes, nets, mus, record, refs, _ = trained
+    dec, q0, _ = nets["trained"]
+    S = len(w.sample_idx)
+    y = np.tile(w.nodes[w.sample_idx], (len(mus), 1)).astype(np.float32)
+    bad = 1
+    y[bad * S:(bad + 1) * S] = w.nodes[w.sample_idx[S // 2]]
+    offsets = np.arange(len(mus) + 1, dtype=np.int64) * S
+    opts = crom.GNOptions(max_iter=1, linearized=True)
+    fb = crom.HeatFallback(dec, nodes, w.grid, w.grid, w.dx, w.dt_fd)
+    runs = {}
+    for name, f in (("plain", None), ("fallback", fb)):
+        ro = heat2d.rollout(dec, np.tile(q0, (len(mus), 1)), y, mus, w.dt, record[-1], opts, record,
+                            offsets=offsets, fallback=f)
+        fields = [heat2d.decode_fields(dec, nodes, q) for q in ro.q]
+        runs[name] = (heat2d.spacetime_error(fields, refs), ro)
+    e_plain, ro_plain = runs["plain"]
+    e_fb, ro_fb = runs["fallback"]
+    print("rollout error without fallback", e_plain.round(4), "with", e_fb.round(4),
+          "fallback steps", ro_fb.fallbacks.tolist())
+    assert ro_plain.flags[-1][bad] & crom.FLAG_SINGULAR
+    assert ro_fb.fallbacks[bad] == record[-1]
+    good = [k for k in range(len(mus)) if k != bad]
+    assert np.all(ro_fb.fallbacks[good] == 0)
+    for qa, qb in zip(ro_plain.q, ro_fb.q):
+        assert np.array_equal(qa[good], qb[good])
+    # frozen without the fallback; tracked with it
+    assert np.array_equal(ro_plain.q[-1][bad], q0[0])
+    assert e_fb[bad] < 0.1 and e_fb[bad] < 0.25 * e_plain[bad]

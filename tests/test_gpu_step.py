@@ -80,27 +80,41 @@ def test_heat2d_step_2000_samples(cuda, seed):
         e_q = normwise_rel(q1[0] - wl.q0, qr - wl.q0)
         print(f"heat2d seed {seed} lin={lin}: dg err {e_dg:.2e} dq err {e_q:.2e} iters "
               f"{info['iters'][0]}/{oinfo.iters} obj {info['obj_last'][0]:.4e}/{oinfo.obj_last:.4e}")
-        assert e_dg <= 1e-2
+        # measured at most 4e-4 (seed 1, Gauss-Newton); the bar leaves 2.5x
+        assert e_dg <= 1e-3
         if lin:
             assert e_q <= _lls_bound(wl.layers, 2, wl.samples, wl.q0)
         else:
             assert info["obj_last"][0] <= oinfo.obj_last * 1.01 + 1e-3 * oinfo.obj_first
 
 
-@pytest.mark.parametrize("prec,tol", [("bf16", 1e-1), ("bf16x3", 1e-2), ("bf16pure", 2e-1)])
-def test_heat2d_step_lowp(cuda, prec, tol):
-    """BF16 modes.  With a bfloat16 latent Jacobian (entries to ~1e-2, see
-    the decode parity) the projection onto its badly conditioned span moves
-    by several percent; with split operands on every column (BF16X3) the
-    step follows the oracle to ~1e-4."""
+# bars from the measured errors (seed 2) with about 1.5-3x of margin:
+# BF16 4.2e-2, BF16X3 6.8e-5, BF16_PURE 5.0e-2
+@pytest.mark.parametrize("prec,tol,tol_j", [("bf16", 6e-2, 2e-2), ("bf16x3", 2e-4, 1e-4), ("bf16pure", 1e-1, 3e-2)])
+def test_heat2d_step_lowp(cuda, prec, tol, tol_j):
+    """BF16 modes.  The decoded change over one step is small (|dt nu Lap g|
+    ~ 1e-5 of |g|) and the latent Jacobian is badly conditioned (cond(J^T J)
+    printed), so the plain-bfloat16 latent Jacobian (entries to ~1e-2, see
+    the decode parity) moves the projection by a few percent of the change:
+    the BF16 step misses the 2e-2 bar on the decoded change at this
+    conditioning, and with split operands on every column (BF16X3) it follows
+    the oracle to ~1e-4.  The latent update itself is held to the
+    least-squares bound: the Jacobian's normwise error (2e-2 BF16, 1e-4
+    BF16X3) times cond(J^T J)^(1/2)."""
+    from oracle import mlp as omlp
     wl = Heat2D(seed=2, bias_scale=0.1)
+    J = omlp.MLPDecoder(wl.layers, 2).value_jac_q(wl.samples, wl.q0)[1].reshape(-1, len(wl.q0))
+    cond = np.linalg.cond(J.T @ J)
     for lin in (True, False):
         q1, info, f, _ = _run(cuda, wl.layers, 2, [0, wl.n_samples], wl.samples, wl.q0, [wl.mu], wl.dt,
                               prec=prec, linearized=lin)
         qr, oinfo, fr = _oracle_step(wl.layers, 2, wl.samples, wl.q0, wl.mu, wl.dt, linearized=lin)
         e_dg = _dg_err(wl.layers, 2, wl.samples, wl.q0, q1[0], qr)
-        print(f"heat2d {prec} lin={lin}: dg err {e_dg:.2e} flags {info['flags'][0]} iters {info['iters'][0]}")
+        e_q = normwise_rel(q1[0], qr)
+        print(f"heat2d {prec} lin={lin}: dg err {e_dg:.2e} q err {e_q:.2e} cond(J^T J) {cond:.3e} "
+              f"bound {tol_j * np.sqrt(cond):.2e} flags {info['flags'][0]} iters {info['iters'][0]}")
         assert e_dg <= tol
+        assert e_q <= tol_j * np.sqrt(cond)
 
 
 def test_batched_ragged_instances(cuda):
@@ -119,7 +133,8 @@ def test_batched_ragged_instances(cuda):
         assert normwise_rel(f[a:b], fr) <= 1e-5
         e_dg = _dg_err(wl.layers, 2, wl.samples[a:b], wl.q0[i], q1[i], qr)
         print(f"inst {i} S={b - a}: dg err {e_dg:.2e}")
-        assert e_dg <= 1e-2
+        # 18 to 70 samples: worse conditioned than 2,000; measured at most 2.2e-3
+        assert e_dg <= 5e-3
 
 
 def test_clamped_samples_target_zero(cuda):
@@ -247,4 +262,38 @@ def test_full_batch_512_sampled(cuda):
         qr, oinfo, _ = _oracle_step(wb.layers, wb.m, y.astype(np.float64), wb.q0[i], wb.mu[i], wb.dt)
         e_dg = _dg_err(wb.layers, wb.m, y.astype(np.float64), wb.q0[i], qb[i], qr)
         print(f"instance {i} S={hi - lo}: dg err {e_dg:.2e}, iters {ib[i]['iters']}/{oinfo.iters}")
-        assert e_dg <= 1e-2
+        assert e_dg <= 1e-3  # measured at most 4.2e-4
+
+
+@pytest.mark.parametrize("linearized", [True, False])
+def test_projection_with_given_targets(cuda, linearized):
+    """CROM_PDE_PROJECT: the inversion alone (eq. "invert") with the targets
+    given at the samples, as the full-order fallback uses it.  Targets: the
+    oracle decoder's values at a nearby latent plus a smooth perturbation
+    outside the manifold.  FP32, against the oracle's inversion from the same
+    start: the decoded change at the samples within the step bars, the
+    objective at the end within 1 %."""
+    import torch
+    from paper_2206_02607_amd import crom
+    wl = Heat2D(seed=4, bias_scale=0.1)
+    odec = mlp.MLPDecoder(wl.layers, 2)
+    y = wl.samples.astype(np.float64)
+    q_t = wl.q0 + 0.01 * np.sin(np.arange(wl.r) + 1.0)
+    target = odec.value(y, q_t)[:, 0] + 1e-4 * np.sin(3 * y[:, 0]) * np.cos(2 * y[:, 1])
+    dec = crom.Decoder.from_layers(wl.layers, 2, precision="fp32", device=cuda)
+    st = crom.Stepper(dec, [0, wl.n_samples], torch.from_numpy(wl.samples).to(cuda), pde="project")
+    opts = crom.GNOptions(max_iter=5, linearized=linearized, tol_step=1e-10)
+    q1 = st.step(torch.from_numpy(wl.q0[None]).to(cuda), torch.from_numpy(target).to(cuda), 0.0, opts)
+    q1 = q1.cpu().numpy()[0]
+    info = st.info()[0]
+    qr, oinfo = ostep.invert(odec, y, target[:, None], wl.q0, OOpts(max_iter=5, linearized=linearized,
+                                                                   tol_step=1e-12))
+    np.testing.assert_array_equal(st.targets().cpu().numpy()[:, 0], target)
+    e_dg = _dg_err(wl.layers, 2, wl.samples, wl.q0, q1, qr)
+    print(f"projection lin={linearized}: dg err {e_dg:.2e} obj {info['obj_last']:.4e}/{oinfo.obj_last:.4e} "
+          f"iters {info['iters']}/{oinfo.iters} flags {info['flags']}")
+    assert info["flags"] & (crom.FLAG_SINGULAR | crom.FLAG_NONFINITE) == 0
+    assert e_dg <= 1e-3
+    assert abs(info["obj_first"] - oinfo.obj_first) <= 1e-4 * oinfo.obj_first
+    if not linearized:
+        assert info["obj_last"] <= oinfo.obj_last * 1.01 + 1e-6 * oinfo.obj_first

@@ -190,3 +190,49 @@ def test_step_is_least_squares_projection(linearized):
     Jq = dec.jets(X, q_n)[3].reshape(-1, dec.r)
     ls = np.linalg.lstsq(Jq, tgt.ravel(), rcond=None)[0]
     np.testing.assert_allclose(q1, ls, rtol=1e-9, atol=1e-12)
+
+
+class _StretchDecoder:
+    """u(X, q) = (c + q_0) X_1 e_1: F = diag(1 + c + q_0, 1, 1) everywhere,
+    det F = 1 + c + q_0 in closed form; zero Hessian."""
+
+    def __init__(self, c, r=2):
+        self.c, self.r = c, r
+
+    def jets(self, X, q):
+        X = np.asarray(X, dtype=np.float64)
+        S = len(X)
+        s = self.c + q[0]
+        u = np.zeros((S, 3))
+        u[:, 0] = s * X[:, 0]
+        G = np.zeros((S, 3, 3))
+        G[:, 0, 0] = s
+        Jq = np.zeros((S, 3, self.r))
+        Jq[:, 0, 0] = X[:, 0]
+        return u, G, np.zeros((S, 3, 3, 3)), Jq
+
+    def value(self, X, q):
+        return self.jets(X, q)[0]
+
+    def value_jac_q(self, X, q):
+        u, _, _, J = self.jets(X, q)
+        return u, J
+
+
+@pytest.mark.parametrize("c,flag", [(-2.0, True), (-1.0, True), (-0.5, False), (0.3, False)])
+def test_inverted_flag_follows_det_F(c, flag):
+    """det F = 1 + c: at or below zero the step reports INVERTED (with
+    NONFINITE from ln J, q stays at q_n); above zero it does not."""
+    from oracle.inversion import INVERTED, NONFINITE
+    g = rng(8)
+    dec = _StretchDecoder(c)
+    X = g.uniform(0.1, 1, size=(5, 3))
+    q_n = np.zeros(dec.r)
+    q1, info, _ = elastic.elastic_step(dec, X, q_n, None, LAM, MU, RHO0, B, 1e-3, GNOptions(max_iter=3))
+    assert bool(info.flags & INVERTED) == flag
+    if flag:
+        assert info.flags & NONFINITE and np.array_equal(q1, q_n)
+    # clamped samples do not use the stress: inverting only there is no flag
+    clamp = np.ones(5, np.uint8)
+    _, info, _ = elastic.elastic_step(dec, X, q_n, None, LAM, MU, RHO0, B, 1e-3, GNOptions(max_iter=3), clamp)
+    assert not info.flags & INVERTED

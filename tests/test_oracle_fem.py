@@ -257,3 +257,25 @@ def test_step_projection_of_affine_latent_decoder():
     _, J = dec.value_jac_q(X[samples], q_n)
     want = np.linalg.lstsq(J.reshape(-1, r), target.ravel(), rcond=None)[0]
     np.testing.assert_allclose(q1, want, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("scale,flag", [(-1.5, True), (-1.0, True), (-0.4, False)])
+def test_inverted_flag_follows_det_F(scale, flag):
+    """The affine decoder u = q_0 E X with E = e_1 e_1^T gives F = diag(1 +
+    q_0, 1, 1) on every tetrahedron: det F = 1 + q_0 <= 0 reports INVERTED
+    (NONFINITE from the undefined rotation, q stays), above zero nothing."""
+    from oracle.inversion import INVERTED, NONFINITE
+    g = rng(13)
+    X, tets = _mesh(g)
+    E = np.zeros((1, 3, 3))
+    E[0, 0, 0] = 1.0
+    dec = _AffineLatent(E)
+    samples = np.array([9, 22, 40])
+    q_n = np.array([scale])
+    q1, info, _ = fem.fem_step(dec, X, tets, samples, q_n, None, LAM, MU, RHO0, B, 1e-3, GNOptions(max_iter=3))
+    assert bool(info.flags & INVERTED) == flag
+    if flag:
+        assert info.flags & NONFINITE and np.array_equal(q1, q_n)
+    _, info, _ = fem.fem_step(dec, X, tets, samples, q_n, None, LAM, MU, RHO0, B, 1e-3, GNOptions(max_iter=3),
+                              np.ones(3, np.uint8))
+    assert not info.flags & INVERTED
