@@ -284,6 +284,8 @@ def batched_leg(args, crom, torch, dev, trained=None):
         st = crom.Stepper(dec, wb.offsets, torch.from_numpy(wb.samples).to(dev))
         for kind, opts in (("lls", crom.GNOptions(max_iter=1, linearized=True)),
                            ("gn", crom.GNOptions(max_iter=5, tol_step=TOL_STEP[prec]))):
+            if args.modes and f"{prec}_{kind}" not in args.modes.split(","):
+                continue
             r = {"precision": prec, "inversion": "linearised" if opts.linearized else "Gauss-Newton",
                  "tol_step": None if opts.linearized else TOL_STEP[prec]}
             if nj:
@@ -349,7 +351,7 @@ def batched_leg(args, crom, torch, dev, trained=None):
     head = max(equal, key=lambda k: modes[k]["point_evals_per_s"])
     out["headline_mode"] = head
     out["headline_rule"] = rule
-    if len(precs) == 2:
+    if len(precs) == 2 and len(modes) == 4:
         a, b = precs
         out["precision_study"] = {
             kind: {"speedup_" + a + "_vs_fp32": modes[f"{b}_{kind}"]["ms_per_step"] / modes[f"{a}_{kind}"]["ms_per_step"],
@@ -798,6 +800,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="host seconds for the oracle's sample of the headline workload (0: skip)")
     ap.add_argument("--single", type=int, default=1, help="the single-instance 2D heat leg (0: skip)")
+    ap.add_argument("--modes", default="", help="comma list of batched modes to run (e.g. bf16_lls; default all four)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--train-time-steps", type=int, default=50)
     ap.add_argument("--train-steps", type=int, default=20000,
