@@ -188,7 +188,7 @@ def train_leg(args, crom, torch, dev):
         dec = crom.Decoder.from_layers(w.layers, w.m, precision=prec, device=dev)
         return dec, crom.Trainer(dec, enc0.copy(), w.enc_hidden, xs, w.batch)
 
-    for prec in ("bf16", "fp32"):
+    for prec in args.train_precs.split(","):
         dec, T = make(prec)
         for _ in range(3):
             T.step(data[:w.batch], 1e-4)
@@ -201,23 +201,24 @@ def train_leg(args, crom, torch, dev):
         t = e[0].elapsed_time(e[1]) * 1e-3 / args.train_time_steps
         out[prec] = {"ms_per_step": t * 1e3, "steps_per_s": 1.0 / t, "achieved_tflops": fl / t / 1e12,
                      "frac_of_peak": fl / t / 1e12 / PEAK[prec]}
-    # the paper's convolutional encoder (16,384 -> 4095 -> 1023 -> 255 -> 63,
-    # dense 32, r), seeded uniform parameters: the step time with it
-    from workloads import rng as _rng
-    n_conv = crom.encoder_param_count(P * w.d, 32, w.r, "conv", w.d)
-    enc_conv = _rng(args.seed + 5).uniform(-0.1, 0.1, size=n_conv).astype(np.float32)
-    decc = crom.Decoder.from_layers(w.layers, w.m, precision="bf16", device=dev)
-    Tc = crom.Trainer(decc, enc_conv, 32, xs, w.batch, enc_kind="conv")
-    for _ in range(3):
-        Tc.step(data[:w.batch], 1e-4)
-    torch.cuda.synchronize()
-    e[0].record()
-    for k in range(args.train_time_steps):
-        Tc.step(data[(k % 12) * w.batch:(k % 12 + 1) * w.batch], 1e-4)
-    e[1].record()
-    torch.cuda.synchronize()
-    out["bf16_conv_encoder"] = {"ms_per_step": e[0].elapsed_time(e[1]) / args.train_time_steps,
-                                "encoder_params": n_conv}
+    if args.train_conv:
+        # the paper's convolutional encoder (16,384 -> 4095 -> 1023 -> 255 -> 63,
+        # dense 32, r), seeded uniform parameters: the step time with it
+        from workloads import rng as _rng
+        n_conv = crom.encoder_param_count(P * w.d, 32, w.r, "conv", w.d)
+        enc_conv = _rng(args.seed + 5).uniform(-0.1, 0.1, size=n_conv).astype(np.float32)
+        decc = crom.Decoder.from_layers(w.layers, w.m, precision="bf16", device=dev)
+        Tc = crom.Trainer(decc, enc_conv, 32, xs, w.batch, enc_kind="conv")
+        for _ in range(3):
+            Tc.step(data[:w.batch], 1e-4)
+        torch.cuda.synchronize()
+        e[0].record()
+        for k in range(args.train_time_steps):
+            Tc.step(data[(k % 12) * w.batch:(k % 12 + 1) * w.batch], 1e-4)
+        e[1].record()
+        torch.cuda.synchronize()
+        out["bf16_conv_encoder"] = {"ms_per_step": e[0].elapsed_time(e[1]) / args.train_time_steps,
+                                    "encoder_params": n_conv}
     if args.train_steps <= 0:
         return out, None
     dec, T = make("bf16")
@@ -803,6 +804,8 @@ def main():
     ap.add_argument("--modes", default="", help="comma list of batched modes to run (e.g. bf16_lls; default all four)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--train-time-steps", type=int, default=50)
+    ap.add_argument("--train-precs", default="bf16,fp32", help="arithmetic of the timed training steps")
+    ap.add_argument("--train-conv", type=int, default=1, help="time the convolutional-encoder training step")
     ap.add_argument("--train-steps", type=int, default=20000,
                     help="BF16 training run whose network the batched leg rolls out (0: untrained)")
     ap.add_argument("--judge", type=int, default=8, help="instances whose rollout error the FD solver judges")

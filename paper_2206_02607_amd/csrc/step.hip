@@ -345,19 +345,18 @@ __global__ __launch_bounds__(SETUP_THREADS) void setup_kernel(StepArgs a) {
     wsp<uint32_t>(a, a.L.inv)[i] = 0;
   }
   __syncthreads();
-  // batch b belongs to the instance i with fb[i] <= b < fb[i+1] (binary search)
+  // instance i owns batches fb[i] .. fb[i+1]-1: one wave per instance at a
+  // time, its lanes over the instance's batches (stores only, no search)
   const int32_t* fbp = in_lds ? fb : first_blk;
-  for (int32_t b = tid; b < nblk; b += SETUP_THREADS) {
-    int lo = 0, hi = a.n_inst - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (fbp[mid] <= b) lo = mid;
-      else hi = mid - 1;
+  const int lane = tid & 63;
+  for (int i = tid >> 6; i < a.n_inst; i += SETUP_THREADS / 64) {
+    const int32_t f = fbp[i], nb = fbp[i + 1] - f;
+    const int64_t base = in_lds ? lo_off[i] : a.offsets[i];
+    for (int32_t k = lane; k < nb; k += 64) {
+      blk_start[f + k] = base + (int64_t)k * PT;
+      blk_inst[f + k] = i;
+      if (a.L.nj) wsp<uint32_t>(a, a.L.bcnt)[f + k] = 0;
     }
-    const int64_t base = in_lds ? lo_off[lo] : a.offsets[lo];
-    blk_start[b] = base + (int64_t)(b - fbp[lo]) * PT;
-    blk_inst[b] = lo;
-    if (a.L.nj) wsp<uint32_t>(a, a.L.bcnt)[b] = 0;
   }
   // state: the phase and flags words of every instance (the first solve
   // forms the rest)
@@ -491,14 +490,19 @@ __device__ void eval_trials_batch(const StepArgs& a, char* lds, const float* par
 // ---------------------------------------------------------------------------
 enum { PK_HEAT = 0, PK_ELASTIC = 1 };
 
-// Latent-tangent chunk of the elastic passes.  Four tangents per pass in
-// every precision: in bfloat16 eight would fit the LDS, but the step
-// kernel's trial evaluation then spills 864 bytes per lane (216 with four),
-// and the four-tangent passes measured faster (neo-Hookean bar, BF16 GN
-// step 2.29 -> 2.08 ms; FE bar 1.47 -> 1.35 ms).
+// Latent-tangent chunk of the elastic passes.  Two tangents per pass in
+// every precision: each chunk of a batch is a work item of the step kernel,
+// so the single bar's 32 batches give 256 work items, one per compute unit
+// (with four tangents, 128: BF16 Gauss-Newton step 0.97 -> 0.93 ms, same
+// bits).  In bfloat16 eight would fit the LDS, but the trial evaluation then
+// spilled 864 bytes per lane and measured slower (2.29 vs 2.08 ms, when a
+// batch was one work item).
+#ifndef CROM_ELASTIC_QC
+#define CROM_ELASTIC_QC 2
+#endif
 template <int PREC>
 struct ElasticChunks {
-  static constexpr int QC = 4;
+  static constexpr int QC = CROM_ELASTIC_QC;
   static constexpr int HC = 3;
 };
 
@@ -883,16 +887,21 @@ __device__ void eval_init_elastic(const StepArgs& a, double* jd, int64_t blk) {
 
 // Trial phases of the elastic step, one latent-tangent chunk `ch` of one
 // batch per call.  A round without the Jacobian (after a rejected trial)
-// runs on chunk 0 alone: the decoder differences at the TV trial latents
-// (one pass), zero Jacobian partials.  A round with the Jacobian at the
-// first trial gives each chunk of QC latent directions its own workgroup
-// (value, the first difference and the chunk's tangents, which the engine
-// takes at the first difference column's latent); the chunks store their
-// Jacobian columns, chunk 0 also the residuals, and the last chunk to
-// arrive stages the whole batch and forms its partials.  With one trial
-// per round the residual comes from chunk 0's difference column (the same
-// column arithmetic as the trial pass).  Returns whether this workgroup
-// formed the batch's partials.
+// evaluates on chunk 0 alone: the decoder differences at the TV trial
+// latents (one pass), zero Jacobian partials.  A round with the Jacobian at
+// the first trial gives each chunk of QC latent directions its own
+// workgroup (value, the first difference and the chunk's tangents, which
+// the engine takes at the first difference column's latent).  The chunks
+// store their Jacobian columns, chunk 0 also the residuals, and the last
+// chunk to arrive stages the whole batch and forms its partials.  Every
+// chunk arrives in every round, also where it has nothing to evaluate: a
+// chunk reads the instance's phase before its arrival, and the instance is
+// solved only after all its arrivals, so no chunk can read the state that
+// the round's own solve writes (a chunk that skipped the arrival could, and
+// would then evaluate the next round's columns early and be counted
+// twice).  With one trial per round the residual comes from chunk 0's
+// difference column (the same column arithmetic as the trial pass).
+// Returns whether this workgroup formed the batch's partials.
 template <class S, int NW, int PREC, int PF>
 __device__ bool eval_trials_elastic(const StepArgs& a, char* lds, double* jd, const float* par, double* qdl,
                                     int64_t blk, int ch, int inst, bool have_qdl, bool with_j) {
@@ -905,55 +914,51 @@ __device__ bool eval_trials_elastic(const StepArgs& a, char* lds, double* jd, co
   using EQ = Engine<S, CQ, 1, NW, PREC, PF>;
   __shared__ int s_lastc;
   double* rho = jd + ROWS * R;
-  const GNState* st = wsp<GNState>(a, a.L.state) + inst;
-  if (!have_qdl) {
-    for (int i = threadIdx.x; i < TV * R; i += blockDim.x) qdl[i] = ld_c(&st->qd[i / R][i % R]);
-    __syncthreads();
-  }
-  const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
-  const int64_t rem = a.offsets[inst + 1] - first;
-  const int n_valid = rem < PT ? (int)rem : PT;
-  const double* qn = a.q_n + (int64_t)inst * R;
-  const double* rho0 = wsp<double>(a, a.L.rho0);
-  const bool merged = with_j && TV == 1;
-  if (!merged && ch == 0) {
-    ET::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
-    __syncthreads();
-    ET::run(lds, par, a.packed, a.depth, 0);
-    const float* res = reinterpret_cast<const float*>(lds + ET::RES_OFF);
-    for (int e = threadIdx.x; e < ROWS * TV; e += blockDim.x) {
-      const int row = e / TV, t = e % TV, i = row / D, oo = row % D;
-      rho[e] = i < n_valid ? rho0[first * D + row] - (double)res[(oo * ET::NT + CT::F0 + t) * PT + i] : 0.0;
-    }
-    __syncthreads();
-  }
-  double* part = wsp<double>(a, a.L.partials) + blk * a.L.nred;
-  if (!with_j) {
-    for (int e = threadIdx.x; e < ROWS * R; e += blockDim.x) jd[e] = 0.0;
-    __syncthreads();
-    batch_partials<R, ROWS>(jd, rho, part);
-    __syncthreads();
-    return true;
-  }
-  const int qb = ch * QC;
-  EQ::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
-  __syncthreads();
-  EQ::run(lds, par, a.packed, a.depth, qb);
-  const float* res = reinterpret_cast<const float*>(lds + EQ::RES_OFF);
   double* jg = wsp<double>(a, a.L.jbuf) + blk * (int64_t)(ROWS * (R + TV));  // [ROWS][R], then [ROWS][TV]
-  for (int e = threadIdx.x; e < ROWS * QC; e += blockDim.x) {
-    const int row = e / QC, c = e % QC, i = row / D, oo = row % D;
-    st_c(jg + row * R + qb + c, i < n_valid ? (double)res[(oo * EQ::NT + CQ::Q0 + c) * PT + i] : 0.0);
-  }
-  if (ch == 0) {
-    for (int e = threadIdx.x; e < ROWS * TV; e += blockDim.x) {
-      const int row = e / TV, i = row / D, oo = row % D;
-      const double v = !merged ? rho[e]
-                     : (i < n_valid ? rho0[first * D + row] - (double)res[(oo * EQ::NT + CQ::F0) * PT + i] : 0.0);
-      st_c(jg + ROWS * R + e, v);
+  if (with_j || ch == 0) {  // uniform over the workgroup
+    const GNState* st = wsp<GNState>(a, a.L.state) + inst;
+    if (!have_qdl) {
+      for (int i = threadIdx.x; i < TV * R; i += blockDim.x) qdl[i] = ld_c(&st->qd[i / R][i % R]);
+      __syncthreads();
+    }
+    const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
+    const int64_t rem = a.offsets[inst + 1] - first;
+    const int n_valid = rem < PT ? (int)rem : PT;
+    const double* qn = a.q_n + (int64_t)inst * R;
+    const double* rho0 = wsp<double>(a, a.L.rho0);
+    const bool merged = with_j && TV == 1;
+    if (!merged && ch == 0) {
+      ET::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
+      __syncthreads();
+      ET::run(lds, par, a.packed, a.depth, 0);
+      const float* res = reinterpret_cast<const float*>(lds + ET::RES_OFF);
+      for (int e = threadIdx.x; e < ROWS * TV; e += blockDim.x) {
+        const int row = e / TV, t = e % TV, i = row / D, oo = row % D;
+        rho[e] = i < n_valid ? rho0[first * D + row] - (double)res[(oo * ET::NT + CT::F0 + t) * PT + i] : 0.0;
+      }
+      __syncthreads();
+    }
+    const float* res = reinterpret_cast<const float*>(lds + EQ::RES_OFF);
+    if (with_j) {
+      const int qb = ch * QC;
+      EQ::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
+      __syncthreads();
+      EQ::run(lds, par, a.packed, a.depth, qb);
+      for (int e = threadIdx.x; e < ROWS * QC; e += blockDim.x) {
+        const int row = e / QC, c = e % QC, i = row / D, oo = row % D;
+        st_c(jg + row * R + qb + c, i < n_valid ? (double)res[(oo * EQ::NT + CQ::Q0 + c) * PT + i] : 0.0);
+      }
+    }
+    if (ch == 0) {
+      for (int e = threadIdx.x; e < ROWS * TV; e += blockDim.x) {
+        const int row = e / TV, i = row / D, oo = row % D;
+        const double v = !merged ? rho[e]
+                       : (i < n_valid ? rho0[first * D + row] - (double)res[(oo * EQ::NT + CQ::F0) * PT + i] : 0.0);
+        st_c(jg + ROWS * R + e, v);
+      }
     }
   }
-  // arrival of this chunk: its columns are complete in memory
+  // arrival of this chunk: what it evaluated is complete in memory
   wait_mem();
   __syncthreads();
   uint32_t* bcnt = wsp<uint32_t>(a, a.L.bcnt) + blk;
@@ -962,12 +967,14 @@ __device__ bool eval_trials_elastic(const StepArgs& a, char* lds, double* jd, co
   const bool last = s_lastc != 0;
   __syncthreads();
   if (!last) return false;
-  // every chunk has arrived: stage the batch and clear its count for the
-  // next round (whose chunks start only after this instance is solved)
-  for (int e = threadIdx.x; e < ROWS * (R + TV); e += blockDim.x) jd[e] = ld_c(jg + e);
+  // every chunk has arrived: stage the batch (zero Jacobian in a round
+  // without it) and clear its count for the next round (whose chunks start
+  // only after this instance is solved)
+  for (int e = threadIdx.x; e < ROWS * (R + TV); e += blockDim.x)
+    jd[e] = with_j || e >= ROWS * R ? ld_c(jg + e) : 0.0;
   if (threadIdx.x == 0) st_c(bcnt, 0u);
   __syncthreads();
-  batch_partials<R, ROWS>(jd, rho, part);
+  batch_partials<R, ROWS>(jd, rho, wsp<double>(a, a.L.partials) + blk * a.L.nred);
   __syncthreads();
   return true;
 }
@@ -1499,7 +1506,6 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
           eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, (p == 1 && first) ? 40 : -1, first);
         else {  // backtracking rounds evaluate the objective only (the solve re-linearises)
           const bool with_j = !(ph == PH_TRIALS && lt > 0);
-          if (!with_j && ch != 0) continue;
           if (!eval_trials_elastic<S, NW, PREC, PF>(a, lds, jd, par, qdl, blk, ch, inst, first, with_j)) continue;
         }
       }

@@ -151,7 +151,7 @@ def test_batched_equals_single(cuda):
 
 
 def test_batched_beyond_resident_grid(cuda):
-    """Twelve instances (384 sample batches, 1,536 latent-tangent chunk work
+    """Twelve instances (384 sample batches, 3,072 latent-tangent chunk work
     items, several per resident workgroup and round): sampled instances
     reproduce their single-instance steps bit for bit in the iterate,
     targets and info.  The instances reject trials (5 to 10 trials for 4
