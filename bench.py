@@ -15,10 +15,14 @@ the FP64 finite-difference solver on a subset, and the headline is the
 fastest mode at the best mode's rollout error.
 
 Reported value: decoder+Jacobian point-evals per second, one point-eval
-being one point through the decoder with all 12 columns (value, 2 gradient
-entries, Laplacian, 8 latent-Jacobian entries; 1,576,448 algorithmic
-FLOP); latent steps per second (instance-steps) beside it.  roofline: the
-headline mode's timed kernels against the matrix-core peak of its
+being one point through the decoder with value, 2 gradient entries,
+Laplacian and the 8 latent-Jacobian entries; latent steps per second
+(instance-steps) beside it.  The linearised step forms the Jacobian by a
+reverse (adjoint) pass: 658,944 algorithmic FLOP per point-eval (value,
+x tangents and Laplacian forward, one adjoint column back); the
+Gauss-Newton rounds use forward tangent columns, and their point-evals are
+counted in units of that 12-column evaluation (1,576,448 FLOP).  roofline:
+the headline mode's timed kernels against the matrix-core peak of its
 arithmetic; cpu_baseline: the FP64 oracle on a bounded sample of the same
 workload.
 
@@ -45,6 +49,11 @@ W, DEPTH, M, R = 128, 5, 2, 8
 FLOP_VALUE_COL = 2 * M * W + 2 * (DEPTH - 1) * W * W + 2 * W        # 131,840
 FLOP_TAN_COL = 2 * (DEPTH - 1) * W * W + 2 * W                      # 131,328
 FLOP_POINT_EVAL = FLOP_VALUE_COL + (M + 1 + R) * FLOP_TAN_COL      # 1,576,448
+# the linearised step's evaluation: value, x tangents and Laplacian forward,
+# the latent Jacobian by one adjoint column back through the hidden layers
+# and the first layer's latent columns
+FLOP_ADJ_COL = 2 * (DEPTH - 1) * W * W + 2 * W * R                  # 133,120
+FLOP_POINT_EVAL_LLS = FLOP_VALUE_COL + (M + 1) * FLOP_TAN_COL + FLOP_ADJ_COL  # 658,944
 # Gauss-Newton step tolerance, relative to 1 + |q|.  The same 1e-6 for every
 # arithmetic: the change of q over one time step is about 1e-4 of |q| here,
 # and the stopping rule stops without moving when the Gauss-Newton step is
@@ -313,7 +322,7 @@ def batched_leg(args, crom, torch, dev, trained=None):
             k_ms, k_n = crom.kernel_timer_read()
             # the same steps again, untimed, reading every step's outcome
             q[args.warmup % 2].copy_(q_w)
-            flop, n_fail, flags_or, iters, lse = 0.0, 0, 0, 0, 0
+            flop, pevals, n_fail, flags_or, iters, lse = 0.0, 0.0, 0, 0, 0, 0
             for i in range(args.steps):
                 st.step(q[(args.warmup + i) % 2], nu, wb.dt, opts, q_next=q[(args.warmup + i + 1) % 2])
                 inf = st.info()
@@ -323,17 +332,21 @@ def batched_leg(args, crom, torch, dev, trained=None):
                 iters += int(inf["iters"].sum())
                 lse += int(inf["ls_evals"].sum())
                 if opts.linearized:
-                    flop += float(S[ok].sum()) * FLOP_POINT_EVAL
+                    pevals += float(S[ok].sum())
+                    flop += float(S[ok].sum()) * FLOP_POINT_EVAL_LLS
                 else:
-                    flop += sum(step_flops(int(S[k]), int(inf["iters"][k]), int(inf["ls_evals"][k]))
-                                for k in np.flatnonzero(ok))
+                    f = sum(step_flops(int(S[k]), int(inf["iters"][k]), int(inf["ls_evals"][k]))
+                            for k in np.flatnonzero(ok))
+                    flop += f
+                    pevals += f / FLOP_POINT_EVAL
             t = wall / args.steps
             kernel_ms = k_ms / max(1, k_n)
             fl_step = flop / args.steps
             r.update({"ms_per_step": t * 1e3, "instance_steps_per_s": (wb.n_inst * args.steps - n_fail) / wall,
-                      "point_evals_per_s": flop / FLOP_POINT_EVAL / wall,
+                      "point_evals_per_s": pevals / wall,
                       "achieved_tflops": fl_step / t / 1e12, "frac_of_peak": fl_step / t / 1e12 / PEAK[prec],
-                      "timed_kernels": ("lls_jets_kernel (the 12-column evaluation)" if opts.linearized else
+                      "timed_kernels": ("lls_jets_kernel (forward value, x tangents and Laplacian, reverse "
+                                        "latent Jacobian)" if opts.linearized else
                                         "gn_round_kernel + gn_solve_kernel, every round of the step"),
                       "timed_kernels_ms": kernel_ms, "flop_per_step": fl_step,
                       "gn_iters_mean": iters / (wb.n_inst * args.steps),
@@ -854,8 +867,11 @@ def main():
             "traffic": measured_traffic("lls_jets_kernel", "traffic_batched_2d_heat.json") if lin else None,
             "kernel": head["timed_kernels"], "avg_ms": head["timed_kernels_ms"],
             "flop_per_launch": head["flop_per_step"],
-            "flop_unit": "1,576,448 algorithmic FLOP per point-eval (12 columns of the 2D decoder, folded first "
-                         "layer, no padding) x the point-evals of one step"}
+            "flop_unit": ("658,944 algorithmic FLOP per point-eval (the 2D decoder: value, 2 x tangents and "
+                          "Laplacian forward, the latent Jacobian by one adjoint column and the first layer's "
+                          "latent columns; folded first layer, no padding) x the point-evals of one step" if lin
+                          else "forward tangent columns: 1,576,448 FLOP per 12-column evaluation plus 131,328 "
+                               "per further tangent column, over every round of the step")}
     cpu = None
     if args.cpu_seconds > 0:
         from workloads import Batched2D

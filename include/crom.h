@@ -98,7 +98,8 @@ enum {
  *                  BF16, and by the training calls in the bfloat16 modes
  *                  (the forward stores cos(z) beside sin(z) for the
  *                  backward); other calls return CROM_ERR_UNSUPPORTED.
- * packed: the fragment-ordered copy of the hidden-to-hidden weights that
+ * packed: the fragment-ordered copy of the hidden-to-hidden weights, and
+ *   of their transposes (for the reverse pass of the latent Jacobian), that
  *   crom_net_pack writes (crom_net_packed_bytes long).  It must be
  *   refreshed after params change. */
 enum { CROM_ACT_ELU = 0, CROM_ACT_SINE = 1 };

@@ -66,19 +66,25 @@ crom_status check_net(const crom_net* net, bool need_packed) {
 // ---------------------------------------------------------------------------
 // Packing of the hidden-to-hidden weights into MFMA A-operand fragments.
 // ---------------------------------------------------------------------------
+// Layers 0 .. depth-2 hold W_l (A[m][k] = W_l[m][k]), then layers depth-1 ..
+// 2 depth-3 the transposes (A[m][k] = W_l[k][m]) for the reverse pass of
+// the latent Jacobian.
 template <int W, int PREC>
 __global__ void pack_kernel(const float* __restrict__ params, ParamIndex pi, int depth,
                             char* __restrict__ out) {
   constexpr int MTILES = W / 16;
-  const int h = blockIdx.y;                       // hidden layer 0 .. depth-2
-  const float* Wl = params + pi.w[h + 1];         // [W][W]
+  const int h = blockIdx.y;                       // packed layer 0 .. 2 (depth-1) - 1
+  const bool tr = h >= depth - 1;
+  const float* Wl = params + pi.w[(tr ? h - (depth - 1) : h) + 1];  // [W][W]
+  // entry (row, col) of the A operand
+  auto at = [&](int row, int col) { return tr ? Wl[col * W + row] : Wl[row * W + col]; };
   if constexpr (PREC == PREC_FP32) {
     constexpr int KQ = W / 16;
     constexpr int N = MTILES * KQ * 64 * 4;
     float* o = reinterpret_cast<float*>(out) + (size_t)h * N;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
       const int v = i & 3, lane = (i >> 2) & 63, kq = (i >> 8) % KQ, mt = (i >> 8) / KQ;
-      o[i] = Wl[(mt * 16 + (lane & 15)) * W + kq * 16 + (lane >> 4) * 4 + v];
+      o[i] = at(mt * 16 + (lane & 15), kq * 16 + (lane >> 4) * 4 + v);
     }
   } else {
     constexpr int KB = W / 32;
@@ -86,7 +92,7 @@ __global__ void pack_kernel(const float* __restrict__ params, ParamIndex pi, int
     __bf16* o = reinterpret_cast<__bf16*>(out) + (size_t)h * 2 * N;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
       const int e = i & 7, lane = (i >> 3) & 63, kb = (i >> 9) % KB, mt = (i >> 9) / KB;
-      const float w = Wl[(mt * 16 + (lane & 15)) * W + (2 * kb + (e >> 2)) * 16 + (lane >> 4) * 4 + (e & 3)];
+      const float w = at(mt * 16 + (lane & 15), (2 * kb + (e >> 2)) * 16 + (lane >> 4) * 4 + (e & 3));
       const __bf16 hi = (__bf16)w;
       o[i] = hi;
       o[N + i] = (__bf16)(w - (float)hi);
@@ -98,7 +104,7 @@ static size_t packed_bytes(int w, int depth, int prec) {
   if (depth < 2) return 0;
   const size_t mt = w / 16;
   const size_t per = prec == CROM_PREC_FP32 ? mt * (w / 16) * 64 * 16 : mt * (w / 32) * 64 * 16 * 2;
-  return per * (depth - 1);
+  return per * 2 * (depth - 1);  // the layers, then their transposes
 }
 
 // ---------------------------------------------------------------------------
@@ -374,7 +380,7 @@ crom_status crom_net_pack(const crom_net* net, void* packed, void* stream) {
   if (!packed) return fail(CROM_ERR_INVALID_ARG, "packed is NULL");
   ParamIndex pi = param_index(net->m, net->r, net->d, net->width, net->depth);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  dim3 grid(64, net->depth - 1);
+  dim3 grid(64, 2 * (net->depth - 1));
   char* out = static_cast<char*>(packed);
   const bool f32 = net->precision == CROM_PREC_FP32;
   switch (net->width) {

@@ -46,6 +46,20 @@ namespace crom {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Rounds a and b to bfloat16 (nearest even, one packed conversion) and
+// returns the pair (a in the low half); ra and rb receive the rounded values
+// as floats, taken from the packed bits, for the hi/lo split.
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b, float& ra, float& rb) {
+  bf16x2 p;
+  p[0] = (__bf16)a;
+  p[1] = (__bf16)b;
+  const uint32_t u = __builtin_bit_cast(uint32_t, p);
+  ra = __uint_as_float(u << 16);
+  rb = __uint_as_float(u & 0xffff0000u);
+  return u;
+}
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int PT = 16;  // points per N-tile
@@ -131,8 +145,10 @@ struct ParamIndex {
   int64_t w[16], b[16];
 };
 
-// e^min(z, 0), written so that a NaN z stays NaN (fminf would drop it).
-__device__ __forceinline__ float elu_exp(float z) { return __expf(z > 0.0f ? 0.0f : z); }
+// e^z for the negative branch of the ELU.  Every caller selects the
+// positive branch by z > 0 itself, so no clamp: for z > 0 the value (up to
+// infinity) is never used, and a NaN z stays NaN.
+__device__ __forceinline__ float elu_exp(float z) { return __expf(z); }
 
 // e^x - 1 without cancellation: Taylor series (6 terms, relative error
 // below 2e-12 for |x| < 1/32) near 0, e^x - 1 beyond.
@@ -287,9 +303,11 @@ struct Engine {
 
   // ---- epilogue ---------------------------------------------------------
   // In place on z[t] for one (unit, lane) across all tiles.
-  static __device__ __forceinline__ void epilogue(float (&z)[NT]) {
+  // s1o (optional): receives each batch's slope s1 = act'(z) of the value
+  // column, for a reverse pass.
+  static __device__ __forceinline__ void epilogue(float (&z)[NT], float* s1o = nullptr) {
     if constexpr (S::ACT == ACT_SINE) {
-      epilogue_sine(z);
+      epilogue_sine(z, s1o);
       return;
     }
 #pragma unroll
@@ -300,6 +318,7 @@ struct Engine {
       const bool pos0 = z0 > 0.0f;
       const float s1 = pos0 ? 1.0f : e0;
       const float s2 = pos0 ? 0.0f : e0;
+      if (s1o) s1o[b] = s1;
       float st = s1;  // tangent scale: at the base latent, or at difference column 0's
 #pragma unroll
       for (int c = C::F0; c < C::X0; ++c) {
@@ -340,7 +359,7 @@ struct Engine {
 
   // The same column rules with s = sin: s1 = cos, s2 = -sin, differences
   // sin(z + Dz) - sin(z) = 2 cos(z + Dz/2) sin(Dz/2).
-  static __device__ __forceinline__ void epilogue_sine(float (&z)[NT]) {
+  static __device__ __forceinline__ void epilogue_sine(float (&z)[NT], float* s1o) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       float* zb = &z[b * CC];
@@ -348,6 +367,7 @@ struct Engine {
       const float r0 = reduce_2pi(z0);
       const float sn0 = __sinf(r0), cs0 = __cosf(r0);
       const float s1 = cs0, s2 = -sn0;
+      if (s1o) s1o[b] = s1;
       float st = s1;  // tangent scale: at the base latent, or at difference column 0's
 #pragma unroll
       for (int c = C::F0; c < C::X0; ++c) {
@@ -385,24 +405,20 @@ struct Engine {
 #pragma unroll
       for (int t = 0; t < NT; ++t) act[(t * KQ + mtg) * 64 + lane] = o[t];
     } else {
-      // fragment (t, kb = mtg/2), element offset (mtg%2)*4
-      bf16x4* act = reinterpret_cast<bf16x4*>(lds);
+      // fragment (t, kb = mtg/2), element offset (mtg%2)*4; four bfloat16
+      // values as two packed pairs
+      uint2* act = reinterpret_cast<uint2*>(lds);
       const int half = mtg & 1;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        bf16x4 h;
-        h[0] = (__bf16)o[t][0];
-        h[1] = (__bf16)o[t][1];
-        h[2] = (__bf16)o[t][2];
-        h[3] = (__bf16)o[t][3];
-        act[((t * KQ + (mtg >> 1)) * 64 + lane) * 2 + half] = h;
         const int b = t / CC, c = t % CC;
+        float r[4];
+        const uint2 h = {bf16_pair(o[t][0], o[t][1], r[0], r[1]), bf16_pair(o[t][2], o[t][3], r[2], r[3])};
+        act[((t * KQ + (mtg >> 1)) * 64 + lane) * 2 + half] = h;
         if (is_split<C, PREC>(c)) {
-          bf16x4 l;
-          l[0] = (__bf16)(o[t][0] - (float)h[0]);
-          l[1] = (__bf16)(o[t][1] - (float)h[1]);
-          l[2] = (__bf16)(o[t][2] - (float)h[2]);
-          l[3] = (__bf16)(o[t][3] - (float)h[3]);
+          float d[4];
+          const uint2 l = {bf16_pair(o[t][0] - r[0], o[t][1] - r[1], d[0], d[1]),
+                           bf16_pair(o[t][2] - r[2], o[t][3] - r[3], d[2], d[3])};
           act[((lo_tile(b, c) * KQ + (mtg >> 1)) * 64 + lane) * 2 + half] = l;
         }
       }
@@ -424,13 +440,13 @@ struct Engine {
   }
 
   // epilogue over the 4 accumulator rows of one M-tile, in place
-  static __device__ __forceinline__ void epilogue_tile(f32x4 (&acc)[NT]) {
+  static __device__ __forceinline__ void epilogue_tile(f32x4 (&acc)[NT], float* s1o = nullptr) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       float z[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) z[t] = acc[t][v];
-      epilogue(z);
+      epilogue(z, s1o ? s1o + v * NB : nullptr);
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t][v] = z[t];
     }
@@ -451,13 +467,35 @@ struct Engine {
     } else {
       if (h > 0) load_frags(cur, packed, h, wave, lane);
     }
-    const float* bias = par + PC::BH(h);
     f32x4 acc[MT][NT];
+    products(lds, par + PC::BH(h), packed, h, cur, acc, wave, lane);
+    __syncthreads();  // every wave has read this layer's activations
+    const bool last = (h == depth - 2);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int mtg = wave * MT + mt;
-      const float* bp = bias + mtg * 16 + g * 4;
-      const f32x4 bv = {bp[0], bp[1], bp[2], bp[3]};
+      epilogue_tile(acc[mt]);
+      if (!last) write_act(lds, mtg, lane, acc[mt]);
+      else out_accum(part, acc[mt], Wout, mtg * 16 + g * 4);
+    }
+    __syncthreads();
+  }
+
+  // acc = W act (+ the bias on value columns): the products of packed layer
+  // h over the staged activations, fragments from `cur` (held) or streamed
+  // from `packed`.
+  static __device__ __forceinline__ void products(const char* lds, const float* bias,
+                                                  const char* __restrict__ packed, int h, const Frags& cur,
+                                                  f32x4 (&acc)[MT][NT], int wave, int lane) {
+    const int g = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int mtg = wave * MT + mt;
+      f32x4 bv = {0.0f, 0.0f, 0.0f, 0.0f};
+      if constexpr (C::NV > 0) {
+        const float* bp = bias + mtg * 16 + g * 4;
+        bv = f32x4{bp[0], bp[1], bp[2], bp[3]};
+      }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const bool isval = C::kind(t % CC) == CK_VAL;
@@ -550,16 +588,6 @@ struct Engine {
 #undef CROM_FRAG_LO
 #undef CROM_STREAM_NEXT
 #undef CROM_STREAM_SHIFT
-    __syncthreads();  // every wave has read this layer's activations
-    const bool last = (h == depth - 2);
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int mtg = wave * MT + mt;
-      epilogue_tile(acc[mt]);
-      if (!last) write_act(lds, mtg, lane, acc[mt]);
-      else out_accum(part, acc[mt], Wout, mtg * 16 + g * 4);
-    }
-    __syncthreads();
   }
 
   // ---- the whole network for one batch -----------------------------------
@@ -569,11 +597,6 @@ struct Engine {
                              int qb) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int g = lane >> 4, j = lane & 15;
-    const float* xs = reinterpret_cast<const float*>(lds + XS_OFF);
-    const float* fold = reinterpret_cast<const float*>(lds + FOLD_OFF);
-    const float* W1 = par + PC::W1(0);
-    const float* Wout = par + PC::WOUT(depth);
     float part[D][NT];
 #pragma unroll
     for (int oo = 0; oo < D; ++oo)
@@ -582,8 +605,30 @@ struct Engine {
 
     Frags fa, fb;  // current and next layer's weight fragments
     if (depth > 1) load_frags(fa, packed, 0, wave, lane);
+    first_layer(lds, par, depth, qb, part, wave, lane);
 
-    // ---------------- layer 1 (VALU, folded) ----------------
+    // ---------------- hidden layers 2..depth (MFMA) ----------------
+    // Two layers per trip so that each weight-fragment buffer keeps a fixed
+    // register home.
+    for (int h = 0; h < depth - 1; h += 2) {
+      hidden_layer(lds, par, packed, depth, h, fa, fb, part, wave, lane);
+      if (h + 1 < depth - 1) hidden_layer(lds, par, packed, depth, h + 1, fb, fa, part, wave, lane);
+    }
+    reduce_outputs(lds, par, depth, part, reinterpret_cast<float*>(lds + RES_OFF), NT, 0, wave, lane);
+  }
+
+  // ---- layer 1 (VALU, folded) ---------------------------------------------
+  // Its activations go to the staged tiles (or, for a one-layer network, to
+  // the output partial sums); s1o (optional) receives the value column's
+  // slope at this lane's entries, [mt][v] (NB == 1).
+  static __device__ __forceinline__ void first_layer(char* lds, const float* par, int depth, int qb,
+                                                     float (&part)[D][NT], int wave, int lane,
+                                                     float (*s1o)[4] = nullptr) {
+    const int g = lane >> 4, j = lane & 15;
+    const float* xs = reinterpret_cast<const float*>(lds + XS_OFF);
+    const float* fold = reinterpret_cast<const float*>(lds + FOLD_OFF);
+    const float* W1 = par + PC::W1(0);
+    const float* Wout = par + PC::WOUT(depth);
     {
       float xr[NB][M];
 #pragma unroll
@@ -618,7 +663,7 @@ struct Engine {
               z[b * CC + c] = val;
             }
           }
-          epilogue(z);
+          epilogue(z, s1o ? &s1o[mt][v] : nullptr);
 #pragma unroll
           for (int t = 0; t < NT; ++t) o4[t][v] = z[t];
         }
@@ -627,16 +672,15 @@ struct Engine {
       }
     }
     __syncthreads();
+  }
 
-    // ---------------- hidden layers 2..depth (MFMA) ----------------
-    // Two layers per trip so that each weight-fragment buffer keeps a fixed
-    // register home.
-    for (int h = 0; h < depth - 1; h += 2) {
-      hidden_layer(lds, par, packed, depth, h, fa, fb, part, wave, lane);
-      if (h + 1 < depth - 1) hidden_layer(lds, par, packed, depth, h + 1, fb, fa, part, wave, lane);
-    }
-
-    // ---------------- output layer: reduce partial dot products ----------
+  // ---- output layer: reduce the partial dot products ------------------------
+  // res[oo * res_nt + res_t0 + t][16] = bout (value columns) + the sum of
+  // every lane group's and wave's part[oo][t].  Reuses the activation region.
+  static __device__ __forceinline__ void reduce_outputs(char* lds, const float* par, int depth,
+                                                        float (&part)[D][NT], float* res, int res_nt,
+                                                        int res_t0, int wave, int lane) {
+    const int g = lane >> 4, j = lane & 15;
 #pragma unroll
     for (int oo = 0; oo < D; ++oo)
 #pragma unroll
@@ -654,7 +698,6 @@ struct Engine {
         for (int t = 0; t < NT; ++t) red[((wave * D + oo) * NT + t) * PT + j] = part[oo][t];
     }
     __syncthreads();
-    float* res = reinterpret_cast<float*>(lds + RES_OFF);
     const float* bout = par + PC::BOUT(depth);
     for (int i = threadIdx.x; i < D * NT * PT; i += THREADS) {
       const int oo = i / (NT * PT);
@@ -662,7 +705,215 @@ struct Engine {
       float s = C::kind(t % CC) == CK_VAL ? bout[oo] : 0.0f;
 #pragma unroll
       for (int w = 0; w < NW; ++w) s += red[w * D * NT * PT + i];
-      res[i] = s;
+      res[(oo * res_nt + res_t0 + t) * PT + (i % PT)] = s;
+    }
+    __syncthreads();
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Value, x tangents and Laplacian by forward mode, the latent Jacobian by
+// one reverse (adjoint) pass per output instead of R forward tangent
+// columns.  The latent Jacobian is the chain rule through the layers (Sec.
+// "Network Inversion" uses dg/dq), accumulated from the output back: with
+// s1_l = act'(z_l) at every layer,
+//   dz_L = s1_L * Wout[o],   dz_{l-1} = s1_{l-1} * (W_l^T dz_l),
+//   dg_o/dq_k = sum_u W1[u][m + k] dz_0[u],
+// the same products the forward tangent columns form, associated the other
+// way.  The forward pass keeps each layer's s1 in registers, so depth is
+// bounded by DMAX; the adjoint columns take the arithmetic of latent-tangent
+// columns (plain bfloat16 in BF16, split in BF16X3) and the transposed
+// weight fragments that crom_net_pack writes after the layers.  Outputs
+// res[D][NTO][16] in the column order of Cols<m, r, 1, 0, true, D2_LAP, r>:
+// value, x tangents, Laplacian, dg/dq_0 .. dg/dq_{r-1}.
+// ---------------------------------------------------------------------------
+#ifndef CROM_REV_DMAX
+#define CROM_REV_DMAX 6
+#endif
+template <class S, int NW, int PREC, int PF, int DMAX = CROM_REV_DMAX>
+struct RevJets {
+  static constexpr int W = S::W, M = S::M, R = S::R, D = S::D;
+  using CF = Cols<M, R, 1, 0, true, D2_LAP, 0>;  // value, x tangents, Laplacian
+  using CB = Cols<M, R, 0, 0, false, D2_NONE, D>;  // one adjoint column per output
+  using CO = Cols<M, R, 1, 0, true, D2_LAP, R>;  // the output columns
+  using EF = Engine<S, CF, 1, NW, PREC, PF>;
+  using EB = Engine<S, CB, 1, NW, PREC, PF>;
+  using PC = ParamCache<S>;
+  static constexpr int MT = EF::MT, NTF = CF::C, NTO = CO::C, THREADS = NW * 64;
+  static_assert(NTF == CO::Q0, "forward columns precede the Jacobian columns");
+  static_assert(EB::ACT_BYTES <= EF::ACT_REGION, "the adjoint tiles fit the activation region");
+  static_assert(NW * D * R * PT * 4 <= EF::ACT_REGION, "the Jacobian reduction fits the activation region");
+  static constexpr int RES_OFF = EF::LDS_BYTES;
+  static constexpr int LDS_BYTES = RES_OFF + D * NTO * PT * 4;  // without the parameter cache
+  static __host__ __device__ constexpr bool supported(int depth) { return depth >= 2 && depth <= DMAX; }
+
+  // The slopes kept for the reverse pass: FP32 in the FP32 and BF16X3
+  // modes; in the bfloat16 modes as packed half-precision pairs (rounded
+  // toward zero, relative error below 2^-10, half the rounding error of the
+  // bfloat16 adjoint operands), which halves their registers.
+  typedef __fp16 h2 __attribute__((ext_vector_type(2)));
+  static constexpr bool S1H = PREC == PREC_BF16 || PREC == PREC_BF16_PURE;
+  struct Slopes {
+    float f[S1H ? 1 : DMAX][MT][4];
+    h2 h[S1H ? DMAX : 1][MT][2];
+  };
+  static __device__ __forceinline__ void put(Slopes& sl, int l, int mt, const float (&v)[4]) {
+    if constexpr (S1H) {
+      sl.h[l][mt][0] = __builtin_amdgcn_cvt_pkrtz(v[0], v[1]);
+      sl.h[l][mt][1] = __builtin_amdgcn_cvt_pkrtz(v[2], v[3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sl.f[l][mt][i] = v[i];
+    }
+  }
+  static __device__ __forceinline__ float get(const Slopes& sl, int l, int mt, int v) {
+    if constexpr (S1H) return (float)sl.h[l][mt][v >> 1][v & 1];
+    else return sl.f[l][mt][v];
+  }
+
+  // Packed layer h's fragments, the address formed where the layer starts:
+  // with the layers unrolled the compiler would otherwise form every
+  // layer's per-lane addresses up front and keep them live.
+  static __device__ __forceinline__ const char* layer_base(const char* packed, int h) {
+    const char* p = packed + (size_t)h * Packing<S, PREC>::LAYER_BYTES;
+    asm volatile("" : "+s"(p));
+    return p;
+  }
+
+  static __device__ void stage(char* lds, const float* __restrict__ x, int64_t first, int n_valid,
+                               const double* __restrict__ lat, const float* par) {
+    EF::stage(lds, x, first, n_valid, lat, R, nullptr, 0, par);
+  }
+
+  static __device__ void run(char* lds, const float* par, const char* __restrict__ packed, int depth) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, j = lane & 15;
+    float* res = reinterpret_cast<float*>(lds + RES_OFF);
+    const float* W1 = par + PC::W1(0);
+    const float* Wout = par + PC::WOUT(depth);
+    Slopes sl;  // slope of layer l at this lane's (unit, point) entries
+    float part[D][NTF];
+#pragma unroll
+    for (int oo = 0; oo < D; ++oo)
+#pragma unroll
+      for (int t = 0; t < NTF; ++t) part[oo][t] = 0.0f;
+
+    // ---- forward: layer 1 on the VALU, then the hidden layers
+    typename EF::Frags ff;
+    if constexpr (!EF::STREAM) EF::load_frags(ff, packed, 0, wave, lane);
+    {
+      float s0[MT][4];
+      EF::first_layer(lds, par, depth, 0, part, wave, lane, s0);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) put(sl, 0, mt, s0[mt]);
+    }
+#pragma unroll
+    for (int l = 1; l < DMAX; ++l) {
+      if (l < depth) {
+        if constexpr (!EF::STREAM) {
+          if (l > 1) EF::load_frags(ff, packed, l - 1, wave, lane);
+        }
+        f32x4 acc[MT][NTF];
+        EF::products(lds, par + PC::BH(l - 1), layer_base(packed, l - 1), 0, ff, acc, wave, lane);
+        __syncthreads();  // every wave has read this layer's activations
+        const bool last = l == depth - 1;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int mtg = wave * MT + mt;
+          float sv[4];
+          EF::epilogue_tile(acc[mt], sv);
+          put(sl, l, mt, sv);
+          if (!last) EF::write_act(lds, mtg, lane, acc[mt]);
+          else EF::out_accum(part, acc[mt], Wout, mtg * 16 + g * 4);
+        }
+        __syncthreads();
+      }
+    }
+    EF::reduce_outputs(lds, par, depth, part, res, NTO, 0, wave, lane);
+
+    // ---- adjoint of the last hidden layer's pre-activation: s1_L * Wout[o]
+#pragma unroll
+    for (int l = 1; l < DMAX; ++l) {
+      if (l == depth - 1) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int mtg = wave * MT + mt;
+          f32x4 o4[D];
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int oo = 0; oo < D; ++oo) o4[oo][v] = get(sl, l, mt, v) * Wout[oo * W + mtg * 16 + g * 4 + v];
+          EB::write_act(lds, mtg, lane, o4);
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- back through the hidden layers (transposed fragments), then W1's
+    // latent columns
+    const char* packed_t = packed + (size_t)(depth - 1) * Packing<S, PREC>::LAYER_BYTES;
+    float jp[D][R];
+#pragma unroll
+    for (int oo = 0; oo < D; ++oo)
+#pragma unroll
+      for (int k = 0; k < R; ++k) jp[oo][k] = 0.0f;
+    typename EB::Frags fb;
+#pragma unroll
+    for (int l = DMAX - 1; l >= 1; --l) {
+      if (l <= depth - 1) {
+        if constexpr (!EB::STREAM) EB::load_frags(fb, packed_t, l - 1, wave, lane);
+        f32x4 acc[MT][D];
+        EB::products(lds, nullptr, layer_base(packed_t, l - 1), 0, fb, acc, wave, lane);
+        __syncthreads();  // every wave has read dz_l
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int mtg = wave * MT + mt;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int oo = 0; oo < D; ++oo) acc[mt][oo][v] *= get(sl, l - 1, mt, v);
+          if (l > 1) {
+            EB::write_act(lds, mtg, lane, acc[mt]);
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const float* w1 = W1 + (mtg * 16 + g * 4 + v) * (M + R) + M;
+#pragma unroll
+              for (int k = 0; k < R; ++k) {
+                const float w = w1[k];
+#pragma unroll
+                for (int oo = 0; oo < D; ++oo) jp[oo][k] += w * acc[mt][oo][v];
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+
+    // ---- sum the Jacobian over lane groups and waves
+#pragma unroll
+    for (int oo = 0; oo < D; ++oo)
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        float t = jp[oo][k];
+        t += __shfl_xor(t, 16);
+        t += __shfl_xor(t, 32);
+        jp[oo][k] = t;
+      }
+    float* red = reinterpret_cast<float*>(lds);
+    if (g == 0) {
+#pragma unroll
+      for (int oo = 0; oo < D; ++oo)
+#pragma unroll
+        for (int k = 0; k < R; ++k) red[((wave * D + oo) * R + k) * PT + j] = jp[oo][k];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < D * R * PT; i += THREADS) {
+      const int oo = i / (R * PT), k = (i / PT) % R;
+      float t = 0.0f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) t += red[w * D * R * PT + i];
+      res[(oo * NTO + NTF + k) * PT + i % PT] = t;
     }
     __syncthreads();
   }

@@ -117,6 +117,41 @@ def test_heat2d_step_lowp(cuda, prec, tol, tol_j):
         assert e_q <= tol_j * np.sqrt(cond)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("depth", [2, 3, 4, 6, 7])
+def test_lls_every_depth(cuda, prec, depth):
+    """The linearised step forms the latent Jacobian by a reverse pass for
+    depth 2 .. 6 (each layer's slope held in registers) and by forward
+    tangent columns beyond: at every depth the step follows the oracle's
+    linearised step (the 2D decoder, 1,995 samples, a ragged last batch).
+    Bars: the targets to 1e-5 (FP32) or 1e-4; the decoded change within the
+    FP32 step's 1e-3 in FP32 and BF16X3 (at depth 3 this network's FP32
+    step is itself 3e-4 off: the conditioning, not the arithmetic), and
+    within 3e-1 in BF16, where the plain-bfloat16 Jacobian meets these
+    random networks' conditioning (forward tangent columns measured 5.2e-2,
+    3.1e-2, 2.0e-1 and 1.3e-1 at depths 2, 3, 4 and 7; the reverse pass
+    1.9e-2, 4.0e-2 and 1.4e-1 at depths 2 to 4); the latent update within
+    the least-squares bound."""
+    wl = Heat2D(seed=5, bias_scale=0.1, depth=depth)
+    wl.samples = wl.samples[:1995]
+    S = wl.samples.shape[0]
+    q1, info, f, _ = _run(cuda, wl.layers, 2, [0, S], wl.samples, wl.q0, [wl.mu], wl.dt, prec=prec,
+                          linearized=True)
+    qr, oinfo, fr = _oracle_step(wl.layers, 2, wl.samples, wl.q0, wl.mu, wl.dt, linearized=True)
+    J = mlp.MLPDecoder(wl.layers, 2).value_jac_q(wl.samples, wl.q0)[1].reshape(-1, len(wl.q0))
+    cond = np.linalg.cond(J.T @ J)
+    e_f = normwise_rel(f, fr)
+    e_dg = _dg_err(wl.layers, 2, wl.samples, wl.q0, q1[0], qr)
+    e_q = normwise_rel(q1[0] - wl.q0, qr - wl.q0)
+    print(f"depth {depth} {prec}: targets {e_f:.2e} dg err {e_dg:.2e} dq err {e_q:.2e} "
+          f"cond(J^T J) {cond:.2e} flags {info['flags'][0]}")
+    assert info["flags"][0] == 0
+    assert e_f <= (1e-5 if prec == "fp32" else 1e-4)
+    tol_dg, tol_j = {"fp32": (1e-3, 1e-5), "bf16x3": (1e-3, 1e-4), "bf16": (3e-1, 2e-2)}[prec]
+    assert e_dg <= tol_dg
+    assert e_q <= tol_j * np.sqrt(cond)
+
+
 def test_batched_ragged_instances(cuda):
     """A ragged batch equals its instances run one at a time (bit for bit:
     each instance's sums are taken in the same order), and each matches the
