@@ -17,11 +17,11 @@ fastest mode at the best mode's rollout error.
 Reported value: decoder+Jacobian point-evals per second, one point-eval
 being one point through the decoder with value, 2 gradient entries,
 Laplacian and the 8 latent-Jacobian entries; latent steps per second
-(instance-steps) beside it.  The linearised step forms the Jacobian by a
+(instance-steps) beside it.  The step forms the latent Jacobian by a
 reverse (adjoint) pass: 658,944 algorithmic FLOP per point-eval (value,
-x tangents and Laplacian forward, one adjoint column back); the
-Gauss-Newton rounds use forward tangent columns, and their point-evals are
-counted in units of that 12-column evaluation (1,576,448 FLOP).  roofline:
+x tangents and Laplacian forward, one adjoint column back); a Gauss-Newton
+step's further iterations and trials are counted in units of that
+evaluation.  roofline:
 the headline mode's timed kernels against the matrix-core peak of its
 arithmetic; cpu_baseline: the FP64 oracle on a bounded sample of the same
 workload.
@@ -95,10 +95,12 @@ def measured_traffic(kernel: str, summary: str = "traffic_2d_heat.json"):
 
 
 def step_flops(S: int, iters: int, ls_evals: int) -> float:
-    """Algorithmic decoder FLOP of one latent step: the 12-column evaluation
-    at q_n, then per Gauss-Newton iteration the r latent tangents at the new
-    iterate, plus one difference column per line-search trial examined."""
-    return S * (FLOP_POINT_EVAL + (ls_evals + iters * R) * FLOP_TAN_COL)
+    """Algorithmic decoder FLOP of one Gauss-Newton latent step as the
+    library forms it for these depths (the reverse pass): the evaluation at
+    q_n (value, x tangents and Laplacian forward, the latent Jacobian by one
+    adjoint column), then per iteration the adjoint column at the new
+    iterate, and one difference column per line-search trial examined."""
+    return S * (FLOP_POINT_EVAL_LLS + iters * FLOP_ADJ_COL + ls_evals * FLOP_TAN_COL)
 
 
 def _cores():
@@ -124,11 +126,11 @@ def cpu_baseline_batched(wb, opts_kw: dict, budget_s: float):
         y = wb.samples[wb.offsets[n]:wb.offsets[n + 1]]
         _, info, _ = ostep.heat_step(dec, y, wb.q0[n], float(wb.mu[n]), wb.dt, GNOptions(**opts_kw))
         S = len(y)
-        flop += S * FLOP_POINT_EVAL if opts_kw.get("linearized") else step_flops(S, info.iters, info.ls_evals)
+        flop += S * FLOP_POINT_EVAL_LLS if opts_kw.get("linearized") else step_flops(S, info.iters, info.ls_evals)
         S_tot += S
         n += 1
     dt = time.perf_counter() - t0
-    return {"value": flop / FLOP_POINT_EVAL / dt, "unit": "point-evals/s", "cores": _cores(), "kind": "oracle",
+    return {"value": flop / FLOP_POINT_EVAL_LLS / dt, "unit": "point-evals/s", "cores": _cores(), "kind": "oracle",
             "sample": f"one latent step ({'linearised' if opts_kw.get('linearized') else 'Gauss-Newton'}) of "
                       f"instances 0..{n - 1} of the 512-instance batch ({S_tot} samples), FP64 NumPy, {dt:.1f} s",
             "latent_steps_per_s": n / dt}
@@ -149,7 +151,7 @@ def cpu_baseline(wl, nodes, n_steps: int):
                                      GNOptions(max_iter=5, tol_step=TOL_STEP["fp32"]))
         flop += len(nodes) * FLOP_VALUE_COL + step_flops(len(wl.samples), info.iters, info.ls_evals)
     dt = time.perf_counter() - t0
-    return {"value": flop / FLOP_POINT_EVAL / dt, "unit": "point-evals/s", "cores": cores,
+    return {"value": flop / FLOP_POINT_EVAL_LLS / dt, "unit": "point-evals/s", "cores": cores,
             "kind": "oracle", "sample": f"{n_steps} steps (full-field decode of {len(nodes)} nodes + "
             f"one Gauss-Newton latent step at {len(wl.samples)} samples each), FP64 NumPy, {dt:.1f} s",
             "latent_steps_per_s": n_steps / dt}
@@ -338,7 +340,7 @@ def batched_leg(args, crom, torch, dev, trained=None):
                     f = sum(step_flops(int(S[k]), int(inf["iters"][k]), int(inf["ls_evals"][k]))
                             for k in np.flatnonzero(ok))
                     flop += f
-                    pevals += f / FLOP_POINT_EVAL
+                    pevals += f / FLOP_POINT_EVAL_LLS
             t = wall / args.steps
             kernel_ms = k_ms / max(1, k_n)
             fl_step = flop / args.steps
@@ -793,7 +795,7 @@ def single_leg(args, crom, torch, dev):
     return {"workload": "2D heat, 256x256 grid: full-field decode of 65,536 nodes + one Gauss-Newton latent "
                         "step at 2,000 samples per step, one instance, Xavier-uniform network",
             "precision": args.prec, "gn_tol_step": TOL_STEP[args.prec],
-            "point_evals_per_s": (flop_dec + flop_step) / FLOP_POINT_EVAL / wall,
+            "point_evals_per_s": (flop_dec + flop_step) / FLOP_POINT_EVAL_LLS / wall,
             "ms_per_step": wall / args.steps * 1e3, "latent_steps_per_s": args.steps / wall,
             "lls_latent_steps_per_s": args.steps / (time.perf_counter() - t1),
             "step_ms_avg": t_step.mean() * 1e3, "decode_ms_avg": t_dec.mean() * 1e3,
@@ -870,8 +872,8 @@ def main():
             "flop_unit": ("658,944 algorithmic FLOP per point-eval (the 2D decoder: value, 2 x tangents and "
                           "Laplacian forward, the latent Jacobian by one adjoint column and the first layer's "
                           "latent columns; folded first layer, no padding) x the point-evals of one step" if lin
-                          else "forward tangent columns: 1,576,448 FLOP per 12-column evaluation plus 131,328 "
-                               "per further tangent column, over every round of the step")}
+                          else "658,944 FLOP per sample for the evaluation at q_n, 133,120 per further adjoint "
+                               "column (iteration) and 131,328 per difference column (trial), over the step")}
     cpu = None
     if args.cpu_seconds > 0:
         from workloads import Batched2D

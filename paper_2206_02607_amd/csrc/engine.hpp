@@ -55,7 +55,10 @@ __device__ __forceinline__ uint32_t bf16_pair(float a, float b, float& ra, float
   bf16x2 p;
   p[0] = (__bf16)a;
   p[1] = (__bf16)b;
-  const uint32_t u = __builtin_bit_cast(uint32_t, p);
+  uint32_t u = __builtin_bit_cast(uint32_t, p);
+  // the rounded values come from these bits: without the empty asm the
+  // compiler converts a a second time, alone, for the low half
+  asm volatile("" : "+v"(u));
   ra = __uint_as_float(u << 16);
   rb = __uint_as_float(u & 0xffff0000u);
   return u;
@@ -226,7 +229,7 @@ struct Engine {
   static constexpr int KQ = Packing<S, PREC>::KQ;
   static constexpr int NACT = NT + NSPL;
   static constexpr int ACT_BYTES = NACT * KQ * 64 * 16;
-  static constexpr int RED_BYTES = NW * D * NT * PT * 4;
+  static constexpr int RED_BYTES = MTILES * D * NT * PT * 4;
   static constexpr int ACT_REGION = ACT_BYTES > RED_BYTES ? ACT_BYTES : RED_BYTES;
   static constexpr int XS_OFF = ACT_REGION;
   static constexpr int NF = C::NV + C::ND;
@@ -303,8 +306,10 @@ struct Engine {
 
   // ---- epilogue ---------------------------------------------------------
   // In place on z[t] for one (unit, lane) across all tiles.
-  // s1o (optional): receives each batch's slope s1 = act'(z) of the value
-  // column, for a reverse pass.
+  // s1o (optional): receives each batch's tangent slope act'(z) (at the
+  // value column's latent, or at difference column 0's when there are
+  // difference columns: the slope the tangent columns take), for a reverse
+  // pass.
   static __device__ __forceinline__ void epilogue(float (&z)[NT], float* s1o = nullptr) {
     if constexpr (S::ACT == ACT_SINE) {
       epilogue_sine(z, s1o);
@@ -318,7 +323,6 @@ struct Engine {
       const bool pos0 = z0 > 0.0f;
       const float s1 = pos0 ? 1.0f : e0;
       const float s2 = pos0 ? 0.0f : e0;
-      if (s1o) s1o[b] = s1;
       float st = s1;  // tangent scale: at the base latent, or at difference column 0's
 #pragma unroll
       for (int c = C::F0; c < C::X0; ++c) {
@@ -331,6 +335,7 @@ struct Engine {
         zb[c] = (pos0 && post) ? dz : ((!pos0 && !post) ? both_neg : cross);
         if (c == C::F0) st = post ? 1.0f : et;
       }
+      if (s1o) s1o[b] = st;
       if constexpr (C::D2 == D2_LAP) {
         float sq = 0.0f;
 #pragma unroll
@@ -367,7 +372,6 @@ struct Engine {
       const float r0 = reduce_2pi(z0);
       const float sn0 = __sinf(r0), cs0 = __cosf(r0);
       const float s1 = cs0, s2 = -sn0;
-      if (s1o) s1o[b] = s1;
       float st = s1;  // tangent scale: at the base latent, or at difference column 0's
 #pragma unroll
       for (int c = C::F0; c < C::X0; ++c) {
@@ -375,6 +379,7 @@ struct Engine {
         zb[c] = 2.0f * cos_r(z0 + 0.5f * dz) * sin_small(0.5f * dz);
         if (c == C::F0) st = cos_r(z0 + dz);
       }
+      if (s1o) s1o[b] = st;
       if constexpr (C::D2 == D2_LAP) {
         float sq = 0.0f;
 #pragma unroll
@@ -459,7 +464,7 @@ struct Engine {
   static __device__ __forceinline__ void hidden_layer(char* lds, const float* par,
                                                       const char* __restrict__ packed, int depth,
                                                       int h, Frags& cur, Frags& nxt,
-                                                      float (&part)[D][NT], int wave, int lane) {
+                                                      float (&part)[MT][D][NT], int wave, int lane) {
     const int g = lane >> 4;
     const float* Wout = par + PC::WOUT(depth);
     if constexpr (PREFETCH) {
@@ -476,7 +481,7 @@ struct Engine {
       const int mtg = wave * MT + mt;
       epilogue_tile(acc[mt]);
       if (!last) write_act(lds, mtg, lane, acc[mt]);
-      else out_accum(part, acc[mt], Wout, mtg * 16 + g * 4);
+      else out_accum(part[mt], acc[mt], Wout, mtg * 16 + g * 4);
     }
     __syncthreads();
   }
@@ -597,11 +602,13 @@ struct Engine {
                              int qb) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    float part[D][NT];
+    float part[MT][D][NT];  // output partial sums per M-tile
 #pragma unroll
-    for (int oo = 0; oo < D; ++oo)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) part[oo][t] = 0.0f;
+      for (int oo = 0; oo < D; ++oo)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) part[mt][oo][t] = 0.0f;
 
     Frags fa, fb;  // current and next layer's weight fragments
     if (depth > 1) load_frags(fa, packed, 0, wave, lane);
@@ -622,7 +629,7 @@ struct Engine {
   // the output partial sums); s1o (optional) receives the value column's
   // slope at this lane's entries, [mt][v] (NB == 1).
   static __device__ __forceinline__ void first_layer(char* lds, const float* par, int depth, int qb,
-                                                     float (&part)[D][NT], int wave, int lane,
+                                                     float (&part)[MT][D][NT], int wave, int lane,
                                                      float (*s1o)[4] = nullptr) {
     const int g = lane >> 4, j = lane & 15;
     const float* xs = reinterpret_cast<const float*>(lds + XS_OFF);
@@ -668,43 +675,56 @@ struct Engine {
           for (int t = 0; t < NT; ++t) o4[t][v] = z[t];
         }
         if (depth > 1) write_act(lds, mtg, lane, o4);
-        else out_accum(part, o4, Wout, mtg * 16 + g * 4);
+        else out_accum(part[mt], o4, Wout, mtg * 16 + g * 4);
       }
     }
     __syncthreads();
   }
 
   // ---- output layer: reduce the partial dot products ------------------------
-  // res[oo * res_nt + res_t0 + t][16] = bout (value columns) + the sum of
-  // every lane group's and wave's part[oo][t].  Reuses the activation region.
+  // res[oo * res_nt + res_t0 + t][16] = bout (value columns) + the sum over
+  // the M-tiles, in tile order, of each tile's lane-group sum of
+  // part[mt][oo][t]: the same order for any number of waves, so results do
+  // not depend on how the tiles are spread over waves.  Reuses the
+  // activation region.
   static __device__ __forceinline__ void reduce_outputs(char* lds, const float* par, int depth,
-                                                        float (&part)[D][NT], float* res, int res_nt,
+                                                        float (&part)[MT][D][NT], float* res, int res_nt,
                                                         int res_t0, int wave, int lane) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) stash_tile(lds, wave * MT + mt, part[mt], lane);
+    __syncthreads();
+    sum_tiles(lds, par, depth, res, res_nt, res_t0);
+  }
+
+  // M-tile mtg's output partial sums, summed over the lane groups, into the
+  // reduction area (the activation region, once every wave has read it).
+  static __device__ __forceinline__ void stash_tile(char* lds, int mtg, float (&pt)[D][NT], int lane) {
     const int g = lane >> 4, j = lane & 15;
+    float* red = reinterpret_cast<float*>(lds);
 #pragma unroll
     for (int oo = 0; oo < D; ++oo)
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        float s = part[oo][t];
+        float s = pt[oo][t];
         s += __shfl_xor(s, 16);
         s += __shfl_xor(s, 32);
-        part[oo][t] = s;
+        if (g == 0) red[((mtg * D + oo) * NT + t) * PT + j] = s;
       }
-    float* red = reinterpret_cast<float*>(lds);
-    if (g == 0) {
-#pragma unroll
-      for (int oo = 0; oo < D; ++oo)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) red[((wave * D + oo) * NT + t) * PT + j] = part[oo][t];
-    }
-    __syncthreads();
+  }
+
+  // The outputs from the stashed tiles (after a barrier), in tile order
+  // (NSL slots: the M-tiles, or fewer slots that each hold a wave's tiles).
+  template <int NSL = MTILES>
+  static __device__ __forceinline__ void sum_tiles(const char* lds, const float* par, int depth, float* res,
+                                                   int res_nt, int res_t0) {
+    const float* red = reinterpret_cast<const float*>(lds);
     const float* bout = par + PC::BOUT(depth);
     for (int i = threadIdx.x; i < D * NT * PT; i += THREADS) {
       const int oo = i / (NT * PT);
       const int t = (i / PT) % NT;
       float s = C::kind(t % CC) == CK_VAL ? bout[oo] : 0.0f;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) s += red[w * D * NT * PT + i];
+      for (int tl = 0; tl < NSL; ++tl) s += red[tl * D * NT * PT + i];
       res[(oo * res_nt + res_t0 + t) * PT + (i % PT)] = s;
     }
     __syncthreads();
@@ -712,37 +732,43 @@ struct Engine {
 };
 
 // ---------------------------------------------------------------------------
-// Value, x tangents and Laplacian by forward mode, the latent Jacobian by
-// one reverse (adjoint) pass per output instead of R forward tangent
-// columns.  The latent Jacobian is the chain rule through the layers (Sec.
-// "Network Inversion" uses dg/dq), accumulated from the output back: with
-// s1_l = act'(z_l) at every layer,
-//   dz_L = s1_L * Wout[o],   dz_{l-1} = s1_{l-1} * (W_l^T dz_l),
+// Forward columns CF (value with x tangents and Laplacian, or value with
+// trial differences) and the latent Jacobian by one reverse (adjoint) pass
+// per output instead of R forward tangent columns.  The latent Jacobian is
+// the chain rule through the layers (Sec. "Network Inversion" uses dg/dq),
+// accumulated from the output back: with s_l the tangent slope act'(z_l)
+// of every layer (at the trial latent when CF has difference columns),
+//   dz_L = s_L * Wout[o],   dz_{l-1} = s_{l-1} * (W_l^T dz_l),
 //   dg_o/dq_k = sum_u W1[u][m + k] dz_0[u],
 // the same products the forward tangent columns form, associated the other
-// way.  The forward pass keeps each layer's s1 in registers, so depth is
+// way.  The forward pass keeps each layer's slope in registers, so depth is
 // bounded by DMAX; the adjoint columns take the arithmetic of latent-tangent
 // columns (plain bfloat16 in BF16, split in BF16X3) and the transposed
 // weight fragments that crom_net_pack writes after the layers.  Outputs
-// res[D][NTO][16] in the column order of Cols<m, r, 1, 0, true, D2_LAP, r>:
-// value, x tangents, Laplacian, dg/dq_0 .. dg/dq_{r-1}.
+// res[D][NTO][16] in the column order of CF with the R latent-tangent
+// columns appended (CO).
 // ---------------------------------------------------------------------------
 #ifndef CROM_REV_DMAX
 #define CROM_REV_DMAX 6
 #endif
-template <class S, int NW, int PREC, int PF, int DMAX = CROM_REV_DMAX>
+// CANON: output and Jacobian sums per M-tile in tile order, so results do
+// not depend on the wave count (kernels of different wave counts then agree
+// bit for bit); else per wave, one sum less deep.
+template <class S, class CF_, int NW, int PREC, int PF, bool CANON = true, int DMAX = CROM_REV_DMAX>
 struct RevJets {
   static constexpr int W = S::W, M = S::M, R = S::R, D = S::D;
-  using CF = Cols<M, R, 1, 0, true, D2_LAP, 0>;  // value, x tangents, Laplacian
+  using CF = CF_;
+  static_assert(CF::NV == 1 && CF::NQ == 0, "one value column, no forward tangent columns");
   using CB = Cols<M, R, 0, 0, false, D2_NONE, D>;  // one adjoint column per output
-  using CO = Cols<M, R, 1, 0, true, D2_LAP, R>;  // the output columns
+  using CO = Cols<M, R, CF::NV, CF::ND, (CF::NX > 0), CF::D2, R>;  // the output columns
   using EF = Engine<S, CF, 1, NW, PREC, PF>;
   using EB = Engine<S, CB, 1, NW, PREC, PF>;
   using PC = ParamCache<S>;
   static constexpr int MT = EF::MT, NTF = CF::C, NTO = CO::C, THREADS = NW * 64;
+  static constexpr int NSLOT = CANON ? S::MTILES : NW;  // partial-sum slots
   static_assert(NTF == CO::Q0, "forward columns precede the Jacobian columns");
   static_assert(EB::ACT_BYTES <= EF::ACT_REGION, "the adjoint tiles fit the activation region");
-  static_assert(NW * D * R * PT * 4 <= EF::ACT_REGION, "the Jacobian reduction fits the activation region");
+  static_assert(S::MTILES * D * R * PT * 4 <= EF::ACT_REGION, "the Jacobian reduction fits the activation region");
   static constexpr int RES_OFF = EF::LDS_BYTES;
   static constexpr int LDS_BYTES = RES_OFF + D * NTO * PT * 4;  // without the parameter cache
   static __host__ __device__ constexpr bool supported(int depth) { return depth >= 2 && depth <= DMAX; }
@@ -780,9 +806,11 @@ struct RevJets {
     return p;
   }
 
+  // lat: the value column's latent; dlat: the difference columns' latents
+  // relative to it (ND of them, stride R).  FP64.
   static __device__ void stage(char* lds, const float* __restrict__ x, int64_t first, int n_valid,
-                               const double* __restrict__ lat, const float* par) {
-    EF::stage(lds, x, first, n_valid, lat, R, nullptr, 0, par);
+                               const double* __restrict__ lat, const double* __restrict__ dlat, const float* par) {
+    EF::stage(lds, x, first, n_valid, lat, R, dlat, R, par);
   }
 
   static __device__ void run(char* lds, const float* par, const char* __restrict__ packed, int depth) {
@@ -791,15 +819,18 @@ struct RevJets {
     const float* W1 = par + PC::W1(0);
     const float* Wout = par + PC::WOUT(depth);
     Slopes sl;  // slope of layer l at this lane's (unit, point) entries
-    float part[D][NTF];
+    float part[MT][D][NTF];  // output sums per tile (first_layer's are unused: depth >= 2)
 #pragma unroll
-    for (int oo = 0; oo < D; ++oo)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int t = 0; t < NTF; ++t) part[oo][t] = 0.0f;
+      for (int oo = 0; oo < D; ++oo)
+#pragma unroll
+        for (int t = 0; t < NTF; ++t) part[mt][oo][t] = 0.0f;
 
-    // ---- forward: layer 1 on the VALU, then the hidden layers
-    typename EF::Frags ff;
-    if constexpr (!EF::STREAM) EF::load_frags(ff, packed, 0, wave, lane);
+    // ---- forward: layer 1 on the VALU, then the hidden layers (held
+    // fragments alternate between two buffers when prefetching)
+    typename EF::Frags ff[2];
+    if constexpr (!EF::STREAM) EF::load_frags(ff[0], layer_base(packed, 0), 0, wave, lane);
     {
       float s0[MT][4];
       EF::first_layer(lds, par, depth, 0, part, wave, lane, s0);
@@ -809,11 +840,14 @@ struct RevJets {
 #pragma unroll
     for (int l = 1; l < DMAX; ++l) {
       if (l < depth) {
-        if constexpr (!EF::STREAM) {
-          if (l > 1) EF::load_frags(ff, packed, l - 1, wave, lane);
+        const int cur = EF::PREFETCH ? (l - 1) & 1 : 0;
+        if constexpr (EF::PREFETCH) {
+          if (l + 1 < depth) EF::load_frags(ff[l & 1], layer_base(packed, l), 0, wave, lane);
+        } else if constexpr (!EF::STREAM) {
+          if (l > 1) EF::load_frags(ff[0], layer_base(packed, l - 1), 0, wave, lane);
         }
         f32x4 acc[MT][NTF];
-        EF::products(lds, par + PC::BH(l - 1), layer_base(packed, l - 1), 0, ff, acc, wave, lane);
+        EF::products(lds, par + PC::BH(l - 1), layer_base(packed, l - 1), 0, ff[cur], acc, wave, lane);
         __syncthreads();  // every wave has read this layer's activations
         const bool last = l == depth - 1;
 #pragma unroll
@@ -822,15 +856,25 @@ struct RevJets {
           float sv[4];
           EF::epilogue_tile(acc[mt], sv);
           put(sl, l, mt, sv);
-          if (!last) EF::write_act(lds, mtg, lane, acc[mt]);
-          else EF::out_accum(part, acc[mt], Wout, mtg * 16 + g * 4);
+          if (!last) {
+            EF::write_act(lds, mtg, lane, acc[mt]);
+          } else if constexpr (CANON) {  // the activations have been read: stash this tile's sums now
+            EF::out_accum(part[mt], acc[mt], Wout, mtg * 16 + g * 4);
+            EF::stash_tile(lds, mtg, part[mt], lane);
+          } else {
+            EF::out_accum(part[0], acc[mt], Wout, mtg * 16 + g * 4);  // the wave's tiles into one sum
+          }
         }
         __syncthreads();
       }
     }
-    EF::reduce_outputs(lds, par, depth, part, res, NTO, 0, wave, lane);
+    if constexpr (!CANON) {
+      EF::stash_tile(lds, wave, part[0], lane);
+      __syncthreads();
+    }
+    EF::template sum_tiles<NSLOT>(lds, par, depth, res, NTO, 0);
 
-    // ---- adjoint of the last hidden layer's pre-activation: s1_L * Wout[o]
+    // ---- adjoint of the last hidden layer's pre-activation: s_L * Wout[o]
 #pragma unroll
     for (int l = 1; l < DMAX; ++l) {
       if (l == depth - 1) {
@@ -851,18 +895,25 @@ struct RevJets {
     // ---- back through the hidden layers (transposed fragments), then W1's
     // latent columns
     const char* packed_t = packed + (size_t)(depth - 1) * Packing<S, PREC>::LAYER_BYTES;
-    float jp[D][R];
+    float* red = reinterpret_cast<float*>(lds);
+    float jp[D][R];  // Jacobian sums: of the tile (CANON) or of the wave's tiles
 #pragma unroll
     for (int oo = 0; oo < D; ++oo)
 #pragma unroll
       for (int k = 0; k < R; ++k) jp[oo][k] = 0.0f;
-    typename EB::Frags fb;
+    typename EB::Frags fb[2];
 #pragma unroll
     for (int l = DMAX - 1; l >= 1; --l) {
       if (l <= depth - 1) {
-        if constexpr (!EB::STREAM) EB::load_frags(fb, packed_t, l - 1, wave, lane);
+        const int cur = EB::PREFETCH ? (l - 1) & 1 : 0;
+        if constexpr (EB::PREFETCH) {
+          if (l == depth - 1) EB::load_frags(fb[(l - 1) & 1], layer_base(packed_t, l - 1), 0, wave, lane);
+          if (l > 1) EB::load_frags(fb[l & 1], layer_base(packed_t, l - 2), 0, wave, lane);
+        } else if constexpr (!EB::STREAM) {
+          EB::load_frags(fb[0], layer_base(packed_t, l - 1), 0, wave, lane);
+        }
         f32x4 acc[MT][D];
-        EB::products(lds, nullptr, layer_base(packed_t, l - 1), 0, fb, acc, wave, lane);
+        EB::products(lds, nullptr, layer_base(packed_t, l - 1), 0, fb[cur], acc, wave, lane);
         __syncthreads();  // every wave has read dz_l
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -874,6 +925,15 @@ struct RevJets {
           if (l > 1) {
             EB::write_act(lds, mtg, lane, acc[mt]);
           } else {
+            // this tile's share of the Jacobian; with CANON summed over its
+            // lane groups and stored at once for the sum over tiles (the
+            // activation region is free: every wave has read dz_1)
+            if constexpr (CANON) {
+#pragma unroll
+              for (int oo = 0; oo < D; ++oo)
+#pragma unroll
+                for (int k = 0; k < R; ++k) jp[oo][k] = 0.0f;
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const float* w1 = W1 + (mtg * 16 + g * 4 + v) * (M + R) + M;
@@ -884,13 +944,32 @@ struct RevJets {
                 for (int oo = 0; oo < D; ++oo) jp[oo][k] += w * acc[mt][oo][v];
               }
             }
+            if constexpr (CANON) stash_jac(red, mtg, jp, lane);
           }
         }
         __syncthreads();
       }
     }
+    if constexpr (!CANON) {
+      stash_jac(red, wave, jp, lane);
+      __syncthreads();
+    }
 
-    // ---- sum the Jacobian over lane groups and waves
+    // ---- the Jacobian: the slots' sums in slot order
+    for (int i = threadIdx.x; i < D * R * PT; i += THREADS) {
+      const int oo = i / (R * PT), k = (i / PT) % R;
+      float t = 0.0f;
+#pragma unroll
+      for (int tl = 0; tl < NSLOT; ++tl) t += red[tl * D * R * PT + i];
+      res[(oo * NTO + NTF + k) * PT + i % PT] = t;
+    }
+    __syncthreads();
+  }
+
+  // Jacobian sums of one slot, summed over the lane groups, into the
+  // reduction area.
+  static __device__ __forceinline__ void stash_jac(float* red, int slot, float (&jp)[D][R], int lane) {
+    const int g = lane >> 4, j = lane & 15;
 #pragma unroll
     for (int oo = 0; oo < D; ++oo)
 #pragma unroll
@@ -898,24 +977,8 @@ struct RevJets {
         float t = jp[oo][k];
         t += __shfl_xor(t, 16);
         t += __shfl_xor(t, 32);
-        jp[oo][k] = t;
+        if (g == 0) red[((slot * D + oo) * R + k) * PT + j] = t;
       }
-    float* red = reinterpret_cast<float*>(lds);
-    if (g == 0) {
-#pragma unroll
-      for (int oo = 0; oo < D; ++oo)
-#pragma unroll
-        for (int k = 0; k < R; ++k) red[((wave * D + oo) * R + k) * PT + j] = jp[oo][k];
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < D * R * PT; i += THREADS) {
-      const int oo = i / (R * PT), k = (i / PT) % R;
-      float t = 0.0f;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) t += red[w * D * R * PT + i];
-      res[(oo * NTO + NTF + k) * PT + i % PT] = t;
-    }
-    __syncthreads();
   }
 };
 

@@ -90,6 +90,12 @@
 #ifndef CROM_LIN_REV_WPE
 #define CROM_LIN_REV_WPE 3
 #endif
+// The Gauss-Newton round kernel holds three engines (the jets, the trial
+// with Jacobian, the objective alone): two waves per SIMD keep it free of
+// spills (three spill 80 registers).
+#ifndef CROM_GN_REV_WPE
+#define CROM_GN_REV_WPE 2
+#endif
 
 namespace crom {
 
@@ -106,6 +112,14 @@ constexpr int RMAX = 16;
 #define CROM_TRIALS 1
 #endif
 constexpr int TV = CROM_TRIALS;
+
+// The reverse-pass evaluations: value, x tangents and Laplacian (the
+// evaluation at q_n), and value with the trial differences (a trial round
+// that re-linearises), each with the latent Jacobian by the adjoint pass.
+template <class S, int NW, int PREC, int PF, bool CANON = true>
+using RevLap = RevJets<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, 0>, NW, PREC, PF, CANON>;
+template <class S, int NW, int PREC, int PF>
+using RevTrial = RevJets<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, 0>, NW, PREC, PF>;
 constexpr int MAXP = 256;    // bound on the phases of one step
 // Instance phases: the first evaluation at q_n; line-search trials along a
 // direction; re-linearisation at an accepted iterate; the evaluation of an
@@ -415,18 +429,21 @@ __device__ __forceinline__ void batch_partials(const double* jd, const double* r
 // ---------------------------------------------------------------------------
 // REV: the latent Jacobian by the reverse pass (RevJets, depth bounded),
 // else by forward tangent columns.
-template <class S, int NW, int PREC, int PF, bool REV = false>
+// CANON (with REV): sums independent of the wave count (the Gauss-Newton
+// kernels, whose round and persistent forms differ in waves); the
+// linearised kernel, alone in its form, sums per wave.
+template <class S, int NW, int PREC, int PF, bool REV = false, bool CANON = true>
 __device__ void eval_jets_batch(const StepArgs& a, char* lds, const float* par, int64_t blk) {
   constexpr int R = S::R;
   using C = Cols<S::M, R, 1, 0, true, D2_LAP, R>;
   using E = Engine<S, C, 1, NW, PREC, PF>;
-  using RJ = RevJets<S, NW, PREC, PF>;
+  using RJ = RevLap<S, NW, PREC, PF, CANON>;
   const int inst = wsp<int32_t>(a, a.L.blk_inst)[blk];
   const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
   const int64_t rem = a.offsets[inst + 1] - first;
   const int n_valid = rem < PT ? (int)rem : PT;
   if constexpr (REV) {
-    RJ::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * R, par);
+    RJ::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * R, nullptr, par);
     __syncthreads();
     RJ::run(lds, par, a.packed, a.depth);
   } else {
@@ -462,13 +479,17 @@ __device__ void eval_jets_batch(const StepArgs& a, char* lds, const float* par, 
 }
 
 // WITH_J: also the latent Jacobian at the first trial (else its partials
-// JᵀJ and Jᵀρ come out zero and only the trial objectives count).
-template <class S, int NW, int PREC, int PF, bool WITH_J = true>
+// JᵀJ and Jᵀρ come out zero and only the trial objectives count).  REV: that
+// Jacobian by the reverse pass (RevTrial, depth bounded).
+template <class S, int NW, int PREC, int PF, bool WITH_J = true, bool REV = false>
 __device__ void eval_trials_batch(const StepArgs& a, char* lds, const float* par, double* qdl,
                                   int64_t blk, int inst, int mb, bool have_qdl) {
   constexpr int R = S::R;
   using C = Cols<S::M, R, 1, TV, false, D2_NONE, WITH_J ? R : 0>;
   using E = Engine<S, C, 1, NW, PREC, PF>;
+  using RT = RevTrial<S, NW, PREC, PF>;
+  constexpr bool RV = REV && WITH_J;
+  static_assert(RT::CO::F0 == C::F0 && (!WITH_J || RT::CO::Q0 == C::Q0), "same output columns");
   const GNState* st = wsp<GNState>(a, a.L.state) + inst;
   if (mb >= 0) trace_mark(a, mb);
   if (!have_qdl) {
@@ -479,12 +500,19 @@ __device__ void eval_trials_batch(const StepArgs& a, char* lds, const float* par
   const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
   const int64_t rem = a.offsets[inst + 1] - first;
   const int n_valid = rem < PT ? (int)rem : PT;
-  E::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * R, R, qdl, R, par);
-  __syncthreads();
-  if (mb >= 0) trace_mark(a, mb + 2);
-  E::run(lds, par, a.packed, a.depth, 0);
+  if constexpr (RV) {
+    RT::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * R, qdl, par);
+    __syncthreads();
+    if (mb >= 0) trace_mark(a, mb + 2);
+    RT::run(lds, par, a.packed, a.depth);
+  } else {
+    E::stage(lds, a.y, first, n_valid, a.q_n + (int64_t)inst * R, R, qdl, R, par);
+    __syncthreads();
+    if (mb >= 0) trace_mark(a, mb + 2);
+    E::run(lds, par, a.packed, a.depth, 0);
+  }
   if (mb >= 0) trace_mark(a, mb + 3);
-  const float* res = reinterpret_cast<const float*>(lds + E::RES_OFF);
+  const float* res = reinterpret_cast<const float*>(lds + (RV ? RT::RES_OFF : E::RES_OFF));
   double* jd = reinterpret_cast<double*>(lds);
   double* rho = jd + PT * R;
   const double* rho0 = wsp<double>(a, a.L.rho0);
@@ -1432,13 +1460,28 @@ constexpr int64_t SPIN_MAX = int64_t(1) << 21;  // bounded waits: ~2e6 polls of 
 // engines' activation regions share the start of the dynamic LDS; the
 // elastic kind keeps its J rows and residuals (FP64) above them; the
 // parameter cache comes last, at PAR.
-template <class S, int NW, int PREC, int PF, int KIND>
+template <class S, int NW, int PREC, int PF, int KIND, bool REV = false>
 struct StepTraits {
   using E0 = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC, PF>;
   using E1 = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, S::R>, 1, NW, PREC, PF>;
   static constexpr int ENG = E0::LDS_BYTES > E1::LDS_BYTES ? E0::LDS_BYTES : E1::LDS_BYTES;
   static constexpr int JD_OFF = ENG;
   static constexpr int PAR = ENG;
+  static constexpr int STAGE = E0::ACT_REGION < E1::ACT_REGION ? E0::ACT_REGION : E1::ACT_REGION;
+};
+// The heat step with the reverse-pass evaluations: the jets at q_n, the
+// trial rounds that re-linearise, and the backtracking rounds' objective.
+template <class S, int NW, int PREC, int PF>
+struct StepTraits<S, NW, PREC, PF, PK_HEAT, true> {
+  using E0 = RevLap<S, NW, PREC, PF>;
+  using E1 = RevTrial<S, NW, PREC, PF>;
+  using E2 = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, 0>, 1, NW, PREC, PF>;
+  static constexpr int ENG01 = E0::LDS_BYTES > E1::LDS_BYTES ? E0::LDS_BYTES : E1::LDS_BYTES;
+  static constexpr int ENG = ENG01 > E2::LDS_BYTES ? ENG01 : E2::LDS_BYTES;
+  static constexpr int JD_OFF = ENG;
+  static constexpr int PAR = ENG;
+  static constexpr int STAGE0 = E0::EF::ACT_REGION < E1::EF::ACT_REGION ? E0::EF::ACT_REGION : E1::EF::ACT_REGION;
+  static constexpr int STAGE = STAGE0 < E2::ACT_REGION ? STAGE0 : E2::ACT_REGION;
 };
 template <class S, int NW, int PREC, int PF>
 struct StepTraits<S, NW, PREC, PF, PK_ELASTIC> {
@@ -1449,10 +1492,10 @@ struct StepTraits<S, NW, PREC, PF, PK_ELASTIC> {
   static constexpr int PAR = JD_OFF + PT * S::D * (S::R + TV) * 8;
 };
 
-template <class S, int NW, int PREC, int PF, int KIND, int WPE>
+template <class S, int NW, int PREC, int PF, int KIND, int WPE, bool REV>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void step_kernel(StepArgs a,
                                                                                           int max_rounds) {
-  using T = StepTraits<S, NW, PREC, PF, KIND>;
+  using T = StepTraits<S, NW, PREC, PF, KIND, REV>;
   constexpr int PAR = T::PAR;
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_last, s_abort, s_ph, s_lt;
@@ -1500,7 +1543,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       const int ch = (int)(w % NCH);
       const int inst = blk_inst[blk];
       if (p == 0) {
-        if constexpr (KIND == PK_HEAT) eval_jets_batch<S, NW, PREC, PF>(a, lds, par, blk);
+        if constexpr (KIND == PK_HEAT) eval_jets_batch<S, NW, PREC, PF, REV>(a, lds, par, blk);
         else if (ch == 0) eval_init_elastic<S>(a, jd, blk);
         else continue;
       } else {
@@ -1518,7 +1561,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
         }
         if (!evaluates_trials(ph)) continue;
         if constexpr (KIND == PK_HEAT)
-          eval_trials_batch<S, NW, PREC, PF>(a, lds, par, qdl, blk, inst, (p == 1 && first) ? 40 : -1, first);
+          eval_trials_batch<S, NW, PREC, PF, true, REV>(a, lds, par, qdl, blk, inst, (p == 1 && first) ? 40 : -1,
+                                                        first);
         else {  // backtracking rounds evaluate the objective only (the solve re-linearises)
           const bool with_j = !(ph == PH_TRIALS && lt > 0);
           if (!eval_trials_elastic<S, NW, PREC, PF>(a, lds, jd, par, qdl, blk, ch, inst, first, with_j)) continue;
@@ -1587,7 +1631,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
 template <class S, int NW, int PREC, int PF, int WPE, bool REV>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void lls_jets_kernel(StepArgs a) {
   using E = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC, PF>;
-  constexpr int ENG = REV ? RevJets<S, NW, PREC, PF>::LDS_BYTES : E::LDS_BYTES;
+  constexpr int ENG = REV ? RevLap<S, NW, PREC, PF, false>::LDS_BYTES : E::LDS_BYTES;
   extern __shared__ __align__(16) char lds[];
   const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
   if ((int64_t)blockIdx.x >= nblk) return;
@@ -1595,7 +1639,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
   E::PC::load(par, a.params, a.pi, a.depth, NW * 64);
   __syncthreads();
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x)
-    eval_jets_batch<S, NW, PREC, PF, REV>(a, lds, par, blk);
+    eval_jets_batch<S, NW, PREC, PF, REV, false>(a, lds, par, blk);
 }
 
 // The instance's batch partials are summed by the whole workgroup: entry e
@@ -1678,7 +1722,7 @@ __global__ __launch_bounds__(LLS_SOLVE_THREADS) void lls_solve_kernel(StepArgs a
 template <class S, int NW, int PREC, int PF, int WPE, int WPE_REV = WPE>
 static crom_status launch_lls(StepArgs a, hipStream_t st) {
   using E = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC, PF>;
-  using RJ = RevJets<S, NW, PREC, PF>;
+  using RJ = RevLap<S, NW, PREC, PF, false>;
   const bool rev = CROM_LLS_REV && RJ::supported(a.depth);
   const int lds_bytes = (rev ? RJ::LDS_BYTES : E::LDS_BYTES) + E::PC::bytes(a.depth);
   if (lds_bytes > LDS_MAX) return fail(CROM_ERR_UNSUPPORTED, "network too deep for the LDS");
@@ -1711,10 +1755,10 @@ static crom_status launch_lls(StepArgs a, hipStream_t st) {
 // persistent kernel, so every instance gets the same bits on either path.
 // Rounds without an active instance return at once.
 // ---------------------------------------------------------------------------
-template <class S, int NW, int PREC, int PF, int WPE>
+template <class S, int NW, int PREC, int PF, int WPE, bool REV>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void gn_round_kernel(StepArgs a,
                                                                                               int p) {
-  using T = StepTraits<S, NW, PREC, PF, PK_HEAT>;
+  using T = StepTraits<S, NW, PREC, PF, PK_HEAT, REV>;
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_ph, s_lt;
   __shared__ double qdl[TV * RMAX];
@@ -1737,7 +1781,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
     const int64_t blk = p == 0 ? it : (int64_t)list[it];
     const int inst = blk_inst[blk];
     if (p == 0) {
-      eval_jets_batch<S, NW, PREC, PF>(a, lds, par, blk);
+      eval_jets_batch<S, NW, PREC, PF, REV>(a, lds, par, blk);
     } else {
       if (threadIdx.x == 0) {
         s_ph = ld_c(&state[inst].phase);
@@ -1752,7 +1796,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       if (ph == PH_TRIALS && lt > 0)
         eval_trials_batch<S, NW, PREC, PF, false>(a, lds, par, qdl, blk, inst, -1, false);
       else
-        eval_trials_batch<S, NW, PREC, PF, true>(a, lds, par, qdl, blk, inst, -1, false);
+        eval_trials_batch<S, NW, PREC, PF, true, REV>(a, lds, par, qdl, blk, inst, -1, false);
     }
   }
 }
@@ -1782,17 +1826,21 @@ __global__ __launch_bounds__(NTH) void gn_solve_kernel(StepArgs a, int p, int is
   for (int32_t i = threadIdx.x; i < b1 - b0; i += blockDim.x) list[s_base + i] = b0 + i;
 }
 
-template <class S, int NW, int PREC, int PF, int WPE>
-static crom_status launch_gn_rounds(StepArgs a, int max_rounds, hipStream_t st) {
-  using T = StepTraits<S, NW, PREC, PF, PK_HEAT>;
+// NWS: the waves of the persistent kernel whose solve the rounds repeat (its
+// thread count fixes the solve's summation order), independent of the
+// evaluation's NW: the evaluations' results do not depend on the wave count.
+template <class S, int NW, int PREC, int PF, int WPE, bool REV, int NWS>
+static crom_status launch_gn_rounds_t(StepArgs a, int max_rounds, hipStream_t st) {
+  using T = StepTraits<S, NW, PREC, PF, PK_HEAT, REV>;
   const int lds_bytes = T::PAR + T::E0::PC::bytes(a.depth);
   if (lds_bytes + (int)sizeof(double) * TV * RMAX + 64 > LDS_MAX)
     return fail(CROM_ERR_UNSUPPORTED, "network too deep for the step kernel's LDS");
   constexpr int NRED = S::R * (S::R + 1) / 2 + S::R + TV;
   constexpr int SOLVE_LDS =
-      (int)((sizeof(GNState) + 15) / 16 * 16) + ((NW * 64) / NRED + 1) * NRED * 8 + 64;
-  auto kr = gn_round_kernel<S, NW, PREC, PF, WPE>;
-  auto ks = gn_solve_kernel<S::R, NW * 64>;
+      (int)((sizeof(GNState) + 15) / 16 * 16) + ((NWS * 64) / NRED + 1) * NRED * 8 + 64;
+  static_assert(PT * S::R * 8 + PT * TV * 8 <= T::STAGE, "staging fits");
+  auto kr = gn_round_kernel<S, NW, PREC, PF, WPE, REV>;
+  auto ks = gn_solve_kernel<S::R, NWS * 64>;
   crom_status s = set_lds(kr, lds_bytes);
   if (s != CROM_OK) return s;
   hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(SETUP_THREADS), 0, st, a);
@@ -1803,10 +1851,21 @@ static crom_status launch_gn_rounds(StepArgs a, int max_rounds, hipStream_t st) 
   timer_mark(st);
   for (int p = 0; p <= max_rounds; ++p) {
     hipLaunchKernelGGL(kr, dim3((unsigned)g), dim3(NW * 64), lds_bytes, st, a, p);
-    hipLaunchKernelGGL(ks, dim3((unsigned)a.n_inst), dim3(NW * 64), SOLVE_LDS, st, a, p, (int)(p == max_rounds));
+    hipLaunchKernelGGL(ks, dim3((unsigned)a.n_inst), dim3(NWS * 64), SOLVE_LDS, st, a, p, (int)(p == max_rounds));
   }
   timer_mark(st);
   return hip_check(hipGetLastError(), "round launches");
+}
+
+// The Gauss-Newton evaluations take the reverse pass where the depth allows.
+#ifndef CROM_GN_REV
+#define CROM_GN_REV 1
+#endif
+template <class S, int NW, int PREC, int PF, int WPE, int WPE_REV, int NWS>
+static crom_status launch_gn_rounds(StepArgs a, int max_rounds, hipStream_t st) {
+  if (CROM_GN_REV && RevLap<S, NW, PREC, PF>::supported(a.depth))
+    return launch_gn_rounds_t<S, NW, PREC, PF, WPE_REV, true, NWS>(a, max_rounds, st);
+  return launch_gn_rounds_t<S, NW, PREC, PF, WPE, false, NWS>(a, max_rounds, st);
 }
 
 // One engine pass of the elastic preparation over every batch.
@@ -1873,22 +1932,19 @@ static crom_status fe_prepare(const StepArgs& a, hipStream_t st) {
   return hip_check(hipGetLastError(), "finite-element targets launch");
 }
 
-template <class S, int NW, int PREC, int PF, int KIND = PK_HEAT, int WPE = 1>
-static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
-  using T = StepTraits<S, NW, PREC, PF, KIND>;
+template <class S, int NW, int PREC, int PF, int KIND, int WPE, bool REV>
+static crom_status launch_step_t(StepArgs a, int max_rounds, hipStream_t st) {
+  using T = StepTraits<S, NW, PREC, PF, KIND, REV>;
   constexpr int PAR = T::PAR;
   const int lds_bytes = PAR + T::E0::PC::bytes(a.depth);
   if (lds_bytes + (int)sizeof(double) * TV * RMAX + 64 > LDS_MAX)
     return fail(CROM_ERR_UNSUPPORTED, "network too deep for the step kernel's LDS");
-  if constexpr (KIND == PK_HEAT) {
-    static_assert(PT * S::R * 8 + PT * TV * 8 <= T::E0::ACT_REGION, "staging fits");
-    static_assert(PT * S::R * 8 + PT * TV * 8 <= T::E1::ACT_REGION, "staging fits");
-  }
+  if constexpr (KIND == PK_HEAT) static_assert(PT * S::R * 8 + PT * TV * 8 <= T::STAGE, "staging fits");
   static_assert(sizeof(GNState) + 16 +
                     (NW * 64 + S::R * (S::R + 1) / 2 + S::R + TV + S::R * S::R + S::R) * 8 <= PAR,
                 "solve scratch fits below the parameter cache");
   static_assert(NW * 64 >= S::R * (S::R + 1) / 2 + S::R + TV, "one thread per reduced entry");
-  auto k = step_kernel<S, NW, PREC, PF, KIND, WPE>;
+  auto k = step_kernel<S, NW, PREC, PF, KIND, WPE, REV>;
   static int resident = 0, resident_lds = -1;
   if (resident_lds != lds_bytes) {
     crom_status s = set_lds(k, LDS_MAX - (int)sizeof(double) * TV * RMAX - 64);
@@ -1922,6 +1978,15 @@ static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
   return s;
 }
 
+template <class S, int NW, int PREC, int PF, int KIND = PK_HEAT, int WPE = 1>
+static crom_status launch_step(StepArgs a, int max_rounds, hipStream_t st) {
+  if constexpr (KIND == PK_HEAT) {
+    if (CROM_GN_REV && RevLap<S, NW, PREC, PF>::supported(a.depth))
+      return launch_step_t<S, NW, PREC, PF, KIND, WPE, true>(a, max_rounds, st);
+  }
+  return launch_step_t<S, NW, PREC, PF, KIND, WPE, false>(a, max_rounds, st);
+}
+
 // Waves per workgroup and weight prefetch per precision, chosen so that the
 // persistent kernel stays clear of register spills: bfloat16 fragments are
 // half the size, so BF16 and BF16_PURE afford eight waves with prefetch.
@@ -1931,7 +1996,7 @@ static crom_status step_prec(int prec, const StepArgs& a, int rounds, hipStream_
   constexpr bool ALL = S::ACT == ACT_ELU;
   if (a.linearized) {
     // four waves with two M-tiles each and streamed weights: the measured
-    // best for the 12-column engine (two workgroups per CU)
+    // best for full batches (three workgroups per CU with the reverse pass)
     constexpr int NWL = S::MTILES < CROM_LIN_NW ? S::MTILES : CROM_LIN_NW;
     if (prec == CROM_PREC_FP32) return launch_lls<S, NWF, PREC_FP32, 0, 1>(a, st);
     if (prec == CROM_PREC_BF16) return launch_lls<S, NWL, PREC_BF16, CROM_LIN_PF, CROM_LIN_WPE, CROM_LIN_REV_WPE>(a, st);
@@ -1943,11 +2008,17 @@ static crom_status step_prec(int prec, const StepArgs& a, int rounds, hipStream_
     return fail(CROM_ERR_UNSUPPORTED, "precision");
   }
   if (a.L.nblk_max > ROUNDS_MIN_BATCHES) {
-    if (prec == CROM_PREC_FP32) return launch_gn_rounds<S, NWF, PREC_FP32, 0, 1>(a, rounds, st);
-    if (prec == CROM_PREC_BF16) return launch_gn_rounds<S, NWB, PREC_BF16, PFB, WPEB>(a, rounds, st);
+    // the evaluations in the linearised step's configuration (the fastest
+    // for full batches), the solves with the persistent kernel's threads
+    constexpr int NWL = S::MTILES < CROM_LIN_NW ? S::MTILES : CROM_LIN_NW;
+    if (prec == CROM_PREC_FP32) return launch_gn_rounds<S, NWF, PREC_FP32, 0, 1, 1, NWF>(a, rounds, st);
+    if (prec == CROM_PREC_BF16)
+      return launch_gn_rounds<S, NWL, PREC_BF16, CROM_LIN_PF, CROM_LIN_WPE, CROM_GN_REV_WPE, NWB>(a, rounds, st);
     if constexpr (ALL) {
-      if (prec == CROM_PREC_BF16_PURE) return launch_gn_rounds<S, NWB, PREC_BF16_PURE, PFB, WPEB>(a, rounds, st);
-      return launch_gn_rounds<S, NWF, PREC_BF16X3, 0, 1>(a, rounds, st);
+      if (prec == CROM_PREC_BF16_PURE)
+        return launch_gn_rounds<S, NWL, PREC_BF16_PURE, CROM_LIN_PF, CROM_LIN_WPE, CROM_GN_REV_WPE, NWB>(a, rounds,
+                                                                                                     st);
+      return launch_gn_rounds<S, NWF, PREC_BF16X3, 0, 1, 1, NWF>(a, rounds, st);
     }
     return fail(CROM_ERR_UNSUPPORTED, "precision");
   }

