@@ -213,8 +213,11 @@ struct ParamCache {
 // PF: 1 prefetches the next layer's weight fragments into a second register
 // set during this layer's products, 0 loads each layer's fragments when the
 // layer starts, 2 streams them one K-block ahead of their products, -1
-// chooses by a register estimate.
-template <class S, class C, int NB, int NW, int PREC, int PF = -1>
+// chooses by a register estimate.  CANON: the output layer's partial dot
+// products are summed per M-tile, the tiles in tile order, so that results
+// do not depend on the wave count; else per wave (the wave's tiles in one
+// running sum, then the waves in order).
+template <class S, class C, int NB, int NW, int PREC, int PF = -1, bool CANON = false>
 struct Engine {
   static constexpr int W = S::W, M = S::M, R = S::R, D = S::D;
   static constexpr int CC = C::C;
@@ -229,7 +232,8 @@ struct Engine {
   static constexpr int KQ = Packing<S, PREC>::KQ;
   static constexpr int NACT = NT + NSPL;
   static constexpr int ACT_BYTES = NACT * KQ * 64 * 16;
-  static constexpr int RED_BYTES = MTILES * D * NT * PT * 4;
+  static constexpr int NSLOT = CANON ? MTILES : NW;  // partial-sum slots of the output reduction
+  static constexpr int RED_BYTES = NSLOT * D * NT * PT * 4;
   static constexpr int ACT_REGION = ACT_BYTES > RED_BYTES ? ACT_BYTES : RED_BYTES;
   static constexpr int XS_OFF = ACT_REGION;
   static constexpr int NF = C::NV + C::ND;
@@ -481,7 +485,7 @@ struct Engine {
       const int mtg = wave * MT + mt;
       epilogue_tile(acc[mt]);
       if (!last) write_act(lds, mtg, lane, acc[mt]);
-      else out_accum(part[mt], acc[mt], Wout, mtg * 16 + g * 4);
+      else out_accum(part[CANON ? mt : 0], acc[mt], Wout, mtg * 16 + g * 4);
     }
     __syncthreads();
   }
@@ -675,25 +679,28 @@ struct Engine {
           for (int t = 0; t < NT; ++t) o4[t][v] = z[t];
         }
         if (depth > 1) write_act(lds, mtg, lane, o4);
-        else out_accum(part[mt], o4, Wout, mtg * 16 + g * 4);
+        else out_accum(part[CANON ? mt : 0], o4, Wout, mtg * 16 + g * 4);
       }
     }
     __syncthreads();
   }
 
   // ---- output layer: reduce the partial dot products ------------------------
-  // res[oo * res_nt + res_t0 + t][16] = bout (value columns) + the sum over
-  // the M-tiles, in tile order, of each tile's lane-group sum of
-  // part[mt][oo][t]: the same order for any number of waves, so results do
-  // not depend on how the tiles are spread over waves.  Reuses the
+  // res[oo * res_nt + res_t0 + t][16] = bout (value columns) + the slots'
+  // lane-group sums in slot order: with CANON one slot per M-tile (the same
+  // order for any number of waves), else one per wave.  Reuses the
   // activation region.
   static __device__ __forceinline__ void reduce_outputs(char* lds, const float* par, int depth,
                                                         float (&part)[MT][D][NT], float* res, int res_nt,
                                                         int res_t0, int wave, int lane) {
+    if constexpr (CANON) {
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) stash_tile(lds, wave * MT + mt, part[mt], lane);
+      for (int mt = 0; mt < MT; ++mt) stash_tile(lds, wave * MT + mt, part[mt], lane);
+    } else {
+      stash_tile(lds, wave, part[0], lane);  // the wave's running sum over its tiles
+    }
     __syncthreads();
-    sum_tiles(lds, par, depth, res, res_nt, res_t0);
+    sum_tiles<NSLOT>(lds, par, depth, res, res_nt, res_t0);
   }
 
   // M-tile mtg's output partial sums, summed over the lane groups, into the
@@ -714,7 +721,7 @@ struct Engine {
 
   // The outputs from the stashed tiles (after a barrier), in tile order
   // (NSL slots: the M-tiles, or fewer slots that each hold a wave's tiles).
-  template <int NSL = MTILES>
+  template <int NSL>
   static __device__ __forceinline__ void sum_tiles(const char* lds, const float* par, int depth, float* res,
                                                    int res_nt, int res_t0) {
     const float* red = reinterpret_cast<const float*>(lds);
@@ -761,8 +768,8 @@ struct RevJets {
   static_assert(CF::NV == 1 && CF::NQ == 0, "one value column, no forward tangent columns");
   using CB = Cols<M, R, 0, 0, false, D2_NONE, D>;  // one adjoint column per output
   using CO = Cols<M, R, CF::NV, CF::ND, (CF::NX > 0), CF::D2, R>;  // the output columns
-  using EF = Engine<S, CF, 1, NW, PREC, PF>;
-  using EB = Engine<S, CB, 1, NW, PREC, PF>;
+  using EF = Engine<S, CF, 1, NW, PREC, PF, CANON>;
+  using EB = Engine<S, CB, 1, NW, PREC, PF, CANON>;
   using PC = ParamCache<S>;
   static constexpr int MT = EF::MT, NTF = CF::C, NTO = CO::C, THREADS = NW * 64;
   static constexpr int NSLOT = CANON ? S::MTILES : NW;  // partial-sum slots

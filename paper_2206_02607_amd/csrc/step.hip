@@ -436,7 +436,7 @@ template <class S, int NW, int PREC, int PF, bool REV = false, bool CANON = true
 __device__ void eval_jets_batch(const StepArgs& a, char* lds, const float* par, int64_t blk) {
   constexpr int R = S::R;
   using C = Cols<S::M, R, 1, 0, true, D2_LAP, R>;
-  using E = Engine<S, C, 1, NW, PREC, PF>;
+  using E = Engine<S, C, 1, NW, PREC, PF, CANON>;
   using RJ = RevLap<S, NW, PREC, PF, CANON>;
   const int inst = wsp<int32_t>(a, a.L.blk_inst)[blk];
   const int64_t first = wsp<int64_t>(a, a.L.blk_start)[blk];
@@ -486,7 +486,7 @@ __device__ void eval_trials_batch(const StepArgs& a, char* lds, const float* par
                                   int64_t blk, int inst, int mb, bool have_qdl) {
   constexpr int R = S::R;
   using C = Cols<S::M, R, 1, TV, false, D2_NONE, WITH_J ? R : 0>;
-  using E = Engine<S, C, 1, NW, PREC, PF>;
+  using E = Engine<S, C, 1, NW, PREC, PF, true>;
   using RT = RevTrial<S, NW, PREC, PF>;
   constexpr bool RV = REV && WITH_J;
   static_assert(RT::CO::F0 == C::F0 && (!WITH_J || RT::CO::Q0 == C::Q0), "same output columns");
@@ -1462,8 +1462,8 @@ constexpr int64_t SPIN_MAX = int64_t(1) << 21;  // bounded waits: ~2e6 polls of 
 // parameter cache comes last, at PAR.
 template <class S, int NW, int PREC, int PF, int KIND, bool REV = false>
 struct StepTraits {
-  using E0 = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC, PF>;
-  using E1 = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, S::R>, 1, NW, PREC, PF>;
+  using E0 = Engine<S, Cols<S::M, S::R, 1, 0, true, D2_LAP, S::R>, 1, NW, PREC, PF, true>;
+  using E1 = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, S::R>, 1, NW, PREC, PF, true>;
   static constexpr int ENG = E0::LDS_BYTES > E1::LDS_BYTES ? E0::LDS_BYTES : E1::LDS_BYTES;
   static constexpr int JD_OFF = ENG;
   static constexpr int PAR = ENG;
@@ -1475,7 +1475,7 @@ template <class S, int NW, int PREC, int PF>
 struct StepTraits<S, NW, PREC, PF, PK_HEAT, true> {
   using E0 = RevLap<S, NW, PREC, PF>;
   using E1 = RevTrial<S, NW, PREC, PF>;
-  using E2 = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, 0>, 1, NW, PREC, PF>;
+  using E2 = Engine<S, Cols<S::M, S::R, 1, TV, false, D2_NONE, 0>, 1, NW, PREC, PF, true>;
   static constexpr int ENG01 = E0::LDS_BYTES > E1::LDS_BYTES ? E0::LDS_BYTES : E1::LDS_BYTES;
   static constexpr int ENG = ENG01 > E2::LDS_BYTES ? ENG01 : E2::LDS_BYTES;
   static constexpr int JD_OFF = ENG;
