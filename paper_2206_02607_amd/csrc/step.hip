@@ -284,8 +284,13 @@ __device__ __forceinline__ void trace_mark(const StepArgs& a, int slot) {
     if (blockIdx.x == gridDim.x - 1) a.trace[64 + slot] = wall_clock64();
   }
 }
+// marks of the solve, from whichever workgroup runs it
+__device__ __forceinline__ void trace_solve(const StepArgs& a, int slot) {
+  if (a.trace && threadIdx.x == 0 && slot < 64) a.trace[slot] = wall_clock64();
+}
 #else
 __device__ __forceinline__ void trace_mark(const StepArgs&, int) {}
+__device__ __forceinline__ void trace_solve(const StepArgs&, int) {}
 #endif
 
 // ---------------------------------------------------------------------------
@@ -1054,13 +1059,31 @@ struct WaveMat {
 // For r <= 8 every lane factors the whole matrix in registers from LDS
 // reads at uniform addresses (no cross-lane traffic), left-looking: column
 // j's pivot and entries subtract the earlier columns' products in the same
-// order as the right-looking updates, and the substitutions divide by the
-// same diagonal, so both forms give the same bits.  Not inlined: its 36
-// register-held entries then do not add to the registers live at the call.
+// order as the right-looking updates.  Not inlined: its 36 register-held
+// entries then do not add to the registers live at the call.  Every lane
+// holds the whole solution, so it also returns |x|^2 and b.x (the same in
+// every lane), which the caller would otherwise sum across lanes.
 struct CholOut {
-  double x;
+  double x, xx, bx;
   int ok;
 };
+// sqrt(d) and 1/sqrt(d) for d > 0: the hardware reciprocal square root
+// estimate refined by two Newton steps, y <- y (3/2 - d/2 y^2), each of
+// which doubles the correct bits (full double precision after two), and
+// one Newton step on the square root, s <- s + y/2 (d - s^2).  Both within
+// an ulp of the correctly rounded values, in a dependent chain of 9
+// operations instead of the IEEE square root and division sequences.
+__device__ __forceinline__ void sqrt_rsqrt(double d, double& s, double& y) {
+  y = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+  double t = fma(-h * y, y, 0.5);
+  y = fma(y, t, y);
+  t = fma(-h * y, y, 0.5);
+  y = fma(y, t, y);
+  s = d * y;
+  s = fma(0.5 * y, fma(-s, s, d), s);
+}
+
 template <int R>
 __device__ __attribute__((noinline)) CholOut lane_chol_solve(const double* up, const double* b) {
   const int lane = threadIdx.x & 63;
@@ -1075,21 +1098,22 @@ __device__ __attribute__((noinline)) CholOut lane_chol_solve(const double* up, c
       if (i == k) dmax = fmax(dmax, v);
     }
   const double thresh = 1e-14 * dmax;
+  double inv[R];  // 1 / L_jj: one division per column, reused by both substitutions
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     double d = L[j][j];
 #pragma unroll
     for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
-    if (!(isfinite(d) && d > thresh)) return CholOut{0.0, 0};  // uniform across the wave
-    const double ljj = sqrt(d);
-    const double inv = 1.0 / ljj;
+    if (!(isfinite(d) && d > thresh)) return CholOut{0.0, 0.0, 0.0, 0};  // uniform across the wave
+    double ljj;
+    sqrt_rsqrt(d, ljj, inv[j]);
     L[j][j] = ljj;
 #pragma unroll
     for (int i = j + 1; i < R; ++i) {
       double v = L[i][j];
 #pragma unroll
       for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
-      L[i][j] = v * inv;
+      L[i][j] = v * inv[j];
     }
   }
   double y[R];
@@ -1097,20 +1121,24 @@ __device__ __attribute__((noinline)) CholOut lane_chol_solve(const double* up, c
   for (int i = 0; i < R; ++i) y[i] = b[i];
 #pragma unroll
   for (int j = 0; j < R; ++j) {  // L y = b
-    y[j] = y[j] / L[j][j];
+    y[j] = y[j] * inv[j];
 #pragma unroll
     for (int i = j + 1; i < R; ++i) y[i] -= L[i][j] * y[j];
   }
 #pragma unroll
   for (int j = R - 1; j >= 0; --j) {  // L^T x = y
-    y[j] = y[j] / L[j][j];
+    y[j] = y[j] * inv[j];
 #pragma unroll
     for (int i = 0; i < j; ++i) y[i] -= L[j][i] * y[j];
   }
-  double x = 0.0;
+  double x = 0.0, xx = 0.0, bx = 0.0;
 #pragma unroll
-  for (int k = 0; k < R; ++k) x = lane == k ? y[k] : x;
-  return CholOut{x, 1};
+  for (int k = 0; k < R; ++k) {
+    x = lane == k ? y[k] : x;
+    xx += y[k] * y[k];
+    bx += b[k] * y[k];
+  }
+  return CholOut{x, xx, bx, 1};
 }
 
 template <int R>
@@ -1217,6 +1245,9 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
   // issued before the first wait (one memory round trip, not two).
   const int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
   const int32_t b0 = first_blk[inst], b1 = first_blk[inst + 1];
+  // wave 0's lanes k < R take q_n[k] for the trial latents: issued here, so
+  // its latency overlaps the partials' loads
+  const double qn_lane = (threadIdx.x < R) ? a.q_n[(int64_t)inst * R + threadIdx.x] : 0.0;
   if (p == 0) {  // the state before the first solve, formed from q_n
     for (int w = threadIdx.x; w < NWORD; w += nth)
       reinterpret_cast<uint64_t*>(st)[w] = gn_initial_word(w, a.q_n + (int64_t)inst * R, R, false);
@@ -1241,6 +1272,7 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
     sub[sl * NRED + e] = acc;
   }
   __syncthreads();
+  if (p == 1) trace_solve(a, 48);
   const int phase = st->phase;
   if (threadIdx.x < NRED) {
     double s = 0.0;
@@ -1248,10 +1280,10 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
     red[threadIdx.x] = s;
   }
   __syncthreads();
+  if (p == 1) trace_solve(a, 49);
 
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
-    const double* qn0 = a.q_n + (int64_t)inst * R;
     const double* bv = red + NA;
     const double* phit = red + NA + R;
     // scalar state (identical in every lane)
@@ -1264,6 +1296,7 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
     // vectors: lane k < R holds entry k
     double qk = lane < R ? st->q[lane] : 0.0;
     double dk = lane < R ? st->delta[lane] : 0.0;
+    const double* qv = st->q;  // the current iterate, readable by every lane
     bool done = false, newdir = false;
     // 1: trials q + alpha_t delta; 2: every trial at q (re-linearise);
     // 3: every trial at the initial guess
@@ -1281,6 +1314,7 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
       // direction found at q_n (kept in the state) goes ahead.
       if (isfinite(phit[0]) && phit[0] < phi) {
         qk = lane < R ? st->qt[0][lane] : 0.0;
+        qv = st->qt[0];
         phi = phit[0];
         obj_last = phi;
         newdir = true;
@@ -1313,9 +1347,15 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
           settrials = 1;
         }
       } else {
-        double qq = qk * qk;
+        double qq = 0.0;
+        if constexpr (R <= 8) {  // the vector from LDS at uniform addresses: no cross-lane rounds
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) qq += __shfl_xor(qq, o);
+          for (int k = 0; k < R; ++k) qq += qv[k] * qv[k];
+        } else {
+          qq = qk * qk;
+#pragma unroll
+          for (int o = 32; o >= 1; o >>= 1) qq += __shfl_xor(qq, o);
+        }
         const double step = alpha[acc] * dnorm;
         qk = lane < R ? st->qt[acc][lane] : 0.0;
         iters += 1;
@@ -1337,6 +1377,7 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
       newdir = true;
     }
 
+    if (p == 1) trace_solve(a, 53);
     if (newdir) {
       bool finite = isfinite(phi);
       for (int e = 0; e < NA + R; ++e) finite &= (bool)isfinite(red[e]);
@@ -1344,18 +1385,34 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
         flags |= CROM_FLAG_NONFINITE;
         done = true;
       } else {
-        double xk = 0.0;
-        if (!wave_chol_solve<R>(red, bv, xk)) {
+        double xk = 0.0, dn = 0.0, qq = 0.0, sl = 0.0;
+        bool ok;
+        if constexpr (R <= 8) {
+          const CholOut o = lane_chol_solve<R>(red, bv);
+          ok = o.ok != 0;
+          xk = o.x;
+          dn = o.xx;
+          sl = o.bx;
+#pragma unroll
+          for (int k = 0; k < R; ++k) qq += qv[k] * qv[k];
+        } else {
+          ok = wave_chol_solve<R>(red, bv, xk);
+        }
+        if (!ok) {
           flags |= CROM_FLAG_SINGULAR;
           done = true;
         } else {
           if (lane >= R) xk = 0.0;
-          double dn = xk * xk, qq = qk * qk, sl = lane < R ? bv[lane] * xk : 0.0;
+          if constexpr (R > 8) {
+            dn = xk * xk;
+            qq = qk * qk;
+            sl = lane < R ? bv[lane] * xk : 0.0;
 #pragma unroll
-          for (int o = 32; o >= 1; o >>= 1) {
-            dn += __shfl_xor(dn, o);
-            qq += __shfl_xor(qq, o);
-            sl += __shfl_xor(sl, o);
+            for (int o = 32; o >= 1; o >>= 1) {
+              dn += __shfl_xor(dn, o);
+              qq += __shfl_xor(qq, o);
+              sl += __shfl_xor(sl, o);
+            }
           }
           dk = xk;
           dnorm = sqrt(dn);
@@ -1383,6 +1440,7 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
         }
       }
     }
+    if (p == 1) trace_solve(a, 54);
     if (!done && is_last) {
       flags |= CROM_FLAG_MAXITER;
       done = true;
@@ -1396,16 +1454,17 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
     }
     // trial latents: lane t * R + k (TV * R <= 64)
     const double q_k = __shfl(qk, lane % R), d_k = __shfl(dk, lane % R);  // all lanes shuffle
+    const double qn_k = __shfl(qn_lane, lane % R);
     if (!done && settrials == 3 && lane < TV * R) {
       const int t = lane / R, k = lane % R;
       const double g = a.q_init[(int64_t)inst * R + k];
       st->qt[t][k] = g;
-      st->qd[t][k] = g - qn0[k];
+      st->qd[t][k] = g - qn_k;
     } else if (!done && settrials && lane < TV * R) {
       const int t = lane / R, k = lane % R;
       const double al = settrials == 1 ? alpha[t] : 0.0;
       st->qt[t][k] = q_k + al * d_k;
-      st->qd[t][k] = (q_k - qn0[k]) + al * d_k;
+      st->qd[t][k] = (q_k - qn_k) + al * d_k;
     }
     if (lane == 0) {
       for (int t = 0; t < TV; ++t) st->alpha[t] = alpha[t];
@@ -1431,6 +1490,7 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
     }
   }
   __syncthreads();
+  if (p == 1) trace_solve(a, 50);
   for (int w = threadIdx.x; w < NWORD; w += nth)
     st_c(reinterpret_cast<uint64_t*>(gst) + w, reinterpret_cast<const uint64_t*>(st)[w]);
   if (threadIdx.x == 0) {
@@ -1439,10 +1499,12 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
   }
   wait_mem();
   __syncthreads();
+  if (p == 1) trace_solve(a, 51);
   const bool cont = s_done == 0;
   if (threadIdx.x == 0)
     atomicAdd(reinterpret_cast<unsigned long long*>(wsp<uint64_t>(a, a.L.sync) + SYNC_SOLVED), 1ull);
   __syncthreads();
+  if (p == 1) trace_solve(a, 52);
   return cont;  // the instance takes part in the next round
 }
 

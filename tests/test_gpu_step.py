@@ -152,6 +152,47 @@ def test_lls_every_depth(cuda, prec, depth):
     assert e_q <= tol_j * np.sqrt(cond)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("depth", [2, 3, 4, 6, 7])
+def test_gn_every_depth(cuda, prec, depth):
+    """Gauss-Newton at every depth: the evaluation at q_n and the trial
+    rounds that re-linearise take the reverse pass for depth 2 .. 6 (the
+    Jacobian at the trial latent from the slopes there) and forward tangent
+    columns beyond.  Against the oracle's Gauss-Newton step from the same
+    q_n, with bars from the measured errors (seed 6, with margin): the
+    targets to 3e-5 (FP32, measured up to 8.9e-6) or 3e-4 (BF16, up to
+    1.2e-4 at depth 4), the decoded change to 3e-3 (FP32: up to 1.6e-3 at
+    depth 7, where the step ends in LS_FAIL along nearly flat directions)
+    or 3e-1 (BF16, the conditioning of these random networks), and the
+    objective reached within 1 % of the oracle's plus the arithmetic's
+    floor (measured within 0.6 %).  A ragged batch of two instances
+    reproduces each instance alone bit for bit."""
+    from paper_2206_02607_amd import crom
+    wl = Heat2D(seed=6, bias_scale=0.1, depth=depth)
+    y = wl.samples[:1403]
+    S = y.shape[0]
+    q1, info, f, _ = _run(cuda, wl.layers, 2, [0, S], y, wl.q0, [wl.mu], wl.dt, prec=prec,
+                          max_iter=5, tol_step=1e-8)
+    qr, oinfo, fr = _oracle_step(wl.layers, 2, y, wl.q0, wl.mu, wl.dt, max_iter=5)
+    e_f = normwise_rel(f, fr)
+    e_dg = _dg_err(wl.layers, 2, y, wl.q0, q1[0], qr)
+    print(f"GN depth {depth} {prec}: targets {e_f:.2e} dg err {e_dg:.2e} obj {info['obj_last'][0]:.4e}/"
+          f"{oinfo.obj_last:.4e} iters {info['iters'][0]}/{oinfo.iters} ls {info['ls_evals'][0]} "
+          f"flags {info['flags'][0]}")
+    assert info["flags"][0] & (crom.FLAG_SINGULAR | crom.FLAG_NONFINITE | crom.FLAG_ABORTED) == 0
+    assert e_f <= (3e-5 if prec == "fp32" else 3e-4)
+    assert e_dg <= (3e-3 if prec == "fp32" else 3e-1)
+    floor = (1e-6 if prec == "fp32" else 1e-2) * oinfo.obj_first
+    assert info["obj_last"][0] <= 1.01 * oinfo.obj_last + floor
+    # two instances in one batch, the first ending in a ragged batch
+    y2 = np.concatenate([y, wl.samples[1403:1800]])
+    q0 = np.stack([wl.q0, wl.q0 + 0.01])
+    qb, ib, _, _ = _run(cuda, wl.layers, 2, [0, S, y2.shape[0]], y2, q0, [wl.mu, 0.5 * wl.mu], wl.dt,
+                        prec=prec, max_iter=5, tol_step=1e-8)
+    np.testing.assert_array_equal(qb[0], q1[0])
+    assert ib[0] == info[0]
+
+
 def test_batched_ragged_instances(cuda):
     """A ragged batch equals its instances run one at a time (bit for bit:
     each instance's sums are taken in the same order), and each matches the
