@@ -71,7 +71,12 @@ typedef enum {
  *   BF16X3     every column with split hi + lo operands.
  * The input layer, the ELU epilogues, the derivative recurrences and the
  * output layer are FP32 in every mode; the latent fold q -> W1q q + b1 is
- * accumulated in FP64. */
+ * accumulated in FP64.  Inside crom_step, dg/dq comes from an adjoint pass
+ * (one column per output back through the layers, transposed weights) for
+ * depths 2..6, in the latent-tangent arithmetic above; each layer's ELU
+ * slope is kept for it in FP32 (FP32, BF16X3) or as a half-precision value
+ * (BF16, BF16_PURE: relative error below 2^-10).  The decode calls form
+ * dg/dq by forward tangent columns. */
 enum { CROM_PREC_FP32 = 0, CROM_PREC_BF16 = 1, CROM_PREC_BF16_PURE = 2, CROM_PREC_BF16X3 = 3 };
 
 /* Second spatial derivatives requested from crom_decode_jac. */
