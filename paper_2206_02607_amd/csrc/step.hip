@@ -1029,40 +1029,21 @@ __device__ bool eval_trials_elastic(const StepArgs& a, char* lds, double* jd, co
 
 // ---------------------------------------------------------------------------
 // Small dense algebra on one wave (64 lanes), FP64.
-// A symmetric R x R matrix is held one element per lane and slot: element
-// e = lane + 64 * slot is (i, k) = (e / R, e % R).  fetch(x, i, k) returns
-// element (i, k) of x to every lane that asks for it.
-// ---------------------------------------------------------------------------
-template <int R>
-struct WaveMat {
-  static constexpr int NE = (R * R + 63) / 64;
-  double v[NE];
-  __device__ __forceinline__ double fetch(int i, int k) const {
-    const int e = i * R + k;
-    const int src = e & 63, slot = e >> 6;
-    double out = 0.0;
-#pragma unroll
-    for (int s = 0; s < NE; ++s) {
-      const double t = __shfl(v[s], src);
-      out = (slot == s) ? t : out;
-    }
-    return out;
-  }
-};
-
+//
 // Cholesky factorisation A = L L^T of the packed upper triangle `up` (LDS,
-// row-major over i <= k), right-looking, one column per step; then the
-// solves L y = b and L^T x = y.  A pivot (the value under the square root)
-// that is not finite or not above thresh = 1e-14 * max diag(A) fails the
-// factorisation (returns false).  On success lane k < R returns x_k.
+// row-major over i <= k), left-looking: column j's pivot and entries
+// subtract the earlier columns' products in increasing column order; then
+// the solves L y = b and L^T x = y.  A pivot (the value under the square
+// root) that is not finite or not above thresh = 1e-14 * max diag(A) fails
+// the factorisation (ok = 0).  Both variants below take the same operations
+// in the same order, so they agree bit for bit where both apply.
 //
 // For r <= 8 every lane factors the whole matrix in registers from LDS
-// reads at uniform addresses (no cross-lane traffic), left-looking: column
-// j's pivot and entries subtract the earlier columns' products in the same
-// order as the right-looking updates.  Not inlined: its 36 register-held
-// entries then do not add to the registers live at the call.  Every lane
-// holds the whole solution, so it also returns |x|^2 and b.x (the same in
-// every lane), which the caller would otherwise sum across lanes.
+// reads at uniform addresses (no cross-lane traffic).  Not inlined: its 36
+// register-held entries then do not add to the registers live at the call.
+// Every lane holds the whole solution, so it also returns |x|^2 and b.x
+// (the same in every lane), which the caller would otherwise sum across
+// lanes.
 struct CholOut {
   double x, xx, bx;
   int ok;
@@ -1141,79 +1122,81 @@ __device__ __attribute__((noinline)) CholOut lane_chol_solve(const double* up, c
   return CholOut{x, xx, bx, 1};
 }
 
-template <int R>
-__device__ bool wave_chol_solve(const double* up, const double* b, double& xk) {
-  if constexpr (R <= 8) {
-    const CholOut o = lane_chol_solve<R>(up, b);
-    xk = o.x;
-    return o.ok != 0;
-  }
-  const int lane = threadIdx.x & 63;
-  WaveMat<R> A;
-  double dmax = -1.0;
-#pragma unroll
-  for (int s = 0; s < WaveMat<R>::NE; ++s) {
-    const int e = lane + 64 * s;
-    double val = 0.0;
-    if (e < R * R) {
-      int i = e / R, k = e % R;
-      if (i > k) { const int t = i; i = k; k = t; }
-      val = up[i * R - i * (i - 1) / 2 + (k - i)];
-      if (i == k) dmax = fmax(dmax, val);
-    }
-    A.v[s] = val;
-  }
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o));
-  const double thresh = 1e-14 * dmax;
-  for (int j = 0; j < R; ++j) {
-    const double d = A.fetch(j, j);
-    if (!(isfinite(d) && d > thresh)) return false;  // uniform across the wave
-    const double ljj = sqrt(d);
-    const double inv = 1.0 / ljj;
-    // every slot's new value from the matrix before this column's update
-    // (with r * r > 64 a lane holds several slots, and a slot written early
-    // would otherwise be fetched by the later ones)
-    double nv[WaveMat<R>::NE];
-#pragma unroll
-    for (int s = 0; s < WaveMat<R>::NE; ++s) {
-      const int e = lane + 64 * s;
-      const int i = e / R, k = e % R;
-      const double lij = A.fetch(i < R ? i : 0, j) * inv;
-      const double lkj = A.fetch(k < R ? k : 0, j) * inv;
-      double val = A.v[s];
-      if (e < R * R) {
-        if (i > j && k > j) val -= lij * lkj;
-        else if (k == j && i > j) val = lij;
-        else if (i == j && k == j) val = ljj;
-      }
-      nv[s] = val;
-    }
-#pragma unroll
-    for (int s = 0; s < WaveMat<R>::NE; ++s) A.v[s] = nv[s];
-  }
-  // lane i holds row i of the substitutions
-  const int i = lane;
-  double acc = i < R ? b[i] : 0.0;
-  double y = 0.0;
-  for (int j = 0; j < R; ++j) {  // L y = b
-    const double yj = __shfl(acc, j) / A.fetch(j, j);
-    const double lij = A.fetch(i < R ? i : 0, j);  // every lane takes part in the shuffles
-    if (i == j) y = yj;
-    if (i > j && i < R) acc -= lij * yj;
-  }
-  acc = y;
-  double x = 0.0;
-  for (int j = R - 1; j >= 0; --j) {  // L^T x = y
-    const double xj = __shfl(acc, j) / A.fetch(j, j);
-    const double lji = A.fetch(j, i < R ? i : 0);
-    if (i == j) x = xj;
-    if (i < j) acc -= lji * xj;
-  }
-  xk = x;
-  return true;
+// Lane l's value of v, in every lane (two scalar lane reads).
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// For 8 < r <= 64 lane i holds row i of A, then of L (r registers); the
+// entries of row j that every lane subtracts are read from lane j, also in
+// the backward substitution, where lane i takes L_ji from row j.  The
+// scalars (pivots, 1 / L_jj, the solution) are the same in every lane, as
+// in the variant above.
+template <int R>
+__device__ __forceinline__ CholOut row_chol_solve(const double* up, const double* b) {
+  static_assert(R <= 64, "one lane per row");
+  const int lane = threadIdx.x & 63;
+  const int i = lane < R ? lane : R - 1;  // lanes past the matrix mirror its last row
+  double l[R];                            // row i: A_ik, then L_ik for k <= i (0 above the diagonal)
+  double dmax = -1.0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int r0 = i < k ? i : k, r1 = i < k ? k : i;
+    l[k] = up[r0 * R - r0 * (r0 - 1) / 2 + (r1 - r0)];
+    dmax = fmax(dmax, up[k * R - k * (k - 1) / 2]);
+  }
+  const double thresh = 1e-14 * dmax;
+  double acc = b[i];
+  double inv[R];  // 1 / L_jj
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    double v = l[j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) v -= l[k] * lane_value(l[k], j);
+    const double d = lane_value(v, j);  // lane j's v: the pivot
+    if (!(isfinite(d) && d > thresh)) return CholOut{0.0, 0.0, 0.0, 0};  // uniform across the wave
+    double ljj;
+    sqrt_rsqrt(d, ljj, inv[j]);
+    l[j] = i == j ? ljj : (i > j ? v * inv[j] : 0.0);
+  }
+  double y[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {  // L y = b
+    y[j] = lane_value(acc, j) * inv[j];
+    if (i > j) acc -= l[j] * y[j];
+  }
+  acc = y[0];
+#pragma unroll
+  for (int k = 1; k < R; ++k) acc = i == k ? y[k] : acc;
+#pragma unroll
+  for (int j = R - 1; j >= 0; --j) {  // L^T x = y
+    y[j] = lane_value(acc, j) * inv[j];
+    double lji = 0.0;  // L_ji, from lane j's row
+#pragma unroll
+    for (int k = 0; k < j; ++k) {
+      const double t = lane_value(l[k], j);
+      lji = i == k ? t : lji;
+    }
+    if (i < j) acc -= lji * y[j];
+  }
+  double x = 0.0, xx = 0.0, bx = 0.0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    x = lane == k ? y[k] : x;
+    xx += y[k] * y[k];
+    bx += b[k] * y[k];
+  }
+  return CholOut{x, xx, bx, 1};
+}
+
+template <int R>
+__device__ __forceinline__ CholOut chol_solve(const double* up, const double* b) {
+  if constexpr (R <= 8) return lane_chol_solve<R>(up, b);
+  else return row_chol_solve<R>(up, b);
+}
 
 // ---------------------------------------------------------------------------
 // Gauss-Newton control of one instance in phase p, by the workgroup that
@@ -1347,15 +1330,9 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
           settrials = 1;
         }
       } else {
-        double qq = 0.0;
-        if constexpr (R <= 8) {  // the vector from LDS at uniform addresses: no cross-lane rounds
+        double qq = 0.0;  // the vector from LDS at uniform addresses: no cross-lane rounds
 #pragma unroll
-          for (int k = 0; k < R; ++k) qq += qv[k] * qv[k];
-        } else {
-          qq = qk * qk;
-#pragma unroll
-          for (int o = 32; o >= 1; o >>= 1) qq += __shfl_xor(qq, o);
-        }
+        for (int k = 0; k < R; ++k) qq += qv[k] * qv[k];
         const double step = alpha[acc] * dnorm;
         qk = lane < R ? st->qt[acc][lane] : 0.0;
         iters += 1;
@@ -1385,35 +1362,15 @@ __device__ bool solve_instance(const StepArgs& a, char* lds, int inst, int p, bo
         flags |= CROM_FLAG_NONFINITE;
         done = true;
       } else {
-        double xk = 0.0, dn = 0.0, qq = 0.0, sl = 0.0;
-        bool ok;
-        if constexpr (R <= 8) {
-          const CholOut o = lane_chol_solve<R>(red, bv);
-          ok = o.ok != 0;
-          xk = o.x;
-          dn = o.xx;
-          sl = o.bx;
+        const CholOut o = chol_solve<R>(red, bv);
+        const double xk = lane < R ? o.x : 0.0, dn = o.xx, sl = o.bx;
+        double qq = 0.0;
 #pragma unroll
-          for (int k = 0; k < R; ++k) qq += qv[k] * qv[k];
-        } else {
-          ok = wave_chol_solve<R>(red, bv, xk);
-        }
-        if (!ok) {
+        for (int k = 0; k < R; ++k) qq += qv[k] * qv[k];
+        if (!o.ok) {
           flags |= CROM_FLAG_SINGULAR;
           done = true;
         } else {
-          if (lane >= R) xk = 0.0;
-          if constexpr (R > 8) {
-            dn = xk * xk;
-            qq = qk * qk;
-            sl = lane < R ? bv[lane] * xk : 0.0;
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-              dn += __shfl_xor(dn, o);
-              qq += __shfl_xor(qq, o);
-              sl += __shfl_xor(sl, o);
-            }
-          }
           dk = xk;
           dnorm = sqrt(dn);
           if (a.linearized) {
@@ -1755,11 +1712,11 @@ __global__ __launch_bounds__(LLS_SOLVE_THREADS) void lls_solve_kernel(StepArgs a
   if (!finite) {
     flags = CROM_FLAG_NONFINITE;
   } else {
-    double xk = 0.0;
-    if (!wave_chol_solve<R>(red, red + NA, xk)) {
+    const CholOut o = chol_solve<R>(red, red + NA);
+    if (!o.ok) {
       flags = CROM_FLAG_SINGULAR;
     } else {
-      qk += xk;
+      qk += lane < R ? o.x : 0.0;
       iters = 1;
     }
   }
