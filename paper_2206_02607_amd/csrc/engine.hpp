@@ -212,8 +212,8 @@ struct ParamCache {
 // several engines share one cache).
 // PF: 1 prefetches the next layer's weight fragments into a second register
 // set during this layer's products, 0 loads each layer's fragments when the
-// layer starts, 2 streams them one K-block ahead of their products, -1
-// chooses by a register estimate.  CANON: the output layer's partial dot
+// layer starts, 2 streams them one K-block ahead of their products, 3 two
+// K-blocks ahead, -1 chooses by a register estimate.  CANON: the output layer's partial dot
 // products are summed per M-tile, the tiles in tile order, so that results
 // do not depend on the wave count; else per wave (the wave's tiles in one
 // running sum, then the waves in order).
@@ -250,7 +250,10 @@ struct Engine {
   // A layer's fragments beyond 64 registers (width 256) are streamed: each
   // K-block's fragments are loaded one block ahead of their products
   // instead of holding the whole layer.
-  static constexpr bool STREAM = FRAG_REGS > 64 || PF == 2;
+  // PF 3: streamed two K-blocks ahead (twice the loads in flight, for
+  // launches with one wave per SIMD, where no other wave hides their latency).
+  static constexpr bool STREAM = FRAG_REGS > 64 || PF == 2 || PF == 3;
+  static constexpr int LA = PF == 3 ? 2 : 1;  // K-blocks loaded ahead when streaming
   static constexpr bool PREFETCH = !STREAM && (PF >= 0 ? PF == 1 : 2 * FRAG_REGS + MT * NT * 4 <= 320);
   static constexpr int TG = 4;  // operand loads allowed to run ahead of their products
 
@@ -511,21 +514,37 @@ struct Engine {
         acc[mt][t] = isval ? bv : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
       }
     }
-    // streamed fragments: sh/sl hold K-block kb, nh/nl the next one
+    // streamed fragments: sh/sl hold K-block kb, nh/nl the next one, and
+    // with a look-ahead of two mh/ml the one after
     const AFrag* wfs = reinterpret_cast<const AFrag*>(packed + (size_t)h * Packing<S, PREC>::LAYER_BYTES);
     constexpr int LO = MTILES * KQ * 64;
-    AFrag sh[MT], sl[MT], nh[MT], nl[MT];
+    constexpr int MH = LA > 1 ? MT : 1;
+    AFrag sh[MT], sl[MT], nh[MT], nl[MT], mh[MH], ml[MH];
     if constexpr (STREAM) {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         sh[mt] = wfs[((wave * MT + mt) * KQ + 0) * 64 + lane];
         if constexpr (NSPL > 0) sl[mt] = wfs[LO + ((wave * MT + mt) * KQ + 0) * 64 + lane];
       }
+      if constexpr (LA > 1 && KQ > 1) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          nh[mt] = wfs[((wave * MT + mt) * KQ + 1) * 64 + lane];
+          if constexpr (NSPL > 0) nl[mt] = wfs[LO + ((wave * MT + mt) * KQ + 1) * 64 + lane];
+        }
+      }
     }
 #define CROM_FRAG_HI(mt, kb) (STREAM ? sh[mt] : cur.hi[mt][(kb) % KH])
 #define CROM_FRAG_LO(mt, kb) (STREAM ? sl[mt] : cur.lo[mt][(kb) % KH])
 #define CROM_STREAM_NEXT(kb)                                                                     \
-    if constexpr (STREAM) {                                                                      \
+    if constexpr (STREAM && LA > 1) {                                                            \
+      if ((kb) + 2 < KQ) {                                                                       \
+        _Pragma("unroll") for (int mt = 0; mt < MT; ++mt) {                                      \
+          mh[mt] = wfs[((wave * MT + mt) * KQ + (kb) + 2) * 64 + lane];                          \
+          if constexpr (NSPL > 0) ml[mt] = wfs[LO + ((wave * MT + mt) * KQ + (kb) + 2) * 64 + lane]; \
+        }                                                                                        \
+      }                                                                                          \
+    } else if constexpr (STREAM) {                                                               \
       if ((kb) + 1 < KQ) {                                                                       \
         _Pragma("unroll") for (int mt = 0; mt < MT; ++mt) {                                      \
           nh[mt] = wfs[((wave * MT + mt) * KQ + (kb) + 1) * 64 + lane];                          \
@@ -538,6 +557,10 @@ struct Engine {
       _Pragma("unroll") for (int mt = 0; mt < MT; ++mt) {                                        \
         sh[mt] = nh[mt];                                                                         \
         if constexpr (NSPL > 0) sl[mt] = nl[mt];                                                 \
+        if constexpr (LA > 1) {                                                                  \
+          nh[mt] = mh[mt];                                                                       \
+          if constexpr (NSPL > 0) nl[mt] = ml[mt];                                               \
+        }                                                                                        \
       }                                                                                          \
     }
     if constexpr (PREC == PREC_FP32) {
