@@ -356,6 +356,8 @@ def batched_leg(args, crom, torch, dev, trained=None):
                       "failed_instance_steps": n_fail, "flags_or": flags_or})
             modes[f"{prec}_{kind}"] = r
     out["modes"] = modes
+    if not modes:
+        raise SystemExit(f"--modes {args.modes!r} selects none of the batched modes of precisions {precs}")
     errs = {k: v.get("rollout_error_mean") for k, v in modes.items()}
     if all(e is not None for e in errs.values()):
         best = min(errs.values())

@@ -559,6 +559,17 @@ template <int PREC>
 struct ElasticChunks {
   static constexpr int QC = CROM_ELASTIC_QC;
   static constexpr int HC = 3;
+  // Every trial round carries the Jacobian in BF16 mode: there a chunk's
+  // pass with its tangents takes about the wall time of the value pass
+  // alone (the chunks run side by side, each latency-bound), so an accepted
+  // trial needs no re-linearisation round.  In the other modes a
+  // backtracking round evaluates the objective only.  Measured per
+  // Gauss-Newton step (single instance, 500 samples) with the Jacobian in
+  // every round against only at first trials: neo-Hookean bar BF16 0.682
+  // against 0.851 ms, BF16_PURE 0.644 against 0.612 ms, FP32 1.545 against
+  // 1.751 ms; corotated FE bar (several backtracks per iteration) BF16 0.486
+  // against 0.533 ms, FP32 1.617 against 1.272 ms.
+  static constexpr bool EAGER_J = PREC == PREC_BF16;
 };
 
 // One engine pass at q_n over one batch, writing the pass's columns of
@@ -941,25 +952,25 @@ __device__ void eval_init_elastic(const StepArgs& a, double* jd, int64_t blk) {
 }
 
 // Trial phases of the elastic step, one latent-tangent chunk `ch` of one
-// batch per call.  Every trial round carries the Jacobian at its first
-// trial, so an accepted trial needs no re-linearisation round: each chunk
-// of QC latent directions has its own workgroup (value, the first
+// batch per call.  A round with the Jacobian at the first trial gives each
+// chunk of QC latent directions its own workgroup (value, the first
 // difference and the chunk's tangents, which the engine takes at the first
-// difference column's latent), and the chunks run side by side, so a round
-// with the Jacobian takes no longer than one without.  The chunks store
-// their Jacobian columns, chunk 0 also the residuals, and the last chunk to
-// arrive stages the whole batch and forms its partials.  Every chunk
-// arrives in every round: a chunk reads the instance's phase before its
-// arrival, and the instance is solved only after all its arrivals, so no
-// chunk can read the state that the round's own solve writes (a chunk that
-// skipped the arrival could, and would then evaluate the next round's
-// columns early and be counted twice).  With one trial per round the
-// residual comes from chunk 0's difference column (the same column
-// arithmetic as the trial pass).  Returns whether this workgroup formed the
-// batch's partials.
+// difference column's latent).  The chunks store their Jacobian columns,
+// chunk 0 also the residuals, and the last chunk to arrive stages the
+// whole batch and forms its partials.  A round without the Jacobian
+// evaluates on chunk 0 alone: the decoder differences at the TV trial
+// latents (one pass), zero Jacobian partials.  Every chunk arrives in every
+// round, also where it has nothing to evaluate: a chunk reads the
+// instance's phase before its arrival, and the instance is solved only
+// after all its arrivals, so no chunk can read the state that the round's
+// own solve writes (a chunk that skipped the arrival could, and would then
+// evaluate the next round's columns early and be counted twice).  With one
+// trial per round the residual comes from chunk 0's difference column (the
+// same column arithmetic as the trial pass).  Returns whether this
+// workgroup formed the batch's partials.
 template <class S, int NW, int PREC, int PF>
 __device__ bool eval_trials_elastic(const StepArgs& a, char* lds, double* jd, const float* par, double* qdl,
-                                    int64_t blk, int ch, int inst, bool have_qdl) {
+                                    int64_t blk, int ch, int inst, bool have_qdl, bool with_j) {
   constexpr int R = S::R, D = S::D, ROWS = PT * D;
   constexpr int QC = ElasticChunks<PREC>::QC;
   constexpr int NCH = R / QC;
@@ -970,7 +981,7 @@ __device__ bool eval_trials_elastic(const StepArgs& a, char* lds, double* jd, co
   __shared__ int s_lastc;
   double* rho = jd + ROWS * R;
   double* jg = wsp<double>(a, a.L.jbuf) + blk * (int64_t)(ROWS * (R + TV));  // [ROWS][R], then [ROWS][TV]
-  {
+  if (with_j || ch == 0) {  // uniform over the workgroup
     const GNState* st = wsp<GNState>(a, a.L.state) + inst;
     if (!have_qdl) {
       for (int i = threadIdx.x; i < TV * R; i += blockDim.x) qdl[i] = ld_c(&st->qd[i / R][i % R]);
@@ -981,7 +992,7 @@ __device__ bool eval_trials_elastic(const StepArgs& a, char* lds, double* jd, co
     const int n_valid = rem < PT ? (int)rem : PT;
     const double* qn = a.q_n + (int64_t)inst * R;
     const double* rho0 = wsp<double>(a, a.L.rho0);
-    constexpr bool merged = TV == 1;
+    const bool merged = with_j && TV == 1;
     if (!merged && ch == 0) {
       ET::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
       __syncthreads();
@@ -994,7 +1005,7 @@ __device__ bool eval_trials_elastic(const StepArgs& a, char* lds, double* jd, co
       __syncthreads();
     }
     const float* res = reinterpret_cast<const float*>(lds + EQ::RES_OFF);
-    {
+    if (with_j) {
       const int qb = ch * QC;
       EQ::stage(lds, a.y, first, n_valid, qn, R, qdl, R, par);
       __syncthreads();
@@ -1022,9 +1033,11 @@ __device__ bool eval_trials_elastic(const StepArgs& a, char* lds, double* jd, co
   const bool last = s_lastc != 0;
   __syncthreads();
   if (!last) return false;
-  // every chunk has arrived: stage the batch and clear its count for the
-  // next round (whose chunks start only after this instance is solved)
-  for (int e = threadIdx.x; e < ROWS * (R + TV); e += blockDim.x) jd[e] = ld_c(jg + e);
+  // every chunk has arrived: stage the batch (zero Jacobian in a round
+  // without it) and clear its count for the next round (whose chunks start
+  // only after this instance is solved)
+  for (int e = threadIdx.x; e < ROWS * (R + TV); e += blockDim.x)
+    jd[e] = with_j || e >= ROWS * R ? ld_c(jg + e) : 0.0;
   if (threadIdx.x == 0) st_c(bcnt, 0u);
   __syncthreads();
   batch_partials<R, ROWS>(jd, rho, wsp<double>(a, a.L.partials) + blk * a.L.nred);
@@ -1522,7 +1535,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
   using T = StepTraits<S, NW, PREC, PF, KIND, REV>;
   constexpr int PAR = T::PAR;
   extern __shared__ __align__(16) char lds[];
-  __shared__ int s_last, s_abort, s_ph;
+  __shared__ int s_last, s_abort, s_ph, s_lt;
   __shared__ int64_t s_act;
   __shared__ double qdl[TV * RMAX];
   float* par = reinterpret_cast<float*>(lds + PAR);
@@ -1534,6 +1547,9 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
   // workgroups (work item w = batch w / NCH, chunk w % NCH)
   constexpr int NCH = KIND == PK_ELASTIC ? S::R / ElasticChunks<PREC>::QC : 1;
   static_assert(KIND != PK_ELASTIC || S::R % ElasticChunks<PREC>::QC == 0, "whole chunks");
+  // backtracking rounds without the Jacobian (the solve re-linearises an
+  // accepted shortened step in a round of its own)
+  constexpr bool LAZY = KIND == PK_ELASTIC && !ElasticChunks<PREC>::EAGER_J;
   const int64_t nwork = nblk * NCH;
   const int32_t* blk_inst = wsp<int32_t>(a, a.L.blk_inst);
   const int32_t* first_blk = wsp<int32_t>(a, a.L.first_blk);
@@ -1552,11 +1568,12 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
     if (threadIdx.x == 0) s_act = ld_c(act_phase + p);  // stable: written only by phase p-1 solves
     if (pre) {
       if (threadIdx.x == blockDim.x - 1) s_ph = ld_c(&state[inst0].phase);
+      if (LAZY && threadIdx.x == blockDim.x - 2) s_lt = ld_c(&state[inst0].ls_tried);
       for (int i = threadIdx.x; i < TV * S::R; i += blockDim.x) qdl[i] = ld_c(&state[inst0].qd[i / S::R][i % S::R]);
     }
     __syncthreads();
     const int64_t act = s_act;
-    const int ph0 = s_ph;
+    const int ph0 = s_ph, lt0 = LAZY ? s_lt : 0;
     __syncthreads();
     if (act == 0) break;
     target += (uint64_t)act;
@@ -1571,18 +1588,23 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
         else continue;
       } else {
         const bool first = w == blockIdx.x;  // phase and trial offsets preloaded
-        int ph = ph0;
+        int ph = ph0, lt = lt0;
         if (!first) {
-          if (threadIdx.x == 0) s_ph = ld_c(&state[inst].phase);  // stable until this batch arrives
+          if (threadIdx.x == 0) {
+            s_ph = ld_c(&state[inst].phase);  // stable until this batch arrives
+            if (LAZY) s_lt = ld_c(&state[inst].ls_tried);
+          }
           __syncthreads();
           ph = s_ph;
+          lt = LAZY ? s_lt : 0;
           __syncthreads();
         }
         if (!evaluates_trials(ph)) continue;
         if constexpr (KIND == PK_HEAT)
           eval_trials_batch<S, NW, PREC, PF, true, REV>(a, lds, par, qdl, blk, inst, (p == 1 && first) ? 40 : -1,
                                                         first);
-        else if (!eval_trials_elastic<S, NW, PREC, PF>(a, lds, jd, par, qdl, blk, ch, inst, first))
+        else if (!eval_trials_elastic<S, NW, PREC, PF>(a, lds, jd, par, qdl, blk, ch, inst, first,
+                                                        !(LAZY && ph == PH_TRIALS && lt > 0)))
           continue;
       }
       // arrival: the partials of this batch are complete in memory
@@ -1599,7 +1621,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       const bool last = s_last != 0;
       __syncthreads();  // every thread has read s_last before thread 0 may write it again
       if (p == 1 && w == blockIdx.x) trace_mark(a, 46);
-      if (last) solve_instance<S::R>(a, lds, inst, p, p == max_rounds);
+      if (last) solve_instance<S::R, LAZY>(a, lds, inst, p, p == max_rounds);
       if (p == 1 && w == blockIdx.x) trace_mark(a, 47);
     }
     trace_mark(a, 4 * p + 1);
