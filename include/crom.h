@@ -35,8 +35,8 @@
  *   - Layouts are row-major and fully packed; the indices are listed with
  *     each argument, slowest first.
  *   - Supported decoder shapes (m, r, d, width): (1, 3, 1, 32),
- *     (2, 8, 1, 128), (3, 16, 3, 256); depth >= 1.  Other shapes return
- *     CROM_ERR_UNSUPPORTED.
+ *     (2, 8, 1, 128), (2, 16, 1, 128), (3, 16, 3, 256); depth >= 1.  Other
+ *     shapes return CROM_ERR_UNSUPPORTED.
  */
 #ifndef CROM_H
 #define CROM_H

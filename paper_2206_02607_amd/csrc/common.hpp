@@ -35,12 +35,13 @@ inline crom_status hip_check(hipError_t e, const char* what) {
 constexpr int LDS_MAX = 160 * 1024;  // LDS per workgroup on gfx950
 
 // Shapes with compiled kernels.
-enum ShapeId { SHAPE_NONE = -1, SHAPE_1D = 0, SHAPE_2D = 1, SHAPE_3D = 2 };
+enum ShapeId { SHAPE_NONE = -1, SHAPE_1D = 0, SHAPE_2D = 1, SHAPE_3D = 2, SHAPE_2D_R16 = 3 };
 
 inline ShapeId shape_id(int m, int r, int d, int w) {
   if (m == 1 && r == 3 && d == 1 && w == 32) return SHAPE_1D;
   if (m == 2 && r == 8 && d == 1 && w == 128) return SHAPE_2D;
   if (m == 3 && r == 16 && d == 3 && w == 256) return SHAPE_3D;
+  if (m == 2 && r == 16 && d == 1 && w == 128) return SHAPE_2D_R16;
   return SHAPE_NONE;
 }
 

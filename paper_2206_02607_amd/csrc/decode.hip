@@ -50,12 +50,13 @@ crom_status check_net(const crom_net* net, bool need_packed) {
   if (net->depth < 1 || net->depth > 15) return fail(CROM_ERR_INVALID_ARG, "depth must be in [1, 15]");
   if (shape_id(net->m, net->r, net->d, net->width) == SHAPE_NONE)
     return fail(CROM_ERR_UNSUPPORTED,
-                "unsupported (m, r, d, width); compiled: (1,3,1,32), (2,8,1,128), (3,16,3,256)");
+                "unsupported (m, r, d, width); compiled: (1,3,1,32), (2,8,1,128), (2,16,1,128), (3,16,3,256)");
   if (net->precision < CROM_PREC_FP32 || net->precision > CROM_PREC_BF16X3)
     return fail(CROM_ERR_UNSUPPORTED, "unknown precision");
   if (net->act != CROM_ACT_ELU && net->act != CROM_ACT_SINE) return fail(CROM_ERR_UNSUPPORTED, "unknown activation");
   if (net->act == CROM_ACT_SINE &&
-      ((net->precision != CROM_PREC_FP32 && net->precision != CROM_PREC_BF16) || shape_id(net->m, net->r, net->d, net->width) == SHAPE_3D))
+      ((net->precision != CROM_PREC_FP32 && net->precision != CROM_PREC_BF16) ||
+       (shape_id(net->m, net->r, net->d, net->width) != SHAPE_1D && shape_id(net->m, net->r, net->d, net->width) != SHAPE_2D)))
     return fail(CROM_ERR_UNSUPPORTED, "sine activation: shapes (1,3,1,32) and (2,8,1,128), FP32 or BF16");
   if (!net->params) return fail(CROM_ERR_INVALID_ARG, "net->params is NULL");
   if (need_packed && net->depth > 1 && !net->packed)
@@ -222,17 +223,18 @@ static crom_status hess_chunks(const DecodeArgs& a, hipStream_t st) {
   }
 }
 
-// Plans the passes of a request.  Narrow nets (width <= 128) take every
-// column in one pass.  At width 256 the activations of all columns would not
-// fit in LDS, so the x tangents with the second derivatives form one pass
-// (Hessian entries in chunks of HC: they need the x tangents'
-// pre-activations in the same pass), and the latent tangents follow in
-// chunks of QC.  Every pass rewrites the values, with identical results.
+// Plans the passes of a request.  Narrow nets (width <= 128, r <= 8) take
+// every column in one pass.  At width 256, or with 16 latent tangents, the
+// activations of all columns would not fit in LDS, so the x tangents with
+// the second derivatives form one pass (Hessian entries in chunks of HC:
+// they need the x tangents' pre-activations in the same pass), and the
+// latent tangents follow in chunks of QC.  Every pass rewrites the values,
+// with identical results.
 template <class S, int NW, int PREC, int QC, int HC>
 static crom_status decode_shape(const DecodeArgs& a0, bool xt, int d2, bool qt, hipStream_t st) {
   DecodeArgs a = a0;
   const bool spatial = xt || d2 != D2_NONE;
-  if constexpr (S::W <= 128) {
+  if constexpr (S::W <= 128 && S::R <= 8) {
 #define CROM_ONE(XT, D2)                                                                  \
     if (spatial == XT && d2 == D2)                                                        \
       return qt ? run_pass<S, NW, PREC, XT, D2, S::R>(a, st) : run_pass<S, NW, PREC, XT, D2, 0>(a, st);
@@ -313,6 +315,7 @@ static crom_status decode_any(const crom_net* net, const float* x, int64_t P, co
       if (net->act == CROM_ACT_SINE) return decode_prec<Shape<128, 2, 8, 1, ACT_SINE>, 4>(net->precision, a, xt, d2, qt, st);
       return decode_prec<Shape<128, 2, 8, 1>, 4>(net->precision, a, xt, d2, qt, st);
     case SHAPE_3D: return decode_prec<Shape<256, 3, 16, 3>, 8>(net->precision, a, xt, d2, qt, st);
+    case SHAPE_2D_R16: return decode_prec<Shape<128, 2, 16, 1>, 4>(net->precision, a, xt, d2, qt, st);
     default: return fail(CROM_ERR_UNSUPPORTED, "shape");
   }
 }

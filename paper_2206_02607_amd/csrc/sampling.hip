@@ -275,6 +275,7 @@ static crom_status residual_any(const crom_net* net, const float* x, int64_t P, 
     case SHAPE_1D: s = residual_prec<Shape<32, 1, 3, 1>>(net->precision, a, n_set, st); break;
     case SHAPE_2D: s = residual_prec<Shape<128, 2, 8, 1>>(net->precision, a, n_set, st); break;
     case SHAPE_3D: s = residual_prec<Shape<256, 3, 16, 3>>(net->precision, a, n_set, st); break;
+    case SHAPE_2D_R16: s = residual_prec<Shape<128, 2, 16, 1>>(net->precision, a, n_set, st); break;
     default: return fail(CROM_ERR_UNSUPPORTED, "shape");
   }
   if (s != CROM_OK || !metric) return s;

@@ -1692,7 +1692,7 @@ __global__ __launch_bounds__(LLS_SOLVE_THREADS) void lls_solve_kernel(StepArgs a
   constexpr int NRED = NA + R + TV;
   constexpr int NS = LLS_SOLVE_THREADS / NRED;
   constexpr int UNR = 8;
-  static_assert(NRED <= 64, "one lane per reduced entry");
+  static_assert(NRED <= LLS_SOLVE_THREADS, "one thread per reduced entry");
   __shared__ double sub[NS * NRED];
   __shared__ double red[NRED];
   const int inst = blockIdx.x, lane = threadIdx.x;
@@ -2077,11 +2077,12 @@ static crom_status step_prec(int prec, const StepArgs& a, int rounds, hipStream_
     // four waves with two M-tiles each and streamed weights: the measured
     // best for full batches (three workgroups per CU with the reverse pass)
     constexpr int NWL = S::MTILES < CROM_LIN_NW ? S::MTILES : CROM_LIN_NW;
+    constexpr int WPE_REV = S::R > 8 ? 2 : CROM_LIN_REV_WPE;  // r = 16: the Jacobian sums need the registers
     if (prec == CROM_PREC_FP32) return launch_lls<S, NWF, PREC_FP32, 0, 1>(a, st);
-    if (prec == CROM_PREC_BF16) return launch_lls<S, NWL, PREC_BF16, CROM_LIN_PF, CROM_LIN_WPE, CROM_LIN_REV_WPE>(a, st);
+    if (prec == CROM_PREC_BF16) return launch_lls<S, NWL, PREC_BF16, CROM_LIN_PF, CROM_LIN_WPE, WPE_REV>(a, st);
     if constexpr (ALL) {
       if (prec == CROM_PREC_BF16_PURE)
-        return launch_lls<S, NWL, PREC_BF16_PURE, CROM_LIN_PF, CROM_LIN_WPE, CROM_LIN_REV_WPE>(a, st);
+        return launch_lls<S, NWL, PREC_BF16_PURE, CROM_LIN_PF, CROM_LIN_WPE, WPE_REV>(a, st);
       return launch_lls<S, NWF, PREC_BF16X3, 0, 1>(a, st);
     }
     return fail(CROM_ERR_UNSUPPORTED, "precision");
@@ -2260,6 +2261,8 @@ crom_status crom_step_guess(const crom_net* net, const crom_pde* pde, int32_t n_
       return step_prec<Shape<128, 2, 8, 1>, CROM_STEP2D_NW, 4, CROM_STEP2D_PF, CROM_STEP2D_WPE>(net->precision, a,
                                                                                          (int)rounds, st);
     case SHAPE_3D: return step_prec_elastic<Shape<256, 3, 16, 3>, CROM_ELASTIC_NW>(net->precision, a, (int)rounds, st);
+    case SHAPE_2D_R16:  // four waves: with r = 16 eight spill in BF16
+      return step_prec<Shape<128, 2, 16, 1>, 4, 4, CROM_STEP2D_PF, 1>(net->precision, a, (int)rounds, st);
     default: return fail(CROM_ERR_UNSUPPORTED, "shape");
   }
 }

@@ -17,7 +17,7 @@ from workloads import rng, uniform_points, xavier_mlp
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = {"1d": (1, 3, 1, 32, 5), "2d": (2, 8, 1, 128, 5), "3d": (3, 16, 3, 256, 6)}
+SHAPES = {"1d": (1, 3, 1, 32, 5), "2d": (2, 8, 1, 128, 5), "2d_r16": (2, 16, 1, 128, 5), "3d": (3, 16, 3, 256, 6)}
 TOL = {"fp32": 1e-5, "bf16": 2e-2, "bf16pure": 5e-2}
 TOL_VALUE = {"fp32": 1e-5, "bf16": 1e-4, "bf16pure": 5e-2}
 
@@ -37,7 +37,7 @@ def _decoder(layers, m, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16pure"])
-@pytest.mark.parametrize("shape", ["1d", "2d", "3d"])
+@pytest.mark.parametrize("shape", ["1d", "2d", "2d_r16", "3d"])
 def test_decode_values(cuda, shape, prec):
     import torch
     layers, x, q, m = _case(shape, 1, 16 * 7 + 5)
@@ -50,7 +50,7 @@ def test_decode_values(cuda, shape, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16pure"])
-@pytest.mark.parametrize("shape", ["1d", "2d", "3d"])
+@pytest.mark.parametrize("shape", ["1d", "2d", "2d_r16", "3d"])
 def test_decode_jac_all_columns(cuda, shape, prec):
     import torch
     from paper_2206_02607_amd import crom
