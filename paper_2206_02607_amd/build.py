@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/decode.hip", "csrc/step.hip", "csrc/fd.hip", "csrc/train.hip", "csrc/sampling.hip", "csrc/stencil.hip", "csrc/guess.hip", "csrc/standardize.hip", "csrc/step_static.hip", "csrc/fallback.hip"]
+SOURCES = ["csrc/step.hip", "csrc/decode.hip", "csrc/fd.hip", "csrc/train.hip", "csrc/sampling.hip", "csrc/stencil.hip", "csrc/guess.hip", "csrc/standardize.hip", "csrc/step_static.hip", "csrc/fallback.hip"]
 LIB = os.path.join(HERE, "libcrom.so")
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
