@@ -558,7 +558,7 @@ enum { PK_HEAT = 0, PK_ELASTIC = 1 };
 template <int PREC>
 struct ElasticChunks {
   static constexpr int QC = CROM_ELASTIC_QC;
-  static constexpr int HC = 3;
+  static constexpr int HC = 2;
   // Every trial round carries the Jacobian in BF16 mode: there a chunk's
   // pass with its tangents takes about the wall time of the value pass
   // alone (the chunks run side by side, each latency-bound), so an accepted
@@ -593,10 +593,9 @@ __device__ void jets_pass_batch(const StepArgs& a, char* lds, const float* par, 
     const float v = res[(oo * NT + c) * PT + i];
     float* row = jets + (first + i) * a.L.nj;
     const int k = C::kind(c);
-    if (k == CK_VAL) {
-      if (blockIdx.y == 0) row[J.val(oo)] = v;  // every chunk computes it alike
+    if (k == CK_VAL || k == CK_XT) {  // every chunk with these columns computes them alike
+      if (blockIdx.y == 0) row[k == CK_VAL ? J.val(oo) : J.grad(oo, c - C::X0)] = v;
     }
-    else if (k == CK_XT) row[J.grad(oo, c - C::X0)] = v;
     else if (k == CK_HESS) row[J.hess(oo, C::HB + (c - C::D0))] = v;
     else if (k == CK_QT) row[J.jac(oo, qb + (c - C::Q0))] = v;
   }
@@ -615,6 +614,65 @@ __global__ __launch_bounds__(NW * 64) void jets_pass_kernel(StepArgs a, int qb) 
   // blockIdx.y picks the chunk of latent directions (one launch for all)
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x)
     jets_pass_batch<S, C, NW, PREC>(a, lds, par, blk, qb + (int)blockIdx.y * C::NQ);
+}
+
+// The elastic preparation's engine passes at q_n in one launch: blockIdx.y
+// below NHC picks a chunk of HC Hessian entries (with the value and the x
+// tangents those entries need), from NHC on a chunk of QC latent
+// directions.  The chunks of a batch run side by side instead of in one
+// launch per Hessian chunk and one for the latent chunks.  Two Hessian
+// entries and four latent directions per chunk keep a 500-sample instance's
+// work items (32 batches x 7 chunks) within one per compute unit.  Single
+// instance, 500 samples, BF16: the preparation took 142 us in three
+// launches (three Hessian entries per chunk, two latent directions), 70 us
+// fused; with these chunks the Gauss-Newton step takes 0.590 ms against
+// 0.613 ms, the linearised one 0.088 ms against 0.110 ms.
+template <class S, int PREC>
+struct ElasticJets {
+  static constexpr int NH = S::M * (S::M + 1) / 2, HC = ElasticChunks<PREC>::HC, QC = 4;
+  static constexpr int NHC = (NH + HC - 1) / HC, NQC = S::R / QC;
+  static_assert(S::R % QC == 0, "whole latent chunks");
+  template <int HB>
+  using CH = Cols<S::M, S::R, 1, 0, true, D2_HESS, 0, HB, (NH - HB < HC ? NH - HB : HC)>;
+  using CQ = Cols<S::M, S::R, 1, 0, false, D2_NONE, QC>;
+  template <int NW, int HB = 0>
+  static constexpr int hess_lds() {
+    if constexpr (HB < NH) {
+      constexpr int b = Engine<S, CH<HB>, 1, NW, PREC, 0>::LDS_BYTES, rest = hess_lds<NW, HB + HC>();
+      return b > rest ? b : rest;
+    } else {
+      return 0;
+    }
+  }
+  template <int NW>
+  static constexpr int lds() {
+    constexpr int h = hess_lds<NW>(), q = Engine<S, CQ, 1, NW, PREC, 0>::LDS_BYTES;
+    return h > q ? h : q;
+  }
+  template <int NW, int HB = 0>
+  static __device__ void hess_batch(const StepArgs& a, char* lds, const float* par, int64_t blk, int y) {
+    if constexpr (HB < NH) {
+      if (y == HB / HC) jets_pass_batch<S, CH<HB>, NW, PREC>(a, lds, par, blk, 0);
+      else hess_batch<NW, HB + HC>(a, lds, par, blk, y);
+    }
+  }
+};
+
+template <class S, int NW, int PREC>
+__global__ __launch_bounds__(NW * 64) void elastic_jets_kernel(StepArgs a) {
+  using EJ = ElasticJets<S, PREC>;
+  using PC = ParamCache<S>;
+  extern __shared__ __align__(16) char lds[];
+  const int64_t nblk = *wsp<int64_t>(a, a.L.nblk);
+  if ((int64_t)blockIdx.x >= nblk) return;
+  float* par = reinterpret_cast<float*>(lds + EJ::template lds<NW>());
+  PC::load(par, a.params, a.pi, a.depth, NW * 64);
+  __syncthreads();
+  const int y = blockIdx.y;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    if (y < EJ::NHC) EJ::template hess_batch<NW>(a, lds, par, blk, y);
+    else jets_pass_batch<S, typename EJ::CQ, NW, PREC>(a, lds, par, blk, (y - EJ::NHC) * EJ::QC);
+  }
 }
 
 // FP64 update at one sample: rho_0 = u_{n+1} - u(q_n) and the target.
@@ -1962,26 +2020,24 @@ static crom_status launch_jets_pass(const StepArgs& a, int qb, hipStream_t st, i
   return hip_check(hipGetLastError(), "jets pass launch");
 }
 
-// Value, x-gradient, x-Hessian (in chunks of HC entries, each pass
+// Value, x-gradient, x-Hessian (in chunks of HC entries, each chunk
 // recomputing the x tangents its entries need) and latent Jacobian (chunks
-// of QC) at q_n, then the FP64 update of every sample.
-template <class S, int NW, int PREC, int HB = 0>
+// of QC) at q_n in one launch, then the FP64 update of every sample.
+template <class S, int NW, int PREC>
 static crom_status elastic_prepare(const StepArgs& a, hipStream_t st) {
-  constexpr int NH = S::M * (S::M + 1) / 2, HC = ElasticChunks<PREC>::HC, QC = ElasticChunks<PREC>::QC;
-  if constexpr (HB < NH) {
-    constexpr int n = NH - HB < HC ? NH - HB : HC;
-    crom_status s = launch_jets_pass<S, Cols<S::M, S::R, 1, 0, true, D2_HESS, 0, HB, n>, NW, PREC>(a, 0, st);
-    if (s != CROM_OK) return s;
-    return elastic_prepare<S, NW, PREC, HB + HC>(a, st);
-  } else {
-    static_assert(S::R % QC == 0, "whole latent chunks");
-    crom_status s = launch_jets_pass<S, Cols<S::M, S::R, 1, 0, false, D2_NONE, QC>, NW, PREC>(a, 0, st, S::R / QC);
-    if (s != CROM_OK) return s;
-    int64_t g = a.L.nblk_max;
-    if (g > 65535) g = 65535;
-    hipLaunchKernelGGL(elastic_targets_kernel<S::R>, dim3((unsigned)g), dim3(64), 0, st, a);
-    return hip_check(hipGetLastError(), "elastic targets launch");
-  }
+  using EJ = ElasticJets<S, PREC>;
+  const int lds_bytes = EJ::template lds<NW>() + ParamCache<S>::bytes(a.depth);
+  if (lds_bytes > LDS_MAX) return fail(CROM_ERR_UNSUPPORTED, "network too deep for the LDS");
+  auto k = elastic_jets_kernel<S, NW, PREC>;
+  crom_status s = set_lds(k, lds_bytes);
+  if (s != CROM_OK) return s;
+  int64_t g = a.L.nblk_max;
+  if (g > 65535) g = 65535;
+  hipLaunchKernelGGL(k, dim3((unsigned)g, (unsigned)(EJ::NHC + EJ::NQC)), dim3(NW * 64), lds_bytes, st, a);
+  s = hip_check(hipGetLastError(), "elastic jets launch");
+  if (s != CROM_OK) return s;
+  hipLaunchKernelGGL(elastic_targets_kernel<S::R>, dim3((unsigned)g), dim3(64), 0, st, a);
+  return hip_check(hipGetLastError(), "elastic targets launch");
 }
 
 // Finite-element preparation: the ring decode at q_n, the samples' value and
